@@ -1,0 +1,524 @@
+/*
+ * oracle.c -- plain CPU reference for the lower-bound iteration of
+ * Heineman, Miller, Reichman, Salls, Sarkozy, Soiffer, "Improved Lower Bounds
+ * on the Expected Length of Longest Common Subsequences" (arXiv 2407.10925).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the package smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The GPU library
+ * never links, loads or calls it; the two share no source, header or table.
+ *
+ * Everything is single-threaded FP64, written to be checked against the
+ * paper by eye, with no blocking, fusion or reordering:
+ *
+ *   - a head-string tuple A = (a_1..a_d), a_j in Sigma^l, is kept decoded as
+ *     symbol arrays; the vector index is an independent mixed-radix encoder
+ *     (position-major, string 1 first, the heads most significant), which for
+ *     sigma = 2 and d = 2 is the interleaved pair of Sec. 3.2 ("Indexing");
+ *   - F_z follows Algorithm 1 ("Calculating F_z"): the strings whose head is
+ *     not z drop their head and take one appended symbol each, every appended
+ *     tuple in Sigma^|N| is visited, and the lag-|N| vector is averaged;
+ *   - F(A) = b(A) + max_z F_z(A) is eq. (4) (which merges the all-match
+ *     inequality (2) and the branch inequality (3));
+ *   - the driver follows Algorithm 2 ("The Feasible Triplet Algorithm"): a
+ *     ring of d+1 vectors, R = max_j (v_d - v_{d-1})[j], then
+ *     W = v_d + dR - F(v_d + (d-1)R, ..., v_d), E = max(0, max W), keep
+ *     (u, r, eps) when R - E >= r - eps, and the bound d (r - eps) of eq. (6);
+ *   - W_n(a_1..a_d) of Sec. 2.1 is evaluated exactly by enumerating every
+ *     random tail and running the textbook LCS dynamic programme.
+ *
+ * Readings of points the paper leaves open:
+ *   - F_z with N empty (z equal to the common head of an all-match tuple)
+ *     would read a vector "v_0" that Algorithm 1 does not receive; that branch
+ *     is skipped, so the all-match value is exactly 1 + the mean of eq. (2).
+ *   - Argument k of F is the vector k steps back (lag k); a branch moving |N|
+ *     strings reads lag |N| (Algorithm 1 reads v_|N|).
+ *   - The sum over the sigma^|N| appended tuples is taken as a pairwise
+ *     (balanced binary) tree over the tuples in lexicographic order, c_1 most
+ *     significant; the mean is that sum divided by sigma^|N|.  Division by a
+ *     power of two is exact, so for sigma in {2,4} this is the exact mean of
+ *     the rounded sum.
+ *   - The certificate is made rigorous by directed rounding: the arguments
+ *     v_d + (d-k)R and every step of F are rounded toward -inf, W and E
+ *     toward +inf, and the reported bound d (R - E) toward -inf.  The C
+ *     rounding mode is switched with fesetround and the file is compiled with
+ *     -frounding-math -ffp-contract=off.
+ */
+#include <fenv.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAX_D 16
+#define OR_MAX_H 40
+
+typedef struct {
+    int sigma, d, h;
+    uint64_t n_entries; /* sigma^(d*h) */
+} or_shape;
+
+/* ------------------------------------------------------------------ */
+/* tuple <-> index                                                     */
+/* ------------------------------------------------------------------ */
+
+static int shape_init(or_shape *s, int sigma, int d, int h)
+{
+    if (sigma < 2 || d < 1 || d > OR_MAX_D || h < 1 || h > OR_MAX_H) return -1;
+    s->sigma = sigma; s->d = d; s->h = h;
+    double approx = pow((double)sigma, (double)d * h);
+    if (approx > 18446744073709551615.0) return -1;
+    uint64_t n = 1;
+    for (int i = 0; i < d * h; ++i) n *= (uint64_t)sigma;
+    s->n_entries = n;
+    return 0;
+}
+
+/* sym[j*h + p] = symbol p (p = 0 is the head) of string j.  The digits of the
+ * index, most significant first, are a_1[0], a_2[0], ..., a_d[0], a_1[1], ... */
+static void decode(const or_shape *s, uint64_t idx, int *sym)
+{
+    for (int p = s->h - 1; p >= 0; --p)
+        for (int j = s->d - 1; j >= 0; --j) {
+            sym[j * s->h + p] = (int)(idx % (uint64_t)s->sigma);
+            idx /= (uint64_t)s->sigma;
+        }
+}
+
+static uint64_t encode(const or_shape *s, const int *sym)
+{
+    uint64_t idx = 0;
+    for (int p = 0; p < s->h; ++p)
+        for (int j = 0; j < s->d; ++j)
+            idx = idx * (uint64_t)s->sigma + (uint64_t)sym[j * s->h + p];
+    return idx;
+}
+
+static uint64_t ipow(int base, int e)
+{
+    uint64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= (uint64_t)base;
+    return r;
+}
+
+/* balanced binary tree over x[0..n) (left half first) */
+static double pairwise_sum(const double *x, uint64_t n)
+{
+    if (n == 1) return x[0];
+    uint64_t m = n / 2;
+    return pairwise_sum(x, m) + pairwise_sum(x + m, n - m);
+}
+
+/* ------------------------------------------------------------------ */
+/* F_z and F at one coordinate (Algorithm 1, eq. (4))                  */
+/* ------------------------------------------------------------------ */
+
+/* Reads of lag k go through get(k, index).  shift[k] is added to every value
+ * read from lag k before it is averaged (0 for the plain iteration,
+ * (d-k)R for the certificate's F(v_d + (d-1)R, ..., v_d)). */
+typedef struct {
+    const double *const *lag; /* lag[k] for k = 1..d; lag[0] unused */
+    const double *shift;      /* shift[k] for k = 1..d, or NULL */
+} or_args;
+
+static double lag_value(const or_args *a, int k, uint64_t idx)
+{
+    double v = a->lag[k][idx];
+    if (a->shift) v = v + a->shift[k];
+    return v;
+}
+
+/* F_z(lag_1..lag_d, A) of Algorithm 1; returns 0 and sets *skip when N is
+ * empty (see the reading above). */
+static double F_z(const or_shape *s, const or_args *a, const int *sym, int z,
+                  double *buf, int *work, int *skip)
+{
+    int N[OR_MAX_D], k = 0;
+    for (int j = 0; j < s->d; ++j)
+        if (sym[j * s->h] != z) N[k++] = j;
+    if (k == 0) { *skip = 1; return 0.0; }
+    *skip = 0;
+    uint64_t count = ipow(s->sigma, k);
+    for (uint64_t t = 0; t < count; ++t) {
+        /* (c_1..c_k): lexicographic, c_1 the most significant digit of t */
+        memcpy(work, sym, sizeof(int) * (size_t)(s->d * s->h));
+        uint64_t rest = t;
+        for (int i = k - 1; i >= 0; --i) {
+            int c = (int)(rest % (uint64_t)s->sigma);
+            rest /= (uint64_t)s->sigma;
+            int j = N[i];
+            /* s_j <- T(s_j) c_i */
+            for (int p = 0; p + 1 < s->h; ++p) work[j * s->h + p] = sym[j * s->h + p + 1];
+            work[j * s->h + s->h - 1] = c;
+        }
+        buf[t] = lag_value(a, k, encode(s, work));
+    }
+    return pairwise_sum(buf, count) / (double)count;
+}
+
+/* F(...)[A] = b(A) + max_z F_z(..., A), eq. (4) */
+static double F_at(const or_shape *s, const or_args *a, uint64_t idx,
+                   double *buf, int *sym, int *work)
+{
+    decode(s, idx, sym);
+    int all_match = 1;
+    for (int j = 1; j < s->d; ++j)
+        if (sym[j * s->h] != sym[0]) all_match = 0;
+    double best = -INFINITY;
+    for (int z = 0; z < s->sigma; ++z) {
+        int skip;
+        double v = F_z(s, a, sym, z, buf, work, &skip);
+        if (!skip && v > best) best = v;
+    }
+    return all_match ? 1.0 + best : best;
+}
+
+/* scratch for one F evaluation */
+typedef struct { double *buf; int *sym; int *work; } or_scratch;
+
+static int scratch_alloc(const or_shape *s, or_scratch *w)
+{
+    w->buf = (double *)malloc(sizeof(double) * ipow(s->sigma, s->d));
+    w->sym = (int *)malloc(sizeof(int) * (size_t)(s->d * s->h));
+    w->work = (int *)malloc(sizeof(int) * (size_t)(s->d * s->h));
+    return (w->buf && w->sym && w->work) ? 0 : -1;
+}
+
+static void scratch_free(or_scratch *w)
+{
+    free(w->buf); free(w->sym); free(w->work);
+}
+
+/* ------------------------------------------------------------------ */
+/* exported: shape, codec                                              */
+/* ------------------------------------------------------------------ */
+
+uint64_t or_num_entries(int sigma, int d, int h)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return 0;
+    return s.n_entries;
+}
+
+int or_decode(int sigma, int d, int h, uint64_t idx, int *sym)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h) || idx >= s.n_entries) return -1;
+    decode(&s, idx, sym);
+    return 0;
+}
+
+uint64_t or_encode(int sigma, int d, int h, const int *sym)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return UINT64_MAX;
+    return encode(&s, sym);
+}
+
+/* ------------------------------------------------------------------ */
+/* exported: one sweep v_new = F(lag_1, ..., lag_d)                     */
+/* ------------------------------------------------------------------ */
+
+/* lags[k-1] = vector k steps back, k = 1..d.  Writes every coordinate of out. */
+int or_sweep(int sigma, int d, int h, const double *const *lags, double *out)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return -1;
+    const double *lag[OR_MAX_D + 1];
+    lag[0] = NULL;
+    for (int k = 1; k <= d; ++k) lag[k] = lags[k - 1];
+    or_args a = {lag, NULL};
+    or_scratch w;
+    if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
+    for (uint64_t i = 0; i < s.n_entries; ++i) out[i] = F_at(&s, &a, i, w.buf, w.sym, w.work);
+    scratch_free(&w);
+    return 0;
+}
+
+/* Same as or_sweep, for a list of coordinates only (sampled checks). */
+int or_sweep_at(int sigma, int d, int h, const double *const *lags,
+                const uint64_t *idx, uint64_t count, double *out)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return -1;
+    const double *lag[OR_MAX_D + 1];
+    lag[0] = NULL;
+    for (int k = 1; k <= d; ++k) lag[k] = lags[k - 1];
+    or_args a = {lag, NULL};
+    or_scratch w;
+    if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
+    for (uint64_t i = 0; i < count; ++i) {
+        if (idx[i] >= s.n_entries) { scratch_free(&w); return -1; }
+        out[i] = F_at(&s, &a, idx[i], w.buf, w.sym, w.work);
+    }
+    scratch_free(&w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* exported: the certificate of one iterate (Algorithm 2, eq. (6))     */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double R;      /* max_j (u - prev)[j], round to nearest                    */
+    double maxW;   /* max_j W[j], W = u + dR - F(u+(d-1)R, ..., u), rounded up  */
+    double E;      /* max(0, maxW)                                             */
+    double bound;  /* d (R - E), rounded down; meaningful when R - E >= 0       */
+    double rho;    /* R - E, rounded down                                      */
+    uint64_t argmax_W;   /* a coordinate where W attains maxW (lowest index)   */
+    uint64_t nonfinite;  /* number of coordinates where u, prev or W is not finite */
+} or_cert;
+
+/* W[A] for a given R, with the rounding directions stated above.  Must be
+ * called with the rounding mode at FE_TONEAREST; restores it. */
+static double W_at(const or_shape *s, const double *u, double R, uint64_t idx,
+                   const double *const *lag, const double *shift, or_scratch *w)
+{
+    or_args a = {lag, shift};
+    fesetround(FE_DOWNWARD);
+    double f_lo = F_at(s, &a, idx, w->buf, w->sym, w->work);
+    fesetround(FE_UPWARD);
+    double dR = (double)s->d * R;
+    double Wv = (u[idx] + dR) - f_lo;
+    fesetround(FE_TONEAREST);
+    return Wv;
+}
+
+/* The d shifted arguments v_d + (d-k)R, rounded down.  Each lag reads u and
+ * adds shift[k] = (d-k)R; that product is formed with rounding toward -inf
+ * so the shifted argument never exceeds its exact value. */
+static void make_shift(const or_shape *s, double R, double *shift)
+{
+    fesetround(FE_DOWNWARD);
+    for (int k = 1; k <= s->d; ++k) shift[k] = (double)(s->d - k) * R;
+    fesetround(FE_TONEAREST);
+}
+
+int or_certify(int sigma, int d, int h, const double *u, const double *prev, or_cert *out)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return -1;
+    or_cert c;
+    memset(&c, 0, sizeof c);
+    /* R = max_j (v_d - v_{d-1})[j] */
+    double R = -INFINITY;
+    for (uint64_t i = 0; i < s.n_entries; ++i) {
+        double diff = u[i] - prev[i];
+        if (!isfinite(u[i]) || !isfinite(prev[i])) c.nonfinite++;
+        if (diff > R) R = diff;
+    }
+    c.R = R;
+    double shift[OR_MAX_D + 1];
+    make_shift(&s, R, shift);
+    const double *lag[OR_MAX_D + 1];
+    lag[0] = NULL;
+    for (int k = 1; k <= d; ++k) lag[k] = u;
+    or_scratch w;
+    if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
+    double maxW = -INFINITY;
+    uint64_t arg = 0;
+    for (uint64_t i = 0; i < s.n_entries; ++i) {
+        double Wv = W_at(&s, u, R, i, lag, shift, &w);
+        if (!isfinite(Wv)) c.nonfinite++;
+        if (Wv > maxW) { maxW = Wv; arg = i; }
+    }
+    scratch_free(&w);
+    c.maxW = maxW;
+    c.argmax_W = arg;
+    c.E = maxW > 0.0 ? maxW : 0.0;
+    fesetround(FE_DOWNWARD);
+    c.rho = c.R - c.E;
+    c.bound = (double)d * c.rho;
+    fesetround(FE_TONEAREST);
+    *out = c;
+    return 0;
+}
+
+/* W at a list of coordinates for a given R (sampled checks at sizes where a
+ * whole-table pass is too slow). */
+int or_certify_W_at(int sigma, int d, int h, const double *u, double R,
+                    const uint64_t *idx, uint64_t count, double *out)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return -1;
+    double shift[OR_MAX_D + 1];
+    make_shift(&s, R, shift);
+    const double *lag[OR_MAX_D + 1];
+    lag[0] = NULL;
+    for (int k = 1; k <= d; ++k) lag[k] = u;
+    or_scratch w;
+    if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
+    for (uint64_t i = 0; i < count; ++i) {
+        if (idx[i] >= s.n_entries) { scratch_free(&w); return -1; }
+        out[i] = W_at(&s, u, R, idx[i], lag, shift, &w);
+    }
+    scratch_free(&w);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* exported: the Feasible Triplet driver (Algorithm 2)                 */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Runs n_sweeps applications of F from the all-zero ring (the first sweep
+ * produces v_d from v_{d-1} = ... = v_0 = 0).  Every `cadence` sweeps the
+ * newest vector is certified and the best triplet is kept with the rule
+ * R - E >= r - eps (a later iterate wins ties).  Algorithm 2 certifies after
+ * every sweep, which is cadence = 1.
+ *
+ * hist (optional, 4 doubles per certified sweep): sweep number, R, E, bound.
+ * best (4 doubles): sweep number, r, eps, bound; all zero when nothing beat
+ * the initial triplet (v_0, 0, 0).
+ * final_ring (optional, d tables of N doubles): lag 1 .. lag d at the end.
+ */
+int or_feasible_triplet(int sigma, int d, int h, int64_t n_sweeps, int64_t cadence,
+                        double *hist, double *best, double *final_ring)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h) || n_sweeps < 0 || cadence < 1) return -1;
+    uint64_t N = s.n_entries;
+    double **ring = (double **)calloc((size_t)d + 1, sizeof(double *));
+    if (!ring) return -2;
+    for (int i = 0; i <= d; ++i) {
+        ring[i] = (double *)calloc(N, sizeof(double));
+        if (!ring[i]) {
+            for (int k = 0; k < i; ++k) free(ring[k]);
+            free(ring);
+            return -2;
+        }
+    }
+    /* ring[0] is the newest vector (lag 1), ring[d] the slot to overwrite */
+    double r_best = 0.0, eps_best = 0.0, bound_best = 0.0, sweep_best = 0.0;
+    int64_t nh = 0;
+    int rc = 0;
+    for (int64_t t = 1; t <= n_sweeps; ++t) {
+        const double *lags[OR_MAX_D];
+        for (int k = 1; k <= d; ++k) lags[k - 1] = ring[k - 1];
+        rc = or_sweep(sigma, d, h, lags, ring[d]);
+        if (rc) break;
+        /* shift the rows: the new vector becomes lag 1 */
+        double *newest = ring[d];
+        for (int k = d; k > 0; --k) ring[k] = ring[k - 1];
+        ring[0] = newest;
+        if (t % cadence == 0) {
+            or_cert c;
+            rc = or_certify(sigma, d, h, ring[0], ring[1], &c);
+            if (rc) break;
+            if (hist) {
+                hist[4 * nh + 0] = (double)t;
+                hist[4 * nh + 1] = c.R;
+                hist[4 * nh + 2] = c.E;
+                hist[4 * nh + 3] = c.bound;
+            }
+            nh++;
+            /* keep (u, r, eps) <- (v_d, R, E) when R - E >= r - eps */
+            fesetround(FE_DOWNWARD);
+            double cur = c.R - c.E;
+            double old = r_best - eps_best;
+            fesetround(FE_TONEAREST);
+            if (c.nonfinite == 0 && cur >= old) {
+                r_best = c.R; eps_best = c.E; bound_best = c.bound; sweep_best = (double)t;
+            }
+        }
+    }
+    if (best) {
+        best[0] = sweep_best; best[1] = r_best; best[2] = eps_best; best[3] = bound_best;
+    }
+    if (final_ring && rc == 0)
+        for (int k = 0; k < d; ++k) memcpy(final_ring + (uint64_t)k * N, ring[k], N * sizeof(double));
+    for (int i = 0; i <= d; ++i) free(ring[i]);
+    free(ring);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* exported: W_n(a_1..a_d) by exhaustive enumeration (Sec. 2.1)         */
+/* ------------------------------------------------------------------ */
+
+/*
+ * W_n(a_1..a_d) = E[ max_{i_1+...+i_d = n} L(a_1 x_1[..i_1], ..., a_d x_d[..i_d]) ]
+ * with x_j uniform in Sigma^n.  Only the first n symbols of each x_j can be
+ * used, so the expectation is an exact average over sigma^(d n) tails.
+ * Returns the integer sum over all tails (the expectation is
+ * *sum / sigma^(d n)).  L is the textbook d-string LCS recurrence over
+ * prefix lengths.  heads[j*h + p] = a_j[p].
+ */
+int or_brute_W(int sigma, int d, int h, int n, const int *heads, uint64_t *sum)
+{
+    if (sigma < 2 || d < 1 || d > 4 || h < 0 || n < 0) return -1;
+    int len = h + n;                 /* full string length */
+    int side = len + 1;              /* prefix lengths 0..len */
+    uint64_t cells = 1;
+    for (int j = 0; j < d; ++j) cells *= (uint64_t)side;
+    if (cells > (1u << 26)) return -1;
+    double tails_d = pow((double)sigma, (double)d * n);
+    if (tails_d > 1e9) return -1;
+    uint64_t tails = ipow(sigma, d * n);
+    int *str = (int *)malloc(sizeof(int) * (size_t)(d * (len > 0 ? len : 1)));
+    uint32_t *L = (uint32_t *)malloc(sizeof(uint32_t) * cells);
+    if (!str || !L) { free(str); free(L); return -2; }
+    uint64_t stride[4];
+    stride[d - 1] = 1;
+    for (int j = d - 2; j >= 0; --j) stride[j] = stride[j + 1] * (uint64_t)side;
+    uint64_t total = 0;
+    for (uint64_t t = 0; t < tails; ++t) {
+        /* string j = a_j followed by x_j (digits of t, string 1 first) */
+        uint64_t rest = t;
+        for (int j = d - 1; j >= 0; --j) {
+            for (int p = 0; p < h; ++p) str[j * len + p] = heads[j * h + p];
+            for (int p = len - 1; p >= h; --p) {
+                str[j * len + p] = (int)(rest % (uint64_t)sigma);
+                rest /= (uint64_t)sigma;
+            }
+        }
+        /* L over prefix-length vectors q, lexicographic order */
+        for (uint64_t cell = 0; cell < cells; ++cell) {
+            int q[4];
+            uint64_t r2 = cell;
+            int any_zero = 0;
+            for (int j = 0; j < d; ++j) {
+                q[j] = (int)(r2 / stride[j]);
+                r2 %= stride[j];
+                if (q[j] == 0) any_zero = 1;
+            }
+            if (any_zero) { L[cell] = 0; continue; }
+            int same = 1;
+            int c0 = str[0 * len + q[0] - 1];
+            for (int j = 1; j < d; ++j)
+                if (str[j * len + q[j] - 1] != c0) same = 0;
+            if (same) {
+                uint64_t back = cell;
+                for (int j = 0; j < d; ++j) back -= stride[j];
+                L[cell] = L[back] + 1;
+            } else {
+                uint32_t m = 0;
+                for (int j = 0; j < d; ++j) {
+                    uint32_t v = L[cell - stride[j]];
+                    if (v > m) m = v;
+                }
+                L[cell] = m;
+            }
+        }
+        /* max over i_1 + ... + i_d = n of L(h + i_1, ..., h + i_d) */
+        uint32_t best = 0;
+        uint64_t splits = ipow(n + 1, d);
+        for (uint64_t sp = 0; sp < splits; ++sp) {
+            uint64_t r3 = sp;
+            int sumi = 0;
+            uint64_t cell = 0;
+            for (int j = 0; j < d; ++j) {
+                int i = (int)(r3 % (uint64_t)(n + 1));
+                r3 /= (uint64_t)(n + 1);
+                sumi += i;
+                cell += (uint64_t)(h + i) * stride[j];
+            }
+            if (sumi != n) continue;
+            if (L[cell] > best) best = L[cell];
+        }
+        total += best;
+    }
+    free(str);
+    free(L);
+    *sum = total;
+    return 0;
+}

@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the sweep of the lower-bound iteration for gamma_{2,2}.
+
+Workload: sigma = d = 2, l = 16 (2^32 table entries), FP32 sweeps renormalised
+by entry 0, with an FP64 round-down certificate every 64 sweeps.  One step is
+one certificate period: 64 sweeps + one certificate.  The reported value is
+table updates per second (2^32 updates per sweep) over the K timed steps,
+with the ring already resident in HBM.
+
+Also printed in the same JSON line:
+  roofline      the sweep kernel's algorithmic bytes per launch (12 B per
+                update: lag 1 and lag 2 read once, the new table written once)
+                over its average launch time, from HIP events on the stream
+                the library launches on, against the 8 TB/s HBM peak; traffic
+                is the rocprofv3-measured HBM bytes per launch when a counter
+                summary for the current kernel source is committed, else null
+  cpu_baseline  the CPU oracle on this host, one sweep over a bounded sample
+                of the same table
+  time_to_bound wall time to a certified bound within 1e-9 of the converged
+                plain FP64 bound, for plain FP64 and for FP32 + FP64 polish
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "updates/s at σ=2,d=2,h=16; time to certified bound, plain vs mixed+learned"
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_s2d2_f32_h16_pmc.json")
+SWEEP_SRC = os.path.join(ROOT, "paper_2407_10925_amd", "csrc", "sweep.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--h", type=int, default=16)
+    p.add_argument("--cadence", type=int, default=64)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-sample-log2", type=int, default=24)
+    p.add_argument("--no-ttb", action="store_true", help="skip the time-to-bound runs")
+    return p.parse_args()
+
+
+def sweep_source_hash():
+    with open(SWEEP_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    or None when absent or taken on a different kernel source."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            s = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if s.get("sweep_hip_sha256") != sweep_source_hash():
+        return None
+    return s.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(h, log2_sample):
+    """The oracle (single thread) on one sweep over every 2^(2h - s)-th entry
+    of an l = h FP32 ring filled with seeded values."""
+    import numpy as np
+    import torch
+
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import seeded_inputs as si
+
+    n = 4 ** h
+    log(f"cpu baseline: generating a seeded l={h} FP32 ring")
+    lags = []
+    for k in range(2):
+        t = si.table(2, 2, h, seed=100 + k, dtype=torch.float32, device="cuda")
+        lags.append(t.cpu().numpy())
+        del t
+    torch.cuda.empty_cache()
+    count = min(n, 1 << log2_sample)
+    idx = np.arange(0, n, n // count, dtype=np.uint64)[:count]
+    oracle.lib()
+    log(f"cpu baseline: oracle sweep over {count} sampled entries")
+    t0 = time.perf_counter()
+    oracle.sweep_at_tables(2, 2, h, lags, idx)
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one sweep at {count} entries (every {n // count}th index) of the "
+                      f"sigma=d=2, l={h} table, FP32 ring read as FP64, single thread, "
+                      f"{dt:.1f} s"}
+
+
+def time_to_bound(pk, h, log_every=True):
+    """Plain FP64 from zero to convergence (certificate every 8 sweeps; stop
+    when the current bound moves by < 1e-10 and is the best so far), then
+    FP32 from zero (certificate every 16 sweeps) switched to an FP64 polish
+    (certificate every 4 sweeps) when its certificate stalls (< 1e-7 gain),
+    until the best bound is within 1e-9 of the plain one."""
+    import torch
+    out = {}
+    # ---- plain FP64
+    P = pk.Lcsb(2, 2, h, "f64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.init_zero()
+    hist = []
+    prev = None
+    while True:
+        P.iterate(8)
+        cur, best = P.certify()
+        hist.append((time.perf_counter() - t0, best["bound"], cur["sweep"]))
+        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
+            break
+        prev = cur["bound"]
+        if cur["sweep"] > 600:
+            break
+    B = best["bound"]
+    target = B - 1e-9
+    t_plain, s_plain = next((t, s) for t, b, s in hist if b >= target)
+    out["plain_f64"] = {"seconds": t_plain, "sweeps": s_plain, "bound": B,
+                        "converged_after_sweeps": hist[-1][2]}
+    log(f"time to bound, plain FP64: {t_plain:.3f} s, {s_plain} sweeps, bound {B:.12f}")
+    # ---- FP32 + FP64 polish (the FP64 ring of the plain run is reused)
+    M = pk.Lcsb(2, 2, h, "f32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M.init_zero()
+    prev = -1.0
+    sweeps32 = 0
+    while True:
+        M.iterate(16)
+        cur, best = M.certify()
+        sweeps32 = cur["sweep"]
+        if best["bound"] >= target or cur["bound"] - prev < 1e-7 or sweeps32 > 600:
+            break
+        prev = cur["bound"]
+    t_switch = time.perf_counter() - t0
+    if best["bound"] < target:
+        P.upcast(M)
+        while best["bound"] < target and cur["sweep"] < 1200:
+            P.iterate(4)
+            cur, best = P.certify()
+    t_mixed = time.perf_counter() - t0
+    out["mixed_f32_polish"] = {"seconds": t_mixed, "sweeps_f32": sweeps32,
+                               "sweeps_total": cur["sweep"], "switch_after_s": t_switch,
+                               "bound": best["bound"], "reached": best["bound"] >= target}
+    log(f"time to bound, FP32 + FP64 polish: {t_mixed:.3f} s, {sweeps32} FP32 + "
+        f"{cur['sweep'] - sweeps32} FP64 sweeps, bound {best['bound']:.12f}")
+    out["mixed_learned"] = None
+    del P, M
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the sweep has no multi-GPU path in this build)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2407_10925_amd as pk
+
+    torch.cuda.set_device(0)
+    h, cad = args.h, args.cadence
+    n = 4 ** h
+    L = pk.Lcsb(2, 2, h, "f32")
+    stream = torch.cuda.current_stream()
+    L.init_zero()
+    log(f"warmup: {args.warmup} steps of {cad} sweeps + 1 certificate at l={h}")
+    for _ in range(args.warmup):
+        L.iterate(cad)
+        L.certify()
+    torch.cuda.synchronize()
+    sweep_ms = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        L.iterate(cad)
+        e1.record(stream)
+        cur, best = L.certify()
+        sweep_ms.append(e0.elapsed_time(e1) / cad)
+        log(f"step {s}: sweep {sweep_ms[-1]:.3f} ms, bound {cur['bound']:.9f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = n * cad * args.steps / elapsed
+    avg_sweep_s = statistics.mean(sweep_ms) * 1e-3
+    algo_bytes = 12 * n  # per launch: (d + 1) tables x 4 bytes per update
+    achieved = algo_bytes / avg_sweep_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(), "kernel": "sweep_s2d2<float>",
+                "algorithmic_bytes_per_launch": algo_bytes,
+                "avg_launch_ms": round(avg_sweep_s * 1e3, 4)}
+    del L
+    torch.cuda.empty_cache()
+
+    ttb = None
+    if not args.no_ttb:
+        ttb = time_to_bound(pk, h)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(h, args.cpu_sample_log2)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 sweeps, f64 certificate", "data": "synthetic (zero-start iteration)",
+        "config": {"workload": f"sigma=2 d=2 l={h}: {n} entries, FP32 renormalised sweeps, "
+                               f"FP64 round-down certificate every {cad} sweeps",
+                   "sweeps_per_step": cad, "entries": n},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "time_to_bound": ttb,
+        "sweep_only_updates_per_s": n / avg_sweep_s,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

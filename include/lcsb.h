@@ -1,0 +1,162 @@
+/*
+ * lcsb.h -- C ABI of the gfx950 library for the lower-bound iteration of
+ * Heineman, Miller, Reichman, Salls, Sarkozy, Soiffer, "Improved Lower Bounds
+ * on the Expected Length of Longest Common Subsequences" (arXiv 2407.10925).
+ *
+ * The library sweeps the table v over all sigma^(d*l) tuples of head strings
+ * with the recurrence F of Sec. 2.1 (eqs. (2)-(4), Algorithm 1) and certifies
+ * an iterate with the feasible-triplet step of Algorithm 2, giving the bound
+ * gamma_{sigma,d} >= d (r - eps) of eq. (6).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an int status: LCSB_OK (0) or a negative code.
+ *     On error lcsb_last_error() returns a message (thread-local, valid until
+ *     the next call on the same thread).  No function throws or aborts.
+ *   - Device pointers are HIP device addresses on the device that is current
+ *     when the function is called; the caller owns every buffer and stream it
+ *     passes and keeps them alive until lcsb_destroy.  The library allocates
+ *     no device memory: the caller (typically PyTorch) allocates the ring and
+ *     the workspace whose sizes lcsb_query reports.
+ *   - Work is enqueued on the stream given to lcsb_bind and is asynchronous,
+ *     except where a function says it synchronises.
+ *   - After an LCSB_EHIP error the context is poisoned: every later call on it
+ *     except lcsb_destroy returns LCSB_ESTATE.
+ *
+ * Table layout.  A tuple A = (a_1..a_d), a_j = a_j[1] .. a_j[l] over the
+ * alphabet {0..sigma-1}, sigma = 2^beta, has the index whose bits, most
+ * significant first, are the beta-bit symbols a_1[1], a_2[1], .., a_d[1],
+ * a_1[2], .., a_d[l] (position-major, string 1 first, heads on top).  For
+ * sigma = d = 2 this is the interleaved pair of Sec. 3.2.  Entry i of a table
+ * buffer is the value at index i (8-byte doubles for LCSB_F64, 4-byte floats
+ * for LCSB_F32).
+ *
+ * Symmetry.  Relabelling every symbol c -> c xor m leaves LCS lengths
+ * unchanged (for sigma = 2 this is the complement symmetry of Sec. 3.3,
+ * eq. (10)).  The sweep computes one representative per orbit and writes the
+ * same value to the other sigma - 1 members, so it requires lag tables that
+ * are exactly invariant under that relabelling; every table the library
+ * writes is, and lcsb_load_ring projects its input onto such tables.  The
+ * certificate does not rely on the symmetry: it evaluates every coordinate.
+ */
+#ifndef LCSB_H
+#define LCSB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LCSB_OK            0
+#define LCSB_EINVAL       (-1) /* bad argument (null pointer, size, range)   */
+#define LCSB_ENOMEM       (-2) /* host allocation of the context failed      */
+#define LCSB_EHIP         (-3) /* a HIP runtime call or launch failed        */
+#define LCSB_ESTATE       (-4) /* call out of order, or context poisoned     */
+#define LCSB_EUNSUPPORTED (-5) /* (sigma, d, dtype) has no GPU kernel here   */
+#define LCSB_ENONFINITE   (-6) /* the certified table holds a NaN or inf     */
+
+/* element types of the ring tables */
+#define LCSB_F64 0
+#define LCSB_F32 1
+
+typedef struct lcsb_ctx lcsb_ctx;
+
+/* One certificate (Algorithm 2 for a single iterate, eq. (6)).
+ * With u the newest table and prev the one before it:
+ *   R     = max_j (u - prev)[j]                         (round to nearest)
+ *   W[A]  = u[A] + dR - F(u + (d-1)R, u + (d-2)R, .., u)[A]
+ *   maxW  = max_A W[A], every W rounded toward +inf (F's arguments and every
+ *           step of F toward -inf)
+ *   E     = max(0, maxW)
+ *   rho   = R - E, rounded toward -inf
+ *   bound = d * rho, rounded toward -inf: a rigorous lower bound on
+ *           gamma_{sigma,d} whenever rho >= 0 (the feasible-triplet lemma,
+ *           Sec. 2.1), for whatever table u was certified. */
+typedef struct {
+    double bound;
+    double R;
+    double E;
+    double maxW;
+    double rho;
+    int64_t sweep;      /* sweeps applied before this certificate            */
+    uint64_t argmax_W;  /* lowest index where W attains maxW                 */
+    uint64_t nonfinite; /* coordinates where u, prev or W is not finite      */
+} lcsb_cert;
+
+/* Create a context for (sigma, d, l = h) and a table element type.
+ * GPU kernels exist for (sigma, d) in {(2,2), (4,2), (2,3)} and both element
+ * types; other pairs give LCSB_EUNSUPPORTED.  h >= 1 and sigma^(d h) <= 2^34
+ * (else LCSB_EINVAL).  *out receives a host object owned by the library. */
+int lcsb_create(int sigma, int d, int h, int dtype, lcsb_ctx **out);
+
+/* Sizes the caller must allocate: nbuf = d + 1 ring tables of bytes_per_buf
+ * bytes each (entries = sigma^(d h) elements), and one device workspace of
+ * workspace_bytes bytes, 256-byte aligned.  Any output pointer may be NULL. */
+int lcsb_query(const lcsb_ctx *ctx, int *nbuf, uint64_t *entries,
+               uint64_t *bytes_per_buf, uint64_t *workspace_bytes);
+
+/* Attach caller-owned device memory and a HIP stream (hipStream_t passed as
+ * void*, NULL for the null stream).  dev_bufs holds nbuf table pointers, each
+ * at least bytes_per_buf bytes and 256-byte aligned.  May be called again to
+ * rebind; the ring contents are then undefined until an init call. */
+int lcsb_bind(lcsb_ctx *ctx, void *const *dev_bufs, int nbuf, void *dev_workspace,
+              void *hip_stream);
+
+/* Set every table to zero and forget the best certificate: the starting
+ * ring v_0 = .. = v_{d-1} = 0 of Algorithm 2 (first row of its pseudo-code)
+ * and the initial triplet (v_0, 0, 0). */
+int lcsb_init_zero(lcsb_ctx *ctx);
+
+/* Set lag k (k = 1..d) to the caller's device table src[k-1] (same element
+ * type and size as the ring; src may not alias a ring buffer), each value
+ * taken at its orbit representative (the index whose string-1 head is 0 after
+ * the symbol relabelling), so the ring is symmetric.  offsets (host, d
+ * doubles, may be NULL = all zero) are the values the FP32 tables are
+ * relative to (true value = offset + stored value); ignored for LCSB_F64.
+ * Resets the sweep count and the best certificate. */
+int lcsb_load_ring(lcsb_ctx *ctx, const void *const *src, int nsrc, const double *offsets);
+
+/* Apply k >= 0 sweeps v_new = F(lag 1, .., lag d) of eq. (4) on the bound
+ * stream; the new table becomes lag 1.  In LCSB_F64 every value is computed
+ * in FP64, round to nearest, summing the sigma^k appended tuples by a
+ * balanced binary tree in lexicographic order (appended symbol of the first
+ * advanced string most significant) and multiplying by sigma^-k.  In
+ * LCSB_F32 the same is done in FP32 relative to lag 1's offset, and the new
+ * table is shifted so that its entry 0 is exactly 0 (translation invariance,
+ * property 2 of the lemma); the FP64 offsets stay on the device. */
+int lcsb_iterate(lcsb_ctx *ctx, int64_t k);
+
+/* Certify the newest table (see lcsb_cert).  Synchronises the stream.  When
+ * nonfinite == 0 and cur.rho >= best.rho, the best certificate is replaced
+ * (Algorithm 2's keep rule; a later iterate wins ties).  Either output
+ * pointer may be NULL.  Returns LCSB_ENONFINITE (after filling the outputs)
+ * when a non-finite value was met; the best certificate is then unchanged.
+ * Needs at least one sweep since the last init (else LCSB_ESTATE). */
+int lcsb_certify(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
+
+/* Device address of lag k (1..d) and, for LCSB_F32, the FP64 offset its
+ * values are relative to (read from the device; synchronises).  The pointer
+ * stays valid until the next lcsb_iterate, lcsb_load_ring or lcsb_bind. */
+int lcsb_lag(const lcsb_ctx *ctx, int k, void **dev_ptr, double *offset);
+
+/* Number of sweeps applied since the last init, and the best certificate. */
+int lcsb_status(const lcsb_ctx *ctx, int64_t *sweeps, lcsb_cert *best);
+
+/* Copy the ring of an LCSB_F32 context into an LCSB_F64 context of the same
+ * (sigma, d, h) as FP64 values offset + stored value (the switch from FP32
+ * sweeps to an FP64 polish).  The sweep count and best certificate move with
+ * it.  Enqueued on dst's stream after synchronising src's. */
+int lcsb_upcast(const lcsb_ctx *src_f32, lcsb_ctx *dst_f64);
+
+/* Release the context (never the caller's buffers or stream). NULL is ok. */
+int lcsb_destroy(lcsb_ctx *ctx);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *lcsb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCSB_H */

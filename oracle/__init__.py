@@ -61,6 +61,14 @@ def lib():
         L.or_sweep.argtypes = [C.c_int, C.c_int, C.c_int, P(P(C.c_double)), P(C.c_double)]
         L.or_sweep_at.argtypes = [C.c_int, C.c_int, C.c_int, P(P(C.c_double)),
                                   P(C.c_uint64), C.c_uint64, P(C.c_double)]
+        L.or_sweep_at_f32.argtypes = [C.c_int, C.c_int, C.c_int, P(P(C.c_float)),
+                                      P(C.c_uint64), C.c_uint64, P(C.c_double)]
+        L.or_certify_W_at_f32.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_float), C.c_double,
+                                          P(C.c_uint64), C.c_uint64, P(C.c_double)]
+        L.or_max_diff.argtypes = [P(C.c_double), P(C.c_double), C.c_uint64, P(C.c_double),
+                                  P(C.c_uint64)]
+        L.or_max_diff_f32.argtypes = [P(C.c_float), P(C.c_float), C.c_uint64, P(C.c_double),
+                                      P(C.c_uint64)]
         L.or_certify.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double), P(C.c_double), P(Cert)]
         L.or_certify_W_at.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double), C.c_double,
                                       P(C.c_uint64), C.c_uint64, P(C.c_double)]
@@ -124,6 +132,53 @@ def sweep_at(sigma, d, h, lags, idx):
     _check(lib().or_sweep_at(sigma, d, h, ptrs, idx.ctypes.data_as(C.POINTER(C.c_uint64)),
                              idx.size, _dptr(out)), "sweep_at")
     return out
+
+
+def _is_f32(a):
+    return isinstance(a, np.ndarray) and a.dtype == np.float32
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def sweep_at_tables(sigma, d, h, lags, idx):
+    """sweep_at for float64 or float32 tables (float32 read as exact doubles)."""
+    if all(_is_f32(x) for x in lags):
+        arrs = [np.ascontiguousarray(x) for x in lags]
+        ptrs = (C.POINTER(C.c_float) * len(arrs))(*[_fptr(a) for a in arrs])
+        idx = np.ascontiguousarray(idx, dtype=np.uint64)
+        out = np.empty(idx.size, dtype=np.float64)
+        _check(lib().or_sweep_at_f32(sigma, d, h, ptrs, idx.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                     idx.size, _dptr(out)), "sweep_at_f32")
+        return out
+    return sweep_at(sigma, d, h, lags, idx)
+
+
+def certify_W_at_table(sigma, d, h, u, R, idx):
+    if _is_f32(u):
+        u = np.ascontiguousarray(u)
+        idx = np.ascontiguousarray(idx, dtype=np.uint64)
+        out = np.empty(idx.size, dtype=np.float64)
+        _check(lib().or_certify_W_at_f32(sigma, d, h, _fptr(u), float(R),
+                                         idx.ctypes.data_as(C.POINTER(C.c_uint64)), idx.size,
+                                         _dptr(out)), "certify_W_at_f32")
+        return out
+    return certify_W_at(sigma, d, h, u, R, idx)
+
+
+def max_diff(u, prev):
+    """R of Algorithm 2 alone: (max_j (u - prev)[j], lowest arg)."""
+    R, arg = C.c_double(), C.c_uint64()
+    if _is_f32(u) and _is_f32(prev):
+        u, prev = np.ascontiguousarray(u), np.ascontiguousarray(prev)
+        _check(lib().or_max_diff_f32(_fptr(u), _fptr(prev), u.size, C.byref(R), C.byref(arg)),
+               "max_diff_f32")
+    else:
+        u, prev = _f64(u), _f64(prev)
+        _check(lib().or_max_diff(_dptr(u), _dptr(prev), u.size, C.byref(R), C.byref(arg)),
+               "max_diff")
+    return R.value, int(arg.value)
 
 
 def certify(sigma, d, h, u, prev):

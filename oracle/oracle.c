@@ -41,7 +41,11 @@
  *     v_d + (d-k)R and every step of F are rounded toward -inf, W and E
  *     toward +inf, and the reported bound d (R - E) toward -inf.  The C
  *     rounding mode is switched with fesetround and the file is compiled with
- *     -frounding-math -ffp-contract=off.
+ *     -frounding-math -ffp-contract=off.  gcc does not promise to keep
+ *     floating-point operations on the right side of a mode switch, so single
+ *     operations go through rnd_add / rnd_mul (operands and result held in
+ *     volatile objects between the switches) and F itself is evaluated by a
+ *     call that is never inlined.
  */
 #include <fenv.h>
 #include <math.h>
@@ -112,17 +116,18 @@ static double pairwise_sum(const double *x, uint64_t n)
 /* F_z and F at one coordinate (Algorithm 1, eq. (4))                  */
 /* ------------------------------------------------------------------ */
 
-/* Reads of lag k go through get(k, index).  shift[k] is added to every value
- * read from lag k before it is averaged (0 for the plain iteration,
- * (d-k)R for the certificate's F(v_d + (d-1)R, ..., v_d)). */
+/* Reads of lag k go through lag_value(k, index).  shift[k] is added to every
+ * value read from lag k before it is averaged (no shift for the plain
+ * iteration, (d-k)R for the certificate's F(v_d + (d-1)R, ..., v_d)). */
 typedef struct {
-    const double *const *lag; /* lag[k] for k = 1..d; lag[0] unused */
+    const void *const *lag;   /* lag[k] for k = 1..d; lag[0] unused */
+    int f32;                  /* lag tables hold floats (read as exact doubles) */
     const double *shift;      /* shift[k] for k = 1..d, or NULL */
 } or_args;
 
 static double lag_value(const or_args *a, int k, uint64_t idx)
 {
-    double v = a->lag[k][idx];
+    double v = a->f32 ? (double)((const float *)a->lag[k])[idx] : ((const double *)a->lag[k])[idx];
     if (a->shift) v = v + a->shift[k];
     return v;
 }
@@ -170,6 +175,44 @@ static double F_at(const or_shape *s, const or_args *a, uint64_t idx,
         if (!skip && v > best) best = v;
     }
     return all_match ? 1.0 + best : best;
+}
+
+/* a + b and a * b under rounding `mode`: the operands are read and the result
+ * written through volatile objects between the two switches, so the operation
+ * cannot be moved outside them. */
+static double rnd_add(double a, double b, int mode)
+{
+    volatile double x = a, y = b;
+    fesetround(mode);
+    volatile double r = x + y;
+    fesetround(FE_TONEAREST);
+    return r;
+}
+
+static double rnd_mul(double a, double b, int mode)
+{
+    volatile double x = a, y = b;
+    fesetround(mode);
+    volatile double r = x * y;
+    fesetround(FE_TONEAREST);
+    return r;
+}
+
+/* F at one coordinate with every step rounded toward -inf */
+static __attribute__((noinline)) double F_at_noinline(const or_shape *s, const or_args *a,
+                                                      uint64_t idx, double *buf, int *sym,
+                                                      int *work)
+{
+    return F_at(s, a, idx, buf, sym, work);
+}
+
+static double F_at_down(const or_shape *s, const or_args *a, uint64_t idx, double *buf,
+                        int *sym, int *work)
+{
+    fesetround(FE_DOWNWARD);
+    volatile double f = F_at_noinline(s, a, idx, buf, sym, work);
+    fesetround(FE_TONEAREST);
+    return f;
 }
 
 /* scratch for one F evaluation */
@@ -223,10 +266,10 @@ int or_sweep(int sigma, int d, int h, const double *const *lags, double *out)
 {
     or_shape s;
     if (shape_init(&s, sigma, d, h)) return -1;
-    const double *lag[OR_MAX_D + 1];
+    const void *lag[OR_MAX_D + 1];
     lag[0] = NULL;
     for (int k = 1; k <= d; ++k) lag[k] = lags[k - 1];
-    or_args a = {lag, NULL};
+    or_args a = {lag, 0, NULL};
     or_scratch w;
     if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
     for (uint64_t i = 0; i < s.n_entries; ++i) out[i] = F_at(&s, &a, i, w.buf, w.sym, w.work);
@@ -235,15 +278,15 @@ int or_sweep(int sigma, int d, int h, const double *const *lags, double *out)
 }
 
 /* Same as or_sweep, for a list of coordinates only (sampled checks). */
-int or_sweep_at(int sigma, int d, int h, const double *const *lags,
-                const uint64_t *idx, uint64_t count, double *out)
+static int sweep_at(int sigma, int d, int h, const void *const *lags, int f32,
+                    const uint64_t *idx, uint64_t count, double *out)
 {
     or_shape s;
     if (shape_init(&s, sigma, d, h)) return -1;
-    const double *lag[OR_MAX_D + 1];
+    const void *lag[OR_MAX_D + 1];
     lag[0] = NULL;
     for (int k = 1; k <= d; ++k) lag[k] = lags[k - 1];
-    or_args a = {lag, NULL};
+    or_args a = {lag, f32, NULL};
     or_scratch w;
     if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
     for (uint64_t i = 0; i < count; ++i) {
@@ -252,6 +295,19 @@ int or_sweep_at(int sigma, int d, int h, const double *const *lags,
     }
     scratch_free(&w);
     return 0;
+}
+
+int or_sweep_at(int sigma, int d, int h, const double *const *lags,
+                const uint64_t *idx, uint64_t count, double *out)
+{
+    return sweep_at(sigma, d, h, (const void *const *)lags, 0, idx, count, out);
+}
+
+/* float tables, every value read as the double it represents exactly */
+int or_sweep_at_f32(int sigma, int d, int h, const float *const *lags,
+                    const uint64_t *idx, uint64_t count, double *out)
+{
+    return sweep_at(sigma, d, h, (const void *const *)lags, 1, idx, count, out);
 }
 
 /* ------------------------------------------------------------------ */
@@ -270,17 +326,14 @@ typedef struct {
 
 /* W[A] for a given R, with the rounding directions stated above.  Must be
  * called with the rounding mode at FE_TONEAREST; restores it. */
-static double W_at(const or_shape *s, const double *u, double R, uint64_t idx,
-                   const double *const *lag, const double *shift, or_scratch *w)
+static double W_at(const or_shape *s, const void *u, int f32, double R, uint64_t idx,
+                   const void *const *lag, const double *shift, or_scratch *w)
 {
-    or_args a = {lag, shift};
-    fesetround(FE_DOWNWARD);
-    double f_lo = F_at(s, &a, idx, w->buf, w->sym, w->work);
-    fesetround(FE_UPWARD);
-    double dR = (double)s->d * R;
-    double Wv = (u[idx] + dR) - f_lo;
-    fesetround(FE_TONEAREST);
-    return Wv;
+    or_args a = {lag, f32, shift};
+    double f_lo = F_at_down(s, &a, idx, w->buf, w->sym, w->work);
+    double dR = rnd_mul((double)s->d, R, FE_UPWARD);
+    double uA = f32 ? (double)((const float *)u)[idx] : ((const double *)u)[idx];
+    return rnd_add(rnd_add(uA, dR, FE_UPWARD), -f_lo, FE_UPWARD);
 }
 
 /* The d shifted arguments v_d + (d-k)R, rounded down.  Each lag reads u and
@@ -288,9 +341,7 @@ static double W_at(const or_shape *s, const double *u, double R, uint64_t idx,
  * so the shifted argument never exceeds its exact value. */
 static void make_shift(const or_shape *s, double R, double *shift)
 {
-    fesetround(FE_DOWNWARD);
-    for (int k = 1; k <= s->d; ++k) shift[k] = (double)(s->d - k) * R;
-    fesetround(FE_TONEAREST);
+    for (int k = 1; k <= s->d; ++k) shift[k] = rnd_mul((double)(s->d - k), R, FE_DOWNWARD);
 }
 
 int or_certify(int sigma, int d, int h, const double *u, const double *prev, or_cert *out)
@@ -309,7 +360,7 @@ int or_certify(int sigma, int d, int h, const double *u, const double *prev, or_
     c.R = R;
     double shift[OR_MAX_D + 1];
     make_shift(&s, R, shift);
-    const double *lag[OR_MAX_D + 1];
+    const void *lag[OR_MAX_D + 1];
     lag[0] = NULL;
     for (int k = 1; k <= d; ++k) lag[k] = u;
     or_scratch w;
@@ -317,7 +368,7 @@ int or_certify(int sigma, int d, int h, const double *u, const double *prev, or_
     double maxW = -INFINITY;
     uint64_t arg = 0;
     for (uint64_t i = 0; i < s.n_entries; ++i) {
-        double Wv = W_at(&s, u, R, i, lag, shift, &w);
+        double Wv = W_at(&s, u, 0, R, i, lag, shift, &w);
         if (!isfinite(Wv)) c.nonfinite++;
         if (Wv > maxW) { maxW = Wv; arg = i; }
     }
@@ -325,33 +376,72 @@ int or_certify(int sigma, int d, int h, const double *u, const double *prev, or_
     c.maxW = maxW;
     c.argmax_W = arg;
     c.E = maxW > 0.0 ? maxW : 0.0;
-    fesetround(FE_DOWNWARD);
-    c.rho = c.R - c.E;
-    c.bound = (double)d * c.rho;
-    fesetround(FE_TONEAREST);
+    c.rho = rnd_add(c.R, -c.E, FE_DOWNWARD);
+    c.bound = rnd_mul((double)d, c.rho, FE_DOWNWARD);
     *out = c;
     return 0;
 }
 
 /* W at a list of coordinates for a given R (sampled checks at sizes where a
  * whole-table pass is too slow). */
-int or_certify_W_at(int sigma, int d, int h, const double *u, double R,
-                    const uint64_t *idx, uint64_t count, double *out)
+static int certify_W_at(int sigma, int d, int h, const void *u, int f32, double R,
+                        const uint64_t *idx, uint64_t count, double *out)
 {
     or_shape s;
     if (shape_init(&s, sigma, d, h)) return -1;
     double shift[OR_MAX_D + 1];
     make_shift(&s, R, shift);
-    const double *lag[OR_MAX_D + 1];
+    const void *lag[OR_MAX_D + 1];
     lag[0] = NULL;
     for (int k = 1; k <= d; ++k) lag[k] = u;
     or_scratch w;
     if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
     for (uint64_t i = 0; i < count; ++i) {
         if (idx[i] >= s.n_entries) { scratch_free(&w); return -1; }
-        out[i] = W_at(&s, u, R, idx[i], lag, shift, &w);
+        out[i] = W_at(&s, u, f32, R, idx[i], lag, shift, &w);
     }
     scratch_free(&w);
+    return 0;
+}
+
+int or_certify_W_at(int sigma, int d, int h, const double *u, double R,
+                    const uint64_t *idx, uint64_t count, double *out)
+{
+    return certify_W_at(sigma, d, h, u, 0, R, idx, count, out);
+}
+
+int or_certify_W_at_f32(int sigma, int d, int h, const float *u, double R,
+                        const uint64_t *idx, uint64_t count, double *out)
+{
+    return certify_W_at(sigma, d, h, u, 1, R, idx, count, out);
+}
+
+/* R = max_j (u - prev)[j] of Algorithm 2 alone (round to nearest), for
+ * whole tables too large for or_certify; the float variant reads exact
+ * doubles.  *arg = lowest index attaining it. */
+int or_max_diff(const double *u, const double *prev, uint64_t n, double *R, uint64_t *arg)
+{
+    double best = -INFINITY;
+    uint64_t at = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        double diff = u[i] - prev[i];
+        if (diff > best) { best = diff; at = i; }
+    }
+    *R = best;
+    *arg = at;
+    return 0;
+}
+
+int or_max_diff_f32(const float *u, const float *prev, uint64_t n, double *R, uint64_t *arg)
+{
+    double best = -INFINITY;
+    uint64_t at = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        double diff = (double)u[i] - (double)prev[i];
+        if (diff > best) { best = diff; at = i; }
+    }
+    *R = best;
+    *arg = at;
     return 0;
 }
 
@@ -412,10 +502,8 @@ int or_feasible_triplet(int sigma, int d, int h, int64_t n_sweeps, int64_t caden
             }
             nh++;
             /* keep (u, r, eps) <- (v_d, R, E) when R - E >= r - eps */
-            fesetround(FE_DOWNWARD);
-            double cur = c.R - c.E;
-            double old = r_best - eps_best;
-            fesetround(FE_TONEAREST);
+            double cur = rnd_add(c.R, -c.E, FE_DOWNWARD);
+            double old = rnd_add(r_best, -eps_best, FE_DOWNWARD);
             if (c.nonfinite == 0 && cur >= old) {
                 r_best = c.R; eps_best = c.E; bound_best = c.bound; sweep_best = (double)t;
             }

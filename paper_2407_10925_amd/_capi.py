@@ -1,0 +1,77 @@
+"""ctypes declarations of the C ABI in include/lcsb.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblcsb.so")
+
+LCSB_OK = 0
+LCSB_EINVAL = -1
+LCSB_ENOMEM = -2
+LCSB_EHIP = -3
+LCSB_ESTATE = -4
+LCSB_EUNSUPPORTED = -5
+LCSB_ENONFINITE = -6
+LCSB_F64 = 0
+LCSB_F32 = 1
+
+_NAMES = {0: "LCSB_OK", -1: "LCSB_EINVAL", -2: "LCSB_ENOMEM", -3: "LCSB_EHIP",
+          -4: "LCSB_ESTATE", -5: "LCSB_EUNSUPPORTED", -6: "LCSB_ENONFINITE"}
+
+
+class LcsbError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+class Cert(C.Structure):
+    _fields_ = [("bound", C.c_double), ("R", C.c_double), ("E", C.c_double),
+                ("maxW", C.c_double), ("rho", C.c_double), ("sweep", C.c_int64),
+                ("argmax_W", C.c_uint64), ("nonfinite", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+P = C.c_void_p
+
+
+def load():
+    """Load the in-tree liblcsb.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(LIB_PATH)
+    L.lcsb_last_error.restype = C.c_char_p
+    L.lcsb_last_error.argtypes = []
+    L.lcsb_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(P)]
+    L.lcsb_query.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                             C.POINTER(C.c_uint64)]
+    L.lcsb_bind.argtypes = [P, C.POINTER(P), C.c_int, P, P]
+    L.lcsb_init_zero.argtypes = [P]
+    L.lcsb_load_ring.argtypes = [P, C.POINTER(P), C.c_int, C.POINTER(C.c_double)]
+    L.lcsb_iterate.argtypes = [P, C.c_int64]
+    L.lcsb_certify.argtypes = [P, C.POINTER(Cert), C.POINTER(Cert)]
+    L.lcsb_lag.argtypes = [P, C.c_int, C.POINTER(P), C.POINTER(C.c_double)]
+    L.lcsb_status.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(Cert)]
+    L.lcsb_upcast.argtypes = [P, P]
+    L.lcsb_destroy.argtypes = [P]
+    for name in ("lcsb_create", "lcsb_query", "lcsb_bind", "lcsb_init_zero", "lcsb_load_ring",
+                 "lcsb_iterate", "lcsb_certify", "lcsb_lag", "lcsb_status", "lcsb_upcast",
+                 "lcsb_destroy"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(rc: int) -> int:
+    if rc != LCSB_OK:
+        raise LcsbError(rc, load().lcsb_last_error().decode(errors="replace"))
+    return rc

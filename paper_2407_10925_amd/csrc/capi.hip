@@ -1,0 +1,315 @@
+// Host side of the C ABI declared in include/lcsb.h: argument checks, the
+// ring of d+1 tables (Algorithm 2 keeps v_{n-d} .. v_n), launches on the
+// caller's stream, and the keep-best rule of Algorithm 2.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "internal.h"
+#include "rounding.h"
+
+using namespace lcsb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+enum State { kCreated = 0, kBound = 1, kReady = 2, kPoisoned = 3 };
+
+}  // namespace
+
+struct lcsb_ctx {
+    Geometry g;
+    int dtype;
+    int nbuf;
+    void *buf[4];
+    unsigned char *ws;
+    hipStream_t stream;
+    int state;
+    int head;        // ring slot holding lag 1
+    int64_t sweeps;  // sweeps since the last init
+    lcsb_cert best;
+};
+
+namespace {
+
+int slot_of_lag(const lcsb_ctx *c, int k) { return ((c->head - (k - 1)) % c->nbuf + c->nbuf) % c->nbuf; }
+
+size_t elem_size(int dtype) { return dtype == LCSB_F32 ? 4 : 8; }
+
+int hip_fail(lcsb_ctx *c, hipError_t e, const char *what)
+{
+    if (c) c->state = kPoisoned;
+    return fail(LCSB_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int need_ready(const lcsb_ctx *c)
+{
+    if (!c) return fail(LCSB_EINVAL, "null context");
+    if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
+    if (c->state != kReady) return fail(LCSB_ESTATE, "context not initialised (bind, then init)");
+    return LCSB_OK;
+}
+
+lcsb_cert initial_best()
+{
+    lcsb_cert b;
+    memset(&b, 0, sizeof b);
+    return b;  // (u, r, eps) = (v_0, 0, 0): rho = 0, bound = 0
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lcsb_last_error(void) { return g_err.c_str(); }
+
+int lcsb_create(int sigma, int d, int h, int dtype, lcsb_ctx **out)
+{
+    if (!out) return fail(LCSB_EINVAL, "out is null");
+    *out = nullptr;
+    if (dtype != LCSB_F64 && dtype != LCSB_F32) return fail(LCSB_EINVAL, "dtype %d", dtype);
+    if (sigma < 2 || d < 1 || h < 1) return fail(LCSB_EINVAL, "sigma=%d d=%d h=%d", sigma, d, h);
+    const bool ok = (sigma == 2 && d == 2) || (sigma == 4 && d == 2) || (sigma == 2 && d == 3);
+    if (!ok) return fail(LCSB_EUNSUPPORTED, "no GPU kernel for sigma=%d d=%d", sigma, d);
+    const int beta = sigma == 2 ? 1 : 2;
+    const int bits = beta * d * h;
+    if (bits > 34) return fail(LCSB_EINVAL, "sigma^(d h) = 2^%d exceeds 2^34", bits);
+    lcsb_ctx *c = new (std::nothrow) lcsb_ctx;
+    if (!c) return fail(LCSB_ENOMEM, "context allocation failed");
+    memset(c, 0, sizeof *c);
+    c->g.sigma = sigma;
+    c->g.d = d;
+    c->g.h = h;
+    c->g.beta = beta;
+    c->g.slot = beta * d;
+    c->g.n = 1ull << bits;
+    c->dtype = dtype;
+    c->nbuf = d + 1;
+    c->state = kCreated;
+    c->best = initial_best();
+    *out = c;
+    return LCSB_OK;
+}
+
+int lcsb_query(const lcsb_ctx *c, int *nbuf, uint64_t *entries, uint64_t *bytes_per_buf,
+               uint64_t *workspace_bytes)
+{
+    if (!c) return fail(LCSB_EINVAL, "null context");
+    if (nbuf) *nbuf = c->nbuf;
+    if (entries) *entries = c->g.n;
+    if (bytes_per_buf) *bytes_per_buf = c->g.n * elem_size(c->dtype);
+    if (workspace_bytes) *workspace_bytes = Ws::kBytes;
+    return LCSB_OK;
+}
+
+int lcsb_bind(lcsb_ctx *c, void *const *bufs, int nbuf, void *ws, void *stream)
+{
+    if (!c) return fail(LCSB_EINVAL, "null context");
+    if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
+    if (!bufs || nbuf != c->nbuf) return fail(LCSB_EINVAL, "need %d ring buffers", c->nbuf);
+    if (!ws || ((uintptr_t)ws & 255)) return fail(LCSB_EINVAL, "workspace null or not 256-byte aligned");
+    for (int k = 0; k < nbuf; ++k) {
+        if (!bufs[k] || ((uintptr_t)bufs[k] & 255))
+            return fail(LCSB_EINVAL, "ring buffer %d null or not 256-byte aligned", k);
+        for (int j = 0; j < k; ++j)
+            if (bufs[j] == bufs[k]) return fail(LCSB_EINVAL, "ring buffers %d and %d alias", j, k);
+    }
+    for (int k = 0; k < nbuf; ++k) c->buf[k] = bufs[k];
+    c->ws = static_cast<unsigned char *>(ws);
+    c->stream = static_cast<hipStream_t>(stream);
+    c->state = kBound;
+    c->head = 0;
+    c->sweeps = 0;
+    c->best = initial_best();
+    return LCSB_OK;
+}
+
+int lcsb_init_zero(lcsb_ctx *c)
+{
+    if (!c) return fail(LCSB_EINVAL, "null context");
+    if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
+    if (c->state < kBound) return fail(LCSB_ESTATE, "bind before init");
+    const uint64_t bytes = c->g.n * elem_size(c->dtype);
+    hipError_t e;
+    for (int k = 0; k < c->nbuf; ++k)
+        if ((e = launch_fill_zero(c->buf[k], bytes, c->stream)) != hipSuccess)
+            return hip_fail(c, e, "fill");
+    if ((e = launch_fill_zero(c->ws, Ws::kBytes, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "fill workspace");
+    c->head = 0;
+    c->sweeps = 0;
+    c->best = initial_best();
+    c->state = kReady;
+    return LCSB_OK;
+}
+
+int lcsb_load_ring(lcsb_ctx *c, const void *const *src, int nsrc, const double *offsets)
+{
+    if (!c) return fail(LCSB_EINVAL, "null context");
+    if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
+    if (c->state < kBound) return fail(LCSB_ESTATE, "bind before load");
+    if (!src || nsrc != c->g.d) return fail(LCSB_EINVAL, "need d = %d source tables", c->g.d);
+    for (int k = 0; k < nsrc; ++k) {
+        if (!src[k]) return fail(LCSB_EINVAL, "source %d is null", k);
+        for (int j = 0; j < c->nbuf; ++j)
+            if (src[k] == c->buf[j]) return fail(LCSB_EINVAL, "source %d aliases a ring buffer", k);
+    }
+    hipError_t e;
+    if ((e = launch_fill_zero(c->ws, Ws::kBytes, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "fill workspace");
+    c->head = 0;
+    for (int k = 1; k <= c->g.d; ++k) {
+        const int slot = slot_of_lag(c, k);
+        if ((e = launch_project_copy(c->g, c->dtype, src[k - 1], c->buf[slot], c->stream)) != hipSuccess)
+            return hip_fail(c, e, "project copy");
+        if (c->dtype == LCSB_F32) {
+            double o = offsets ? offsets[k - 1] : 0.0;
+            double *dev = reinterpret_cast<double *>(c->ws + Ws::kOffsets) + slot;
+            if ((e = launch_fill_f64(dev, 1, o, c->stream)) != hipSuccess)
+                return hip_fail(c, e, "offset");
+        }
+    }
+    c->sweeps = 0;
+    c->best = initial_best();
+    c->state = kReady;
+    return LCSB_OK;
+}
+
+int lcsb_iterate(lcsb_ctx *c, int64_t k)
+{
+    int rc = need_ready(c);
+    if (rc) return rc;
+    if (k < 0) return fail(LCSB_EINVAL, "negative sweep count");
+    for (int64_t t = 0; t < k; ++t) {
+        SweepLaunch a;
+        memset(&a, 0, sizeof a);
+        for (int j = 1; j <= c->g.d; ++j) {
+            a.lag_slot[j - 1] = slot_of_lag(c, j);
+            a.lag[j - 1] = c->buf[a.lag_slot[j - 1]];
+        }
+        a.new_slot = (c->head + 1) % c->nbuf;
+        a.out = c->buf[a.new_slot];
+        a.offsets = reinterpret_cast<double *>(c->ws + Ws::kOffsets);
+        hipError_t e = launch_sweep(c->g, c->dtype, a, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+        c->head = a.new_slot;
+        c->sweeps++;
+    }
+    return LCSB_OK;
+}
+
+int lcsb_certify(lcsb_ctx *c, lcsb_cert *cur, lcsb_cert *best)
+{
+    int rc = need_ready(c);
+    if (rc) return rc;
+    const int su = slot_of_lag(c, 1), sp = slot_of_lag(c, 2);
+    hipError_t e = launch_certify(c->g, c->dtype, c->buf[su], c->buf[sp], su, sp, c->ws, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "certify launch");
+    unsigned char host[Ws::kScalarBytes];
+    if ((e = hipMemcpyAsync(host, c->ws, Ws::kScalarBytes, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "certify copy");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "certify sync");
+    double sc[Ws::kScalarBytes / 8];
+    memcpy(sc, host, sizeof sc);
+    lcsb_cert k;
+    memset(&k, 0, sizeof k);
+    k.R = sc[Ws::kR / 8];
+    k.maxW = sc[Ws::kMaxW / 8];
+    uint64_t u64[Ws::kScalarBytes / 8];
+    memcpy(u64, host, sizeof u64);
+    k.argmax_W = u64[Ws::kArgmax / 8];
+    k.nonfinite = u64[Ws::kNonfinite / 8] + u64[Ws::kNonfiniteR / 8];
+    k.E = k.maxW > 0.0 ? k.maxW : 0.0;
+    k.rho = add_rd(k.R, -k.E);
+    k.bound = mul_rd((double)c->g.d, k.rho);
+    k.sweep = c->sweeps;
+    // keep (u, r, eps) <- (v_d, R, E) when R - E >= r - eps (Algorithm 2)
+    if (k.nonfinite == 0 && k.rho >= c->best.rho) c->best = k;
+    if (cur) *cur = k;
+    if (best) *best = c->best;
+    if (k.nonfinite) return fail(LCSB_ENONFINITE, "%llu non-finite values in the certified tables",
+                                 (unsigned long long)k.nonfinite);
+    return LCSB_OK;
+}
+
+int lcsb_lag(const lcsb_ctx *c, int k, void **dev_ptr, double *offset)
+{
+    int rc = need_ready(c);
+    if (rc) return rc;
+    if (k < 1 || k > c->g.d) return fail(LCSB_EINVAL, "lag %d outside 1..%d", k, c->g.d);
+    const int slot = slot_of_lag(c, k);
+    if (dev_ptr) *dev_ptr = c->buf[slot];
+    if (offset) {
+        *offset = 0.0;
+        if (c->dtype == LCSB_F32) {
+            hipError_t e = hipMemcpyAsync(offset, c->ws + Ws::kOffsets + 8 * slot, 8,
+                                          hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) return fail(LCSB_EHIP, "offset read: %s", hipGetErrorString(e));
+        }
+    }
+    return LCSB_OK;
+}
+
+int lcsb_status(const lcsb_ctx *c, int64_t *sweeps, lcsb_cert *best)
+{
+    if (!c) return fail(LCSB_EINVAL, "null context");
+    if (sweeps) *sweeps = c->sweeps;
+    if (best) *best = c->best;
+    return LCSB_OK;
+}
+
+int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
+{
+    int rc = need_ready(src);
+    if (rc) return rc;
+    if (!dst) return fail(LCSB_EINVAL, "null destination");
+    if (dst->state == kPoisoned) return fail(LCSB_ESTATE, "destination poisoned");
+    if (dst->state < kBound) return fail(LCSB_ESTATE, "bind the destination first");
+    if (src->dtype != LCSB_F32 || dst->dtype != LCSB_F64)
+        return fail(LCSB_EINVAL, "upcast goes from an FP32 to an FP64 context");
+    if (src->g.sigma != dst->g.sigma || src->g.d != dst->g.d || src->g.h != dst->g.h)
+        return fail(LCSB_EINVAL, "shape mismatch");
+    hipError_t e = hipStreamSynchronize(src->stream);
+    if (e != hipSuccess) return fail(LCSB_EHIP, "source sync: %s", hipGetErrorString(e));
+    if ((e = launch_fill_zero(dst->ws, Ws::kBytes, dst->stream)) != hipSuccess)
+        return hip_fail(dst, e, "fill workspace");
+    dst->head = src->head;
+    for (int k = 1; k <= src->g.d; ++k) {
+        const int slot = slot_of_lag(src, k);
+        const double *off = reinterpret_cast<const double *>(src->ws + Ws::kOffsets) + slot;
+        if ((e = launch_upcast(src->g, static_cast<const float *>(src->buf[slot]), off,
+                               static_cast<double *>(dst->buf[slot]), dst->stream)) != hipSuccess)
+            return hip_fail(dst, e, "upcast");
+    }
+    dst->sweeps = src->sweeps;
+    dst->best = src->best;
+    dst->state = kReady;
+    return LCSB_OK;
+}
+
+int lcsb_destroy(lcsb_ctx *c)
+{
+    delete c;
+    return LCSB_OK;
+}
+
+}  // extern "C"

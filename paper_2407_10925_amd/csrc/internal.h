@@ -1,0 +1,63 @@
+// Declarations shared by the library's translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lcsb.h"
+
+namespace lcsb {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts)
+constexpr int kMaxReduceBlocks = 4096;
+
+// Device workspace layout (byte offsets).  The caller allocates
+// kWorkspaceBytes; the library clears the parts it uses.
+struct Ws {
+    // scalars written by the certificate kernels
+    static constexpr size_t kR = 0;          // double: R (offset-corrected)
+    static constexpr size_t kDRup = 8;       // double: d*R rounded up
+    static constexpr size_t kShift = 16;     // double[4]: (d-k)R rounded down, k = 0..3
+    static constexpr size_t kMaxW = 48;      // double
+    static constexpr size_t kArgmax = 56;    // uint64
+    static constexpr size_t kNonfinite = 64; // uint64: W pass
+    static constexpr size_t kNonfiniteR = 72;// uint64: R pass (u, prev)
+    static constexpr size_t kScalarBytes = 80;
+    // FP64 offsets of the FP32 tables, one per ring slot
+    static constexpr size_t kOffsets = 256;  // double[8]
+    // per-workgroup partials of the reductions
+    static constexpr size_t kPartVal = 512;                                  // double[kMaxReduceBlocks]
+    static constexpr size_t kPartIdx = kPartVal + 8 * kMaxReduceBlocks;      // uint64[kMaxReduceBlocks]
+    static constexpr size_t kPartCnt = kPartIdx + 8 * kMaxReduceBlocks;      // uint64[kMaxReduceBlocks]
+    static constexpr size_t kBytes = kPartCnt + 8 * kMaxReduceBlocks;
+};
+
+struct Geometry {
+    int sigma, d, h, beta, slot;  // slot = bits per position = d * beta
+    uint64_t n;                   // sigma^(d h) entries
+};
+
+// One sweep: reads lag 1..d (ring slots lag_slot[0..d-1]), writes slot new_slot.
+struct SweepLaunch {
+    const void *lag[3];
+    void *out;
+    int lag_slot[3];
+    int new_slot;
+    double *offsets;  // device, per slot (FP32 only)
+};
+
+hipError_t launch_sweep(const Geometry &g, int dtype, const SweepLaunch &a, hipStream_t s);
+
+// Certificate passes (see lcsb_cert); results land in the workspace scalars.
+hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const void *prev,
+                          int u_slot, int prev_slot, unsigned char *ws, hipStream_t s);
+
+// Utilities
+hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
+hipError_t launch_fill_f64(double *p, uint64_t count, double v, hipStream_t s);
+hipError_t launch_project_copy(const Geometry &g, int dtype, const void *src, void *dst,
+                               hipStream_t s);
+hipError_t launch_upcast(const Geometry &g, const float *src, const double *offset_dev,
+                         double *dst, hipStream_t s);
+
+}  // namespace lcsb

@@ -1,0 +1,83 @@
+"""The C-ABI library loads and exports what include/lcsb.h declares; host-only
+argument checks.  No call here touches a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lcsb.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lcsb_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2407_10925_amd import _capi
+    if not os.path.exists(_capi.LIB_PATH):
+        pytest.fail("liblcsb.so is not built (run __graft_entry__.build())")
+    return _capi.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_create_validates_arguments(lib):
+    from paper_2407_10925_amd import _capi
+    ctx = C.c_void_p()
+    assert lib.lcsb_create(3, 2, 2, 0, C.byref(ctx)) == _capi.LCSB_EUNSUPPORTED
+    assert lib.lcsb_create(2, 4, 2, 0, C.byref(ctx)) == _capi.LCSB_EUNSUPPORTED
+    assert lib.lcsb_create(2, 2, 0, 0, C.byref(ctx)) == _capi.LCSB_EINVAL
+    assert lib.lcsb_create(2, 2, 18, 0, C.byref(ctx)) == _capi.LCSB_EINVAL  # 2^36 > 2^34
+    assert lib.lcsb_create(2, 2, 6, 7, C.byref(ctx)) == _capi.LCSB_EINVAL
+    assert b"dtype" in lib.lcsb_last_error()
+    assert lib.lcsb_create(2, 2, 6, 0, None) == _capi.LCSB_EINVAL
+
+
+@pytest.mark.parametrize("sigma,d,h,dtype,n,elem", [(2, 2, 6, 0, 4096, 8), (2, 2, 16, 1, 2**32, 4),
+                                                    (4, 2, 8, 1, 2**32, 4), (2, 3, 10, 1, 2**30, 4),
+                                                    (2, 2, 17, 1, 2**34, 4)])
+def test_query_sizes(lib, sigma, d, h, dtype, n, elem):
+    ctx = C.c_void_p()
+    assert lib.lcsb_create(sigma, d, h, dtype, C.byref(ctx)) == 0
+    nbuf, ent, bpb, ws = C.c_int(), C.c_uint64(), C.c_uint64(), C.c_uint64()
+    assert lib.lcsb_query(ctx, C.byref(nbuf), C.byref(ent), C.byref(bpb), C.byref(ws)) == 0
+    assert (nbuf.value, ent.value, bpb.value) == (d + 1, n, n * elem)
+    assert ws.value > 0 and ws.value % 256 == 0
+    assert lib.lcsb_destroy(ctx) == 0
+
+
+def test_call_order_is_enforced_without_a_gpu(lib):
+    from paper_2407_10925_amd import _capi
+    ctx = C.c_void_p()
+    assert lib.lcsb_create(2, 2, 4, 0, C.byref(ctx)) == 0
+    assert lib.lcsb_iterate(ctx, 1) == _capi.LCSB_ESTATE
+    assert lib.lcsb_certify(ctx, None, None) == _capi.LCSB_ESTATE
+    assert lib.lcsb_init_zero(ctx) == _capi.LCSB_ESTATE
+    # bind checks pointers before storing anything
+    assert lib.lcsb_bind(ctx, None, 3, None, None) == _capi.LCSB_EINVAL
+    bufs = (C.c_void_p * 3)(256, 512, 256)  # aliasing, never dereferenced
+    assert lib.lcsb_bind(ctx, bufs, 3, C.c_void_p(1024), None) == _capi.LCSB_EINVAL
+    bufs = (C.c_void_p * 3)(256, 512, 768)
+    assert lib.lcsb_bind(ctx, bufs, 3, C.c_void_p(1000), None) == _capi.LCSB_EINVAL  # misaligned ws
+    assert lib.lcsb_bind(ctx, bufs, 2, C.c_void_p(1024), None) == _capi.LCSB_EINVAL
+    assert lib.lcsb_destroy(ctx) == 0
+    assert lib.lcsb_destroy(None) == 0
+
+
+def test_python_binding_refuses_without_gpu():
+    import torch
+    import paper_2407_10925_amd as pk
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        pk.Lcsb(2, 2, 4)

@@ -1,0 +1,295 @@
+"""GPU parity: the gfx950 library (through its C ABI) against the CPU oracle.
+
+FP64 sweeps and every certificate must be bit-identical to the oracle on the
+same seeded inputs.  FP32 sweeps are compared with the oracle's FP64 values
+within the FP32 error bound stated in each test.  Inputs come from
+tests/seeded_inputs.py only; nothing the GPU computes is fed to the oracle.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+CERT_KEYS = ("R", "maxW", "E", "rho", "bound", "argmax_W", "nonfinite")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pk():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2407_10925_amd as pk
+    return pk
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _same_cert(gpu, ref):
+    for k in CERT_KEYS:
+        a, b = gpu[k], ref[k]
+        assert (a == b) or (isinstance(a, float) and math.isnan(a) and math.isnan(b)), (k, a, b)
+
+
+# ------------------------------------------------------------------ FP64, zero start
+@pytest.mark.parametrize("sigma,d,h,sweeps,printed", [
+    (2, 2, 6, 200, 0.770273),   # Table 2, l = 6
+    (2, 2, 1, 60, 0.666666),    # Table 2, l = 1
+    (4, 2, 2, 120, 0.542373),   # Appendix C, l = 2
+    (2, 3, 3, 150, 0.687410),   # Appendix C, l = 3
+])
+def test_fp64_zero_start_trajectory_is_bit_exact(pk, sigma, d, h, sweeps, printed):
+    say(f"zero-start FP64 sigma={sigma} d={d} h={h} sweeps={sweeps}")
+    L = pk.Lcsb(sigma, d, h, "f64")
+    L.init_zero()
+    N = sigma ** (d * h)
+    ring = [np.zeros(N) for _ in range(d)]
+    best_ref = {"rho": 0.0, "bound": 0.0, "sweep": 0}  # the initial triplet (v_0, 0, 0)
+    for t in range(1, sweeps + 1):
+        new = oracle.sweep(sigma, d, h, ring)
+        L.iterate(1)
+        got, off = L.lag(1)
+        assert off == 0.0
+        assert np.array_equal(_host(got), new), f"sweep {t}"
+        ring = [new] + ring[:-1]
+        cur, best = L.certify()
+        ref = oracle.certify(sigma, d, h, ring[0], ring[1])
+        _same_cert(cur, ref)
+        assert cur["sweep"] == t
+        if ref["nonfinite"] == 0 and ref["rho"] >= best_ref["rho"]:  # Algorithm 2's keep rule
+            best_ref = {"rho": ref["rho"], "bound": ref["bound"], "sweep": t}
+        assert (best["bound"], best["sweep"]) == (best_ref["bound"], best_ref["sweep"])
+    b = best["bound"]
+    assert {round(math.floor(b * 1e6) / 1e6, 6), round(b, 6)} & {printed}
+
+
+# ------------------------------------------------------------------ FP64, random tables
+CASES = [(2, 2, h) for h in (1, 2, 3, 5, 8, 10)] + [(4, 2, h) for h in (1, 2, 3, 4)] + \
+        [(2, 3, h) for h in (1, 2, 3, 5, 6)]
+
+
+@pytest.mark.parametrize("sigma,d,h", CASES, ids=lambda v: str(v))
+def test_fp64_random_ring_one_sweep_and_certificate(pk, sigma, d, h):
+    say(f"random FP64 ring sigma={sigma} d={d} h={h}")
+    lags = [si.table(sigma, d, h, seed=10 + k, dtype=torch.float64) for k in range(d)]
+    L = pk.Lcsb(sigma, d, h, "f64")
+    L.load_ring([x.cuda() for x in lags])
+    # certificate of the loaded ring (u = lag 1, prev = lag 2)
+    cur, _ = L.certify()
+    _same_cert(cur, oracle.certify(sigma, d, h, lags[0].numpy(), lags[1].numpy()))
+    L.iterate(1)
+    new = oracle.sweep(sigma, d, h, [x.numpy() for x in lags])
+    got, _ = L.lag(1)
+    assert np.array_equal(_host(got), new)
+    cur, _ = L.certify()
+    _same_cert(cur, oracle.certify(sigma, d, h, new, lags[0].numpy()))
+
+
+def test_load_ring_projects_onto_symmetric_tables(pk):
+    say("load_ring projection")
+    sigma, d, h = 4, 2, 3
+    raw = [si.table(sigma, d, h, seed=40 + k, symmetric=False) for k in range(d)]
+    sym = [si.table(sigma, d, h, seed=40 + k, symmetric=True) for k in range(d)]
+    L = pk.Lcsb(sigma, d, h, "f64")
+    L.load_ring([x.cuda() for x in raw])
+    for k in (1, 2):
+        got, _ = L.lag(k)
+        assert torch.equal(got.cpu(), sym[k - 1])
+
+
+# ------------------------------------------------------------------ full size, sampled
+@pytest.mark.timeout(600)
+def test_fp64_h14_sampled_sweep_and_certificate(pk):
+    """sigma = d = 2, l = 14: 2^28 FP64 entries per table (the plain at-scale
+    configuration), one sweep from a seeded ring, checked at 20000 sampled
+    coordinates plus the head-class boundaries; the certificate's R over the
+    whole table and W at its argmax and at the samples."""
+    sigma, d, h = 2, 2, 14
+    say("h=14 FP64: generating seeded ring on the device")
+    lags_dev = [si.table(sigma, d, h, seed=20 + k, device="cuda") for k in range(d)]
+    lags = [_host(x) for x in lags_dev]
+    L = pk.Lcsb(sigma, d, h, "f64")
+    L.load_ring(lags_dev)
+    L.iterate(1)
+    say("h=14 FP64: sweep done, sampling")
+    idx = si.sample_indices(L.n, 20000, seed=3).numpy().astype(np.uint64)
+    got, _ = L.lag(1)
+    got_h = _host(got)
+    ref = oracle.sweep_at(sigma, d, h, lags, idx)
+    assert np.array_equal(got_h[idx.astype(np.int64)], ref)
+    # certificate of (u = lag1, prev = lag2) of the loaded ring, before any sweep
+    L2 = pk.Lcsb(sigma, d, h, "f64")
+    L2.load_ring(lags_dev)
+    cur, _ = L2.certify()
+    R, _ = oracle.max_diff(lags[0], lags[1])
+    assert cur["R"] == R
+    w_arg = oracle.certify_W_at(sigma, d, h, lags[0], R, np.array([cur["argmax_W"]], np.uint64))
+    assert w_arg[0] == cur["maxW"]
+    w_s = oracle.certify_W_at(sigma, d, h, lags[0], R, idx)
+    assert np.all(w_s <= cur["maxW"])
+    assert np.all(w_s[idx < cur["argmax_W"]] < cur["maxW"])  # lowest index attains it
+
+
+def _fp32_bound(values_abs_max):
+    """FP32 error of one sweep on exact float inputs, per entry: the pairwise
+    sum of at most 16 values (4 levels), the exact scaling, the offset
+    difference delta_k, the 1 +, and the shift by y0 each round once with
+    relative error 2^-24 on magnitudes at most 16 * max|input| + |delta| + 1;
+    eight roundings of that size bound the total."""
+    return 8 * 2.0 ** -24 * (16 * values_abs_max + 2)
+
+
+@pytest.mark.parametrize("sigma,d,h", [(2, 2, 4), (2, 2, 9), (4, 2, 3), (2, 3, 5)])
+def test_fp32_random_ring_one_sweep(pk, sigma, d, h):
+    say(f"random FP32 ring sigma={sigma} d={d} h={h}")
+    lags = [si.table(sigma, d, h, seed=60 + k, dtype=torch.float32) for k in range(d)]
+    offs = [0.75 * k for k in range(d)]  # lag k relative to offset 0.75 k
+    L = pk.Lcsb(sigma, d, h, "f32")
+    L.load_ring([x.cuda() for x in lags], offsets=offs)
+    L.iterate(1)
+    got, o_new = L.lag(1)
+    val = o_new + _host(got).astype(np.float64)
+    ref = oracle.sweep(sigma, d, h, [x.numpy().astype(np.float64) + o for x, o in zip(lags, offs)])
+    tol = _fp32_bound(8.0 + 0.75 * d)
+    assert np.max(np.abs(val - ref)) <= tol
+    assert _host(got)[0] == 0.0  # entry 0 is the reference entry
+    # certificate of FP32 tables: bit-exact on the loaded ring (offsets zero)
+    L2 = pk.Lcsb(sigma, d, h, "f32")
+    L2.load_ring([x.cuda() for x in lags])
+    cur, _ = L2.certify()
+    _same_cert(cur, oracle.certify(sigma, d, h, lags[0].numpy().astype(np.float64),
+                                   lags[1].numpy().astype(np.float64)))
+
+
+@pytest.mark.timeout(900)
+def test_fp32_h16_sampled_sweep_and_certificate(pk):
+    """sigma = d = 2, l = 16 in FP32 (2^32 entries per table: the benchmark's
+    configuration), one sweep from a seeded ring checked at sampled
+    coordinates against the FP64 oracle, and the certificate of the seeded
+    ring: R over the whole table, W at its argmax and at the samples."""
+    sigma, d, h = 2, 2, 16
+    free, _ = torch.cuda.mem_get_info()
+    if free < 90 * 2**30:
+        pytest.skip("needs ~80 GiB of free device memory")
+    say("h=16 FP32: generating seeded ring on the device")
+    lags_dev = [si.table(sigma, d, h, seed=80 + k, dtype=torch.float32, device="cuda")
+                for k in range(d)]
+    L = pk.Lcsb(sigma, d, h, "f32")
+    L.load_ring(lags_dev)
+    say("h=16 FP32: certificate of the seeded ring")
+    cur, _ = L.certify()
+    say("h=16 FP32: sweep")
+    L.iterate(1)
+    got, o_new = L.lag(1)
+    idx = si.sample_indices(L.n, 20000, seed=5).to("cuda")
+    got_s = got[idx].double().cpu().numpy() + o_new
+    idx = idx.cpu().numpy().astype(np.uint64)
+    say("h=16 FP32: copying the seeded ring to the host")
+    lags = [_host(x) for x in lags_dev]
+    del got, L, lags_dev  # the context holds the loaded tables until it goes
+    torch.cuda.empty_cache()
+    ref = oracle.sweep_at_tables(sigma, d, h, lags, idx)
+    assert np.max(np.abs(got_s - ref)) <= _fp32_bound(8.0)
+    say("h=16 FP32: oracle R over 2^32 entries")
+    R, _ = oracle.max_diff(lags[0], lags[1])
+    assert cur["R"] == R
+    w_arg = oracle.certify_W_at_table(sigma, d, h, lags[0], R, np.array([cur["argmax_W"]], np.uint64))
+    assert w_arg[0] == cur["maxW"]
+    w_s = oracle.certify_W_at_table(sigma, d, h, lags[0], R, idx)
+    assert np.all(w_s <= cur["maxW"])
+
+
+# ------------------------------------------------------------------ FP32 iteration, polish
+def test_fp32_zero_start_error_and_fp64_polish(pk):
+    """FP32 sweeps from zero at sigma = d = 2, l = 8 against the FP64 oracle:
+    after normalising both by entry 0, every entry is within 1e-6 of the
+    table's spread; then the FP32 ring is converted to FP64 and polished, and
+    the best certified bound comes within 1e-9 of the plain FP64 run."""
+    sigma, d, h = 2, 2, 8
+    say("FP32 zero start h=8")
+    plain, _, ring = oracle.feasible_triplet(sigma, d, h, 200, 4, want_ring=False)
+    L = pk.Lcsb(sigma, d, h, "f32")
+    L.init_zero()
+    N = 4 ** h
+    oring = [np.zeros(N), np.zeros(N)]
+    for t in range(120):
+        L.iterate(1)
+        new = oracle.sweep(sigma, d, h, oring)
+        oring = [new, oring[0]]
+    got, off = L.lag(1)
+    g = _host(got).astype(np.float64)
+    ref = oring[0] - oring[0][0]
+    spread = ref.max() - ref.min()
+    err = np.max(np.abs(g - ref)) / spread
+    say(f"FP32 per-entry error / spread after 120 sweeps: {err:.3e}")
+    assert err <= 1e-6
+    assert abs((off + g[5]) - oring[0][5]) <= 1e-6 * spread
+    P = pk.Lcsb(sigma, d, h, "f64")
+    P.upcast(L)
+    for _ in range(20):
+        P.iterate(4)
+        P.certify()
+    _, best = P.certify()
+    say(f"polished bound {best['bound']:.12f} plain {plain['bound']:.12f}")
+    assert abs(best["bound"] - plain["bound"]) <= 1e-9
+
+
+# ------------------------------------------------------------------ edges and errors
+def test_zero_sweeps_and_repeatability(pk):
+    say("repeatability h=10")
+    a = pk.Lcsb(2, 2, 10, "f64")
+    b = pk.Lcsb(2, 2, 10, "f64")
+    for L in (a, b):
+        L.init_zero()
+        L.iterate(0)
+        L.iterate(37)
+    assert torch.equal(a.lag(1)[0], b.lag(1)[0])
+    assert a.certify()[0] == b.certify()[0]
+
+
+def test_nonfinite_table_is_reported_and_never_kept(pk):
+    say("non-finite certificate")
+    sigma, d, h = 2, 2, 3
+    lags = [si.table(sigma, d, h, seed=90 + k).cuda() for k in range(d)]
+    lags[0][17] = float("nan")
+    L = pk.Lcsb(sigma, d, h, "f64")
+    L.load_ring(lags)
+    with pytest.raises(pk.LcsbError) as e:
+        L.certify()
+    assert e.value.code == -6
+    cur, best = L.certify(allow_nonfinite=True)
+    assert cur["nonfinite"] > 0
+    assert best["bound"] == 0.0 and best["sweep"] == 0
+
+
+def test_call_order_and_bad_arguments(pk):
+    from paper_2407_10925_amd import _capi
+    import ctypes as C
+    L = pk.Lcsb(2, 2, 4, "f64")
+    with pytest.raises(pk.LcsbError) as e:
+        L.iterate(1)
+    assert e.value.code == _capi.LCSB_ESTATE
+    L.init_zero()
+    with pytest.raises(pk.LcsbError):
+        L.iterate(-1)
+    with pytest.raises(pk.LcsbError):
+        L.lag(3)
+    lib = _capi.load()
+    assert lib.lcsb_load_ring(L._ctx, None, 2, None) == _capi.LCSB_EINVAL
+    same = (C.c_void_p * 2)(L.bufs[0].data_ptr(), L.bufs[1].data_ptr())
+    assert lib.lcsb_load_ring(L._ctx, same, 2, None) == _capi.LCSB_EINVAL
+    # upcast needs FP32 -> FP64
+    M = pk.Lcsb(2, 2, 4, "f64")
+    assert lib.lcsb_upcast(L._ctx, M._ctx) == _capi.LCSB_EINVAL

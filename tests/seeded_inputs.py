@@ -69,6 +69,6 @@ def sample_indices(n: int, count: int, seed: int) -> torch.Tensor:
     """Sorted distinct-ish sample of [0, n) plus both ends and the quarter
     boundaries (where the head symbols change)."""
     base = (_lsr(splitmix64(seed, torch.arange(count, dtype=torch.int64)), 1) % n)
-    edges = torch.tensor(sorted({0, 1, n - 2, n - 1, n // 4 - 1, n // 4, n // 2 - 1, n // 2,
-                                 3 * n // 4 - 1, 3 * n // 4} & set(range(n))), dtype=torch.int64)
+    cand = {0, 1, n - 2, n - 1, n // 4 - 1, n // 4, n // 2 - 1, n // 2, 3 * n // 4 - 1, 3 * n // 4}
+    edges = torch.tensor(sorted(e for e in cand if 0 <= e < n), dtype=torch.int64)
     return torch.unique(torch.cat([base, edges]))

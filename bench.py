@@ -50,6 +50,12 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-sample-log2", type=int, default=24)
     p.add_argument("--no-ttb", action="store_true", help="skip the time-to-bound runs")
+    p.add_argument("--profile-sweeps", type=int, default=0,
+                   help="only run this many FP32 sweeps from zero (for counter collection)")
+    p.add_argument("--configs", action="store_true",
+                   help="only time one sweep and one certificate for every configuration")
+    p.add_argument("--copy-gib", type=float, default=0.0,
+                   help="only run one plain device copy of this many GiB (counter calibration)")
     return p.parse_args()
 
 
@@ -102,15 +108,22 @@ def cpu_baseline(h, log2_sample):
                       f"{dt:.1f} s"}
 
 
-def time_to_bound(pk, h, log_every=True):
-    """Plain FP64 from zero to convergence (certificate every 8 sweeps; stop
-    when the current bound moves by < 1e-10 and is the best so far), then
-    FP32 from zero (certificate every 16 sweeps) switched to an FP64 polish
-    (certificate every 4 sweeps) when its certificate stalls (< 1e-7 gain),
-    until the best bound is within 1e-9 of the plain one."""
+def time_to_bound(pk, h):
+    """Wall time from the init call to the first certificate within 1e-9 of
+    the converged plain FP64 bound B.
+
+    plain:  FP64 from zero, a certificate every 16 sweeps, run until the
+            current certificate moves by less than 1e-10 and is the best so
+            far (B = that best); the time is that of the first certificate
+            >= B - 1e-9.
+    mixed:  FP32 from zero with a certificate every 32 sweeps; once a
+            certificate is positive and the best bound gains less than 1e-7
+            over a period, the FP32 ring is converted to FP64 and polished
+            with a certificate every 8 sweeps until the best bound reaches
+            B - 1e-9.
+    """
     import torch
     out = {}
-    # ---- plain FP64
     P = pk.Lcsb(2, 2, h, "f64")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -118,50 +131,114 @@ def time_to_bound(pk, h, log_every=True):
     hist = []
     prev = None
     while True:
-        P.iterate(8)
+        P.iterate(16)
         cur, best = P.certify()
         hist.append((time.perf_counter() - t0, best["bound"], cur["sweep"]))
         if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
             break
         prev = cur["bound"]
-        if cur["sweep"] > 600:
+        if cur["sweep"] >= 800:
             break
     B = best["bound"]
     target = B - 1e-9
     t_plain, s_plain = next((t, s) for t, b, s in hist if b >= target)
-    out["plain_f64"] = {"seconds": t_plain, "sweeps": s_plain, "bound": B,
-                        "converged_after_sweeps": hist[-1][2]}
+    out["plain_f64"] = {"seconds": round(t_plain, 4), "sweeps": s_plain, "bound": B,
+                        "ran_sweeps": hist[-1][2], "certificate_every": 16}
     log(f"time to bound, plain FP64: {t_plain:.3f} s, {s_plain} sweeps, bound {B:.12f}")
-    # ---- FP32 + FP64 polish (the FP64 ring of the plain run is reused)
+
     M = pk.Lcsb(2, 2, h, "f32")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     M.init_zero()
-    prev = -1.0
-    sweeps32 = 0
+    best_prev = None
     while True:
-        M.iterate(16)
+        M.iterate(32)
         cur, best = M.certify()
-        sweeps32 = cur["sweep"]
-        if best["bound"] >= target or cur["bound"] - prev < 1e-7 or sweeps32 > 600:
+        if best["bound"] >= target or cur["sweep"] >= 800:
             break
-        prev = cur["bound"]
+        if cur["bound"] > 0 and best_prev is not None and best["bound"] - best_prev < 1e-7:
+            break
+        best_prev = best["bound"]
+    sweeps32 = cur["sweep"]
     t_switch = time.perf_counter() - t0
     if best["bound"] < target:
         P.upcast(M)
-        while best["bound"] < target and cur["sweep"] < 1200:
-            P.iterate(4)
+        while best["bound"] < target and cur["sweep"] < 1600:
+            P.iterate(8)
             cur, best = P.certify()
     t_mixed = time.perf_counter() - t0
-    out["mixed_f32_polish"] = {"seconds": t_mixed, "sweeps_f32": sweeps32,
-                               "sweeps_total": cur["sweep"], "switch_after_s": t_switch,
-                               "bound": best["bound"], "reached": best["bound"] >= target}
+    out["mixed_f32_polish"] = {"seconds": round(t_mixed, 4), "sweeps_f32": sweeps32,
+                               "sweeps_f64": cur["sweep"] - sweeps32,
+                               "switch_after_s": round(t_switch, 4), "bound": best["bound"],
+                               "reached": best["bound"] >= target}
     log(f"time to bound, FP32 + FP64 polish: {t_mixed:.3f} s, {sweeps32} FP32 + "
         f"{cur['sweep'] - sweeps32} FP64 sweeps, bound {best['bound']:.12f}")
     out["mixed_learned"] = None
     del P, M
     torch.cuda.empty_cache()
     return out
+
+
+CONFIGS = [  # (sigma, d, l, dtype)
+    (2, 2, 6, "f64"), (2, 2, 14, "f64"), (2, 2, 16, "f32"), (2, 2, 16, "f64"),
+    (4, 2, 8, "f32"), (2, 3, 10, "f32"), (4, 2, 8, "f64"), (2, 3, 10, "f64"),
+]
+
+
+def config_table(pk):
+    """Average sweep and certificate time per configuration (HIP events)."""
+    import torch
+    rows = []
+    for sigma, d, h, dt in CONFIGS:
+        L = pk.Lcsb(sigma, d, h, dt)
+        L.init_zero()
+        L.iterate(8)
+        stream = torch.cuda.current_stream()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        reps = 16
+        e[0].record(stream)
+        L.iterate(reps)
+        e[1].record(stream)
+        e[2].record(stream)
+        L.certify()
+        e[3].record(stream)
+        torch.cuda.synchronize()
+        sweep_ms = e[0].elapsed_time(e[1]) / reps
+        cert_ms = e[2].elapsed_time(e[3])
+        elem = 8 if dt == "f64" else 4
+        algo = (d + 1) * elem * L.n
+        rows.append({"sigma": sigma, "d": d, "l": h, "dtype": dt, "entries": L.n,
+                     "sweep_ms": round(sweep_ms, 4), "certificate_ms": round(cert_ms, 3),
+                     "algorithmic_GBps": round(algo / sweep_ms / 1e6, 1),
+                     "frac_of_peak": round(algo / sweep_ms / 1e6 / HBM_PEAK_GBS, 4),
+                     "updates_per_s": L.n / sweep_ms * 1e3})
+        log(json.dumps(rows[-1]))
+        del L
+        torch.cuda.empty_cache()
+    print(json.dumps({"configs": rows}), flush=True)
+
+
+def profile_only(pk, h, sweeps):
+    import torch
+    L = pk.Lcsb(2, 2, h, "f32")
+    L.init_zero()
+    L.iterate(sweeps)
+    torch.cuda.synchronize()
+    log(f"ran {sweeps} FP32 sweeps at l={h}")
+
+
+def copy_only(gib):
+    """One plain device-to-device copy of `gib` GiB (after one warmup copy),
+    the reference for scaling the HBM counters."""
+    import torch
+    n = int(gib * 2**30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {n * 4} bytes twice")
 
 
 def main():
@@ -175,6 +252,12 @@ def main():
     import paper_2407_10925_amd as pk
 
     torch.cuda.set_device(0)
+    if args.profile_sweeps:
+        return profile_only(pk, args.h, args.profile_sweeps)
+    if args.copy_gib:
+        return copy_only(args.copy_gib)
+    if args.configs:
+        return config_table(pk)
     h, cad = args.h, args.cadence
     n = 4 ** h
     L = pk.Lcsb(2, 2, h, "f32")

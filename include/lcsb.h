@@ -132,7 +132,8 @@ int lcsb_iterate(lcsb_ctx *ctx, int64_t k);
  * (Algorithm 2's keep rule; a later iterate wins ties).  Either output
  * pointer may be NULL.  Returns LCSB_ENONFINITE (after filling the outputs)
  * when a non-finite value was met; the best certificate is then unchanged.
- * Needs at least one sweep since the last init (else LCSB_ESTATE). */
+ * Right after an init call it certifies the initial ring (lag 1 against
+ * lag 2). */
 int lcsb_certify(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
 
 /* Device address of lag k (1..d) and, for LCSB_F32, the FP64 offset its
@@ -148,6 +149,76 @@ int lcsb_status(const lcsb_ctx *ctx, int64_t *sweeps, lcsb_cert *best);
  * sweeps to an FP64 polish).  The sweep count and best certificate move with
  * it.  Enqueued on dst's stream after synchronising src's. */
 int lcsb_upcast(const lcsb_ctx *src_f32, lcsb_ctx *dst_f64);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start for sigma = d = 2 (not part of the paper's method: the
+ * limit of Algorithm 2's iteration does not depend on the starting ring, so
+ * a better start only shortens the run; the certificate judges the result).
+ *
+ * Network: 32 inputs -> 256 -> 256 -> 256 -> 1, ReLU, every matrix product
+ * with BF16 operands and FP32 accumulation (gfx950 MFMA).  Parameters are one
+ * FP32 master vector of LCSB_MLP_NPARAMS floats, matrices output-major:
+ *   W1[256][32] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] w4[256] b4[1]
+ * plus a BF16 copy (uint16 bit patterns, same layout, round to nearest even)
+ * used as the matrix operands.  Inputs of a table index at window length h
+ * (8 <= h <= 16): the symbols of strings a and b at positions 1..8 and
+ * h-7..h, slot 2j = a, slot 2j+1 = b, symbol s -> 2s - 1.  Activations are
+ * rounded to BF16 after each ReLU.
+ * All pointers are device pointers; work is enqueued on `stream` (hipStream_t
+ * as void*, NULL = null stream).  `batch` is a positive multiple of 256.
+ * ------------------------------------------------------------------------ */
+#define LCSB_MLP_INPUTS 32
+#define LCSB_MLP_WIDTH 256
+#define LCSB_MLP_NPARAMS 140289
+
+/* Bytes of the training workspace for `batch` samples (activations, BF16
+ * transposes, split-K partial sums). */
+int lcsb_mlp_workspace(int64_t batch, uint64_t *bytes);
+
+/* Seeded initialisation: every weight of a layer with fan-in k uniform in
+ * (-sqrt(6/k), sqrt(6/k)) (He initialisation for ReLU networks), drawn from
+ * SplitMix64 at counter seed * 2^32 + i + 1 for parameter i; biases 0. */
+int lcsb_mlp_init(float *params, uint64_t seed, void *stream);
+
+/* wbf16[i] = BF16 rounding of params[i] for every parameter. */
+int lcsb_mlp_to_bf16(const float *params, uint16_t *wbf16, void *stream);
+
+/* Draw `batch` table indices uniformly (SplitMix64 of Steele, Lea and Flood,
+ * counter seed * 2^32 + j + 1, top 2h bits) from a sigma = d = 2 table of
+ * window length h (FP64 or FP32 per dtype, 4^h entries) and gather the
+ * normalised targets target[j] = table[idx[j]] - table[0] (as FP32). */
+int lcsb_mlp_sample(const void *table, int dtype, int h, uint64_t seed, int64_t batch,
+                    uint64_t *idx, float *target, void *stream);
+
+/* y[j] = network(idx[j]) at window length h.  If ws is non-null (a training
+ * workspace for this batch) the BF16 activations are kept there for
+ * lcsb_mlp_backward. */
+int lcsb_mlp_forward(const float *params, const uint16_t *wbf16, const uint64_t *idx, int h,
+                     int64_t batch, void *ws, float *y, void *stream);
+
+/* Mean squared error: dy[j] = 2 (y[j] - target[j]) / batch, *loss (device
+ * double) = mean of (y - target)^2. */
+int lcsb_mlp_loss(const float *y, const float *target, int64_t batch, float *dy, double *loss,
+                  void *stream);
+
+/* Gradient of the loss with respect to every parameter (FP32, layout as the
+ * parameters), from dy and the activations a preceding lcsb_mlp_forward left
+ * in ws for the same idx, h and batch.  The BF16 rounding of the weights and
+ * activations passes gradients unchanged. */
+int lcsb_mlp_backward(const uint16_t *wbf16, const uint64_t *idx, int h, const float *dy,
+                      int64_t batch, void *ws, float *grad, void *stream);
+
+/* One Adam step (Kingma and Ba, 2015) on the FP32 master parameters with FP32
+ * moments m and v, step number t >= 1; refreshes the BF16 copy. */
+int lcsb_mlp_adam(float *params, uint16_t *wbf16, const float *grad, float *m, float *v,
+                  float lr, float beta1, float beta2, float eps, int64_t t, void *stream);
+
+/* Fill the ring of a sigma = d = 2 context (8 <= h <= 16) from the network:
+ * for every index i whose string-a head is 0, u = network(i), and lag 2 =
+ * u, lag 1 = u + rate at i and at its complement 4^h - 1 - i (the ring stays
+ * symmetric).  FP32 offsets are set to 0.  Resets the sweep count and the best
+ * certificate, like the other init calls. */
+int lcsb_init_seed_mlp(lcsb_ctx *ctx, const float *params, const uint16_t *wbf16, double rate);
 
 /* Release the context (never the caller's buffers or stream). NULL is ok. */
 int lcsb_destroy(lcsb_ctx *ctx);

@@ -14,7 +14,7 @@ import ctypes as C
 from . import _capi
 from ._capi import (LCSB_F32, LCSB_F64, Cert, LcsbError, check)
 
-__all__ = ["Lcsb", "LcsbError", "LCSB_F32", "LCSB_F64", "create"]
+__all__ = ["Lcsb", "Mlp", "LcsbError", "LCSB_F32", "LCSB_F64", "create"]
 
 _DTYPES = {"f64": LCSB_F64, "f32": LCSB_F32}
 
@@ -98,6 +98,11 @@ class Lcsb:
         check(self._lib.lcsb_status(self._ctx, C.byref(s), C.byref(best)))
         return s.value, best.as_dict()
 
+    def init_seed_mlp(self, mlp: "Mlp", rate: float):
+        """Fill the ring from the warm-start network: lag 2 = u, lag 1 = u + rate."""
+        check(self._lib.lcsb_init_seed_mlp(self._ctx, C.c_void_p(mlp.params.data_ptr()),
+                                           C.c_void_p(mlp.wbf16.data_ptr()), float(rate)))
+
     def upcast(self, src: "Lcsb"):
         """Fill this FP64 ring from the FP32 ring ``src`` (FP64 polish)."""
         check(self._lib.lcsb_upcast(src._ctx, self._ctx))
@@ -112,6 +117,93 @@ class Lcsb:
             self.destroy()
         except Exception:
             pass
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Mlp:
+    """Warm-start network state on one device: FP32 master parameters, their
+    BF16 copy, Adam moments and a training workspace for one batch size.
+    Methods mirror the lcsb_mlp_* entry points."""
+
+    def __init__(self, device=None, seed: int = 2407, batch: int = 8192):
+        import torch
+        self._lib = _capi.load()
+        self.device = torch.device(device if device is not None else "cuda")
+        n = _capi.LCSB_MLP_NPARAMS
+        self.params = torch.empty(n, dtype=torch.float32, device=self.device)
+        self.wbf16 = torch.empty(n, dtype=torch.int16, device=self.device)
+        self.m = torch.zeros(n, dtype=torch.float32, device=self.device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=self.device)
+        self.grad = torch.zeros(n, dtype=torch.float32, device=self.device)
+        self.t = 0
+        self.stream = torch.cuda.current_stream(self.device)
+        check(self._lib.lcsb_mlp_init(_ptr(self.params), seed, self._s()))
+        self.to_bf16()
+        self.set_batch(batch)
+
+    def _s(self):
+        return C.c_void_p(self.stream.cuda_stream)
+
+    def set_batch(self, batch: int):
+        import torch
+        b = C.c_uint64()
+        check(self._lib.lcsb_mlp_workspace(batch, C.byref(b)))
+        self.batch = batch
+        self.ws = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        self.idx = torch.empty(batch, dtype=torch.int64, device=self.device)
+        self.target = torch.empty(batch, dtype=torch.float32, device=self.device)
+        self.y = torch.empty(batch, dtype=torch.float32, device=self.device)
+        self.dy = torch.empty(batch, dtype=torch.float32, device=self.device)
+        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def load(self, params):
+        """Copy FP32 parameters in (device tensor) and refresh the BF16 copy."""
+        self.params.copy_(params)
+        self.to_bf16()
+
+    def to_bf16(self):
+        check(self._lib.lcsb_mlp_to_bf16(_ptr(self.params), _ptr(self.wbf16), self._s()))
+
+    def sample(self, table, h: int, seed: int):
+        dt = LCSB_F32 if table.dtype == _torch_f32() else LCSB_F64
+        check(self._lib.lcsb_mlp_sample(_ptr(table), dt, h, seed, self.batch, _ptr(self.idx),
+                                        _ptr(self.target), self._s()))
+
+    def forward(self, idx, h: int, y, keep: bool = False):
+        check(self._lib.lcsb_mlp_forward(_ptr(self.params), _ptr(self.wbf16), _ptr(idx), h,
+                                         idx.numel(), _ptr(self.ws) if keep else None, _ptr(y),
+                                         self._s()))
+
+    def loss(self, y, target, dy):
+        check(self._lib.lcsb_mlp_loss(_ptr(y), _ptr(target), y.numel(), _ptr(dy),
+                                      _ptr(self.loss_dev), self._s()))
+
+    def backward(self, idx, h: int, dy):
+        check(self._lib.lcsb_mlp_backward(_ptr(self.wbf16), _ptr(idx), h, _ptr(dy), idx.numel(),
+                                          _ptr(self.ws), _ptr(self.grad), self._s()))
+
+    def adam(self, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.t += 1
+        check(self._lib.lcsb_mlp_adam(_ptr(self.params), _ptr(self.wbf16), _ptr(self.grad),
+                                      _ptr(self.m), _ptr(self.v), lr, beta1, beta2, eps, self.t,
+                                      self._s()))
+
+    def train_step(self, table, h: int, seed: int, lr: float):
+        """Sample a batch from `table`, one forward/backward/Adam step; the
+        batch loss stays on the device (self.loss_dev)."""
+        self.sample(table, h, seed)
+        self.forward(self.idx, h, self.y, keep=True)
+        self.loss(self.y, self.target, self.dy)
+        self.backward(self.idx, h, self.dy)
+        self.adam(lr)
+
+
+def _torch_f32():
+    import torch
+    return torch.float32
 
 
 def create(sigma: int, d: int, h: int, dtype: str = "f64", device=None) -> Lcsb:

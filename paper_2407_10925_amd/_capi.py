@@ -16,6 +16,7 @@ LCSB_EUNSUPPORTED = -5
 LCSB_ENONFINITE = -6
 LCSB_F64 = 0
 LCSB_F32 = 1
+LCSB_MLP_NPARAMS = 140289
 
 _NAMES = {0: "LCSB_OK", -1: "LCSB_EINVAL", -2: "LCSB_ENOMEM", -3: "LCSB_EHIP",
           -4: "LCSB_ESTATE", -5: "LCSB_EUNSUPPORTED", -6: "LCSB_ENONFINITE"}
@@ -63,9 +64,21 @@ def load():
     L.lcsb_status.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(Cert)]
     L.lcsb_upcast.argtypes = [P, P]
     L.lcsb_destroy.argtypes = [P]
+    L.lcsb_mlp_workspace.argtypes = [C.c_int64, C.POINTER(C.c_uint64)]
+    L.lcsb_mlp_init.argtypes = [P, C.c_uint64, P]
+    L.lcsb_mlp_to_bf16.argtypes = [P, P, P]
+    L.lcsb_mlp_sample.argtypes = [P, C.c_int, C.c_int, C.c_uint64, C.c_int64, P, P, P]
+    L.lcsb_mlp_forward.argtypes = [P, P, P, C.c_int, C.c_int64, P, P, P]
+    L.lcsb_mlp_loss.argtypes = [P, P, C.c_int64, P, P, P]
+    L.lcsb_mlp_backward.argtypes = [P, P, C.c_int, P, C.c_int64, P, P, P]
+    L.lcsb_mlp_adam.argtypes = [P, P, P, P, P, C.c_float, C.c_float, C.c_float, C.c_float,
+                                C.c_int64, P]
+    L.lcsb_init_seed_mlp.argtypes = [P, P, P, C.c_double]
     for name in ("lcsb_create", "lcsb_query", "lcsb_bind", "lcsb_init_zero", "lcsb_load_ring",
                  "lcsb_iterate", "lcsb_certify", "lcsb_lag", "lcsb_status", "lcsb_upcast",
-                 "lcsb_destroy"):
+                 "lcsb_destroy", "lcsb_mlp_workspace", "lcsb_mlp_init", "lcsb_mlp_to_bf16",
+                 "lcsb_mlp_sample", "lcsb_mlp_forward", "lcsb_mlp_loss", "lcsb_mlp_backward",
+                 "lcsb_mlp_adam", "lcsb_init_seed_mlp"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

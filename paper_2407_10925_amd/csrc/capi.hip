@@ -306,6 +306,129 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
     return LCSB_OK;
 }
 
+// ------------------------------------------------------------------ warm start
+static int check_batch(int64_t batch)
+{
+    if (batch <= 0 || batch % 256 || batch > (int64_t)1 << 26)
+        return fail(LCSB_EINVAL, "batch %lld must be a positive multiple of 256 up to 2^26",
+                    (long long)batch);
+    return LCSB_OK;
+}
+
+static int check_h(int h)
+{
+    if (h < 8 || h > 16) return fail(LCSB_EINVAL, "window length %d outside 8..16", h);
+    return LCSB_OK;
+}
+
+static int launch_status(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) return fail(LCSB_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return LCSB_OK;
+}
+
+int lcsb_mlp_workspace(int64_t batch, uint64_t *bytes)
+{
+    int rc = check_batch(batch);
+    if (rc) return rc;
+    if (!bytes) return fail(LCSB_EINVAL, "bytes is null");
+    *bytes = mlp_ws_layout(batch).bytes;
+    return LCSB_OK;
+}
+
+int lcsb_mlp_init(float *params, uint64_t seed, void *stream)
+{
+    if (!params) return fail(LCSB_EINVAL, "null pointer");
+    return launch_status(launch_mlp_init(params, seed, static_cast<hipStream_t>(stream)), "init");
+}
+
+int lcsb_mlp_to_bf16(const float *params, uint16_t *wbf16, void *stream)
+{
+    if (!params || !wbf16) return fail(LCSB_EINVAL, "null pointer");
+    return launch_status(launch_to_bf16(params, wbf16, static_cast<hipStream_t>(stream)), "to_bf16");
+}
+
+int lcsb_mlp_sample(const void *table, int dtype, int h, uint64_t seed, int64_t batch,
+                    uint64_t *idx, float *target, void *stream)
+{
+    int rc = check_batch(batch);
+    if (rc) return rc;
+    if (!table || !idx || !target) return fail(LCSB_EINVAL, "null pointer");
+    if (dtype != LCSB_F32 && dtype != LCSB_F64) return fail(LCSB_EINVAL, "dtype %d", dtype);
+    if (h < 1 || h > 16) return fail(LCSB_EINVAL, "window length %d outside 1..16", h);
+    return launch_status(launch_mlp_sample(table, dtype, 2 * h, seed, batch, idx, target,
+                                           static_cast<hipStream_t>(stream)), "sample");
+}
+
+int lcsb_mlp_forward(const float *params, const uint16_t *wbf16, const uint64_t *idx, int h,
+                     int64_t batch, void *ws, float *y, void *stream)
+{
+    int rc = check_batch(batch);
+    if (rc || (rc = check_h(h))) return rc;
+    if (!params || !wbf16 || !idx || !y) return fail(LCSB_EINVAL, "null pointer");
+    if (ws && ((uintptr_t)ws & 255)) return fail(LCSB_EINVAL, "workspace not 256-byte aligned");
+    uint16_t *act = ws ? reinterpret_cast<uint16_t *>(static_cast<unsigned char *>(ws) +
+                                                      mlp_ws_layout(batch).act)
+                       : nullptr;
+    return launch_status(launch_mlp_forward(wbf16, params, idx, h, batch, y, act,
+                                            static_cast<hipStream_t>(stream)), "forward");
+}
+
+int lcsb_mlp_loss(const float *y, const float *target, int64_t batch, float *dy, double *loss,
+                  void *stream)
+{
+    int rc = check_batch(batch);
+    if (rc) return rc;
+    if (!y || !target || !dy || !loss) return fail(LCSB_EINVAL, "null pointer");
+    return launch_status(launch_mlp_mse(y, target, batch, dy, loss, static_cast<hipStream_t>(stream)),
+                         "loss");
+}
+
+int lcsb_mlp_backward(const uint16_t *wbf16, const uint64_t *idx, int h, const float *dy,
+                      int64_t batch, void *ws, float *grad, void *stream)
+{
+    int rc = check_batch(batch);
+    if (rc || (rc = check_h(h))) return rc;
+    if (!wbf16 || !idx || !dy || !ws || !grad) return fail(LCSB_EINVAL, "null pointer");
+    if ((uintptr_t)ws & 255) return fail(LCSB_EINVAL, "workspace not 256-byte aligned");
+    const MlpWs L = mlp_ws_layout(batch);
+    return launch_status(launch_mlp_backward(wbf16, dy, batch, static_cast<unsigned char *>(ws), L,
+                                             idx, h, grad, static_cast<hipStream_t>(stream)),
+                         "backward");
+}
+
+int lcsb_mlp_adam(float *params, uint16_t *wbf16, const float *grad, float *m, float *v,
+                  float lr, float beta1, float beta2, float eps, int64_t t, void *stream)
+{
+    if (!params || !wbf16 || !grad || !m || !v) return fail(LCSB_EINVAL, "null pointer");
+    if (t < 1) return fail(LCSB_EINVAL, "Adam step number starts at 1");
+    return launch_status(launch_mlp_adam(params, wbf16, grad, m, v, lr, beta1, beta2, eps, t,
+                                         static_cast<hipStream_t>(stream)), "adam");
+}
+
+int lcsb_init_seed_mlp(lcsb_ctx *c, const float *params, const uint16_t *wbf16, double rate)
+{
+    if (!c) return fail(LCSB_EINVAL, "null context");
+    if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
+    if (c->state < kBound) return fail(LCSB_ESTATE, "bind before init");
+    if (c->g.sigma != 2 || c->g.d != 2) return fail(LCSB_EUNSUPPORTED, "the network is for sigma = d = 2");
+    int rc = check_h(c->g.h);
+    if (rc) return rc;
+    if (!params || !wbf16) return fail(LCSB_EINVAL, "null pointer");
+    hipError_t e;
+    if ((e = launch_fill_zero(c->ws, Ws::kBytes, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "fill workspace");
+    c->head = 0;
+    const int s1 = slot_of_lag(c, 1), s2 = slot_of_lag(c, 2);
+    if ((e = launch_mlp_seed(c->g, c->dtype, wbf16, params, c->buf[s1], c->buf[s2], rate,
+                             c->stream)) != hipSuccess)
+        return hip_fail(c, e, "seed");
+    c->sweeps = 0;
+    c->best = initial_best();
+    c->state = kReady;
+    return LCSB_OK;
+}
+
 int lcsb_destroy(lcsb_ctx *c)
 {
     delete c;

@@ -60,4 +60,26 @@ hipError_t launch_project_copy(const Geometry &g, int dtype, const void *src, vo
 hipError_t launch_upcast(const Geometry &g, const float *src, const double *offset_dev,
                          double *dst, hipStream_t s);
 
+// Learned warm start (csrc/mlp.hip)
+struct MlpWs {  // byte offsets inside the caller's training workspace
+    size_t act, X, dZ, dH, T1, T2, WT, part, bytes;
+    int splits;
+};
+MlpWs mlp_ws_layout(int64_t batch);
+hipError_t launch_mlp_forward(const uint16_t *wb, const float *pf, const uint64_t *idx, int h,
+                              int64_t count, float *y, uint16_t *act, hipStream_t s);
+hipError_t launch_mlp_seed(const Geometry &g, int dtype, const uint16_t *wb, const float *pf,
+                           void *lag1, void *lag2, double rate, hipStream_t s);
+hipError_t launch_mlp_backward(const uint16_t *wb, const float *dy, int64_t count,
+                               unsigned char *ws, const MlpWs &L, const uint64_t *idx, int h,
+                               float *grad, hipStream_t s);
+hipError_t launch_mlp_mse(const float *y, const float *t, int64_t count, float *dy, double *loss,
+                          hipStream_t s);
+hipError_t launch_mlp_adam(float *p, uint16_t *wb, const float *g, float *m, float *v, float lr,
+                           float b1, float b2, float eps, int64_t t, hipStream_t s);
+hipError_t launch_to_bf16(const float *p, uint16_t *wb, hipStream_t s);
+hipError_t launch_mlp_init(float *p, uint64_t seed, hipStream_t s);
+hipError_t launch_mlp_sample(const void *table, int dtype, int bits, uint64_t seed, int64_t count,
+                             uint64_t *idx, float *target, hipStream_t s);
+
 }  // namespace lcsb

@@ -1,0 +1,650 @@
+// Learned warm start: a 32 -> 256 -> 256 -> 256 -> 1 ReLU network that maps
+// a tuple of two binary head strings to a guess of the normalised converged
+// table value, trained on converged tables at smaller window length and used
+// once to fill the FP32 ring before the iteration of Algorithm 2 starts (the
+// limit of that iteration does not depend on where it starts).
+//
+// Every matrix product runs on the gfx950 matrix cores as
+// v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation.  Parameters
+// live as one FP32 master vector (layout below) plus its BF16 rounding
+// (round to nearest, ties to even); biases are applied in FP32 and the
+// activation handed to the next layer is rounded to BF16 after the ReLU.
+//
+// Parameter layout (floats), matrices output-major ([out][in]):
+//   W1[256][32] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] w4[256] b4[1]
+//
+// Inputs (32): window positions P(l) = (1..8, l-7..l); slot 2j holds string
+// a at P_j, slot 2j+1 string b, symbol s -> 2s - 1.  At l = 16 these are
+// the index bits in order.
+#include <algorithm>
+#include <type_traits>
+
+#include "internal.h"
+
+namespace lcsb {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kIn = 32, kW = 256;
+constexpr int oW1 = 0, ob1 = oW1 + kW * kIn, oW2 = ob1 + kW, ob2 = oW2 + kW * kW;
+constexpr int oW3 = ob2 + kW, ob3 = oW3 + kW * kW, ow4 = ob3 + kW, ob4 = ow4 + kW;
+constexpr int kNParams = ob4 + 1;
+static_assert(kNParams == LCSB_MLP_NPARAMS, "parameter count");
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ __bf16 to_bf(float f) { return __builtin_bit_cast(__bf16, f2bf(f)); }
+
+__device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p)
+{
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(p));
+}
+
+// two groups of four consecutive BF16 values
+__device__ __forceinline__ bf16x8 load4x2(const uint16_t *p, const uint16_t *q)
+{
+    u32x2 a = *reinterpret_cast<const u32x2 *>(p);
+    u32x2 b = *reinterpret_cast<const u32x2 *>(q);
+    u32x4 v = {a.x, a.y, b.x, b.y};
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// window position (1-based) feeding input pair j
+__device__ __forceinline__ int pos_of(int j, int h) { return j < 8 ? j + 1 : h - 15 + j; }
+
+// input slot value for index i at window length h
+__device__ __forceinline__ float input_at(uint64_t i, int h, int slot)
+{
+    const int p = pos_of(slot >> 1, h);
+    const int bit = 2 * (h - p) + ((slot & 1) ? 0 : 1);
+    return ((i >> bit) & 1) ? 1.0f : -1.0f;
+}
+
+// ------------------------------------------------------------------ fused forward
+// One wave owns 32 samples (two 16-sample MFMA column blocks).  A layer is
+// computed transposed, Y^T = W X^T: the weight tile is the A operand (rows =
+// output features) and the activations are the B operand (columns =
+// samples).  The MFMA result layout (lane holds 4 consecutive output
+// features of one sample) is then already the next layer's B operand once the
+// k order inside each 32-feature block is permuted: slot t of lane group g
+// in k-block kb holds feature 32kb + 4g + t (t < 4) or 32kb + 16 + 4g + t-4
+// (t >= 4).  Weight fragments are loaded with the same permutation, so the
+// sum over k is unchanged and activations never leave the registers.  Layers
+// 2 and 3 stream their weights through LDS one 16-row tile (8 KB) at a time,
+// double-buffered and shared by the workgroup's waves.
+constexpr int kFwdWaves = 4;  // one wave per SIMD: the kernel needs ~400 registers per lane
+constexpr int kFwdThreads = 64 * kFwdWaves;
+constexpr int kFwdSamples = 32 * kFwdWaves;  // per workgroup batch
+
+__device__ __forceinline__ int feat_of(int kb, int g, int t)
+{
+    return 32 * kb + (t < 4 ? 4 * g + t : 16 + 4 * g + (t - 4));
+}
+
+enum : int { kSrcIdx = 0, kSrcReps = 1 };
+
+struct FwdArgs {
+    const uint16_t *wb;      // BF16 parameters
+    const float *pf;         // FP32 parameters (biases)
+    const uint64_t *idx;     // explicit sample indices (kSrcIdx)
+    uint64_t count;          // samples
+    int h;                   // window length of the indices
+    float *y;                // predictions (or null)
+    uint16_t *act;           // if non-null: H1, H2, H3 as BF16 [3][count][256] for backward
+    void *lag1, *lag2;       // seed targets (kSrcReps)
+    uint64_t n;              // table entries (kSrcReps)
+    double rate;             // lag 1 = u + rate, lag 2 = u
+};
+
+__device__ __forceinline__ uint32_t pack2(float lo, float hi);
+
+// H_layer[s][feature] = the BF16 activations of the wave's samples (backward)
+__device__ __forceinline__ void store_act(const FwdArgs &a, int layer, uint64_t s0, int r, int g,
+                                          const bool (&valid)[2], const uint32_t (&act)[8][2][4])
+{
+    uint16_t *H = a.act + (size_t)layer * a.count * kW;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        if (!valid[b]) continue;
+        const uint64_t s = s0 + 16 * b + r;
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                H[s * kW + feat_of(kb, g, 2 * q)] = (uint16_t)(act[kb][b][q] & 0xFFFFu);
+                H[s * kW + feat_of(kb, g, 2 * q + 1)] = (uint16_t)(act[kb][b][q] >> 16);
+            }
+    }
+}
+
+__device__ __forceinline__ uint32_t pack2(float lo, float hi)
+{
+    return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf8(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3)
+{
+    u32x4 v = {w0, w1, w2, w3};
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// Activations of one wave: A[kb][b][w] = BF16 pair (2w, 2w+1) of k-block kb,
+// sample block b (slots as described above).  An output tile f fills words
+// (f&1)*2 and (f&1)*2+1 of k-block f/2.
+template <int SRC, bool STORE, typename T>
+__global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
+{
+    __shared__ uint16_t wt[2][16 * kW];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const uint64_t nbatch = (a.count + kFwdSamples - 1) / kFwdSamples;
+
+    for (uint64_t batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
+        const uint64_t s0 = batch * kFwdSamples + (uint64_t)wave * 32;
+        uint64_t sidx[2];
+        bool valid[2];
+        bf16x8 x[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const uint64_t s = s0 + 16 * b + r;
+            valid[b] = s < a.count;
+            const uint64_t sc = valid[b] ? s : 0;
+            sidx[b] = SRC == kSrcIdx ? a.idx[sc] : sc;
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                w[q] = pack2(input_at(sidx[b], a.h, 8 * g + 2 * q), input_at(sidx[b], a.h, 8 * g + 2 * q + 1));
+            x[b] = as_bf8(w[0], w[1], w[2], w[3]);
+        }
+        uint32_t act[8][2][4];
+
+        // layer 1 (K = 32: one MFMA per output tile), weights straight from L2
+#pragma unroll
+        for (int f = 0; f < 16; ++f) {
+            const bf16x8 wf = load8(a.wb + oW1 + (16 * f + r) * kIn + 8 * g);
+            const float *bias = a.pf + ob1 + 16 * f + 4 * g;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const floatx4 acc = mfma(wf, x[b], floatx4{0, 0, 0, 0});
+                act[f >> 1][b][(f & 1) * 2 + 0] =
+                    pack2(fmaxf(acc[0] + bias[0], 0.0f), fmaxf(acc[1] + bias[1], 0.0f));
+                act[f >> 1][b][(f & 1) * 2 + 1] =
+                    pack2(fmaxf(acc[2] + bias[2], 0.0f), fmaxf(acc[3] + bias[3], 0.0f));
+            }
+        }
+
+        // layers 2 and 3
+#pragma unroll 1
+        for (int layer = 0; layer < 2; ++layer) {
+            const uint16_t *W = a.wb + (layer == 0 ? oW2 : oW3);
+            const float *bias_v = a.pf + (layer == 0 ? ob2 : ob3);
+            if constexpr (STORE) store_act(a, layer, s0, r, g, valid, act);
+            uint32_t nxt[8][2][4];
+            for (int q = threadIdx.x; q < 512; q += kFwdThreads)  // stage tile 0 (8 KB)
+                reinterpret_cast<u32x4 *>(wt[0])[q] = reinterpret_cast<const u32x4 *>(W)[q];
+            __syncthreads();
+#pragma unroll
+            for (int f = 0; f < 16; ++f) {
+                if (f + 1 < 16)  // stage the next tile into the other buffer
+                    for (int q = threadIdx.x; q < 512; q += kFwdThreads)
+                        reinterpret_cast<u32x4 *>(wt[(f + 1) & 1])[q] =
+                            reinterpret_cast<const u32x4 *>(W + (f + 1) * 16 * kW)[q];
+                const uint16_t *tile = wt[f & 1] + r * kW;
+                floatx4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+                for (int kb = 0; kb < 8; ++kb) {
+                    const bf16x8 wf = load4x2(tile + 32 * kb + 4 * g, tile + 32 * kb + 16 + 4 * g);
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[b] = mfma(wf, as_bf8(act[kb][b][0], act[kb][b][1], act[kb][b][2],
+                                                 act[kb][b][3]), acc[b]);
+                }
+                const float *bias = bias_v + 16 * f + 4 * g;
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    nxt[f >> 1][b][(f & 1) * 2 + 0] =
+                        pack2(fmaxf(acc[b][0] + bias[0], 0.0f), fmaxf(acc[b][1] + bias[1], 0.0f));
+                    nxt[f >> 1][b][(f & 1) * 2 + 1] =
+                        pack2(fmaxf(acc[b][2] + bias[2], 0.0f), fmaxf(acc[b][3] + bias[3], 0.0f));
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) act[kb][b][q] = nxt[kb][b][q];
+        }
+        if constexpr (STORE) store_act(a, 2, s0, r, g, valid, act);
+
+        // layer 4: y = w4 . h3 + b4, FP32 accumulation, then the four lane groups
+        float part[2] = {0.0f, 0.0f};
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f0 = feat_of(kb, g, 2 * q), f1 = feat_of(kb, g, 2 * q + 1);
+                const float w0 = bf2f(a.wb[ow4 + f0]), w1 = bf2f(a.wb[ow4 + f1]);
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    part[b] += w0 * bf2f((uint16_t)(act[kb][b][q] & 0xFFFFu));
+                    part[b] += w1 * bf2f((uint16_t)(act[kb][b][q] >> 16));
+                }
+            }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            part[b] += __shfl_xor(part[b], 16);
+            part[b] += __shfl_xor(part[b], 32);
+        }
+        if (g == 0) {
+            const float b4 = a.pf[ob4];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if (!valid[b]) continue;
+                const float u = part[b] + b4;
+                const uint64_t s = s0 + 16 * b + r;
+                if (a.y) a.y[s] = u;
+                if constexpr (SRC == kSrcReps) {
+                    T *l1 = static_cast<T *>(a.lag1);
+                    T *l2 = static_cast<T *>(a.lag2);
+                    const uint64_t i = sidx[b], m = a.n - 1 - i;
+                    const T v2 = (T)u;
+                    const T v1 = (T)((double)u + a.rate);
+                    l2[i] = v2;
+                    l2[m] = v2;
+                    l1[i] = v1;
+                    l1[m] = v1;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ NT GEMM
+// C_s[M][N] = sum_{k in split s} A[m][k] B[n][k] (A, B BF16 row-major, K
+// contiguous).  A wave computes a 32 x 32 tile (2 x 2 MFMA blocks); a
+// workgroup of four waves 64 x 64.  M, N, K multiples of 32; split s writes
+// its partial sums to C + s M N (reduced in a fixed order afterwards).
+__global__ __launch_bounds__(256) void gemm_nt(const uint16_t *__restrict__ A,
+                                               const uint16_t *__restrict__ B,
+                                               float *__restrict__ C, int M, int N, int K,
+                                               int kchunk)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
+    const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    if (m0 >= M || n0 >= N) return;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    floatx4 acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+    for (int k = kbeg; k < kend; k += 32) {
+        bf16x8 av[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            av[i] = load8(A + (size_t)(m0 + 16 * i + r) * K + k + 8 * g);
+            bv[i] = load8(B + (size_t)(n0 + 16 * i + r) * K + k + 8 * g);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
+    }
+    float *Cs = C + (size_t)blockIdx.z * M * N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+                Cs[(size_t)(m0 + 16 * i + 4 * g + rr) * N + n0 + 16 * j + r] = acc[i][j][rr];
+}
+
+// out[e] = sum_s part[s][e] in increasing s (deterministic)
+__global__ __launch_bounds__(256) void reduce_splits(const float *__restrict__ part, int splits,
+                                                     size_t count, float *__restrict__ out)
+{
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
+        float s = 0.0f;
+        for (int k = 0; k < splits; ++k) s += part[(size_t)k * count + e];
+        out[e] = s;
+    }
+}
+
+// ------------------------------------------------------------------ elementwise
+__global__ __launch_bounds__(256) void encode_x(const uint64_t *__restrict__ idx, int h,
+                                                uint64_t count, uint16_t *__restrict__ X)
+{
+    const uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count * kIn) return;
+    const uint64_t s = e / kIn;
+    X[e] = f2bf(input_at(idx[s], h, (int)(e % kIn)));
+}
+
+// T[c][r] = S[r][c] for a rows x cols BF16 matrix
+__global__ __launch_bounds__(256) void transpose_bf16(const uint16_t *__restrict__ S,
+                                                      uint16_t *__restrict__ T, int rows, int cols)
+{
+    __shared__ uint16_t tile[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int k = ty; k < 32; k += 8) tile[k][tx] = S[(size_t)(r0 + k) * cols + c0 + tx];
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) T[(size_t)(c0 + k) * rows + r0 + tx] = tile[tx][k];
+}
+
+// dZ3[s][o] = bf16(dy[s] * w4[o]) where h3 > 0; dw4[o] = sum_s dy[s] h3[s][o]
+__global__ __launch_bounds__(256) void head_backward(const float *__restrict__ dy,
+                                                     const uint16_t *__restrict__ H3,
+                                                     const uint16_t *__restrict__ wb, int count,
+                                                     uint16_t *__restrict__ dZ3)
+{
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)count * kW) return;
+    const int o = (int)(e % kW);
+    const size_t s = e / kW;
+    const float h = bf2f(H3[e]);
+    dZ3[e] = f2bf(h > 0.0f ? dy[s] * bf2f(wb[ow4 + o]) : 0.0f);
+}
+
+// dZ = bf16(dH) where H > 0 (dH FP32, H BF16)
+__global__ __launch_bounds__(256) void relu_backward(const float *__restrict__ dH,
+                                                     const uint16_t *__restrict__ H, size_t count,
+                                                     uint16_t *__restrict__ dZ)
+{
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count) return;
+    dZ[e] = f2bf(bf2f(H[e]) > 0.0f ? dH[e] : 0.0f);
+}
+
+// out[c] = sum_r w[r] * M[r][c] (w = null means 1), M BF16 rows x 256, one
+// thread per column, rows in increasing order
+__global__ __launch_bounds__(256) void column_sums(const uint16_t *__restrict__ M,
+                                                   const float *__restrict__ w, int rows,
+                                                   float *__restrict__ out)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= kW) return;
+    float s = 0.0f;
+    for (int r = 0; r < rows; ++r) s += (w ? w[r] : 1.0f) * bf2f(M[(size_t)r * kW + c]);
+    out[c] = s;
+}
+
+__global__ void sum_vector(const float *__restrict__ v, int count, float *__restrict__ out)
+{
+    __shared__ float part[256];
+    float s = 0.0f;
+    for (int k = threadIdx.x; k < count; k += 256) s += v[k];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int k = 0; k < 256; ++k) t += part[k];
+        *out = t;
+    }
+}
+
+// dy = 2 (y - t) / B, loss = mean (y - t)^2 (FP64 sum, one workgroup)
+__global__ void mse_kernel(const float *__restrict__ y, const float *__restrict__ t, int count,
+                           float *__restrict__ dy, double *__restrict__ loss)
+{
+    __shared__ double part[256];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < count; k += 256) {
+        const float r = y[k] - t[k];
+        dy[k] = 2.0f * r / (float)count;
+        s += (double)r * r;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int k = 0; k < 256; ++k) tot += part[k];
+        *loss = tot / count;
+    }
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, uint16_t *__restrict__ wb,
+                                                   const float *__restrict__ g, float *__restrict__ m,
+                                                   float *__restrict__ v, float lr, float b1, float b2,
+                                                   float eps, float c1, float c2)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kNParams) return;
+    const float ge = g[e];
+    const float me = b1 * m[e] + (1.0f - b1) * ge;
+    const float ve = b2 * v[e] + (1.0f - b2) * ge * ge;
+    m[e] = me;
+    v[e] = ve;
+    const float pe = p[e] - lr * (me / c1) / (sqrtf(ve / c2) + eps);
+    p[e] = pe;
+    wb[e] = f2bf(pe);
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float *__restrict__ p,
+                                                      uint16_t *__restrict__ wb, int count)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e < count) wb[e] = f2bf(p[e]);
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): the mix of state (seed 2^32 + j + 1) * golden
+__device__ __forceinline__ uint64_t splitmix(uint64_t seed, uint64_t j)
+{
+    uint64_t z = ((seed << 32) + j + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// He-uniform initialisation: weights of a layer with fan-in k uniform in
+// (-sqrt(6/k), sqrt(6/k)) from SplitMix64 at counter e, biases 0.
+__global__ __launch_bounds__(256) void init_kernel(float *__restrict__ p, uint64_t seed)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kNParams) return;
+    int fan = 0;
+    if (e < ob1) fan = kIn;
+    else if (e >= oW2 && e < ob2) fan = kW;
+    else if (e >= oW3 && e < ob3) fan = kW;
+    else if (e >= ow4 && e < ob4) fan = kW;
+    if (!fan) { p[e] = 0.0f; return; }
+    const double u = (double)(splitmix(seed, (uint64_t)e) >> 11) * 0x1.0p-53;  // [0, 1)
+    p[e] = (float)((2.0 * u - 1.0) * sqrt(6.0 / fan));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sample_kernel(const T *__restrict__ table, int bits,
+                                                     uint64_t seed, int count,
+                                                     uint64_t *__restrict__ idx,
+                                                     float *__restrict__ target)
+{
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= count) return;
+    const uint64_t i = splitmix(seed, (uint64_t)s) >> (64 - bits);
+    idx[s] = i;
+    target[s] = (float)((double)table[i] - (double)table[0]);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+MlpWs mlp_ws_layout(int64_t batch)
+{
+    MlpWs w;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o += (bytes + 255) & ~size_t(255); return at; };
+    const size_t B = (size_t)batch;
+    w.act = take(3 * B * kW * 2);
+    w.X = take(B * kIn * 2);
+    w.dZ = take(B * kW * 2);
+    w.dH = take(B * kW * 4);
+    w.T1 = take(B * kW * 2);
+    w.T2 = take(B * kW * 2);
+    w.WT = take((size_t)2 * kW * kW * 2);
+    w.splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, batch / 512));
+    w.part = take((size_t)w.splits * kW * kW * 4);
+    w.bytes = o;
+    return w;
+}
+
+hipError_t launch_mlp_forward(const uint16_t *wb, const float *pf, const uint64_t *idx, int h,
+                              int64_t count, float *y, uint16_t *act, hipStream_t s)
+{
+    FwdArgs a{};
+    a.wb = wb; a.pf = pf; a.idx = idx; a.count = (uint64_t)count; a.h = h; a.y = y; a.act = act;
+    const uint64_t nb = ((uint64_t)count + kFwdSamples - 1) / kFwdSamples;
+    const unsigned grid = (unsigned)std::min<uint64_t>(nb, 256ull * 8);
+    if (act)
+        mlp_fwd<kSrcIdx, true, float><<<grid, kFwdThreads, 0, s>>>(a);
+    else
+        mlp_fwd<kSrcIdx, false, float><<<grid, kFwdThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_seed(const Geometry &g, int dtype, const uint16_t *wb, const float *pf,
+                           void *lag1, void *lag2, double rate, hipStream_t s)
+{
+    FwdArgs a{};
+    a.wb = wb; a.pf = pf; a.count = g.n / 2; a.h = g.h; a.lag1 = lag1; a.lag2 = lag2;
+    a.n = g.n; a.rate = rate;
+    const uint64_t nb = (a.count + kFwdSamples - 1) / kFwdSamples;
+    const unsigned grid = (unsigned)std::min<uint64_t>(nb, 256ull * 8);
+    if (dtype == LCSB_F32)
+        mlp_fwd<kSrcReps, false, float><<<grid, kFwdThreads, 0, s>>>(a);
+    else
+        mlp_fwd<kSrcReps, false, double><<<grid, kFwdThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+static hipError_t gemm(const uint16_t *A, const uint16_t *B, float *C, int M, int N, int K,
+                       int splits, float *part, hipStream_t s)
+{
+    // split K into `splits` chunks of whole 32-wide steps
+    const int steps = K / 32;
+    const int per = (steps + splits - 1) / splits;
+    const int used = (steps + per - 1) / per;
+    dim3 grid((M + 63) / 64, (N + 63) / 64, used);
+    float *dst = used == 1 ? C : part;
+    gemm_nt<<<grid, 256, 0, s>>>(A, B, dst, M, N, K, per * 32);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || used == 1) return e;
+    const size_t cnt = (size_t)M * N;
+    reduce_splits<<<(unsigned)std::min<size_t>((cnt + 255) / 256, 4096), 256, 0, s>>>(part, used, cnt, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward(const uint16_t *wb, const float *dy, int64_t count,
+                               unsigned char *ws, const MlpWs &L, const uint64_t *idx, int h,
+                               float *grad, hipStream_t s)
+{
+    const int B = (int)count;
+    uint16_t *H1 = reinterpret_cast<uint16_t *>(ws + L.act);
+    uint16_t *H2 = H1 + (size_t)B * kW;
+    uint16_t *H3 = H2 + (size_t)B * kW;
+    uint16_t *X = reinterpret_cast<uint16_t *>(ws + L.X);
+    uint16_t *dZ = reinterpret_cast<uint16_t *>(ws + L.dZ);
+    float *dH = reinterpret_cast<float *>(ws + L.dH);
+    uint16_t *T1 = reinterpret_cast<uint16_t *>(ws + L.T1);
+    uint16_t *T2 = reinterpret_cast<uint16_t *>(ws + L.T2);
+    uint16_t *WT = reinterpret_cast<uint16_t *>(ws + L.WT);
+    float *part = reinterpret_cast<float *>(ws + L.part);
+    const unsigned ew = (unsigned)(((size_t)B * kW + 255) / 256);
+    hipError_t e;
+#define LCSB_TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
+    // layer 4
+    column_sums<<<1, 256, 0, s>>>(H3, dy, B, grad + ow4);
+    LCSB_TRY(hipGetLastError());
+    sum_vector<<<1, 256, 0, s>>>(dy, B, grad + ob4);
+    LCSB_TRY(hipGetLastError());
+    head_backward<<<ew, 256, 0, s>>>(dy, H3, wb, B, dZ);
+    LCSB_TRY(hipGetLastError());
+    // layers 3, 2: gW = dZ^T H_in, gb = column sums of dZ, dH_in = dZ W
+    const uint16_t *Hin[2] = {H2, H1};
+    const int oW[2] = {oW3, oW2}, ob[2] = {ob3, ob2};
+    for (int L3 = 0; L3 < 2; ++L3) {
+        column_sums<<<1, 256, 0, s>>>(dZ, nullptr, B, grad + ob[L3]);
+        LCSB_TRY(hipGetLastError());
+        transpose_bf16<<<dim3(kW / 32, B / 32), 256, 0, s>>>(dZ, T1, B, kW);      // dZ^T [256][B]
+        LCSB_TRY(hipGetLastError());
+        transpose_bf16<<<dim3(kW / 32, B / 32), 256, 0, s>>>(Hin[L3], T2, B, kW);  // H^T [256][B]
+        LCSB_TRY(hipGetLastError());
+        LCSB_TRY(gemm(T1, T2, grad + oW[L3], kW, kW, B, L.splits, part, s));
+        transpose_bf16<<<dim3(kW / 32, kW / 32), 256, 0, s>>>(wb + oW[L3], WT, kW, kW);  // W^T
+        LCSB_TRY(hipGetLastError());
+        LCSB_TRY(gemm(dZ, WT, dH, B, kW, kW, 1, part, s));                              // dZ W
+        relu_backward<<<ew, 256, 0, s>>>(dH, Hin[L3], (size_t)B * kW, dZ);
+        LCSB_TRY(hipGetLastError());
+    }
+    // layer 1: gW1 = dZ1^T X, gb1
+    column_sums<<<1, 256, 0, s>>>(dZ, nullptr, B, grad + ob1);
+    LCSB_TRY(hipGetLastError());
+    encode_x<<<(unsigned)(((size_t)B * kIn + 255) / 256), 256, 0, s>>>(idx, h, (uint64_t)B, X);
+    LCSB_TRY(hipGetLastError());
+    transpose_bf16<<<dim3(kW / 32, B / 32), 256, 0, s>>>(dZ, T1, B, kW);
+    LCSB_TRY(hipGetLastError());
+    transpose_bf16<<<dim3(kIn / 32, B / 32), 256, 0, s>>>(X, T2, B, kIn);  // X^T [32][B]
+    LCSB_TRY(hipGetLastError());
+    LCSB_TRY(gemm(T1, T2, grad + oW1, kW, kIn, B, L.splits, part, s));
+#undef LCSB_TRY
+    return hipSuccess;
+}
+
+hipError_t launch_mlp_mse(const float *y, const float *t, int64_t count, float *dy, double *loss,
+                          hipStream_t s)
+{
+    mse_kernel<<<1, 256, 0, s>>>(y, t, (int)count, dy, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float *p, uint16_t *wb, const float *g, float *m, float *v, float lr,
+                           float b1, float b2, float eps, int64_t t, hipStream_t s)
+{
+    const float c1 = 1.0f - powf(b1, (float)t);
+    const float c2 = 1.0f - powf(b2, (float)t);
+    adam_kernel<<<(kNParams + 255) / 256, 256, 0, s>>>(p, wb, g, m, v, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *p, uint16_t *wb, hipStream_t s)
+{
+    to_bf16_kernel<<<(kNParams + 255) / 256, 256, 0, s>>>(p, wb, kNParams);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_init(float *p, uint64_t seed, hipStream_t s)
+{
+    init_kernel<<<(kNParams + 255) / 256, 256, 0, s>>>(p, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_sample(const void *table, int dtype, int bits, uint64_t seed, int64_t count,
+                             uint64_t *idx, float *target, hipStream_t s)
+{
+    const unsigned grid = (unsigned)((count + 255) / 256);
+    if (dtype == LCSB_F32)
+        sample_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float *>(table), bits, seed,
+                                                  (int)count, idx, target);
+    else
+        sample_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double *>(table), bits, seed,
+                                                   (int)count, idx, target);
+    return hipGetLastError();
+}
+
+}  // namespace lcsb

@@ -1,0 +1,209 @@
+"""GPU parity of the warm-start network (BF16 MFMA kernels) against the FP64
+reference in oracle/mlp.py, and the warm start's effect on the iteration.
+
+Tolerances.  Weights are the same BF16 values on both sides and the inputs
+are exactly +-1, so the only differences are the FP32 accumulation order of
+the matrix cores against exact FP64 sums (relative 2^-24 per operation), and
+the rare BF16 rounding of an activation that lands on the other side of a
+rounding boundary because of that (one BF16 step, relative 2^-8, for that
+activation).  The forward check therefore asks for agreement to 1e-4 of the
+output scale on 99% of samples and to 2^-5 of the scale on all; the backward
+also rounds every upstream gradient to BF16 (relative 2^-9 each), so each
+gradient tensor must agree to 2e-2 in relative L2 norm with cosine >= 0.999.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import seeded_inputs as si
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pk():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2407_10925_amd as pk
+    return pk
+
+
+def _params(seed, scale=0.1):
+    u = si.uniform(seed, torch.arange(omlp.NPARAMS, dtype=torch.int64), scale=2.0)  # [0, 2)
+    return ((u - 1.0) * scale).to(torch.float32)
+
+
+def _indices(n, count, seed):
+    return si.sample_indices(n, count, seed)[:count]
+
+
+def test_to_bf16_bit_exact(pk):
+    say("bf16 conversion")
+    p = _params(1, scale=3.0)
+    M = pk.Mlp(batch=256)
+    M.load(p.cuda())
+    got = M.wbf16.cpu().numpy().view(np.uint16)
+    ref = omlp.bf16(p.numpy().astype(np.float64)).astype(np.float32).view(np.uint32) >> 16
+    assert np.array_equal(got.astype(np.uint32), ref)
+
+
+def test_init_is_seeded_and_scaled(pk):
+    a = pk.Mlp(seed=5, batch=256).params.cpu().numpy()
+    b = pk.Mlp(seed=5, batch=256).params.cpu().numpy()
+    c = pk.Mlp(seed=6, batch=256).params.cpu().numpy()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    P = omlp.unpack(a)
+    assert np.all(P["b1"] == 0) and np.all(P["b2"] == 0) and P["b4"][0] == 0
+    assert np.max(np.abs(P["W1"])) <= np.sqrt(6 / 32) and np.max(np.abs(P["W2"])) <= np.sqrt(6 / 256)
+    assert abs(np.std(P["W2"]) - np.sqrt(2 / 256)) < 0.1 * np.sqrt(2 / 256)
+
+
+@pytest.mark.parametrize("h", [12, 16])
+def test_forward_matches_reference(pk, h):
+    say(f"forward h={h}")
+    B = 1024
+    p = _params(2)
+    M = pk.Mlp(batch=B)
+    M.load(p.cuda())
+    idx = _indices(4 ** h, B, seed=7 + h)
+    y = torch.empty(B, dtype=torch.float32, device="cuda")
+    M.forward(idx.cuda(), h, y)
+    got = y.cpu().numpy().astype(np.float64)
+    ref, cache = omlp.forward(p.numpy().astype(np.float64), omlp.encode(idx.numpy().astype(np.uint64), h))
+    scale = np.abs(cache["a3"]) @ np.abs(cache["w4"]) + abs(float(p[-1])) + 1e-3
+    err = np.abs(got - ref) / scale
+    say(f"forward max rel err {err.max():.2e}, 99th pct {np.quantile(err, 0.99):.2e}")
+    assert np.quantile(err, 0.99) <= 1e-4
+    assert err.max() <= 2.0 ** -5
+
+
+def test_backward_matches_reference(pk):
+    say("backward")
+    B, h = 512, 12
+    p = _params(3)
+    M = pk.Mlp(batch=B)
+    M.load(p.cuda())
+    idx = _indices(4 ** h, B, seed=11)
+    t = si.uniform(12, torch.arange(B), scale=4.0).to(torch.float32)
+    y = torch.empty(B, dtype=torch.float32, device="cuda")
+    dy = torch.empty_like(y)
+    idx_d = idx.cuda()
+    M.forward(idx_d, h, y, keep=True)
+    M.loss(y, t.cuda(), dy)
+    M.backward(idx_d, h, dy)
+    g = M.grad.cpu().numpy().astype(np.float64)
+    yr, cache = omlp.forward(p.numpy().astype(np.float64), omlp.encode(idx.numpy().astype(np.uint64), h))
+    loss_r, dy_r = omlp.mse(yr, t.numpy())
+    assert abs(M.loss_dev.item() - loss_r) <= 1e-3 * loss_r
+    gr = omlp.backward(cache, dy_r)
+    for name, (o, shape) in omlp.OFFSETS.items():
+        n = int(np.prod(shape))
+        a, b = g[o:o + n], gr[o:o + n]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        cos = a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30)
+        say(f"grad {name}: rel {rel:.2e} cos {cos:.6f}")
+        assert rel <= 2e-2 and cos >= 0.999, name
+
+
+def test_adam_step_matches_reference(pk):
+    M = pk.Mlp(batch=256)
+    p = _params(4)
+    g = _params(5, scale=1e-2)
+    M.load(p.cuda())
+    M.grad.copy_(g.cuda())
+    M.adam(1e-3)
+    M.grad.copy_((g * 0.5).cuda())
+    M.adam(1e-3)
+    q, m, v = omlp.adam(p.numpy().astype(np.float64), g.numpy().astype(np.float64),
+                        np.zeros(omlp.NPARAMS), np.zeros(omlp.NPARAMS), 1, 1e-3)
+    q, m, v = omlp.adam(q, 0.5 * g.numpy().astype(np.float64), m, v, 2, 1e-3)
+    np.testing.assert_allclose(M.params.cpu().numpy(), q, rtol=0, atol=2e-6)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_sample_draws_in_range_and_gathers_targets(pk, dtype):
+    h = 9
+    table = si.table(2, 2, h, seed=33, dtype=dtype).cuda()
+    M = pk.Mlp(batch=4096)
+    M.sample(table, h, seed=1)
+    idx = M.idx.cpu().numpy()
+    assert idx.min() >= 0 and idx.max() < 4 ** h
+    assert len(np.unique(idx)) > 3000
+    tab = table.cpu().numpy().astype(np.float64)
+    assert np.array_equal(M.target.cpu().numpy(), (tab[idx] - tab[0]).astype(np.float32))
+
+
+def _converged_table(pk, h, sweeps):
+    L = pk.Lcsb(2, 2, h, "f64")
+    L.init_zero()
+    L.iterate(sweeps)
+    _, best = L.certify()
+    return L, best
+
+
+def test_training_reduces_the_loss_and_seed_is_consistent(pk):
+    """Train on a converged l = 8 table; the loss falls by 10x; the seed the
+    library writes into an l = 8 ring equals the network's forward values at
+    the representatives, the complement partners hold the same values, and
+    lag 1 = lag 2 + rate."""
+    say("training on l=8")
+    h = 8
+    L, best = _converged_table(pk, h, 160)
+    table, _ = L.lag(1)
+    M = pk.Mlp(batch=1024, seed=9)
+    losses = []
+    for step in range(300):
+        M.train_step(table, h, seed=1000 + step, lr=2e-3)
+        if step % 50 == 0 or step == 299:
+            losses.append(M.loss_dev.item())
+    say(f"losses {losses}")
+    assert losses[-1] < losses[0] / 10
+    R = L.certify()[0]["R"]
+    S = pk.Lcsb(2, 2, h, "f32")
+    S.init_seed_mlp(M, rate=R)
+    n = 4 ** h
+    reps = torch.arange(n // 2, dtype=torch.int64, device="cuda")
+    y = torch.empty(n // 2, dtype=torch.float32, device="cuda")
+    M.forward(reps[: (n // 2) // 256 * 256], h, y[: (n // 2) // 256 * 256])
+    lag2 = S.lag(2)[0]
+    lag1 = S.lag(1)[0]
+    assert torch.equal(lag2[: n // 2], y)
+    assert torch.equal(lag2.flip(0), lag2) and torch.equal(lag1.flip(0), lag1)
+    assert torch.equal(lag1, (lag2.double() + R).float())
+
+
+def test_seeded_run_reaches_the_plain_bound(pk):
+    """l = 10: the network trained on converged l = 8 and l = 9 tables seeds
+    an FP32 ring; FP32 sweeps followed by the FP64 polish reach the plain
+    FP64 bound within 1e-9 (the limit does not depend on the start)."""
+    say("seeded run l=10")
+    P, plain = _converged_table(pk, 10, 240)
+    M = pk.Mlp(batch=2048, seed=10)
+    tabs = []
+    for h in (8, 9):
+        L, _ = _converged_table(pk, h, 200)
+        tabs.append((h, L))
+    for step in range(400):
+        h, L = tabs[step % 2]
+        M.train_step(L.lag(1)[0], h, seed=step, lr=2e-3)
+    rate = tabs[1][1].certify()[0]["R"]
+    S = pk.Lcsb(2, 2, 10, "f32")
+    S.init_seed_mlp(M, rate=rate)
+    S.iterate(80)
+    Q = pk.Lcsb(2, 2, 10, "f64")
+    Q.upcast(S)
+    best = None
+    for _ in range(40):
+        Q.iterate(4)
+        _, best = Q.certify()
+        if best["bound"] >= plain["bound"] - 1e-9:
+            break
+    say(f"seeded {best['bound']:.12f} at sweep {best['sweep']}, plain {plain['bound']:.12f}")
+    assert abs(best["bound"] - plain["bound"]) <= 1e-9

@@ -22,6 +22,7 @@ Also printed in the same JSON line:
 import argparse
 import hashlib
 import json
+import math
 import os
 import statistics
 import sys
@@ -50,6 +51,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-sample-log2", type=int, default=24)
     p.add_argument("--no-ttb", action="store_true", help="skip the time-to-bound runs")
+    p.add_argument("--train-steps", type=int, default=3000)
     p.add_argument("--profile-sweeps", type=int, default=0,
                    help="only run this many FP32 sweeps from zero (for counter collection)")
     p.add_argument("--configs", action="store_true",
@@ -108,7 +110,7 @@ def cpu_baseline(h, log2_sample):
                       f"{dt:.1f} s"}
 
 
-def time_to_bound(pk, h):
+def time_to_bound(pk, h, train_steps=3000):
     """Wall time from the init call to the first certificate within 1e-9 of
     the converged plain FP64 bound B.
 
@@ -173,10 +175,85 @@ def time_to_bound(pk, h):
                                "reached": best["bound"] >= target}
     log(f"time to bound, FP32 + FP64 polish: {t_mixed:.3f} s, {sweeps32} FP32 + "
         f"{cur['sweep'] - sweeps32} FP64 sweeps, bound {best['bound']:.12f}")
-    out["mixed_learned"] = None
+    out["mixed_learned"] = learned_run(pk, h, P, target, train_steps)
     del P, M
     torch.cuda.empty_cache()
     return out
+
+
+def learned_run(pk, h, P, target, train_steps):
+    """FP32 + FP64 polish started from the warm-start network.  Training data:
+    converged FP64 tables at l = h-4, h-3, h-2 (zero start, sweeps until the
+    certificate moves by < 1e-10); training: `train_steps` Adam steps on
+    batches of 8192 drawn from those tables in turn; the seed uses the rate R
+    of the l = h-2 run.  Times are reported without and with data generation
+    and training."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tables = []
+    for hh in (h - 4, h - 3, h - 2):
+        T = pk.Lcsb(2, 2, hh, "f64")
+        T.init_zero()
+        prev = None
+        while True:
+            T.iterate(16)
+            cur, _ = T.certify()
+            if prev is not None and abs(cur["bound"] - prev) < 1e-10:
+                break
+            prev = cur["bound"]
+        tables.append((hh, T))
+    rate = cur["R"]
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    M = pk.Mlp(batch=8192, seed=2407)
+    t1 = time.perf_counter()
+    lr0 = 2e-3
+    for step in range(train_steps):
+        hh, T = tables[step % 3]
+        lr = lr0 * 0.5 * (1 + math.cos(math.pi * step / train_steps))
+        M.train_step(T.lag(1)[0], hh, seed=10925 + step, lr=lr)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    loss = M.loss_dev.item()
+    del tables
+    torch.cuda.empty_cache()
+    log(f"warm start: data {t_data:.2f} s, training {t_train:.2f} s ({train_steps} steps), "
+        f"last batch loss {loss:.3e}")
+
+    S = pk.Lcsb(2, 2, h, "f32")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    S.init_seed_mlp(M, rate)
+    torch.cuda.synchronize()
+    t_seed = time.perf_counter() - t2
+    best_prev = None
+    while True:
+        S.iterate(32)
+        cur, best = S.certify()
+        if best["bound"] >= target or cur["sweep"] >= 800:
+            break
+        if cur["bound"] > 0 and best_prev is not None and best["bound"] - best_prev < 1e-7:
+            break
+        best_prev = best["bound"]
+    sweeps32 = cur["sweep"]
+    if best["bound"] < target:
+        P.upcast(S)
+        while best["bound"] < target and cur["sweep"] < 1600:
+            P.iterate(8)
+            cur, best = P.certify()
+    t_run = time.perf_counter() - t2
+    res = {"seconds": round(t_run, 4), "seconds_with_training": round(t_run + t_data + t_train, 4),
+           "data_s": round(t_data, 4), "training_s": round(t_train, 4), "train_steps": train_steps,
+           "last_batch_loss": loss, "seed_s": round(t_seed, 4),
+           "seed_tflops": round(2.79e5 * (4 ** h // 2) / t_seed / 1e12, 1),
+           "sweeps_f32": sweeps32, "sweeps_f64": cur["sweep"] - sweeps32,
+           "bound": best["bound"], "reached": best["bound"] >= target}
+    log(f"time to bound, learned + FP32 + FP64 polish: {t_run:.3f} s ({t_seed:.3f} s seed), "
+        f"{sweeps32} FP32 + {cur['sweep'] - sweeps32} FP64 sweeps, bound {best['bound']:.12f}")
+    del S, M
+    torch.cuda.empty_cache()
+    return res
 
 
 CONFIGS = [  # (sigma, d, l, dtype)
@@ -296,7 +373,7 @@ def main():
 
     ttb = None
     if not args.no_ttb:
-        ttb = time_to_bound(pk, h)
+        ttb = time_to_bound(pk, h, args.train_steps)
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(h, args.cpu_sample_log2)

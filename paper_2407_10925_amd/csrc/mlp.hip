@@ -55,15 +55,6 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t *p)
     return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(p));
 }
 
-// two groups of four consecutive BF16 values
-__device__ __forceinline__ bf16x8 load4x2(const uint16_t *p, const uint16_t *q)
-{
-    u32x2 a = *reinterpret_cast<const u32x2 *>(p);
-    u32x2 b = *reinterpret_cast<const u32x2 *>(q);
-    u32x4 v = {a.x, a.y, b.x, b.y};
-    return __builtin_bit_cast(bf16x8, v);
-}
-
 // window position (1-based) feeding input pair j
 __device__ __forceinline__ int pos_of(int j, int h) { return j < 8 ? j + 1 : h - 15 + j; }
 
@@ -79,21 +70,26 @@ __device__ __forceinline__ float input_at(uint64_t i, int h, int slot)
 // One wave owns 32 samples (two 16-sample MFMA column blocks).  A layer is
 // computed transposed, Y^T = W X^T: the weight tile is the A operand (rows =
 // output features) and the activations are the B operand (columns =
-// samples).  The MFMA result layout (lane holds 4 consecutive output
-// features of one sample) is then already the next layer's B operand once the
-// k order inside each 32-feature block is permuted: slot t of lane group g
-// in k-block kb holds feature 32kb + 4g + t (t < 4) or 32kb + 16 + 4g + t-4
-// (t >= 4).  Weight fragments are loaded with the same permutation, so the
-// sum over k is unchanged and activations never leave the registers.  Layers
+// samples).  The MFMA result layout (lane group g holds rows 4g .. 4g+3 of
+// a 16-row output tile for one sample) becomes the next layer's B operand
+// (lane group g holds k = 8g .. 8g+7 of a 32-wide k block) without moving
+// data, because output tile f is made of the weight rows
+//   perm_row(f, i) = 32 (f/2) + 8 (i/4) + 4 (f%2) + i%4,   i = 0..15,
+// so tiles 2kb and 2kb+1 give lane group g the eight consecutive features
+// 32kb + 8g .. 32kb + 8g + 7: input feature 32kb + 8g + t of the next layer
+// sits in slot t.  Activations never leave the registers.  Layers
 // 2 and 3 stream their weights through LDS one 16-row tile (8 KB) at a time,
 // double-buffered and shared by the workgroup's waves.
-constexpr int kFwdWaves = 4;  // one wave per SIMD: the kernel needs ~400 registers per lane
+constexpr int kFwdWaves = 8;
 constexpr int kFwdThreads = 64 * kFwdWaves;
 constexpr int kFwdSamples = 32 * kFwdWaves;  // per workgroup batch
 
-__device__ __forceinline__ int feat_of(int kb, int g, int t)
+__device__ __forceinline__ int feat_of(int kb, int g, int t) { return 32 * kb + 8 * g + t; }
+
+// weight row (output feature) computed in row i of output tile f
+__device__ __forceinline__ int perm_row(int f, int i)
 {
-    return 32 * kb + (t < 4 ? 4 * g + t : 16 + 4 * g + (t - 4));
+    return 32 * (f >> 1) + 8 * (i >> 2) + 4 * (f & 1) + (i & 3);
 }
 
 enum : int { kSrcIdx = 0, kSrcReps = 1 };
@@ -132,9 +128,13 @@ __device__ __forceinline__ void store_act(const FwdArgs &a, int layer, uint64_t 
     }
 }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// two floats -> BF16 pair (round to nearest even; one v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint32_t pack2(float lo, float hi)
 {
-    return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+    bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 __device__ __forceinline__ bf16x8 as_bf8(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3)
@@ -143,16 +143,115 @@ __device__ __forceinline__ bf16x8 as_bf8(uint32_t w0, uint32_t w1, uint32_t w2, 
     return __builtin_bit_cast(bf16x8, v);
 }
 
-// Activations of one wave: A[kb][b][w] = BF16 pair (2w, 2w+1) of k-block kb,
-// sample block b (slots as described above).  An output tile f fills words
-// (f&1)*2 and (f&1)*2+1 of k-block f/2.
+// Activations of one wave: act[kb][b][w] = BF16 pair (2w, 2w+1) of k-block
+// kb, sample block b (slots as described above).  An output tile f fills
+// words (f&1)*2 and (f&1)*2+1 of k-block f/2.
+//
+// Everything a lane reads at a lane-dependent address lives in LDS (W1, the
+// biases, w4, the streamed W2/W3 tiles), so those reads use immediate
+// offsets.  W2 and W3 do not fit in LDS together, so their 16-row tiles flow
+// through a ring of kRing slots as one endless stream (W2 tiles 0..15, W3
+// tiles 0..15, W2 again for the next batch, ...) loaded kRing-1 tiles ahead
+// by direct global-to-LDS loads.  The stream position of tile f is
+// congruent to f modulo kRing, so slot indices are compile-time constants.
+constexpr int kRing = 8;  // weight tiles in flight (8 KB each)
+
+// The ring slots are separate LDS objects so the compiler's wait insertion
+// can tell a read of one slot from the loads still landing in the others.
+__shared__ uint16_t ring0[16 * kW], ring1[16 * kW], ring2[16 * kW], ring3[16 * kW];
+__shared__ uint16_t ring4[16 * kW], ring5[16 * kW], ring6[16 * kW], ring7[16 * kW];
+static_assert(kRing == 8, "eight ring slots");
+
+__device__ __forceinline__ uint16_t *ring_slot(int k)
+{
+    switch (k & 7) {
+    case 0: return ring0;
+    case 1: return ring1;
+    case 2: return ring2;
+    case 3: return ring3;
+    case 4: return ring4;
+    case 5: return ring5;
+    case 6: return ring6;
+    default: return ring7;
+    }
+}
+
+constexpr int kW1Stride = kIn + 8;  // padded LDS row of W1 (80 bytes)
+
+struct FwdSmem {
+    uint16_t w1[kW * kW1Stride];    // W1, rows padded
+    float bias[3][kW];              // b1, b2, b3
+    float w4[kW];                   // BF16 w4 as floats
+};
+
+// Tile (layer, f) = weight rows perm_row(f, 0..15) of W2 (layer 0) or W3
+// (layer 1).  Each thread moves one 16-byte chunk straight from global memory
+// into the ring slot (gfx950 global_load_lds_dwordx4: no registers, counted
+// by vmcnt).  Thread t fills slot row t/32, chunk position t%32 of that row,
+// which holds weight chunk (t%32) xor (row%16): the swizzle spreads the 16
+// rows a fragment read touches over distinct LDS banks.
+__device__ __forceinline__ void issue_tile(const uint16_t *wb, int layer, int f, uint16_t *slot)
+{
+    const int t = threadIdx.x, row = t >> 5, pos = t & 31;
+    const uint16_t *src = wb + (layer ? oW3 : oW2) + perm_row(f, row) * kW + (pos ^ (row & 15)) * 8;
+    uint16_t *dst = slot + (threadIdx.x & ~63) * 8;  // the wave's 1 KB; lane i lands at +16 i
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                     (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+}
+
+// s_waitcnt vmcnt(n) (expcnt and lgkmcnt left free), n < 16
+// Workgroup barrier without a memory fence: a fence would make every wave
+// wait for all of its loads still landing in the ring.  Callers wait for the
+// loads they need (wait_vmcnt) before it; the "memory" clobber keeps the
+// compiler from moving LDS accesses across it.
+__device__ __forceinline__ void ring_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// s_waitcnt vmcnt(n), expcnt and lgkmcnt left free (n < 16)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 16, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt(0xF70 | N);
+}
+
+// s_waitcnt vmcnt(n) lgkmcnt(0): also every LDS read of this wave is done, so
+// after the following barrier no wave still reads the slot about to be
+// refilled (the compiler may move the reads' consumers past the barrier).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt_lds()
+{
+    static_assert(N >= 0 && N < 16, "vmcnt field");
+    __builtin_amdgcn_s_waitcnt(0x070 | N);
+}
+
 template <int SRC, bool STORE, typename T>
 __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
 {
-    __shared__ uint16_t wt[2][16 * kW];
+    __shared__ FwdSmem sm;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
     const uint64_t nbatch = (a.count + kFwdSamples - 1) / kFwdSamples;
+
+    // resident parameters (once per workgroup)
+    for (int q = threadIdx.x; q < kW * kIn / 8; q += kFwdThreads)  // 16-byte chunks
+        *reinterpret_cast<u32x4 *>(sm.w1 + (q >> 2) * kW1Stride + (q & 3) * 8) =
+            reinterpret_cast<const u32x4 *>(a.wb + oW1)[q];
+    for (int q = threadIdx.x; q < kW; q += kFwdThreads) {
+        sm.bias[0][q] = a.pf[ob1 + q];
+        sm.bias[1][q] = a.pf[ob2 + q];
+        sm.bias[2][q] = a.pf[ob3 + q];
+        sm.w4[q] = bf2f(a.wb[ow4 + q]);
+    }
+    const float b4 = a.pf[ob4];
+    wait_vmcnt<0>();
+#pragma unroll
+    for (int f = 0; f < kRing - 1; ++f) issue_tile(a.wb, 0, f, ring_slot(f));
+    __syncthreads();
+
+    // the four input pairs of this lane: window positions of pairs 4g .. 4g+3
+    int shift[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) shift[q] = 2 * (a.h - pos_of(4 * g + q, a.h));
 
     for (uint64_t batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
         const uint64_t s0 = batch * kFwdSamples + (uint64_t)wave * 32;
@@ -167,17 +266,20 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
             sidx[b] = SRC == kSrcIdx ? a.idx[sc] : sc;
             uint32_t w[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                w[q] = pack2(input_at(sidx[b], a.h, 8 * g + 2 * q), input_at(sidx[b], a.h, 8 * g + 2 * q + 1));
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t ab = (uint32_t)(sidx[b] >> shift[q]) & 3u;  // (a bit, b bit)
+                w[q] = pack2((ab & 2u) ? 1.0f : -1.0f, (ab & 1u) ? 1.0f : -1.0f);
+            }
             x[b] = as_bf8(w[0], w[1], w[2], w[3]);
         }
         uint32_t act[8][2][4];
 
-        // layer 1 (K = 32: one MFMA per output tile), weights straight from L2
+        // layer 1 (K = 32: one MFMA per output tile)
 #pragma unroll
         for (int f = 0; f < 16; ++f) {
-            const bf16x8 wf = load8(a.wb + oW1 + (16 * f + r) * kIn + 8 * g);
-            const float *bias = a.pf + ob1 + 16 * f + 4 * g;
+            const bf16x8 wf = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const u32x4 *>(sm.w1 + perm_row(f, r) * kW1Stride + 8 * g));
+            const float *bias = sm.bias[0] + perm_row(f, 4 * g);
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 const floatx4 acc = mfma(wf, x[b], floatx4{0, 0, 0, 0});
@@ -191,30 +293,32 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
         // layers 2 and 3
 #pragma unroll 1
         for (int layer = 0; layer < 2; ++layer) {
-            const uint16_t *W = a.wb + (layer == 0 ? oW2 : oW3);
-            const float *bias_v = a.pf + (layer == 0 ? ob2 : ob3);
-            if constexpr (STORE) store_act(a, layer, s0, r, g, valid, act);
+            if constexpr (STORE) {
+                store_act(a, layer, s0, r, g, valid, act);
+                wait_vmcnt<0>();  // keep vmcnt counting tile loads only
+            }
+            const float *bias_v = sm.bias[1 + layer];
             uint32_t nxt[8][2][4];
-            for (int q = threadIdx.x; q < 512; q += kFwdThreads)  // stage tile 0 (8 KB)
-                reinterpret_cast<u32x4 *>(wt[0])[q] = reinterpret_cast<const u32x4 *>(W)[q];
-            __syncthreads();
 #pragma unroll
             for (int f = 0; f < 16; ++f) {
-                if (f + 1 < 16)  // stage the next tile into the other buffer
-                    for (int q = threadIdx.x; q < 512; q += kFwdThreads)
-                        reinterpret_cast<u32x4 *>(wt[(f + 1) & 1])[q] =
-                            reinterpret_cast<const u32x4 *>(W + (f + 1) * 16 * kW)[q];
-                const uint16_t *tile = wt[f & 1] + r * kW;
+                wait_vmcnt_lds<kRing - 2>();  // this wave's part of tile f has landed
+                ring_barrier();               // every wave's part has; slot f-1 is free
+                {
+                    const int fn = f + kRing - 1;  // next tile of the stream
+                    issue_tile(a.wb, fn < 16 ? layer : layer ^ 1, fn & 15, ring_slot(fn));
+                }
+                const uint16_t *tile = ring_slot(f) + r * kW;
                 floatx4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
                 for (int kb = 0; kb < 8; ++kb) {
-                    const bf16x8 wf = load4x2(tile + 32 * kb + 4 * g, tile + 32 * kb + 16 + 4 * g);
+                    const bf16x8 wf = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const u32x4 *>(tile + (((4 * kb + g) ^ r) * 8)));
 #pragma unroll
                     for (int b = 0; b < 2; ++b)
                         acc[b] = mfma(wf, as_bf8(act[kb][b][0], act[kb][b][1], act[kb][b][2],
                                                  act[kb][b][3]), acc[b]);
                 }
-                const float *bias = bias_v + 16 * f + 4 * g;
+                const float *bias = bias_v + perm_row(f, 4 * g);
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                     nxt[f >> 1][b][(f & 1) * 2 + 0] =
@@ -222,7 +326,6 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
                     nxt[f >> 1][b][(f & 1) * 2 + 1] =
                         pack2(fmaxf(acc[b][2] + bias[2], 0.0f), fmaxf(acc[b][3] + bias[3], 0.0f));
                 }
-                __syncthreads();
             }
 #pragma unroll
             for (int kb = 0; kb < 8; ++kb)
@@ -239,8 +342,7 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
         for (int kb = 0; kb < 8; ++kb)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int f0 = feat_of(kb, g, 2 * q), f1 = feat_of(kb, g, 2 * q + 1);
-                const float w0 = bf2f(a.wb[ow4 + f0]), w1 = bf2f(a.wb[ow4 + f1]);
+                const float w0 = sm.w4[feat_of(kb, g, 2 * q)], w1 = sm.w4[feat_of(kb, g, 2 * q + 1)];
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                     part[b] += w0 * bf2f((uint16_t)(act[kb][b][q] & 0xFFFFu));
@@ -253,7 +355,6 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
             part[b] += __shfl_xor(part[b], 32);
         }
         if (g == 0) {
-            const float b4 = a.pf[ob4];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
                 if (!valid[b]) continue;
@@ -273,7 +374,9 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
                 }
             }
         }
+        wait_vmcnt<0>();  // outputs written; vmcnt again counts tile loads only
     }
+    wait_vmcnt<0>();      // no load into LDS outlives the workgroup
 }
 
 // ------------------------------------------------------------------ NT GEMM
@@ -373,17 +476,19 @@ __global__ __launch_bounds__(256) void relu_backward(const float *__restrict__ d
     dZ[e] = f2bf(bf2f(H[e]) > 0.0f ? dH[e] : 0.0f);
 }
 
-// out[c] = sum_r w[r] * M[r][c] (w = null means 1), M BF16 rows x 256, one
-// thread per column, rows in increasing order
-__global__ __launch_bounds__(256) void column_sums(const uint16_t *__restrict__ M,
-                                                   const float *__restrict__ w, int rows,
-                                                   float *__restrict__ out)
+// part[k][c] = sum over rows r of chunk k (kColChunk rows) of w[r] * M[r][c]
+// (w = null means 1), M BF16 rows x 256; reduce_splits then adds the chunks
+// in increasing order (deterministic).
+constexpr int kColChunk = 64;
+__global__ __launch_bounds__(256) void column_sums_part(const uint16_t *__restrict__ M,
+                                                        const float *__restrict__ w, int rows,
+                                                        float *__restrict__ part)
 {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= kW) return;
+    const int c = threadIdx.x, k = blockIdx.x;
+    const int r0 = k * kColChunk, r1 = min(rows, r0 + kColChunk);
     float s = 0.0f;
-    for (int r = 0; r < rows; ++r) s += (w ? w[r] : 1.0f) * bf2f(M[(size_t)r * kW + c]);
-    out[c] = s;
+    for (int r = r0; r < r1; ++r) s += (w ? w[r] : 1.0f) * bf2f(M[(size_t)r * kW + c]);
+    part[(size_t)k * kW + c] = s;
 }
 
 __global__ void sum_vector(const float *__restrict__ v, int count, float *__restrict__ out)
@@ -499,7 +604,10 @@ MlpWs mlp_ws_layout(int64_t batch)
     w.T2 = take(B * kW * 2);
     w.WT = take((size_t)2 * kW * kW * 2);
     w.splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, batch / 512));
-    w.part = take((size_t)w.splits * kW * kW * 4);
+    // split-K partial sums of the weight gradients, or the column-sum partials
+    const size_t part_floats = std::max<size_t>((size_t)w.splits * kW * kW,
+                                                (size_t)((batch + kColChunk - 1) / kColChunk) * kW);
+    w.part = take(part_floats * 4);
     w.bytes = o;
     return w;
 }
@@ -550,6 +658,17 @@ static hipError_t gemm(const uint16_t *A, const uint16_t *B, float *C, int M, in
     return hipGetLastError();
 }
 
+static hipError_t column_sums(const uint16_t *M, const float *w, int rows, float *part, float *out,
+                              hipStream_t s)
+{
+    const int chunks = (rows + kColChunk - 1) / kColChunk;
+    column_sums_part<<<chunks, 256, 0, s>>>(M, w, rows, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    reduce_splits<<<1, 256, 0, s>>>(part, chunks, (size_t)kW, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_backward(const uint16_t *wb, const float *dy, int64_t count,
                                unsigned char *ws, const MlpWs &L, const uint64_t *idx, int h,
                                float *grad, hipStream_t s)
@@ -569,8 +688,7 @@ hipError_t launch_mlp_backward(const uint16_t *wb, const float *dy, int64_t coun
     hipError_t e;
 #define LCSB_TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
     // layer 4
-    column_sums<<<1, 256, 0, s>>>(H3, dy, B, grad + ow4);
-    LCSB_TRY(hipGetLastError());
+    LCSB_TRY(column_sums(H3, dy, B, part, grad + ow4, s));
     sum_vector<<<1, 256, 0, s>>>(dy, B, grad + ob4);
     LCSB_TRY(hipGetLastError());
     head_backward<<<ew, 256, 0, s>>>(dy, H3, wb, B, dZ);
@@ -579,8 +697,7 @@ hipError_t launch_mlp_backward(const uint16_t *wb, const float *dy, int64_t coun
     const uint16_t *Hin[2] = {H2, H1};
     const int oW[2] = {oW3, oW2}, ob[2] = {ob3, ob2};
     for (int L3 = 0; L3 < 2; ++L3) {
-        column_sums<<<1, 256, 0, s>>>(dZ, nullptr, B, grad + ob[L3]);
-        LCSB_TRY(hipGetLastError());
+        LCSB_TRY(column_sums(dZ, nullptr, B, part, grad + ob[L3], s));
         transpose_bf16<<<dim3(kW / 32, B / 32), 256, 0, s>>>(dZ, T1, B, kW);      // dZ^T [256][B]
         LCSB_TRY(hipGetLastError());
         transpose_bf16<<<dim3(kW / 32, B / 32), 256, 0, s>>>(Hin[L3], T2, B, kW);  // H^T [256][B]
@@ -593,8 +710,7 @@ hipError_t launch_mlp_backward(const uint16_t *wb, const float *dy, int64_t coun
         LCSB_TRY(hipGetLastError());
     }
     // layer 1: gW1 = dZ1^T X, gb1
-    column_sums<<<1, 256, 0, s>>>(dZ, nullptr, B, grad + ob1);
-    LCSB_TRY(hipGetLastError());
+    LCSB_TRY(column_sums(dZ, nullptr, B, part, grad + ob1, s));
     encode_x<<<(unsigned)(((size_t)B * kIn + 255) / 256), 256, 0, s>>>(idx, h, (uint64_t)B, X);
     LCSB_TRY(hipGetLastError());
     transpose_bf16<<<dim3(kW / 32, B / 32), 256, 0, s>>>(dZ, T1, B, kW);

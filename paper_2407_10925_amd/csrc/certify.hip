@@ -100,123 +100,189 @@ __global__ __launch_bounds__(kBlock) void cert_r_final(unsigned char *__restrict
     }
 }
 
-// Offset, inside the lowest slot, of the t-th appended tuple of the strings
-// in SET: lexicographic order, the smallest string index most significant.
-template <int SIGMA, int D, int SET>
-__device__ __forceinline__ constexpr uint64_t tuple_offset(int t)
+// ------------------------------------------------------------------ W pass
+// One thread per x (the non-head positions) evaluates W at every head slot
+// of x, reading the all-advance group of x once and each branch group as a
+// vector.  Per coordinate the arithmetic is exactly the one stated above
+// (identical to evaluating each coordinate on its own).
+
+template <typename T>
+__device__ __forceinline__ void ld4(const T *p, double *v)
 {
-    constexpr int BETA = SIGMA == 2 ? 1 : 2;
-    uint64_t o = 0;
-    int rest = t;
-    for (int j = D - 1; j >= 0; --j)
-        if ((SET >> j) & 1) {
-            o |= (uint64_t)(rest & (SIGMA - 1)) << (BETA * (D - 1 - j));
-            rest >>= BETA;
-        }
-    return o;
+    if constexpr (std::is_same<T, float>::value) {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+        const double2 a = reinterpret_cast<const double2 *>(p)[0];
+        const double2 b = reinterpret_cast<const double2 *>(p)[1];
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
 }
 
-// Mean over the branch advancing the strings in SET (Algorithm 1), every
-// operation rounded toward -inf; reads u + (d-k)R with k = |SET|.
-// smask[j] = the symbol field of string j replicated over every position.
-template <int SIGMA, int D, int SET, typename T>
-__device__ __forceinline__ double branch_mean_rd(const T *__restrict__ u, uint64_t i, uint64_t n,
-                                                 const uint64_t *smask, const double *shift)
+// mean over CNT values of (v + shift): every add rounded toward -inf, the
+// pairwise tree in the given order, exact power-of-two scaling rounded down
+template <int CNT>
+__device__ __forceinline__ double mean_rd(double *v, double shift, int log2cnt)
 {
-    constexpr int BETA = SIGMA == 2 ? 1 : 2;
-    constexpr int SLOT = BETA * D;
-    constexpr int K = __builtin_popcount(SET);
-    constexpr int CNT = 1 << (BETA * K);
-    uint64_t sm = 0;
 #pragma unroll
-    for (int j = 0; j < D; ++j)
-        if ((SET >> j) & 1) sm |= smask[j];
-    const uint64_t base = (i & ~sm) | ((i << SLOT) & sm & (n - 1));
-    double v[CNT];
-#pragma unroll
-    for (int t = 0; t < CNT; ++t)
-        v[t] = add_rd((double)u[base | tuple_offset<SIGMA, D, SET>(t)], shift[K]);
+    for (int t = 0; t < CNT; ++t) v[t] = add_rd(v[t], shift);
 #pragma unroll
     for (int step = 1; step < CNT; step <<= 1)
 #pragma unroll
         for (int t = 0; t < CNT; t += 2 * step) v[t] = add_rd(v[t], v[t + step]);
-    return scale_pow2_rd(v[0], BETA * K);
+    return scale_pow2_rd(v[0], log2cnt);
 }
 
-// max over the branch sets that occur (bit SET of `occurs`); order-free (max)
-template <int SIGMA, int D, int SET, typename T>
-__device__ __forceinline__ void max_branches(const T *__restrict__ u, uint64_t i, uint64_t n,
-                                             uint32_t occurs, const uint64_t *smask,
-                                             const double *shift, double &best)
+struct WBest {
+    double w = -INFINITY;
+    uint64_t arg = 0, nonfinite = 0;
+    // candidates arrive in any order: keep the max, lowest index on ties
+    __device__ __forceinline__ void add(double u_i, double f_lo, double dR_up, uint64_t i)
+    {
+        const double w_i = add_ru(add_ru(u_i, dR_up), -f_lo);
+        if (!isfinite(w_i)) ++nonfinite;
+        if (w_i > w || (w_i == w && i < arg)) { w = w_i; arg = i; }
+    }
+};
+
+// sigma = d = 2: heads 00, 01, 10, 11 of x
+template <typename T>
+__device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint64_t x,
+                                      const double *shift, double dR_up, WBest &best)
 {
-    if constexpr (SET > 0) {
-        if ((occurs >> SET) & 1u) {
-            const double m = branch_mean_rd<SIGMA, D, SET, T>(u, i, n, smask, shift);
-            if (m > best) best = m;
+    const uint64_t nq = n >> 2, am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
+    double g[4];
+    ld4(u + 4 * x, g);
+    const double f_match = add_rd(1.0, mean_rd<4>(g, shift[2], 2));
+    best.add((double)u[x], f_match, dR_up, x);
+    best.add((double)u[3 * nq + x], f_match, dR_up, 3 * nq + x);
+#pragma unroll
+    for (int hd = 1; hd <= 2; ++hd) {  // heads 01, 10
+        const uint64_t i = (uint64_t)hd * nq + x;
+        const uint64_t sb = (i & am) | ((i << 2) & bm);
+        const uint64_t sa = ((i << 2) & am) | (i & bm);
+        double q[4], pb[2], pa[2];
+        ld4(u + (sb & ~(uint64_t)3), q);
+        pb[0] = q[sb & 3]; pb[1] = q[(sb & 3) + 1];
+        ld4(u + (sa & ~(uint64_t)3), q);
+        pa[0] = q[sa & 1]; pa[1] = q[(sa & 1) + 2];
+        const double mb = mean_rd<2>(pb, shift[1], 1);
+        const double ma = mean_rd<2>(pa, shift[1], 1);
+        best.add((double)u[i], ma > mb ? ma : mb, dR_up, i);
+    }
+}
+
+// sigma = 4, d = 2: all 16 head pairs (a1, b1) of x.  Branches of a
+// mismatched pair: advance b (depends on a1), advance a (depends on b1),
+// advance both (shared with the all-match value).
+template <typename T>
+__device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int h, uint64_t x,
+                                      const double *shift, double dR_up, WBest &best)
+{
+    const int top = 4 * (h - 1);
+    const uint64_t am = 0xCCCCCCCCCCCCCCCCull & (n - 1), bm = ~am & (n - 1);
+    double g[16];
+#pragma unroll
+    for (int t = 0; t < 16; t += 4) ld4(u + 16 * x + t, g + t);
+    const double m_both = mean_rd<16>(g, shift[2], 4);
+    const double f_match = add_rd(1.0, m_both);
+    double mb[4], ma[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        // head slot (c, .): advance b keeps a = (c, a_2..a_h)
+        const uint64_t ib = ((uint64_t)(c << 2) << top) | x;
+        const uint64_t sb = (ib & am) | ((ib << 4) & bm);
+        double q[4];
+        ld4(u + sb, q);
+        mb[c] = mean_rd<4>(q, shift[1], 2);
+        // head slot (., c): advance a keeps b = (c, b_2..b_h)
+        const uint64_t ia = ((uint64_t)c << top) | x;
+        const uint64_t sa = ((ia << 4) & am) | (ia & bm);
+        double v[4] = {(double)u[sa], (double)u[sa + 4], (double)u[sa + 8], (double)u[sa + 12]};
+        ma[c] = mean_rd<4>(v, shift[1], 2);
+    }
+#pragma unroll
+    for (int a1 = 0; a1 < 4; ++a1)
+#pragma unroll
+        for (int b1 = 0; b1 < 4; ++b1) {
+            const uint64_t i = ((uint64_t)(a1 * 4 + b1) << top) | x;
+            double f;
+            if (a1 == b1) {
+                f = f_match;
+            } else {
+                f = mb[a1] > ma[b1] ? mb[a1] : ma[b1];
+                f = m_both > f ? m_both : f;
+            }
+            best.add((double)u[i], f, dR_up, i);
         }
-        max_branches<SIGMA, D, SET - 1, T>(u, i, n, occurs, smask, shift, best);
-    }
 }
 
-// W[i] = (u[i] + dR) - F(u + shift_1, .., u + shift_d)[i]: F rounded down,
-// the two outer operations rounded up.
-template <int SIGMA, int D, typename T>
-__device__ double w_at(const T *__restrict__ u, uint64_t i, uint64_t n, int h,
-                       const uint64_t *smask, const double *shift, double dR_up)
+// sigma = 2, d = 3: the 8 head triples of x.  A mismatched triple has two
+// branches: the strings with head 1 advance (z = 0) and the strings with
+// head 0 advance (z = 1); k = |N| selects the lag and shift.
+template <int SET, typename T>
+__device__ __forceinline__ double branch23(const T *__restrict__ u, uint64_t n, uint64_t i,
+                                           const double *shift)
 {
-    constexpr int BETA = SIGMA == 2 ? 1 : 2;
-    constexpr int SLOT = BETA * D;
-    const int top = SLOT * (h - 1);
-    int hs[D];
+    // SET: bit 2 = string 1, bit 1 = string 2, bit 0 = string 3
+    constexpr int K = __builtin_popcount(SET);
+    const uint64_t r3 = (n - 1) / 7;
+    const uint64_t sm = ((SET & 4) ? r3 << 2 : 0) | ((SET & 2) ? r3 << 1 : 0) | ((SET & 1) ? r3 : 0);
+    const uint64_t base = (i & ~sm) | ((i << 3) & sm & (n - 1));
+    double v[K == 1 ? 2 : 4];
+    int t = 0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) hs[j] = (int)((i >> (top + BETA * (D - 1 - j))) & (SIGMA - 1));
-    bool all_match = true;
-#pragma unroll
-    for (int j = 1; j < D; ++j) all_match = all_match && hs[j] == hs[0];
-    // N_z = strings whose head is not z; the empty set (z = common head) is skipped
-    uint32_t occurs = 0;
-#pragma unroll
-    for (int z = 0; z < SIGMA; ++z) {
-        uint32_t set = 0;
-#pragma unroll
-        for (int j = 0; j < D; ++j)
-            if (hs[j] != z) set |= 1u << j;
-        occurs |= 1u << set;
+    for (int c = 0; c < 8; ++c)  // appended tuples in lexicographic order of the moved strings
+        if ((c & ~SET) == 0) v[t++] = (double)u[base | (uint64_t)c];
+    return K == 1 ? mean_rd<2>(v, shift[1], 1) : mean_rd<4>(v, shift[2], 2);
+}
+
+template <typename T>
+__device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int h, uint64_t x,
+                                      const double *shift, double dR_up, WBest &best)
+{
+    const int top = 3 * (h - 1);
+    double g[8];
+    ld4(u + 8 * x, g);
+    ld4(u + 8 * x + 4, g + 4);
+    const double f_match = add_rd(1.0, mean_rd<8>(g, shift[3], 3));
+    best.add((double)u[x], f_match, dR_up, x);
+    const uint64_t i7 = ((uint64_t)7 << top) | x;
+    best.add((double)u[i7], f_match, dR_up, i7);
+#define LCSB_HEAD(H)                                                                      \
+    {                                                                                     \
+        const uint64_t i = ((uint64_t)(H) << top) | x;                                    \
+        const double b1 = branch23<(H), T>(u, n, i, shift);      /* z = 0 */             \
+        const double b0 = branch23<(~(H)) & 7, T>(u, n, i, shift); /* z = 1 */           \
+        best.add((double)u[i], b0 > b1 ? b0 : b1, dR_up, i);                              \
     }
-    occurs &= ~1u;
-    double best = -INFINITY;
-    max_branches<SIGMA, D, (1 << D) - 1, T>(u, i, n, occurs, smask, shift, best);
-    const double f_lo = all_match ? add_rd(1.0, best) : best;
-    return add_ru(add_ru((double)u[i], dR_up), -f_lo);
+    LCSB_HEAD(1) LCSB_HEAD(2) LCSB_HEAD(3) LCSB_HEAD(4) LCSB_HEAD(5) LCSB_HEAD(6)
+#undef LCSB_HEAD
 }
 
 template <int SIGMA, int D, typename T>
 __global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u, uint64_t n, int h,
                                                 unsigned char *__restrict__ ws)
 {
-    constexpr int BETA = SIGMA == 2 ? 1 : 2;
-    constexpr int SLOT = BETA * D;
+    constexpr int SLOT = (SIGMA == 2 ? 1 : 2) * D;
     const double *sc = reinterpret_cast<const double *>(ws);
     const double dR_up = sc[Ws::kDRup / 8];
-    double shift[D + 1];
+    double shift[4];
 #pragma unroll
-    for (int k = 0; k <= D; ++k) shift[k] = sc[Ws::kShift / 8 + k];  // (d-k)R, rounded down
-    uint64_t rep = (n - 1) / ((1ull << SLOT) - 1);  // 1 in the lowest bit of every slot
-    uint64_t smask[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) smask[j] = (rep * (((1ull << BETA) - 1))) << (BETA * (D - 1 - j));
-
-    double best = -INFINITY;
-    uint64_t arg = 0, nonfinite = 0;
+    for (int k = 0; k < 4; ++k) shift[k] = sc[Ws::kShift / 8 + k];  // (d-k)R, rounded down
+    const uint64_t nx = n >> SLOT;
+    WBest best;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
-        const double w = w_at<SIGMA, D, T>(u, j, n, h, smask, shift, dR_up);
-        if (!isfinite(w)) ++nonfinite;
-        if (w > best) { best = w; arg = j; }
+    for (uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x; x < nx; x += stride) {
+        if constexpr (SIGMA == 2 && D == 2) w_s2d2<T>(u, n, x, shift, dR_up, best);
+        else if constexpr (SIGMA == 4) w_s4d2<T>(u, n, h, x, shift, dR_up, best);
+        else w_s2d3<T>(u, n, h, x, shift, dR_up, best);
     }
-    block_reduce(best, arg, nonfinite);
+    double w = best.w;
+    uint64_t arg = best.arg, nonfinite = best.nonfinite;
+    block_reduce(w, arg, nonfinite);
     if (threadIdx.x == 0) {
-        reinterpret_cast<double *>(ws + Ws::kPartVal)[blockIdx.x] = best;
+        reinterpret_cast<double *>(ws + Ws::kPartVal)[blockIdx.x] = w;
         reinterpret_cast<uint64_t *>(ws + Ws::kPartIdx)[blockIdx.x] = arg;
         reinterpret_cast<uint64_t *>(ws + Ws::kPartCnt)[blockIdx.x] = nonfinite;
     }
@@ -246,14 +312,14 @@ int reduce_blocks(uint64_t n)
 }
 
 template <typename T>
-hipError_t launch_w(const Geometry &g, const T *u, unsigned char *ws, int nb, hipStream_t s)
+hipError_t launch_w(const Geometry &g, const T *u, unsigned char *ws, int nbw, hipStream_t s)
 {
     if (g.sigma == 2 && g.d == 2)
-        cert_w<2, 2, T><<<nb, kBlock, 0, s>>>(u, g.n, g.h, ws);
+        cert_w<2, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else if (g.sigma == 4 && g.d == 2)
-        cert_w<4, 2, T><<<nb, kBlock, 0, s>>>(u, g.n, g.h, ws);
+        cert_w<4, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else if (g.sigma == 2 && g.d == 3)
-        cert_w<2, 3, T><<<nb, kBlock, 0, s>>>(u, g.n, g.h, ws);
+        cert_w<2, 3, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -271,8 +337,9 @@ hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int
     cert_r_final<<<1, kBlock, 0, s>>>(ws, nb, g.d, std::is_same<T, float>::value ? 1 : 0,
                                       u_slot, prev_slot);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_w<T>(g, static_cast<const T *>(u), ws, nb, s)) != hipSuccess) return e;
-    cert_w_final<<<1, kBlock, 0, s>>>(ws, nb);
+    const int nbw = reduce_blocks(g.n >> g.slot);  // one thread per x
+    if ((e = launch_w<T>(g, static_cast<const T *>(u), ws, nbw, s)) != hipSuccess) return e;
+    cert_w_final<<<1, kBlock, 0, s>>>(ws, nbw);
     return hipGetLastError();
 }
 

@@ -45,6 +45,11 @@ __device__ __forceinline__ T tree16(const T *g) { return tree8(g) + tree8(g + 8)
 template <typename T>
 __device__ __forceinline__ T vmax(T best, T cand) { return cand > best ? cand : best; }
 
+// The new table is not read again until the next sweep, after 2-3 more
+// tables have streamed through the caches: write it non-temporally.
+template <typename T>
+__device__ __forceinline__ void put(T *p, T v) { __builtin_nontemporal_store(v, p); }
+
 // contiguous aligned loads
 __device__ __forceinline__ void load2(const double *p, double &a, double &b)
 {
@@ -109,19 +114,24 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
     T b0, b1;
     load2(lag1 + sb, b0, b1);
     const T mb = (b0 + b1) * (T)0.5;
-    const T ma = (lag1[sa] + lag1[sa + 2]) * (T)0.5;
+    // the advance-a pair sa, sa+2 is the even or odd half of the aligned
+    // group sa & ~3, which the neighbouring thread (x ^ 1) also reads: one
+    // vector load of the group serves both
+    T q[4];
+    load4(lag1 + (sa & ~(uint64_t)3), q);
+    const T ma = ((sa & 1) ? (q[1] + q[3]) : (q[0] + q[2])) * (T)0.5;
     const T mis = vmax(mb, ma);
 
     if constexpr (kF32) {
-        out[x] = match - y0;
-        out[n - 1 - x] = match - y0;
-        out[i] = mis - y0;
-        out[n - 1 - i] = mis - y0;
+        put(out + x, match - y0);
+        put(out + (n - 1 - x), match - y0);
+        put(out + i, mis - y0);
+        put(out + (n - 1 - i), mis - y0);
     } else {
-        out[x] = match;
-        out[n - 1 - x] = match;
-        out[i] = mis;
-        out[n - 1 - i] = mis;
+        put(out + x, match);
+        put(out + (n - 1 - x), match);
+        put(out + i, mis);
+        put(out + (n - 1 - i), mis);
     }
 }
 
@@ -182,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
         const uint64_t i = ((uint64_t)r << top) | x;
         const T v = kF32 ? (T)(val[r] - y0) : val[r];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) out[i ^ ((uint64_t)m * rep)] = v;
+        for (int m = 0; m < 4; ++m) put(out + (i ^ ((uint64_t)m * rep)), v);
     }
 }
 
@@ -265,8 +275,8 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
     for (int r = 0; r < 4; ++r) {
         const uint64_t i = ((uint64_t)r << top) | x;
         const T v = kF32 ? (T)(val[r] - y0) : val[r];
-        out[i] = v;
-        out[mask - i] = v;
+        put(out + i, v);
+        put(out + (mask - i), v);
     }
 }
 

@@ -8,6 +8,12 @@
 //           with F rounded down step by step (each shifted argument, every
 //           add of the pairwise tree, the scaling by sigma^-k, the 1 +) and
 //           both outer operations rounded up; maxW and its lowest index.
+//           The W pass runs with the wave's FP rounding mode set to toward
+//           -inf, so every directed operation is one hardware instruction;
+//           a round-up sum is the negation of the round-down sum of the
+//           negated operands.  IEEE-754 fixes each directed result
+//           uniquely, so this equals the error-free-transform evaluation
+//           bit for bit.
 //
 // Unlike the sweep, this evaluates every coordinate and assumes no symmetry
 // of u, so the certificate holds for any table.  FP32 tables are certified as
@@ -119,27 +125,59 @@ __device__ __forceinline__ void ld4(const T *p, double *v)
     }
 }
 
-// mean over CNT values of (v + shift): every add rounded toward -inf, the
-// pairwise tree in the given order, exact power-of-two scaling rounded down
+// Set this wave's FP rounding mode (MODE.FP_ROUND, single and double
+// fields) to toward -inf.  The wave keeps the mode until it ends; a new
+// wave starts from the kernel descriptor's mode.  The returned zero is
+// opaque to the compiler: every load of the pass adds it to its base, so no
+// arithmetic on loaded data can be scheduled ahead of the switch.  Within
+// such a pass the code must not negate a product (the compiler may rewrite
+// -(a b) as a (-b), which is equal only under round-to-nearest); sums,
+// differences, negated sums, max and the exact FP32 -> FP64 widening are
+// safe.
+__device__ __forceinline__ uint64_t round_toward_neg_inf()
+{
+    uint64_t z = 0;
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 0, 4), 10\n\ts_nop 3" : "+s"(z));
+    return z;
+}
+
+// 2^-j for j = 1..4, hidden from the compiler so that the scaling stays a
+// multiply (rounded by the mode) rather than a rewrite into ldexp.
+struct Scales {
+    double q[5];
+    __device__ __forceinline__ Scales()
+    {
+        q[0] = 1.0; q[1] = 0.5; q[2] = 0.25; q[3] = 0.125; q[4] = 0.0625;
+#pragma unroll
+        for (int j = 1; j <= 4; ++j) asm volatile("" : "+s"(q[j]));
+    }
+};
+
+// In round-toward-minus-infinity mode: mean over CNT values of (v + shift),
+// every add rounded down, the pairwise tree in the given order, the exact
+// power-of-two scaling rounded down.
 template <int CNT>
-__device__ __forceinline__ double mean_rd(double *v, double shift, int log2cnt)
+__device__ __forceinline__ double mean_rd(double *v, double shift, double scale)
 {
 #pragma unroll
-    for (int t = 0; t < CNT; ++t) v[t] = add_rd(v[t], shift);
+    for (int t = 0; t < CNT; ++t) v[t] = v[t] + shift;
 #pragma unroll
     for (int step = 1; step < CNT; step <<= 1)
 #pragma unroll
-        for (int t = 0; t < CNT; t += 2 * step) v[t] = add_rd(v[t], v[t + step]);
-    return scale_pow2_rd(v[0], log2cnt);
+        for (int t = 0; t < CNT; t += 2 * step) v[t] = v[t] + v[t + step];
+    return v[0] * scale;
 }
 
 struct WBest {
     double w = -INFINITY;
     uint64_t arg = 0, nonfinite = 0;
-    // candidates arrive in any order: keep the max, lowest index on ties
+    // In round-toward-minus-infinity mode: W = RU(RU(u_i + dR_up) - f_lo)
+    // = -RD(RD(-u_i - dR_up) + f_lo).  Candidates arrive in any order: keep
+    // the max, lowest index on ties.
     __device__ __forceinline__ void add(double u_i, double f_lo, double dR_up, uint64_t i)
     {
-        const double w_i = add_ru(add_ru(u_i, dR_up), -f_lo);
+        const double t = (-u_i) - dR_up;
+        const double w_i = -(t + f_lo);
         if (!isfinite(w_i)) ++nonfinite;
         if (w_i > w || (w_i == w && i < arg)) { w = w_i; arg = i; }
     }
@@ -148,12 +186,13 @@ struct WBest {
 // sigma = d = 2: heads 00, 01, 10, 11 of x
 template <typename T>
 __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint64_t x,
-                                      const double *shift, double dR_up, WBest &best)
+                                      const double *shift, const Scales &sc, double dR_up,
+                                      WBest &best)
 {
     const uint64_t nq = n >> 2, am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
     double g[4];
     ld4(u + 4 * x, g);
-    const double f_match = add_rd(1.0, mean_rd<4>(g, shift[2], 2));
+    const double f_match = 1.0 + mean_rd<4>(g, shift[2], sc.q[2]);
     best.add((double)u[x], f_match, dR_up, x);
     best.add((double)u[3 * nq + x], f_match, dR_up, 3 * nq + x);
 #pragma unroll
@@ -166,8 +205,8 @@ __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint
         pb[0] = q[sb & 3]; pb[1] = q[(sb & 3) + 1];
         ld4(u + (sa & ~(uint64_t)3), q);
         pa[0] = q[sa & 1]; pa[1] = q[(sa & 1) + 2];
-        const double mb = mean_rd<2>(pb, shift[1], 1);
-        const double ma = mean_rd<2>(pa, shift[1], 1);
+        const double mb = mean_rd<2>(pb, shift[1], sc.q[1]);
+        const double ma = mean_rd<2>(pa, shift[1], sc.q[1]);
         best.add((double)u[i], ma > mb ? ma : mb, dR_up, i);
     }
 }
@@ -177,15 +216,16 @@ __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint
 // advance both (shared with the all-match value).
 template <typename T>
 __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int h, uint64_t x,
-                                      const double *shift, double dR_up, WBest &best)
+                                      const double *shift, const Scales &sc, double dR_up,
+                                      WBest &best)
 {
     const int top = 4 * (h - 1);
     const uint64_t am = 0xCCCCCCCCCCCCCCCCull & (n - 1), bm = ~am & (n - 1);
     double g[16];
 #pragma unroll
     for (int t = 0; t < 16; t += 4) ld4(u + 16 * x + t, g + t);
-    const double m_both = mean_rd<16>(g, shift[2], 4);
-    const double f_match = add_rd(1.0, m_both);
+    const double m_both = mean_rd<16>(g, shift[2], sc.q[4]);
+    const double f_match = 1.0 + m_both;
     double mb[4], ma[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -194,12 +234,12 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
         const uint64_t sb = (ib & am) | ((ib << 4) & bm);
         double q[4];
         ld4(u + sb, q);
-        mb[c] = mean_rd<4>(q, shift[1], 2);
+        mb[c] = mean_rd<4>(q, shift[1], sc.q[2]);
         // head slot (., c): advance a keeps b = (c, b_2..b_h)
         const uint64_t ia = ((uint64_t)c << top) | x;
         const uint64_t sa = ((ia << 4) & am) | (ia & bm);
         double v[4] = {(double)u[sa], (double)u[sa + 4], (double)u[sa + 8], (double)u[sa + 12]};
-        ma[c] = mean_rd<4>(v, shift[1], 2);
+        ma[c] = mean_rd<4>(v, shift[1], sc.q[2]);
     }
 #pragma unroll
     for (int a1 = 0; a1 < 4; ++a1)
@@ -222,7 +262,7 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
 // head 0 advance (z = 1); k = |N| selects the lag and shift.
 template <int SET, typename T>
 __device__ __forceinline__ double branch23(const T *__restrict__ u, uint64_t n, uint64_t i,
-                                           const double *shift)
+                                           const double *shift, const Scales &sc)
 {
     // SET: bit 2 = string 1, bit 1 = string 2, bit 0 = string 3
     constexpr int K = __builtin_popcount(SET);
@@ -234,26 +274,27 @@ __device__ __forceinline__ double branch23(const T *__restrict__ u, uint64_t n, 
 #pragma unroll
     for (int c = 0; c < 8; ++c)  // appended tuples in lexicographic order of the moved strings
         if ((c & ~SET) == 0) v[t++] = (double)u[base | (uint64_t)c];
-    return K == 1 ? mean_rd<2>(v, shift[1], 1) : mean_rd<4>(v, shift[2], 2);
+    return K == 1 ? mean_rd<2>(v, shift[1], sc.q[1]) : mean_rd<4>(v, shift[2], sc.q[2]);
 }
 
 template <typename T>
 __device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int h, uint64_t x,
-                                      const double *shift, double dR_up, WBest &best)
+                                      const double *shift, const Scales &sc, double dR_up,
+                                      WBest &best)
 {
     const int top = 3 * (h - 1);
     double g[8];
     ld4(u + 8 * x, g);
     ld4(u + 8 * x + 4, g + 4);
-    const double f_match = add_rd(1.0, mean_rd<8>(g, shift[3], 3));
+    const double f_match = 1.0 + mean_rd<8>(g, shift[3], sc.q[3]);
     best.add((double)u[x], f_match, dR_up, x);
     const uint64_t i7 = ((uint64_t)7 << top) | x;
     best.add((double)u[i7], f_match, dR_up, i7);
 #define LCSB_HEAD(H)                                                                      \
     {                                                                                     \
         const uint64_t i = ((uint64_t)(H) << top) | x;                                    \
-        const double b1 = branch23<(H), T>(u, n, i, shift);      /* z = 0 */             \
-        const double b0 = branch23<(~(H)) & 7, T>(u, n, i, shift); /* z = 1 */           \
+        const double b1 = branch23<(H), T>(u, n, i, shift, sc);      /* z = 0 */         \
+        const double b0 = branch23<(~(H)) & 7, T>(u, n, i, shift, sc); /* z = 1 */       \
         best.add((double)u[i], b0 > b1 ? b0 : b1, dR_up, i);                              \
     }
     LCSB_HEAD(1) LCSB_HEAD(2) LCSB_HEAD(3) LCSB_HEAD(4) LCSB_HEAD(5) LCSB_HEAD(6)
@@ -261,22 +302,25 @@ __device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int 
 }
 
 template <int SIGMA, int D, typename T>
-__global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u, uint64_t n, int h,
+__global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u_arg, uint64_t n, int h,
                                                 unsigned char *__restrict__ ws)
 {
     constexpr int SLOT = (SIGMA == 2 ? 1 : 2) * D;
-    const double *sc = reinterpret_cast<const double *>(ws);
-    const double dR_up = sc[Ws::kDRup / 8];
+    const uint64_t z = round_toward_neg_inf();
+    const T *__restrict__ u = u_arg + z;
+    const double *sc_ws = reinterpret_cast<const double *>(ws + z);
+    const double dR_up = sc_ws[Ws::kDRup / 8];
     double shift[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) shift[k] = sc[Ws::kShift / 8 + k];  // (d-k)R, rounded down
+    for (int k = 0; k < 4; ++k) shift[k] = sc_ws[Ws::kShift / 8 + k];  // (d-k)R, rounded down
+    const Scales sc;
     const uint64_t nx = n >> SLOT;
     WBest best;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x; x < nx; x += stride) {
-        if constexpr (SIGMA == 2 && D == 2) w_s2d2<T>(u, n, x, shift, dR_up, best);
-        else if constexpr (SIGMA == 4) w_s4d2<T>(u, n, h, x, shift, dR_up, best);
-        else w_s2d3<T>(u, n, h, x, shift, dR_up, best);
+        if constexpr (SIGMA == 2 && D == 2) w_s2d2<T>(u, n, x, shift, sc, dR_up, best);
+        else if constexpr (SIGMA == 4) w_s4d2<T>(u, n, h, x, shift, sc, dR_up, best);
+        else w_s2d3<T>(u, n, h, x, shift, sc, dR_up, best);
     }
     double w = best.w;
     uint64_t arg = best.arg, nonfinite = best.nonfinite;

@@ -97,6 +97,30 @@ def test_fp64_random_ring_one_sweep_and_certificate(pk, sigma, d, h):
     _same_cert(cur, oracle.certify(sigma, d, h, new, lags[0].numpy()))
 
 
+@pytest.mark.parametrize("sigma,d,h", [(2, 2, 5), (4, 2, 2), (2, 3, 3)], ids=lambda v: str(v))
+@pytest.mark.parametrize("scale", [1e-300, 2.0 ** -1021], ids=["tiny", "subnormal"])
+def test_fp64_tiny_and_subnormal_tables(pk, sigma, d, h, scale):
+    """Values near and below the smallest normal double: the sums stay exact
+    but halving an odd multiple of the smallest subnormal does not, and
+    1 + mean and the outer W steps round in both directions.  Sweep (round to
+    nearest) and certificate (directed) must still match bit for bit."""
+    say(f"tiny FP64 ring sigma={sigma} d={d} h={h} scale={scale:.3g}")
+    lags = [si.table(sigma, d, h, seed=60 + k, dtype=torch.float64, scale=scale) for k in range(d)]
+    assert bool((lags[0] > 0).any()) and (scale > 1e-305 or bool((lags[0] < 2.0 ** -1022).any()))
+    L = pk.Lcsb(sigma, d, h, "f64")
+    L.load_ring([x.cuda() for x in lags])
+    cur, _ = L.certify()
+    _same_cert(cur, oracle.certify(sigma, d, h, lags[0].numpy(), lags[1].numpy()))
+    for t in range(3):
+        L.iterate(1)
+        new = oracle.sweep(sigma, d, h, [x.numpy() for x in lags])
+        got, _ = L.lag(1)
+        assert np.array_equal(_host(got), new), f"sweep {t}"
+        lags = [torch.from_numpy(new)] + lags[:-1]
+        cur, _ = L.certify()
+        _same_cert(cur, oracle.certify(sigma, d, h, new, lags[1].numpy()))
+
+
 def test_load_ring_projects_onto_symmetric_tables(pk):
     say("load_ring projection")
     sigma, d, h = 4, 2, 3

@@ -17,7 +17,8 @@ Also printed in the same JSON line:
   cpu_baseline  the CPU oracle on this host, one sweep over a bounded sample
                 of the same table
   time_to_bound wall time to a certified bound within 1e-9 of the converged
-                plain FP64 bound, for plain FP64 and for FP32 + FP64 polish
+                plain FP64 bound, for plain FP64, for FP32 + FP64 polish, and
+                for the same started from the learned warm start
 """
 import argparse
 import hashlib
@@ -58,6 +59,8 @@ def parse():
                    help="only time one sweep and one certificate for every configuration")
     p.add_argument("--copy-gib", type=float, default=0.0,
                    help="only run one plain device copy of this many GiB (counter calibration)")
+    p.add_argument("--profile-seed", action="store_true",
+                   help="only seed an FP32 ring from an (untrained) warm-start network, twice")
     return p.parse_args()
 
 
@@ -110,19 +113,61 @@ def cpu_baseline(h, log2_sample):
                       f"{dt:.1f} s"}
 
 
+# Certification policy shared by every time-to-bound run (none uses B):
+TTB_CADENCE = 16      # plain FP64 and FP32 phases: sweeps between certificates
+SWITCH_GAIN = 2e-5    # leave FP32 once a positive best bound gains less than this in a period
+POLISH_FIRST = 32     # FP64 sweeps after the upcast before the first polish certificate
+POLISH_CADENCE = 8    # then a certificate every this many FP64 sweeps
+MAX_SWEEPS = 1600
+
+
+def fp32_until_floor(S):
+    """FP32 sweeps with a certificate every TTB_CADENCE sweeps until the best
+    bound is positive and gains less than SWITCH_GAIN over one period (the
+    FP32 error floor).  Returns (cur, best, certificates)."""
+    best_prev = None
+    certs = 0
+    while True:
+        S.iterate(TTB_CADENCE)
+        cur, best = S.certify()
+        certs += 1
+        if cur["sweep"] >= MAX_SWEEPS:
+            break
+        if best["bound"] > 0 and best_prev is not None and best["bound"] - best_prev < SWITCH_GAIN:
+            break
+        best_prev = best["bound"]
+    return cur, best, certs
+
+
+def polish(P, S, best, target):
+    """Upcast the FP32 ring into P and continue in FP64 until the best
+    certified bound reaches target.  Returns (FP64 sweeps, certificates, best)."""
+    if best["bound"] >= target:
+        return 0, 0, best
+    P.upcast(S)
+    swept, certs = 0, 0
+    step = POLISH_FIRST
+    while best["bound"] < target and swept < MAX_SWEEPS:
+        P.iterate(step)
+        swept += step
+        _, best = P.certify()  # the upcast carried the FP32 run's best over
+        certs += 1
+        step = POLISH_CADENCE
+    return swept, certs, best
+
+
 def time_to_bound(pk, h, train_steps=3000):
     """Wall time from the init call to the first certificate within 1e-9 of
-    the converged plain FP64 bound B.
+    the converged plain FP64 bound B (certificates, upcast and seeding
+    included).
 
-    plain:  FP64 from zero, a certificate every 16 sweeps, run until the
-            current certificate moves by less than 1e-10 and is the best so
-            far (B = that best); the time is that of the first certificate
+    plain:  FP64 from zero, a certificate every TTB_CADENCE sweeps, run on
+            until consecutive certificates move by less than 1e-10 (B = the
+            best bound then); its time is that of its first certificate
             >= B - 1e-9.
-    mixed:  FP32 from zero with a certificate every 32 sweeps; once a
-            certificate is positive and the best bound gains less than 1e-7
-            over a period, the FP32 ring is converted to FP64 and polished
-            with a certificate every 8 sweeps until the best bound reaches
-            B - 1e-9.
+    mixed:  FP32 from zero until its error floor (fp32_until_floor), then the
+            FP64 polish (polish) until the best bound reaches B - 1e-9.
+    learned: as mixed, from the warm-start network's seed (learned_run).
     """
     import torch
     out = {}
@@ -133,75 +178,64 @@ def time_to_bound(pk, h, train_steps=3000):
     hist = []
     prev = None
     while True:
-        P.iterate(16)
+        P.iterate(TTB_CADENCE)
         cur, best = P.certify()
         hist.append((time.perf_counter() - t0, best["bound"], cur["sweep"]))
         if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
             break
         prev = cur["bound"]
-        if cur["sweep"] >= 800:
+        if cur["sweep"] >= MAX_SWEEPS:
             break
     B = best["bound"]
     target = B - 1e-9
-    t_plain, s_plain = next((t, s) for t, b, s in hist if b >= target)
-    out["plain_f64"] = {"seconds": round(t_plain, 4), "sweeps": s_plain, "bound": B,
-                        "ran_sweeps": hist[-1][2], "certificate_every": 16}
+    k = next(i for i, (_, b, _) in enumerate(hist) if b >= target)
+    t_plain, s_plain = hist[k][0], hist[k][2]
+    out["plain_f64"] = {"seconds": round(t_plain, 4), "sweeps": s_plain, "certificates": k + 1,
+                        "bound": B, "ran_sweeps": hist[-1][2],
+                        "certificate_every": TTB_CADENCE}
     log(f"time to bound, plain FP64: {t_plain:.3f} s, {s_plain} sweeps, bound {B:.12f}")
 
     M = pk.Lcsb(2, 2, h, "f32")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     M.init_zero()
-    best_prev = None
-    while True:
-        M.iterate(32)
-        cur, best = M.certify()
-        if best["bound"] >= target or cur["sweep"] >= 800:
-            break
-        if cur["bound"] > 0 and best_prev is not None and best["bound"] - best_prev < 1e-7:
-            break
-        best_prev = best["bound"]
+    cur, best, certs32 = fp32_until_floor(M)
     sweeps32 = cur["sweep"]
     t_switch = time.perf_counter() - t0
-    if best["bound"] < target:
-        P.upcast(M)
-        while best["bound"] < target and cur["sweep"] < 1600:
-            P.iterate(8)
-            cur, best = P.certify()
+    sweeps64, certs64, best = polish(P, M, best, target)
+    torch.cuda.synchronize()
     t_mixed = time.perf_counter() - t0
     out["mixed_f32_polish"] = {"seconds": round(t_mixed, 4), "sweeps_f32": sweeps32,
-                               "sweeps_f64": cur["sweep"] - sweeps32,
+                               "sweeps_f64": sweeps64, "certificates": certs32 + certs64,
                                "switch_after_s": round(t_switch, 4), "bound": best["bound"],
                                "reached": best["bound"] >= target}
     log(f"time to bound, FP32 + FP64 polish: {t_mixed:.3f} s, {sweeps32} FP32 + "
-        f"{cur['sweep'] - sweeps32} FP64 sweeps, bound {best['bound']:.12f}")
+        f"{sweeps64} FP64 sweeps, bound {best['bound']:.12f}")
+    del M
+    torch.cuda.empty_cache()
     out["mixed_learned"] = learned_run(pk, h, P, target, train_steps)
-    del P, M
+    out["policy"] = {"certificate_every": TTB_CADENCE, "switch_gain": SWITCH_GAIN,
+                     "polish_first": POLISH_FIRST, "polish_every": POLISH_CADENCE}
+    del P
     torch.cuda.empty_cache()
     return out
 
 
 def learned_run(pk, h, P, target, train_steps):
     """FP32 + FP64 polish started from the warm-start network.  Training data:
-    converged FP64 tables at l = h-4, h-3, h-2 (zero start, sweeps until the
-    certificate moves by < 1e-10); training: `train_steps` Adam steps on
-    batches of 8192 drawn from those tables in turn; the seed uses the rate R
-    of the l = h-2 run.  Times are reported without and with data generation
-    and training."""
+    FP32 tables at l = h-4, h-3, h-2 run from zero to their error floor
+    (fp32_until_floor); training: `train_steps` Adam steps on batches of 8192
+    drawn from those tables in turn, cosine learning-rate decay; the seed
+    uses the rate R of the l = h-2 run.  Times are reported without and with
+    data generation and training."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tables = []
     for hh in (h - 4, h - 3, h - 2):
-        T = pk.Lcsb(2, 2, hh, "f64")
+        T = pk.Lcsb(2, 2, hh, "f32")
         T.init_zero()
-        prev = None
-        while True:
-            T.iterate(16)
-            cur, _ = T.certify()
-            if prev is not None and abs(cur["bound"] - prev) < 1e-10:
-                break
-            prev = cur["bound"]
+        cur, _, _ = fp32_until_floor(T)
         tables.append((hh, T))
     rate = cur["R"]
     torch.cuda.synchronize()
@@ -227,30 +261,19 @@ def learned_run(pk, h, P, target, train_steps):
     S.init_seed_mlp(M, rate)
     torch.cuda.synchronize()
     t_seed = time.perf_counter() - t2
-    best_prev = None
-    while True:
-        S.iterate(32)
-        cur, best = S.certify()
-        if best["bound"] >= target or cur["sweep"] >= 800:
-            break
-        if cur["bound"] > 0 and best_prev is not None and best["bound"] - best_prev < 1e-7:
-            break
-        best_prev = best["bound"]
+    cur, best, certs32 = fp32_until_floor(S)
     sweeps32 = cur["sweep"]
-    if best["bound"] < target:
-        P.upcast(S)
-        while best["bound"] < target and cur["sweep"] < 1600:
-            P.iterate(8)
-            cur, best = P.certify()
+    sweeps64, certs64, best = polish(P, S, best, target)
+    torch.cuda.synchronize()
     t_run = time.perf_counter() - t2
     res = {"seconds": round(t_run, 4), "seconds_with_training": round(t_run + t_data + t_train, 4),
            "data_s": round(t_data, 4), "training_s": round(t_train, 4), "train_steps": train_steps,
            "last_batch_loss": loss, "seed_s": round(t_seed, 4),
            "seed_tflops": round(2.79e5 * (4 ** h // 2) / t_seed / 1e12, 1),
-           "sweeps_f32": sweeps32, "sweeps_f64": cur["sweep"] - sweeps32,
+           "sweeps_f32": sweeps32, "sweeps_f64": sweeps64, "certificates": certs32 + certs64,
            "bound": best["bound"], "reached": best["bound"] >= target}
     log(f"time to bound, learned + FP32 + FP64 polish: {t_run:.3f} s ({t_seed:.3f} s seed), "
-        f"{sweeps32} FP32 + {cur['sweep'] - sweeps32} FP64 sweeps, bound {best['bound']:.12f}")
+        f"{sweeps32} FP32 + {sweeps64} FP64 sweeps, bound {best['bound']:.12f}")
     del S, M
     torch.cuda.empty_cache()
     return res
@@ -304,6 +327,23 @@ def profile_only(pk, h, sweeps):
     log(f"ran {sweeps} FP32 sweeps at l={h}")
 
 
+def seed_only(pk, h):
+    """Two seedings of an l = h FP32 ring by the warm-start network (random
+    initial weights: the same work as a trained one), the second one timed."""
+    import torch
+    M = pk.Mlp(batch=256, seed=1)
+    S = pk.Lcsb(2, 2, h, "f32")
+    S.init_seed_mlp(M, 0.39)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.init_seed_mlp(M, 0.39)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flop = 2.79e5 * (4 ** h // 2)
+    log(f"seed at l={h}: {dt * 1e3:.1f} ms, {flop / dt / 1e12:.0f} TFLOP/s over {4 ** h // 2} "
+        f"representatives")
+
+
 def copy_only(gib):
     """One plain device-to-device copy of `gib` GiB (after one warmup copy),
     the reference for scaling the HBM counters."""
@@ -333,6 +373,8 @@ def main():
         return profile_only(pk, args.h, args.profile_sweeps)
     if args.copy_gib:
         return copy_only(args.copy_gib)
+    if args.profile_seed:
+        return seed_only(pk, args.h)
     if args.configs:
         return config_table(pk)
     h, cad = args.h, args.cadence

@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import glob
 import os
+import re
 import subprocess
 from concurrent.futures import ThreadPoolExecutor
 
@@ -27,18 +28,42 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+# Kernels that count their own outstanding memory operations (the weight
+# ring of the network's forward kernel waits on vmcnt values) are only
+# correct if the compiler adds no memory operations of its own, so the
+# build rejects any kernel that spills to scratch.
+RESOURCE_REMARKS = ["-Rpass-analysis=kernel-resource-usage"]
+
+
+def scratch_users(remarks: str):
+    """Kernels with a non-zero ScratchSize in hipcc's resource-usage remarks."""
+    users, name = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"remark:\s+ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name and int(m.group(1)) > 0:
+            users.append((name, int(m.group(1))))
+    return users
+
+
 def build(jobs: int = 8, verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+        cmd = [HIPCC, *COMMON, *RESOURCE_REMARKS, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
+        spills = scratch_users(r.stderr)
+        if spills:
+            raise RuntimeError(f"{src}: kernels use scratch memory (register spills): {spills}")
         return obj
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:

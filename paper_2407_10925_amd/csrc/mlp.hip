@@ -78,11 +78,12 @@ __device__ __forceinline__ float input_at(uint64_t i, int h, int slot)
 // so tiles 2kb and 2kb+1 give lane group g the eight consecutive features
 // 32kb + 8g .. 32kb + 8g + 7: input feature 32kb + 8g + t of the next layer
 // sits in slot t.  Activations never leave the registers.  Layers
-// 2 and 3 stream their weights through LDS one 16-row tile (8 KB) at a time,
-// double-buffered and shared by the workgroup's waves.
+// 2 and 3 stream their weights through LDS in 16-row tiles (8 KB), consumed
+// two per workgroup barrier and shared by the workgroup's waves.
 constexpr int kFwdWaves = 8;
+constexpr int kFwdBlocks = 2;                          // 16-sample MFMA column blocks per wave
 constexpr int kFwdThreads = 64 * kFwdWaves;
-constexpr int kFwdSamples = 32 * kFwdWaves;  // per workgroup batch
+constexpr int kFwdSamples = 16 * kFwdBlocks * kFwdWaves;  // per workgroup batch
 
 __device__ __forceinline__ int feat_of(int kb, int g, int t) { return 32 * kb + 8 * g + t; }
 
@@ -109,22 +110,22 @@ struct FwdArgs {
 
 __device__ __forceinline__ uint32_t pack2(float lo, float hi);
 
-// H_layer[s][feature] = the BF16 activations of the wave's samples (backward)
+// H_layer[s][feature] = the BF16 activations of the wave's samples (backward).
+// Words act[kb][b][0..3] of a lane hold features 32 kb + 8 g .. 32 kb + 8 g + 7
+// of its sample in memory order, so each k block is one 16-byte store.
 __device__ __forceinline__ void store_act(const FwdArgs &a, int layer, uint64_t s0, int r, int g,
-                                          const bool (&valid)[2], const uint32_t (&act)[8][2][4])
+                                          const bool (&valid)[kFwdBlocks],
+                                          const uint32_t (&act)[8][kFwdBlocks][4])
 {
     uint16_t *H = a.act + (size_t)layer * a.count * kW;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < kFwdBlocks; ++b) {
         if (!valid[b]) continue;
-        const uint64_t s = s0 + 16 * b + r;
+        uint16_t *row = H + (s0 + 16 * b + r) * kW + 8 * g;
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                H[s * kW + feat_of(kb, g, 2 * q)] = (uint16_t)(act[kb][b][q] & 0xFFFFu);
-                H[s * kW + feat_of(kb, g, 2 * q + 1)] = (uint16_t)(act[kb][b][q] >> 16);
-            }
+            *reinterpret_cast<u32x4 *>(row + 32 * kb) =
+                u32x4{act[kb][b][0], act[kb][b][1], act[kb][b][2], act[kb][b][3]};
     }
 }
 
@@ -133,7 +134,8 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 // two floats -> BF16 pair (round to nearest even; one v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint32_t pack2(float lo, float hi)
 {
-    bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    typedef float float2v __attribute__((ext_vector_type(2)));
+    const bf16x2 v = __builtin_convertvector(float2v{lo, hi}, bf16x2);
     return __builtin_bit_cast(uint32_t, v);
 }
 
@@ -151,8 +153,8 @@ __device__ __forceinline__ bf16x8 as_bf8(uint32_t w0, uint32_t w1, uint32_t w2, 
 // biases, w4, the streamed W2/W3 tiles), so those reads use immediate
 // offsets.  W2 and W3 do not fit in LDS together, so their 16-row tiles flow
 // through a ring of kRing slots as one endless stream (W2 tiles 0..15, W3
-// tiles 0..15, W2 again for the next batch, ...) loaded kRing-1 tiles ahead
-// by direct global-to-LDS loads.  The stream position of tile f is
+// tiles 0..15, W2 again for the next batch, ...) loaded three tile pairs
+// ahead by direct global-to-LDS loads.  The stream position of tile f is
 // congruent to f modulo kRing, so slot indices are compile-time constants.
 constexpr int kRing = 8;  // weight tiles in flight (8 KB each)
 
@@ -181,22 +183,55 @@ constexpr int kW1Stride = kIn + 8;  // padded LDS row of W1 (80 bytes)
 struct FwdSmem {
     uint16_t w1[kW * kW1Stride];    // W1, rows padded
     float bias[3][kW];              // b1, b2, b3
-    float w4[kW];                   // BF16 w4 as floats
+    uint16_t w4[kW];                // BF16 w4
 };
 
-// Tile (layer, f) = weight rows perm_row(f, 0..15) of W2 (layer 0) or W3
-// (layer 1).  Each thread moves one 16-byte chunk straight from global memory
-// into the ring slot (gfx950 global_load_lds_dwordx4: no registers, counted
-// by vmcnt).  Thread t fills slot row t/32, chunk position t%32 of that row,
-// which holds weight chunk (t%32) xor (row%16): the swizzle spreads the 16
-// rows a fragment read touches over distinct LDS banks.
-__device__ __forceinline__ void issue_tile(const uint16_t *wb, int layer, int f, uint16_t *slot)
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+// ReLU of two BF16 values packed in a word: a BF16 number and its int16 bit
+// pattern have the same sign, so an elementwise int16 max with 0 does it
+// (-0 becomes +0).  BF16 rounding keeps the sign, so ReLU after rounding
+// equals rounding after ReLU.
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t w)
 {
-    const int t = threadIdx.x, row = t >> 5, pos = t & 31;
-    const uint16_t *src = wb + (layer ? oW3 : oW2) + perm_row(f, row) * kW + (pos ^ (row & 15)) * 8;
+    const short2v v = __builtin_elementwise_max(__builtin_bit_cast(short2v, w), short2v{0, 0});
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// the four FP32 biases of output rows perm_row(f, 4g .. 4g+3): the initial
+// accumulator of an output tile, so the matrix cores add the bias
+__device__ __forceinline__ floatx4 bias4(const float *b, int f, int g)
+{
+    return *reinterpret_cast<const floatx4 *>(b + perm_row(f, 4 * g));
+}
+
+// Tile (layer, f) = weight rows perm_row(f, 0..15) of W2 (layer 0) or W3
+// (layer 1), stored chunk-major: the 16-byte chunk c (k = 8c .. 8c+7) of
+// tile row i sits at byte 16 (16 c + i).  Each thread moves one chunk
+// straight from global memory into the ring slot (gfx950 buffer_load_dwordx4
+// with the lds bit: no registers, counted by vmcnt); thread t lands at byte
+// 16 t, so it fetches chunk t/16 of row t%16.  A fragment read (lane (i, g)
+// needs chunk 4 kb + g of row i) is then the 1 KB at byte 16 lane + 1024 kb:
+// contiguous across the 64 lanes (no bank conflicts) and one base address
+// plus immediate offsets for every k block and slot.  The buffer form (not
+// global_load_lds) matters: the compiler treats the global form as a flat
+// access that may touch LDS and then waits for every outstanding LDS read
+// before each use of one, which serialises the fragment pipeline below.
+// The descriptor's record count bounds the loads to the parameter vector.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t weight_rsrc(const uint16_t *wb)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(wb), (short)0,
+                                             (int)(kNParams * sizeof(uint16_t)), 0x00020000);
+}
+
+__device__ __forceinline__ void issue_tile(__amdgpu_buffer_rsrc_t rs, int layer, int f,
+                                           uint16_t *slot)
+{
+    const int t = threadIdx.x, row = t & 15, c = t >> 4;
+    const int byte = 2 * ((layer ? oW3 : oW2) + perm_row(f, row) * kW + c * 8);
     uint16_t *dst = slot + (threadIdx.x & ~63) * 8;  // the wave's 1 KB; lane i lands at +16 i
-    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
-                                     (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)dst, 16,
+                                             byte, 0, 0, 0);
 }
 
 // s_waitcnt vmcnt(n) (expcnt and lgkmcnt left free), n < 16
@@ -227,6 +262,7 @@ __device__ __forceinline__ void wait_vmcnt_lds()
 template <int SRC, bool STORE, typename T>
 __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
 {
+    constexpr int NB = kFwdBlocks;
     __shared__ FwdSmem sm;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
@@ -240,12 +276,13 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
         sm.bias[0][q] = a.pf[ob1 + q];
         sm.bias[1][q] = a.pf[ob2 + q];
         sm.bias[2][q] = a.pf[ob3 + q];
-        sm.w4[q] = bf2f(a.wb[ow4 + q]);
+        sm.w4[q] = a.wb[ow4 + q];
     }
     const float b4 = a.pf[ob4];
+    const __amdgpu_buffer_rsrc_t wrs = weight_rsrc(a.wb);
     wait_vmcnt<0>();
 #pragma unroll
-    for (int f = 0; f < kRing - 1; ++f) issue_tile(a.wb, 0, f, ring_slot(f));
+    for (int f = 0; f < kRing - 2; ++f) issue_tile(wrs, 0, f, ring_slot(f));
     __syncthreads();
 
     // the four input pairs of this lane: window positions of pairs 4g .. 4g+3
@@ -254,12 +291,12 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
     for (int q = 0; q < 4; ++q) shift[q] = 2 * (a.h - pos_of(4 * g + q, a.h));
 
     for (uint64_t batch = blockIdx.x; batch < nbatch; batch += gridDim.x) {
-        const uint64_t s0 = batch * kFwdSamples + (uint64_t)wave * 32;
-        uint64_t sidx[2];
-        bool valid[2];
-        bf16x8 x[2];
+        const uint64_t s0 = batch * kFwdSamples + (uint64_t)wave * (16 * NB);
+        uint64_t sidx[NB];
+        bool valid[NB];
+        bf16x8 x[NB];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < NB; ++b) {
             const uint64_t s = s0 + 16 * b + r;
             valid[b] = s < a.count;
             const uint64_t sc = valid[b] ? s : 0;
@@ -272,93 +309,121 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
             }
             x[b] = as_bf8(w[0], w[1], w[2], w[3]);
         }
-        uint32_t act[8][2][4];
 
-        // layer 1 (K = 32: one MFMA per output tile)
+        // layer 1 (K = 32: one MFMA per output tile, started from the bias)
+        uint32_t act[8][NB][4];
 #pragma unroll
         for (int f = 0; f < 16; ++f) {
             const bf16x8 wf = __builtin_bit_cast(
                 bf16x8, *reinterpret_cast<const u32x4 *>(sm.w1 + perm_row(f, r) * kW1Stride + 8 * g));
-            const float *bias = sm.bias[0] + perm_row(f, 4 * g);
+            const floatx4 b0 = bias4(sm.bias[0], f, g);
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const floatx4 acc = mfma(wf, x[b], floatx4{0, 0, 0, 0});
-                act[f >> 1][b][(f & 1) * 2 + 0] =
-                    pack2(fmaxf(acc[0] + bias[0], 0.0f), fmaxf(acc[1] + bias[1], 0.0f));
-                act[f >> 1][b][(f & 1) * 2 + 1] =
-                    pack2(fmaxf(acc[2] + bias[2], 0.0f), fmaxf(acc[3] + bias[3], 0.0f));
+            for (int b = 0; b < NB; ++b) {
+                const floatx4 acc = mfma(wf, x[b], b0);
+                act[f >> 1][b][(f & 1) * 2 + 0] = relu_bf16x2(pack2(acc[0], acc[1]));
+                act[f >> 1][b][(f & 1) * 2 + 1] = relu_bf16x2(pack2(acc[2], acc[3]));
             }
         }
 
-        // layers 2 and 3
-#pragma unroll 1
+        // layers 2 and 3: tile pairs (2p, 2p+1), the pair three ahead in flight
+        uint32_t hid[8][NB][4];
+#pragma unroll
         for (int layer = 0; layer < 2; ++layer) {
+            uint32_t (&in)[8][NB][4] = layer ? hid : act;
+            uint32_t (&out)[8][NB][4] = layer ? act : hid;
             if constexpr (STORE) {
-                store_act(a, layer, s0, r, g, valid, act);
+                store_act(a, layer, s0, r, g, valid, in);
                 wait_vmcnt<0>();  // keep vmcnt counting tile loads only
+                __builtin_amdgcn_sched_barrier(0);
             }
             const float *bias_v = sm.bias[1 + layer];
-            uint32_t nxt[8][2][4];
 #pragma unroll
-            for (int f = 0; f < 16; ++f) {
-                wait_vmcnt_lds<kRing - 2>();  // this wave's part of tile f has landed
-                ring_barrier();               // every wave's part has; slot f-1 is free
-                {
-                    const int fn = f + kRing - 1;  // next tile of the stream
-                    issue_tile(a.wb, fn < 16 ? layer : layer ^ 1, fn & 15, ring_slot(fn));
+            for (int p = 0; p < 8; ++p) {
+                // this wave's part of pair p has landed (pairs p+1, p+2 may be in
+                // flight).  The first pair of a batch waits for everything: the
+                // previous batch's output stores are counted by vmcnt too.
+                if (p == 0 && layer == 0) wait_vmcnt_lds<0>();
+                else wait_vmcnt_lds<4>();
+                ring_barrier();  // every wave's part has landed; pair p-1's slots are free
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int fn = 2 * p + kRing - 2 + t;  // next tiles of the stream
+                    issue_tile(wrs, fn < 16 ? layer : layer ^ 1, fn & 15, ring_slot(fn));
                 }
-                const uint16_t *tile = ring_slot(f) + r * kW;
-                floatx4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+                // Weight fragments are requested PF k blocks ahead of the
+                // products that use them (LDS answers in order, so a product
+                // waits only for its own fragment); the scheduling barriers
+                // keep the compiler from pulling the requests back next to
+                // their uses.  The activation-storing variant keeps one block
+                // fewer in flight to stay within its registers.
+                constexpr int PF = STORE ? 3 : 4;
+                const uint16_t *slot0 = ring_slot(2 * p) + lane * 8;
+                const uint16_t *slot1 = ring_slot(2 * p + 1) + lane * 8;
+                u32x4 wf[8][2];
+#pragma unroll
+                for (int kb = 0; kb < PF; ++kb) {
+                    wf[kb][0] = *reinterpret_cast<const u32x4 *>(slot0 + kb * 512);
+                    wf[kb][1] = *reinterpret_cast<const u32x4 *>(slot1 + kb * 512);
+                }
+                floatx4 acc[2][NB];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const floatx4 bt = bias4(bias_v, 2 * p + t, g);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) acc[t][b] = bt;
+                }
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int kb = 0; kb < 8; ++kb) {
-                    const bf16x8 wf = __builtin_bit_cast(
-                        bf16x8, *reinterpret_cast<const u32x4 *>(tile + (((4 * kb + g) ^ r) * 8)));
 #pragma unroll
-                    for (int b = 0; b < 2; ++b)
-                        acc[b] = mfma(wf, as_bf8(act[kb][b][0], act[kb][b][1], act[kb][b][2],
-                                                 act[kb][b][3]), acc[b]);
-                }
-                const float *bias = bias_v + perm_row(f, 4 * g);
+                    for (int t = 0; t < 2; ++t)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    nxt[f >> 1][b][(f & 1) * 2 + 0] =
-                        pack2(fmaxf(acc[b][0] + bias[0], 0.0f), fmaxf(acc[b][1] + bias[1], 0.0f));
-                    nxt[f >> 1][b][(f & 1) * 2 + 1] =
-                        pack2(fmaxf(acc[b][2] + bias[2], 0.0f), fmaxf(acc[b][3] + bias[3], 0.0f));
+                        for (int b = 0; b < NB; ++b)
+                            acc[t][b] = mfma(__builtin_bit_cast(bf16x8, wf[kb][t]),
+                                             as_bf8(in[kb][b][0], in[kb][b][1], in[kb][b][2],
+                                                    in[kb][b][3]), acc[t][b]);
+                    if (kb + PF < 8) {
+                        wf[kb + PF][0] = *reinterpret_cast<const u32x4 *>(slot0 + (kb + PF) * 512);
+                        wf[kb + PF][1] = *reinterpret_cast<const u32x4 *>(slot1 + (kb + PF) * 512);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        out[p][b][t * 2 + 0] = relu_bf16x2(pack2(acc[t][b][0], acc[t][b][1]));
+                        out[p][b][t * 2 + 1] = relu_bf16x2(pack2(acc[t][b][2], acc[t][b][3]));
+                    }
             }
-#pragma unroll
-            for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) act[kb][b][q] = nxt[kb][b][q];
         }
         if constexpr (STORE) store_act(a, 2, s0, r, g, valid, act);
 
-        // layer 4: y = w4 . h3 + b4, FP32 accumulation, then the four lane groups
-        float part[2] = {0.0f, 0.0f};
+        // layer 4: y = w4 . h3 + b4 on the matrix cores: every row of the A
+        // operand is w4, the accumulator starts at b4, so each lane ends with
+        // y of its sample column in all four rows
+        float part[NB];
+        {
+            floatx4 acc4[NB];
 #pragma unroll
-        for (int kb = 0; kb < 8; ++kb)
+            for (int b = 0; b < NB; ++b) acc4[b] = floatx4{b4, b4, b4, b4};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float w0 = sm.w4[feat_of(kb, g, 2 * q)], w1 = sm.w4[feat_of(kb, g, 2 * q + 1)];
+            for (int kb = 0; kb < 8; ++kb) {
+                const bf16x8 w4f = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const u32x4 *>(sm.w4 + feat_of(kb, g, 0)));
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    part[b] += w0 * bf2f((uint16_t)(act[kb][b][q] & 0xFFFFu));
-                    part[b] += w1 * bf2f((uint16_t)(act[kb][b][q] >> 16));
-                }
+                for (int b = 0; b < NB; ++b)
+                    acc4[b] = mfma(w4f, as_bf8(act[kb][b][0], act[kb][b][1], act[kb][b][2],
+                                               act[kb][b][3]), acc4[b]);
             }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            part[b] += __shfl_xor(part[b], 16);
-            part[b] += __shfl_xor(part[b], 32);
+            for (int b = 0; b < NB; ++b) part[b] = acc4[b][0];
         }
         if (g == 0) {
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
+            for (int b = 0; b < NB; ++b) {
                 if (!valid[b]) continue;
-                const float u = part[b] + b4;
+                const float u = part[b];
                 const uint64_t s = s0 + 16 * b + r;
                 if (a.y) a.y[s] = u;
                 if constexpr (SRC == kSrcReps) {
@@ -374,9 +439,9 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
                 }
             }
         }
-        wait_vmcnt<0>();  // outputs written; vmcnt again counts tile loads only
+        if constexpr (STORE) wait_vmcnt<0>();  // the next batch stores activations first
     }
-    wait_vmcnt<0>();      // no load into LDS outlives the workgroup
+    wait_vmcnt<0>();  // no load into LDS outlives the workgroup
 }
 
 // ------------------------------------------------------------------ NT GEMM

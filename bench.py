@@ -269,7 +269,7 @@ def learned_run(pk, h, P, target, train_steps):
     res = {"seconds": round(t_run, 4), "seconds_with_training": round(t_run + t_data + t_train, 4),
            "data_s": round(t_data, 4), "training_s": round(t_train, 4), "train_steps": train_steps,
            "last_batch_loss": loss, "seed_s": round(t_seed, 4),
-           "seed_tflops": round(2.79e5 * (4 ** h // 2) / t_seed / 1e12, 1),
+           "seed_tflops": round(MLP_FLOP * seed_evaluations(h) / t_seed / 1e12, 1),
            "sweeps_f32": sweeps32, "sweeps_f64": sweeps64, "certificates": certs32 + certs64,
            "bound": best["bound"], "reached": best["bound"] >= target}
     log(f"time to bound, learned + FP32 + FP64 polish: {t_run:.3f} s ({t_seed:.3f} s seed), "
@@ -327,6 +327,15 @@ def profile_only(pk, h, sweeps):
     log(f"ran {sweeps} FP32 sweeps at l={h}")
 
 
+MLP_FLOP = 2 * (32 * 256 + 2 * 256 * 256 + 256)  # multiply-adds of one network evaluation, x2
+
+
+def seed_evaluations(h):
+    """Network evaluations of one seeding: one per orbit of exchanging the
+    strings and complementing both, (4^l + 2^(l+1)) / 4."""
+    return ((1 << h) + 2) << (h - 2)
+
+
 def seed_only(pk, h):
     """Two seedings of an l = h FP32 ring by the warm-start network (random
     initial weights: the same work as a trained one), the second one timed."""
@@ -339,9 +348,9 @@ def seed_only(pk, h):
     S.init_seed_mlp(M, 0.39)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    flop = 2.79e5 * (4 ** h // 2)
-    log(f"seed at l={h}: {dt * 1e3:.1f} ms, {flop / dt / 1e12:.0f} TFLOP/s over {4 ** h // 2} "
-        f"representatives")
+    flop = MLP_FLOP * seed_evaluations(h)
+    log(f"seed at l={h}: {dt * 1e3:.1f} ms, {flop / dt / 1e12:.0f} TFLOP/s over "
+        f"{seed_evaluations(h)} orbit representatives")
 
 
 def copy_only(gib):

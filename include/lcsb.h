@@ -213,10 +213,13 @@ int lcsb_mlp_backward(const uint16_t *wbf16, const uint64_t *idx, int h, const f
 int lcsb_mlp_adam(float *params, uint16_t *wbf16, const float *grad, float *m, float *v,
                   float lr, float beta1, float beta2, float eps, int64_t t, void *stream);
 
-/* Fill the ring of a sigma = d = 2 context (8 <= h <= 16) from the network:
- * for every index i whose string-a head is 0, u = network(i), and lag 2 =
- * u, lag 1 = u + rate at i and at its complement 4^h - 1 - i (the ring stays
- * symmetric).  FP32 offsets are set to 0.  Resets the sweep count and the best
+/* Fill the ring of a sigma = d = 2 context (8 <= h <= 16) from the network.
+ * The network is evaluated once per orbit of the group generated by
+ * exchanging the two strings and complementing both (Sec. 3.3: the converged
+ * table is invariant under both), at one member u = network(i) of the orbit,
+ * and lag 2 = u, lag 1 = u + rate are written at every member (so the ring
+ * is symmetric, as the sweeps require).  (4^h + 2^(h+1)) / 4 evaluations.
+ * FP32 offsets are set to 0.  Resets the sweep count and the best
  * certificate, like the other init calls. */
 int lcsb_init_seed_mlp(lcsb_ctx *ctx, const float *params, const uint16_t *wbf16, double rate);
 

@@ -66,6 +66,59 @@ __device__ __forceinline__ float input_at(uint64_t i, int h, int slot)
     return ((i >> bit) & 1) ? 1.0f : -1.0f;
 }
 
+// ------------------------------------------------------------------ seed orbits
+// The converged table is invariant under exchanging the two strings and under
+// complementing both (Sec. 3.3), so the seed evaluates the network once per
+// orbit of the group these generate and writes the value to every member.
+// With c = a xor b, both maps fix c and act on a as a -> a xor {0, c, 1..1,
+// ~c}: an orbit is a coset of the span of 1..1 and c' (c or ~c, whichever
+// has head 0).  Its unique member with a zero bit at both pivots (a's head
+// and the highest set bit of c') is the representative.  For c in {0, 1..1}
+// the span is one-dimensional and only a's head is fixed.  Orbit number t:
+//   t <  2^h 2^(l-2): c = t >> (l-2), x = the low l-2 bits, a = x with a
+//                     zero inserted at c's pivot (head bit 0); for c in
+//                     {0, 1..1}, a = x (the half of a with bit l-2 clear);
+//   t >= 2^h 2^(l-2): the other half for c = 0, then for c = 1..1.
+// Count (2^l + 2) 2^(l-2) = 4^l / 4 + 2^(l-1).
+__device__ __forceinline__ uint32_t spread16(uint32_t x)  // bit k -> bit 2k
+{
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t orbit_rep_index(uint64_t t, int h)
+{
+    const int lo = h - 2;
+    const uint32_t all = (1u << h) - 1u;
+    const uint32_t ci = (uint32_t)(t >> lo), x = (uint32_t)t & ((1u << lo) - 1u);
+    uint32_t a, c;
+    if (ci >= (1u << h)) {
+        c = ci == (1u << h) ? 0u : all;
+        a = x | (1u << lo);
+    } else {
+        c = ci;
+        const uint32_t cp = (c >> (h - 1)) ? (c ^ all) : c;
+        if (cp == 0u) {
+            a = x;
+        } else {
+            const int j = 31 - __builtin_clz(cp);
+            a = ((x >> j) << (j + 1)) | (x & ((1u << j) - 1u));
+        }
+    }
+    const uint32_t b = a ^ c;
+    return ((uint64_t)spread16(a) << 1) | spread16(b);  // string a in the odd bits
+}
+
+__device__ __forceinline__ uint64_t swap_strings(uint64_t i)
+{
+    const uint64_t ev = 0x5555555555555555ull;
+    return ((i >> 1) & ev) | ((i & ev) << 1);
+}
+
 // ------------------------------------------------------------------ fused forward
 // One wave owns 32 samples (two 16-sample MFMA column blocks).  A layer is
 // computed transposed, Y^T = W X^T: the weight tile is the A operand (rows =
@@ -93,7 +146,7 @@ __device__ __forceinline__ int perm_row(int f, int i)
     return 32 * (f >> 1) + 8 * (i >> 2) + 4 * (f & 1) + (i & 3);
 }
 
-enum : int { kSrcIdx = 0, kSrcReps = 1 };
+enum : int { kSrcIdx = 0, kSrcOrbits = 1 };
 
 struct FwdArgs {
     const uint16_t *wb;      // BF16 parameters
@@ -103,8 +156,8 @@ struct FwdArgs {
     int h;                   // window length of the indices
     float *y;                // predictions (or null)
     uint16_t *act;           // if non-null: H1, H2, H3 as BF16 [3][count][256] for backward
-    void *lag1, *lag2;       // seed targets (kSrcReps)
-    uint64_t n;              // table entries (kSrcReps)
+    void *lag1, *lag2;       // seed targets (kSrcOrbits)
+    uint64_t n;              // table entries (kSrcOrbits)
     double rate;             // lag 1 = u + rate, lag 2 = u
 };
 
@@ -162,11 +215,11 @@ constexpr int kRing = 8;  // weight tiles in flight (8 KB each)
 // can tell a read of one slot from the loads still landing in the others.
 __shared__ uint16_t ring0[16 * kW], ring1[16 * kW], ring2[16 * kW], ring3[16 * kW];
 __shared__ uint16_t ring4[16 * kW], ring5[16 * kW], ring6[16 * kW], ring7[16 * kW];
-static_assert(kRing == 8, "eight ring slots");
+static_assert(kRing == 4 || kRing == 8, "four or eight ring slots");
 
 __device__ __forceinline__ uint16_t *ring_slot(int k)
 {
-    switch (k & 7) {
+    switch (k % kRing) {
     case 0: return ring0;
     case 1: return ring1;
     case 2: return ring2;
@@ -224,14 +277,21 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t weight_rsrc(const uint16_t *wb
                                              (int)(kNParams * sizeof(uint16_t)), 0x00020000);
 }
 
+constexpr int kTileChunks = 16 * kW / 8;                  // 16-byte chunks per tile (512)
+constexpr int kTileOps = kTileChunks / kFwdThreads;         // loads per thread (and wave) per tile
+static_assert(kTileChunks % kFwdThreads == 0, "whole chunks per thread");
+
 __device__ __forceinline__ void issue_tile(__amdgpu_buffer_rsrc_t rs, int layer, int f,
                                            uint16_t *slot)
 {
-    const int t = threadIdx.x, row = t & 15, c = t >> 4;
-    const int byte = 2 * ((layer ? oW3 : oW2) + perm_row(f, row) * kW + c * 8);
-    uint16_t *dst = slot + (threadIdx.x & ~63) * 8;  // the wave's 1 KB; lane i lands at +16 i
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)dst, 16,
-                                             byte, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < kTileOps; ++k) {
+        const int q = threadIdx.x + k * kFwdThreads, row = q & 15, c = q >> 4;
+        const int byte = 2 * ((layer ? oW3 : oW2) + perm_row(f, row) * kW + c * 8);
+        uint16_t *dst = slot + (q & ~63) * 8;  // the wave's 1 KB; lane i lands at +16 i
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)dst,
+                                                 16, byte, 0, 0, 0);
+    }
 }
 
 // s_waitcnt vmcnt(n) (expcnt and lgkmcnt left free), n < 16
@@ -300,7 +360,7 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
             const uint64_t s = s0 + 16 * b + r;
             valid[b] = s < a.count;
             const uint64_t sc = valid[b] ? s : 0;
-            sidx[b] = SRC == kSrcIdx ? a.idx[sc] : sc;
+            sidx[b] = SRC == kSrcIdx ? a.idx[sc] : orbit_rep_index(sc, a.h);
             uint32_t w[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -339,11 +399,12 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
             const float *bias_v = sm.bias[1 + layer];
 #pragma unroll
             for (int p = 0; p < 8; ++p) {
-                // this wave's part of pair p has landed (pairs p+1, p+2 may be in
-                // flight).  The first pair of a batch waits for everything: the
-                // previous batch's output stores are counted by vmcnt too.
+                // this wave's part of pair p has landed (the kRing/2 - 2 pairs
+                // after it may be in flight).  The first pair of a batch waits
+                // for everything: the previous batch's output stores are
+                // counted by vmcnt too.
                 if (p == 0 && layer == 0) wait_vmcnt_lds<0>();
-                else wait_vmcnt_lds<4>();
+                else wait_vmcnt_lds<(kRing / 2 - 2) * 2 * kTileOps>();
                 ring_barrier();  // every wave's part has landed; pair p-1's slots are free
 #pragma unroll
                 for (int t = 0; t < 2; ++t) {
@@ -426,16 +487,20 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
                 const float u = part[b];
                 const uint64_t s = s0 + 16 * b + r;
                 if (a.y) a.y[s] = u;
-                if constexpr (SRC == kSrcReps) {
+                if constexpr (SRC == kSrcOrbits) {
                     T *l1 = static_cast<T *>(a.lag1);
                     T *l2 = static_cast<T *>(a.lag2);
-                    const uint64_t i = sidx[b], m = a.n - 1 - i;
+                    const uint64_t i = sidx[b], j = swap_strings(i), m = a.n - 1;
                     const T v2 = (T)u;
                     const T v1 = (T)((double)u + a.rate);
                     l2[i] = v2;
-                    l2[m] = v2;
+                    l2[j] = v2;
+                    l2[i ^ m] = v2;
+                    l2[j ^ m] = v2;
                     l1[i] = v1;
-                    l1[m] = v1;
+                    l1[j] = v1;
+                    l1[i ^ m] = v1;
+                    l1[j ^ m] = v1;
                 }
             }
         }
@@ -695,14 +760,15 @@ hipError_t launch_mlp_seed(const Geometry &g, int dtype, const uint16_t *wb, con
                            void *lag1, void *lag2, double rate, hipStream_t s)
 {
     FwdArgs a{};
-    a.wb = wb; a.pf = pf; a.count = g.n / 2; a.h = g.h; a.lag1 = lag1; a.lag2 = lag2;
+    a.wb = wb; a.pf = pf; a.h = g.h; a.lag1 = lag1; a.lag2 = lag2;
+    a.count = ((1ull << g.h) + 2) << (g.h - 2);  // orbits of exchange and complement
     a.n = g.n; a.rate = rate;
     const uint64_t nb = (a.count + kFwdSamples - 1) / kFwdSamples;
     const unsigned grid = (unsigned)std::min<uint64_t>(nb, 256ull * 8);
     if (dtype == LCSB_F32)
-        mlp_fwd<kSrcReps, false, float><<<grid, kFwdThreads, 0, s>>>(a);
+        mlp_fwd<kSrcOrbits, false, float><<<grid, kFwdThreads, 0, s>>>(a);
     else
-        mlp_fwd<kSrcReps, false, double><<<grid, kFwdThreads, 0, s>>>(a);
+        mlp_fwd<kSrcOrbits, false, double><<<grid, kFwdThreads, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -148,11 +148,18 @@ def _converged_table(pk, h, sweeps):
     return L, best
 
 
+def _swap_strings(i):
+    """Index of the same tuple with strings a and b exchanged (pair layout)."""
+    ev = 0x5555555555555555
+    return ((i >> 1) & ev) | ((i & ev) << 1)
+
+
 def test_training_reduces_the_loss_and_seed_is_consistent(pk):
-    """Train on a converged l = 8 table; the loss falls by 10x; the seed the
-    library writes into an l = 8 ring equals the network's forward values at
-    the representatives, the complement partners hold the same values, and
-    lag 1 = lag 2 + rate."""
+    """Train on a converged l = 8 table; the loss falls by 10x.  Seed an
+    l = 8 ring that was filled with NaN: every entry is written, lag 2 is
+    invariant under exchanging the strings and under complementing both,
+    each lag 2 value is the network's output at one member of that orbit,
+    and lag 1 = lag 2 + rate."""
     say("training on l=8")
     h = 8
     L, best = _converged_table(pk, h, 160)
@@ -166,16 +173,28 @@ def test_training_reduces_the_loss_and_seed_is_consistent(pk):
     say(f"losses {losses}")
     assert losses[-1] < losses[0] / 10
     R = L.certify()[0]["R"]
-    S = pk.Lcsb(2, 2, h, "f32")
-    S.init_seed_mlp(M, rate=R)
     n = 4 ** h
-    reps = torch.arange(n // 2, dtype=torch.int64, device="cuda")
-    y = torch.empty(n // 2, dtype=torch.float32, device="cuda")
-    M.forward(reps[: (n // 2) // 256 * 256], h, y[: (n // 2) // 256 * 256])
-    lag2 = S.lag(2)[0]
-    lag1 = S.lag(1)[0]
-    assert torch.equal(lag2[: n // 2], y)
-    assert torch.equal(lag2.flip(0), lag2) and torch.equal(lag1.flip(0), lag1)
+    S = pk.Lcsb(2, 2, h, "f32")
+    nan = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+    S.load_ring([nan, nan.clone()])
+    S.init_seed_mlp(M, rate=R)
+    lag2 = S.lag(2)[0].cpu()
+    lag1 = S.lag(1)[0].cpu()
+    assert not torch.isnan(lag2).any() and not torch.isnan(lag1).any()
+    i = np.arange(n, dtype=np.uint64)
+    j = _swap_strings(i)
+    m = np.uint64(n - 1)
+    l2 = lag2.numpy()
+    assert np.array_equal(l2, l2[j.astype(np.int64)])
+    assert np.array_equal(l2, l2[(i ^ m).astype(np.int64)])
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    M.forward(torch.arange(n, dtype=torch.int64, device="cuda"), h, y)
+    yh = y.cpu().numpy()
+    members = [i, j, i ^ m, j ^ m]
+    hit = np.zeros(n, dtype=bool)
+    for mem in members:
+        hit |= l2 == yh[mem.astype(np.int64)]
+    assert hit.all()
     assert torch.equal(lag1, (lag2.double() + R).float())
 
 

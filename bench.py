@@ -61,6 +61,8 @@ def parse():
                    help="only run one plain device copy of this many GiB (counter calibration)")
     p.add_argument("--profile-seed", action="store_true",
                    help="only seed an FP32 ring from an (untrained) warm-start network, twice")
+    p.add_argument("--profile-train", type=int, default=0,
+                   help="only generate the warm-start training tables and run this many steps")
     return p.parse_args()
 
 
@@ -353,6 +355,30 @@ def seed_only(pk, h):
         f"{seed_evaluations(h)} orbit representatives")
 
 
+def train_only(pk, h, steps, batch=8192):
+    """Training tables at l = h-4..h-2 (FP32 to their floor), then `steps`
+    training steps of the warm-start network, timed."""
+    import torch
+    tables = []
+    for hh in (h - 4, h - 3, h - 2):
+        T = pk.Lcsb(2, 2, hh, "f32")
+        T.init_zero()
+        fp32_until_floor(T)
+        tables.append((hh, T))
+    M = pk.Mlp(batch=batch, seed=2407)
+    M.train_step(tables[0][1].lag(1)[0], tables[0][0], seed=1, lr=1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(steps):
+        hh, T = tables[step % 3]
+        M.train_step(T.lag(1)[0], hh, seed=10925 + step, lr=1e-3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flop = 3 * MLP_FLOP * batch * steps  # forward + backward (twice the forward)
+    log(f"training: {steps} steps of batch {batch} in {dt:.3f} s, {dt / steps * 1e3:.3f} ms/step, "
+        f"{flop / dt / 1e12:.1f} TFLOP/s, last loss {M.loss_dev.item():.3e}")
+
+
 def copy_only(gib):
     """One plain device-to-device copy of `gib` GiB (after one warmup copy),
     the reference for scaling the HBM counters."""
@@ -384,6 +410,8 @@ def main():
         return copy_only(args.copy_gib)
     if args.profile_seed:
         return seed_only(pk, args.h)
+    if args.profile_train:
+        return train_only(pk, args.h, args.profile_train)
     if args.configs:
         return config_table(pk)
     h, cad = args.h, args.cadence

@@ -81,3 +81,19 @@ def test_python_binding_refuses_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         pk.Lcsb(2, 2, 4)
+
+
+def test_build_rejects_kernels_that_spill():
+    """The build parses hipcc's resource-usage remarks and names every kernel
+    with scratch memory (the forward kernel's weight ring counts its own
+    outstanding loads and would miscount compiler-issued spill traffic)."""
+    from paper_2407_10925_amd import build as B
+    remarks = "\n".join([
+        "x.hip:1:1: remark: Function Name: _Z4goodv [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:1:1: remark:     VGPRs: 12 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark: Function Name: _Z5spillv [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark:     ScratchSize [bytes/lane]: 28 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    assert B.scratch_users(remarks) == [("_Z5spillv", 28)]
+    assert B.scratch_users("") == []

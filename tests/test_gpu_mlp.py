@@ -198,12 +198,25 @@ def test_training_reduces_the_loss_and_seed_is_consistent(pk):
     assert torch.equal(lag1, (lag2.double() + R).float())
 
 
-def test_seeded_run_reaches_the_plain_bound(pk):
+def _sweeps_to_gap(S, target, gap, limit=300):
+    """FP32 sweeps (a certificate every 2) until the best bound is within gap of target."""
+    while True:
+        S.iterate(2)
+        _, best = S.certify()
+        if target - best["bound"] <= gap or best["sweep"] >= limit:
+            return best["sweep"], best
+
+
+def test_seeded_run_gains_sweeps_and_reaches_the_plain_bound(pk):
     """l = 10: the network trained on converged l = 8 and l = 9 tables seeds
-    an FP32 ring; FP32 sweeps followed by the FP64 polish reach the plain
-    FP64 bound within 1e-9 (the limit does not depend on the start)."""
+    an FP32 ring.  What the network gains over the method without it: the
+    seeded FP32 run comes within 1e-5 of the plain FP64 bound in fewer sweeps
+    than the zero-started one.  The seeded run then reaches the plain bound
+    within 1e-9 after the FP64 polish (the limit does not depend on the
+    start)."""
     say("seeded run l=10")
     P, plain = _converged_table(pk, 10, 240)
+    B = plain["bound"]
     M = pk.Mlp(batch=2048, seed=10)
     tabs = []
     for h in (8, 9):
@@ -213,16 +226,21 @@ def test_seeded_run_reaches_the_plain_bound(pk):
         h, L = tabs[step % 2]
         M.train_step(L.lag(1)[0], h, seed=step, lr=2e-3)
     rate = tabs[1][1].certify()[0]["R"]
+    Z = pk.Lcsb(2, 2, 10, "f32")
+    Z.init_zero()
+    zero_sweeps, _ = _sweeps_to_gap(Z, B, 1e-5)
     S = pk.Lcsb(2, 2, 10, "f32")
     S.init_seed_mlp(M, rate=rate)
-    S.iterate(80)
+    seeded_sweeps, best = _sweeps_to_gap(S, B, 1e-5)
+    say(f"sweeps to within 1e-5 of the plain bound: zero start {zero_sweeps}, seeded {seeded_sweeps}")
+    assert B - best["bound"] <= 1e-5
+    assert seeded_sweeps < zero_sweeps
     Q = pk.Lcsb(2, 2, 10, "f64")
     Q.upcast(S)
-    best = None
     for _ in range(40):
         Q.iterate(4)
         _, best = Q.certify()
-        if best["bound"] >= plain["bound"] - 1e-9:
+        if best["bound"] >= B - 1e-9:
             break
-    say(f"seeded {best['bound']:.12f} at sweep {best['sweep']}, plain {plain['bound']:.12f}")
-    assert abs(best["bound"] - plain["bound"]) <= 1e-9
+    say(f"seeded {best['bound']:.12f} at sweep {best['sweep']}, plain {B:.12f}")
+    assert abs(best["bound"] - B) <= 1e-9

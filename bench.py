@@ -52,7 +52,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-sample-log2", type=int, default=24)
     p.add_argument("--no-ttb", action="store_true", help="skip the time-to-bound runs")
-    p.add_argument("--train-steps", type=int, default=3000)
+    p.add_argument("--train-steps", type=int, default=1000)
     p.add_argument("--profile-sweeps", type=int, default=0,
                    help="only run this many FP32 sweeps from zero (for counter collection)")
     p.add_argument("--configs", action="store_true",
@@ -158,7 +158,7 @@ def polish(P, S, best, target):
     return swept, certs, best
 
 
-def time_to_bound(pk, h, train_steps=3000):
+def time_to_bound(pk, h, train_steps=1000):
     """Wall time from the init call to the first certificate within 1e-9 of
     the converged plain FP64 bound B (certificates, upcast and seeding
     included).

@@ -238,7 +238,7 @@ def learned_run(pk, h, P, target, train_steps):
         T = pk.Lcsb(2, 2, hh, "f32")
         T.init_zero()
         cur, _, _ = fp32_until_floor(T)
-        tables.append((hh, T))
+        tables.append((hh, T, T.lag(1)[0]))  # lag() reads the offset back: once, not per step
     rate = cur["R"]
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
@@ -246,9 +246,9 @@ def learned_run(pk, h, P, target, train_steps):
     t1 = time.perf_counter()
     lr0 = 2e-3
     for step in range(train_steps):
-        hh, T = tables[step % 3]
+        hh, _, table = tables[step % 3]
         lr = lr0 * 0.5 * (1 + math.cos(math.pi * step / train_steps))
-        M.train_step(T.lag(1)[0], hh, seed=10925 + step, lr=lr)
+        M.train_step(table, hh, seed=10925 + step, lr=lr)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     loss = M.loss_dev.item()
@@ -364,14 +364,14 @@ def train_only(pk, h, steps, batch=8192):
         T = pk.Lcsb(2, 2, hh, "f32")
         T.init_zero()
         fp32_until_floor(T)
-        tables.append((hh, T))
+        tables.append((hh, T, T.lag(1)[0]))
     M = pk.Mlp(batch=batch, seed=2407)
-    M.train_step(tables[0][1].lag(1)[0], tables[0][0], seed=1, lr=1e-3)
+    M.train_step(tables[0][2], tables[0][0], seed=1, lr=1e-3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(steps):
-        hh, T = tables[step % 3]
-        M.train_step(T.lag(1)[0], hh, seed=10925 + step, lr=1e-3)
+        hh, _, table = tables[step % 3]
+        M.train_step(table, hh, seed=10925 + step, lr=1e-3)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     flop = 3 * MLP_FLOP * batch * steps  # forward + backward (twice the forward)

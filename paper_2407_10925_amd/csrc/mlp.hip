@@ -527,6 +527,7 @@ __global__ __launch_bounds__(256) void gemm_nt(const uint16_t *__restrict__ A,
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
     floatx4 acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
+#pragma unroll 4
     for (int k = kbeg; k < kend; k += 32) {
         bf16x8 av[2], bv[2];
 #pragma unroll
@@ -555,7 +556,8 @@ __global__ __launch_bounds__(256) void reduce_splits(const float *__restrict__ p
 {
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
         float s = 0.0f;
-        for (int k = 0; k < splits; ++k) s += part[(size_t)k * count + e];
+#pragma unroll 8
+        for (int k = 0; k < splits; ++k) s += part[(size_t)k * count + e];  // in order
         out[e] = s;
     }
 }
@@ -617,42 +619,48 @@ __global__ __launch_bounds__(256) void column_sums_part(const uint16_t *__restri
     const int c = threadIdx.x, k = blockIdx.x;
     const int r0 = k * kColChunk, r1 = min(rows, r0 + kColChunk);
     float s = 0.0f;
-    for (int r = r0; r < r1; ++r) s += (w ? w[r] : 1.0f) * bf2f(M[(size_t)r * kW + c]);
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) s += (w ? w[r] : 1.0f) * bf2f(M[(size_t)r * kW + c]);  // in order
     part[(size_t)k * kW + c] = s;
 }
 
-__global__ void sum_vector(const float *__restrict__ v, int count, float *__restrict__ out)
+// Sums of one 256-thread workgroup in a fixed order: each thread's strided
+// terms in index order, then a butterfly over the wave, then the four waves
+// in order (deterministic, and no serial loop over 256 partials).
+template <typename A>
+__device__ __forceinline__ A workgroup_sum(A s)
 {
-    __shared__ float part[256];
-    float s = 0.0f;
-    for (int k = threadIdx.x; k < count; k += 256) s += v[k];
-    part[threadIdx.x] = s;
+    __shared__ A part[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        float t = 0.0f;
-        for (int k = 0; k < 256; ++k) t += part[k];
-        *out = t;
-    }
+    return ((part[0] + part[1]) + part[2]) + part[3];
 }
 
-// dy = 2 (y - t) / B, loss = mean (y - t)^2 (FP64 sum, one workgroup)
-__global__ void mse_kernel(const float *__restrict__ y, const float *__restrict__ t, int count,
-                           float *__restrict__ dy, double *__restrict__ loss)
+__global__ __launch_bounds__(256) void sum_vector(const float *__restrict__ v, int count,
+                                                  float *__restrict__ out)
 {
-    __shared__ double part[256];
+    float s = 0.0f;
+#pragma unroll 8
+    for (int k = threadIdx.x; k < count; k += 256) s += v[k];
+    s = workgroup_sum(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+__global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ y,
+                                                  const float *__restrict__ t, int count,
+                                                  float *__restrict__ dy, double *__restrict__ loss)
+{
     double s = 0.0;
+#pragma unroll 8
     for (int k = threadIdx.x; k < count; k += 256) {
         const float r = y[k] - t[k];
         dy[k] = 2.0f * r / (float)count;
         s += (double)r * r;
     }
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int k = 0; k < 256; ++k) tot += part[k];
-        *loss = tot / count;
-    }
+    s = workgroup_sum(s);
+    if (threadIdx.x == 0) *loss = s / count;
 }
 
 __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p, uint16_t *__restrict__ wb,

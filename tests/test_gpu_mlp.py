@@ -222,9 +222,10 @@ def test_seeded_run_gains_sweeps_and_reaches_the_plain_bound(pk):
     for h in (8, 9):
         L, _ = _converged_table(pk, h, 200)
         tabs.append((h, L))
+    tables = [(h, L.lag(1)[0]) for h, L in tabs]
     for step in range(400):
-        h, L = tabs[step % 2]
-        M.train_step(L.lag(1)[0], h, seed=step, lr=2e-3)
+        h, table = tables[step % 2]
+        M.train_step(table, h, seed=step, lr=2e-3)
     rate = tabs[1][1].certify()[0]["R"]
     Z = pk.Lcsb(2, 2, 10, "f32")
     Z.init_zero()

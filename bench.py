@@ -400,7 +400,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the sweep has no multi-GPU path in this build)", file=sys.stderr)
+              f"(the library has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     import torch
 

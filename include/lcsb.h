@@ -153,7 +153,7 @@ int lcsb_upcast(const lcsb_ctx *src_f32, lcsb_ctx *dst_f64);
 /* ------------------------------------------------------------------------
  * Learned warm start for sigma = d = 2 (not part of the paper's method: the
  * limit of Algorithm 2's iteration does not depend on the starting ring, so
- * a better start only shortens the run; the certificate judges the result).
+ * a better start only shortens the run; the certificate decides the result).
  *
  * Network: 32 inputs -> 256 -> 256 -> 256 -> 1, ReLU, every matrix product
  * with BF16 operands and FP32 accumulation (gfx950 MFMA).  Parameters are one

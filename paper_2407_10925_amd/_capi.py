@@ -48,7 +48,7 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
-            f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+            f"{LIB_PATH} is missing: build it first (python -m paper_2407_10925_amd.build)")
     L = C.CDLL(LIB_PATH)
     L.lcsb_last_error.restype = C.c_char_p
     L.lcsb_last_error.argtypes = []

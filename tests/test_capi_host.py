@@ -20,7 +20,7 @@ def _declared():
 def lib():
     from paper_2407_10925_amd import _capi
     if not os.path.exists(_capi.LIB_PATH):
-        pytest.fail("liblcsb.so is not built (run __graft_entry__.build())")
+        pytest.fail("liblcsb.so is not built (run python -m paper_2407_10925_amd.build)")
     return _capi.load()
 
 

@@ -50,6 +50,8 @@ def parse():
     p.add_argument("--h", type=int, default=16)
     p.add_argument("--sigma", type=int, default=2, help="alphabet size (counter-collection modes)")
     p.add_argument("--d", type=int, default=2, help="number of strings (counter-collection modes)")
+    p.add_argument("--dtype", default="f32", choices=["f32", "f64"],
+                   help="table type (counter-collection modes)")
     p.add_argument("--cadence", type=int, default=64)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-sample-log2", type=int, default=24)
@@ -322,14 +324,14 @@ def config_table(pk):
     print(json.dumps({"configs": rows}), flush=True)
 
 
-def profile_only(pk, h, sweeps, sigma=2, d=2):
-    """Only `sweeps` FP32 sweeps from zero at (sigma, d, l = h), for counters."""
+def profile_only(pk, h, sweeps, sigma=2, d=2, dtype="f32"):
+    """Only `sweeps` sweeps from zero at (sigma, d, l = h), for counters."""
     import torch
-    L = pk.Lcsb(sigma, d, h, "f32")
+    L = pk.Lcsb(sigma, d, h, dtype)
     L.init_zero()
     L.iterate(sweeps)
     torch.cuda.synchronize()
-    log(f"ran {sweeps} FP32 sweeps at sigma={sigma} d={d} l={h}")
+    log(f"ran {sweeps} {dtype} sweeps at sigma={sigma} d={d} l={h}")
 
 
 MLP_FLOP = 2 * (32 * 256 + 2 * 256 * 256 + 256)  # multiply-adds of one network evaluation, x2
@@ -408,7 +410,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.profile_sweeps:
-        return profile_only(pk, args.h, args.profile_sweeps, args.sigma, args.d)
+        return profile_only(pk, args.h, args.profile_sweeps, args.sigma, args.d, args.dtype)
     if args.copy_gib:
         return copy_only(args.copy_gib)
     if args.profile_seed:

@@ -67,11 +67,28 @@ __device__ __forceinline__ void load4(const double *p, double *g)
     double2 v = reinterpret_cast<const double2 *>(p)[1];
     g[0] = u.x; g[1] = u.y; g[2] = v.x; g[3] = v.y;
 }
+// Streaming variants for the sigma = d = 2 kernel, whose lag bytes are each
+// read once per sweep: FP64 reads are non-temporal there (1.8% faster at
+// l = 16; FP32 unchanged).  The other kernels share groups between
+// representatives through L2 and keep ordinary loads (non-temporal reads
+// made their FP64 sweeps 15-55% slower).
+__device__ __forceinline__ void stream2(const double *p, double &a, double &b)
+{
+    a = __builtin_nontemporal_load(p);
+    b = __builtin_nontemporal_load(p + 1);
+}
+__device__ __forceinline__ void stream4(const double *p, double *g)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] = __builtin_nontemporal_load(p + k);
+}
+__device__ __forceinline__ void stream2(const float *p, float &a, float &b) { load2(p, a, b); }
 __device__ __forceinline__ void load4(const float *p, float *g)
 {
     float4 v = *reinterpret_cast<const float4 *>(p);
     g[0] = v.x; g[1] = v.y; g[2] = v.z; g[3] = v.w;
 }
+__device__ __forceinline__ void stream4(const float *p, float *g) { load4(p, g); }
 
 constexpr uint64_t kAlt2 = 0xAAAAAAAAAAAAAAAAull;  // high bit of every 2-bit slot
 constexpr uint64_t kAlt4Hi = 0xCCCCCCCCCCCCCCCCull; // high 2-bit field of every nibble
@@ -102,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
     if (x >= nq) return;
 
     T g[4];
-    load4(lag2 + 4 * x, g);
+    stream4(lag2 + 4 * x, g);
     T m2 = tree4(g[0], g[1], g[2], g[3]) * (T)0.25;
     if constexpr (kF32) m2 = m2 + d2;
     const T match = (T)1 + m2;
@@ -112,13 +129,13 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
     const uint64_t sb = (i & am) | ((i << 2) & bm);
     const uint64_t sa = ((i << 2) & am) | (i & bm);
     T b0, b1;
-    load2(lag1 + sb, b0, b1);
+    stream2(lag1 + sb, b0, b1);
     const T mb = (b0 + b1) * (T)0.5;
     // the advance-a pair sa, sa+2 is the even or odd half of the aligned
     // group sa & ~3, which the neighbouring thread (x ^ 1) also reads: one
     // vector load of the group serves both
     T q[4];
-    load4(lag1 + (sa & ~(uint64_t)3), q);
+    stream4(lag1 + (sa & ~(uint64_t)3), q);
     const T ma = ((sa & 1) ? (q[1] + q[3]) : (q[0] + q[2])) * (T)0.5;
     const T mis = vmax(mb, ma);
 

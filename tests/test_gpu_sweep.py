@@ -198,41 +198,48 @@ def test_fp32_random_ring_one_sweep(pk, sigma, d, h):
 
 
 @pytest.mark.timeout(900)
-def test_fp32_h16_sampled_sweep_and_certificate(pk):
-    """sigma = d = 2, l = 16 in FP32 (2^32 entries per table: the benchmark's
-    configuration), one sweep from a seeded ring checked at sampled
+@pytest.mark.parametrize("sigma,d,h,seed", [(2, 2, 16, 80), (4, 2, 8, 90), (2, 3, 10, 95)],
+                         ids=lambda v: str(v))
+def test_fp32_full_size_sampled_sweep_and_certificate(pk, sigma, d, h, seed):
+    """The FP32 configurations the benchmark times at their full size
+    (sigma = d = 2, l = 16 and sigma = 4, d = 2, l = 8: 2^32 entries per
+    table; sigma = 2, d = 3, l = 10: 2^30), in the library's own launch
+    configuration: one sweep from a seeded ring checked at sampled
     coordinates against the FP64 oracle, and the certificate of the seeded
     ring: R over the whole table, W at its argmax and at the samples."""
-    sigma, d, h = 2, 2, 16
+    n = sigma ** (d * h)
+    need = (2 * d + 1) * 4 * n + 8 * 2**30
     free, _ = torch.cuda.mem_get_info()
-    if free < 90 * 2**30:
-        pytest.skip("needs ~80 GiB of free device memory")
-    say("h=16 FP32: generating seeded ring on the device")
-    lags_dev = [si.table(sigma, d, h, seed=80 + k, dtype=torch.float32, device="cuda")
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory")
+    tag = f"sigma={sigma} d={d} l={h} FP32"
+    say(f"{tag}: generating seeded ring on the device")
+    lags_dev = [si.table(sigma, d, h, seed=seed + k, dtype=torch.float32, device="cuda")
                 for k in range(d)]
     L = pk.Lcsb(sigma, d, h, "f32")
     L.load_ring(lags_dev)
-    say("h=16 FP32: certificate of the seeded ring")
+    say(f"{tag}: certificate of the seeded ring")
     cur, _ = L.certify()
-    say("h=16 FP32: sweep")
+    say(f"{tag}: sweep")
     L.iterate(1)
     got, o_new = L.lag(1)
     idx = si.sample_indices(L.n, 20000, seed=5).to("cuda")
     got_s = got[idx].double().cpu().numpy() + o_new
     idx = idx.cpu().numpy().astype(np.uint64)
-    say("h=16 FP32: copying the seeded ring to the host")
+    say(f"{tag}: copying the seeded ring to the host")
     lags = [_host(x) for x in lags_dev]
     del got, L, lags_dev  # the context holds the loaded tables until it goes
     torch.cuda.empty_cache()
     ref = oracle.sweep_at_tables(sigma, d, h, lags, idx)
     assert np.max(np.abs(got_s - ref)) <= _fp32_bound(8.0)
-    say("h=16 FP32: oracle R over 2^32 entries")
+    say(f"{tag}: oracle R over {n} entries")
     R, _ = oracle.max_diff(lags[0], lags[1])
     assert cur["R"] == R
     w_arg = oracle.certify_W_at_table(sigma, d, h, lags[0], R, np.array([cur["argmax_W"]], np.uint64))
     assert w_arg[0] == cur["maxW"]
     w_s = oracle.certify_W_at_table(sigma, d, h, lags[0], R, idx)
     assert np.all(w_s <= cur["maxW"])
+    assert np.all(w_s[idx < cur["argmax_W"]] < cur["maxW"])  # lowest index attains it
 
 
 # ------------------------------------------------------------------ FP32 iteration, polish

@@ -209,13 +209,17 @@ __device__ __forceinline__ bf16x8 as_bf8(uint32_t w0, uint32_t w1, uint32_t w2, 
 // tiles 0..15, W2 again for the next batch, ...) loaded three tile pairs
 // ahead by direct global-to-LDS loads.  The stream position of tile f is
 // congruent to f modulo kRing, so slot indices are compile-time constants.
-constexpr int kRing = 8;  // weight tiles in flight (8 KB each)
+constexpr int kRing = 8;   // ring slots (one 8 KB tile each); divides 16
+constexpr int kStep = 2;   // tiles consumed per workgroup barrier; divides kRing
+constexpr int kPf = 4;     // k blocks a wave's fragment requests run ahead of its products
+static_assert(16 % kRing == 0 && kRing % kStep == 0 && kRing / kStep >= 2, "ring shape");
 
 // The ring slots are separate LDS objects so the compiler's wait insertion
 // can tell a read of one slot from the loads still landing in the others.
 __shared__ uint16_t ring0[16 * kW], ring1[16 * kW], ring2[16 * kW], ring3[16 * kW];
 __shared__ uint16_t ring4[16 * kW], ring5[16 * kW], ring6[16 * kW], ring7[16 * kW];
-static_assert(kRing == 4 || kRing == 8, "four or eight ring slots");
+__shared__ uint16_t ring8[16 * kW], ring9[16 * kW], ring10[16 * kW], ring11[16 * kW];
+__shared__ uint16_t ring12[16 * kW], ring13[16 * kW], ring14[16 * kW], ring15[16 * kW];
 
 __device__ __forceinline__ uint16_t *ring_slot(int k)
 {
@@ -227,7 +231,15 @@ __device__ __forceinline__ uint16_t *ring_slot(int k)
     case 4: return ring4;
     case 5: return ring5;
     case 6: return ring6;
-    default: return ring7;
+    case 7: return ring7;
+    case 8: return ring8;
+    case 9: return ring9;
+    case 10: return ring10;
+    case 11: return ring11;
+    case 12: return ring12;
+    case 13: return ring13;
+    case 14: return ring14;
+    default: return ring15;
     }
 }
 
@@ -342,7 +354,7 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
     const __amdgpu_buffer_rsrc_t wrs = weight_rsrc(a.wb);
     wait_vmcnt<0>();
 #pragma unroll
-    for (int f = 0; f < kRing - 2; ++f) issue_tile(wrs, 0, f, ring_slot(f));
+    for (int f = 0; f < kRing - kStep; ++f) issue_tile(wrs, 0, f, ring_slot(f));
     __syncthreads();
 
     // the four input pairs of this lane: window positions of pairs 4g .. 4g+3
@@ -385,7 +397,8 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
             }
         }
 
-        // layers 2 and 3: tile pairs (2p, 2p+1), the pair three ahead in flight
+        // layers 2 and 3: kStep tiles per workgroup barrier, the ring's
+        // remaining kRing - kStep tiles in flight
         uint32_t hid[8][NB][4];
 #pragma unroll
         for (int layer = 0; layer < 2; ++layer) {
@@ -398,38 +411,39 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
             }
             const float *bias_v = sm.bias[1 + layer];
 #pragma unroll
-            for (int p = 0; p < 8; ++p) {
-                // this wave's part of pair p has landed (the kRing/2 - 2 pairs
-                // after it may be in flight).  The first pair of a batch waits
-                // for everything: the previous batch's output stores are
-                // counted by vmcnt too.
+            for (int p = 0; p < 16 / kStep; ++p) {
+                // this wave's part of step p's tiles has landed (the tiles of
+                // the following kRing/kStep - 2 steps may be in flight).  The
+                // first step of a batch waits for everything: the previous
+                // batch's output stores are counted by vmcnt too.
                 if (p == 0 && layer == 0) wait_vmcnt_lds<0>();
-                else wait_vmcnt_lds<(kRing / 2 - 2) * 2 * kTileOps>();
-                ring_barrier();  // every wave's part has landed; pair p-1's slots are free
+                else wait_vmcnt_lds<(kRing - 2 * kStep) * kTileOps>();
+                ring_barrier();  // every wave's part has landed; step p-1's slots are free
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int fn = 2 * p + kRing - 2 + t;  // next tiles of the stream
+                for (int t = 0; t < kStep; ++t) {
+                    const int fn = kStep * p + kRing - kStep + t;  // next tiles of the stream
                     issue_tile(wrs, fn < 16 ? layer : layer ^ 1, fn & 15, ring_slot(fn));
                 }
-                // Weight fragments are requested PF k blocks ahead of the
+                // Weight fragments are requested kPf k blocks ahead of the
                 // products that use them (LDS answers in order, so a product
                 // waits only for its own fragment); the scheduling barriers
                 // keep the compiler from pulling the requests back next to
                 // their uses.  The activation-storing variant keeps one block
                 // fewer in flight to stay within its registers.
-                constexpr int PF = STORE ? 3 : 4;
-                const uint16_t *slot0 = ring_slot(2 * p) + lane * 8;
-                const uint16_t *slot1 = ring_slot(2 * p + 1) + lane * 8;
-                u32x4 wf[8][2];
+                constexpr int PF = STORE ? kPf - 1 : kPf;
+                const uint16_t *slot[kStep];
 #pragma unroll
-                for (int kb = 0; kb < PF; ++kb) {
-                    wf[kb][0] = *reinterpret_cast<const u32x4 *>(slot0 + kb * 512);
-                    wf[kb][1] = *reinterpret_cast<const u32x4 *>(slot1 + kb * 512);
-                }
-                floatx4 acc[2][NB];
+                for (int t = 0; t < kStep; ++t) slot[t] = ring_slot(kStep * p + t) + lane * 8;
+                u32x4 wf[8][kStep];
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const floatx4 bt = bias4(bias_v, 2 * p + t, g);
+                for (int kb = 0; kb < PF; ++kb)
+#pragma unroll
+                    for (int t = 0; t < kStep; ++t)
+                        wf[kb][t] = *reinterpret_cast<const u32x4 *>(slot[t] + kb * 512);
+                floatx4 acc[kStep][NB];
+#pragma unroll
+                for (int t = 0; t < kStep; ++t) {
+                    const floatx4 bt = bias4(bias_v, kStep * p + t, g);
 #pragma unroll
                     for (int b = 0; b < NB; ++b) acc[t][b] = bt;
                 }
@@ -437,25 +451,30 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
 #pragma unroll
                 for (int kb = 0; kb < 8; ++kb) {
 #pragma unroll
-                    for (int t = 0; t < 2; ++t)
+                    for (int t = 0; t < kStep; ++t)
 #pragma unroll
                         for (int b = 0; b < NB; ++b)
                             acc[t][b] = mfma(__builtin_bit_cast(bf16x8, wf[kb][t]),
                                              as_bf8(in[kb][b][0], in[kb][b][1], in[kb][b][2],
                                                     in[kb][b][3]), acc[t][b]);
                     if (kb + PF < 8) {
-                        wf[kb + PF][0] = *reinterpret_cast<const u32x4 *>(slot0 + (kb + PF) * 512);
-                        wf[kb + PF][1] = *reinterpret_cast<const u32x4 *>(slot1 + (kb + PF) * 512);
+#pragma unroll
+                        for (int t = 0; t < kStep; ++t)
+                            wf[kb + PF][t] = *reinterpret_cast<const u32x4 *>(slot[t] + (kb + PF) * 512);
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
+                // output tile f = kStep p + t fills words (f & 1) * 2 .. +1 of
+                // k block f / 2 of the next layer's activations
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int t = 0; t < kStep; ++t) {
+                    const int f = kStep * p + t;
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
-                        out[p][b][t * 2 + 0] = relu_bf16x2(pack2(acc[t][b][0], acc[t][b][1]));
-                        out[p][b][t * 2 + 1] = relu_bf16x2(pack2(acc[t][b][2], acc[t][b][3]));
+                        out[f >> 1][b][(f & 1) * 2 + 0] = relu_bf16x2(pack2(acc[t][b][0], acc[t][b][1]));
+                        out[f >> 1][b][(f & 1) * 2 + 1] = relu_bf16x2(pack2(acc[t][b][2], acc[t][b][3]));
                     }
+                }
             }
         }
         if constexpr (STORE) store_act(a, 2, s0, r, g, valid, act);

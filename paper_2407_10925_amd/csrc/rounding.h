@@ -1,7 +1,9 @@
-// Directed rounding for the certificate, built from round-to-nearest
-// operations with error-free transforms: Knuth's TwoSum for sums and the
-// FMA-based TwoProduct for products (Ogita, Rump, Oishi, "Accurate sum and
-// dot product", SIAM J. Sci. Comput. 26(6), 2005).  IEEE-754 defines the
+// Directed rounding for the scalar steps of the certificate (the host's
+// E, R - E and d (R - E); the device's d R and (d - k) R), built from
+// round-to-nearest operations with error-free transforms: Knuth's TwoSum
+// for sums and the FMA-based TwoProduct for products (Ogita, Rump, Oishi,
+// "Accurate sum and dot product", SIAM J. Sci. Comput. 26(6), 2005).  The
+// certificate's per-entry pass uses the GPU's rounding mode instead.  IEEE-754 defines the
 // directed-rounding result uniquely, so these agree bit for bit with any
 // correct implementation (the CPU's rounding-mode switch included) as long
 // as no intermediate overflows; the certificate's values are far from that.
@@ -52,13 +54,6 @@ __host__ __device__ inline double add_rd(double a, double b)
     return e < 0.0 ? next_down(s) : s;
 }
 
-__host__ __device__ inline double add_ru(double a, double b)
-{
-    double s = a + b;
-    double e = two_sum_err(a, b, s);
-    return e > 0.0 ? next_up(s) : s;
-}
-
 __host__ __device__ inline double mul_rd(double a, double b)
 {
     double p = a * b;
@@ -71,15 +66,6 @@ __host__ __device__ inline double mul_ru(double a, double b)
     double p = a * b;
     double e = __builtin_fma(a, b, -p);
     return e > 0.0 ? next_up(p) : p;
-}
-
-// s * 2^-j rounded toward -inf.  p = fl(s 2^-j) is exact unless it is
-// subnormal; p 2^j is always exact, so comparing it with s decides.
-__host__ __device__ inline double scale_pow2_rd(double s, int j)
-{
-    double p = __builtin_ldexp(s, -j);
-    double back = __builtin_ldexp(p, j);
-    return back > s ? next_down(p) : p;
 }
 
 }  // namespace lcsb

@@ -67,6 +67,7 @@ def parse():
                    help="only seed an FP32 ring from an (untrained) warm-start network, twice")
     p.add_argument("--profile-train", type=int, default=0,
                    help="only generate the warm-start training tables and run this many steps")
+    p.add_argument("--train-batch", type=int, default=8192, help="batch of --profile-train")
     return p.parse_args()
 
 
@@ -442,7 +443,7 @@ def main():
     if args.profile_seed:
         return seed_only(pk, args.h)
     if args.profile_train:
-        return train_only(pk, args.h, args.profile_train)
+        return train_only(pk, args.h, args.profile_train, args.train_batch)
     if args.configs:
         return config_table(pk)
     h, cad = args.h, args.cadence

@@ -62,7 +62,7 @@ hipError_t launch_upcast(const Geometry &g, const float *src, const double *offs
 
 // Learned warm start (csrc/mlp.hip)
 struct MlpWs {  // byte offsets inside the caller's training workspace
-    size_t act, X, dZ, dH, T1, T2, WT, part, bytes;
+    size_t act, X, dZ, T1, WT, part, bytes;
     int splits;
 };
 MlpWs mlp_ws_layout(int64_t batch);

@@ -528,57 +528,157 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
     wait_vmcnt<0>();  // no load into LDS outlives the workgroup
 }
 
-// ------------------------------------------------------------------ NT GEMM
-// C_s[M][N] = sum_{k in split s} A[m][k] B[n][k] (A, B BF16 row-major, K
-// contiguous).  A wave computes a 32 x 32 tile (2 x 2 MFMA blocks); a
-// workgroup of four waves 64 x 64.  M, N, K multiples of 32; split s writes
-// its partial sums to C + s M N (reduced in a fixed order afterwards).
-__global__ __launch_bounds__(256) void gemm_nt(const uint16_t *__restrict__ A,
-                                               const uint16_t *__restrict__ B,
-                                               float *__restrict__ C, int M, int N, int K,
-                                               int kchunk)
+// ------------------------------------------------------------------ backward GEMMs
+// Weight gradient of one layer: G[m][n] = sum over samples s of A[s][m] B[s][n]
+// (A = dZ of the layer, B = its input; both sample-major BF16 with row
+// lengths lda, ldb), for the workgroup's 128 x TN output tile, over the
+// 32-sample steps [z per, (z+1) per) of split z = blockIdx.z.  Each step
+// stages both operands through LDS transposed (feature-major rows of 32
+// samples, padded to 40 elements so the 16 rows of a fragment read fall in
+// distinct banks), so a lane's MFMA fragment (8 samples of one feature) is
+// one 16-byte read.  Split z writes its partial G to part + z (M N + M) and,
+// in the workgroups of output column 0, the bias-gradient partial
+// (sum over its samples of A[s][m]) right after it: a fixed-order reduction
+// over z then yields the weight and bias gradients, which sit next to each
+// other in the parameter layout.
+constexpr int kWgRow = 40;
+
+template <int TN>
+__global__ __launch_bounds__(256) void wgrad(const uint16_t *__restrict__ A, int lda,
+                                             const uint16_t *__restrict__ Bm, int ldb, int ksteps,
+                                             int per, int M, int N, float *__restrict__ part)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r = lane & 15, g = lane >> 4;
-    const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
-    const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
-    if (m0 >= M || n0 >= N) return;
-    const int kbeg = blockIdx.z * kchunk;
-    const int kend = min(K, kbeg + kchunk);
-    floatx4 acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
-#pragma unroll 4
-    for (int k = kbeg; k < kend; k += 32) {
-        bf16x8 av[2], bv[2];
+    constexpr int WM = TN == 128 ? 64 : 32, WN = TN == 128 ? 64 : 32;
+    constexpr int WAVES_N = TN / WN;  // 2 x 2 waves of 64 x 64, or 4 x 1 waves of 32 x 32
+    constexpr int FM = WM / 16, FN = WN / 16;
+    __shared__ uint32_t sa[128 * kWgRow / 2];  // A^T: 128 features x 32 samples (+ padding)
+    __shared__ uint32_t sb[TN * kWgRow / 2];   // B^T: TN features x 32 samples (+ padding)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+    const int m0 = blockIdx.x * 128, n0 = blockIdx.y * TN;
+    const int kbeg = blockIdx.z * per, kend = min(ksteps, kbeg + per);
+    // staging: thread q moves features 8c .. 8c+7 of samples 2p, 2p+1 (two
+    // 16-byte loads) into eight 32-bit LDS words (row 8c + t, samples 2p, 2p+1)
+    const int p = threadIdx.x & 15, c = threadIdx.x >> 4;  // c < 16
+    constexpr int CB = TN / 8;                              // chunks of a B row
+    floatx4 acc[FM][FN];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            av[i] = load8(A + (size_t)(m0 + 16 * i + r) * K + k + 8 * g);
-            bv[i] = load8(B + (size_t)(n0 + 16 * i + r) * K + k + 8 * g);
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
+    float bsum = 0.0f;  // bias partial of row threadIdx.x / 2, samples 16 (threadIdx.x & 1) ..
+    u32x4 ra[2], rb[2];
+    auto fetch = [&](int ks) {
+        const size_t s = (size_t)ks * 32 + 2 * p;
+        ra[0] = *reinterpret_cast<const u32x4 *>(A + s * lda + m0 + 8 * c);
+        ra[1] = *reinterpret_cast<const u32x4 *>(A + (s + 1) * lda + m0 + 8 * c);
+        if (c < CB) {
+            rb[0] = *reinterpret_cast<const u32x4 *>(Bm + s * ldb + n0 + 8 * c);
+            rb[1] = *reinterpret_cast<const u32x4 *>(Bm + (s + 1) * ldb + n0 + 8 * c);
         }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int ks = kbeg; ks < kend; ++ks) {
+        __syncthreads();  // every wave is done with the previous step's tiles
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int t = 0; t < 8; ++t) {  // word t/2 of a chunk holds features 2(t/2), 2(t/2)+1
+            const int sh = (t & 1) * 16, w = t >> 1;
+            sa[(8 * c + t) * (kWgRow / 2) + p] = (ra[0][w] >> sh & 0xFFFFu) | ((ra[1][w] >> sh) << 16);
+            if (c < CB)
+                sb[(8 * c + t) * (kWgRow / 2) + p] = (rb[0][w] >> sh & 0xFFFFu) | ((rb[1][w] >> sh) << 16);
+        }
+        __syncthreads();
+        if (ks + 1 < kend) fetch(ks + 1);  // in flight during the products
+        if (blockIdx.y == 0) {
+            const uint32_t *row = sa + (threadIdx.x >> 1) * (kWgRow / 2) + 8 * (threadIdx.x & 1);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
+            for (int j = 0; j < 8; ++j) bsum += bf2f((uint16_t)(row[j] & 0xFFFFu)) + bf2f((uint16_t)(row[j] >> 16));
+        }
+        const uint16_t *ta = reinterpret_cast<const uint16_t *>(sa);
+        const uint16_t *tb = reinterpret_cast<const uint16_t *>(sb);
+        bf16x8 fa[FM], fb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) fa[i] = load8(ta + (wm * WM + 16 * i + r) * kWgRow + 8 * g);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) fb[j] = load8(tb + (wn * WN + 16 * j + r) * kWgRow + 8 * g);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[i][j] = mfma(fa[i], fb[j], acc[i][j]);
     }
-    float *Cs = C + (size_t)blockIdx.z * M * N;
+    float *P = part + (size_t)blockIdx.z * ((size_t)M * N + M);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
-                Cs[(size_t)(m0 + 16 * i + 4 * g + rr) * N + n0 + 16 * j + r] = acc[i][j][rr];
+            for (int q = 0; q < 4; ++q)
+                P[(size_t)(m0 + wm * WM + 16 * i + 4 * g + q) * N + n0 + wn * WN + 16 * j + r] = acc[i][j][q];
+    if (blockIdx.y == 0) {
+        bsum += __shfl_xor(bsum, 1);  // the two halves of a row, low half first
+        if ((threadIdx.x & 1) == 0) P[(size_t)M * N + m0 + (threadIdx.x >> 1)] = bsum;
+    }
 }
 
-// out[e] = sum_s part[s][e] in increasing s (deterministic)
-__global__ __launch_bounds__(256) void reduce_splits(const float *__restrict__ part, int splits,
-                                                     size_t count, float *__restrict__ out)
+// out[e] = sum over z = 0 .. nz-1, in order, of part[z][e]; count % 4 == 0
+__global__ __launch_bounds__(256) void reduce_parts(const float *__restrict__ part, int nz,
+                                                    size_t count, float *__restrict__ out)
 {
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256) {
-        float s = 0.0f;
+    const size_t e = ((size_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (e >= count) return;
+    floatx4 s = {0, 0, 0, 0};
 #pragma unroll 8
-        for (int k = 0; k < splits; ++k) s += part[(size_t)k * count + e];  // in order
-        out[e] = s;
+    for (int z = 0; z < nz; ++z) s += *reinterpret_cast<const floatx4 *>(part + (size_t)z * count + e);
+    *reinterpret_cast<floatx4 *>(out + e) = s;
+}
+
+// Data gradient through one layer, computed transposed so each lane ends
+// with four consecutive features of one sample: C[i][s] = sum over o of
+// WT[i][o] dZ[s][o] (WT = W^T, 256 x 256; dZ sample-major), then
+// Zp[s][i] = bf16(C[i][s]) where the layer input Hp[s][i] > 0, else 0.
+// Tile 128 i x 128 s per workgroup, 64 x 64 per wave; operands straight
+// from global memory (W^T stays in the caches).
+__global__ __launch_bounds__(256) void dgrad(const uint16_t *__restrict__ WT,
+                                             const uint16_t *__restrict__ dZ,
+                                             const uint16_t *__restrict__ Hp,
+                                             uint16_t *__restrict__ Zp)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+    const int i0 = blockIdx.x * 128 + (wave & 1) * 64;
+    const size_t s0 = (size_t)blockIdx.y * 128 + (wave >> 1) * 64;
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < kW; k += 32) {
+        bf16x8 fa[4], fb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fa[i] = load8(WT + (size_t)(i0 + 16 * i + r) * kW + k + 8 * g);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fb[j] = load8(dZ + (s0 + 16 * j + r) * kW + k + 8 * g);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma(fa[i], fb[j], acc[i][j]);
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t at = (s0 + 16 * j + r) * kW + i0 + 16 * i + 4 * g;
+            const u32x2 h = *reinterpret_cast<const u32x2 *>(Hp + at);
+            uint32_t w[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t z = pack2(acc[i][j][2 * q], acc[i][j][2 * q + 1]);
+                const uint32_t keep = ((h[q] & 0x8000u) == 0u && (h[q] & 0x7FFFu) != 0u ? 0x0000FFFFu : 0u) |
+                                      ((h[q] & 0x80000000u) == 0u && (h[q] & 0x7FFF0000u) != 0u ? 0xFFFF0000u : 0u);
+                w[q] = z & keep;
+            }
+            *reinterpret_cast<u32x2 *>(Zp + at) = u32x2{w[0], w[1]};
+        }
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -617,68 +717,89 @@ __global__ __launch_bounds__(256) void head_backward(const float *__restrict__ d
     dZ3[e] = f2bf(h > 0.0f ? dy[s] * bf2f(wb[ow4 + o]) : 0.0f);
 }
 
-// dZ = bf16(dH) where H > 0 (dH FP32, H BF16)
-__global__ __launch_bounds__(256) void relu_backward(const float *__restrict__ dH,
-                                                     const uint16_t *__restrict__ H, size_t count,
-                                                     uint16_t *__restrict__ dZ)
-{
-    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= count) return;
-    dZ[e] = f2bf(bf2f(H[e]) > 0.0f ? dH[e] : 0.0f);
-}
 
-// part[k][c] = sum over rows r of chunk k (kColChunk rows) of w[r] * M[r][c]
-// (w = null means 1), M BF16 rows x 256; reduce_splits then adds the chunks
-// in increasing order (deterministic).
-constexpr int kColChunk = 64;
+// part[k][c] = sum over the rows of chunk k (rows k*per .. k*per+per-1) of
+// w[r] * M[r][c] in row order (w = null means 1), M BF16 rows x 256;
+// reduce_columns then adds the chunks in a fixed order (deterministic).
 __global__ __launch_bounds__(256) void column_sums_part(const uint16_t *__restrict__ M,
                                                         const float *__restrict__ w, int rows,
-                                                        float *__restrict__ part)
+                                                        int per, float *__restrict__ part)
 {
     const int c = threadIdx.x, k = blockIdx.x;
-    const int r0 = k * kColChunk, r1 = min(rows, r0 + kColChunk);
+    const int r0 = k * per, r1 = min(rows, r0 + per);
     float s = 0.0f;
 #pragma unroll 8
     for (int r = r0; r < r1; ++r) s += (w ? w[r] : 1.0f) * bf2f(M[(size_t)r * kW + c]);  // in order
     part[(size_t)k * kW + c] = s;
 }
 
-// Sums of one 256-thread workgroup in a fixed order: each thread's strided
-// terms in index order, then a butterfly over the wave, then the four waves
-// in order (deterministic, and no serial loop over 256 partials).
-template <typename A>
+// out[e] = sum over z of part[z][e] (count outputs, nz parts), one wave per
+// output: lane j adds parts j, j+64, ... in order, then a butterfly over the
+// lanes (a fixed order)
+__global__ __launch_bounds__(256) void reduce_columns(const float *__restrict__ part, int nz,
+                                                      int count, float *__restrict__ out)
+{
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (e >= count) return;
+    float s = 0.0f;
+    for (int z = lane; z < nz; z += 64) s += part[(size_t)z * count + e];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) out[e] = s;
+}
+
+// Sums over one workgroup of WAVES waves in a fixed order: each thread's
+// strided terms in index order, then a butterfly over the wave, then the
+// waves in order (deterministic, and no serial loop over all partials).
+template <int WAVES, typename A>
 __device__ __forceinline__ A workgroup_sum(A s)
 {
-    __shared__ A part[4];
+    __shared__ A part[WAVES];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
     __syncthreads();
-    return ((part[0] + part[1]) + part[2]) + part[3];
+    A t = part[0];
+#pragma unroll
+    for (int w = 1; w < WAVES; ++w) t += part[w];
+    return t;
 }
 
-__global__ __launch_bounds__(256) void sum_vector(const float *__restrict__ v, int count,
-                                                  float *__restrict__ out)
+// One workgroup of 1024 threads; count % 4 == 0
+__global__ __launch_bounds__(1024) void sum_vector(const float *__restrict__ v, int count,
+                                                   float *__restrict__ out)
 {
     float s = 0.0f;
-#pragma unroll 8
-    for (int k = threadIdx.x; k < count; k += 256) s += v[k];
-    s = workgroup_sum(s);
+#pragma unroll 4
+    for (int k = 4 * threadIdx.x; k < count; k += 4 * 1024) {
+        const floatx4 q = *reinterpret_cast<const floatx4 *>(v + k);
+        s += ((q[0] + q[1]) + q[2]) + q[3];
+    }
+    s = workgroup_sum<16>(s);
     if (threadIdx.x == 0) *out = s;
 }
 
-__global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ y,
-                                                  const float *__restrict__ t, int count,
-                                                  float *__restrict__ dy, double *__restrict__ loss)
+// One workgroup of 1024 threads; count % 4 == 0
+__global__ __launch_bounds__(1024) void mse_kernel(const float *__restrict__ y,
+                                                   const float *__restrict__ t, int count,
+                                                   float *__restrict__ dy, double *__restrict__ loss)
 {
     double s = 0.0;
-#pragma unroll 8
-    for (int k = threadIdx.x; k < count; k += 256) {
-        const float r = y[k] - t[k];
-        dy[k] = 2.0f * r / (float)count;
-        s += (double)r * r;
+    const float scale = 2.0f / (float)count;
+#pragma unroll 4
+    for (int k = 4 * threadIdx.x; k < count; k += 4 * 1024) {
+        const floatx4 a = *reinterpret_cast<const floatx4 *>(y + k);
+        const floatx4 b = *reinterpret_cast<const floatx4 *>(t + k);
+        floatx4 d;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float r = a[q] - b[q];
+            d[q] = scale * r;
+            s += (double)r * r;
+        }
+        *reinterpret_cast<floatx4 *>(dy + k) = d;
     }
-    s = workgroup_sum(s);
+    s = workgroup_sum<16>(s);
     if (threadIdx.x == 0) *loss = s / count;
 }
 
@@ -756,15 +877,11 @@ MlpWs mlp_ws_layout(int64_t batch)
     w.act = take(3 * B * kW * 2);
     w.X = take(B * kIn * 2);
     w.dZ = take(B * kW * 2);
-    w.dH = take(B * kW * 4);
-    w.T1 = take(B * kW * 2);
-    w.T2 = take(B * kW * 2);
+    w.T1 = take(B * kW * 2);            // the other dZ of the ping-pong
     w.WT = take((size_t)2 * kW * kW * 2);
-    w.splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, batch / 512));
-    // split-K partial sums of the weight gradients, or the column-sum partials
-    const size_t part_floats = std::max<size_t>((size_t)w.splits * kW * kW,
-                                                (size_t)((batch + kColChunk - 1) / kColChunk) * kW);
-    w.part = take(part_floats * 4);
+    // batch splits of the weight gradients: enough workgroups for the chip
+    w.splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, batch / 256));
+    w.part = take((size_t)w.splits * (kW * kW + kW) * 4);
     w.bytes = o;
     return w;
 }
@@ -799,31 +916,31 @@ hipError_t launch_mlp_seed(const Geometry &g, int dtype, const uint16_t *wb, con
     return hipGetLastError();
 }
 
-static hipError_t gemm(const uint16_t *A, const uint16_t *B, float *C, int M, int N, int K,
-                       int splits, float *part, hipStream_t s)
-{
-    // split K into `splits` chunks of whole 32-wide steps
-    const int steps = K / 32;
-    const int per = (steps + splits - 1) / splits;
-    const int used = (steps + per - 1) / per;
-    dim3 grid((M + 63) / 64, (N + 63) / 64, used);
-    float *dst = used == 1 ? C : part;
-    gemm_nt<<<grid, 256, 0, s>>>(A, B, dst, M, N, K, per * 32);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || used == 1) return e;
-    const size_t cnt = (size_t)M * N;
-    reduce_splits<<<(unsigned)std::min<size_t>((cnt + 255) / 256, 4096), 256, 0, s>>>(part, used, cnt, C);
-    return hipGetLastError();
-}
-
 static hipError_t column_sums(const uint16_t *M, const float *w, int rows, float *part, float *out,
                               hipStream_t s)
 {
-    const int chunks = (rows + kColChunk - 1) / kColChunk;
-    column_sums_part<<<chunks, 256, 0, s>>>(M, w, rows, part);
+    const int chunks = std::min(256, (rows + 63) / 64), per = (rows + chunks - 1) / chunks;
+    column_sums_part<<<chunks, 256, 0, s>>>(M, w, rows, per, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    reduce_splits<<<1, 256, 0, s>>>(part, chunks, (size_t)kW, out);
+    reduce_columns<<<kW / 4, 256, 0, s>>>(part, chunks, kW, out);
+    return hipGetLastError();
+}
+
+static hipError_t weight_grad(const uint16_t *A, const uint16_t *Bm, int ldb, int B, int splits,
+                              float *part, float *out, hipStream_t s)
+{
+    const int ksteps = B / 32, per = (ksteps + splits - 1) / splits;
+    const int used = (ksteps + per - 1) / per;
+    const int N = ldb;
+    if (N == kW)
+        wgrad<128><<<dim3(kW / 128, kW / 128, used), 256, 0, s>>>(A, kW, Bm, ldb, ksteps, per, kW, N, part);
+    else
+        wgrad<32><<<dim3(kW / 128, 1, used), 256, 0, s>>>(A, kW, Bm, ldb, ksteps, per, kW, N, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t count = (size_t)kW * N + kW;  // weights, then the biases that follow them
+    reduce_parts<<<(unsigned)((count / 4 + 255) / 256), 256, 0, s>>>(part, used, count, out);
     return hipGetLastError();
 }
 
@@ -836,46 +953,35 @@ hipError_t launch_mlp_backward(const uint16_t *wb, const float *dy, int64_t coun
     uint16_t *H2 = H1 + (size_t)B * kW;
     uint16_t *H3 = H2 + (size_t)B * kW;
     uint16_t *X = reinterpret_cast<uint16_t *>(ws + L.X);
-    uint16_t *dZ = reinterpret_cast<uint16_t *>(ws + L.dZ);
-    float *dH = reinterpret_cast<float *>(ws + L.dH);
-    uint16_t *T1 = reinterpret_cast<uint16_t *>(ws + L.T1);
-    uint16_t *T2 = reinterpret_cast<uint16_t *>(ws + L.T2);
+    uint16_t *dZa = reinterpret_cast<uint16_t *>(ws + L.dZ);
+    uint16_t *dZb = reinterpret_cast<uint16_t *>(ws + L.T1);
     uint16_t *WT = reinterpret_cast<uint16_t *>(ws + L.WT);
     float *part = reinterpret_cast<float *>(ws + L.part);
     const unsigned ew = (unsigned)(((size_t)B * kW + 255) / 256);
     hipError_t e;
 #define LCSB_TRY(x) do { if ((e = (x)) != hipSuccess) return e; } while (0)
-    // layer 4
+    // layer 4: gw4 = sum_s dy[s] H3[s][:], gb4 = sum_s dy[s]; dZ3
     LCSB_TRY(column_sums(H3, dy, B, part, grad + ow4, s));
-    sum_vector<<<1, 256, 0, s>>>(dy, B, grad + ob4);
+    sum_vector<<<1, 1024, 0, s>>>(dy, B, grad + ob4);
     LCSB_TRY(hipGetLastError());
-    head_backward<<<ew, 256, 0, s>>>(dy, H3, wb, B, dZ);
+    head_backward<<<ew, 256, 0, s>>>(dy, H3, wb, B, dZa);
     LCSB_TRY(hipGetLastError());
-    // layers 3, 2: gW = dZ^T H_in, gb = column sums of dZ, dH_in = dZ W
-    const uint16_t *Hin[2] = {H2, H1};
-    const int oW[2] = {oW3, oW2}, ob[2] = {ob3, ob2};
-    for (int L3 = 0; L3 < 2; ++L3) {
-        LCSB_TRY(column_sums(dZ, nullptr, B, part, grad + ob[L3], s));
-        transpose_bf16<<<dim3(kW / 32, B / 32), 256, 0, s>>>(dZ, T1, B, kW);      // dZ^T [256][B]
-        LCSB_TRY(hipGetLastError());
-        transpose_bf16<<<dim3(kW / 32, B / 32), 256, 0, s>>>(Hin[L3], T2, B, kW);  // H^T [256][B]
-        LCSB_TRY(hipGetLastError());
-        LCSB_TRY(gemm(T1, T2, grad + oW[L3], kW, kW, B, L.splits, part, s));
-        transpose_bf16<<<dim3(kW / 32, kW / 32), 256, 0, s>>>(wb + oW[L3], WT, kW, kW);  // W^T
-        LCSB_TRY(hipGetLastError());
-        LCSB_TRY(gemm(dZ, WT, dH, B, kW, kW, 1, part, s));                              // dZ W
-        relu_backward<<<ew, 256, 0, s>>>(dH, Hin[L3], (size_t)B * kW, dZ);
-        LCSB_TRY(hipGetLastError());
-    }
-    // layer 1: gW1 = dZ1^T X, gb1
-    LCSB_TRY(column_sums(dZ, nullptr, B, part, grad + ob1, s));
+    transpose_bf16<<<dim3(kW / 32, kW / 32), 256, 0, s>>>(wb + oW3, WT, kW, kW);
+    LCSB_TRY(hipGetLastError());
+    transpose_bf16<<<dim3(kW / 32, kW / 32), 256, 0, s>>>(wb + oW2, WT + kW * kW, kW, kW);
+    LCSB_TRY(hipGetLastError());
+    // layer 3: gW3, gb3 from dZ3 and H2; dZ2 = relu'(H2) (dZ3 W3)
+    LCSB_TRY(weight_grad(dZa, H2, kW, B, L.splits, part, grad + oW3, s));
+    dgrad<<<dim3(kW / 128, B / 128), 256, 0, s>>>(WT, dZa, H2, dZb);
+    LCSB_TRY(hipGetLastError());
+    // layer 2: gW2, gb2 from dZ2 and H1; dZ1 = relu'(H1) (dZ2 W2)
+    LCSB_TRY(weight_grad(dZb, H1, kW, B, L.splits, part, grad + oW2, s));
+    dgrad<<<dim3(kW / 128, B / 128), 256, 0, s>>>(WT + kW * kW, dZb, H1, dZa);
+    LCSB_TRY(hipGetLastError());
+    // layer 1: gW1, gb1 from dZ1 and the encoded inputs
     encode_x<<<(unsigned)(((size_t)B * kIn + 255) / 256), 256, 0, s>>>(idx, h, (uint64_t)B, X);
     LCSB_TRY(hipGetLastError());
-    transpose_bf16<<<dim3(kW / 32, B / 32), 256, 0, s>>>(dZ, T1, B, kW);
-    LCSB_TRY(hipGetLastError());
-    transpose_bf16<<<dim3(kIn / 32, B / 32), 256, 0, s>>>(X, T2, B, kIn);  // X^T [32][B]
-    LCSB_TRY(hipGetLastError());
-    LCSB_TRY(gemm(T1, T2, grad + oW1, kW, kIn, B, L.splits, part, s));
+    LCSB_TRY(weight_grad(dZa, X, kIn, B, L.splits, part, grad + oW1, s));
 #undef LCSB_TRY
     return hipSuccess;
 }
@@ -883,7 +989,7 @@ hipError_t launch_mlp_backward(const uint16_t *wb, const float *dy, int64_t coun
 hipError_t launch_mlp_mse(const float *y, const float *t, int64_t count, float *dy, double *loss,
                           hipStream_t s)
 {
-    mse_kernel<<<1, 256, 0, s>>>(y, t, (int)count, dy, loss);
+    mse_kernel<<<1, 1024, 0, s>>>(y, t, (int)count, dy, loss);
     return hipGetLastError();
 }
 

@@ -163,6 +163,31 @@ def polish(P, S, best, target):
     return swept, certs, best
 
 
+def fp64_sweep(pk, h, sweeps=32):
+    """The plain FP64 sweep (bit-identical to the oracle) at sigma = d = 2,
+    l = h from zero: average launch time from HIP events on the library's
+    stream, against the HBM peak (24 algorithmic bytes per update)."""
+    import torch
+    L = pk.Lcsb(2, 2, h, "f64")
+    L.init_zero()
+    L.iterate(8)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    L.iterate(sweeps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / sweeps
+    n = 4 ** h
+    gbs = 24 * n / ms / 1e6
+    del L
+    torch.cuda.empty_cache()
+    return {"workload": f"sigma=2 d=2 l={h}: {n} FP64 entries", "bound": "hbm",
+            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(ms, 4),
+            "updates_per_s": n / ms * 1e3}
+
+
 def fp32_error(P, S, chunk=1 << 28):
     """Largest per-entry difference between the FP32 table of S and the FP64
     table of P, both taken relative to their entry 0, over the FP64 table's
@@ -481,6 +506,8 @@ def main():
                 "avg_launch_ms": round(avg_sweep_s * 1e3, 4)}
     del L
     torch.cuda.empty_cache()
+    fp64 = fp64_sweep(pk, 14)
+    log(f"plain FP64 sweep at l=14: {fp64['avg_launch_ms']} ms, {fp64['frac']} of peak")
 
     ttb = None
     if not args.no_ttb:
@@ -498,6 +525,7 @@ def main():
                                f"FP64 round-down certificate every {cad} sweeps",
                    "sweeps_per_step": cad, "entries": n},
         "roofline": roofline,
+        "fp64_sweep": fp64,
         "cpu_baseline": cpu,
         "time_to_bound": ttb,
         "sweep_only_updates_per_s": n / avg_sweep_s,

@@ -75,9 +75,14 @@ __device__ __forceinline__ float input_at(uint64_t i, int h, int slot)
 // has head 0).  Its unique member with a zero bit at both pivots (a's head
 // and the highest set bit of c') is the representative.  For c in {0, 1..1}
 // the span is one-dimensional and only a's head is fixed.  Orbit number t:
-//   t <  2^h 2^(l-2): c = t >> (l-2), x = the low l-2 bits, a = x with a
-//                     zero inserted at c's pivot (head bit 0); for c in
-//                     {0, 1..1}, a = x (the half of a with bit l-2 clear);
+//   t <  2^h 2^(l-2): t's bits are, from the lowest, x0 x1 c0 c1, then the
+//                     other l-4 bits of x, then the other l-2 bits of c; a =
+//                     x with a zero inserted at c's pivot (head bit 0); for
+//                     c in {0, 1..1}, a = x (the half of a with bit l-2
+//                     clear).  Sixteen consecutive t thus hold every value of
+//                     the last two symbols of both strings and, unless the
+//                     pivot is among those two positions, write one aligned
+//                     16-entry window of each orbit member;
 //   t >= 2^h 2^(l-2): the other half for c = 0, then for c = 1..1.
 // Count (2^l + 2) 2^(l-2) = 4^l / 4 + 2^(l-1).
 __device__ __forceinline__ uint32_t spread16(uint32_t x)  // bit k -> bit 2k
@@ -94,13 +99,11 @@ __device__ __forceinline__ uint64_t orbit_rep_index(uint64_t t, int h)
 {
     const int lo = h - 2;
     const uint32_t all = (1u << h) - 1u;
-    const uint32_t ci = (uint32_t)(t >> lo), x = (uint32_t)t & ((1u << lo) - 1u);
     uint32_t a, c;
-    if (ci >= (1u << h)) {
-        c = ci == (1u << h) ? 0u : all;
-        a = x | (1u << lo);
-    } else {
-        c = ci;
+    if (t < (1ull << (2 * h - 2))) {
+        const uint32_t tt = (uint32_t)t;
+        const uint32_t x = (tt & 3u) | (((tt >> 4) & ((1u << (h - 4)) - 1u)) << 2);
+        c = ((tt >> 2) & 3u) | ((tt >> h) << 2);
         const uint32_t cp = (c >> (h - 1)) ? (c ^ all) : c;
         if (cp == 0u) {
             a = x;
@@ -108,6 +111,10 @@ __device__ __forceinline__ uint64_t orbit_rep_index(uint64_t t, int h)
             const int j = 31 - __builtin_clz(cp);
             a = ((x >> j) << (j + 1)) | (x & ((1u << j) - 1u));
         }
+    } else {
+        const uint32_t u = (uint32_t)(t - (1ull << (2 * h - 2)));
+        c = (u >> lo) == 0u ? 0u : all;
+        a = (u & ((1u << lo) - 1u)) | (1u << lo);
     }
     const uint32_t b = a ^ c;
     return ((uint64_t)spread16(a) << 1) | spread16(b);  // string a in the odd bits

@@ -166,6 +166,47 @@ def test_fp64_h14_sampled_sweep_and_certificate(pk):
     assert np.all(w_s[idx < cur["argmax_W"]] < cur["maxW"])  # lowest index attains it
 
 
+def test_fp64_h16_sampled_sweep_and_certificate(pk):
+    """The largest FP64 table: sigma = d = 2, l = 16, 2^32 entries (32 GiB)
+    per table, as the time-to-bound runs use it.  One sweep from a seeded
+    ring, bit-identical to the oracle at 20000 sampled coordinates; the
+    certificate of the seeded ring: R over the whole table, W at its argmax
+    and at the samples."""
+    sigma, d, h = 2, 2, 16
+    n = 4 ** h
+    free, _ = torch.cuda.mem_get_info()
+    if free < 5 * 8 * n + 8 * 2**30:
+        pytest.skip("needs ~170 GiB of free device memory")
+    say("h=16 FP64: generating seeded ring on the device")
+    lags_dev = [si.table(sigma, d, h, seed=30 + k, device="cuda") for k in range(d)]
+    L = pk.Lcsb(sigma, d, h, "f64")
+    L.load_ring(lags_dev)
+    say("h=16 FP64: certificate of the seeded ring")
+    cur, _ = L.certify()
+    say("h=16 FP64: sweep")
+    L.iterate(1)
+    got, _ = L.lag(1)
+    idx = si.sample_indices(n, 20000, seed=7).to("cuda")
+    got_s = got[idx].cpu().numpy()
+    idx = idx.cpu().numpy().astype(np.uint64)
+    del got, L
+    torch.cuda.empty_cache()
+    say("h=16 FP64: copying the seeded ring to the host")
+    lags = [_host(x) for x in lags_dev]
+    del lags_dev
+    torch.cuda.empty_cache()
+    ref = oracle.sweep_at(sigma, d, h, lags, idx)
+    assert np.array_equal(got_s, ref)
+    say("h=16 FP64: oracle R over 2^32 entries")
+    R, _ = oracle.max_diff(lags[0], lags[1])
+    assert cur["R"] == R
+    w_arg = oracle.certify_W_at(sigma, d, h, lags[0], R, np.array([cur["argmax_W"]], np.uint64))
+    assert w_arg[0] == cur["maxW"]
+    w_s = oracle.certify_W_at(sigma, d, h, lags[0], R, idx)
+    assert np.all(w_s <= cur["maxW"])
+    assert np.all(w_s[idx < cur["argmax_W"]] < cur["maxW"])  # lowest index attains it
+
+
 def _fp32_bound(values_abs_max):
     """FP32 error of one sweep on exact float inputs, per entry: the pairwise
     sum of at most 16 values (4 levels), the exact scaling, the offset

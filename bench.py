@@ -68,6 +68,8 @@ def parse():
     p.add_argument("--profile-train", type=int, default=0,
                    help="only generate the warm-start training tables and run this many steps")
     p.add_argument("--train-batch", type=int, default=8192, help="batch of --profile-train")
+    p.add_argument("--profile-certify", action="store_true",
+                   help="only run 8 sweeps from zero and two certificates (counter collection)")
     return p.parse_args()
 
 
@@ -436,6 +438,18 @@ def train_only(pk, h, steps, batch=8192):
         f"{flop / dt / 1e12:.1f} TFLOP/s, last loss {M.loss_dev.item():.3e}")
 
 
+def certify_only(pk, h, sigma=2, d=2, dtype="f32"):
+    """8 sweeps from zero at (sigma, d, l = h), then two certificates."""
+    import torch
+    L = pk.Lcsb(sigma, d, h, dtype)
+    L.init_zero()
+    L.iterate(8)
+    L.certify()
+    L.certify()
+    torch.cuda.synchronize()
+    log(f"two certificates at sigma={sigma} d={d} l={h} {dtype}")
+
+
 def copy_only(gib):
     """One plain device-to-device copy of `gib` GiB (after one warmup copy),
     the reference for scaling the HBM counters."""
@@ -467,6 +481,8 @@ def main():
         return copy_only(args.copy_gib)
     if args.profile_seed:
         return seed_only(pk, args.h)
+    if args.profile_certify:
+        return certify_only(pk, args.h, args.sigma, args.d, args.dtype)
     if args.profile_train:
         return train_only(pk, args.h, args.profile_train, args.train_batch)
     if args.configs:

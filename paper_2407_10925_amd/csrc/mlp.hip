@@ -7,8 +7,9 @@
 // Every matrix product runs on the gfx950 matrix cores as
 // v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation.  Parameters
 // live as one FP32 master vector (layout below) plus its BF16 rounding
-// (round to nearest, ties to even); biases are applied in FP32 and the
-// activation handed to the next layer is rounded to BF16 after the ReLU.
+// (round to nearest, ties to even); biases are added in FP32 (as the
+// accumulators' initial value) and the activation handed to the next layer
+// is the BF16 rounding of its ReLU.
 //
 // Parameter layout (floats), matrices output-major ([out][in]):
 //   W1[256][32] b1[256] W2[256][256] b2[256] W3[256][256] b3[256] w4[256] b4[1]
@@ -43,7 +44,6 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-__device__ __forceinline__ __bf16 to_bf(float f) { return __builtin_bit_cast(__bf16, f2bf(f)); }
 
 __device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c)
 {
@@ -75,7 +75,7 @@ __device__ __forceinline__ float input_at(uint64_t i, int h, int slot)
 // has head 0).  Its unique member with a zero bit at both pivots (a's head
 // and the highest set bit of c') is the representative.  For c in {0, 1..1}
 // the span is one-dimensional and only a's head is fixed.  Orbit number t:
-//   t <  2^h 2^(l-2): t's bits are, from the lowest, x0 x1 c0 c1, then the
+//   t <  2^(2l-2):    t's bits are, from the lowest, x0 x1 c0 c1, then the
 //                     other l-4 bits of x, then the other l-2 bits of c; a =
 //                     x with a zero inserted at c's pivot (head bit 0); for
 //                     c in {0, 1..1}, a = x (the half of a with bit l-2
@@ -83,7 +83,7 @@ __device__ __forceinline__ float input_at(uint64_t i, int h, int slot)
 //                     the last two symbols of both strings and, unless the
 //                     pivot is among those two positions, write one aligned
 //                     16-entry window of each orbit member;
-//   t >= 2^h 2^(l-2): the other half for c = 0, then for c = 1..1.
+//   t >= 2^(2l-2):    the other half for c = 0, then for c = 1..1.
 // Count (2^l + 2) 2^(l-2) = 4^l / 4 + 2^(l-1).
 __device__ __forceinline__ uint32_t spread16(uint32_t x)  // bit k -> bit 2k
 {
@@ -139,7 +139,7 @@ __device__ __forceinline__ uint64_t swap_strings(uint64_t i)
 // 32kb + 8g .. 32kb + 8g + 7: input feature 32kb + 8g + t of the next layer
 // sits in slot t.  Activations never leave the registers.  Layers
 // 2 and 3 stream their weights through LDS in 16-row tiles (8 KB), consumed
-// two per workgroup barrier and shared by the workgroup's waves.
+// kStep per workgroup barrier and shared by the workgroup's waves.
 constexpr int kFwdWaves = 8;
 constexpr int kFwdBlocks = 2;                          // 16-sample MFMA column blocks per wave
 constexpr int kFwdThreads = 64 * kFwdWaves;
@@ -167,8 +167,6 @@ struct FwdArgs {
     uint64_t n;              // table entries (kSrcOrbits)
     double rate;             // lag 1 = u + rate, lag 2 = u
 };
-
-__device__ __forceinline__ uint32_t pack2(float lo, float hi);
 
 // H_layer[s][feature] = the BF16 activations of the wave's samples (backward).
 // Words act[kb][b][0..3] of a lane hold features 32 kb + 8 g .. 32 kb + 8 g + 7
@@ -213,7 +211,7 @@ __device__ __forceinline__ bf16x8 as_bf8(uint32_t w0, uint32_t w1, uint32_t w2, 
 // biases, w4, the streamed W2/W3 tiles), so those reads use immediate
 // offsets.  W2 and W3 do not fit in LDS together, so their 16-row tiles flow
 // through a ring of kRing slots as one endless stream (W2 tiles 0..15, W3
-// tiles 0..15, W2 again for the next batch, ...) loaded three tile pairs
+// tiles 0..15, W2 again for the next batch, ...) loaded kRing - kStep tiles
 // ahead by direct global-to-LDS loads.  The stream position of tile f is
 // congruent to f modulo kRing, so slot indices are compile-time constants.
 constexpr int kRing = 8;   // ring slots (one 8 KB tile each); divides 16
@@ -279,10 +277,11 @@ __device__ __forceinline__ floatx4 bias4(const float *b, int f, int g)
 
 // Tile (layer, f) = weight rows perm_row(f, 0..15) of W2 (layer 0) or W3
 // (layer 1), stored chunk-major: the 16-byte chunk c (k = 8c .. 8c+7) of
-// tile row i sits at byte 16 (16 c + i).  Each thread moves one chunk
-// straight from global memory into the ring slot (gfx950 buffer_load_dwordx4
-// with the lds bit: no registers, counted by vmcnt); thread t lands at byte
-// 16 t, so it fetches chunk t/16 of row t%16.  A fragment read (lane (i, g)
+// tile row i sits at byte 16 (16 c + i).  The workgroup's threads move the
+// 512 chunks straight from global memory into the ring slot (gfx950
+// buffer_load_dwordx4 with the lds bit: no registers, counted by vmcnt),
+// kTileOps per thread; chunk q lands at byte 16 q, so it is chunk q/16 of
+// row q%16.  A fragment read (lane (i, g)
 // needs chunk 4 kb + g of row i) is then the 1 KB at byte 16 lane + 1024 kb:
 // contiguous across the 64 lanes (no bank conflicts) and one base address
 // plus immediate offsets for every k block and slot.  The buffer form (not
@@ -313,7 +312,6 @@ __device__ __forceinline__ void issue_tile(__amdgpu_buffer_rsrc_t rs, int layer,
     }
 }
 
-// s_waitcnt vmcnt(n) (expcnt and lgkmcnt left free), n < 16
 // Workgroup barrier without a memory fence: a fence would make every wave
 // wait for all of its loads still landing in the ring.  Callers wait for the
 // loads they need (wait_vmcnt) before it; the "memory" clobber keeps the

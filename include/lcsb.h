@@ -171,8 +171,9 @@ int lcsb_upcast(const lcsb_ctx *src_f32, lcsb_ctx *dst_f64);
 #define LCSB_MLP_WIDTH 256
 #define LCSB_MLP_NPARAMS 140289
 
-/* Bytes of the training workspace for `batch` samples (activations, BF16
- * transposes, split-K partial sums). */
+/* Bytes of the training workspace for `batch` samples (the stored BF16
+ * activations and encoded inputs, two BF16 gradient buffers, the transposed
+ * hidden weights, and the per-split partial sums of the weight gradients). */
 int lcsb_mlp_workspace(int64_t batch, uint64_t *bytes);
 
 /* Seeded initialisation: every weight of a layer with fan-in k uniform in
@@ -204,7 +205,9 @@ int lcsb_mlp_loss(const float *y, const float *target, int64_t batch, float *dy,
 /* Gradient of the loss with respect to every parameter (FP32, layout as the
  * parameters), from dy and the activations a preceding lcsb_mlp_forward left
  * in ws for the same idx, h and batch.  The BF16 rounding of the weights and
- * activations passes gradients unchanged. */
+ * activations passes gradients unchanged; every upstream gradient is rounded
+ * to BF16 before it meets a weight matrix.  Deterministic: every sum runs in
+ * a fixed order. */
 int lcsb_mlp_backward(const uint16_t *wbf16, const uint64_t *idx, int h, const float *dy,
                       int64_t batch, void *ws, float *grad, void *stream);
 

@@ -708,7 +708,8 @@ __global__ __launch_bounds__(256) void transpose_bf16(const uint16_t *__restrict
     for (int k = ty; k < 32; k += 8) T[(size_t)(c0 + k) * rows + r0 + tx] = tile[tx][k];
 }
 
-// dZ3[s][o] = bf16(dy[s] * w4[o]) where h3 > 0; dw4[o] = sum_s dy[s] h3[s][o]
+// dZ3[s][o] = bf16(dy[s] * w4[o]) where H3[s][o] > 0, else 0 (the output layer's
+// weight gradient sum_s dy[s] H3[s][o] is column_sums with weights dy)
 __global__ __launch_bounds__(256) void head_backward(const float *__restrict__ dy,
                                                      const uint16_t *__restrict__ H3,
                                                      const uint16_t *__restrict__ wb, int count,

@@ -263,14 +263,24 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
         T p0, p1;
         load2(lag1 + b1, p0, p1);
         const T k1 = (p0 + p1) * (T)0.5;
-        T k2 = tree4(lag2[b2], lag2[b2 + 2], lag2[b2 + 4], lag2[b2 + 6]) * (T)0.25;
+        // entries b2 + 0, 2, 4, 6: the even or odd half of the aligned group
+        // b2 & ~7, whose other half another thread of the wave reads
+        T q[8];
+        load4(lag2 + (b2 & ~(uint64_t)7), q);
+        load4(lag2 + (b2 & ~(uint64_t)7) + 4, q + 4);
+        const int o = (int)(b2 & 1);
+        T k2 = tree4(q[o], q[o + 2], q[o + 4], q[o + 6]) * (T)0.25;
         if constexpr (kF32) k2 = k2 + d2;
         val[1] = vmax(k1, k2);
     }
     {   // 010
         const uint64_t i = ((uint64_t)2 << top) | x;
         const uint64_t b1 = base(i, S2), b2 = base(i, S1 | S3);
-        const T k1 = (lag1[b1] + lag1[b1 + 2]) * (T)0.5;
+        T e[8];  // entries b1, b1 + 2 from their aligned group
+        load4(lag1 + (b1 & ~(uint64_t)7), e);
+        load4(lag1 + (b1 & ~(uint64_t)7) + 4, e + 4);
+        const int o = (int)(b1 & 7);
+        const T k1 = (e[o] + e[o + 2]) * (T)0.5;
         T q0, q1, q2, q3;
         load2(lag2 + b2, q0, q1);
         load2(lag2 + b2 + 4, q2, q3);
@@ -285,7 +295,11 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
         load4(lag2 + b2, q);
         T k2 = tree4(q[0], q[1], q[2], q[3]) * (T)0.25;
         if constexpr (kF32) k2 = k2 + d2;
-        const T k1 = (lag1[b1] + lag1[b1 + 4]) * (T)0.5;
+        T e[8];  // entries b1, b1 + 4 from their aligned group
+        load4(lag1 + (b1 & ~(uint64_t)7), e);
+        load4(lag1 + (b1 & ~(uint64_t)7) + 4, e + 4);
+        const int o = (int)(b1 & 7);
+        const T k1 = (e[o] + e[o + 4]) * (T)0.5;
         val[3] = vmax(k2, k1);
     }
 #pragma unroll

@@ -1,16 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the sweep of the lower-bound iteration for gamma_{2,2}.
 
-Workload: sigma = d = 2, l = 16 (2^32 table entries), FP32 sweeps renormalised
-by entry 0, with an FP64 round-down certificate every 64 sweeps.  One step is
-one certificate period: 64 sweeps + one certificate.  The reported value is
-table updates per second (2^32 updates per sweep) over the K timed steps,
-with the ring already resident in HBM.
+Workload: sigma = d = 2, l = 16 (2^32 table indices, of which the 2^31 with
+string-1 head 0 are stored: the complement symmetry of Sec. 3.3), FP32 sweeps
+renormalised by entry 0, with an FP64 round-down certificate every 64 sweeps.
+One step is one certificate period: 64 sweeps + one certificate.  The
+reported value is table updates per second (2^32 updates per sweep, one per
+index) over the K timed steps, with the ring already resident in HBM.
 
 Also printed in the same JSON line:
   roofline      the sweep kernel's algorithmic bytes per launch (12 B per
-                update: lag 1 and lag 2 read once, the new table written once)
-                over its average launch time, from HIP events on the stream
+                stored entry: lag 1 and lag 2 read once, the new table
+                written once; 6 B per update) over its average launch time,
+                from HIP events on the stream
                 the library launches on, against the 8 TB/s HBM peak; traffic
                 is the rocprofv3-measured HBM bytes per launch when a counter
                 summary for the current kernel source is committed, else null
@@ -168,7 +170,7 @@ def polish(P, S, best, target):
 def fp64_sweep(pk, h, sweeps=32):
     """The plain FP64 sweep (bit-identical to the oracle) at sigma = d = 2,
     l = h from zero: average launch time from HIP events on the library's
-    stream, against the HBM peak (24 algorithmic bytes per update)."""
+    stream, against the HBM peak (24 algorithmic bytes per stored entry)."""
     import torch
     L = pk.Lcsb(2, 2, h, "f64")
     L.init_zero()
@@ -181,7 +183,7 @@ def fp64_sweep(pk, h, sweeps=32):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / sweeps
     n = 4 ** h
-    gbs = 24 * n / ms / 1e6
+    gbs = 24 * L.stored / ms / 1e6
     del L
     torch.cuda.empty_cache()
     return {"workload": f"sigma=2 d=2 l={h}: {n} FP64 entries", "bound": "hbm",
@@ -366,7 +368,7 @@ def config_table(pk):
         sweep_ms = e[0].elapsed_time(e[1]) / reps
         cert_ms = e[2].elapsed_time(e[3])
         elem = 8 if dt == "f64" else 4
-        algo = (d + 1) * elem * L.n
+        algo = (d + 1) * elem * L.stored
         rows.append({"sigma": sigma, "d": d, "l": h, "dtype": dt, "entries": L.n,
                      "sweep_ms": round(sweep_ms, 4), "certificate_ms": round(cert_ms, 3),
                      "algorithmic_GBps": round(algo / sweep_ms / 1e6, 1),
@@ -513,7 +515,7 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * cad * args.steps / elapsed
     avg_sweep_s = statistics.mean(sweep_ms) * 1e-3
-    algo_bytes = 12 * n  # per launch: (d + 1) tables x 4 bytes per update
+    algo_bytes = 12 * L.stored  # per launch: (d + 1) tables x 4 bytes per stored entry
     achieved = algo_bytes / avg_sweep_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -539,7 +541,7 @@ def main():
         "dtype": "f32 sweeps, f64 certificate", "data": "synthetic (zero-start iteration)",
         "config": {"workload": f"sigma=2 d=2 l={h}: {n} entries, FP32 renormalised sweeps, "
                                f"FP64 round-down certificate every {cad} sweeps",
-                   "sweeps_per_step": cad, "entries": n},
+                   "sweeps_per_step": cad, "entries": n, "stored_entries": n // 2},
         "roofline": roofline,
         "fp64_sweep": fp64,
         "cpu_baseline": cpu,

@@ -26,17 +26,18 @@
  * alphabet {0..sigma-1}, sigma = 2^beta, has the index whose bits, most
  * significant first, are the beta-bit symbols a_1[1], a_2[1], .., a_d[1],
  * a_1[2], .., a_d[l] (position-major, string 1 first, heads on top).  For
- * sigma = d = 2 this is the interleaved pair of Sec. 3.2.  Entry i of a table
- * buffer is the value at index i (8-byte doubles for LCSB_F64, 4-byte floats
- * for LCSB_F32).
+ * sigma = d = 2 this is the interleaved pair of Sec. 3.2.
  *
- * Symmetry.  Relabelling every symbol c -> c xor m leaves LCS lengths
+ * Folded storage.  Relabelling every symbol c -> c xor m leaves LCS lengths
  * unchanged (for sigma = 2 this is the complement symmetry of Sec. 3.3,
- * eq. (10)).  The sweep computes one representative per orbit and writes the
- * same value to the other sigma - 1 members, so it requires lag tables that
- * are exactly invariant under that relabelling; every table the library
- * writes is, and lcsb_load_ring projects its input onto such tables.  The
- * certificate does not rely on the symmetry: it evaluates every coordinate.
+ * eq. (10)), and so every iterate: v[i] = v[i xor (m rep)], rep the index with
+ * symbol 1 at every position.  A table buffer therefore holds only the
+ * n / sigma indices whose string-1 head is 0, which are the lowest n / sigma
+ * indices: entry i is the value at index i for i < n / sigma (8-byte doubles
+ * for LCSB_F64, 4-byte floats for LCSB_F32), and index i with string-1 head
+ * m holds the value of entry i xor (m rep).  With the branch sums taken in
+ * the order stated at lcsb_iterate, every sweep and certificate on the folded
+ * table is bit-identical to the same computation on the full table.
  */
 #ifndef LCSB_H
 #define LCSB_H
@@ -81,7 +82,7 @@ typedef struct {
     double rho;
     int64_t sweep;      /* sweeps applied before this certificate            */
     uint64_t argmax_W;  /* lowest index where W attains maxW                 */
-    uint64_t nonfinite; /* coordinates where u, prev or W is not finite      */
+    uint64_t nonfinite; /* stored coordinates where u, prev or W is not finite */
 } lcsb_cert;
 
 /* Create a context for (sigma, d, l = h) and a table element type.
@@ -91,8 +92,9 @@ typedef struct {
 int lcsb_create(int sigma, int d, int h, int dtype, lcsb_ctx **out);
 
 /* Sizes the caller must allocate: nbuf = d + 1 ring tables of bytes_per_buf
- * bytes each (entries = sigma^(d h) elements), and one device workspace of
- * workspace_bytes bytes, 256-byte aligned.  Any output pointer may be NULL. */
+ * bytes each (entries = sigma^(d h - 1) stored elements, see folded storage),
+ * and one device workspace of workspace_bytes bytes, 256-byte aligned.  Any
+ * output pointer may be NULL. */
 int lcsb_query(const lcsb_ctx *ctx, int *nbuf, uint64_t *entries,
                uint64_t *bytes_per_buf, uint64_t *workspace_bytes);
 
@@ -108,13 +110,15 @@ int lcsb_bind(lcsb_ctx *ctx, void *const *dev_bufs, int nbuf, void *dev_workspac
  * and the initial triplet (v_0, 0, 0). */
 int lcsb_init_zero(lcsb_ctx *ctx);
 
-/* Set lag k (k = 1..d) to the caller's device table src[k-1] (same element
- * type and size as the ring; src may not alias a ring buffer), each value
- * taken at its orbit representative (the index whose string-1 head is 0 after
- * the symbol relabelling), so the ring is symmetric.  offsets (host, d
- * doubles, may be NULL = all zero) are the values the FP32 tables are
- * relative to (true value = offset + stored value); ignored for LCSB_F64.
- * Resets the sweep count and the best certificate. */
+/* Set lag k (k = 1..d) to the caller's device table src[k-1]: the ring's
+ * element type, aligned to it, at least `entries` elements (a full table of
+ * sigma^(d h) values may be passed), not aliasing a ring buffer.  Its first
+ * `entries` values are copied: every other index takes the value of its image
+ * with string-1 head 0, so the loaded ring is the symmetric table that agrees
+ * with src at the stored indices.  offsets (host, d doubles, may be NULL =
+ * all zero) are the values the FP32 tables are relative to (true value =
+ * offset + stored value); ignored for LCSB_F64.  Resets the sweep count and
+ * the best certificate. */
 int lcsb_load_ring(lcsb_ctx *ctx, const void *const *src, int nsrc, const double *offsets);
 
 /* Apply k >= 0 sweeps v_new = F(lag 1, .., lag d) of eq. (4) on the bound
@@ -185,9 +189,10 @@ int lcsb_mlp_init(float *params, uint64_t seed, void *stream);
 int lcsb_mlp_to_bf16(const float *params, uint16_t *wbf16, void *stream);
 
 /* Draw `batch` table indices uniformly (SplitMix64 of Steele, Lea and Flood,
- * counter seed * 2^32 + j + 1, top 2h bits) from a sigma = d = 2 table of
- * window length h (FP64 or FP32 per dtype, 4^h entries) and gather the
- * normalised targets target[j] = table[idx[j]] - table[0] (as FP32). */
+ * counter seed * 2^32 + j + 1, top 2h bits) from a folded sigma = d = 2 table
+ * of window length h (FP64 or FP32 per dtype, 4^h / 2 stored entries) and
+ * gather the normalised targets target[j] = v[idx[j]] - v[0] (as FP32), an
+ * index with string-1 head 1 read at its complement. */
 int lcsb_mlp_sample(const void *table, int dtype, int h, uint64_t seed, int64_t batch,
                     uint64_t *idx, float *target, void *stream);
 

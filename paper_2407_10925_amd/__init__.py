@@ -22,8 +22,11 @@ _DTYPES = {"f64": LCSB_F64, "f32": LCSB_F32}
 class Lcsb:
     """One ring of d+1 tables for (sigma, d, h) on one GPU.
 
-    Methods mirror the C entry points: init_zero, load_ring, iterate,
-    certify, lag, status, upcast, destroy.
+    ``n`` = sigma^(d h) is the number of table indices; every table stores the
+    ``stored`` = n / sigma lowest ones (string-1 head 0), the others being
+    equal to their image under the symbol relabelling.  Methods mirror the C
+    entry points: init_zero, load_ring, iterate, certify, lag, status,
+    upcast, destroy.
     """
 
     def __init__(self, sigma: int, d: int, h: int, dtype: str = "f64", device=None):
@@ -44,10 +47,12 @@ class Lcsb:
         self._ctx = ctx
         nbuf, n, bpb, wsb = C.c_int(), C.c_uint64(), C.c_uint64(), C.c_uint64()
         check(lib.lcsb_query(ctx, C.byref(nbuf), C.byref(n), C.byref(bpb), C.byref(wsb)))
-        self.nbuf, self.n = nbuf.value, n.value
+        self.nbuf, self.stored = nbuf.value, n.value
+        self.n = sigma ** (d * h)
         tdt = torch.float64 if dtype == "f64" else torch.float32
         self.torch_dtype = tdt
-        self.bufs = [torch.empty(self.n, dtype=tdt, device=self.device) for _ in range(self.nbuf)]
+        self.bufs = [torch.empty(self.stored, dtype=tdt, device=self.device)
+                     for _ in range(self.nbuf)]
         self.ws = torch.empty(wsb.value, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         ptrs = (C.c_void_p * self.nbuf)(*[b.data_ptr() for b in self.bufs])
@@ -59,12 +64,13 @@ class Lcsb:
         check(self._lib.lcsb_init_zero(self._ctx))
 
     def load_ring(self, tables, offsets=None):
-        """tables[k-1] = lag k, device tensors of the ring's dtype and size."""
+        """tables[k-1] = lag k: device tensors of the ring's dtype holding all n
+        indices or only the stored ones (the first ``stored`` values are used)."""
         if len(tables) != self.d:
             raise ValueError(f"need {self.d} tables")
         for t in tables:
-            if t.dtype != self.torch_dtype or t.numel() != self.n or not t.is_contiguous() \
-                    or t.device != self.device:
+            if t.dtype != self.torch_dtype or t.numel() not in (self.n, self.stored) \
+                    or not t.is_contiguous() or t.device != self.device:
                 raise ValueError("table dtype, size, layout or device does not match the ring")
         self._keep = list(tables)
         ptrs = (C.c_void_p * self.d)(*[t.data_ptr() for t in tables])
@@ -85,7 +91,8 @@ class Lcsb:
         return cur.as_dict(), best.as_dict()
 
     def lag(self, k: int = 1):
-        """(tensor aliasing lag k, its FP64 offset).  Valid until the next sweep."""
+        """(tensor aliasing the stored entries of lag k, its FP64 offset).
+        Valid until the next sweep."""
         p, off = C.c_void_p(), C.c_double()
         check(self._lib.lcsb_lag(self._ctx, k, C.byref(p), C.byref(off)))
         for b in self.bufs:

@@ -101,6 +101,7 @@ int lcsb_create(int sigma, int d, int h, int dtype, lcsb_ctx **out)
     c->g.beta = beta;
     c->g.slot = beta * d;
     c->g.n = 1ull << bits;
+    c->g.ns = c->g.n >> beta;
     c->dtype = dtype;
     c->nbuf = d + 1;
     c->state = kCreated;
@@ -114,8 +115,8 @@ int lcsb_query(const lcsb_ctx *c, int *nbuf, uint64_t *entries, uint64_t *bytes_
 {
     if (!c) return fail(LCSB_EINVAL, "null context");
     if (nbuf) *nbuf = c->nbuf;
-    if (entries) *entries = c->g.n;
-    if (bytes_per_buf) *bytes_per_buf = c->g.n * elem_size(c->dtype);
+    if (entries) *entries = c->g.ns;
+    if (bytes_per_buf) *bytes_per_buf = c->g.ns * elem_size(c->dtype);
     if (workspace_bytes) *workspace_bytes = Ws::kBytes;
     return LCSB_OK;
 }
@@ -147,7 +148,7 @@ int lcsb_init_zero(lcsb_ctx *c)
     if (!c) return fail(LCSB_EINVAL, "null context");
     if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
     if (c->state < kBound) return fail(LCSB_ESTATE, "bind before init");
-    const uint64_t bytes = c->g.n * elem_size(c->dtype);
+    const uint64_t bytes = c->g.ns * elem_size(c->dtype);
     hipError_t e;
     for (int k = 0; k < c->nbuf; ++k)
         if ((e = launch_fill_zero(c->buf[k], bytes, c->stream)) != hipSuccess)
@@ -168,7 +169,8 @@ int lcsb_load_ring(lcsb_ctx *c, const void *const *src, int nsrc, const double *
     if (c->state < kBound) return fail(LCSB_ESTATE, "bind before load");
     if (!src || nsrc != c->g.d) return fail(LCSB_EINVAL, "need d = %d source tables", c->g.d);
     for (int k = 0; k < nsrc; ++k) {
-        if (!src[k]) return fail(LCSB_EINVAL, "source %d is null", k);
+        if (!src[k] || ((uintptr_t)src[k] & (elem_size(c->dtype) - 1)))
+            return fail(LCSB_EINVAL, "source %d null or not aligned to its element", k);
         for (int j = 0; j < c->nbuf; ++j)
             if (src[k] == c->buf[j]) return fail(LCSB_EINVAL, "source %d aliases a ring buffer", k);
     }
@@ -178,8 +180,9 @@ int lcsb_load_ring(lcsb_ctx *c, const void *const *src, int nsrc, const double *
     c->head = 0;
     for (int k = 1; k <= c->g.d; ++k) {
         const int slot = slot_of_lag(c, k);
-        if ((e = launch_project_copy(c->g, c->dtype, src[k - 1], c->buf[slot], c->stream)) != hipSuccess)
-            return hip_fail(c, e, "project copy");
+        if ((e = launch_copy(src[k - 1], c->buf[slot], c->g.ns * elem_size(c->dtype), c->stream)) !=
+            hipSuccess)
+            return hip_fail(c, e, "copy");
         if (c->dtype == LCSB_F32) {
             double o = offsets ? offsets[k - 1] : 0.0;
             double *dev = reinterpret_cast<double *>(c->ws + Ws::kOffsets) + slot;

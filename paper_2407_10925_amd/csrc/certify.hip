@@ -15,10 +15,16 @@
 //           uniquely, so this equals the error-free-transform evaluation
 //           bit for bit.
 //
-// Unlike the sweep, this evaluates every coordinate and assumes no symmetry
-// of u, so the certificate holds for any table.  FP32 tables are certified as
-// their exact FP64 values: the certificate is translation invariant, so the
-// FP64 offset of an FP32 table does not enter W; it enters only R.
+// Tables are stored folded (the indices with string-1 head 0; every other
+// index holds the value of its image under the symbol relabelling, Sec. 3.3).
+// Both passes evaluate every stored coordinate.  The coordinate i xor (m rep)
+// reads the images of the values coordinate i reads, in an order that only
+// swaps operands of commutative additions and of the max, so its W equals W[i]
+// bit for bit in every rounding mode: the max over stored coordinates is the
+// max over all coordinates, and its lowest index is a stored one.  FP32 tables
+// are certified as their exact FP64 values: the certificate is translation
+// invariant, so the FP64 offset of an FP32 table does not enter W; it enters
+// only R.
 #include <math.h>
 
 #include <type_traits>
@@ -183,39 +189,47 @@ struct WBest {
     }
 };
 
-// sigma = d = 2: heads 00, 01, 10, 11 of x
+// sigma = d = 2: thread t < n/8 evaluates the stored coordinates 0/0|t,
+// 0/0|xc, 0/1|t, 0/1|xc (xc = n/4-1-t, the complement of t).  The lag-2 group
+// of xc is the image of the one of t; the advance-a pair of 0/1|xc is read in
+// the image group at the other parity (see the sweep).
 template <typename T>
-__device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint64_t x,
+__device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint64_t t,
                                       const double *shift, const Scales &sc, double dR_up,
                                       WBest &best)
 {
-    const uint64_t nq = n >> 2, am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
+    const uint64_t nq = n >> 2, xc = nq - 1 - t;
+    const uint64_t am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
     double g[4];
-    ld4(u + 4 * x, g);
+    ld4(u + 4 * t, g);
     const double f_match = 1.0 + mean_rd<4>(g, shift[2], sc.q[2]);
-    best.add((double)u[x], f_match, dR_up, x);
-    best.add((double)u[3 * nq + x], f_match, dR_up, 3 * nq + x);
+    best.add((double)u[t], f_match, dR_up, t);
+    best.add((double)u[xc], f_match, dR_up, xc);
 #pragma unroll
-    for (int hd = 1; hd <= 2; ++hd) {  // heads 01, 10
-        const uint64_t i = (uint64_t)hd * nq + x;
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t i = nq + (c ? xc : t);
         const uint64_t sb = (i & am) | ((i << 2) & bm);
         const uint64_t sa = ((i << 2) & am) | (i & bm);
         double q[4], pb[2], pa[2];
         ld4(u + (sb & ~(uint64_t)3), q);
         pb[0] = q[sb & 3]; pb[1] = q[(sb & 3) + 1];
-        ld4(u + (sa & ~(uint64_t)3), q);
-        pa[0] = q[sa & 1]; pa[1] = q[(sa & 1) + 2];
+        const uint64_t grp = sa & ~(uint64_t)3;
+        ld4(u + (c ? (n - 4) - grp : grp), q);
+        const int o = (int)(sa & 1) ^ c;
+        pa[0] = q[o]; pa[1] = q[o + 2];
         const double mb = mean_rd<2>(pb, shift[1], sc.q[1]);
         const double ma = mean_rd<2>(pa, shift[1], sc.q[1]);
         best.add((double)u[i], ma > mb ? ma : mb, dR_up, i);
     }
 }
 
-// sigma = 4, d = 2: all 16 head pairs (a1, b1) of x.  Branches of a
-// mismatched pair: advance b (depends on a1), advance a (depends on b1),
-// advance both (shared with the all-match value).
+// sigma = 4, d = 2: thread t < n/64 evaluates the stored coordinates
+// (0, b1)|x_m, x_m = t xor (m rep), m, b1 = 0..3.  Branches of a mismatched
+// pair: advance b (stored directly), advance a (the image of the advance-a
+// group of (0, b1 xor m)|t), advance both (the image of t's group, shared
+// with the all-match value).
 template <typename T>
-__device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int h, uint64_t x,
+__device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int h, uint64_t t,
                                       const double *shift, const Scales &sc, double dR_up,
                                       WBest &best)
 {
@@ -223,46 +237,44 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
     const uint64_t am = 0xCCCCCCCCCCCCCCCCull & (n - 1), bm = ~am & (n - 1);
     double g[16];
 #pragma unroll
-    for (int t = 0; t < 16; t += 4) ld4(u + 16 * x + t, g + t);
+    for (int k = 0; k < 16; k += 4) ld4(u + 16 * t + k, g + k);
     const double m_both = mean_rd<16>(g, shift[2], sc.q[4]);
     const double f_match = 1.0 + m_both;
-    double mb[4], ma[4];
+    double ma[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        // head slot (c, .): advance b keeps a = (c, a_2..a_h)
-        const uint64_t ib = ((uint64_t)(c << 2) << top) | x;
-        const uint64_t sb = (ib & am) | ((ib << 4) & bm);
+    for (int v = 0; v < 4; ++v) {
+        const uint64_t i = ((uint64_t)v << top) | t;
+        const uint64_t sa = ((i << 4) & am) | (i & bm);
+        double q[4] = {(double)u[sa], (double)u[sa + 4], (double)u[sa + 8], (double)u[sa + 12]};
+        ma[v] = mean_rd<4>(q, shift[1], sc.q[2]);
+    }
+    const uint64_t rep = ((n >> 4) - 1) / 3;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const uint64_t x = t ^ ((uint64_t)m * rep);
+        const uint64_t sb = (x & am) | ((x << 4) & bm);
         double q[4];
         ld4(u + sb, q);
-        mb[c] = mean_rd<4>(q, shift[1], sc.q[2]);
-        // head slot (., c): advance a keeps b = (c, b_2..b_h)
-        const uint64_t ia = ((uint64_t)c << top) | x;
-        const uint64_t sa = ((ia << 4) & am) | (ia & bm);
-        double v[4] = {(double)u[sa], (double)u[sa + 4], (double)u[sa + 8], (double)u[sa + 12]};
-        ma[c] = mean_rd<4>(v, shift[1], sc.q[2]);
-    }
+        const double mb = mean_rd<4>(q, shift[1], sc.q[2]);
+        best.add((double)u[x], f_match, dR_up, x);
 #pragma unroll
-    for (int a1 = 0; a1 < 4; ++a1)
-#pragma unroll
-        for (int b1 = 0; b1 < 4; ++b1) {
-            const uint64_t i = ((uint64_t)(a1 * 4 + b1) << top) | x;
-            double f;
-            if (a1 == b1) {
-                f = f_match;
-            } else {
-                f = mb[a1] > ma[b1] ? mb[a1] : ma[b1];
-                f = m_both > f ? m_both : f;
-            }
+        for (int b1 = 1; b1 < 4; ++b1) {
+            const uint64_t i = ((uint64_t)b1 << top) | x;
+            double f = mb > ma[b1 ^ m] ? mb : ma[b1 ^ m];
+            f = m_both > f ? m_both : f;
             best.add((double)u[i], f, dR_up, i);
         }
+    }
 }
 
-// sigma = 2, d = 3: the 8 head triples of x.  A mismatched triple has two
-// branches: the strings with head 1 advance (z = 0) and the strings with
-// head 0 advance (z = 1); k = |N| selects the lag and shift.
+// sigma = 2, d = 3: thread t < n/16 evaluates the stored head triples 000 ..
+// 011 of x = t and of its complement xc.  A mismatched triple has two
+// branches: the strings with head 1 advance (z = 0) and the strings with head
+// 0 advance (z = 1); k = |N| selects the lag and shift.  A branch that moves
+// string 1 of xc reads every value at the image of its index.
 template <int SET, typename T>
 __device__ __forceinline__ double branch23(const T *__restrict__ u, uint64_t n, uint64_t i,
-                                           const double *shift, const Scales &sc)
+                                           int img, const double *shift, const Scales &sc)
 {
     // SET: bit 2 = string 1, bit 1 = string 2, bit 0 = string 3
     constexpr int K = __builtin_popcount(SET);
@@ -270,42 +282,50 @@ __device__ __forceinline__ double branch23(const T *__restrict__ u, uint64_t n, 
     const uint64_t sm = ((SET & 4) ? r3 << 2 : 0) | ((SET & 2) ? r3 << 1 : 0) | ((SET & 1) ? r3 : 0);
     const uint64_t base = (i & ~sm) | ((i << 3) & sm & (n - 1));
     double v[K == 1 ? 2 : 4];
-    int t = 0;
+    int k = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c)  // appended tuples in lexicographic order of the moved strings
-        if ((c & ~SET) == 0) v[t++] = (double)u[base | (uint64_t)c];
+        if ((c & ~SET) == 0) {
+            const uint64_t e = base | (uint64_t)c;
+            v[k++] = (double)u[img ? (n - 1) - e : e];
+        }
     return K == 1 ? mean_rd<2>(v, shift[1], sc.q[1]) : mean_rd<4>(v, shift[2], sc.q[2]);
 }
 
 template <typename T>
-__device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int h, uint64_t x,
+__device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int h, uint64_t t,
                                       const double *shift, const Scales &sc, double dR_up,
                                       WBest &best)
 {
     const int top = 3 * (h - 1);
+    const uint64_t xc = (n >> 3) - 1 - t;
     double g[8];
-    ld4(u + 8 * x, g);
-    ld4(u + 8 * x + 4, g + 4);
+    ld4(u + 8 * t, g);
+    ld4(u + 8 * t + 4, g + 4);
     const double f_match = 1.0 + mean_rd<8>(g, shift[3], sc.q[3]);
-    best.add((double)u[x], f_match, dR_up, x);
-    const uint64_t i7 = ((uint64_t)7 << top) | x;
-    best.add((double)u[i7], f_match, dR_up, i7);
-#define LCSB_HEAD(H)                                                                      \
-    {                                                                                     \
-        const uint64_t i = ((uint64_t)(H) << top) | x;                                    \
-        const double b1 = branch23<(H), T>(u, n, i, shift, sc);      /* z = 0 */         \
-        const double b0 = branch23<(~(H)) & 7, T>(u, n, i, shift, sc); /* z = 1 */       \
-        best.add((double)u[i], b0 > b1 ? b0 : b1, dR_up, i);                              \
-    }
-    LCSB_HEAD(1) LCSB_HEAD(2) LCSB_HEAD(3) LCSB_HEAD(4) LCSB_HEAD(5) LCSB_HEAD(6)
+    best.add((double)u[t], f_match, dR_up, t);
+    best.add((double)u[xc], f_match, dR_up, xc);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t x = c ? xc : t;
+#define LCSB_HEAD(H)                                                                            \
+        {                                                                                       \
+            const uint64_t i = ((uint64_t)(H) << top) | x;                                      \
+            const double b1 = branch23<(H), T>(u, n, i, ((H) & 4) ? c : 0, shift, sc);        \
+            const double b0 = branch23<(~(H)) & 7, T>(u, n, i, ((~(H)) & 4) ? c : 0, shift,  \
+                                                      sc);                                      \
+            best.add((double)u[i], b0 > b1 ? b0 : b1, dR_up, i);                                \
+        }
+        LCSB_HEAD(1) LCSB_HEAD(2) LCSB_HEAD(3)
 #undef LCSB_HEAD
+    }
 }
 
 template <int SIGMA, int D, typename T>
 __global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u_arg, uint64_t n, int h,
                                                 unsigned char *__restrict__ ws)
 {
-    constexpr int SLOT = (SIGMA == 2 ? 1 : 2) * D;
+    constexpr int BITS = (SIGMA == 2 ? 1 : 2) * (D + 1);  // head slot and string-1 symbol 2
     const uint64_t z = round_toward_neg_inf();
     const T *__restrict__ u = u_arg + z;
     const double *sc_ws = reinterpret_cast<const double *>(ws + z);
@@ -314,13 +334,13 @@ __global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u_arg, ui
 #pragma unroll
     for (int k = 0; k < 4; ++k) shift[k] = sc_ws[Ws::kShift / 8 + k];  // (d-k)R, rounded down
     const Scales sc;
-    const uint64_t nx = n >> SLOT;
+    const uint64_t nt = n >> BITS;
     WBest best;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x; x < nx; x += stride) {
-        if constexpr (SIGMA == 2 && D == 2) w_s2d2<T>(u, n, x, shift, sc, dR_up, best);
-        else if constexpr (SIGMA == 4) w_s4d2<T>(u, n, h, x, shift, sc, dR_up, best);
-        else w_s2d3<T>(u, n, h, x, shift, sc, dR_up, best);
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < nt; t += stride) {
+        if constexpr (SIGMA == 2 && D == 2) w_s2d2<T>(u, n, t, shift, sc, dR_up, best);
+        else if constexpr (SIGMA == 4) w_s4d2<T>(u, n, h, t, shift, sc, dR_up, best);
+        else w_s2d3<T>(u, n, h, t, shift, sc, dR_up, best);
     }
     double w = best.w;
     uint64_t arg = best.arg, nonfinite = best.nonfinite;
@@ -329,6 +349,100 @@ __global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u_arg, ui
         reinterpret_cast<double *>(ws + Ws::kPartVal)[blockIdx.x] = w;
         reinterpret_cast<uint64_t *>(ws + Ws::kPartIdx)[blockIdx.x] = arg;
         reinterpret_cast<uint64_t *>(ws + Ws::kPartCnt)[blockIdx.x] = nonfinite;
+    }
+}
+
+// l = 1: each branch appends its symbols in the head slot, so its tuples
+// straddle the stored half and every value is read at the image of its
+// index.  One workgroup; thread j evaluates stored coordinate j.  Templates on
+// (sigma, d) and the moved set M keep every array in registers.
+template <int SIGMA, int D>
+struct L1 {
+    static constexpr int kBeta = SIGMA == 2 ? 1 : 2;
+    static constexpr int kN = 1 << (kBeta * D);
+    static constexpr int kNs = kN >> kBeta;
+    static constexpr int kRep = (kN - 1) / (SIGMA - 1);
+    static __device__ __forceinline__ int image(int i) { return i ^ ((i >> (kBeta * (D - 1))) * kRep); }
+    template <int M>  // head with the moved strings' symbols replaced by tuple c
+    static __device__ __forceinline__ int successor(int head, int c)
+    {
+#pragma unroll
+        for (int s = D - 1; s >= 0; --s) {
+            if (!((M >> s) & 1)) continue;
+            const int sh = kBeta * (D - 1 - s);
+            head = (head & ~((SIGMA - 1) << sh)) | ((c & (SIGMA - 1)) << sh);
+            c >>= kBeta;
+        }
+        return head;
+    }
+};
+
+// In round-toward-minus-infinity mode: the branch mean of moved set `moved`
+// (searched from M up) over u + shift_|M|, as mean_rd.
+template <typename T, int SIGMA, int D, int M>
+__device__ __forceinline__ double l1_branch_rd(const T *__restrict__ u, const double *shift,
+                                               const Scales &sc, int head, int moved)
+{
+    using G = L1<SIGMA, D>;
+    if constexpr (M >= (1 << D)) {
+        return 0.0;
+    } else {
+        if (moved != M) return l1_branch_rd<T, SIGMA, D, M + 1>(u, shift, sc, head, moved);
+        constexpr int K = __builtin_popcount(M), CNT = 1 << (G::kBeta * K);
+        double v[CNT];
+#pragma unroll
+        for (int c = 0; c < CNT; ++c) v[c] = (double)u[G::image(G::template successor<M>(head, c))];
+        return mean_rd<CNT>(v, shift[K], sc.q[G::kBeta * K]);
+    }
+}
+
+template <typename T, int SIGMA, int D>
+__global__ __launch_bounds__(kBlock) void cert_w_l1(const T *__restrict__ u_arg,
+                                                   unsigned char *__restrict__ ws)
+{
+    using G = L1<SIGMA, D>;
+    const uint64_t z = round_toward_neg_inf();
+    const T *__restrict__ u = u_arg + z;
+    const double *sc_ws = reinterpret_cast<const double *>(ws + z);
+    const double dR_up = sc_ws[Ws::kDRup / 8];
+    double shift[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) shift[k] = sc_ws[Ws::kShift / 8 + k];
+    const Scales sc;
+    WBest best;
+    const int j = threadIdx.x;
+    if (j < G::kNs) {
+        int sym[D];
+        bool same = true;
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            sym[s] = (j >> (G::kBeta * (D - 1 - s))) & (SIGMA - 1);
+            same = same && sym[s] == sym[0];
+        }
+        double f;
+        if (same) {
+            f = 1.0 + l1_branch_rd<T, SIGMA, D, 1>(u, shift, sc, j, (1 << D) - 1);
+        } else {
+            f = -INFINITY;
+#pragma unroll
+            for (int zz = 0; zz < SIGMA; ++zz) {
+                int moved = 0;
+#pragma unroll
+                for (int s = 0; s < D; ++s)
+                    if (sym[s] != zz) moved |= 1 << s;
+                const double m = l1_branch_rd<T, SIGMA, D, 1>(u, shift, sc, j, moved);
+                f = m > f ? m : f;
+            }
+        }
+        best.add((double)u[j], f, dR_up, (uint64_t)j);
+    }
+    double w = best.w;
+    uint64_t arg = best.arg, nonfinite = best.nonfinite;
+    block_reduce(w, arg, nonfinite);
+    if (threadIdx.x == 0) {
+        reinterpret_cast<double *>(ws + Ws::kPartVal)[0] = w;
+        reinterpret_cast<uint64_t *>(ws + Ws::kPartIdx)[0] = arg;
+        reinterpret_cast<uint64_t *>(ws + Ws::kPartCnt)[0] = nonfinite;
     }
 }
 
@@ -358,7 +472,15 @@ int reduce_blocks(uint64_t n)
 template <typename T>
 hipError_t launch_w(const Geometry &g, const T *u, unsigned char *ws, int nbw, hipStream_t s)
 {
-    if (g.sigma == 2 && g.d == 2)
+    if (g.h == 1 && g.sigma == 2 && g.d == 2)
+        cert_w_l1<T, 2, 2><<<1, kBlock, 0, s>>>(u, ws);
+    else if (g.h == 1 && g.sigma == 4 && g.d == 2)
+        cert_w_l1<T, 4, 2><<<1, kBlock, 0, s>>>(u, ws);
+    else if (g.h == 1 && g.sigma == 2 && g.d == 3)
+        cert_w_l1<T, 2, 3><<<1, kBlock, 0, s>>>(u, ws);
+    else if (g.h == 1)
+        return hipErrorInvalidValue;
+    else if (g.sigma == 2 && g.d == 2)
         cert_w<2, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else if (g.sigma == 4 && g.d == 2)
         cert_w<4, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
@@ -373,15 +495,16 @@ template <typename T>
 hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int u_slot,
                          int prev_slot, unsigned char *ws, hipStream_t s)
 {
-    const int nb = reduce_blocks(g.n);
+    const int nb = reduce_blocks(g.ns);
     cert_r<T><<<nb, kBlock, 0, s>>>(static_cast<const T *>(u), static_cast<const T *>(prev),
-                                     g.n, ws);
+                                     g.ns, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     cert_r_final<<<1, kBlock, 0, s>>>(ws, nb, g.d, std::is_same<T, float>::value ? 1 : 0,
                                       u_slot, prev_slot);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int nbw = reduce_blocks(g.n >> g.slot);  // one thread per x
+    // one thread per x with string-1 symbol 0 at position 2 (one workgroup at l = 1)
+    const int nbw = g.h == 1 ? 1 : reduce_blocks(g.n >> (g.slot + g.beta));
     if ((e = launch_w<T>(g, static_cast<const T *>(u), ws, nbw, s)) != hipSuccess) return e;
     cert_w_final<<<1, kBlock, 0, s>>>(ws, nbw);
     return hipGetLastError();

@@ -34,7 +34,8 @@ struct Ws {
 
 struct Geometry {
     int sigma, d, h, beta, slot;  // slot = bits per position = d * beta
-    uint64_t n;                   // sigma^(d h) entries
+    uint64_t n;                   // sigma^(d h) indices
+    uint64_t ns;                  // n / sigma stored entries: the string-1 head is 0
 };
 
 // One sweep: reads lag 1..d (ring slots lag_slot[0..d-1]), writes slot new_slot.
@@ -55,8 +56,7 @@ hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const voi
 // Utilities
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_fill_f64(double *p, uint64_t count, double v, hipStream_t s);
-hipError_t launch_project_copy(const Geometry &g, int dtype, const void *src, void *dst,
-                               hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_upcast(const Geometry &g, const float *src, const double *offset_dev,
                          double *dst, hipStream_t s);
 

@@ -69,7 +69,9 @@ __device__ __forceinline__ float input_at(uint64_t i, int h, int slot)
 // ------------------------------------------------------------------ seed orbits
 // The converged table is invariant under exchanging the two strings and under
 // complementing both (Sec. 3.3), so the seed evaluates the network once per
-// orbit of the group these generate and writes the value to every member.
+// orbit of the group these generate and writes the value to the members the
+// folded table stores (string-1 head 0: the representative and one of the
+// two members with the strings exchanged).
 // With c = a xor b, both maps fix c and act on a as a -> a xor {0, c, 1..1,
 // ~c}: an orbit is a coset of the span of 1..1 and c' (c or ~c, whichever
 // has head 0).  Its unique member with a zero bit at both pivots (a's head
@@ -82,7 +84,7 @@ __device__ __forceinline__ float input_at(uint64_t i, int h, int slot)
 //                     clear).  Sixteen consecutive t thus hold every value of
 //                     the last two symbols of both strings and, unless the
 //                     pivot is among those two positions, write one aligned
-//                     16-entry window of each orbit member;
+//                     16-entry window of each stored member;
 //   t >= 2^(2l-2):    the other half for c = 0, then for c = 1..1.
 // Count (2^l + 2) 2^(l-2) = 4^l / 4 + 2^(l-1).
 __device__ __forceinline__ uint32_t spread16(uint32_t x)  // bit k -> bit 2k
@@ -164,7 +166,7 @@ struct FwdArgs {
     float *y;                // predictions (or null)
     uint16_t *act;           // if non-null: H1, H2, H3 as BF16 [3][count][256] for backward
     void *lag1, *lag2;       // seed targets (kSrcOrbits)
-    uint64_t n;              // table entries (kSrcOrbits)
+    uint64_t n;              // indices of the unfolded table (kSrcOrbits)
     double rate;             // lag 1 = u + rate, lag 2 = u
 };
 
@@ -514,17 +516,15 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
                 if constexpr (SRC == kSrcOrbits) {
                     T *l1 = static_cast<T *>(a.lag1);
                     T *l2 = static_cast<T *>(a.lag2);
-                    const uint64_t i = sidx[b], j = swap_strings(i), m = a.n - 1;
+                    // the stored members: i and whichever of j, ~j has string-1 head 0
+                    const uint64_t i = sidx[b], j = swap_strings(i);
+                    const uint64_t js = (j & (a.n >> 1)) ? j ^ (a.n - 1) : j;
                     const T v2 = (T)u;
                     const T v1 = (T)((double)u + a.rate);
                     l2[i] = v2;
-                    l2[j] = v2;
-                    l2[i ^ m] = v2;
-                    l2[j ^ m] = v2;
+                    l2[js] = v2;
                     l1[i] = v1;
-                    l1[j] = v1;
-                    l1[i ^ m] = v1;
-                    l1[j ^ m] = v1;
+                    l1[js] = v1;
                 }
             }
         }
@@ -868,7 +868,9 @@ __global__ __launch_bounds__(256) void sample_kernel(const T *__restrict__ table
     if (s >= count) return;
     const uint64_t i = splitmix(seed, (uint64_t)s) >> (64 - bits);
     idx[s] = i;
-    target[s] = (float)((double)table[i] - (double)table[0]);
+    // the table stores the indices with string-1 head 0; i reads its complement otherwise
+    const uint64_t is = ((i >> (bits - 1)) & 1) ? i ^ ((1ull << bits) - 1) : i;
+    target[s] = (float)((double)table[is] - (double)table[0]);
 }
 
 }  // namespace

@@ -7,13 +7,22 @@
 // symbol fields up one slot and appends the new symbols in the lowest slot,
 // so every branch reads sigma^|N| entries of one aligned sigma^d group.
 //
-// Work split: one thread per x.  The thread evaluates the tuples whose
-// string-1 head is 0 (one per orbit of the symbol relabelling c -> c xor m,
-// the complement symmetry of Sec. 3.3 for sigma = 2) and stores each value
-// at all sigma members of its orbit.  Over the grid every lag table is read
-// once and the output written once: (d+1) * sizeof(T) bytes per entry for
-// d = 2 (one lag-2 group shared by all heads, the lag-1 branch groups of the
-// representatives, sigma writes per value).
+// Folded storage (Sec. 3.3): relabelling every symbol c -> c xor m leaves
+// the table unchanged (the complement of eq. (10) for sigma = 2), so a table
+// stores only the ns = n / sigma indices whose string-1 head is 0 -- the
+// lowest ns indices -- and index i is read at its image i xor (m rep), m the
+// string-1 head of i, rep the index with symbol 1 everywhere.  For l >= 2 the
+// image of an aligned group is an aligned group whose members are permuted
+// by the same xor (reversed, for sigma = 2).  Every branch sum is a balanced
+// tree over its members in order, and a xor of the member indices only swaps
+// the two operands of some of its additions, so a branch read through the
+// image gives the same bits as on the unfolded table.
+//
+// Work split (l >= 2): one thread per x whose string-1 symbol at position 2
+// is 0, which also computes the x' = x xor (m rep) of the other m (the
+// complement of x for sigma = 2): the all-advance lag-d group of x' is the
+// image of the one of x and is read once for both.  Per sweep each stored
+// lag table is then read at most twice and the output written once.
 //
 // Arithmetic (bit-exact with the FP64 reference): each branch sums its
 // sigma^k values with a balanced binary tree in lexicographic order of the
@@ -67,38 +76,31 @@ __device__ __forceinline__ void load4(const double *p, double *g)
     double2 v = reinterpret_cast<const double2 *>(p)[1];
     g[0] = u.x; g[1] = u.y; g[2] = v.x; g[3] = v.y;
 }
-// Streaming variants for the sigma = d = 2 kernel, whose lag bytes are each
-// read once per sweep: FP64 reads are non-temporal there (1.8% faster at
-// l = 16; FP32 unchanged).  The other kernels share groups between
-// representatives through L2 and keep ordinary loads (non-temporal reads
-// made their FP64 sweeps 15-55% slower).
-__device__ __forceinline__ void stream2(const double *p, double &a, double &b)
-{
-    a = __builtin_nontemporal_load(p);
-    b = __builtin_nontemporal_load(p + 1);
-}
-__device__ __forceinline__ void stream4(const double *p, double *g)
-{
-#pragma unroll
-    for (int k = 0; k < 4; ++k) g[k] = __builtin_nontemporal_load(p + k);
-}
-__device__ __forceinline__ void stream2(const float *p, float &a, float &b) { load2(p, a, b); }
 __device__ __forceinline__ void load4(const float *p, float *g)
 {
     float4 v = *reinterpret_cast<const float4 *>(p);
     g[0] = v.x; g[1] = v.y; g[2] = v.z; g[3] = v.w;
 }
-__device__ __forceinline__ void stream4(const float *p, float *g) { load4(p, g); }
+template <typename T>
+__device__ __forceinline__ void load8(const T *p, T *g)
+{
+    load4(p, g);
+    load4(p + 4, g + 4);
+}
 
 constexpr uint64_t kAlt2 = 0xAAAAAAAAAAAAAAAAull;  // high bit of every 2-bit slot
 constexpr uint64_t kAlt4Hi = 0xCCCCCCCCCCCCCCCCull; // high 2-bit field of every nibble
 
 // ---------------------------------------------------------------- sigma = 2, d = 2
-// Slot = (a bit, b bit).  Representatives: 0/0|x (all-match) and 0/1|x.
+// Slot = (a bit, b bit); stored heads 0/0 (all-match) and 0/1.
 //   0/0|x : 1 + mean(lag2[4x .. 4x+3])                         (eq. (2))
 //   0/1|x : max( mean lag1[sb], lag1[sb+1]   (advance b, z = 0),
 //                mean lag1[sa], lag1[sa+2] ) (advance a, z = 1) (Alg. 1)
-// Orbit partner of index i under the complement is n-1-i (eq. (10)).
+// Thread t < n/8 computes x = t and its complement xc = n/4-1-t.  The lag-2
+// group of xc is the image of the one of t, so 0/0|t and 0/0|xc share their
+// value.  Advance b keeps a (head 0) and reads the stored half directly;
+// advance a reads head a_2, 0 for t and 1 for xc, whose pair sa, sa+2 is then
+// read in the image group n-4-(sa & ~3) at the other parity.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
                                                     const T *__restrict__ lag2,
@@ -108,55 +110,60 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
     const uint64_t nq = n >> 2;
-    const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     T d2 = 0, y0 = 0;
     if constexpr (kF32) {
         const double o1 = off[s1];
         d2 = (float)(off[s2] - o1);
         y0 = 1.0f + (tree4(lag2[0], lag2[1], lag2[2], lag2[3]) * 0.25f + d2);
-        if (x == 0) off[snew] = o1 + (double)y0;
+        if (t == 0) off[snew] = o1 + (double)y0;
     }
-    if (x >= nq) return;
+    if (t >= (n >> 3)) return;
+    const uint64_t xc = nq - 1 - t;
 
     T g[4];
-    stream4(lag2 + 4 * x, g);
+    load4(lag2 + 4 * t, g);
     T m2 = tree4(g[0], g[1], g[2], g[3]) * (T)0.25;
     if constexpr (kF32) m2 = m2 + d2;
     const T match = (T)1 + m2;
 
     const uint64_t am = kAlt2 & (n - 1), bm = ~kAlt2 & (n - 1);
-    const uint64_t i = nq + x;
-    const uint64_t sb = (i & am) | ((i << 2) & bm);
-    const uint64_t sa = ((i << 2) & am) | (i & bm);
-    T b0, b1;
-    stream2(lag1 + sb, b0, b1);
-    const T mb = (b0 + b1) * (T)0.5;
-    // the advance-a pair sa, sa+2 is the even or odd half of the aligned
-    // group sa & ~3, which the neighbouring thread (x ^ 1) also reads: one
-    // vector load of the group serves both
-    T q[4];
-    stream4(lag1 + (sa & ~(uint64_t)3), q);
-    const T ma = ((sa & 1) ? (q[1] + q[3]) : (q[0] + q[2])) * (T)0.5;
-    const T mis = vmax(mb, ma);
-
-    if constexpr (kF32) {
-        put(out + x, match - y0);
-        put(out + (n - 1 - x), match - y0);
-        put(out + i, mis - y0);
-        put(out + (n - 1 - i), mis - y0);
-    } else {
-        put(out + x, match);
-        put(out + (n - 1 - x), match);
-        put(out + i, mis);
-        put(out + (n - 1 - i), mis);
+    T mis[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t i = nq + (c ? xc : t);
+        const uint64_t sb = (i & am) | ((i << 2) & bm);
+        const uint64_t sa = ((i << 2) & am) | (i & bm);
+        T b0, b1;
+        load2(lag1 + sb, b0, b1);
+        const T mb = (b0 + b1) * (T)0.5;
+        // the advance-a pair is the even or odd half of an aligned group that
+        // the neighbouring thread (t ^ 1) also reads: one vector load serves both
+        T q[4];
+        const uint64_t grp = sa & ~(uint64_t)3;
+        load4(lag1 + (c ? (n - 4) - grp : grp), q);
+        const int o = (int)(sa & 1) ^ c;
+        const T ma = (q[o] + q[o + 2]) * (T)0.5;
+        mis[c] = vmax(mb, ma);
     }
+
+    put(out + t, kF32 ? (T)(match - y0) : match);
+    put(out + xc, kF32 ? (T)(match - y0) : match);
+    put(out + nq + t, kF32 ? (T)(mis[0] - y0) : mis[0]);
+    put(out + nq + xc, kF32 ? (T)(mis[1] - y0) : mis[1]);
 }
 
 // ---------------------------------------------------------------- sigma = 4, d = 2
-// Slot = (a: 2 bits, b: 2 bits).  Representatives (0, b1)|x, b1 = 0..3.
+// Slot = (a: 2 bits, b: 2 bits); stored heads (0, b1), b1 = 0..3.
 // Branches of (0, b1), b1 != 0: z = 0 advances b (lag 1), z = b1 advances a
 // (lag 1), the two other z advance both (lag 2, the same group as the
-// all-match representative).  Orbit: xor every 2-bit symbol with m.
+// all-match tuple).  Thread t < n/64 owns x = t (string-1 symbol 0 at
+// position 2) and its images x_m = x xor (m rep), m = 0..3:
+//   - advance both: the lag-2 group of x_m is the image of the one of x;
+//   - advance b keeps string 1 (head 0): stored directly;
+//   - advance a of (0, b1)|x_m reads string-1 head m; its image is the
+//     advance-a group of (0, b1 xor m)|x, so four means ma[v] serve all
+//     twelve mismatched tuples.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
                                                     const T *__restrict__ lag2,
@@ -165,60 +172,61 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
                                                     int snew)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
-    const uint64_t ng = n >> 4;
-    const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const int top = 4 * (h - 1);
     T d2 = 0, y0 = 0;
     if constexpr (kF32) {
         const double o1 = off[s1];
         d2 = (float)(off[s2] - o1);
         T g0[16];
-        for (int t = 0; t < 16; t += 4) load4(lag2 + t, g0 + t);
+        for (int k = 0; k < 16; k += 4) load4(lag2 + k, g0 + k);
         y0 = 1.0f + (tree16(g0) * 0.0625f + d2);
-        if (x == 0) off[snew] = o1 + (double)y0;
+        if (t == 0) off[snew] = o1 + (double)y0;
     }
-    if (x >= ng) return;
+    if (t >= (n >> 6)) return;
 
     T g[16];
 #pragma unroll
-    for (int t = 0; t < 16; t += 4) load4(lag2 + 16 * x + t, g + t);
+    for (int k = 0; k < 16; k += 4) load4(lag2 + 16 * t + k, g + k);
     T both = tree16(g) * (T)0.0625;
     if constexpr (kF32) both = both + d2;
+    const T match = (T)1 + both;
 
     const uint64_t am = kAlt4Hi & (n - 1), bm = ~kAlt4Hi & (n - 1);
-    const uint64_t sb = (x & am) | ((x << 4) & bm);
-    T bv[4];
-    load4(lag1 + sb, bv);
-    const T mb = tree4(bv[0], bv[1], bv[2], bv[3]) * (T)0.25;
-    const uint64_t sa0 = ((x << 4) & am) | (x & bm);
-
-    T val[4];
-    val[0] = (T)1 + both;
+    T ma[4];
 #pragma unroll
-    for (int b1 = 1; b1 < 4; ++b1) {
-        const uint64_t sa = sa0 | ((uint64_t)b1 << top);
-        const T ma = tree4(lag1[sa], lag1[sa + 4], lag1[sa + 8], lag1[sa + 12]) * (T)0.25;
-        T best = mb;                                     // z = 0
-#pragma unroll
-        for (int z = 1; z < 4; ++z) best = vmax(best, z == b1 ? ma : both);
-        val[b1] = best;
+    for (int v = 0; v < 4; ++v) {
+        const uint64_t i = ((uint64_t)v << top) | t;
+        const uint64_t sa = ((i << 4) & am) | (i & bm);
+        ma[v] = tree4(lag1[sa], lag1[sa + 4], lag1[sa + 8], lag1[sa + 12]) * (T)0.25;
     }
-    const uint64_t rep = (n - 1) / 3;  // 01 in every 2-bit field
+    const uint64_t rep = ((n >> 4) - 1) / 3;  // symbol 1 at every position of x
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const uint64_t i = ((uint64_t)r << top) | x;
-        const T v = kF32 ? (T)(val[r] - y0) : val[r];
+    for (int m = 0; m < 4; ++m) {
+        const uint64_t x = t ^ ((uint64_t)m * rep);
+        const uint64_t sb = (x & am) | ((x << 4) & bm);
+        T bv[4];
+        load4(lag1 + sb, bv);
+        const T mb = tree4(bv[0], bv[1], bv[2], bv[3]) * (T)0.25;
+        put(out + x, kF32 ? (T)(match - y0) : match);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) put(out + (i ^ ((uint64_t)m * rep)), v);
+        for (int b1 = 1; b1 < 4; ++b1) {
+            T best = mb;                                     // z = 0
+#pragma unroll
+            for (int z = 1; z < 4; ++z) best = vmax(best, z == b1 ? ma[b1 ^ m] : both);
+            put(out + (((uint64_t)b1 << top) | x), kF32 ? (T)(best - y0) : best);
+        }
     }
 }
 
 // ---------------------------------------------------------------- sigma = 2, d = 3
-// Slot = (s1, s2, s3) bits.  Representatives 000|x (all-match), 001|x,
-// 010|x, 011|x.  Each mismatch representative has one branch moving the
-// single string whose head differs (lag 1) and one moving the other two
-// (lag 2):  001: z=0 -> {3}, z=1 -> {1,2};  010: z=0 -> {2}, z=1 -> {1,3};
-// 011: z=0 -> {2,3}, z=1 -> {1}.  Orbit partner: n-1-i.
+// Slot = (s1, s2, s3) bits; stored heads 000 (all-match), 001, 010, 011.
+// Each mismatched tuple has one branch moving the single string whose head
+// differs (lag 1) and one moving the other two (lag 2):  001: z=0 -> {3},
+// z=1 -> {1,2};  010: z=0 -> {2}, z=1 -> {1,3};  011: z=0 -> {2,3},
+// z=1 -> {1}.  Thread t < n/16 computes x = t and its complement xc; a
+// branch that moves string 1 reads head s1_2, which is 1 for xc, and then
+// reads the image group, whose members are the reversed originals.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
                                                     const T *__restrict__ lag2,
@@ -228,8 +236,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
                                                     int s3, int snew)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
-    const uint64_t ng = n >> 3;
-    const uint64_t x = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const int top = 3 * (h - 1);
     T d2 = 0, d3 = 0, y0 = 0;
     if constexpr (kF32) {
@@ -237,77 +244,186 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
         d2 = (float)(off[s2] - o1);
         d3 = (float)(off[s3] - o1);
         T g0[8];
-        load4(lag3, g0);
-        load4(lag3 + 4, g0 + 4);
+        load8(lag3, g0);
         y0 = 1.0f + (tree8(g0) * 0.125f + d3);
-        if (x == 0) off[snew] = o1 + (double)y0;
+        if (t == 0) off[snew] = o1 + (double)y0;
     }
-    if (x >= ng) return;
+    if (t >= (n >> 4)) return;
+    const uint64_t xc = (n >> 3) - 1 - t;
 
     T g[8];
-    load4(lag3 + 8 * x, g);
-    load4(lag3 + 8 * x + 4, g + 4);
+    load8(lag3 + 8 * t, g);
     T all3 = tree8(g) * (T)0.125;
     if constexpr (kF32) all3 = all3 + d3;
+    const T match = (T)1 + all3;
 
     const uint64_t mask = n - 1;
     const uint64_t r3 = mask / 7;  // 001 in every slot
     const uint64_t S1 = r3 << 2, S2 = r3 << 1, S3 = r3;
     auto base = [&](uint64_t i, uint64_t sm) { return (i & ~sm) | ((i << 3) & sm & mask); };
+    // the aligned 8-group holding entry e, or its image
+    auto group = [&](const T *tab, uint64_t e, int img, T *q) {
+        const uint64_t grp = e & ~(uint64_t)7;
+        load8(tab + (img ? (mask - 7) - grp : grp), q);
+    };
 
-    T val[4];
-    val[0] = (T)1 + all3;
-    {   // 001
-        const uint64_t i = ((uint64_t)1 << top) | x;
-        const uint64_t b1 = base(i, S3), b2 = base(i, S1 | S2);
-        T p0, p1;
-        load2(lag1 + b1, p0, p1);
-        const T k1 = (p0 + p1) * (T)0.5;
-        // entries b2 + 0, 2, 4, 6: the even or odd half of the aligned group
-        // b2 & ~7, whose other half another thread of the wave reads
-        T q[8];
-        load4(lag2 + (b2 & ~(uint64_t)7), q);
-        load4(lag2 + (b2 & ~(uint64_t)7) + 4, q + 4);
-        const int o = (int)(b2 & 1);
-        T k2 = tree4(q[o], q[o + 2], q[o + 4], q[o + 6]) * (T)0.25;
-        if constexpr (kF32) k2 = k2 + d2;
-        val[1] = vmax(k1, k2);
-    }
-    {   // 010
-        const uint64_t i = ((uint64_t)2 << top) | x;
-        const uint64_t b1 = base(i, S2), b2 = base(i, S1 | S3);
-        T e[8];  // entries b1, b1 + 2 from their aligned group
-        load4(lag1 + (b1 & ~(uint64_t)7), e);
-        load4(lag1 + (b1 & ~(uint64_t)7) + 4, e + 4);
-        const int o = (int)(b1 & 7);
-        const T k1 = (e[o] + e[o + 2]) * (T)0.5;
-        T q0, q1, q2, q3;
-        load2(lag2 + b2, q0, q1);
-        load2(lag2 + b2 + 4, q2, q3);
-        T k2 = tree4(q0, q1, q2, q3) * (T)0.25;
-        if constexpr (kF32) k2 = k2 + d2;
-        val[2] = vmax(k1, k2);
-    }
-    {   // 011
-        const uint64_t i = ((uint64_t)3 << top) | x;
-        const uint64_t b2 = base(i, S2 | S3), b1 = base(i, S1);
-        T q[4];
-        load4(lag2 + b2, q);
-        T k2 = tree4(q[0], q[1], q[2], q[3]) * (T)0.25;
-        if constexpr (kF32) k2 = k2 + d2;
-        T e[8];  // entries b1, b1 + 4 from their aligned group
-        load4(lag1 + (b1 & ~(uint64_t)7), e);
-        load4(lag1 + (b1 & ~(uint64_t)7) + 4, e + 4);
-        const int o = (int)(b1 & 7);
-        const T k1 = (e[o] + e[o + 4]) * (T)0.5;
-        val[3] = vmax(k2, k1);
-    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const uint64_t i = ((uint64_t)r << top) | x;
-        const T v = kF32 ? (T)(val[r] - y0) : val[r];
-        put(out + i, v);
-        put(out + (mask - i), v);
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t x = c ? xc : t;
+        T val[4];
+        val[0] = match;
+        {   // 001: lag 1 entries b1, b1 + 1; lag 2 entries b2 + 0, 2, 4, 6
+            const uint64_t i = ((uint64_t)1 << top) | x;
+            const uint64_t b1 = base(i, S3), b2 = base(i, S1 | S2);
+            T p0, p1;
+            load2(lag1 + b1, p0, p1);
+            const T k1 = (p0 + p1) * (T)0.5;
+            T q[8];
+            group(lag2, b2, c, q);
+            const int o = (int)(b2 & 1) ^ c;
+            T k2 = tree4(q[o], q[o + 2], q[o + 4], q[o + 6]) * (T)0.25;
+            if constexpr (kF32) k2 = k2 + d2;
+            val[1] = vmax(k1, k2);
+        }
+        {   // 010: lag 1 entries b1, b1 + 2; lag 2 entries b2 + 0, 1, 4, 5
+            const uint64_t i = ((uint64_t)2 << top) | x;
+            const uint64_t b1 = base(i, S2), b2 = base(i, S1 | S3);
+            T e[8];
+            group(lag1, b1, 0, e);
+            const int o = (int)(b1 & 7);
+            const T k1 = (e[o] + e[o + 2]) * (T)0.5;
+            T q[8];
+            group(lag2, b2, c, q);
+            const int o2 = c ? 2 - (int)(b2 & 7) : (int)(b2 & 7);
+            T k2 = tree4(q[o2], q[o2 + 1], q[o2 + 4], q[o2 + 5]) * (T)0.25;
+            if constexpr (kF32) k2 = k2 + d2;
+            val[2] = vmax(k1, k2);
+        }
+        {   // 011: lag 2 entries b2 + 0..3; lag 1 entries b1, b1 + 4
+            const uint64_t i = ((uint64_t)3 << top) | x;
+            const uint64_t b2 = base(i, S2 | S3), b1 = base(i, S1);
+            T q[4];
+            load4(lag2 + b2, q);
+            T k2 = tree4(q[0], q[1], q[2], q[3]) * (T)0.25;
+            if constexpr (kF32) k2 = k2 + d2;
+            T e[8];
+            group(lag1, b1, c, e);
+            const int o = c ? 3 - (int)(b1 & 7) : (int)(b1 & 7);
+            const T k1 = (e[o] + e[o + 4]) * (T)0.5;
+            val[3] = vmax(k2, k1);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            put(out + (((uint64_t)r << top) | x), kF32 ? (T)(val[r] - y0) : val[r]);
+    }
+}
+
+// ---------------------------------------------------------------- l = 1
+// Every tuple is its head slot and each branch appends its symbols in that
+// slot, so a branch group straddles the stored half: every value is read at
+// the image of its index.  One workgroup; thread j computes stored entry j.
+// Templates on (sigma, d) and the moved set M keep every array in registers.
+template <int SIGMA, int D>
+struct L1 {
+    static constexpr int kBeta = SIGMA == 2 ? 1 : 2;
+    static constexpr int kN = 1 << (kBeta * D);
+    static constexpr int kNs = kN >> kBeta;
+    static constexpr int kRep = (kN - 1) / (SIGMA - 1);
+    static __device__ __forceinline__ int image(int i) { return i ^ ((i >> (kBeta * (D - 1))) * kRep); }
+    // head with the symbols of the strings in M replaced by appended tuple c
+    // (lexicographic, first moved string most significant)
+    template <int M>
+    static __device__ __forceinline__ int successor(int head, int c)
+    {
+#pragma unroll
+        for (int s = D - 1; s >= 0; --s) {
+            if (!((M >> s) & 1)) continue;
+            const int sh = kBeta * (D - 1 - s);
+            head = (head & ~((SIGMA - 1) << sh)) | ((c & (SIGMA - 1)) << sh);
+            c >>= kBeta;
+        }
+        return head;
+    }
+};
+
+template <typename T, int CNT>
+__device__ __forceinline__ T tree_pow2(T *v)  // the balanced tree over CNT = 2^k values
+{
+#pragma unroll
+    for (int step = 1; step < CNT; step <<= 1)
+#pragma unroll
+        for (int k = 0; k < CNT; k += 2 * step) v[k] = v[k] + v[k + step];
+    return v[0];
+}
+
+// mean of lag |M| over the successors of `head` for moved set M, FP32 tables
+// shifted by delta_|M|; the mean of the set `moved` when M reaches it
+template <typename T, int SIGMA, int D, int M>
+__device__ __forceinline__ T l1_branch(const T *const *lag, const T *delta, int head, int moved)
+{
+    using G = L1<SIGMA, D>;
+    if constexpr (M >= (1 << D)) {
+        return (T)0;
+    } else {
+        if (moved != M) return l1_branch<T, SIGMA, D, M + 1>(lag, delta, head, moved);
+        constexpr int K = __builtin_popcount(M), CNT = 1 << (G::kBeta * K);
+        T v[CNT];
+#pragma unroll
+        for (int c = 0; c < CNT; ++c) v[c] = lag[K - 1][G::image(G::template successor<M>(head, c))];
+        T m = tree_pow2<T, CNT>(v) * ((T)1 / (T)CNT);
+        if (std::is_same<T, float>::value && K >= 2) m = m + delta[K - 1];
+        return m;
+    }
+}
+
+template <typename T, int SIGMA, int D>
+__device__ __forceinline__ T l1_value(const T *const *lag, const T *delta, int head)
+{
+    constexpr int kBeta = L1<SIGMA, D>::kBeta;
+    int sym[D];
+    bool same = true;
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+        sym[s] = (head >> (kBeta * (D - 1 - s))) & (SIGMA - 1);
+        same = same && sym[s] == sym[0];
+    }
+    if (same) return (T)1 + l1_branch<T, SIGMA, D, 1>(lag, delta, head, (1 << D) - 1);
+    T best = 0;
+#pragma unroll
+    for (int z = 0; z < SIGMA; ++z) {
+        int moved = 0;
+#pragma unroll
+        for (int s = 0; s < D; ++s)
+            if (sym[s] != z) moved |= 1 << s;
+        const T m = l1_branch<T, SIGMA, D, 1>(lag, delta, head, moved);
+        best = z == 0 ? m : vmax(best, m);
+    }
+    return best;
+}
+
+template <typename T, int SIGMA, int D>
+__global__ __launch_bounds__(kBlock) void sweep_l1(const T *__restrict__ lag1,
+                                                  const T *__restrict__ lag2,
+                                                  const T *__restrict__ lag3,
+                                                  T *__restrict__ out,
+                                                  double *__restrict__ off, int s1, int s2,
+                                                  int s3, int snew)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    const T *lag[3] = {lag1, lag2, lag3};
+    T delta[3] = {0, 0, 0};
+    double o1 = 0.0;
+    if constexpr (kF32) {
+        o1 = off[s1];
+        delta[1] = (float)(off[s2] - o1);
+        if (D == 3) delta[2] = (float)(off[s3] - o1);
+    }
+    const T y0 = kF32 ? l1_value<T, SIGMA, D>(lag, delta, 0) : (T)0;
+    const int j = threadIdx.x;
+    if (kF32 && j == 0) off[snew] = o1 + (double)y0;
+    if (j < L1<SIGMA, D>::kNs) {
+        const T v = l1_value<T, SIGMA, D>(lag, delta, j);
+        out[j] = kF32 ? (T)(v - y0) : v;
     }
 }
 
@@ -316,9 +432,26 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
 {
     const T *l1 = static_cast<const T *>(a.lag[0]);
     const T *l2 = static_cast<const T *>(a.lag[1]);
+    const T *l3 = g.d == 3 ? static_cast<const T *>(a.lag[2]) : nullptr;
     T *out = static_cast<T *>(a.out);
-    const uint64_t groups = g.n >> g.slot;  // one thread per x
-    const uint64_t blocks = (groups + kBlock - 1) / kBlock;
+    if (g.h == 1) {
+        const int s3 = g.d == 3 ? a.lag_slot[2] : 0;
+        if (g.sigma == 2 && g.d == 2)
+            sweep_l1<T, 2, 2><<<1, kBlock, 0, s>>>(l1, l2, l3, out, a.offsets, a.lag_slot[0],
+                                                   a.lag_slot[1], s3, a.new_slot);
+        else if (g.sigma == 4 && g.d == 2)
+            sweep_l1<T, 4, 2><<<1, kBlock, 0, s>>>(l1, l2, l3, out, a.offsets, a.lag_slot[0],
+                                                   a.lag_slot[1], s3, a.new_slot);
+        else if (g.sigma == 2 && g.d == 3)
+            sweep_l1<T, 2, 3><<<1, kBlock, 0, s>>>(l1, l2, l3, out, a.offsets, a.lag_slot[0],
+                                                   a.lag_slot[1], s3, a.new_slot);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
+    // one thread per x with string-1 symbol 0 at position 2
+    const uint64_t threads = g.n >> (g.slot + g.beta);
+    const uint64_t blocks = (threads + kBlock - 1) / kBlock;
     if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)blocks), block(kBlock);
     if (g.sigma == 2 && g.d == 2) {
@@ -328,7 +461,6 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
         sweep_s4d2<T><<<grid, block, 0, s>>>(l1, l2, out, g.n, g.h, a.offsets, a.lag_slot[0],
                                               a.lag_slot[1], a.new_slot);
     } else if (g.sigma == 2 && g.d == 3) {
-        const T *l3 = static_cast<const T *>(a.lag[2]);
         sweep_s2d3<T><<<grid, block, 0, s>>>(l1, l2, l3, out, g.n, g.h, a.offsets,
                                               a.lag_slot[0], a.lag_slot[1], a.lag_slot[2],
                                               a.new_slot);

@@ -1,6 +1,5 @@
-// Small device kernels around the sweep: clearing, loading a ring with the
-// symbol-relabelling symmetry enforced, and FP32 -> FP64 conversion for the
-// FP64 polish.  Fill kernels stand in for hipMemsetAsync so that the calls
+// Small device kernels around the sweep: clearing, copying a ring in, and
+// FP32 -> FP64 conversion for the FP64 polish.  Fill kernels stand in for hipMemsetAsync so that the calls
 // stay valid inside captured HIP graphs.
 #include "internal.h"
 
@@ -27,19 +26,18 @@ __global__ __launch_bounds__(kBlock) void fill_f64_kernel(double *__restrict__ p
     for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < count; j += stride) p[j] = v;
 }
 
-// dst[i] = src[representative of i]: the representative has string-1 head 0
-// and is reached by xor-ing every symbol with the string-1 head of i.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void project_copy(const T *__restrict__ src,
-                                                       T *__restrict__ dst, uint64_t n,
-                                                       int head_shift, uint64_t sym_mask,
-                                                       uint64_t sym_rep)
+// dst[0 .. words) = src[0 .. words); 16-byte vectors when both are aligned
+__global__ __launch_bounds__(kBlock) void copy_u32(const uint32_t *__restrict__ src,
+                                                   uint32_t *__restrict__ dst, uint64_t words,
+                                                   int vec)
 {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
-        const uint64_t m = (i >> head_shift) & sym_mask;
-        dst[i] = src[i ^ (m * sym_rep)];
-    }
+    const uint64_t quads = vec ? words >> 2 : 0;
+    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < quads; j += stride)
+        reinterpret_cast<uint4 *>(dst)[j] = reinterpret_cast<const uint4 *>(src)[j];
+    for (uint64_t j = (quads << 2) + (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < words;
+         j += stride)
+        dst[j] = src[j];
 }
 
 __global__ __launch_bounds__(kBlock) void upcast_kernel(const float *__restrict__ src,
@@ -76,27 +74,20 @@ hipError_t launch_fill_f64(double *p, uint64_t count, double v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_project_copy(const Geometry &g, int dtype, const void *src, void *dst,
-                               hipStream_t s)
+hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s)
 {
-    const int head_shift = g.slot * (g.h - 1) + g.beta * (g.d - 1);
-    const uint64_t sym_mask = (uint64_t)g.sigma - 1;
-    const uint64_t sym_rep = (g.n - 1) / sym_mask;  // 1 in the lowest bit of every symbol
-    if (dtype == LCSB_F32)
-        project_copy<float><<<grid_for(g.n), kBlock, 0, s>>>(
-            static_cast<const float *>(src), static_cast<float *>(dst), g.n, head_shift,
-            sym_mask, sym_rep);
-    else
-        project_copy<double><<<grid_for(g.n), kBlock, 0, s>>>(
-            static_cast<const double *>(src), static_cast<double *>(dst), g.n, head_shift,
-            sym_mask, sym_rep);
+    if (bytes % 4 || ((uintptr_t)src & 3) || ((uintptr_t)dst & 3)) return hipErrorInvalidValue;
+    const uint64_t words = bytes / 4;
+    const int vec = (((uintptr_t)src | (uintptr_t)dst) & 15) == 0;
+    copy_u32<<<grid_for(vec ? words / 4 : words), kBlock, 0, s>>>(
+        static_cast<const uint32_t *>(src), static_cast<uint32_t *>(dst), words, vec);
     return hipGetLastError();
 }
 
 hipError_t launch_upcast(const Geometry &g, const float *src, const double *offset_dev,
                          double *dst, hipStream_t s)
 {
-    upcast_kernel<<<grid_for(g.n), kBlock, 0, s>>>(src, offset_dev, dst, g.n);
+    upcast_kernel<<<grid_for(g.ns), kBlock, 0, s>>>(src, offset_dev, dst, g.ns);
     return hipGetLastError();
 }
 

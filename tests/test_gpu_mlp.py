@@ -129,14 +129,17 @@ def test_adam_step_matches_reference(pk):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_sample_draws_in_range_and_gathers_targets(pk, dtype):
+    """Sampling from a folded table (the 4^h / 2 stored entries) gathers the
+    value of every drawn index, also those read at their complement."""
     h = 9
-    table = si.table(2, 2, h, seed=33, dtype=dtype).cuda()
+    full = si.table(2, 2, h, seed=33, dtype=dtype)
+    table = full[:4 ** h // 2].cuda()
     M = pk.Mlp(batch=4096)
     M.sample(table, h, seed=1)
     idx = M.idx.cpu().numpy()
     assert idx.min() >= 0 and idx.max() < 4 ** h
-    assert len(np.unique(idx)) > 3000
-    tab = table.cpu().numpy().astype(np.float64)
+    assert len(np.unique(idx)) > 3000 and (idx >= 4 ** h // 2).sum() > 1000
+    tab = full.numpy().astype(np.float64)
     assert np.array_equal(M.target.cpu().numpy(), (tab[idx] - tab[0]).astype(np.float32))
 
 
@@ -180,11 +183,13 @@ def test_training_reduces_the_loss_and_seed_is_consistent(pk):
     S.init_seed_mlp(M, rate=R)
     lag2 = S.lag(2)[0].cpu()
     lag1 = S.lag(1)[0].cpu()
+    assert lag2.numel() == n // 2
     assert not torch.isnan(lag2).any() and not torch.isnan(lag1).any()
     i = np.arange(n, dtype=np.uint64)
     j = _swap_strings(i)
     m = np.uint64(n - 1)
-    l2 = lag2.numpy()
+    stored = si.representative(torch.arange(n, dtype=torch.int64), 2, 2, h).numpy()
+    l2 = lag2.numpy()[stored]  # every index, read at its stored representative
     assert np.array_equal(l2, l2[j.astype(np.int64)])
     assert np.array_equal(l2, l2[(i ^ m).astype(np.int64)])
     y = torch.empty(n, dtype=torch.float32, device="cuda")

@@ -70,6 +70,8 @@ def parse():
     p.add_argument("--profile-train", type=int, default=0,
                    help="only generate the warm-start training tables and run this many steps")
     p.add_argument("--train-batch", type=int, default=8192, help="batch of --profile-train")
+    p.add_argument("--converge", type=int, default=0, metavar="L",
+                   help="only run the plain FP64 iteration at sigma = d = 2, l = L to convergence")
     p.add_argument("--profile-certify", action="store_true",
                    help="only run 8 sweeps from zero and two certificates (counter collection)")
     return p.parse_args()
@@ -440,6 +442,36 @@ def train_only(pk, h, steps, batch=8192):
         f"{flop / dt / 1e12:.1f} TFLOP/s, last loss {M.loss_dev.item():.3e}")
 
 
+def converge_only(pk, h):
+    """Plain FP64 iteration at sigma = d = 2, l = h from zero, a certificate
+    every TTB_CADENCE sweeps, until consecutive certificates move by less than
+    1e-10; prints the best certified bound, rounded down at the 6th decimal
+    as Table 2 prints it."""
+    import torch
+    P = pk.Lcsb(2, 2, h, "f64")
+    log(f"plain FP64 at l={h}: {P.n} indices, {P.stored} stored, "
+        f"{3 * 8 * P.stored / 2**30:.0f} GiB ring")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.init_zero()
+    prev = None
+    while True:
+        P.iterate(TTB_CADENCE)
+        cur, best = P.certify()
+        log(f"sweep {cur['sweep']}: bound {cur['bound']:.12f} best {best['bound']:.12f} "
+            f"({time.perf_counter() - t0:.2f} s)")
+        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
+            break
+        prev = cur["bound"]
+        if cur["sweep"] >= MAX_SWEEPS:
+            break
+    seconds = time.perf_counter() - t0
+    b = best["bound"]
+    print(json.dumps({"sigma": 2, "d": 2, "l": h, "indices": P.n, "stored": P.stored,
+                      "bound": b, "floor6": math.floor(b * 1e6) / 1e6, "sweeps": cur["sweep"],
+                      "best_sweep": best["sweep"], "seconds": round(seconds, 3)}), flush=True)
+
+
 def certify_only(pk, h, sigma=2, d=2, dtype="f32"):
     """8 sweeps from zero at (sigma, d, l = h), then two certificates."""
     import torch
@@ -483,6 +515,8 @@ def main():
         return copy_only(args.copy_gib)
     if args.profile_seed:
         return seed_only(pk, args.h)
+    if args.converge:
+        return converge_only(pk, args.converge)
     if args.profile_certify:
         return certify_only(pk, args.h, args.sigma, args.d, args.dtype)
     if args.profile_train:

@@ -192,8 +192,8 @@ def test_fp64_h14_sampled_sweep_and_certificate(pk):
 
 
 def test_fp64_h16_sampled_sweep_and_certificate(pk):
-    """The largest FP64 table: sigma = d = 2, l = 16, 2^32 entries (32 GiB)
-    per table, as the time-to-bound runs use it.  One sweep from a seeded
+    """The l = 16 FP64 ring: sigma = d = 2, 2^32 indices, 2^31 stored entries
+    (16 GiB) per table, as the time-to-bound runs use it.  One sweep from a seeded
     ring, bit-identical to the oracle at 20000 sampled coordinates; the
     certificate of the seeded ring: R over the whole table, W at its argmax
     and at the samples."""

@@ -151,7 +151,12 @@ int lcsb_status(const lcsb_ctx *ctx, int64_t *sweeps, lcsb_cert *best);
 /* Copy the ring of an LCSB_F32 context into an LCSB_F64 context of the same
  * (sigma, d, h) as FP64 values offset + stored value (the switch from FP32
  * sweeps to an FP64 polish).  The sweep count and best certificate move with
- * it.  Enqueued on dst's stream after synchronising src's. */
+ * it.  Enqueued on dst's stream after synchronising src's.  The two rings are
+ * either disjoint, or src was bound to dst's own buffers slot for slot (each
+ * FP32 table in the first half of its FP64 buffer): then every table is
+ * widened in place and src's tables are consumed, so one FP64 ring of memory
+ * serves both precisions.  Any other sharing of buffers, or a shared
+ * workspace, gives LCSB_EINVAL. */
 int lcsb_upcast(const lcsb_ctx *src_f32, lcsb_ctx *dst_f64);
 
 /* ------------------------------------------------------------------------

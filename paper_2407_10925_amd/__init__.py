@@ -29,7 +29,12 @@ class Lcsb:
     upcast, destroy.
     """
 
-    def __init__(self, sigma: int, d: int, h: int, dtype: str = "f64", device=None):
+    def __init__(self, sigma: int, d: int, h: int, dtype: str = "f64", device=None,
+                 bufs=None):
+        """``bufs``: optional ring buffers to bind instead of allocating, d + 1
+        contiguous device tensors of at least the ring's bytes each (for an FP32
+        ring inside an FP64 ring's memory, ``[b.view(torch.float32) for b in
+        P.bufs]``; see :meth:`upcast`)."""
         import torch
 
         if dtype not in _DTYPES:
@@ -51,8 +56,16 @@ class Lcsb:
         self.n = sigma ** (d * h)
         tdt = torch.float64 if dtype == "f64" else torch.float32
         self.torch_dtype = tdt
-        self.bufs = [torch.empty(self.stored, dtype=tdt, device=self.device)
-                     for _ in range(self.nbuf)]
+        if bufs is None:
+            self.bufs = [torch.empty(self.stored, dtype=tdt, device=self.device)
+                         for _ in range(self.nbuf)]
+        else:
+            if len(bufs) != self.nbuf or any(
+                    b.dtype != tdt or b.numel() < self.stored or not b.is_contiguous()
+                    or b.device != self.device for b in bufs):
+                raise ValueError(f"need {self.nbuf} contiguous {tdt} device buffers of at least "
+                                 f"{self.stored} elements")
+            self.bufs = [b[:self.stored] for b in bufs]
         self.ws = torch.empty(wsb.value, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         ptrs = (C.c_void_p * self.nbuf)(*[b.data_ptr() for b in self.bufs])
@@ -111,7 +124,8 @@ class Lcsb:
                                            C.c_void_p(mlp.wbf16.data_ptr()), float(rate)))
 
     def upcast(self, src: "Lcsb"):
-        """Fill this FP64 ring from the FP32 ring ``src`` (FP64 polish)."""
+        """Fill this FP64 ring from the FP32 ring ``src`` (FP64 polish); in place
+        when ``src`` was bound to this ring's buffers."""
         check(self._lib.lcsb_upcast(src._ctx, self._ctx))
 
     def destroy(self):

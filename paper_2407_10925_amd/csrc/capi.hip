@@ -291,6 +291,15 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
         return fail(LCSB_EINVAL, "upcast goes from an FP32 to an FP64 context");
     if (src->g.sigma != dst->g.sigma || src->g.d != dst->g.d || src->g.h != dst->g.h)
         return fail(LCSB_EINVAL, "shape mismatch");
+    // every destination slot is either the source slot's own buffer (widened
+    // in place) or no source slot's buffer
+    const bool inplace = dst->buf[0] == src->buf[0];
+    for (int j = 0; j < dst->nbuf; ++j)
+        for (int k = 0; k < src->nbuf; ++k)
+            if ((dst->buf[j] == src->buf[k]) != (inplace && j == k))
+                return fail(LCSB_EINVAL, "destination buffers must be the source's, slot for slot, "
+                                         "or none of them");
+    if (dst->ws == src->ws) return fail(LCSB_EINVAL, "the two contexts share a workspace");
     hipError_t e = hipStreamSynchronize(src->stream);
     if (e != hipSuccess) return fail(LCSB_EHIP, "source sync: %s", hipGetErrorString(e));
     if ((e = launch_fill_zero(dst->ws, Ws::kBytes, dst->stream)) != hipSuccess)
@@ -299,9 +308,10 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
     for (int k = 1; k <= src->g.d; ++k) {
         const int slot = slot_of_lag(src, k);
         const double *off = reinterpret_cast<const double *>(src->ws + Ws::kOffsets) + slot;
-        if ((e = launch_upcast(src->g, static_cast<const float *>(src->buf[slot]), off,
-                               static_cast<double *>(dst->buf[slot]), dst->stream)) != hipSuccess)
-            return hip_fail(dst, e, "upcast");
+        e = inplace ? launch_upcast_inplace(src->g, dst->buf[slot], off, dst->stream)
+                    : launch_upcast(src->g, static_cast<const float *>(src->buf[slot]), off,
+                                    static_cast<double *>(dst->buf[slot]), dst->stream);
+        if (e != hipSuccess) return hip_fail(dst, e, "upcast");
     }
     dst->sweeps = src->sweeps;
     dst->best = src->best;

@@ -59,6 +59,9 @@ hipError_t launch_fill_f64(double *p, uint64_t count, double v, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_upcast(const Geometry &g, const float *src, const double *offset_dev,
                          double *dst, hipStream_t s);
+// the FP32 table in the first half of an FP64-sized buffer, widened in place
+hipError_t launch_upcast_inplace(const Geometry &g, void *buf, const double *offset_dev,
+                                 hipStream_t s);
 
 // Learned warm start (csrc/mlp.hip)
 struct MlpWs {  // byte offsets inside the caller's training workspace

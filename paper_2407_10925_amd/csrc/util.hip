@@ -50,6 +50,23 @@ __global__ __launch_bounds__(kBlock) void upcast_kernel(const float *__restrict_
         dst[i] = o + (double)src[i];
 }
 
+// In-place widening, one range [lo, hi) of a table whose FP32 values sit in
+// the first half of its FP64 buffer: reads bytes [4 lo, 4 hi), writes bytes
+// [8 lo, 8 hi).  For lo = hi / 2 the two ranges are disjoint, and every byte
+// written was read by an earlier range (larger indices go first), so ranges
+// launched from the top down never read a widened value.  No restrict: the
+// two pointers alias.
+__global__ __launch_bounds__(kBlock) void upcast_range(const float *src, const double *offset,
+                                                       double *dst, uint64_t lo, uint64_t hi)
+{
+    const double o = *offset;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = lo + (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < hi; i += stride) {
+        const float v = src[i];
+        dst[i] = o + (double)v;
+    }
+}
+
 unsigned grid_for(uint64_t work)
 {
     uint64_t b = (work + kBlock - 1) / kBlock;
@@ -89,6 +106,21 @@ hipError_t launch_upcast(const Geometry &g, const float *src, const double *offs
 {
     upcast_kernel<<<grid_for(g.ns), kBlock, 0, s>>>(src, offset_dev, dst, g.ns);
     return hipGetLastError();
+}
+
+hipError_t launch_upcast_inplace(const Geometry &g, void *buf, const double *offset_dev,
+                                 hipStream_t s)
+{
+    const float *src = static_cast<const float *>(buf);
+    double *dst = static_cast<double *>(buf);
+    for (uint64_t hi = g.ns; hi > 0;) {
+        const uint64_t lo = hi / 2;
+        upcast_range<<<grid_for(hi - lo), kBlock, 0, s>>>(src, offset_dev, dst, lo, hi);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hi = lo;
+    }
+    return hipSuccess;
 }
 
 }  // namespace lcsb

@@ -377,6 +377,36 @@ def test_fp32_zero_start_error_and_fp64_polish(pk):
     assert abs(best["bound"] - plain["bound"]) <= 1e-9
 
 
+@pytest.mark.parametrize("sigma,d,h", [(2, 2, 9), (4, 2, 3), (2, 3, 5)], ids=lambda v: str(v))
+def test_fp32_ring_inside_fp64_ring_upcasts_in_place(pk, sigma, d, h):
+    """An FP32 ring bound to the first halves of an FP64 ring's buffers sweeps
+    like one in its own memory, the upcast widens it in place to the same FP64
+    ring an upcast into separate memory gives, and the polish continues
+    identically; any other sharing of buffers is refused."""
+    say(f"in-place upcast sigma={sigma} d={d} h={h}")
+    A = pk.Lcsb(sigma, d, h, "f32")
+    P = pk.Lcsb(sigma, d, h, "f64")
+    B = pk.Lcsb(sigma, d, h, "f32", bufs=[b.view(torch.float32) for b in P.bufs])
+    for L in (A, B):
+        L.init_zero()
+        L.iterate(30)
+        L.certify()
+    assert torch.equal(A.lag(1)[0], B.lag(1)[0]) and A.lag(1)[1] == B.lag(1)[1]
+    Q = pk.Lcsb(sigma, d, h, "f64")
+    Q.upcast(A)
+    P.upcast(B)
+    for k in range(1, d + 1):
+        assert torch.equal(P.lag(k)[0], Q.lag(k)[0])
+    for L in (P, Q):
+        L.iterate(8)
+    assert torch.equal(P.lag(1)[0], Q.lag(1)[0])
+    assert P.certify()[0] == Q.certify()[0]
+    C = pk.Lcsb(sigma, d, h, "f32", bufs=[b.view(torch.float32) for b in P.bufs[1:] + P.bufs[:1]])
+    C.init_zero()
+    with pytest.raises(pk.LcsbError):
+        P.upcast(C)
+
+
 # ------------------------------------------------------------------ edges and errors
 def test_zero_sweeps_and_repeatability(pk):
     say("repeatability h=10")

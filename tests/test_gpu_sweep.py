@@ -275,7 +275,8 @@ def _fp32_bound(values_abs_max):
     return 8 * 2.0 ** -24 * (16 * values_abs_max + 2)
 
 
-@pytest.mark.parametrize("sigma,d,h", [(2, 2, 4), (2, 2, 9), (4, 2, 3), (2, 3, 5)])
+@pytest.mark.parametrize("sigma,d,h", [(2, 2, 1), (2, 2, 2), (2, 2, 4), (2, 2, 9), (4, 2, 1),
+                                       (4, 2, 2), (4, 2, 3), (2, 3, 1), (2, 3, 2), (2, 3, 5)])
 def test_fp32_random_ring_one_sweep(pk, sigma, d, h):
     say(f"random FP32 ring sigma={sigma} d={d} h={h}")
     lags = [si.table(sigma, d, h, seed=60 + k, dtype=torch.float32) for k in range(d)]

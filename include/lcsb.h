@@ -56,6 +56,7 @@ extern "C" {
 #define LCSB_ESTATE       (-4) /* call out of order, or context poisoned     */
 #define LCSB_EUNSUPPORTED (-5) /* (sigma, d, dtype) has no GPU kernel here   */
 #define LCSB_ENONFINITE   (-6) /* the certified table holds a NaN or inf     */
+#define LCSB_ECKPT        (-7) /* checkpoint file missing, foreign or corrupt */
 
 /* element types of the ring tables */
 #define LCSB_F64 0
@@ -159,7 +160,25 @@ int lcsb_status(const lcsb_ctx *ctx, int64_t *sweeps, lcsb_cert *best);
  * workspace, gives LCSB_EINVAL. */
 int lcsb_upcast(const lcsb_ctx *src_f32, lcsb_ctx *dst_f64);
 
+/* Write the ring to `path` (created or truncated): the stored entries of lag
+ * 1 .. d, the FP32 offsets, the sweep count and the best certificate, with a
+ * hash of every table and of the header.  Synchronises the stream; stages
+ * through a 64 MiB pinned host buffer it allocates and frees.  LCSB_ECKPT on a
+ * file error. */
+int lcsb_save(const lcsb_ctx *ctx, const char *path);
+
+/* Restore a ring written by lcsb_save for the same (sigma, d, l, dtype) into
+ * a bound context: afterwards iterate and certify continue bit for bit as
+ * the saved context would have.  The header (magic, version, shape, its hash
+ * and the file size) is checked before anything is written; a foreign,
+ * truncated or corrupt file gives LCSB_ECKPT.  A table hash mismatch is only
+ * found while the ring is being overwritten: the context is then left bound
+ * but not initialised (iterate and certify return LCSB_ESTATE until an init
+ * call or a good load).  Synchronises the stream. */
+int lcsb_load(lcsb_ctx *ctx, const char *path);
+
 /* ------------------------------------------------------------------------
+ * Learned warm start/* ------------------------------------------------------------------------
  * Learned warm start for sigma = d = 2 (not part of the paper's method: the
  * limit of Algorithm 2's iteration does not depend on the starting ring, so
  * a better start only shortens the run; the certificate decides the result).

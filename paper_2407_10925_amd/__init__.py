@@ -123,6 +123,14 @@ class Lcsb:
         check(self._lib.lcsb_init_seed_mlp(self._ctx, C.c_void_p(mlp.params.data_ptr()),
                                            C.c_void_p(mlp.wbf16.data_ptr()), float(rate)))
 
+    def save(self, path: str):
+        """Checkpoint the ring, its offsets, sweep count and best certificate."""
+        check(self._lib.lcsb_save(self._ctx, str(path).encode()))
+
+    def load(self, path: str):
+        """Restore a checkpoint written by :meth:`save` for the same shape."""
+        check(self._lib.lcsb_load(self._ctx, str(path).encode()))
+
     def upcast(self, src: "Lcsb"):
         """Fill this FP64 ring from the FP32 ring ``src`` (FP64 polish); in place
         when ``src`` was bound to this ring's buffers."""

@@ -14,12 +14,14 @@ LCSB_EHIP = -3
 LCSB_ESTATE = -4
 LCSB_EUNSUPPORTED = -5
 LCSB_ENONFINITE = -6
+LCSB_ECKPT = -7
 LCSB_F64 = 0
 LCSB_F32 = 1
 LCSB_MLP_NPARAMS = 140289
 
 _NAMES = {0: "LCSB_OK", -1: "LCSB_EINVAL", -2: "LCSB_ENOMEM", -3: "LCSB_EHIP",
-          -4: "LCSB_ESTATE", -5: "LCSB_EUNSUPPORTED", -6: "LCSB_ENONFINITE"}
+          -4: "LCSB_ESTATE", -5: "LCSB_EUNSUPPORTED", -6: "LCSB_ENONFINITE",
+          -7: "LCSB_ECKPT"}
 
 
 class LcsbError(RuntimeError):
@@ -63,6 +65,8 @@ def load():
     L.lcsb_lag.argtypes = [P, C.c_int, C.POINTER(P), C.POINTER(C.c_double)]
     L.lcsb_status.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(Cert)]
     L.lcsb_upcast.argtypes = [P, P]
+    L.lcsb_save.argtypes = [P, C.c_char_p]
+    L.lcsb_load.argtypes = [P, C.c_char_p]
     L.lcsb_destroy.argtypes = [P]
     L.lcsb_mlp_workspace.argtypes = [C.c_int64, C.POINTER(C.c_uint64)]
     L.lcsb_mlp_init.argtypes = [P, C.c_uint64, P]
@@ -76,7 +80,7 @@ def load():
     L.lcsb_init_seed_mlp.argtypes = [P, P, P, C.c_double]
     for name in ("lcsb_create", "lcsb_query", "lcsb_bind", "lcsb_init_zero", "lcsb_load_ring",
                  "lcsb_iterate", "lcsb_certify", "lcsb_lag", "lcsb_status", "lcsb_upcast",
-                 "lcsb_destroy", "lcsb_mlp_workspace", "lcsb_mlp_init", "lcsb_mlp_to_bf16",
+                 "lcsb_save", "lcsb_load", "lcsb_destroy", "lcsb_mlp_workspace", "lcsb_mlp_init", "lcsb_mlp_to_bf16",
                  "lcsb_mlp_sample", "lcsb_mlp_forward", "lcsb_mlp_loss", "lcsb_mlp_backward",
                  "lcsb_mlp_adam", "lcsb_init_seed_mlp"):
         getattr(L, name).restype = C.c_int

@@ -7,6 +7,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
+#include <cstddef>
 #include <new>
 #include <string>
 
@@ -438,6 +440,188 @@ int lcsb_init_seed_mlp(lcsb_ctx *c, const float *params, const uint16_t *wbf16, 
         return hip_fail(c, e, "seed");
     c->sweeps = 0;
     c->best = initial_best();
+    c->state = kReady;
+    return LCSB_OK;
+}
+
+// ------------------------------------------------------------------ checkpoint
+// File: a fixed header (every field little-endian, as on the host), then the
+// stored entries of lag 1 .. lag d.  The header carries a hash of each table
+// and a hash of itself; a file whose sizes or hashes do not match is refused.
+namespace {
+
+constexpr char kCkptMagic[8] = {'L', 'C', 'S', 'B', 'R', 'I', 'N', 'G'};
+constexpr uint32_t kCkptVersion = 1;
+constexpr size_t kStageBytes = size_t(64) << 20;  // pinned staging buffer
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t sigma, d, h, dtype;
+    uint32_t pad;
+    uint64_t stored;
+    int64_t sweeps;
+    double bound, R, E, maxW, rho;
+    int64_t best_sweep;
+    uint64_t argmax_W, nonfinite;
+    double offsets[3];
+    uint64_t table_hash[3];
+    uint64_t header_hash;  // of every byte before this field
+};
+
+// 64-bit hash of a byte stream, 8-byte words (a zero-padded tail word);
+// streaming: feed consecutive chunks whose sizes are multiples of 8.
+struct Hash64 {
+    uint64_t h = 0x243F6A8885A308D3ull;
+    void feed(const unsigned char *p, size_t bytes)
+    {
+        for (size_t i = 0; i < bytes; i += 8) {
+            uint64_t w = 0;
+            memcpy(&w, p + i, bytes - i < 8 ? bytes - i : 8);
+            h ^= w;
+            h *= 0x9E3779B97F4A7C15ull;
+            h ^= h >> 29;
+        }
+    }
+};
+
+uint64_t header_hash(const CkptHeader &hd)
+{
+    Hash64 hs;
+    hs.feed(reinterpret_cast<const unsigned char *>(&hd), offsetof(CkptHeader, header_hash));
+    return hs.h;
+}
+
+struct File {
+    FILE *f = nullptr;
+    ~File() { if (f) fclose(f); }
+};
+
+struct Pinned {
+    void *p = nullptr;
+    ~Pinned() { if (p) (void)hipHostFree(p); }
+};
+
+}  // namespace
+
+int lcsb_save(const lcsb_ctx *c, const char *path)
+{
+    int rc = need_ready(c);
+    if (rc) return rc;
+    if (!path) return fail(LCSB_EINVAL, "path is null");
+    const size_t es = elem_size(c->dtype);
+    const uint64_t tbytes = c->g.ns * es;
+    CkptHeader hd;
+    memset(&hd, 0, sizeof hd);
+    memcpy(hd.magic, kCkptMagic, 8);
+    hd.version = kCkptVersion;
+    hd.sigma = c->g.sigma; hd.d = c->g.d; hd.h = c->g.h; hd.dtype = c->dtype;
+    hd.stored = c->g.ns;
+    hd.sweeps = c->sweeps;
+    hd.bound = c->best.bound; hd.R = c->best.R; hd.E = c->best.E; hd.maxW = c->best.maxW;
+    hd.rho = c->best.rho; hd.best_sweep = c->best.sweep;
+    hd.argmax_W = c->best.argmax_W; hd.nonfinite = c->best.nonfinite;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(LCSB_EHIP, "sync: %s", hipGetErrorString(e));
+    if (c->dtype == LCSB_F32) {
+        for (int k = 1; k <= c->g.d; ++k) {
+            e = hipMemcpy(&hd.offsets[k - 1], c->ws + Ws::kOffsets + 8 * slot_of_lag(c, k), 8,
+                          hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return fail(LCSB_EHIP, "offset read: %s", hipGetErrorString(e));
+        }
+    }
+    File out;
+    out.f = fopen(path, "wb");
+    if (!out.f) return fail(LCSB_ECKPT, "cannot create %s", path);
+    if (fwrite(&hd, sizeof hd, 1, out.f) != 1) return fail(LCSB_ECKPT, "write failed: %s", path);
+    Pinned stage;
+    if ((e = hipHostMalloc(&stage.p, kStageBytes, hipHostMallocDefault)) != hipSuccess)
+        return fail(LCSB_EHIP, "pinned staging buffer: %s", hipGetErrorString(e));
+    for (int k = 1; k <= c->g.d; ++k) {
+        const unsigned char *src = static_cast<const unsigned char *>(c->buf[slot_of_lag(c, k)]);
+        Hash64 hs;
+        for (uint64_t at = 0; at < tbytes; at += kStageBytes) {
+            const size_t n = (size_t)std::min<uint64_t>(kStageBytes, tbytes - at);
+            e = hipMemcpyAsync(stage.p, src + at, n, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) return fail(LCSB_EHIP, "table read: %s", hipGetErrorString(e));
+            hs.feed(static_cast<const unsigned char *>(stage.p), n);
+            if (fwrite(stage.p, 1, n, out.f) != n) return fail(LCSB_ECKPT, "write failed: %s", path);
+        }
+        hd.table_hash[k - 1] = hs.h;
+    }
+    hd.header_hash = header_hash(hd);
+    if (fseek(out.f, 0, SEEK_SET) != 0 || fwrite(&hd, sizeof hd, 1, out.f) != 1)
+        return fail(LCSB_ECKPT, "header rewrite failed: %s", path);
+    const int closed = fclose(out.f);
+    out.f = nullptr;
+    if (closed != 0) return fail(LCSB_ECKPT, "close failed: %s", path);
+    return LCSB_OK;
+}
+
+int lcsb_load(lcsb_ctx *c, const char *path)
+{
+    if (!c) return fail(LCSB_EINVAL, "null context");
+    if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
+    if (c->state < kBound) return fail(LCSB_ESTATE, "bind before load");
+    if (!path) return fail(LCSB_EINVAL, "path is null");
+    File in;
+    in.f = fopen(path, "rb");
+    if (!in.f) return fail(LCSB_ECKPT, "cannot open %s", path);
+    CkptHeader hd;
+    if (fread(&hd, sizeof hd, 1, in.f) != 1) return fail(LCSB_ECKPT, "%s: short header", path);
+    if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != kCkptVersion)
+        return fail(LCSB_ECKPT, "%s: not a ring checkpoint of this version", path);
+    if (hd.header_hash != header_hash(hd)) return fail(LCSB_ECKPT, "%s: header hash mismatch", path);
+    if (hd.sigma != c->g.sigma || hd.d != c->g.d || hd.h != c->g.h || hd.dtype != c->dtype ||
+        hd.stored != c->g.ns)
+        return fail(LCSB_ECKPT, "%s: holds sigma=%d d=%d l=%d dtype=%d, the context is sigma=%d "
+                                "d=%d l=%d dtype=%d", path, hd.sigma, hd.d, hd.h, hd.dtype,
+                    c->g.sigma, c->g.d, c->g.h, c->dtype);
+    const size_t es = elem_size(c->dtype);
+    const uint64_t tbytes = c->g.ns * es;
+    if (fseek(in.f, 0, SEEK_END) != 0) return fail(LCSB_ECKPT, "%s: cannot seek", path);
+    const long long size = ftell(in.f);
+    if (size < 0 || (uint64_t)size != sizeof hd + (uint64_t)c->g.d * tbytes)
+        return fail(LCSB_ECKPT, "%s: %lld bytes, expected %llu", path, size,
+                    (unsigned long long)(sizeof hd + (uint64_t)c->g.d * tbytes));
+    if (fseek(in.f, (long)sizeof hd, SEEK_SET) != 0) return fail(LCSB_ECKPT, "%s: cannot seek", path);
+    // from here the ring is being overwritten: not ready until every hash checks
+    c->state = kBound;
+    hipError_t e;
+    Pinned stage;
+    if ((e = hipHostMalloc(&stage.p, kStageBytes, hipHostMallocDefault)) != hipSuccess)
+        return fail(LCSB_EHIP, "pinned staging buffer: %s", hipGetErrorString(e));
+    if ((e = launch_fill_zero(c->ws, Ws::kBytes, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "fill workspace");
+    c->head = 0;
+    for (int k = 1; k <= c->g.d; ++k) {
+        unsigned char *dst = static_cast<unsigned char *>(c->buf[slot_of_lag(c, k)]);
+        Hash64 hs;
+        for (uint64_t at = 0; at < tbytes; at += kStageBytes) {
+            const size_t n = (size_t)std::min<uint64_t>(kStageBytes, tbytes - at);
+            // the previous chunk's copy must finish before the buffer is refilled
+            if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "sync");
+            if (fread(stage.p, 1, n, in.f) != n) return fail(LCSB_ECKPT, "%s: short read", path);
+            hs.feed(static_cast<const unsigned char *>(stage.p), n);
+            if ((e = hipMemcpyAsync(dst + at, stage.p, n, hipMemcpyHostToDevice, c->stream)) !=
+                hipSuccess)
+                return hip_fail(c, e, "table write");
+        }
+        if (hs.h != hd.table_hash[k - 1])
+            return fail(LCSB_ECKPT, "%s: lag %d hash mismatch (corrupt checkpoint)", path, k);
+        if (c->dtype == LCSB_F32) {
+            double *dev = reinterpret_cast<double *>(c->ws + Ws::kOffsets) + slot_of_lag(c, k);
+            if ((e = launch_fill_f64(dev, 1, hd.offsets[k - 1], c->stream)) != hipSuccess)
+                return hip_fail(c, e, "offset");
+        }
+    }
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "sync");
+    c->sweeps = hd.sweeps;
+    c->best = initial_best();
+    c->best.bound = hd.bound; c->best.R = hd.R; c->best.E = hd.E; c->best.maxW = hd.maxW;
+    c->best.rho = hd.rho; c->best.sweep = hd.best_sweep;
+    c->best.argmax_W = hd.argmax_W; c->best.nonfinite = hd.nonfinite;
     c->state = kReady;
     return LCSB_OK;
 }

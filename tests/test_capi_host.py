@@ -98,3 +98,58 @@ def test_build_rejects_kernels_that_spill():
     ])
     assert B.scratch_users(remarks) == [("_Z5spillv", 28)]
     assert B.scratch_users("") == []
+
+
+# ------------------------------------------------------------------ checkpoint files
+_HDR = "<8sIiiiiIQqdddddqQQ3d3QQ"  # the checkpoint header of include/lcsb.h's lcsb_save
+
+
+def _hash64(data: bytes) -> int:
+    """The header/table hash: 8-byte little-endian words, zero-padded tail."""
+    h, m = 0x243F6A8885A308D3, (1 << 64) - 1
+    for i in range(0, len(data), 8):
+        w = int.from_bytes(data[i:i + 8].ljust(8, b"\0"), "little")
+        h = ((h ^ w) * 0x9E3779B97F4A7C15) & m
+        h ^= h >> 29
+    return h
+
+
+def _header(sigma, d, h, dtype, stored):
+    import struct
+    body = struct.pack(_HDR[:-1], b"LCSBRING", 1, sigma, d, h, dtype, 0, stored, 5,
+                       0.5, 0.25, 0.0, -1.0, 0.25, 4, 0, 0, 0.0, 0.0, 0.0, 1, 2, 3)
+    return body + struct.pack("<Q", _hash64(body))
+
+
+def test_checkpoint_header_is_checked_before_the_ring_is_touched(lib, tmp_path):
+    """Every refusal here happens before any device access (the ring pointers
+    are not device memory: this runs without a GPU)."""
+    import struct
+    from paper_2407_10925_amd import _capi
+    assert struct.calcsize(_HDR) == 168
+    ctx = C.c_void_p()
+    assert lib.lcsb_create(2, 2, 4, 0, C.byref(ctx)) == 0
+    assert lib.lcsb_load(ctx, str(tmp_path / "x").encode()) == _capi.LCSB_ESTATE  # not bound
+    bufs = (C.c_void_p * 3)(256, 512, 768)
+    assert lib.lcsb_bind(ctx, bufs, 3, C.c_void_p(1024), None) == 0
+    assert lib.lcsb_save(ctx, str(tmp_path / "x").encode()) == _capi.LCSB_ESTATE  # no ring yet
+    assert lib.lcsb_load(ctx, None) == _capi.LCSB_EINVAL
+    assert lib.lcsb_load(ctx, str(tmp_path / "missing").encode()) == _capi.LCSB_ECKPT
+    stored, tbytes = 4 ** 4 // 2, 8 * 4 ** 4 // 2
+    good = _header(2, 2, 4, 0, stored)
+    cases = {
+        "short": good[:100],
+        "magic": b"LCSBRINX" + good[8:],
+        "hash": good[:40] + b"\x07" + good[41:],
+        "shape": _header(2, 2, 5, 0, 4 ** 5 // 2) + bytes(2 * 8 * 4 ** 5 // 2),
+        "dtype": _header(2, 2, 4, 1, stored) + bytes(2 * 4 * stored),
+        "truncated": good + bytes(2 * tbytes - 8),
+        "too long": good + bytes(2 * tbytes + 8),
+    }
+    for name, blob in cases.items():
+        p = tmp_path / name
+        p.write_bytes(blob)
+        assert lib.lcsb_load(ctx, str(p).encode()) == _capi.LCSB_ECKPT, name
+        assert b"checkpoint" in lib.lcsb_last_error() or str(p).encode() in lib.lcsb_last_error()
+    assert lib.lcsb_iterate(ctx, 1) == _capi.LCSB_ESTATE  # still not initialised
+    assert lib.lcsb_destroy(ctx) == 0

@@ -408,6 +408,68 @@ def test_fp32_ring_inside_fp64_ring_upcasts_in_place(pk, sigma, d, h):
         P.upcast(C)
 
 
+@pytest.mark.parametrize("sigma,d,h,dt", [(2, 2, 8, "f64"), (2, 2, 8, "f32"), (4, 2, 3, "f32"),
+                                          (2, 3, 4, "f64")], ids=lambda v: str(v))
+def test_checkpoint_resume_is_bit_identical(pk, tmp_path, sigma, d, h, dt):
+    """Save after k sweeps, sweep on; a fresh context loaded from the file and
+    swept as far gives the same tables bit for bit, the same certificates,
+    sweep count and best triplet (FP32: the offsets travel with the file)."""
+    say(f"checkpoint sigma={sigma} d={d} h={h} {dt}")
+    path = tmp_path / "ring.ckpt"
+    A = pk.Lcsb(sigma, d, h, dt)
+    A.init_zero()
+    A.iterate(25)
+    A.certify()
+    A.save(path)
+    assert path.stat().st_size == 168 + d * A.stored * (8 if dt == "f64" else 4)
+    A.iterate(11)
+    cur_a, best_a = A.certify()
+    B = pk.Lcsb(sigma, d, h, dt)
+    B.load(path)
+    assert B.status()[0] == 25
+    B.iterate(11)
+    cur_b, best_b = B.certify()
+    assert cur_a == cur_b and best_a == best_b
+    for k in range(1, d + 1):
+        ta, oa = A.lag(k)
+        tb, ob = B.lag(k)
+        assert torch.equal(ta, tb) and oa == ob
+
+
+def test_corrupt_checkpoint_is_refused(pk, tmp_path):
+    """A flipped byte in a table is found by its hash (the context is left
+    bound but not initialised); a flipped header byte is found before the
+    ring is touched."""
+    say("corrupt checkpoint")
+    path = tmp_path / "ring.ckpt"
+    A = pk.Lcsb(2, 2, 6, "f64")
+    A.init_zero()
+    A.iterate(9)
+    A.save(path)
+    blob = bytearray(path.read_bytes())
+    blob[168 + 8 * 1000 + 3] ^= 0x10
+    bad = tmp_path / "bad_table.ckpt"
+    bad.write_bytes(bytes(blob))
+    B = pk.Lcsb(2, 2, 6, "f64")
+    with pytest.raises(pk.LcsbError) as e:
+        B.load(bad)
+    assert e.value.code == -7 and "hash" in str(e.value)
+    with pytest.raises(pk.LcsbError) as e:
+        B.iterate(1)
+    assert e.value.code == -4
+    B.load(path)  # a good file makes it ready again
+    B.iterate(1)
+    blob = bytearray(path.read_bytes())
+    blob[44] ^= 0x01  # the sweep count
+    bad.write_bytes(bytes(blob))
+    C = pk.Lcsb(2, 2, 6, "f64")
+    C.init_zero()
+    with pytest.raises(pk.LcsbError) as e:
+        C.load(bad)
+    assert e.value.code == -7
+    C.iterate(1)  # refused before the ring was touched: still ready
+
+
 # ------------------------------------------------------------------ edges and errors
 def test_zero_sweeps_and_repeatability(pk):
     say("repeatability h=10")

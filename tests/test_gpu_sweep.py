@@ -303,7 +303,7 @@ def test_fp32_random_ring_one_sweep(pk, sigma, d, h):
                          ids=lambda v: str(v))
 def test_fp32_full_size_sampled_sweep_and_certificate(pk, sigma, d, h, seed):
     """The FP32 configurations the benchmark times at their full size
-    (sigma = d = 2, l = 16 and sigma = 4, d = 2, l = 8: 2^32 entries per
+    (sigma = d = 2, l = 16 and sigma = 4, d = 2, l = 8: 2^32 indices per
     table; sigma = 2, d = 3, l = 10: 2^30), in the library's own launch
     configuration: one sweep from a seeded ring checked at sampled
     coordinates against the FP64 oracle, and the certificate of the seeded

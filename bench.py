@@ -348,6 +348,7 @@ def learned_run(pk, h, P, target, train_steps):
 CONFIGS = [  # (sigma, d, l, dtype)
     (2, 2, 6, "f64"), (2, 2, 14, "f64"), (2, 2, 16, "f32"), (2, 2, 16, "f64"),
     (4, 2, 8, "f32"), (2, 3, 10, "f32"), (4, 2, 8, "f64"), (2, 3, 10, "f64"),
+    (2, 2, 17, "f32"), (2, 2, 17, "f64"),
 ]
 
 

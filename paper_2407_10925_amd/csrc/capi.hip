@@ -497,9 +497,17 @@ struct File {
     ~File() { if (f) fclose(f); }
 };
 
+// Pinned staging buffer; copies from or to it run on `stream`, which is
+// drained before the buffer is freed (also on every early return).
 struct Pinned {
     void *p = nullptr;
-    ~Pinned() { if (p) (void)hipHostFree(p); }
+    hipStream_t stream = nullptr;
+    ~Pinned()
+    {
+        if (!p) return;
+        (void)hipStreamSynchronize(stream);
+        (void)hipHostFree(p);
+    }
 };
 
 }  // namespace
@@ -535,6 +543,7 @@ int lcsb_save(const lcsb_ctx *c, const char *path)
     if (!out.f) return fail(LCSB_ECKPT, "cannot create %s", path);
     if (fwrite(&hd, sizeof hd, 1, out.f) != 1) return fail(LCSB_ECKPT, "write failed: %s", path);
     Pinned stage;
+    stage.stream = c->stream;
     if ((e = hipHostMalloc(&stage.p, kStageBytes, hipHostMallocDefault)) != hipSuccess)
         return fail(LCSB_EHIP, "pinned staging buffer: %s", hipGetErrorString(e));
     for (int k = 1; k <= c->g.d; ++k) {
@@ -590,6 +599,7 @@ int lcsb_load(lcsb_ctx *c, const char *path)
     c->state = kBound;
     hipError_t e;
     Pinned stage;
+    stage.stream = c->stream;
     if ((e = hipHostMalloc(&stage.p, kStageBytes, hipHostMallocDefault)) != hipSuccess)
         return fail(LCSB_EHIP, "pinned staging buffer: %s", hipGetErrorString(e));
     if ((e = launch_fill_zero(c->ws, Ws::kBytes, c->stream)) != hipSuccess)

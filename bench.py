@@ -71,7 +71,7 @@ def parse():
                    help="only generate the warm-start training tables and run this many steps")
     p.add_argument("--train-batch", type=int, default=8192, help="batch of --profile-train")
     p.add_argument("--converge", type=int, default=0, metavar="L",
-                   help="only run plain FP64 at sigma = d = 2, l = L to convergence, then FP32 + "
+                   help="only run plain FP64 at (--sigma, --d, l = L) to convergence, then FP32 + "
                         "FP64 polish to the same bound in the same memory")
     p.add_argument("--profile-certify", action="store_true",
                    help="only run 8 sweeps from zero and two certificates (counter collection)")
@@ -445,17 +445,17 @@ def train_only(pk, h, steps, batch=8192):
         f"{flop / dt / 1e12:.1f} TFLOP/s, last loss {M.loss_dev.item():.3e}")
 
 
-def converge_only(pk, h):
-    """At sigma = d = 2, l = h: the plain FP64 iteration from zero, a
+def converge_only(pk, h, sigma=2, d=2):
+    """At (sigma, d, l = h): the plain FP64 iteration from zero, a
     certificate every TTB_CADENCE sweeps, until consecutive certificates move
     by less than 1e-10 (B = the best bound then, also printed rounded down at
     the 6th decimal as Table 2 prints it); then FP32 from zero + FP64 polish to
     B - 1e-9 in the same memory (the FP32 ring bound to the first halves of the
     FP64 ring's buffers, widened in place by the upcast)."""
     import torch
-    P = pk.Lcsb(2, 2, h, "f64")
-    log(f"plain FP64 at l={h}: {P.n} indices, {P.stored} stored, "
-        f"{3 * 8 * P.stored / 2**30:.0f} GiB ring")
+    P = pk.Lcsb(sigma, d, h, "f64")
+    log(f"plain FP64 at sigma={sigma} d={d} l={h}: {P.n} indices, {P.stored} stored, "
+        f"{(d + 1) * 8 * P.stored / 2**30:.0f} GiB ring")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P.init_zero()
@@ -474,12 +474,12 @@ def converge_only(pk, h):
     B = best["bound"]
     target = B - 1e-9
     k = next(i for i, (_, b, _) in enumerate(hist) if b >= target)
-    out = {"sigma": 2, "d": 2, "l": h, "indices": P.n, "stored": P.stored,
+    out = {"sigma": sigma, "d": d, "l": h, "indices": P.n, "stored": P.stored,
            "bound": B, "floor6": math.floor(B * 1e6) / 1e6,
            "plain_f64": {"seconds_to_target": round(hist[k][0], 3), "sweeps_to_target": hist[k][2],
                          "converged_after_sweeps": cur["sweep"],
                          "converged_after_s": round(hist[-1][0], 3)}}
-    M = pk.Lcsb(2, 2, h, "f32", bufs=[b.view(torch.float32) for b in P.bufs])
+    M = pk.Lcsb(sigma, d, h, "f32", bufs=[b.view(torch.float32) for b in P.bufs])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     M.init_zero()
@@ -539,7 +539,7 @@ def main():
     if args.profile_seed:
         return seed_only(pk, args.h)
     if args.converge:
-        return converge_only(pk, args.converge)
+        return converge_only(pk, args.converge, args.sigma, args.d)
     if args.profile_certify:
         return certify_only(pk, args.h, args.sigma, args.d, args.dtype)
     if args.profile_train:

@@ -266,6 +266,41 @@ def test_fp64_l17_converged_bound_is_table2s(pk):
     torch.cuda.empty_cache()
 
 
+def _table3(sigma, d):
+    import pathlib
+    for line in (pathlib.Path(__file__).parent / "golden" / "table3_general_bounds.txt").read_text().splitlines():
+        f = line.split()
+        if f and not f[0].startswith("#") and (int(f[0]), int(f[1])) == (sigma, d):
+            return int(f[2]), float(f[3])
+    raise KeyError((sigma, d))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("sigma,d", [(4, 2), (2, 3)], ids=lambda v: str(v))
+def test_fp64_generality_converges_to_table3(pk, sigma, d):
+    """The generality configurations at the l Table 3 gives for them
+    (sigma = 4, d = 2, l = 8: 2^32 indices, 2^30 stored; sigma = 2, d = 3,
+    l = 10: 2^30 indices, 2^29 stored): the plain FP64 iteration from zero,
+    certified every 16 sweeps until consecutive certificates move by less
+    than 1e-10, gives Table 3's bound rounded down at the 6th decimal."""
+    h, printed = _table3(sigma, d)
+    say(f"sigma={sigma} d={d} l={h} FP64: plain iteration to convergence")
+    L = pk.Lcsb(sigma, d, h, "f64")
+    L.init_zero()
+    prev = None
+    while True:
+        L.iterate(16)
+        cur, best = L.certify()
+        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
+            break
+        prev = cur["bound"]
+        assert cur["sweep"] < 1600
+    say(f"sigma={sigma} d={d} l={h}: {best['bound']:.12f} after {cur['sweep']} sweeps")
+    assert math.floor(best["bound"] * 1e6) / 1e6 == printed
+    del L
+    torch.cuda.empty_cache()
+
+
 def _fp32_bound(values_abs_max):
     """FP32 error of one sweep on exact float inputs, per entry: the pairwise
     sum of at most 16 values (4 levels), the exact scaling, the offset

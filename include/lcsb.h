@@ -160,11 +160,13 @@ int lcsb_status(const lcsb_ctx *ctx, int64_t *sweeps, lcsb_cert *best);
  * workspace, gives LCSB_EINVAL. */
 int lcsb_upcast(const lcsb_ctx *src_f32, lcsb_ctx *dst_f64);
 
-/* Write the ring to `path` (created or truncated): the stored entries of lag
- * 1 .. d, the FP32 offsets, the sweep count and the best certificate, with a
- * hash of every table and of the header.  Synchronises the stream; stages
- * through a 64 MiB pinned host buffer it allocates and frees.  LCSB_ECKPT on a
- * file error. */
+/* Write the ring to `path`: the stored entries of lag 1 .. d, the FP32
+ * offsets, the sweep count and the best certificate, with a hash of every
+ * table and of the header.  The file is written as `path`.part and renamed
+ * over `path` once complete, so an interrupted save leaves an earlier
+ * checkpoint at `path` intact.  Synchronises the stream; stages through a
+ * 64 MiB pinned host buffer it allocates and frees.  LCSB_ECKPT on a file
+ * error. */
 int lcsb_save(const lcsb_ctx *ctx, const char *path);
 
 /* Restore a ring written by lcsb_save for the same (sigma, d, l, dtype) into

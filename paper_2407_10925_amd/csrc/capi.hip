@@ -538,9 +538,12 @@ int lcsb_save(const lcsb_ctx *c, const char *path)
             if (e != hipSuccess) return fail(LCSB_EHIP, "offset read: %s", hipGetErrorString(e));
         }
     }
+    // written beside the target and renamed over it once complete, so a run
+    // killed while saving keeps its previous checkpoint
+    const std::string part = std::string(path) + ".part";
     File out;
-    out.f = fopen(path, "wb");
-    if (!out.f) return fail(LCSB_ECKPT, "cannot create %s", path);
+    out.f = fopen(part.c_str(), "wb");
+    if (!out.f) return fail(LCSB_ECKPT, "cannot create %s", part.c_str());
     if (fwrite(&hd, sizeof hd, 1, out.f) != 1) return fail(LCSB_ECKPT, "write failed: %s", path);
     Pinned stage;
     stage.stream = c->stream;
@@ -564,7 +567,8 @@ int lcsb_save(const lcsb_ctx *c, const char *path)
         return fail(LCSB_ECKPT, "header rewrite failed: %s", path);
     const int closed = fclose(out.f);
     out.f = nullptr;
-    if (closed != 0) return fail(LCSB_ECKPT, "close failed: %s", path);
+    if (closed != 0) return fail(LCSB_ECKPT, "close failed: %s", part.c_str());
+    if (rename(part.c_str(), path) != 0) return fail(LCSB_ECKPT, "cannot rename %s to %s", part.c_str(), path);
     return LCSB_OK;
 }
 

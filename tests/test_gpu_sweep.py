@@ -469,6 +469,7 @@ def test_checkpoint_resume_is_bit_identical(pk, tmp_path, sigma, d, h, dt):
     A.certify()
     A.save(path)
     assert path.stat().st_size == 168 + d * A.stored * (8 if dt == "f64" else 4)
+    assert not (tmp_path / "ring.ckpt.part").exists()
     A.iterate(11)
     cur_a, best_a = A.certify()
     B = pk.Lcsb(sigma, d, h, dt)

@@ -138,36 +138,22 @@ MAX_SWEEPS = 1600
 def fp32_until_floor(S):
     """FP32 sweeps with a certificate every TTB_CADENCE sweeps until the best
     bound is positive and gains less than SWITCH_GAIN over one period (the
-    FP32 error floor).  Returns (cur, best, certificates)."""
-    best_prev = None
-    certs = 0
-    while True:
-        S.iterate(TTB_CADENCE)
-        cur, best = S.certify()
-        certs += 1
-        if cur["sweep"] >= MAX_SWEEPS:
-            break
-        if best["bound"] > 0 and best_prev is not None and best["bound"] - best_prev < SWITCH_GAIN:
-            break
-        best_prev = best["bound"]
+    FP32 error floor), as one lcsb_run.  Returns (cur, best, certificates)."""
+    cur, best, certs, _ = S.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, min_gain=SWITCH_GAIN)
     return cur, best, certs
 
 
 def polish(P, S, best, target):
-    """Upcast the FP32 ring into P and continue in FP64 until the best
+    """Upcast the FP32 ring into P and continue in FP64 (first certificate
+    after POLISH_FIRST sweeps, then every POLISH_CADENCE) until the best
     certified bound reaches target.  Returns (FP64 sweeps, certificates, best)."""
     if best["bound"] >= target:
         return 0, 0, best
-    P.upcast(S)
-    swept, certs = 0, 0
-    step = POLISH_FIRST
-    while best["bound"] < target and swept < MAX_SWEEPS:
-        P.iterate(step)
-        swept += step
-        _, best = P.certify()  # the upcast carried the FP32 run's best over
-        certs += 1
-        step = POLISH_CADENCE
-    return swept, certs, best
+    P.upcast(S)  # the best certificate of the FP32 run moves over
+    start = P.status()[0]
+    _, best, certs, _ = P.run(POLISH_CADENCE, first=POLISH_FIRST, max_sweeps=MAX_SWEEPS,
+                              target=target)
+    return P.status()[0] - start, certs, best
 
 
 def fp64_sweep(pk, h, sweeps=32):
@@ -217,41 +203,25 @@ def fp32_error(P, S, chunk=1 << 28):
 def time_to_bound(pk, h, train_steps=1000):
     """Wall time from the init call to the first certificate within 1e-9 of
     the converged plain FP64 bound B (certificates, upcast and seeding
-    included).
+    included).  Every run is driven by lcsb_run.
 
-    plain:  FP64 from zero, a certificate every TTB_CADENCE sweeps, run on
-            until consecutive certificates move by less than 1e-10 (B = the
-            best bound then); its time is that of its first certificate
-            >= B - 1e-9.
-    mixed:  FP32 from zero until its error floor (fp32_until_floor), then the
-            FP64 polish (polish) until the best bound reaches B - 1e-9.
+    B:       FP64 from zero, a certificate every TTB_CADENCE sweeps, until
+             consecutive certificates move by less than 1e-10 (untimed).
+    plain:   FP64 from zero, a certificate every TTB_CADENCE sweeps, until the
+             best bound reaches B - 1e-9.
+    mixed:   FP32 from zero until its error floor (fp32_until_floor), then the
+             FP64 polish (polish) until the best bound reaches B - 1e-9.
     learned: as mixed, from the warm-start network's seed (learned_run).
     """
     import torch
     out = {}
     P = pk.Lcsb(2, 2, h, "f64")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     P.init_zero()
-    hist = []
-    prev = None
-    while True:
-        P.iterate(TTB_CADENCE)
-        cur, best = P.certify()
-        hist.append((time.perf_counter() - t0, best["bound"], cur["sweep"]))
-        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
-            break
-        prev = cur["bound"]
-        if cur["sweep"] >= MAX_SWEEPS:
-            break
+    cur, best, _, why = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, stop_delta=1e-10)
     B = best["bound"]
     target = B - 1e-9
-    k = next(i for i, (_, b, _) in enumerate(hist) if b >= target)
-    t_plain, s_plain = hist[k][0], hist[k][2]
-    out["plain_f64"] = {"seconds": round(t_plain, 4), "sweeps": s_plain, "certificates": k + 1,
-                        "bound": B, "ran_sweeps": hist[-1][2],
-                        "certificate_every": TTB_CADENCE}
-    log(f"time to bound, plain FP64: {t_plain:.3f} s, {s_plain} sweeps, bound {B:.12f}")
+    converged_after = cur["sweep"]
+    log(f"converged plain FP64 bound B = {B:.12f} after {converged_after} sweeps ({why})")
 
     M = pk.Lcsb(2, 2, h, "f32")
     torch.cuda.synchronize()
@@ -279,9 +249,22 @@ def time_to_bound(pk, h, train_steps=1000):
         f"{sweeps64} FP64 sweeps, bound {best['bound']:.12f}")
     del M
     torch.cuda.empty_cache()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.init_zero()
+    cur, best, certs, _ = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, target=target)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    out["plain_f64"] = {"seconds": round(t_plain, 4), "sweeps": cur["sweep"], "certificates": certs,
+                        "bound": B, "converged_after_sweeps": converged_after,
+                        "certificate_every": TTB_CADENCE}
+    log(f"time to bound, plain FP64: {t_plain:.3f} s, {cur['sweep']} sweeps, bound {B:.12f}")
+
     out["mixed_learned"] = learned_run(pk, h, P, target, train_steps)
     out["policy"] = {"certificate_every": TTB_CADENCE, "switch_gain": SWITCH_GAIN,
-                     "polish_first": POLISH_FIRST, "polish_every": POLISH_CADENCE}
+                     "polish_first": POLISH_FIRST, "polish_every": POLISH_CADENCE,
+                     "driver": "lcsb_run"}
     del P
     torch.cuda.empty_cache()
     return out
@@ -446,12 +429,13 @@ def train_only(pk, h, steps, batch=8192):
 
 
 def converge_only(pk, h, sigma=2, d=2):
-    """At (sigma, d, l = h): the plain FP64 iteration from zero, a
-    certificate every TTB_CADENCE sweeps, until consecutive certificates move
-    by less than 1e-10 (B = the best bound then, also printed rounded down at
-    the 6th decimal as Table 2 prints it); then FP32 from zero + FP64 polish to
-    B - 1e-9 in the same memory (the FP32 ring bound to the first halves of the
-    FP64 ring's buffers, widened in place by the upcast)."""
+    """At (sigma, d, l = h): the plain FP64 iteration from zero, a certificate
+    every TTB_CADENCE sweeps, until consecutive certificates move by less than
+    1e-10 (B = the best bound then, also printed rounded down at the 6th
+    decimal as the paper's tables print it); then, timed, plain FP64 from zero
+    to B - 1e-9, and FP32 from zero + FP64 polish to B - 1e-9 in the same
+    memory (the FP32 ring bound to the first halves of the FP64 ring's
+    buffers, widened in place by the upcast).  Every run is one lcsb_run."""
     import torch
     P = pk.Lcsb(sigma, d, h, "f64")
     log(f"plain FP64 at sigma={sigma} d={d} l={h}: {P.n} indices, {P.stored} stored, "
@@ -459,26 +443,23 @@ def converge_only(pk, h, sigma=2, d=2):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P.init_zero()
-    prev, hist = None, []
-    while True:
-        P.iterate(TTB_CADENCE)
-        cur, best = P.certify()
-        hist.append((time.perf_counter() - t0, best["bound"], cur["sweep"]))
-        log(f"sweep {cur['sweep']}: bound {cur['bound']:.12f} best {best['bound']:.12f} "
-            f"({hist[-1][0]:.2f} s)")
-        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
-            break
-        prev = cur["bound"]
-        if cur["sweep"] >= MAX_SWEEPS:
-            break
+    cur, best, _, why = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, stop_delta=1e-10)
+    torch.cuda.synchronize()
+    t_conv = time.perf_counter() - t0
     B = best["bound"]
     target = B - 1e-9
-    k = next(i for i, (_, b, _) in enumerate(hist) if b >= target)
+    log(f"converged: {B:.12f} after {cur['sweep']} sweeps, {t_conv:.2f} s ({why})")
     out = {"sigma": sigma, "d": d, "l": h, "indices": P.n, "stored": P.stored,
            "bound": B, "floor6": math.floor(B * 1e6) / 1e6,
-           "plain_f64": {"seconds_to_target": round(hist[k][0], 3), "sweeps_to_target": hist[k][2],
-                         "converged_after_sweeps": cur["sweep"],
-                         "converged_after_s": round(hist[-1][0], 3)}}
+           "converged_after_sweeps": cur["sweep"], "converged_after_s": round(t_conv, 3)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.init_zero()
+    cur, best, certs, _ = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, target=target)
+    torch.cuda.synchronize()
+    out["plain_f64"] = {"seconds_to_target": round(time.perf_counter() - t0, 3),
+                        "sweeps_to_target": cur["sweep"], "certificates": certs}
+    log(f"plain to B - 1e-9: {out['plain_f64']['seconds_to_target']:.2f} s, {cur['sweep']} sweeps")
     M = pk.Lcsb(sigma, d, h, "f32", bufs=[b.view(torch.float32) for b in P.bufs])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -491,7 +472,7 @@ def converge_only(pk, h, sigma=2, d=2):
     out["mixed_f32_polish"] = {"seconds_to_target": round(t_mixed, 3), "sweeps_f32": sweeps32,
                                "sweeps_f64": sweeps64, "certificates": certs32 + certs64,
                                "bound": best["bound"], "reached": best["bound"] >= target}
-    log(f"mixed at l={h}: {t_mixed:.2f} s, {sweeps32} FP32 + {sweeps64} FP64 sweeps")
+    log(f"mixed to B - 1e-9: {t_mixed:.2f} s, {sweeps32} FP32 + {sweeps64} FP64 sweeps")
     print(json.dumps(out), flush=True)
 
 

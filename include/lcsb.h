@@ -149,7 +149,38 @@ int lcsb_lag(const lcsb_ctx *ctx, int k, void **dev_ptr, double *offset);
 /* Number of sweeps applied since the last init, and the best certificate. */
 int lcsb_status(const lcsb_ctx *ctx, int64_t *sweeps, lcsb_cert *best);
 
-/* Copy the ring of an LCSB_F32 context into an LCSB_F64 context of the same
+/* Stop rule and certificate cadence of a run (Algorithm 2's loop with its
+ * certificate taken every `cadence` sweeps instead of every sweep). */
+typedef struct {
+    int64_t cadence;     /* sweeps between certificates, > 0                  */
+    int64_t first;       /* sweeps before the first certificate; 0 = cadence  */
+    int64_t max_sweeps;  /* no new period once this many sweeps have run in
+                            this call (the last period may pass it), >= 0     */
+    double target;       /* stop once best.bound >= target; NaN = no target    */
+    double stop_delta;   /* stop once two consecutive certificates differ by
+                            less than this and the newer is >= best; 0 = off  */
+    double min_gain;     /* stop once a positive best bound gained less than
+                            this over one period (an FP32 run at its error
+                            floor); 0 = off                                   */
+} lcsb_run_policy;
+
+#define LCSB_STOP_MAX_SWEEPS 0  /* max_sweeps reached                          */
+#define LCSB_STOP_TARGET     1  /* best.bound >= target (possibly at entry)    */
+#define LCSB_STOP_CONVERGED  2  /* consecutive certificates within stop_delta  */
+#define LCSB_STOP_FLOOR      3  /* best bound gained less than min_gain        */
+
+/* Sweep and certify under policy p until one of its stop conditions holds
+ * (checked after each certificate in the order target, converged, floor,
+ * then the sweep limit).  If the best bound already meets the target, no
+ * sweep is run.  Outputs (each may be NULL): the last certificate (the best
+ * one if none was taken), the best certificate, the number of certificates
+ * taken and the LCSB_STOP_* reason.  Errors are those of lcsb_iterate and
+ * lcsb_certify (an LCSB_ENONFINITE certificate ends the run with that code,
+ * after filling the outputs). */
+int lcsb_run(lcsb_ctx *ctx, const lcsb_run_policy *p, lcsb_cert *cur, lcsb_cert *best,
+             int64_t *certificates, int *stop);
+
+/* Copy the ring of an LCSB_F32 context into an LCSB_F64 context of the same/* Copy the ring of an LCSB_F32 context into an LCSB_F64 context of the same
  * (sigma, d, h) as FP64 values offset + stored value (the switch from FP32
  * sweeps to an FP64 polish).  The sweep count and best certificate move with
  * it.  Enqueued on dst's stream after synchronising src's.  The two rings are

@@ -25,8 +25,8 @@ class Lcsb:
     ``n`` = sigma^(d h) is the number of table indices; every table stores the
     ``stored`` = n / sigma lowest ones (string-1 head 0), the others being
     equal to their image under the symbol relabelling.  Methods mirror the C
-    entry points: init_zero, load_ring, iterate, certify, lag, status,
-    upcast, destroy.
+    entry points: init_zero, load_ring, iterate, certify, run, lag, status,
+    upcast, save, load, destroy.
     """
 
     def __init__(self, sigma: int, d: int, h: int, dtype: str = "f64", device=None,
@@ -102,6 +102,20 @@ class Lcsb:
         if rc != 0 and not (allow_nonfinite and rc == _capi.LCSB_ENONFINITE):
             check(rc)
         return cur.as_dict(), best.as_dict()
+
+    def run(self, cadence: int, first: int = 0, max_sweeps: int = 1 << 40,
+            target: float = float("nan"), stop_delta: float = 0.0, min_gain: float = 0.0):
+        """lcsb_run: sweep and certify every `cadence` sweeps (the first
+        certificate after `first`) until the best bound reaches `target`,
+        consecutive certificates move by less than `stop_delta`, a positive
+        best bound gains less than `min_gain` in a period, or `max_sweeps`.
+        Returns (current, best, certificates, reason)."""
+        pol = _capi.RunPolicy(int(cadence), int(first), int(max_sweeps), float(target),
+                              float(stop_delta), float(min_gain))
+        cur, best, certs, why = Cert(), Cert(), C.c_int64(), C.c_int()
+        check(self._lib.lcsb_run(self._ctx, C.byref(pol), C.byref(cur), C.byref(best),
+                                 C.byref(certs), C.byref(why)))
+        return cur.as_dict(), best.as_dict(), certs.value, _capi.LCSB_STOP_NAMES[why.value]
 
     def lag(self, k: int = 1):
         """(tensor aliasing the stored entries of lag k, its FP64 offset).

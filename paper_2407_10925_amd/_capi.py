@@ -30,6 +30,14 @@ class LcsbError(RuntimeError):
         self.code = code
 
 
+LCSB_STOP_NAMES = {0: "max_sweeps", 1: "target", 2: "converged", 3: "floor"}
+
+
+class RunPolicy(C.Structure):
+    _fields_ = [("cadence", C.c_int64), ("first", C.c_int64), ("max_sweeps", C.c_int64),
+                ("target", C.c_double), ("stop_delta", C.c_double), ("min_gain", C.c_double)]
+
+
 class Cert(C.Structure):
     _fields_ = [("bound", C.c_double), ("R", C.c_double), ("E", C.c_double),
                 ("maxW", C.c_double), ("rho", C.c_double), ("sweep", C.c_int64),
@@ -65,6 +73,8 @@ def load():
     L.lcsb_lag.argtypes = [P, C.c_int, C.POINTER(P), C.POINTER(C.c_double)]
     L.lcsb_status.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(Cert)]
     L.lcsb_upcast.argtypes = [P, P]
+    L.lcsb_run.argtypes = [P, C.POINTER(RunPolicy), C.POINTER(Cert), C.POINTER(Cert),
+                           C.POINTER(C.c_int64), C.POINTER(C.c_int)]
     L.lcsb_save.argtypes = [P, C.c_char_p]
     L.lcsb_load.argtypes = [P, C.c_char_p]
     L.lcsb_destroy.argtypes = [P]
@@ -80,7 +90,7 @@ def load():
     L.lcsb_init_seed_mlp.argtypes = [P, P, P, C.c_double]
     for name in ("lcsb_create", "lcsb_query", "lcsb_bind", "lcsb_init_zero", "lcsb_load_ring",
                  "lcsb_iterate", "lcsb_certify", "lcsb_lag", "lcsb_status", "lcsb_upcast",
-                 "lcsb_save", "lcsb_load", "lcsb_destroy", "lcsb_mlp_workspace", "lcsb_mlp_init", "lcsb_mlp_to_bf16",
+                 "lcsb_run", "lcsb_save", "lcsb_load", "lcsb_destroy", "lcsb_mlp_workspace", "lcsb_mlp_init", "lcsb_mlp_to_bf16",
                  "lcsb_mlp_sample", "lcsb_mlp_forward", "lcsb_mlp_loss", "lcsb_mlp_backward",
                  "lcsb_mlp_adam", "lcsb_init_seed_mlp"):
         getattr(L, name).restype = C.c_int

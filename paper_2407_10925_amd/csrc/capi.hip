@@ -282,6 +282,55 @@ int lcsb_status(const lcsb_ctx *c, int64_t *sweeps, lcsb_cert *best)
     return LCSB_OK;
 }
 
+int lcsb_run(lcsb_ctx *c, const lcsb_run_policy *p, lcsb_cert *cur_out, lcsb_cert *best_out,
+             int64_t *certificates, int *stop)
+{
+    int rc = need_ready(c);
+    if (rc) return rc;
+    if (!p) return fail(LCSB_EINVAL, "policy is null");
+    if (p->cadence <= 0 || p->first < 0 || p->max_sweeps < 0 || !(p->stop_delta >= 0.0) ||
+        !(p->min_gain >= 0.0))
+        return fail(LCSB_EINVAL, "policy: cadence > 0, first >= 0, max_sweeps >= 0, "
+                                 "stop_delta >= 0 and min_gain >= 0 required");
+    const bool use_target = !isnan(p->target);
+    int64_t certs = 0;
+    int why = LCSB_STOP_MAX_SWEEPS;
+    lcsb_cert cur = c->best, best = c->best;
+    if (use_target && best.bound >= p->target) {
+        why = LCSB_STOP_TARGET;
+    } else {
+        const int64_t start = c->sweeps;
+        int64_t step = p->first > 0 ? p->first : p->cadence;
+        bool have_prev = false;
+        double prev = 0.0, best_prev = 0.0;
+        while (c->sweeps - start < p->max_sweeps) {
+            if ((rc = lcsb_iterate(c, step)) != LCSB_OK) return rc;
+            step = p->cadence;
+            rc = lcsb_certify(c, &cur, &best);
+            ++certs;
+            if (rc != LCSB_OK) {
+                if (cur_out) *cur_out = cur;
+                if (best_out) *best_out = best;
+                if (certificates) *certificates = certs;
+                return rc;
+            }
+            if (use_target && best.bound >= p->target) { why = LCSB_STOP_TARGET; break; }
+            if (p->stop_delta > 0.0 && have_prev && fabs(cur.bound - prev) < p->stop_delta &&
+                cur.bound >= best.bound) { why = LCSB_STOP_CONVERGED; break; }
+            if (p->min_gain > 0.0 && have_prev && best.bound > 0.0 &&
+                best.bound - best_prev < p->min_gain) { why = LCSB_STOP_FLOOR; break; }
+            prev = cur.bound;
+            best_prev = best.bound;
+            have_prev = true;
+        }
+    }
+    if (cur_out) *cur_out = cur;
+    if (best_out) *best_out = best;
+    if (certificates) *certificates = certs;
+    if (stop) *stop = why;
+    return LCSB_OK;
+}
+
 int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
 {
     int rc = need_ready(src);

@@ -518,6 +518,60 @@ def test_corrupt_checkpoint_is_refused(pk, tmp_path):
     C.iterate(1)  # refused before the ring was touched: still ready
 
 
+def test_run_driver_matches_the_host_loop(pk):
+    """lcsb_run stops where the same loop of lcsb_iterate / lcsb_certify calls
+    stops, with the same certificates: convergence (stop_delta), a target
+    with a first period, an FP32 error floor (min_gain), a target already
+    met (no sweep), the sweep limit; a bad policy is refused."""
+    say("lcsb_run against host loops")
+    h = 8
+    A = pk.Lcsb(2, 2, h, "f64")
+    A.init_zero()
+    prev, n = None, 0
+    while True:
+        A.iterate(16)
+        cur, best = A.certify()
+        n += 1
+        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
+            break
+        prev = cur["bound"]
+    B = pk.Lcsb(2, 2, h, "f64")
+    B.init_zero()
+    assert B.run(16, stop_delta=1e-10) == (cur, best, n, "converged")
+    target = best["bound"] - 1e-6
+    A.init_zero()
+    step, n = 32, 0
+    while best["bound"] < target or n == 0:
+        A.iterate(step)
+        cur, best = A.certify()
+        n += 1
+        step = 8
+    B.init_zero()
+    assert B.run(8, first=32, target=target) == (cur, best, n, "target")
+    sweeps = B.status()[0]
+    _, best2, n2, why = B.run(8, target=target)
+    assert (n2, why, B.status()[0], best2) == (0, "target", sweeps, best)
+    A = pk.Lcsb(2, 2, h, "f32")
+    A.init_zero()
+    best_prev, n = None, 0
+    while True:
+        A.iterate(16)
+        cur, best = A.certify()
+        n += 1
+        if best["bound"] > 0 and best_prev is not None and best["bound"] - best_prev < 2e-5:
+            break
+        best_prev = best["bound"]
+    C = pk.Lcsb(2, 2, h, "f32")
+    C.init_zero()
+    assert C.run(16, min_gain=2e-5) == (cur, best, n, "floor")
+    C.init_zero()
+    _, _, n, why = C.run(16, max_sweeps=40)
+    assert (n, why, C.status()[0]) == (3, "max_sweeps", 48)
+    with pytest.raises(pk.LcsbError) as e:
+        C.run(0)
+    assert e.value.code == -1
+
+
 # ------------------------------------------------------------------ edges and errors
 def test_zero_sweeps_and_repeatability(pk):
     say("repeatability h=10")

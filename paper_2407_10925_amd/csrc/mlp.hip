@@ -252,8 +252,26 @@ __device__ __forceinline__ uint16_t *ring_slot(int k)
 
 constexpr int kW1Stride = kIn + 8;  // padded LDS row of W1 (80 bytes)
 
+// LDS element offset of W1 row `row`.  The eight lanes of a layer-1 fragment
+// read that LDS serves together take rows b + {0..3, 8..11} at the same
+// 16-byte chunk; with the 80-byte stride alone rows r and r + 8 share banks,
+// so every block of 8 rows starts 64 bytes further on (rows stay disjoint)
+// and the eight chunks fall in distinct bank groups.
+__device__ __forceinline__ int w1_off(int row) { return row * kW1Stride + 32 * (row >> 3); }
+// w1_off(perm_row(f, r)) + 8 g split into a lane part and a per-tile constant
+// (perm_row(f, r) >> 3 = 4 (f >> 1) + (r >> 2)), so the unrolled tile loop
+// reads at one base register plus immediate offsets.
+__device__ __forceinline__ int w1_lane(int r, int g)
+{
+    return (8 * (r >> 2) + (r & 3)) * kW1Stride + 32 * (r >> 2) + 8 * g;
+}
+__host__ __device__ constexpr int w1_tile(int f)
+{
+    return (32 * (f >> 1) + 4 * (f & 1)) * kW1Stride + 128 * (f >> 1);
+}
+
 struct FwdSmem {
-    uint16_t w1[kW * kW1Stride];    // W1, rows padded
+    uint16_t w1[kW * kW1Stride + 32 * (kW / 8 - 1)];  // W1, rows padded and skewed (w1_off)
     float bias[3][kW];              // b1, b2, b3
     uint16_t w4[kW];                // BF16 w4
 };
@@ -349,7 +367,7 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
 
     // resident parameters (once per workgroup)
     for (int q = threadIdx.x; q < kW * kIn / 8; q += kFwdThreads)  // 16-byte chunks
-        *reinterpret_cast<u32x4 *>(sm.w1 + (q >> 2) * kW1Stride + (q & 3) * 8) =
+        *reinterpret_cast<u32x4 *>(sm.w1 + w1_off(q >> 2) + (q & 3) * 8) =
             reinterpret_cast<const u32x4 *>(a.wb + oW1)[q];
     for (int q = threadIdx.x; q < kW; q += kFwdThreads) {
         sm.bias[0][q] = a.pf[ob1 + q];
@@ -391,10 +409,10 @@ __global__ __launch_bounds__(kFwdThreads) void mlp_fwd(FwdArgs a)
 
         // layer 1 (K = 32: one MFMA per output tile, started from the bias)
         uint32_t act[8][NB][4];
+        const uint16_t *w1l = sm.w1 + w1_lane(r, g);
 #pragma unroll
         for (int f = 0; f < 16; ++f) {
-            const bf16x8 wf = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const u32x4 *>(sm.w1 + perm_row(f, r) * kW1Stride + 8 * g));
+            const bf16x8 wf = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(w1l + w1_tile(f)));
             const floatx4 b0 = bias4(sm.bias[0], f, g);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {

@@ -11,8 +11,9 @@ index) over the K timed steps, with the ring already resident in HBM.
 Also printed in the same JSON line:
   roofline      the sweep kernel's algorithmic bytes per launch (12 B per
                 stored entry: lag 1 and lag 2 read once, the new table
-                written once; 6 B per update) over its average launch time,
-                from HIP events on the stream
+                written once; 6 B per update) over its average launch time
+                (traffic_GBps / traffic_frac: the same with the measured HBM
+                bytes), from HIP events on the stream
                 the library launches on, against the 8 TB/s HBM peak; traffic
                 is the rocprofv3-measured HBM bytes per launch when a counter
                 summary for the current kernel source is committed, else null
@@ -37,6 +38,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "updates/s at σ=2,d=2,h=16; time to certified bound, plain vs mixed+learned"
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_s2d2_f32_h16_pmc.json")
+PMC_SUMMARY_F64_H14 = os.path.join(ROOT, "profiles", "sweep_s2d2_f64_h14_pmc.json")
 SWEEP_SRC = os.path.join(ROOT, "paper_2407_10925_amd", "csrc", "sweep.hip")
 
 
@@ -83,11 +85,11 @@ def sweep_source_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+def measured_traffic(path=PMC_SUMMARY):
+    """HBM bytes per sweep launch from a committed rocprofv3 counter summary,
     or None when absent or taken on a different kernel source."""
     try:
-        with open(PMC_SUMMARY) as f:
+        with open(path) as f:
             s = json.load(f)
     except (OSError, ValueError):
         return None
@@ -175,11 +177,17 @@ def fp64_sweep(pk, h, sweeps=32):
     gbs = 24 * L.stored / ms / 1e6
     del L
     torch.cuda.empty_cache()
-    return {"workload": f"sigma=2 d=2 l={h}: {n} FP64 table indices ({n // 2} stored)",
-            "bound": "hbm",
-            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(ms, 4),
-            "updates_per_s": n / ms * 1e3}
+    out = {"workload": f"sigma=2 d=2 l={h}: {n} FP64 table indices ({n // 2} stored)",
+           "bound": "hbm",
+           "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(ms, 4),
+           "updates_per_s": n / ms * 1e3, "traffic": None}
+    traffic = measured_traffic(PMC_SUMMARY_F64_H14) if h == 14 else None
+    if traffic is not None:  # rocprofv3-measured HBM bytes per launch, at this launch time
+        out["traffic"] = traffic
+        out["traffic_GBps"] = round(traffic / ms / 1e6, 1)
+        out["traffic_frac"] = round(traffic / ms / 1e6 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def fp32_error(P, S, chunk=1 << 28):
@@ -555,11 +563,15 @@ def main():
     avg_sweep_s = statistics.mean(sweep_ms) * 1e-3
     algo_bytes = 12 * L.stored  # per launch: (d + 1) tables x 4 bytes per stored entry
     achieved = algo_bytes / avg_sweep_s / 1e9
+    traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(), "kernel": "sweep_s2d2<float>",
+                "traffic": traffic, "kernel": "sweep_s2d2<float>",
                 "algorithmic_bytes_per_launch": algo_bytes,
                 "avg_launch_ms": round(avg_sweep_s * 1e3, 4)}
+    if traffic is not None:  # rocprofv3-measured HBM bytes per launch, at this launch time
+        roofline["traffic_GBps"] = round(traffic / avg_sweep_s / 1e9, 1)
+        roofline["traffic_frac"] = round(traffic / avg_sweep_s / 1e9 / HBM_PEAK_GBS, 4)
     del L
     torch.cuda.empty_cache()
     fp64 = fp64_sweep(pk, 14)

@@ -36,7 +36,13 @@
  *     (balanced binary) tree over the tuples in lexicographic order, c_1 most
  *     significant; the mean is that sum divided by sigma^|N|.  Division by a
  *     power of two is exact, so for sigma in {2,4} this is the exact mean of
- *     the rounded sum.
+ *     the rounded sum.  For sigma = 2 the leaves are the tuples t with
+ *     c_1 = 0, in lexicographic order, each followed by its complement
+ *     (00, 11, 01, 10 for |N| = 2).  Complementing every appended symbol
+ *     maps each pair to itself, and for |N| = 2 so does exchanging the two
+ *     moved strings, so the tree only sees the two operands of some
+ *     additions swapped: F then keeps the complement symmetry of eq. (10)
+ *     and, for d = 2, the exchange of the two strings bit for bit.
  *   - The certificate is made rigorous by directed rounding: the arguments
  *     v_d + (d-k)R and every step of F are rounded toward -inf, W and E
  *     toward +inf, and the reported bound d (R - E) toward -inf.  The C
@@ -157,6 +163,15 @@ static double F_z(const or_shape *s, const or_args *a, const int *sym, int z,
         }
         buf[t] = lag_value(a, k, encode(s, work));
     }
+    if (s->sigma == 2 && count > 2) {
+        /* complement-paired leaf order: t, ~t for t = 0 .. count/2 - 1 */
+        double *leaves = buf + count;  /* the scratch holds 2 sigma^d values */
+        for (uint64_t j = 0; j < count; ++j) {
+            uint64_t t = j >> 1;
+            leaves[j] = buf[(j & 1) ? count - 1 - t : t];
+        }
+        return pairwise_sum(leaves, count) / (double)count;
+    }
     return pairwise_sum(buf, count) / (double)count;
 }
 
@@ -220,7 +235,7 @@ typedef struct { double *buf; int *sym; int *work; } or_scratch;
 
 static int scratch_alloc(const or_shape *s, or_scratch *w)
 {
-    w->buf = (double *)malloc(sizeof(double) * ipow(s->sigma, s->d));
+    w->buf = (double *)malloc(2 * sizeof(double) * ipow(s->sigma, s->d));
     w->sym = (int *)malloc(sizeof(int) * (size_t)(s->d * s->h));
     w->work = (int *)malloc(sizeof(int) * (size_t)(s->d * s->h));
     return (w->buf && w->sym && w->work) ? 0 : -1;

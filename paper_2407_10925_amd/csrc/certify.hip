@@ -161,7 +161,8 @@ struct Scales {
 
 // In round-toward-minus-infinity mode: mean over CNT values of (v + shift),
 // every add rounded down, the pairwise tree in the given order, the exact
-// power-of-two scaling rounded down.
+// power-of-two scaling rounded down.  Callers pass sigma = 2 groups in the
+// complement-paired leaf order of the sweep (t, ~t for t = 0, 1, ..).
 template <int CNT>
 __device__ __forceinline__ double mean_rd(double *v, double shift, double scale)
 {
@@ -200,8 +201,9 @@ __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint
 {
     const uint64_t nq = n >> 2, xc = nq - 1 - t;
     const uint64_t am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
-    double g[4];
-    ld4(u + 4 * t, g);
+    double q4[4];
+    ld4(u + 4 * t, q4);
+    double g[4] = {q4[0], q4[3], q4[1], q4[2]};
     const double f_match = 1.0 + mean_rd<4>(g, shift[2], sc.q[2]);
     best.add((double)u[t], f_match, dR_up, t);
     best.add((double)u[xc], f_match, dR_up, xc);
@@ -281,15 +283,17 @@ __device__ __forceinline__ double branch23(const T *__restrict__ u, uint64_t n, 
     const uint64_t r3 = (n - 1) / 7;
     const uint64_t sm = ((SET & 4) ? r3 << 2 : 0) | ((SET & 2) ? r3 << 1 : 0) | ((SET & 1) ? r3 : 0);
     const uint64_t base = (i & ~sm) | ((i << 3) & sm & (n - 1));
-    double v[K == 1 ? 2 : 4];
+    double lx[K == 1 ? 2 : 4];
     int k = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c)  // appended tuples in lexicographic order of the moved strings
         if ((c & ~SET) == 0) {
             const uint64_t e = base | (uint64_t)c;
-            v[k++] = (double)u[img ? (n - 1) - e : e];
+            lx[k++] = (double)u[img ? (n - 1) - e : e];
         }
-    return K == 1 ? mean_rd<2>(v, shift[1], sc.q[1]) : mean_rd<4>(v, shift[2], sc.q[2]);
+    if constexpr (K == 1) return mean_rd<2>(lx, shift[1], sc.q[1]);
+    double v[4] = {lx[0], lx[3], lx[1], lx[2]};  // complement-paired leaves
+    return mean_rd<4>(v, shift[2], sc.q[2]);
 }
 
 template <typename T>
@@ -299,9 +303,10 @@ __device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int 
 {
     const int top = 3 * (h - 1);
     const uint64_t xc = (n >> 3) - 1 - t;
-    double g[8];
-    ld4(u + 8 * t, g);
-    ld4(u + 8 * t + 4, g + 4);
+    double q8[8];
+    ld4(u + 8 * t, q8);
+    ld4(u + 8 * t + 4, q8 + 4);
+    double g[8] = {q8[0], q8[7], q8[1], q8[6], q8[2], q8[5], q8[3], q8[4]};
     const double f_match = 1.0 + mean_rd<8>(g, shift[3], sc.q[3]);
     best.add((double)u[t], f_match, dR_up, t);
     best.add((double)u[xc], f_match, dR_up, xc);
@@ -375,6 +380,11 @@ struct L1 {
         }
         return head;
     }
+    template <int CNT>  // appended tuple at leaf j of the branch tree
+    static __device__ __forceinline__ int leaf(int j)
+    {
+        return SIGMA == 2 && (j & 1) ? CNT - 1 - (j >> 1) : SIGMA == 2 ? j >> 1 : j;
+    }
 };
 
 // In round-toward-minus-infinity mode: the branch mean of moved set `moved`
@@ -391,7 +401,8 @@ __device__ __forceinline__ double l1_branch_rd(const T *__restrict__ u, const do
         constexpr int K = __builtin_popcount(M), CNT = 1 << (G::kBeta * K);
         double v[CNT];
 #pragma unroll
-        for (int c = 0; c < CNT; ++c) v[c] = (double)u[G::image(G::template successor<M>(head, c))];
+        for (int c = 0; c < CNT; ++c)
+            v[c] = (double)u[G::image(G::template successor<M>(head, G::template leaf<CNT>(c)))];
         return mean_rd<CNT>(v, shift[K], sc.q[G::kBeta * K]);
     }
 }

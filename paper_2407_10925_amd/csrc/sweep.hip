@@ -25,8 +25,11 @@
 // lag table is then read at most twice and the output written once.
 //
 // Arithmetic (bit-exact with the FP64 reference): each branch sums its
-// sigma^k values with a balanced binary tree in lexicographic order of the
-// appended symbols (first advanced string most significant), multiplies by
+// sigma^k values with a balanced binary tree over the appended tuples in
+// lexicographic order (first advanced string most significant); for sigma = 2
+// the leaves are the tuples t starting with 0, each followed by its complement
+// ~t (00, 11, 01, 10), so that complementing the symbols, and for two moved
+// strings exchanging them, maps every pair to itself.  It multiplies by
 // the exact power of two sigma^-k, takes the max over branches, and adds 1 to
 // all-match tuples.  FP32 tables store values relative to a per-slot FP64
 // offset: a branch reading lag k adds delta_k = offset(lag k) - offset(lag 1)
@@ -41,6 +44,17 @@ namespace {
 
 template <typename T>
 __device__ __forceinline__ T tree4(T a, T b, T c, T d) { return (a + b) + (c + d); }
+
+// sigma = 2 groups, members in lexicographic order of the appended bits:
+// complement-paired trees
+template <typename T>
+__device__ __forceinline__ T pair4(T m0, T m1, T m2, T m3) { return (m0 + m3) + (m1 + m2); }
+
+template <typename T>
+__device__ __forceinline__ T pair8(const T *g)
+{
+    return ((g[0] + g[7]) + (g[1] + g[6])) + ((g[2] + g[5]) + (g[3] + g[4]));
+}
 
 template <typename T>
 __device__ __forceinline__ T tree8(const T *g)
@@ -142,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
     if constexpr (kF32) {
         const double o1 = off[s1];
         d2 = (float)(off[s2] - o1);
-        y0 = 1.0f + (tree4(lag2[0], lag2[1], lag2[2], lag2[3]) * 0.25f + d2);
+        y0 = 1.0f + (pair4(lag2[0], lag2[1], lag2[2], lag2[3]) * 0.25f + d2);
         if (t == 0) off[snew] = o1 + (double)y0;
     }
     if (t >= (n >> 3)) return;
@@ -150,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
 
     T g[4];
     stream4<true>(lag2 + 4 * t, g);
-    T m2 = tree4(g[0], g[1], g[2], g[3]) * (T)0.25;
+    T m2 = pair4(g[0], g[1], g[2], g[3]) * (T)0.25;
     if constexpr (kF32) m2 = m2 + d2;
     const T match = (T)1 + m2;
 
@@ -272,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
         d3 = (float)(off[s3] - o1);
         T g0[8];
         load8(lag3, g0);
-        y0 = 1.0f + (tree8(g0) * 0.125f + d3);
+        y0 = 1.0f + (pair8(g0) * 0.125f + d3);
         if (t == 0) off[snew] = o1 + (double)y0;
     }
     if (t >= (n >> 4)) return;
@@ -281,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
     T g[8];
     stream4<kF32>(lag3 + 8 * t, g);  // read once: non-temporal in FP32 (4.8% faster)
     stream4<kF32>(lag3 + 8 * t + 4, g + 4);
-    T all3 = tree8(g) * (T)0.125;
+    T all3 = pair8(g) * (T)0.125;
     if constexpr (kF32) all3 = all3 + d3;
     const T match = (T)1 + all3;
 
@@ -309,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
             T q[8];
             group(lag2, b2, c, q);
             const int o = (int)(b2 & 1) ^ c;
-            T k2 = tree4(q[o], q[o + 2], q[o + 4], q[o + 6]) * (T)0.25;
+            T k2 = pair4(q[o], q[o + 2], q[o + 4], q[o + 6]) * (T)0.25;
             if constexpr (kF32) k2 = k2 + d2;
             val[1] = vmax(k1, k2);
         }
@@ -323,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
             T q[8];
             group(lag2, b2, c, q);
             const int o2 = c ? 2 - (int)(b2 & 7) : (int)(b2 & 7);
-            T k2 = tree4(q[o2], q[o2 + 1], q[o2 + 4], q[o2 + 5]) * (T)0.25;
+            T k2 = pair4(q[o2], q[o2 + 1], q[o2 + 4], q[o2 + 5]) * (T)0.25;
             if constexpr (kF32) k2 = k2 + d2;
             val[2] = vmax(k1, k2);
         }
@@ -332,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
             const uint64_t b2 = base(i, S2 | S3), b1 = base(i, S1);
             T q[4];
             load4(lag2 + b2, q);
-            T k2 = tree4(q[0], q[1], q[2], q[3]) * (T)0.25;
+            T k2 = pair4(q[0], q[1], q[2], q[3]) * (T)0.25;
             if constexpr (kF32) k2 = k2 + d2;
             T e[8];
             group(lag1, b1, c, e);
@@ -372,6 +386,12 @@ struct L1 {
         }
         return head;
     }
+    // appended tuple at leaf j of the branch tree over CNT tuples
+    template <int CNT>
+    static __device__ __forceinline__ int leaf(int j)
+    {
+        return SIGMA == 2 && (j & 1) ? CNT - 1 - (j >> 1) : SIGMA == 2 ? j >> 1 : j;
+    }
 };
 
 template <typename T, int CNT>
@@ -397,7 +417,8 @@ __device__ __forceinline__ T l1_branch(const T *const *lag, const T *delta, int 
         constexpr int K = __builtin_popcount(M), CNT = 1 << (G::kBeta * K);
         T v[CNT];
 #pragma unroll
-        for (int c = 0; c < CNT; ++c) v[c] = lag[K - 1][G::image(G::template successor<M>(head, c))];
+        for (int c = 0; c < CNT; ++c)
+            v[c] = lag[K - 1][G::image(G::template successor<M>(head, G::template leaf<CNT>(c)))];
         T m = tree_pow2<T, CNT>(v) * ((T)1 / (T)CNT);
         if (std::is_same<T, float>::value && K >= 2) m = m + delta[K - 1];
         return m;

@@ -107,19 +107,49 @@ def test_certificate_nonfinite_is_counted(orc):
 
 def test_summation_tree_convention(orc):
     """Reading of an unstated detail: the sigma^k appended tuples (c_1..c_k)
-    are visited in lexicographic order, c_1 (the symbol appended to the
-    first advanced string) most significant, and summed by a balanced binary
-    tree, left half first.  A lag-2 group whose sum depends on that order
-    (1 + 2^53 rounds to 2^53) fixes it: for the 0/0 pair x = 0 of l = 1 the
-    group is lag-2 entries 0..3 in (c_1, c_2) order 00, 01, 10, 11."""
+    are summed by a balanced binary tree, left half first; for sigma = 2 the
+    leaves are the tuples with c_1 = 0 in lexicographic order, each followed
+    by its complement, so a lag-2 group (c_1 c_2 = 00, 01, 10, 11) is summed
+    as (00 + 11) + (01 + 10).  Entries around 2^53, where the rounding of a
+    sum depends on the association, tell that order from the lexicographic
+    one and from the transposed one: for the 0/0 pair x = 0 of l = 1 the
+    group is lag-2 entries 0..3."""
     big = 2.0 ** 53
-    lag2 = np.array([big, 1.0, -big, 1.0])
+    a, b, c, d = big, 1.0, 0.5, -big          # members 00, 01, 10, 11
+    lag2 = np.array([a, b, c, d])
     lag1 = np.zeros(4)
     F = orc.sweep(2, 2, 1, [lag1, lag2])
-    tree = ((big + 1.0) + (-big + 1.0)) / 4       # = 1/4
-    transposed = ((big + -big) + (1.0 + 1.0)) / 4  # = 1/2
-    assert tree != transposed
-    assert F[0] == 1.0 + tree
+    paired = ((a + d) + (b + c)) / 4       # 3/8
+    lexicographic = ((a + b) + (c + d)) / 4  # 0
+    transposed = ((a + c) + (b + d)) / 4   # 1/4
+    assert len({paired, lexicographic, transposed}) == 3
+    assert F[0] == 1.0 + paired
+
+
+@pytest.mark.parametrize("d,h", [(2, 2), (2, 3), (3, 2)])
+def test_sigma2_tree_keeps_string_exchange_bit_for_bit(orc, d, h):
+    """With the complement-paired order, a sweep of tables symmetric under
+    exchanging strings 1 and 2 returns a table with the same symmetry bit
+    for bit: the all-advance pairs t, ~t map to themselves or to each other,
+    a branch moving strings 1 and 2 keeps its pairs, and a branch moving one
+    of them and string 3 becomes the branch moving the other, with its
+    leaves in the same order.  Random values over sixty binades make any
+    other association of the lag-2 (d = 2) or lag-3 (d = 3) group round
+    differently somewhere."""
+    sigma = 2
+    n = sigma ** (d * h)
+    rng = np.random.default_rng(7 + d * 10 + h)
+    swap = np.empty(n, dtype=np.int64)
+    for i in range(n):
+        s = orc.decode(sigma, d, h, i).copy()
+        s[[0, 1]] = s[[1, 0]]
+        swap[i] = orc.encode(sigma, d, h, s)
+    lags = []
+    for _ in range(d):
+        v = rng.standard_normal(n) * np.exp2(rng.integers(-30, 30, n).astype(np.float64))
+        lags.append(np.maximum(v, v[swap]))
+    out = orc.sweep(sigma, d, h, lags)
+    assert np.array_equal(out, out[swap])
 
 
 @pytest.mark.parametrize("sigma,d,h,n", [(3, 2, 1, 80), (2, 2, 1, 60), (2, 2, 2, 120)])

@@ -119,14 +119,17 @@ int lcsb_init_zero(lcsb_ctx *ctx);
  * with src at the stored indices.  offsets (host, d doubles, may be NULL =
  * all zero) are the values the FP32 tables are relative to (true value =
  * offset + stored value); ignored for LCSB_F64.  Resets the sweep count and
- * the best certificate. */
+ * the best certificate.  For sigma = d = 2 it then checks whether the ring
+ * is symmetric under exchanging the two strings (see lcsb_swap_symmetric;
+ * one read of the ring, synchronises the stream). */
 int lcsb_load_ring(lcsb_ctx *ctx, const void *const *src, int nsrc, const double *offsets);
 
 /* Apply k >= 0 sweeps v_new = F(lag 1, .., lag d) of eq. (4) on the bound
  * stream; the new table becomes lag 1.  In LCSB_F64 every value is computed
  * in FP64, round to nearest, summing the sigma^k appended tuples by a
  * balanced binary tree in lexicographic order (appended symbol of the first
- * advanced string most significant) and multiplying by sigma^-k.  In
+ * advanced string most significant; for sigma = 2 each tuple starting with 0
+ * followed by its complement: 00, 11, 01, 10) and multiplying by sigma^-k.  In
  * LCSB_F32 the same is done in FP32 relative to lag 1's offset, and the new
  * table is shifted so that its entry 0 is exactly 0 (translation invariance,
  * property 2 of the lemma); the FP64 offsets stay on the device. */
@@ -145,6 +148,16 @@ int lcsb_certify(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
  * values are relative to (read from the device; synchronises).  The pointer
  * stays valid until the next lcsb_iterate, lcsb_load_ring or lcsb_bind. */
 int lcsb_lag(const lcsb_ctx *ctx, int k, void **dev_ptr, double *offset);
+
+/* sigma = d = 2, l >= 2: *symmetric = 1 when every lag table is known to be
+ * symmetric, bit for bit, under exchanging the two strings (after
+ * lcsb_init_zero, lcsb_init_seed_mlp, a load_ring or load of such a ring, an
+ * upcast of such a ring, and every sweep of such a ring: F keeps the
+ * symmetry exactly).  lcsb_iterate and lcsb_certify then run on one tuple of
+ * each exchanged pair and write or count both, which halves the bytes they
+ * read; otherwise (and for every other shape) *symmetric = 0 and every tuple
+ * is computed.  The results are the same bits either way. */
+int lcsb_swap_symmetric(const lcsb_ctx *ctx, int *symmetric);
 
 /* Number of sweeps applied since the last init, and the best certificate. */
 int lcsb_status(const lcsb_ctx *ctx, int64_t *sweeps, lcsb_cert *best);
@@ -207,7 +220,8 @@ int lcsb_save(const lcsb_ctx *ctx, const char *path);
  * truncated or corrupt file gives LCSB_ECKPT.  A table hash mismatch is only
  * found while the ring is being overwritten: the context is then left bound
  * but not initialised (iterate and certify return LCSB_ESTATE until an init
- * call or a good load).  Synchronises the stream. */
+ * call or a good load).  Checks the exchange symmetry as lcsb_load_ring
+ * does.  Synchronises the stream. */
 int lcsb_load(lcsb_ctx *ctx, const char *path);
 
 /* ------------------------------------------------------------------------

@@ -26,7 +26,7 @@ class Lcsb:
     ``stored`` = n / sigma lowest ones (string-1 head 0), the others being
     equal to their image under the symbol relabelling.  Methods mirror the C
     entry points: init_zero, load_ring, iterate, certify, run, lag, status,
-    upcast, save, load, destroy.
+    upcast, save, load, swap_symmetric, destroy.
     """
 
     def __init__(self, sigma: int, d: int, h: int, dtype: str = "f64", device=None,
@@ -131,6 +131,13 @@ class Lcsb:
         s, best = C.c_int64(), Cert()
         check(self._lib.lcsb_status(self._ctx, C.byref(s), C.byref(best)))
         return s.value, best.as_dict()
+
+    def swap_symmetric(self) -> bool:
+        """Whether the ring is known to be symmetric in the two strings
+        (sigma = d = 2): sweeps and certificates then read half the bytes."""
+        v = C.c_int()
+        check(self._lib.lcsb_swap_symmetric(self._ctx, C.byref(v)))
+        return bool(v.value)
 
     def init_seed_mlp(self, mlp: "Mlp", rate: float):
         """Fill the ring from the warm-start network: lag 2 = u, lag 1 = u + rate."""

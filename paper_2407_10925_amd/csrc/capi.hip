@@ -48,6 +48,7 @@ struct lcsb_ctx {
     int head;        // ring slot holding lag 1
     int64_t sweeps;  // sweeps since the last init
     lcsb_cert best;
+    int swap_sym;    // sigma = d = 2, l >= 2: lag 1 .. d symmetric in the two strings
 };
 
 namespace {
@@ -67,6 +68,29 @@ int need_ready(const lcsb_ctx *c)
     if (!c) return fail(LCSB_EINVAL, "null context");
     if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
     if (c->state != kReady) return fail(LCSB_ESTATE, "context not initialised (bind, then init)");
+    return LCSB_OK;
+}
+
+// the exchange-folded kernels apply to sigma = d = 2 at l >= 2
+bool swap_shape(const lcsb_ctx *c) { return c->g.sigma == 2 && c->g.d == 2 && c->g.h >= 2; }
+
+// Set c->swap_sym by checking lag 1 .. d on the device (synchronises).
+int refresh_swap(lcsb_ctx *c)
+{
+    c->swap_sym = 0;
+    if (!swap_shape(c)) return LCSB_OK;
+    uint32_t *flag = reinterpret_cast<uint32_t *>(c->ws + Ws::kAsym);
+    hipError_t e;
+    if ((e = launch_fill_zero(flag, 4, c->stream)) != hipSuccess) return hip_fail(c, e, "fill");
+    for (int k = 1; k <= c->g.d; ++k)
+        if ((e = launch_check_swap(c->g, c->dtype, c->buf[slot_of_lag(c, k)], flag, c->stream)) !=
+            hipSuccess)
+            return hip_fail(c, e, "symmetry check");
+    uint32_t host = 1;
+    if ((e = hipMemcpyAsync(&host, flag, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "symmetry copy");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "symmetry sync");
+    c->swap_sym = host == 0;
     return LCSB_OK;
 }
 
@@ -142,6 +166,7 @@ int lcsb_bind(lcsb_ctx *c, void *const *bufs, int nbuf, void *ws, void *stream)
     c->head = 0;
     c->sweeps = 0;
     c->best = initial_best();
+    c->swap_sym = 0;
     return LCSB_OK;
 }
 
@@ -160,6 +185,7 @@ int lcsb_init_zero(lcsb_ctx *c)
     c->head = 0;
     c->sweeps = 0;
     c->best = initial_best();
+    c->swap_sym = swap_shape(c);
     c->state = kReady;
     return LCSB_OK;
 }
@@ -194,6 +220,8 @@ int lcsb_load_ring(lcsb_ctx *c, const void *const *src, int nsrc, const double *
     }
     c->sweeps = 0;
     c->best = initial_best();
+    int rc = refresh_swap(c);
+    if (rc) return rc;
     c->state = kReady;
     return LCSB_OK;
 }
@@ -213,6 +241,7 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
         a.new_slot = (c->head + 1) % c->nbuf;
         a.out = c->buf[a.new_slot];
         a.offsets = reinterpret_cast<double *>(c->ws + Ws::kOffsets);
+        a.swap_sym = c->swap_sym;
         hipError_t e = launch_sweep(c->g, c->dtype, a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
         c->head = a.new_slot;
@@ -226,7 +255,8 @@ int lcsb_certify(lcsb_ctx *c, lcsb_cert *cur, lcsb_cert *best)
     int rc = need_ready(c);
     if (rc) return rc;
     const int su = slot_of_lag(c, 1), sp = slot_of_lag(c, 2);
-    hipError_t e = launch_certify(c->g, c->dtype, c->buf[su], c->buf[sp], su, sp, c->ws, c->stream);
+    hipError_t e = launch_certify(c->g, c->dtype, c->buf[su], c->buf[sp], su, sp, c->swap_sym,
+                                  c->ws, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "certify launch");
     unsigned char host[Ws::kScalarBytes];
     if ((e = hipMemcpyAsync(host, c->ws, Ws::kScalarBytes, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
@@ -271,6 +301,15 @@ int lcsb_lag(const lcsb_ctx *c, int k, void **dev_ptr, double *offset)
             if (e != hipSuccess) return fail(LCSB_EHIP, "offset read: %s", hipGetErrorString(e));
         }
     }
+    return LCSB_OK;
+}
+
+int lcsb_swap_symmetric(const lcsb_ctx *c, int *symmetric)
+{
+    int rc = need_ready(c);
+    if (rc) return rc;
+    if (!symmetric) return fail(LCSB_EINVAL, "null output");
+    *symmetric = c->swap_sym;
     return LCSB_OK;
 }
 
@@ -366,6 +405,7 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
     }
     dst->sweeps = src->sweeps;
     dst->best = src->best;
+    dst->swap_sym = src->swap_sym;
     dst->state = kReady;
     return LCSB_OK;
 }
@@ -489,6 +529,7 @@ int lcsb_init_seed_mlp(lcsb_ctx *c, const float *params, const uint16_t *wbf16, 
         return hip_fail(c, e, "seed");
     c->sweeps = 0;
     c->best = initial_best();
+    c->swap_sym = swap_shape(c);  // one value per exchange orbit
     c->state = kReady;
     return LCSB_OK;
 }
@@ -685,6 +726,8 @@ int lcsb_load(lcsb_ctx *c, const char *path)
     c->best.bound = hd.bound; c->best.R = hd.R; c->best.E = hd.E; c->best.maxW = hd.maxW;
     c->best.rho = hd.rho; c->best.sweep = hd.best_sweep;
     c->best.argmax_W = hd.argmax_W; c->best.nonfinite = hd.nonfinite;
+    const int rc = refresh_swap(c);
+    if (rc) return rc;
     c->state = kReady;
     return LCSB_OK;
 }

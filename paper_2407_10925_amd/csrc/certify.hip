@@ -175,17 +175,23 @@ __device__ __forceinline__ double mean_rd(double *v, double shift, double scale)
     return v[0] * scale;
 }
 
+// F's max over branch means starts from -inf (a NaN branch never wins, every
+// branch NaN gives -inf): the first value of each max chain goes through this.
+__device__ __forceinline__ double first(double v) { return v > -INFINITY ? v : -INFINITY; }
+
 struct WBest {
     double w = -INFINITY;
     uint64_t arg = 0, nonfinite = 0;
     // In round-toward-minus-infinity mode: W = RU(RU(u_i + dR_up) - f_lo)
     // = -RD(RD(-u_i - dR_up) + f_lo).  Candidates arrive in any order: keep
     // the max, lowest index on ties.
-    __device__ __forceinline__ void add(double u_i, double f_lo, double dR_up, uint64_t i)
+    // `mult`: how many coordinates of equal W this evaluation stands for
+    __device__ __forceinline__ void add(double u_i, double f_lo, double dR_up, uint64_t i,
+                                        int mult = 1)
     {
         const double t = (-u_i) - dR_up;
         const double w_i = -(t + f_lo);
-        if (!isfinite(w_i)) ++nonfinite;
+        if (!isfinite(w_i)) nonfinite += (uint64_t)mult;
         if (w_i > w || (w_i == w && i < arg)) { w = w_i; arg = i; }
     }
 };
@@ -194,19 +200,35 @@ struct WBest {
 // 0/0|xc, 0/1|t, 0/1|xc (xc = n/4-1-t, the complement of t).  The lag-2 group
 // of xc is the image of the one of t; the advance-a pair of 0/1|xc is read in
 // the image group at the other parity (see the sweep).
-template <typename T>
+// SWAP (a table symmetric under exchanging the strings): W is then equal, bit
+// for bit, at exchanged tuples (the trees are exchange-invariant), so only the
+// lower of the threads t and p (St or ~St, as in the sweep) evaluates, each
+// value standing for two coordinates unless p = t.  The lowest index of each
+// pair is t, ~St, 0/1|t and 0/1|St.
+template <typename T, bool SWAP>
 __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint64_t t,
                                       const double *shift, const Scales &sc, double dR_up,
                                       WBest &best)
 {
     const uint64_t nq = n >> 2, xc = nq - 1 - t;
+    uint64_t rep_xc = xc, rep_mis1 = nq + xc;
+    int mult = 1;
+    if constexpr (SWAP) {
+        const uint64_t mq = nq - 1, aq = 0xAAAAAAAAAAAAAAAAull & mq;
+        const uint64_t st = ((t & aq) >> 1) | ((t & ~aq & mq) << 1);
+        const uint64_t p = (t & (nq >> 2)) ? st ^ mq : st;
+        if (p < t) return;
+        mult = p == t ? 1 : 2;
+        rep_xc = mq - st;
+        rep_mis1 = nq + st;
+    }
     const uint64_t am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
     double q4[4];
     ld4(u + 4 * t, q4);
     double g[4] = {q4[0], q4[3], q4[1], q4[2]};
-    const double f_match = 1.0 + mean_rd<4>(g, shift[2], sc.q[2]);
-    best.add((double)u[t], f_match, dR_up, t);
-    best.add((double)u[xc], f_match, dR_up, xc);
+    const double f_match = 1.0 + first(mean_rd<4>(g, shift[2], sc.q[2]));
+    best.add((double)u[t], f_match, dR_up, t, mult);
+    best.add((double)u[xc], f_match, dR_up, rep_xc, mult);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const uint64_t i = nq + (c ? xc : t);
@@ -221,7 +243,8 @@ __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint
         pa[0] = q[o]; pa[1] = q[o + 2];
         const double mb = mean_rd<2>(pb, shift[1], sc.q[1]);
         const double ma = mean_rd<2>(pa, shift[1], sc.q[1]);
-        best.add((double)u[i], ma > mb ? ma : mb, dR_up, i);
+        const double fb = first(mb);  // z = 0 advances b
+        best.add((double)u[i], ma > fb ? ma : fb, dR_up, c ? rep_mis1 : i, mult);
     }
 }
 
@@ -241,7 +264,7 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
 #pragma unroll
     for (int k = 0; k < 16; k += 4) ld4(u + 16 * t + k, g + k);
     const double m_both = mean_rd<16>(g, shift[2], sc.q[4]);
-    const double f_match = 1.0 + m_both;
+    const double f_match = 1.0 + first(m_both);
     double ma[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -262,7 +285,8 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
 #pragma unroll
         for (int b1 = 1; b1 < 4; ++b1) {
             const uint64_t i = ((uint64_t)b1 << top) | x;
-            double f = mb > ma[b1 ^ m] ? mb : ma[b1 ^ m];
+            double f = first(mb);  // z = 0 advances b
+            f = ma[b1 ^ m] > f ? ma[b1 ^ m] : f;
             f = m_both > f ? m_both : f;
             best.add((double)u[i], f, dR_up, i);
         }
@@ -307,7 +331,7 @@ __device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int 
     ld4(u + 8 * t, q8);
     ld4(u + 8 * t + 4, q8 + 4);
     double g[8] = {q8[0], q8[7], q8[1], q8[6], q8[2], q8[5], q8[3], q8[4]};
-    const double f_match = 1.0 + mean_rd<8>(g, shift[3], sc.q[3]);
+    const double f_match = 1.0 + first(mean_rd<8>(g, shift[3], sc.q[3]));
     best.add((double)u[t], f_match, dR_up, t);
     best.add((double)u[xc], f_match, dR_up, xc);
 #pragma unroll
@@ -319,14 +343,15 @@ __device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int 
             const double b1 = branch23<(H), T>(u, n, i, ((H) & 4) ? c : 0, shift, sc);        \
             const double b0 = branch23<(~(H)) & 7, T>(u, n, i, ((~(H)) & 4) ? c : 0, shift,  \
                                                       sc);                                      \
-            best.add((double)u[i], b0 > b1 ? b0 : b1, dR_up, i);                                \
+            const double f0 = first(b0);                                                    \
+            best.add((double)u[i], b1 > f0 ? b1 : f0, dR_up, i);                                \
         }
         LCSB_HEAD(1) LCSB_HEAD(2) LCSB_HEAD(3)
 #undef LCSB_HEAD
     }
 }
 
-template <int SIGMA, int D, typename T>
+template <int SIGMA, int D, typename T, bool SWAP = false>
 __global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u_arg, uint64_t n, int h,
                                                 unsigned char *__restrict__ ws)
 {
@@ -343,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u_arg, ui
     WBest best;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < nt; t += stride) {
-        if constexpr (SIGMA == 2 && D == 2) w_s2d2<T>(u, n, t, shift, sc, dR_up, best);
+        if constexpr (SIGMA == 2 && D == 2) w_s2d2<T, SWAP>(u, n, t, shift, sc, dR_up, best);
         else if constexpr (SIGMA == 4) w_s4d2<T>(u, n, h, t, shift, sc, dR_up, best);
         else w_s2d3<T>(u, n, h, t, shift, sc, dR_up, best);
     }
@@ -432,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void cert_w_l1(const T *__restrict__ u_arg,
         }
         double f;
         if (same) {
-            f = 1.0 + l1_branch_rd<T, SIGMA, D, 1>(u, shift, sc, j, (1 << D) - 1);
+            f = 1.0 + first(l1_branch_rd<T, SIGMA, D, 1>(u, shift, sc, j, (1 << D) - 1));
         } else {
             f = -INFINITY;
 #pragma unroll
@@ -481,7 +506,8 @@ int reduce_blocks(uint64_t n)
 }
 
 template <typename T>
-hipError_t launch_w(const Geometry &g, const T *u, unsigned char *ws, int nbw, hipStream_t s)
+hipError_t launch_w(const Geometry &g, const T *u, int swap_sym, unsigned char *ws, int nbw,
+                    hipStream_t s)
 {
     if (g.h == 1 && g.sigma == 2 && g.d == 2)
         cert_w_l1<T, 2, 2><<<1, kBlock, 0, s>>>(u, ws);
@@ -491,6 +517,8 @@ hipError_t launch_w(const Geometry &g, const T *u, unsigned char *ws, int nbw, h
         cert_w_l1<T, 2, 3><<<1, kBlock, 0, s>>>(u, ws);
     else if (g.h == 1)
         return hipErrorInvalidValue;
+    else if (g.sigma == 2 && g.d == 2 && swap_sym)
+        cert_w<2, 2, T, true><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else if (g.sigma == 2 && g.d == 2)
         cert_w<2, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else if (g.sigma == 4 && g.d == 2)
@@ -504,7 +532,7 @@ hipError_t launch_w(const Geometry &g, const T *u, unsigned char *ws, int nbw, h
 
 template <typename T>
 hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int u_slot,
-                         int prev_slot, unsigned char *ws, hipStream_t s)
+                         int prev_slot, int swap_sym, unsigned char *ws, hipStream_t s)
 {
     const int nb = reduce_blocks(g.ns);
     cert_r<T><<<nb, kBlock, 0, s>>>(static_cast<const T *>(u), static_cast<const T *>(prev),
@@ -516,7 +544,8 @@ hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // one thread per x with string-1 symbol 0 at position 2 (one workgroup at l = 1)
     const int nbw = g.h == 1 ? 1 : reduce_blocks(g.n >> (g.slot + g.beta));
-    if ((e = launch_w<T>(g, static_cast<const T *>(u), ws, nbw, s)) != hipSuccess) return e;
+    if ((e = launch_w<T>(g, static_cast<const T *>(u), swap_sym, ws, nbw, s)) != hipSuccess)
+        return e;
     cert_w_final<<<1, kBlock, 0, s>>>(ws, nbw);
     return hipGetLastError();
 }
@@ -524,10 +553,12 @@ hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int
 }  // namespace
 
 hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const void *prev,
-                          int u_slot, int prev_slot, unsigned char *ws, hipStream_t s)
+                          int u_slot, int prev_slot, int swap_sym, unsigned char *ws,
+                          hipStream_t s)
 {
-    return dtype == LCSB_F32 ? certify_typed<float>(g, u, prev, u_slot, prev_slot, ws, s)
-                             : certify_typed<double>(g, u, prev, u_slot, prev_slot, ws, s);
+    return dtype == LCSB_F32
+               ? certify_typed<float>(g, u, prev, u_slot, prev_slot, swap_sym, ws, s)
+               : certify_typed<double>(g, u, prev, u_slot, prev_slot, swap_sym, ws, s);
 }
 
 }  // namespace lcsb

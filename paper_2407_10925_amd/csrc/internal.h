@@ -23,6 +23,7 @@ struct Ws {
     static constexpr size_t kNonfinite = 64; // uint64: W pass
     static constexpr size_t kNonfiniteR = 72;// uint64: R pass (u, prev)
     static constexpr size_t kScalarBytes = 80;
+    static constexpr size_t kAsym = 128;     // uint32: set when a table is not exchange-symmetric
     // FP64 offsets of the FP32 tables, one per ring slot
     static constexpr size_t kOffsets = 256;  // double[8]
     // per-workgroup partials of the reductions
@@ -45,18 +46,26 @@ struct SweepLaunch {
     int lag_slot[3];
     int new_slot;
     double *offsets;  // device, per slot (FP32 only)
+    int swap_sym;     // sigma = d = 2: the lag tables are symmetric under exchanging the strings
 };
 
 hipError_t launch_sweep(const Geometry &g, int dtype, const SweepLaunch &a, hipStream_t s);
 
 // Certificate passes (see lcsb_cert); results land in the workspace scalars.
+// swap_sym: as in SweepLaunch (the W pass then evaluates one coordinate per
+// exchange pair)
 hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const void *prev,
-                          int u_slot, int prev_slot, unsigned char *ws, hipStream_t s);
+                          int u_slot, int prev_slot, int swap_sym, unsigned char *ws,
+                          hipStream_t s);
 
 // Utilities
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_fill_f64(double *p, uint64_t count, double v, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
+// sigma = d = 2, l >= 2: set *flag (device) to 1 unless every stored entry
+// equals, bit for bit, the stored entry of its string-exchanged tuple
+hipError_t launch_check_swap(const Geometry &g, int dtype, const void *table, uint32_t *flag,
+                             hipStream_t s);
 hipError_t launch_upcast(const Geometry &g, const float *src, const double *offset_dev,
                          double *dst, hipStream_t s);
 // the FP32 table in the first half of an FP64-sized buffer, widened in place

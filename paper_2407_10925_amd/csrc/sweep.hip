@@ -68,6 +68,12 @@ __device__ __forceinline__ T tree16(const T *g) { return tree8(g) + tree8(g + 8)
 template <typename T>
 __device__ __forceinline__ T vmax(T best, T cand) { return cand > best ? cand : best; }
 
+// F takes the max over the branch means starting from -inf, so a NaN branch
+// never wins and a tuple whose every branch is NaN gets -inf: the first value
+// of every max chain goes through this (a no-op on every other value).
+template <typename T>
+__device__ __forceinline__ T first(T v) { return v > -(T)INFINITY ? v : -(T)INFINITY; }
+
 // The new table is not read again until the next sweep, after 2-3 more
 // tables have streamed through the caches: write it non-temporally.
 template <typename T>
@@ -142,7 +148,17 @@ constexpr uint64_t kAlt4Hi = 0xCCCCCCCCCCCCCCCCull; // high 2-bit field of every
 // value.  Advance b keeps a (head 0) and reads the stored half directly;
 // advance a reads head a_2, 0 for t and 1 for xc, whose pair sa, sa+2 is then
 // read in the image group n-4-(sa & ~3) at the other parity.
-template <typename T>
+//
+// SWAP (a ring symmetric under exchanging the two strings, bit for bit: the
+// zero start, the network seed and every sweep of such a ring): with S the
+// exchange of the a and b bits of every slot of x, 0/0|x and 0/0|Sx are
+// exchanged tuples, and so are 0/1|x and 0/1|~Sx (exchange, then complement
+// to bring the head back to 0/1).  The branch trees are exchange-invariant,
+// so a thread's four values also belong at St, ~St (0/0) and ~St, St (0/1).
+// Of the two threads t and p = St or ~St (whichever has a_2 = 0) only the
+// lower one runs and writes all eight entries: every group is read by half
+// as many threads, the output is still written once.
+template <typename T, bool SWAP>
 __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
                                                     const T *__restrict__ lag2,
                                                     T *__restrict__ out, uint64_t n,
@@ -156,17 +172,24 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
     if constexpr (kF32) {
         const double o1 = off[s1];
         d2 = (float)(off[s2] - o1);
-        y0 = 1.0f + (pair4(lag2[0], lag2[1], lag2[2], lag2[3]) * 0.25f + d2);
+        y0 = 1.0f + first(pair4(lag2[0], lag2[1], lag2[2], lag2[3]) * 0.25f + d2);
         if (t == 0) off[snew] = o1 + (double)y0;
     }
     if (t >= (n >> 3)) return;
     const uint64_t xc = nq - 1 - t;
+    uint64_t st = 0;
+    if constexpr (SWAP) {
+        const uint64_t mq = nq - 1, am = kAlt2 & mq;
+        st = ((t & am) >> 1) | ((t & ~am & mq) << 1);
+        const uint64_t p = (t & (nq >> 2)) ? st ^ mq : st;  // b_2 = 1: ~St has a_2 = 0
+        if (p < t) return;
+    }
 
     T g[4];
     stream4<true>(lag2 + 4 * t, g);
     T m2 = pair4(g[0], g[1], g[2], g[3]) * (T)0.25;
     if constexpr (kF32) m2 = m2 + d2;
-    const T match = (T)1 + m2;
+    const T match = (T)1 + first(m2);
 
     const uint64_t am = kAlt2 & (n - 1), bm = ~kAlt2 & (n - 1);
     T mis[2];
@@ -185,13 +208,23 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
         stream4<kF32>(lag1 + (c ? (n - 4) - grp : grp), q);
         const int o = (int)(sa & 1) ^ c;
         const T ma = (q[o] + q[o + 2]) * (T)0.5;
-        mis[c] = vmax(mb, ma);
+        mis[c] = vmax(first(mb), ma);
     }
 
-    put(out + t, kF32 ? (T)(match - y0) : match);
-    put(out + xc, kF32 ? (T)(match - y0) : match);
-    put(out + nq + t, kF32 ? (T)(mis[0] - y0) : mis[0]);
-    put(out + nq + xc, kF32 ? (T)(mis[1] - y0) : mis[1]);
+    const T vm = kF32 ? (T)(match - y0) : match;
+    const T v0 = kF32 ? (T)(mis[0] - y0) : mis[0];
+    const T v1 = kF32 ? (T)(mis[1] - y0) : mis[1];
+    put(out + t, vm);
+    put(out + xc, vm);
+    put(out + nq + t, v0);
+    put(out + nq + xc, v1);
+    if constexpr (SWAP) {
+        const uint64_t sc = nq - 1 - st;
+        put(out + st, vm);
+        put(out + sc, vm);
+        put(out + nq + sc, v0);
+        put(out + nq + st, v1);
+    }
 }
 
 // ---------------------------------------------------------------- sigma = 4, d = 2
@@ -221,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
         d2 = (float)(off[s2] - o1);
         T g0[16];
         for (int k = 0; k < 16; k += 4) load4(lag2 + k, g0 + k);
-        y0 = 1.0f + (tree16(g0) * 0.0625f + d2);
+        y0 = 1.0f + first(tree16(g0) * 0.0625f + d2);
         if (t == 0) off[snew] = o1 + (double)y0;
     }
     if (t >= (n >> 6)) return;
@@ -231,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
     for (int k = 0; k < 16; k += 4) load4(lag2 + 16 * t + k, g + k);
     T both = tree16(g) * (T)0.0625;
     if constexpr (kF32) both = both + d2;
-    const T match = (T)1 + both;
+    const T match = (T)1 + first(both);
 
     const uint64_t am = kAlt4Hi & (n - 1), bm = ~kAlt4Hi & (n - 1);
     T ma[4];
@@ -252,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
         put(out + x, kF32 ? (T)(match - y0) : match);
 #pragma unroll
         for (int b1 = 1; b1 < 4; ++b1) {
-            T best = mb;                                     // z = 0
+            T best = first(mb);                              // z = 0
 #pragma unroll
             for (int z = 1; z < 4; ++z) best = vmax(best, z == b1 ? ma[b1 ^ m] : both);
             put(out + (((uint64_t)b1 << top) | x), kF32 ? (T)(best - y0) : best);
@@ -286,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
         d3 = (float)(off[s3] - o1);
         T g0[8];
         load8(lag3, g0);
-        y0 = 1.0f + (pair8(g0) * 0.125f + d3);
+        y0 = 1.0f + first(pair8(g0) * 0.125f + d3);
         if (t == 0) off[snew] = o1 + (double)y0;
     }
     if (t >= (n >> 4)) return;
@@ -297,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
     stream4<kF32>(lag3 + 8 * t + 4, g + 4);
     T all3 = pair8(g) * (T)0.125;
     if constexpr (kF32) all3 = all3 + d3;
-    const T match = (T)1 + all3;
+    const T match = (T)1 + first(all3);
 
     const uint64_t mask = n - 1;
     const uint64_t r3 = mask / 7;  // 001 in every slot
@@ -325,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
             const int o = (int)(b2 & 1) ^ c;
             T k2 = pair4(q[o], q[o + 2], q[o + 4], q[o + 6]) * (T)0.25;
             if constexpr (kF32) k2 = k2 + d2;
-            val[1] = vmax(k1, k2);
+            val[1] = vmax(first(k1), k2);
         }
         {   // 010: lag 1 entries b1, b1 + 2; lag 2 entries b2 + 0, 1, 4, 5
             const uint64_t i = ((uint64_t)2 << top) | x;
@@ -339,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
             const int o2 = c ? 2 - (int)(b2 & 7) : (int)(b2 & 7);
             T k2 = pair4(q[o2], q[o2 + 1], q[o2 + 4], q[o2 + 5]) * (T)0.25;
             if constexpr (kF32) k2 = k2 + d2;
-            val[2] = vmax(k1, k2);
+            val[2] = vmax(first(k1), k2);
         }
         {   // 011: lag 2 entries b2 + 0..3; lag 1 entries b1, b1 + 4
             const uint64_t i = ((uint64_t)3 << top) | x;
@@ -352,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
             group(lag1, b1, c, e);
             const int o = c ? 3 - (int)(b1 & 7) : (int)(b1 & 7);
             const T k1 = (e[o] + e[o + 4]) * (T)0.5;
-            val[3] = vmax(k2, k1);
+            val[3] = vmax(first(k2), k1);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -436,7 +469,7 @@ __device__ __forceinline__ T l1_value(const T *const *lag, const T *delta, int h
         sym[s] = (head >> (kBeta * (D - 1 - s))) & (SIGMA - 1);
         same = same && sym[s] == sym[0];
     }
-    if (same) return (T)1 + l1_branch<T, SIGMA, D, 1>(lag, delta, head, (1 << D) - 1);
+    if (same) return (T)1 + first(l1_branch<T, SIGMA, D, 1>(lag, delta, head, (1 << D) - 1));
     T best = 0;
 #pragma unroll
     for (int z = 0; z < SIGMA; ++z) {
@@ -445,7 +478,7 @@ __device__ __forceinline__ T l1_value(const T *const *lag, const T *delta, int h
         for (int s = 0; s < D; ++s)
             if (sym[s] != z) moved |= 1 << s;
         const T m = l1_branch<T, SIGMA, D, 1>(lag, delta, head, moved);
-        best = z == 0 ? m : vmax(best, m);
+        best = z == 0 ? first(m) : vmax(best, m);
     }
     return best;
 }
@@ -504,8 +537,12 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
     if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)blocks), block(kBlock);
     if (g.sigma == 2 && g.d == 2) {
-        sweep_s2d2<T><<<grid, block, 0, s>>>(l1, l2, out, g.n, a.offsets, a.lag_slot[0],
-                                              a.lag_slot[1], a.new_slot);
+        if (a.swap_sym)
+            sweep_s2d2<T, true><<<grid, block, 0, s>>>(l1, l2, out, g.n, a.offsets,
+                                                       a.lag_slot[0], a.lag_slot[1], a.new_slot);
+        else
+            sweep_s2d2<T, false><<<grid, block, 0, s>>>(l1, l2, out, g.n, a.offsets,
+                                                        a.lag_slot[0], a.lag_slot[1], a.new_slot);
     } else if (g.sigma == 4 && g.d == 2) {
         sweep_s4d2<T><<<grid, block, 0, s>>>(l1, l2, out, g.n, g.h, a.offsets, a.lag_slot[0],
                                               a.lag_slot[1], a.new_slot);

@@ -67,6 +67,24 @@ __global__ __launch_bounds__(kBlock) void upcast_range(const float *src, const d
     }
 }
 
+// sigma = d = 2: raise *flag if a stored entry differs, bit for bit, from the
+// stored entry of its tuple with the two strings exchanged (the a and b bits
+// of every slot swapped, then complemented when that makes the head 1)
+template <typename W>
+__global__ __launch_bounds__(kBlock) void check_swap_kernel(const W *__restrict__ v, uint64_t n,
+                                                            uint32_t *__restrict__ flag)
+{
+    const uint64_t ns = n >> 1, am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    bool bad = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < ns; i += stride) {
+        const uint64_t j = ((i & am) >> 1) | ((i & bm) << 1);
+        const uint64_t js = (j & ns) ? j ^ (n - 1) : j;
+        bad = bad || v[i] != v[js];
+    }
+    if (bad) *flag = 1u;
+}
+
 unsigned grid_for(uint64_t work)
 {
     uint64_t b = (work + kBlock - 1) / kBlock;
@@ -76,6 +94,19 @@ unsigned grid_for(uint64_t work)
 }
 
 }  // namespace
+
+hipError_t launch_check_swap(const Geometry &g, int dtype, const void *table, uint32_t *flag,
+                             hipStream_t s)
+{
+    if (g.sigma != 2 || g.d != 2 || g.h < 2) return hipErrorInvalidValue;
+    if (dtype == LCSB_F32)
+        check_swap_kernel<uint32_t><<<grid_for(g.ns), kBlock, 0, s>>>(
+            static_cast<const uint32_t *>(table), g.n, flag);
+    else
+        check_swap_kernel<uint64_t><<<grid_for(g.ns), kBlock, 0, s>>>(
+            static_cast<const uint64_t *>(table), g.n, flag);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s)
 {

@@ -2,8 +2,9 @@
 
 Holds no arithmetic of the method: only a counter-based random generator
 (SplitMix64; Steele, Lea, Flood, "Fast splittable pseudorandom number
-generators", OOPSLA 2014) and the relabelling of symbols used to make a table
-invariant under c -> c xor m.  Everything is torch integer arithmetic, so the
+generators", OOPSLA 2014), the relabelling of symbols used to make a table
+invariant under c -> c xor m, and the exchange of the two strings (sigma =
+d = 2) used to make it invariant under that too.  Everything is torch integer arithmetic, so the
 same call gives identical bits on the CPU and on a GPU.
 """
 from __future__ import annotations
@@ -52,15 +53,31 @@ def representative(idx: torch.Tensor, sigma: int, d: int, h: int) -> torch.Tenso
     return idx ^ (m * _s64(rep_bits))
 
 
+def exchanged(idx: torch.Tensor, sigma: int, d: int, h: int) -> torch.Tensor:
+    """sigma = d = 2: index of the tuple with the two strings exchanged (the
+    two bits of every position swapped)."""
+    assert sigma == 2 and d == 2
+    a = _s64(0xAAAAAAAAAAAAAAAA & ((1 << (2 * h)) - 1))
+    b = _s64(0x5555555555555555 & ((1 << (2 * h)) - 1))
+    return _lsr(idx & a, 1) | ((idx & b) << 1)
+
+
 def table(sigma: int, d: int, h: int, seed: int, dtype=torch.float64, device="cpu",
-          symmetric: bool = True, scale: float = 8.0, chunk: int = 1 << 26) -> torch.Tensor:
-    """A seeded table of sigma^(d h) values; symmetric under c -> c xor m if asked."""
+          symmetric: bool = True, scale: float = 8.0, chunk: int = 1 << 26,
+          exchange: bool = False) -> torch.Tensor:
+    """A seeded table of sigma^(d h) values; symmetric under c -> c xor m if
+    asked, and (sigma = d = 2) also under exchanging the two strings if
+    `exchange`: each value is then drawn at the lower of the two
+    representatives."""
     n = sigma ** (d * h)
     out = torch.empty(n, dtype=dtype, device=device)
     for lo in range(0, n, chunk):
         idx = torch.arange(lo, min(n, lo + chunk), dtype=torch.int64, device=device)
         if symmetric:
             idx = representative(idx, sigma, d, h)
+        if exchange:
+            assert symmetric
+            idx = torch.minimum(idx, representative(exchanged(idx, sigma, d, h), sigma, d, h))
         out[lo:lo + idx.numel()] = uniform(seed, idx, scale).to(dtype)
     return out
 

@@ -181,6 +181,7 @@ def test_training_reduces_the_loss_and_seed_is_consistent(pk):
     nan = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
     S.load_ring([nan, nan.clone()])
     S.init_seed_mlp(M, rate=R)
+    assert S.swap_symmetric()  # one value per exchange orbit: sweeps run folded
     lag2 = S.lag(2)[0].cpu()
     lag1 = S.lag(1)[0].cpu()
     assert lag2.numel() == n // 2

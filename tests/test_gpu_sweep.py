@@ -51,9 +51,14 @@ def _full(L, got):
     return _host(got)[_rep(L, torch.arange(L.n, dtype=torch.int64)).numpy()]
 
 
-def _same_cert(gpu, ref):
+def _same_cert(gpu, ref, sigma=None):
+    """Every certificate field equal.  With sigma given, the non-finite count
+    is compared as stored coordinates (the library's unit) times sigma, the
+    number of indices each stored coordinate stands for (the oracle's unit)."""
     for k in CERT_KEYS:
         a, b = gpu[k], ref[k]
+        if k == "nonfinite" and sigma is not None:
+            a = a * sigma
         assert (a == b) or (isinstance(a, float) and math.isnan(a) and math.isnan(b)), (k, a, b)
 
 
@@ -68,6 +73,8 @@ def test_fp64_zero_start_trajectory_is_bit_exact(pk, sigma, d, h, sweeps, printe
     say(f"zero-start FP64 sigma={sigma} d={d} h={h} sweeps={sweeps}")
     L = pk.Lcsb(sigma, d, h, "f64")
     L.init_zero()
+    # the zero ring is symmetric in the two strings: sigma = d = 2 runs folded
+    assert L.swap_symmetric() == (sigma == 2 and d == 2 and h >= 2)
     N = sigma ** (d * h)
     ring = [np.zeros(N) for _ in range(d)]
     best_ref = {"rho": 0.0, "bound": 0.0, "sweep": 0}  # the initial triplet (v_0, 0, 0)
@@ -101,6 +108,7 @@ def test_fp64_random_ring_one_sweep_and_certificate(pk, sigma, d, h):
     lags = [si.table(sigma, d, h, seed=10 + k, dtype=torch.float64) for k in range(d)]
     L = pk.Lcsb(sigma, d, h, "f64")
     L.load_ring([x.cuda() for x in lags])
+    assert not L.swap_symmetric()  # random tables are not symmetric in the strings
     # certificate of the loaded ring (u = lag 1, prev = lag 2)
     cur, _ = L.certify()
     _same_cert(cur, oracle.certify(sigma, d, h, lags[0].numpy(), lags[1].numpy()))
@@ -112,18 +120,21 @@ def test_fp64_random_ring_one_sweep_and_certificate(pk, sigma, d, h):
     _same_cert(cur, oracle.certify(sigma, d, h, new, lags[0].numpy()))
 
 
-@pytest.mark.parametrize("sigma,d,h", [(2, 2, 5), (4, 2, 2), (2, 3, 3)], ids=lambda v: str(v))
+@pytest.mark.parametrize("sigma,d,h,exchange", [(2, 2, 5, False), (2, 2, 5, True), (4, 2, 2, False),
+                                                (2, 3, 3, False)], ids=lambda v: str(v))
 @pytest.mark.parametrize("scale", [1e-300, 2.0 ** -1021], ids=["tiny", "subnormal"])
-def test_fp64_tiny_and_subnormal_tables(pk, sigma, d, h, scale):
+def test_fp64_tiny_and_subnormal_tables(pk, sigma, d, h, exchange, scale):
     """Values near and below the smallest normal double: the sums stay exact
     but halving an odd multiple of the smallest subnormal does not, and
     1 + mean and the outer W steps round in both directions.  Sweep (round to
     nearest) and certificate (directed) must still match bit for bit."""
-    say(f"tiny FP64 ring sigma={sigma} d={d} h={h} scale={scale:.3g}")
-    lags = [si.table(sigma, d, h, seed=60 + k, dtype=torch.float64, scale=scale) for k in range(d)]
+    say(f"tiny FP64 ring sigma={sigma} d={d} h={h} exchange={exchange} scale={scale:.3g}")
+    lags = [si.table(sigma, d, h, seed=60 + k, dtype=torch.float64, scale=scale,
+                     exchange=exchange) for k in range(d)]
     assert bool((lags[0] > 0).any()) and (scale > 1e-305 or bool((lags[0] < 2.0 ** -1022).any()))
     L = pk.Lcsb(sigma, d, h, "f64")
     L.load_ring([x.cuda() for x in lags])
+    assert L.swap_symmetric() == exchange
     cur, _ = L.certify()
     _same_cert(cur, oracle.certify(sigma, d, h, lags[0].numpy(), lags[1].numpy()))
     for t in range(3):
@@ -155,6 +166,114 @@ def test_load_ring_projects_onto_symmetric_tables(pk):
         assert torch.equal(M.lag(k)[0], L.lag(k)[0])
     with pytest.raises(ValueError):
         M.load_ring([x[:M.stored - 1].cuda() for x in raw])
+
+
+# ------------------------------------------------------------------ exchange-symmetric rings
+@pytest.mark.parametrize("h", [2, 3, 5, 8, 10])
+def test_fp64_exchange_symmetric_ring_takes_the_folded_path(pk, h):
+    """A ring symmetric in the two strings is recognised when loaded; sweeps
+    and certificates then compute one tuple of each exchanged pair and write
+    or count both.  Sweeps and certificates must still match the oracle bit
+    for bit (random values, so every association and every max matters), and
+    the ring must stay symmetric."""
+    say(f"exchange-symmetric FP64 ring h={h}")
+    lags = [si.table(2, 2, h, seed=110 + k, exchange=True) for k in range(2)]
+    L = pk.Lcsb(2, 2, h, "f64")
+    L.load_ring([x.cuda() for x in lags])
+    assert L.swap_symmetric()
+    cur, _ = L.certify()
+    _same_cert(cur, oracle.certify(2, 2, h, lags[0].numpy(), lags[1].numpy()))
+    ring = [x.numpy() for x in lags]
+    for t in range(3):
+        L.iterate(1)
+        new = oracle.sweep(2, 2, h, ring)
+        got, _ = L.lag(1)
+        assert np.array_equal(_full(L, got), new), f"sweep {t}"
+        ring = [new] + ring[:-1]
+        cur, _ = L.certify()
+        _same_cert(cur, oracle.certify(2, 2, h, ring[0], ring[1]))
+    assert L.swap_symmetric()
+
+
+@pytest.mark.parametrize("h", [2, 4, 9])
+def test_fp32_exchange_symmetric_ring(pk, h):
+    say(f"exchange-symmetric FP32 ring h={h}")
+    lags = [si.table(2, 2, h, seed=120 + k, dtype=torch.float32, exchange=True) for k in range(2)]
+    offs = [0.0, 0.75]
+    L = pk.Lcsb(2, 2, h, "f32")
+    L.load_ring([x.cuda() for x in lags], offsets=offs)
+    assert L.swap_symmetric()
+    L.iterate(1)
+    got, o_new = L.lag(1)
+    full = _full(L, got)
+    ex = si.exchanged(torch.arange(L.n), 2, 2, h).numpy()
+    assert np.array_equal(full, full[ex])
+    val = o_new + full.astype(np.float64)
+    ref = oracle.sweep(2, 2, h, [x.numpy().astype(np.float64) + o for x, o in zip(lags, offs)])
+    assert np.max(np.abs(val - ref)) <= _fp32_bound(8.0 + 0.75 * 2)
+    L2 = pk.Lcsb(2, 2, h, "f32")
+    L2.load_ring([x.cuda() for x in lags])
+    assert L2.swap_symmetric()
+    cur, _ = L2.certify()
+    _same_cert(cur, oracle.certify(2, 2, h, lags[0].numpy().astype(np.float64),
+                                   lags[1].numpy().astype(np.float64)))
+
+
+@pytest.mark.parametrize("sigma,d,h,exchange", [(2, 2, 4, False), (2, 2, 4, True), (2, 2, 1, False),
+                                                (4, 2, 2, False), (2, 3, 3, False)],
+                         ids=lambda v: str(v))
+def test_nonfinite_tables_follow_the_oracle(pk, sigma, d, h, exchange):
+    """Tables holding NaN, +inf and -inf: F's max starts from -inf, so a NaN
+    branch never wins and a tuple whose branches are all NaN gets -inf.  The
+    sweep must give the oracle's table (NaN where it has NaN) and the
+    certificate its R, W, argmax and non-finite count."""
+    say(f"non-finite tables sigma={sigma} d={d} h={h} exchange={exchange}")
+    n = sigma ** (d * h)
+    lags = [si.table(sigma, d, h, seed=140 + k, exchange=exchange) for k in range(d)]
+    rep = si.representative(torch.arange(n), sigma, d, h)
+    if exchange:
+        rep = torch.minimum(rep, si.representative(si.exchanged(rep, 2, 2, h), 2, 2, h))
+    for k, (where, bad) in enumerate([((3, 11), float("nan")), ((5,), float("inf")),
+                                      ((7,), -float("inf"))]):
+        for j in where:
+            r = rep[j % n]
+            lags[k % d][rep == r] = bad  # every index of the orbit, so the symmetry holds
+    L = pk.Lcsb(sigma, d, h, "f64")
+    L.load_ring([x.cuda() for x in lags])
+    assert L.swap_symmetric() == (exchange and h >= 2)
+    cur, best = L.certify(allow_nonfinite=True)
+    ref = oracle.certify(sigma, d, h, lags[0].numpy(), lags[1].numpy())
+    assert ref["nonfinite"] > 0
+    _same_cert(cur, ref, sigma)
+    assert best["bound"] == 0.0 and best["sweep"] == 0
+    L.iterate(1)
+    new = oracle.sweep(sigma, d, h, [x.numpy() for x in lags])
+    got, _ = L.lag(1)
+    assert np.array_equal(_full(L, got), new, equal_nan=True)
+    cur, _ = L.certify(allow_nonfinite=True)
+    _same_cert(cur, oracle.certify(sigma, d, h, new, lags[0].numpy()), sigma)
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")], ids=["nan", "inf"])
+def test_nonfinite_exchange_symmetric_ring_counts_every_coordinate(pk, bad):
+    """The folded certificate counts each non-finite W once per coordinate
+    it stands for: the count equals the oracle's."""
+    say(f"non-finite exchange-symmetric ring {bad}")
+    h = 4
+    lags = [si.table(2, 2, h, seed=130 + k, exchange=True) for k in range(2)]
+    n = 4 ** h
+    for i in (5, 40, 77):  # the whole orbit of each, so the ring stays symmetric
+        orb = {i, n - 1 - i}
+        orb |= {int(si.exchanged(torch.tensor([j]), 2, 2, h)[0]) for j in orb}
+        lags[0][list(orb)] = bad
+    L = pk.Lcsb(2, 2, h, "f64")
+    L.load_ring([x.cuda() for x in lags])
+    assert L.swap_symmetric()
+    cur, best = L.certify(allow_nonfinite=True)
+    ref = oracle.certify(2, 2, h, lags[0].numpy(), lags[1].numpy())
+    assert ref["nonfinite"] > 0
+    _same_cert(cur, ref, 2)
+    assert best["bound"] == 0.0 and best["sweep"] == 0
 
 
 # ------------------------------------------------------------------ full size, sampled
@@ -443,6 +562,7 @@ def test_fp32_ring_inside_fp64_ring_upcasts_in_place(pk, sigma, d, h):
     Q = pk.Lcsb(sigma, d, h, "f64")
     Q.upcast(A)
     P.upcast(B)
+    assert P.swap_symmetric() == Q.swap_symmetric() == A.swap_symmetric()
     for k in range(1, d + 1):
         assert torch.equal(P.lag(k)[0], Q.lag(k)[0])
     for L in (P, Q):
@@ -475,6 +595,7 @@ def test_checkpoint_resume_is_bit_identical(pk, tmp_path, sigma, d, h, dt):
     B = pk.Lcsb(sigma, d, h, dt)
     B.load(path)
     assert B.status()[0] == 25
+    assert B.swap_symmetric() == A.swap_symmetric() == (sigma == 2 and d == 2)
     B.iterate(11)
     cur_b, best_b = B.certify()
     assert cur_a == cur_b and best_a == best_b

@@ -63,7 +63,11 @@ __device__ void block_reduce(double &v, uint64_t &i, uint64_t &c)
     }
 }
 
-template <typename T>
+// n = stored entries.  SWAP (sigma = d = 2, both tables symmetric in the two
+// strings): u - prev is equal at a stored entry and at its exchanged twin (the
+// a and b bits of every slot swapped, folded back to string-1 head 0), so only
+// the lower of the two is read, counted twice unless it is its own twin.
+template <typename T, bool SWAP>
 __global__ __launch_bounds__(kBlock) void cert_r(const T *__restrict__ u,
                                                 const T *__restrict__ prev, uint64_t n,
                                                 unsigned char *__restrict__ ws)
@@ -71,9 +75,17 @@ __global__ __launch_bounds__(kBlock) void cert_r(const T *__restrict__ u,
     double best = -INFINITY;
     uint64_t arg = 0, nonfinite = 0;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    const uint64_t full = 2 * n - 1, am = 0xAAAAAAAAAAAAAAAAull & full, bm = ~am & full;
     for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
+        uint64_t mult = 1;
+        if constexpr (SWAP) {
+            const uint64_t x = ((j & am) >> 1) | ((j & bm) << 1);
+            const uint64_t js = (x & n) ? x ^ full : x;
+            if (js < j) continue;
+            mult = js == j ? 1 : 2;
+        }
         const double a = (double)u[j], b = (double)prev[j];
-        if (!isfinite(a) || !isfinite(b)) ++nonfinite;
+        if (!isfinite(a) || !isfinite(b)) nonfinite += mult;
         const double diff = a - b;
         if (diff > best) { best = diff; arg = j; }
     }
@@ -535,8 +547,12 @@ hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int
                          int prev_slot, int swap_sym, unsigned char *ws, hipStream_t s)
 {
     const int nb = reduce_blocks(g.ns);
-    cert_r<T><<<nb, kBlock, 0, s>>>(static_cast<const T *>(u), static_cast<const T *>(prev),
-                                     g.ns, ws);
+    if (swap_sym && g.sigma == 2 && g.d == 2 && g.h >= 2)
+        cert_r<T, true><<<nb, kBlock, 0, s>>>(static_cast<const T *>(u),
+                                              static_cast<const T *>(prev), g.ns, ws);
+    else
+        cert_r<T, false><<<nb, kBlock, 0, s>>>(static_cast<const T *>(u),
+                                               static_cast<const T *>(prev), g.ns, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     cert_r_final<<<1, kBlock, 0, s>>>(ws, nb, g.d, std::is_same<T, float>::value ? 1 : 0,

@@ -9,13 +9,13 @@ reported value is table updates per second (2^32 updates per sweep, one per
 index) over the K timed steps, with the ring already resident in HBM.
 
 The zero-start ring is symmetric in the two strings, so the sweep runs the
-exchange-folded kernel (one tuple of each exchanged pair computed, both
-written).
+exchange-folded kernel (one tuple of each exchanged pair computed and
+stored; the table is completed only where it is read as a whole).
 
 Also printed in the same JSON line:
-  roofline      the sweep kernel's algorithmic bytes per launch (8 B per
-                stored entry: lag 1 and lag 2 read at one entry of each
-                exchanged pair, the new stored table written once; 4 B per
+  roofline      the sweep kernel's algorithmic bytes per launch (6 B per
+                stored FP32 entry: lag 1 and lag 2 read, and the new table
+                written, at one entry of each exchanged pair; 3 B per
                 update) over its average launch time
                 (traffic_GBps / traffic_frac: the same with the measured HBM
                 bytes), from HIP events on the stream
@@ -167,15 +167,16 @@ def algorithmic_bytes(L, elem):
     """Bytes one sigma = d = 2 sweep must move: lag 1 and lag 2 read once and
     the new stored table written once; on an exchange-symmetric ring one
     entry of each exchanged pair carries the information, so each lag is
-    read at half its stored entries."""
-    reads = 1 if L.swap_symmetric() else 2  # stored tables' worth of lag reads
-    return (reads + 1) * elem * L.stored
+    read, and the new table written, at half its stored entries."""
+    if L.swap_symmetric():
+        return 3 * elem * L.stored // 2
+    return 3 * elem * L.stored
 
 
 def fp64_sweep(pk, h, sweeps=32):
     """The plain FP64 sweep (bit-identical to the oracle) at sigma = d = 2,
     l = h from zero: average launch time from HIP events on the library's
-    stream, against the HBM peak (16 algorithmic bytes per stored entry)."""
+    stream, against the HBM peak (12 algorithmic bytes per stored entry)."""
     import torch
     L = pk.Lcsb(2, 2, h, "f64")
     L.init_zero()
@@ -613,7 +614,7 @@ def main():
         "dtype": "f32 sweeps, f64 certificate", "data": "synthetic (zero-start iteration)",
         "config": {"workload": f"sigma=2 d=2 l={h}: {n} table indices ({n // 2} stored, "
                                f"complement-folded; exchange-symmetric ring, one tuple of "
-                               f"each exchanged pair computed), FP32 renormalised sweeps, "
+                               f"each exchanged pair computed and stored), FP32 renormalised sweeps, "
                                f"FP64 round-down certificate every {cad} sweeps",
                    "sweeps_per_step": cad, "entries": n, "stored_entries": n // 2},
         "roofline": roofline,

@@ -146,17 +146,22 @@ int lcsb_certify(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
 
 /* Device address of lag k (1..d) and, for LCSB_F32, the FP64 offset its
  * values are relative to (read from the device; synchronises).  The pointer
- * stays valid until the next lcsb_iterate, lcsb_load_ring or lcsb_bind. */
+ * stays valid until the next lcsb_iterate, lcsb_load_ring or lcsb_bind.  On
+ * an exchange-symmetric ring (lcsb_swap_symmetric) sweeps write only one
+ * entry of each exchanged pair; this call first completes the table on the
+ * stream (one kernel over the table), so every stored entry can be read. */
 int lcsb_lag(const lcsb_ctx *ctx, int k, void **dev_ptr, double *offset);
 
 /* sigma = d = 2, l >= 2: *symmetric = 1 when every lag table is known to be
  * symmetric, bit for bit, under exchanging the two strings (after
  * lcsb_init_zero, lcsb_init_seed_mlp, a load_ring or load of such a ring, an
  * upcast of such a ring, and every sweep of such a ring: F keeps the
- * symmetry exactly).  lcsb_iterate and lcsb_certify then run on one tuple of
- * each exchanged pair and write or count both, which halves the bytes they
- * read; otherwise (and for every other shape) *symmetric = 0 and every tuple
- * is computed.  The results are the same bits either way. */
+ * symmetry exactly).  lcsb_iterate and lcsb_certify then compute one tuple of
+ * each exchanged pair, and a sweep writes only the entry of the pair with the
+ * lower stored index (lcsb_lag and lcsb_save complete the table before it is
+ * read), which halves the bytes they move; otherwise (and for every other
+ * shape) *symmetric = 0 and every tuple is computed and written.  The
+ * results are the same bits either way. */
 int lcsb_swap_symmetric(const lcsb_ctx *ctx, int *symmetric);
 
 /* Number of sweeps applied since the last init, and the best certificate. */

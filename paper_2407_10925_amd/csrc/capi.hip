@@ -49,6 +49,7 @@ struct lcsb_ctx {
     int64_t sweeps;  // sweeps since the last init
     lcsb_cert best;
     int swap_sym;    // sigma = d = 2, l >= 2: lag 1 .. d symmetric in the two strings
+    int lazy[4];     // per slot: only the lower index of each exchanged pair written
 };
 
 namespace {
@@ -74,10 +75,23 @@ int need_ready(const lcsb_ctx *c)
 // the exchange-folded kernels apply to sigma = d = 2 at l >= 2
 bool swap_shape(const lcsb_ctx *c) { return c->g.sigma == 2 && c->g.d == 2 && c->g.h >= 2; }
 
+void clear_lazy(lcsb_ctx *c) { for (int k = 0; k < 4; ++k) c->lazy[k] = 0; }
+
+// Complete the exchanged entries of a lazily written slot (stream order).
+int materialize(lcsb_ctx *c, int slot)
+{
+    if (!c->lazy[slot]) return LCSB_OK;
+    hipError_t e = launch_materialize_swap(c->g, c->dtype, c->buf[slot], c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "materialize");
+    c->lazy[slot] = 0;
+    return LCSB_OK;
+}
+
 // Set c->swap_sym by checking lag 1 .. d on the device (synchronises).
 int refresh_swap(lcsb_ctx *c)
 {
     c->swap_sym = 0;
+    clear_lazy(c);
     if (!swap_shape(c)) return LCSB_OK;
     uint32_t *flag = reinterpret_cast<uint32_t *>(c->ws + Ws::kAsym);
     hipError_t e;
@@ -167,6 +181,7 @@ int lcsb_bind(lcsb_ctx *c, void *const *bufs, int nbuf, void *ws, void *stream)
     c->sweeps = 0;
     c->best = initial_best();
     c->swap_sym = 0;
+    clear_lazy(c);
     return LCSB_OK;
 }
 
@@ -186,6 +201,7 @@ int lcsb_init_zero(lcsb_ctx *c)
     c->sweeps = 0;
     c->best = initial_best();
     c->swap_sym = swap_shape(c);
+    clear_lazy(c);
     c->state = kReady;
     return LCSB_OK;
 }
@@ -244,6 +260,7 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
         a.swap_sym = c->swap_sym;
         hipError_t e = launch_sweep(c->g, c->dtype, a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+        c->lazy[a.new_slot] = c->swap_sym;
         c->head = a.new_slot;
         c->sweeps++;
     }
@@ -291,6 +308,9 @@ int lcsb_lag(const lcsb_ctx *c, int k, void **dev_ptr, double *offset)
     if (rc) return rc;
     if (k < 1 || k > c->g.d) return fail(LCSB_EINVAL, "lag %d outside 1..%d", k, c->g.d);
     const int slot = slot_of_lag(c, k);
+    // the caller may read any stored entry: complete a lazily written table
+    // (its values do not change, so the context stays logically const)
+    if ((rc = materialize(const_cast<lcsb_ctx *>(c), slot))) return rc;
     if (dev_ptr) *dev_ptr = c->buf[slot];
     if (offset) {
         *offset = 0.0;
@@ -406,6 +426,7 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
     dst->sweeps = src->sweeps;
     dst->best = src->best;
     dst->swap_sym = src->swap_sym;
+    for (int k = 0; k < 4; ++k) dst->lazy[k] = src->lazy[k];  // same slots, converted as stored
     dst->state = kReady;
     return LCSB_OK;
 }
@@ -529,7 +550,8 @@ int lcsb_init_seed_mlp(lcsb_ctx *c, const float *params, const uint16_t *wbf16, 
         return hip_fail(c, e, "seed");
     c->sweeps = 0;
     c->best = initial_best();
-    c->swap_sym = swap_shape(c);  // one value per exchange orbit
+    c->swap_sym = swap_shape(c);  // one value per exchange orbit, written to every member
+    clear_lazy(c);
     c->state = kReady;
     return LCSB_OK;
 }
@@ -619,6 +641,8 @@ int lcsb_save(const lcsb_ctx *c, const char *path)
     hd.bound = c->best.bound; hd.R = c->best.R; hd.E = c->best.E; hd.maxW = c->best.maxW;
     hd.rho = c->best.rho; hd.best_sweep = c->best.sweep;
     hd.argmax_W = c->best.argmax_W; hd.nonfinite = c->best.nonfinite;
+    for (int k = 1; k <= c->g.d; ++k)  // the file holds complete tables
+        if ((rc = materialize(const_cast<lcsb_ctx *>(c), slot_of_lag(c, k)))) return rc;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(LCSB_EHIP, "sync: %s", hipGetErrorString(e));
     if (c->dtype == LCSB_F32) {

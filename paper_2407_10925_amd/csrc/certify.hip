@@ -216,7 +216,8 @@ struct WBest {
 // for bit, at exchanged tuples (the trees are exchange-invariant), so only the
 // lower of the threads t and p (St or ~St, as in the sweep) evaluates, each
 // value standing for two coordinates unless p = t.  The lowest index of each
-// pair is t, ~St, 0/1|t and 0/1|St.
+// pair is t, ~St, 0/1|t and 0/1|St; the table is kept lazily (TwinGroup), so
+// u is read there and every group through its lower members.
 template <typename T, bool SWAP>
 __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint64_t t,
                                       const double *shift, const Scales &sc, double dR_up,
@@ -235,28 +236,41 @@ __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint
         rep_mis1 = nq + st;
     }
     const uint64_t am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
+    // the group at `base` in member order (through its lower members if SWAP)
+    auto group = [&](uint64_t base, double *e) {
+        if constexpr (SWAP) {
+            const TwinGroup tg = twin_group(base, n);
+            double q[4];
+            ld4(u + tg.read, q);
+            twin_values(q, tg.mode, e);
+        } else {
+            ld4(u + base, e);
+        }
+    };
     double q4[4];
-    ld4(u + 4 * t, q4);
+    group(4 * t, q4);
     double g[4] = {q4[0], q4[3], q4[1], q4[2]};
     const double f_match = 1.0 + first(mean_rd<4>(g, shift[2], sc.q[2]));
     best.add((double)u[t], f_match, dR_up, t, mult);
-    best.add((double)u[xc], f_match, dR_up, rep_xc, mult);
+    best.add((double)u[rep_xc], f_match, dR_up, rep_xc, mult);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const uint64_t i = nq + (c ? xc : t);
         const uint64_t sb = (i & am) | ((i << 2) & bm);
         const uint64_t sa = ((i << 2) & am) | (i & bm);
         double q[4], pb[2], pa[2];
-        ld4(u + (sb & ~(uint64_t)3), q);
-        pb[0] = q[sb & 3]; pb[1] = q[(sb & 3) + 1];
+        group(sb & ~(uint64_t)3, q);
+        const bool hi = (sb & 2) != 0;
+        pb[0] = hi ? q[2] : q[0]; pb[1] = hi ? q[3] : q[1];
         const uint64_t grp = sa & ~(uint64_t)3;
-        ld4(u + (c ? (n - 4) - grp : grp), q);
-        const int o = (int)(sa & 1) ^ c;
-        pa[0] = q[o]; pa[1] = q[o + 2];
+        group(c ? (n - 4) - grp : grp, q);
+        const bool odd = ((sa & 1) ^ (uint64_t)c) != 0;
+        pa[0] = odd ? q[1] : q[0]; pa[1] = odd ? q[3] : q[2];
         const double mb = mean_rd<2>(pb, shift[1], sc.q[1]);
         const double ma = mean_rd<2>(pa, shift[1], sc.q[1]);
         const double fb = first(mb);  // z = 0 advances b
-        best.add((double)u[i], ma > fb ? ma : fb, dR_up, c ? rep_mis1 : i, mult);
+        const uint64_t at = c ? rep_mis1 : i;  // i itself unless SWAP
+        best.add((double)u[at], ma > fb ? ma : fb, dR_up, at, mult);
     }
 }
 

@@ -47,6 +47,7 @@ struct SweepLaunch {
     int new_slot;
     double *offsets;  // device, per slot (FP32 only)
     int swap_sym;     // sigma = d = 2: the lag tables are symmetric under exchanging the strings
+                      // (read lazily, see TwinGroup; the new table is written lazily)
 };
 
 hipError_t launch_sweep(const Geometry &g, int dtype, const SweepLaunch &a, hipStream_t s);
@@ -66,11 +67,46 @@ hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s
 // equals, bit for bit, the stored entry of its string-exchanged tuple
 hipError_t launch_check_swap(const Geometry &g, int dtype, const void *table, uint32_t *flag,
                              hipStream_t s);
+// a lazily written table (see TwinGroup): set every upper entry to its lower twin
+hipError_t launch_materialize_swap(const Geometry &g, int dtype, void *table, hipStream_t s);
 hipError_t launch_upcast(const Geometry &g, const float *src, const double *offset_dev,
                          double *dst, hipStream_t s);
 // the FP32 table in the first half of an FP64-sized buffer, widened in place
 hipError_t launch_upcast_inplace(const Geometry &g, void *buf, const double *offset_dev,
                                  hipStream_t s);
+
+// sigma = d = 2 rings symmetric in the two strings are written lazily: of the
+// exchanged pair {j, J(j)} of stored entries (J swaps the a and b bits of
+// every slot, then complements when that makes the string-1 head 1) only the
+// lower index is kept.  An aligned group of four shares its prefix, so it is
+// entirely lower (read as is), entirely upper (read at its twin group, member
+// v at position perm(v): perm swaps 1 and 2 for heads 0/0 and 0 and 3 for
+// heads 0/1), or its own twin (each upper member read at its lower partner).
+struct TwinGroup {
+    uint64_t read;  // base of the group to load
+    int mode;       // 0 own, 1 twin (0/0), 2 twin (0/1), 3 self (0/0), 4 self (0/1)
+};
+
+__host__ __device__ inline TwinGroup twin_group(uint64_t base, uint64_t n)
+{
+    const uint64_t full = n - 1, am = 0xAAAAAAAAAAAAAAAAull & full;
+    const uint64_t x = ((base & am) >> 1) | ((base & ~am & full) << 1);
+    const bool h01 = (x & (n >> 1)) != 0;  // the exchange moved a head 1 to string 1
+    const uint64_t jb = h01 ? x ^ (full & ~(uint64_t)3) : x;
+    if (jb > base) return {base, 0};
+    if (jb < base) return {jb, h01 ? 2 : 1};
+    return {base, h01 ? 4 : 3};
+}
+
+// the group's four values, in its own member order, from the loaded q
+template <typename T>
+__device__ __forceinline__ void twin_values(const T *q, int mode, T *g)
+{
+    g[0] = mode == 2 ? q[3] : q[0];
+    g[1] = mode == 1 ? q[2] : q[1];
+    g[2] = (mode == 1 || mode == 3) ? q[1] : q[2];
+    g[3] = (mode == 2 || mode == 4) ? q[0] : q[3];
+}
 
 // Learned warm start (csrc/mlp.hip)
 struct MlpWs {  // byte offsets inside the caller's training workspace

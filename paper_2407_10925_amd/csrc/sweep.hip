@@ -156,8 +156,10 @@ constexpr uint64_t kAlt4Hi = 0xCCCCCCCCCCCCCCCCull; // high 2-bit field of every
 // to bring the head back to 0/1).  The branch trees are exchange-invariant,
 // so a thread's four values also belong at St, ~St (0/0) and ~St, St (0/1).
 // Of the two threads t and p = St or ~St (whichever has a_2 = 0) only the
-// lower one runs and writes all eight entries: every group is read by half
-// as many threads, the output is still written once.
+// lower one runs.  Tables are kept lazily (TwinGroup): the thread writes the
+// lower index of each of its four exchanged pairs (t and ~St at 0/0, t and St
+// at 0/1) and reads every group through its lower members, so a sweep reads
+// half of the groups and writes half of the stored table.
 template <typename T, bool SWAP>
 __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
                                                     const T *__restrict__ lag2,
@@ -172,7 +174,15 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
     if constexpr (kF32) {
         const double o1 = off[s1];
         d2 = (float)(off[s2] - o1);
-        y0 = 1.0f + first(pair4(lag2[0], lag2[1], lag2[2], lag2[3]) * 0.25f + d2);
+        T e[4];
+        if constexpr (SWAP) {
+            const TwinGroup tg = twin_group(0, n);
+            T q[4] = {lag2[tg.read], lag2[tg.read + 1], lag2[tg.read + 2], lag2[tg.read + 3]};
+            twin_values(q, tg.mode, e);
+        } else {
+            e[0] = lag2[0]; e[1] = lag2[1]; e[2] = lag2[2]; e[3] = lag2[3];
+        }
+        y0 = 1.0f + first(pair4(e[0], e[1], e[2], e[3]) * 0.25f + d2);
         if (t == 0) off[snew] = o1 + (double)y0;
     }
     if (t >= (n >> 3)) return;
@@ -186,7 +196,14 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
     }
 
     T g[4];
-    stream4<true>(lag2 + 4 * t, g);
+    if constexpr (SWAP) {
+        const TwinGroup tg = twin_group(4 * t, n);
+        T q[4];
+        stream4<true>(lag2 + tg.read, q);
+        twin_values(q, tg.mode, g);
+    } else {
+        stream4<true>(lag2 + 4 * t, g);
+    }
     T m2 = pair4(g[0], g[1], g[2], g[3]) * (T)0.25;
     if constexpr (kF32) m2 = m2 + d2;
     const T match = (T)1 + first(m2);
@@ -199,31 +216,49 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
         const uint64_t sb = (i & am) | ((i << 2) & bm);
         const uint64_t sa = ((i << 2) & am) | (i & bm);
         T b0, b1;
-        stream2<kF32>(lag1 + sb, b0, b1);
+        if constexpr (SWAP) {
+            // the advance-b pair is the low or high half of its group
+            const TwinGroup tg = twin_group(sb & ~(uint64_t)3, n);
+            T q[4], e[4];
+            stream4<kF32>(lag1 + tg.read, q);
+            twin_values(q, tg.mode, e);
+            const bool hi = (sb & 2) != 0;
+            b0 = hi ? e[2] : e[0];
+            b1 = hi ? e[3] : e[1];
+        } else {
+            stream2<kF32>(lag1 + sb, b0, b1);
+        }
         const T mb = (b0 + b1) * (T)0.5;
         // the advance-a pair is the even or odd half of an aligned group that
         // the neighbouring thread (t ^ 1) also reads: one vector load serves both
         T q[4];
-        const uint64_t grp = sa & ~(uint64_t)3;
-        stream4<kF32>(lag1 + (c ? (n - 4) - grp : grp), q);
-        const int o = (int)(sa & 1) ^ c;
-        const T ma = (q[o] + q[o + 2]) * (T)0.5;
+        const uint64_t grp = sa & ~(uint64_t)3, gbase = c ? (n - 4) - grp : grp;
+        if constexpr (SWAP) {
+            const TwinGroup tg = twin_group(gbase, n);
+            T r[4];
+            stream4<kF32>(lag1 + tg.read, r);
+            twin_values(r, tg.mode, q);
+        } else {
+            stream4<kF32>(lag1 + gbase, q);
+        }
+        const bool odd = ((sa & 1) ^ (uint64_t)c) != 0;
+        const T ma = ((odd ? q[1] : q[0]) + (odd ? q[3] : q[2])) * (T)0.5;
         mis[c] = vmax(first(mb), ma);
     }
 
     const T vm = kF32 ? (T)(match - y0) : match;
     const T v0 = kF32 ? (T)(mis[0] - y0) : mis[0];
     const T v1 = kF32 ? (T)(mis[1] - y0) : mis[1];
-    put(out + t, vm);
-    put(out + xc, vm);
-    put(out + nq + t, v0);
-    put(out + nq + xc, v1);
-    if constexpr (SWAP) {
-        const uint64_t sc = nq - 1 - st;
-        put(out + st, vm);
-        put(out + sc, vm);
-        put(out + nq + sc, v0);
+    if constexpr (SWAP) {  // the lower index of each exchanged pair
+        put(out + t, vm);
+        put(out + (nq - 1 - st), vm);
+        put(out + nq + t, v0);
         put(out + nq + st, v1);
+    } else {
+        put(out + t, vm);
+        put(out + xc, vm);
+        put(out + nq + t, v0);
+        put(out + nq + xc, v1);
     }
 }
 

@@ -1,5 +1,6 @@
-// Small device kernels around the sweep: clearing, copying a ring in, and
-// FP32 -> FP64 conversion for the FP64 polish.  Fill kernels stand in for hipMemsetAsync so that the calls
+// Small device kernels around the sweep: clearing, copying a ring in,
+// FP32 -> FP64 conversion for the FP64 polish, and the exchange-symmetry check
+// and completion of sigma = d = 2 tables.  Fill kernels stand in for hipMemsetAsync so that the calls
 // stay valid inside captured HIP graphs.
 #include "internal.h"
 
@@ -85,6 +86,21 @@ __global__ __launch_bounds__(kBlock) void check_swap_kernel(const W *__restrict_
     if (bad) *flag = 1u;
 }
 
+// a lazily written sigma = d = 2 table: every stored entry that is the upper
+// index of its exchanged pair takes the value of the lower one (reads only
+// lower entries, writes only upper ones)
+template <typename W>
+__global__ __launch_bounds__(kBlock) void materialize_swap_kernel(W *__restrict__ v, uint64_t n)
+{
+    const uint64_t ns = n >> 1, am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < ns; i += stride) {
+        const uint64_t j = ((i & am) >> 1) | ((i & bm) << 1);
+        const uint64_t js = (j & ns) ? j ^ (n - 1) : j;
+        if (js < i) v[i] = v[js];
+    }
+}
+
 unsigned grid_for(uint64_t work)
 {
     uint64_t b = (work + kBlock - 1) / kBlock;
@@ -105,6 +121,18 @@ hipError_t launch_check_swap(const Geometry &g, int dtype, const void *table, ui
     else
         check_swap_kernel<uint64_t><<<grid_for(g.ns), kBlock, 0, s>>>(
             static_cast<const uint64_t *>(table), g.n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_materialize_swap(const Geometry &g, int dtype, void *table, hipStream_t s)
+{
+    if (g.sigma != 2 || g.d != 2 || g.h < 2) return hipErrorInvalidValue;
+    if (dtype == LCSB_F32)
+        materialize_swap_kernel<uint32_t><<<grid_for(g.ns), kBlock, 0, s>>>(
+            static_cast<uint32_t *>(table), g.n);
+    else
+        materialize_swap_kernel<uint64_t><<<grid_for(g.ns), kBlock, 0, s>>>(
+            static_cast<uint64_t *>(table), g.n);
     return hipGetLastError();
 }
 

@@ -195,6 +195,50 @@ def test_fp64_exchange_symmetric_ring_takes_the_folded_path(pk, h):
     assert L.swap_symmetric()
 
 
+@pytest.mark.parametrize("h,dt", [(2, "f64"), (3, "f64"), (5, "f64"), (8, "f64"), (5, "f32")],
+                         ids=lambda v: str(v))
+def test_exchange_folded_passes_read_only_lower_entries(pk, h, dt):
+    """On an exchange-symmetric ring a sweep writes only the lower stored index
+    of each exchanged pair, and sweeps and certificates read only those.  With
+    every upper entry of both lags set to NaN, the certificate and the next
+    sweep must still match the oracle (FP64: bit for bit; FP32: the
+    certificate bit for bit, the sweep within the FP32 bound), and the table
+    lcsb_lag returns must be complete."""
+    say(f"lower-entry reads h={h} {dt}")
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    lags = [si.table(2, 2, h, seed=150 + k, dtype=tdt, exchange=True) for k in range(2)]
+    L = pk.Lcsb(2, 2, h, dt)
+    L.load_ring([x.cuda() for x in lags])
+    assert L.swap_symmetric()
+    ns = L.stored
+    idx = torch.arange(ns)
+    twin = si.representative(si.exchanged(idx, 2, 2, h), 2, 2, h)
+    upper = (twin < idx).cuda()
+    assert bool(upper.any())
+    ring = [x.numpy().astype(np.float64) for x in lags]
+    for t in range(3):
+        for k in (1, 2):
+            buf, off = L.lag(k)
+            assert off == 0.0 or dt == "f32"
+            buf[upper] = float("nan")
+        cur, _ = L.certify()
+        if dt == "f64" or t == 0:  # FP32: bit-exact while every offset is 0
+            _same_cert(cur, oracle.certify(2, 2, h, ring[0], ring[1]))
+        else:
+            assert cur["nonfinite"] == 0
+        L.iterate(1)
+        new = oracle.sweep(2, 2, h, ring)
+        got, o_new = L.lag(1)
+        full = _full(L, got).astype(np.float64)
+        assert not np.isnan(full).any()
+        if dt == "f64":
+            assert np.array_equal(full, new), f"sweep {t}"
+            ring = [new] + ring[:-1]
+        else:
+            assert np.max(np.abs(o_new + full - new)) <= _fp32_bound(8.0 + 1.0 + 2.0 * t)
+            ring = [o_new + full] + ring[:-1]  # the true values of the stored FP32 table
+
+
 @pytest.mark.parametrize("h", [2, 4, 9])
 def test_fp32_exchange_symmetric_ring(pk, h):
     say(f"exchange-symmetric FP32 ring h={h}")

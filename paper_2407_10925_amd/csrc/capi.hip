@@ -72,8 +72,11 @@ int need_ready(const lcsb_ctx *c)
     return LCSB_OK;
 }
 
-// the exchange-folded kernels apply to sigma = d = 2 at l >= 2
-bool swap_shape(const lcsb_ctx *c) { return c->g.sigma == 2 && c->g.d == 2 && c->g.h >= 2; }
+// the exchange-folded kernels apply to sigma = 2, d = 2 or 3, at l >= 2
+bool swap_shape(const lcsb_ctx *c)
+{
+    return c->g.sigma == 2 && (c->g.d == 2 || c->g.d == 3) && c->g.h >= 2;
+}
 
 void clear_lazy(lcsb_ctx *c) { for (int k = 0; k < 4; ++k) c->lazy[k] = 0; }
 
@@ -550,7 +553,7 @@ int lcsb_init_seed_mlp(lcsb_ctx *c, const float *params, const uint16_t *wbf16, 
         return hip_fail(c, e, "seed");
     c->sweeps = 0;
     c->best = initial_best();
-    c->swap_sym = swap_shape(c);  // one value per exchange orbit, written to every member
+    c->swap_sym = c->g.d == 2 && swap_shape(c);  // one value per exchange orbit, written to every member
     clear_lazy(c);
     c->state = kReady;
     return LCSB_OK;

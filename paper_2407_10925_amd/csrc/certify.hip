@@ -63,11 +63,11 @@ __device__ void block_reduce(double &v, uint64_t &i, uint64_t &c)
     }
 }
 
-// n = stored entries.  SWAP (sigma = d = 2, both tables symmetric in the two
-// strings): u - prev is equal at a stored entry and at its exchanged twin (the
-// a and b bits of every slot swapped, folded back to string-1 head 0), so only
-// the lower of the two is read, counted twice unless it is its own twin.
-template <typename T, bool SWAP>
+// n = stored entries.  SWAP (sigma = 2, d = 2 or 3, both tables symmetric in
+// strings 1 and 2): u - prev is equal at a stored entry and at its exchanged
+// twin (exchange_twin), so only the lower of the two is read, counted twice
+// unless it is its own twin.
+template <typename T, int SWAP_D>
 __global__ __launch_bounds__(kBlock) void cert_r(const T *__restrict__ u,
                                                 const T *__restrict__ prev, uint64_t n,
                                                 unsigned char *__restrict__ ws)
@@ -75,12 +75,10 @@ __global__ __launch_bounds__(kBlock) void cert_r(const T *__restrict__ u,
     double best = -INFINITY;
     uint64_t arg = 0, nonfinite = 0;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    const uint64_t full = 2 * n - 1, am = 0xAAAAAAAAAAAAAAAAull & full, bm = ~am & full;
     for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
         uint64_t mult = 1;
-        if constexpr (SWAP) {
-            const uint64_t x = ((j & am) >> 1) | ((j & bm) << 1);
-            const uint64_t js = (x & n) ? x ^ full : x;
+        if constexpr (SWAP_D != 0) {
+            const uint64_t js = exchange_twin(j, 2 * n, SWAP_D);
             if (js < j) continue;
             mult = js == j ? 1 : 2;
         }
@@ -324,7 +322,7 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
 // branches: the strings with head 1 advance (z = 0) and the strings with head
 // 0 advance (z = 1); k = |N| selects the lag and shift.  A branch that moves
 // string 1 of xc reads every value at the image of its index.
-template <int SET, typename T>
+template <int SET, bool SWAP, typename T>
 __device__ __forceinline__ double branch23(const T *__restrict__ u, uint64_t n, uint64_t i,
                                            int img, const double *shift, const Scales &sc)
 {
@@ -339,38 +337,71 @@ __device__ __forceinline__ double branch23(const T *__restrict__ u, uint64_t n, 
     for (int c = 0; c < 8; ++c)  // appended tuples in lexicographic order of the moved strings
         if ((c & ~SET) == 0) {
             const uint64_t e = base | (uint64_t)c;
-            lx[k++] = (double)u[img ? (n - 1) - e : e];
+            uint64_t at = img ? (n - 1) - e : e;
+            if constexpr (SWAP) {  // the lower member of its exchanged pair
+                const uint64_t tw = exchange_twin(at, n, 3);
+                at = tw < at ? tw : at;
+            }
+            lx[k++] = (double)u[at];
         }
     if constexpr (K == 1) return mean_rd<2>(lx, shift[1], sc.q[1]);
     double v[4] = {lx[0], lx[3], lx[1], lx[2]};  // complement-paired leaves
     return mean_rd<4>(v, shift[2], sc.q[2]);
 }
 
-template <typename T>
+// SWAP (a table symmetric in strings 1 and 2): as for d = 2, only the lower of
+// the threads t and p (Et or ~Et, as in the sweep) evaluates; every value is
+// read, and reported, at the lower index of its exchanged pair, and counts
+// for both coordinates unless p = t.
+template <typename T, bool SWAP>
 __device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int h, uint64_t t,
                                       const double *shift, const Scales &sc, double dR_up,
                                       WBest &best)
 {
     const int top = 3 * (h - 1);
-    const uint64_t xc = (n >> 3) - 1 - t;
+    const uint64_t mx = (n >> 3) - 1, xc = mx - t;
+    int mult = 1;
+    if constexpr (SWAP) {
+        const uint64_t et = exchange12(t, n >> 3);
+        const uint64_t p = (t & (mx + 1) >> 2) ? et ^ mx : et;
+        if (p < t) return;
+        mult = p == t ? 1 : 2;
+    }
+    auto lower = [&](uint64_t j) {
+        if constexpr (SWAP) {
+            const uint64_t tw = exchange_twin(j, n, 3);
+            return tw < j ? tw : j;
+        } else {
+            return j;
+        }
+    };
     double q8[8];
-    ld4(u + 8 * t, q8);
-    ld4(u + 8 * t + 4, q8 + 4);
+    if constexpr (SWAP) {
+        const TwinGroup tg = twin_group8(8 * t, n);
+        double r8[8];
+        ld4(u + tg.read, r8);
+        ld4(u + tg.read + 4, r8 + 4);
+        twin_values8(r8, tg.mode, q8);
+    } else {
+        ld4(u + 8 * t, q8);
+        ld4(u + 8 * t + 4, q8 + 4);
+    }
     double g[8] = {q8[0], q8[7], q8[1], q8[6], q8[2], q8[5], q8[3], q8[4]};
     const double f_match = 1.0 + first(mean_rd<8>(g, shift[3], sc.q[3]));
-    best.add((double)u[t], f_match, dR_up, t);
-    best.add((double)u[xc], f_match, dR_up, xc);
+    best.add((double)u[lower(t)], f_match, dR_up, lower(t), mult);
+    best.add((double)u[lower(xc)], f_match, dR_up, lower(xc), mult);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const uint64_t x = c ? xc : t;
 #define LCSB_HEAD(H)                                                                            \
         {                                                                                       \
             const uint64_t i = ((uint64_t)(H) << top) | x;                                      \
-            const double b1 = branch23<(H), T>(u, n, i, ((H) & 4) ? c : 0, shift, sc);        \
-            const double b0 = branch23<(~(H)) & 7, T>(u, n, i, ((~(H)) & 4) ? c : 0, shift,  \
-                                                      sc);                                      \
+            const double b1 = branch23<(H), SWAP, T>(u, n, i, ((H) & 4) ? c : 0, shift, sc);  \
+            const double b0 = branch23<(~(H)) & 7, SWAP, T>(u, n, i, ((~(H)) & 4) ? c : 0,   \
+                                                            shift, sc);                         \
             const double f0 = first(b0);                                                    \
-            best.add((double)u[i], b1 > f0 ? b1 : f0, dR_up, i);                                \
+            const uint64_t at = lower(i);                                                   \
+            best.add((double)u[at], b1 > f0 ? b1 : f0, dR_up, at, mult);                        \
         }
         LCSB_HEAD(1) LCSB_HEAD(2) LCSB_HEAD(3)
 #undef LCSB_HEAD
@@ -396,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u_arg, ui
     for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < nt; t += stride) {
         if constexpr (SIGMA == 2 && D == 2) w_s2d2<T, SWAP>(u, n, t, shift, sc, dR_up, best);
         else if constexpr (SIGMA == 4) w_s4d2<T>(u, n, h, t, shift, sc, dR_up, best);
-        else w_s2d3<T>(u, n, h, t, shift, sc, dR_up, best);
+        else w_s2d3<T, SWAP>(u, n, h, t, shift, sc, dR_up, best);
     }
     double w = best.w;
     uint64_t arg = best.arg, nonfinite = best.nonfinite;
@@ -549,6 +580,8 @@ hipError_t launch_w(const Geometry &g, const T *u, int swap_sym, unsigned char *
         cert_w<2, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else if (g.sigma == 4 && g.d == 2)
         cert_w<4, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
+    else if (g.sigma == 2 && g.d == 3 && swap_sym)
+        cert_w<2, 3, T, true><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else if (g.sigma == 2 && g.d == 3)
         cert_w<2, 3, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else
@@ -561,12 +594,13 @@ hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int
                          int prev_slot, int swap_sym, unsigned char *ws, hipStream_t s)
 {
     const int nb = reduce_blocks(g.ns);
+    const T *uu = static_cast<const T *>(u), *pp = static_cast<const T *>(prev);
     if (swap_sym && g.sigma == 2 && g.d == 2 && g.h >= 2)
-        cert_r<T, true><<<nb, kBlock, 0, s>>>(static_cast<const T *>(u),
-                                              static_cast<const T *>(prev), g.ns, ws);
+        cert_r<T, 2><<<nb, kBlock, 0, s>>>(uu, pp, g.ns, ws);
+    else if (swap_sym && g.sigma == 2 && g.d == 3 && g.h >= 2)
+        cert_r<T, 3><<<nb, kBlock, 0, s>>>(uu, pp, g.ns, ws);
     else
-        cert_r<T, false><<<nb, kBlock, 0, s>>>(static_cast<const T *>(u),
-                                               static_cast<const T *>(prev), g.ns, ws);
+        cert_r<T, 0><<<nb, kBlock, 0, s>>>(uu, pp, g.ns, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     cert_r_final<<<1, kBlock, 0, s>>>(ws, nb, g.d, std::is_same<T, float>::value ? 1 : 0,

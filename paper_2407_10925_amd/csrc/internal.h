@@ -46,7 +46,7 @@ struct SweepLaunch {
     int lag_slot[3];
     int new_slot;
     double *offsets;  // device, per slot (FP32 only)
-    int swap_sym;     // sigma = d = 2: the lag tables are symmetric under exchanging the strings
+    int swap_sym;     // sigma = 2, d = 2 or 3: the lag tables are symmetric in strings 1 and 2
                       // (read lazily, see TwinGroup; the new table is written lazily)
 };
 
@@ -63,8 +63,9 @@ hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const voi
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_fill_f64(double *p, uint64_t count, double v, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
-// sigma = d = 2, l >= 2: set *flag (device) to 1 unless every stored entry
-// equals, bit for bit, the stored entry of its string-exchanged tuple
+// sigma = 2, d = 2 or 3, l >= 2: set *flag (device) to 1 unless every stored
+// entry equals, bit for bit, the stored entry of its tuple with strings 1 and
+// 2 exchanged
 hipError_t launch_check_swap(const Geometry &g, int dtype, const void *table, uint32_t *flag,
                              hipStream_t s);
 // a lazily written table (see TwinGroup): set every upper entry to its lower twin
@@ -106,6 +107,64 @@ __device__ __forceinline__ void twin_values(const T *q, int mode, T *g)
     g[1] = mode == 1 ? q[2] : q[1];
     g[2] = (mode == 1 || mode == 3) ? q[1] : q[2];
     g[3] = (mode == 2 || mode == 4) ? q[0] : q[3];
+}
+
+// The same for sigma = 2, d = 3 with strings 1 and 2 exchanged: J swaps the
+// string-1 and string-2 bits of every 3-bit slot, then complements when that
+// makes the string-1 head 1.  Groups are aligned runs of eight (the last
+// slot, members c1 c2 c3); a twin group holds member v at PE[v] (c1 and c2
+// swapped) or, when J complements, at 7 - PE[v].
+__host__ __device__ inline uint64_t exchange12(uint64_t x, uint64_t n)
+{
+    const uint64_t r3 = (n - 1) / 7;  // bit 0 of every slot
+    return (x & r3) | ((x & (r3 << 2)) >> 1) | ((x & (r3 << 1)) << 1);
+}
+
+// J for d = 2 (bits of each 2-bit slot swapped) or d = 3 (exchange12), folded
+__host__ __device__ inline uint64_t exchange_twin(uint64_t j, uint64_t n, int d)
+{
+    uint64_t x;
+    if (d == 2) {
+        const uint64_t am = 0xAAAAAAAAAAAAAAAAull & (n - 1);
+        x = ((j & am) >> 1) | ((j & ~am & (n - 1)) << 1);
+    } else {
+        x = exchange12(j, n);
+    }
+    return (x & (n >> 1)) ? x ^ (n - 1) : x;
+}
+
+__host__ __device__ inline TwinGroup twin_group8(uint64_t base, uint64_t n)
+{
+    const uint64_t x = exchange12(base, n);
+    const bool h1 = (x & (n >> 1)) != 0;
+    const uint64_t jb = h1 ? x ^ ((n - 1) & ~(uint64_t)7) : x;
+    if (jb > base) return {base, 0};
+    if (jb < base) return {jb, h1 ? 2 : 1};
+    return {base, h1 ? 4 : 3};
+}
+
+// the group's eight values, in its own member order, from the loaded q:
+// mode 1 q[PE[v]], 2 q[7 - PE[v]], 3 q[min(v, PE[v])], 4 q[min(v, 7 - PE[v])],
+// PE = {0, 1, 4, 5, 2, 3, 6, 7}
+template <typename T>
+__device__ __forceinline__ void twin_values8(const T *qm, int mode, T *g)
+{
+    // the values as registers: otherwise the compiler may turn the selects
+    // below into one load from a private copy of q at a computed offset
+    T q[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        q[v] = qm[v];
+        asm volatile("" : "+v"(q[v]));
+    }
+    g[0] = mode == 2 ? q[7] : q[0];
+    g[1] = mode == 2 ? q[6] : q[1];
+    g[2] = (mode == 1) ? q[4] : mode == 2 ? q[3] : q[2];
+    g[3] = (mode == 1) ? q[5] : mode == 2 ? q[2] : mode == 4 ? q[2] : q[3];
+    g[4] = (mode == 1 || mode == 3) ? q[2] : mode == 2 ? q[5] : q[4];
+    g[5] = (mode == 1 || mode == 3) ? q[3] : (mode == 2 || mode == 4) ? q[4] : q[5];
+    g[6] = mode == 2 ? q[1] : mode == 4 ? q[1] : q[6];
+    g[7] = (mode == 2 || mode == 4) ? q[0] : q[7];
 }
 
 // Learned warm start (csrc/mlp.hip)

@@ -336,7 +336,17 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
 // z=1 -> {1}.  Thread t < n/16 computes x = t and its complement xc; a
 // branch that moves string 1 reads head s1_2, which is 1 for xc, and then
 // reads the image group, whose members are the reversed originals.
-template <typename T>
+//
+// SWAP (a ring symmetric in strings 1 and 2, bit for bit): with E the
+// exchange of the s1 and s2 bits of every slot of x, 000|x and 001|x are
+// exchanged with 000|Ex and 001|Ex, and 010|x with 011|~Ex (the exchange,
+// then the complement that brings string 1's head back to 0).  Thread t and
+// the thread p of its twin (Et when s2_2 = 0, ~Et otherwise) compute the same
+// eight values, so only the lower runs; it stores each value at the lower
+// index of its exchanged pair (exchange_twin) and reads every group through
+// its lower members (TwinGroup, eight members), so a sweep reads half of the
+// groups and writes half of the table.
+template <typename T, bool SWAP>
 __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
                                                     const T *__restrict__ lag2,
                                                     const T *__restrict__ lag3,
@@ -353,16 +363,36 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
         d2 = (float)(off[s2] - o1);
         d3 = (float)(off[s3] - o1);
         T g0[8];
-        load8(lag3, g0);
+        if constexpr (SWAP) {
+            const TwinGroup tg = twin_group8(0, n);
+            T q[8];
+            load8(lag3 + tg.read, q);
+            twin_values8(q, tg.mode, g0);
+        } else {
+            load8(lag3, g0);
+        }
         y0 = 1.0f + first(pair8(g0) * 0.125f + d3);
         if (t == 0) off[snew] = o1 + (double)y0;
     }
     if (t >= (n >> 4)) return;
-    const uint64_t xc = (n >> 3) - 1 - t;
+    const uint64_t mx = (n >> 3) - 1, xc = mx - t;
+    if constexpr (SWAP) {
+        const uint64_t et = exchange12(t, n >> 3);
+        const uint64_t p = (t & (mx + 1) >> 2) ? et ^ mx : et;  // s2_2 = 1: ~Et has s1_2 = 0
+        if (p < t) return;
+    }
 
     T g[8];
-    stream4<kF32>(lag3 + 8 * t, g);  // read once: non-temporal in FP32 (4.8% faster)
-    stream4<kF32>(lag3 + 8 * t + 4, g + 4);
+    if constexpr (SWAP) {
+        const TwinGroup tg = twin_group8(8 * t, n);
+        T q[8];
+        stream4<kF32>(lag3 + tg.read, q);
+        stream4<kF32>(lag3 + tg.read + 4, q + 4);
+        twin_values8(q, tg.mode, g);
+    } else {
+        stream4<kF32>(lag3 + 8 * t, g);  // read once: non-temporal in FP32 (4.8% faster)
+        stream4<kF32>(lag3 + 8 * t + 4, g + 4);
+    }
     T all3 = pair8(g) * (T)0.125;
     if constexpr (kF32) all3 = all3 + d3;
     const T match = (T)1 + first(all3);
@@ -371,10 +401,18 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
     const uint64_t r3 = mask / 7;  // 001 in every slot
     const uint64_t S1 = r3 << 2, S2 = r3 << 1, S3 = r3;
     auto base = [&](uint64_t i, uint64_t sm) { return (i & ~sm) | ((i << 3) & sm & mask); };
-    // the aligned 8-group holding entry e, or its image
+    // the aligned 8-group holding entry e, or its image (through its lower
+    // members if SWAP)
     auto group = [&](const T *tab, uint64_t e, int img, T *q) {
-        const uint64_t grp = e & ~(uint64_t)7;
-        load8(tab + (img ? (mask - 7) - grp : grp), q);
+        const uint64_t grp = e & ~(uint64_t)7, at = img ? (mask - 7) - grp : grp;
+        if constexpr (SWAP) {
+            const TwinGroup tg = twin_group8(at, n);
+            T r[8];
+            load8(tab + tg.read, r);
+            twin_values8(r, tg.mode, q);
+        } else {
+            load8(tab + at, q);
+        }
     };
 
 #pragma unroll
@@ -386,7 +424,15 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
             const uint64_t i = ((uint64_t)1 << top) | x;
             const uint64_t b1 = base(i, S3), b2 = base(i, S1 | S2);
             T p0, p1;
-            load2(lag1 + b1, p0, p1);
+            if constexpr (SWAP) {
+                T e[8];
+                group(lag1, b1, 0, e);
+                const int o = (int)(b1 & 7);
+                p0 = e[o];
+                p1 = e[o + 1];
+            } else {
+                load2(lag1 + b1, p0, p1);
+            }
             const T k1 = (p0 + p1) * (T)0.5;
             T q[8];
             group(lag2, b2, c, q);
@@ -413,7 +459,14 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
             const uint64_t i = ((uint64_t)3 << top) | x;
             const uint64_t b2 = base(i, S2 | S3), b1 = base(i, S1);
             T q[4];
-            load4(lag2 + b2, q);
+            if constexpr (SWAP) {
+                T e[8];
+                group(lag2, b2, 0, e);
+                const int o = (int)(b2 & 4);
+                q[0] = e[o]; q[1] = e[o + 1]; q[2] = e[o + 2]; q[3] = e[o + 3];
+            } else {
+                load4(lag2 + b2, q);
+            }
             T k2 = pair4(q[0], q[1], q[2], q[3]) * (T)0.25;
             if constexpr (kF32) k2 = k2 + d2;
             T e[8];
@@ -423,8 +476,14 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
             val[3] = vmax(first(k2), k1);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            put(out + (((uint64_t)r << top) | x), kF32 ? (T)(val[r] - y0) : val[r]);
+        for (int r = 0; r < 4; ++r) {
+            uint64_t j = ((uint64_t)r << top) | x;
+            if constexpr (SWAP) {  // the lower index of the exchanged pair
+                const uint64_t jj = exchange_twin(j, n, 3);
+                j = jj < j ? jj : j;
+            }
+            put(out + j, kF32 ? (T)(val[r] - y0) : val[r]);
+        }
     }
 }
 
@@ -582,9 +641,14 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
         sweep_s4d2<T><<<grid, block, 0, s>>>(l1, l2, out, g.n, g.h, a.offsets, a.lag_slot[0],
                                               a.lag_slot[1], a.new_slot);
     } else if (g.sigma == 2 && g.d == 3) {
-        sweep_s2d3<T><<<grid, block, 0, s>>>(l1, l2, l3, out, g.n, g.h, a.offsets,
-                                              a.lag_slot[0], a.lag_slot[1], a.lag_slot[2],
-                                              a.new_slot);
+        if (a.swap_sym)
+            sweep_s2d3<T, true><<<grid, block, 0, s>>>(l1, l2, l3, out, g.n, g.h, a.offsets,
+                                                       a.lag_slot[0], a.lag_slot[1],
+                                                       a.lag_slot[2], a.new_slot);
+        else
+            sweep_s2d3<T, false><<<grid, block, 0, s>>>(l1, l2, l3, out, g.n, g.h, a.offsets,
+                                                        a.lag_slot[0], a.lag_slot[1],
+                                                        a.lag_slot[2], a.new_slot);
     } else {
         return hipErrorInvalidValue;
     }

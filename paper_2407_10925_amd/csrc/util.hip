@@ -68,35 +68,31 @@ __global__ __launch_bounds__(kBlock) void upcast_range(const float *src, const d
     }
 }
 
-// sigma = d = 2: raise *flag if a stored entry differs, bit for bit, from the
-// stored entry of its tuple with the two strings exchanged (the a and b bits
-// of every slot swapped, then complemented when that makes the head 1)
-template <typename W>
+// sigma = 2, d = 2 or 3: raise *flag if a stored entry differs, bit for bit,
+// from the stored entry of its tuple with strings 1 and 2 exchanged
+// (exchange_twin)
+template <typename W, int D>
 __global__ __launch_bounds__(kBlock) void check_swap_kernel(const W *__restrict__ v, uint64_t n,
                                                             uint32_t *__restrict__ flag)
 {
-    const uint64_t ns = n >> 1, am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
+    const uint64_t ns = n >> 1;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     bool bad = false;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < ns; i += stride) {
-        const uint64_t j = ((i & am) >> 1) | ((i & bm) << 1);
-        const uint64_t js = (j & ns) ? j ^ (n - 1) : j;
-        bad = bad || v[i] != v[js];
-    }
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < ns; i += stride)
+        bad = bad || v[i] != v[exchange_twin(i, n, D)];
     if (bad) *flag = 1u;
 }
 
-// a lazily written sigma = d = 2 table: every stored entry that is the upper
-// index of its exchanged pair takes the value of the lower one (reads only
-// lower entries, writes only upper ones)
-template <typename W>
+// a lazily written table: every stored entry that is the upper index of its
+// exchanged pair takes the value of the lower one (reads only lower entries,
+// writes only upper ones)
+template <typename W, int D>
 __global__ __launch_bounds__(kBlock) void materialize_swap_kernel(W *__restrict__ v, uint64_t n)
 {
-    const uint64_t ns = n >> 1, am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
+    const uint64_t ns = n >> 1;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < ns; i += stride) {
-        const uint64_t j = ((i & am) >> 1) | ((i & bm) << 1);
-        const uint64_t js = (j & ns) ? j ^ (n - 1) : j;
+        const uint64_t js = exchange_twin(i, n, D);
         if (js < i) v[i] = v[js];
     }
 }
@@ -114,24 +110,38 @@ unsigned grid_for(uint64_t work)
 hipError_t launch_check_swap(const Geometry &g, int dtype, const void *table, uint32_t *flag,
                              hipStream_t s)
 {
-    if (g.sigma != 2 || g.d != 2 || g.h < 2) return hipErrorInvalidValue;
-    if (dtype == LCSB_F32)
-        check_swap_kernel<uint32_t><<<grid_for(g.ns), kBlock, 0, s>>>(
+    if (g.sigma != 2 || (g.d != 2 && g.d != 3) || g.h < 2) return hipErrorInvalidValue;
+    const unsigned grid = grid_for(g.ns);
+    if (dtype == LCSB_F32 && g.d == 2)
+        check_swap_kernel<uint32_t, 2><<<grid, kBlock, 0, s>>>(
             static_cast<const uint32_t *>(table), g.n, flag);
+    else if (dtype == LCSB_F32)
+        check_swap_kernel<uint32_t, 3><<<grid, kBlock, 0, s>>>(
+            static_cast<const uint32_t *>(table), g.n, flag);
+    else if (g.d == 2)
+        check_swap_kernel<uint64_t, 2><<<grid, kBlock, 0, s>>>(
+            static_cast<const uint64_t *>(table), g.n, flag);
     else
-        check_swap_kernel<uint64_t><<<grid_for(g.ns), kBlock, 0, s>>>(
+        check_swap_kernel<uint64_t, 3><<<grid, kBlock, 0, s>>>(
             static_cast<const uint64_t *>(table), g.n, flag);
     return hipGetLastError();
 }
 
 hipError_t launch_materialize_swap(const Geometry &g, int dtype, void *table, hipStream_t s)
 {
-    if (g.sigma != 2 || g.d != 2 || g.h < 2) return hipErrorInvalidValue;
-    if (dtype == LCSB_F32)
-        materialize_swap_kernel<uint32_t><<<grid_for(g.ns), kBlock, 0, s>>>(
+    if (g.sigma != 2 || (g.d != 2 && g.d != 3) || g.h < 2) return hipErrorInvalidValue;
+    const unsigned grid = grid_for(g.ns);
+    if (dtype == LCSB_F32 && g.d == 2)
+        materialize_swap_kernel<uint32_t, 2><<<grid, kBlock, 0, s>>>(
             static_cast<uint32_t *>(table), g.n);
+    else if (dtype == LCSB_F32)
+        materialize_swap_kernel<uint32_t, 3><<<grid, kBlock, 0, s>>>(
+            static_cast<uint32_t *>(table), g.n);
+    else if (g.d == 2)
+        materialize_swap_kernel<uint64_t, 2><<<grid, kBlock, 0, s>>>(
+            static_cast<uint64_t *>(table), g.n);
     else
-        materialize_swap_kernel<uint64_t><<<grid_for(g.ns), kBlock, 0, s>>>(
+        materialize_swap_kernel<uint64_t, 3><<<grid, kBlock, 0, s>>>(
             static_cast<uint64_t *>(table), g.n);
     return hipGetLastError();
 }

@@ -239,11 +239,23 @@ def time_to_bound(pk, h, train_steps=1000):
     mixed:   FP32 from zero until its error floor (fp32_until_floor), then the
              FP64 polish (polish) until the best bound reaches B - 1e-9.
     learned: as mixed, from the warm-start network's seed (learned_run).
+
+    Each run also reports the algorithmic bytes of its sweeps over its whole
+    wall time against the HBM peak (certificates, upcast and seeding count
+    as time, not as bytes: a lower bound on the HBM use of the run).
     """
     import torch
     out = {}
     P = pk.Lcsb(2, 2, h, "f64")
     P.init_zero()
+    alg64 = algorithmic_bytes(P, 8)      # every ring here is exchange-symmetric
+    alg32 = alg64 // 2
+
+    def hbm(sweeps32, sweeps64, seconds):
+        tbps = (sweeps32 * alg32 + sweeps64 * alg64) / seconds / 1e12
+        return {"sweep_algorithmic_TBps": round(tbps, 3),
+                "roofline_frac": round(tbps * 1e3 / HBM_PEAK_GBS, 4)}
+
     cur, best, _, why = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, stop_delta=1e-10)
     B = best["bound"]
     target = B - 1e-9
@@ -271,7 +283,7 @@ def time_to_bound(pk, h, train_steps=1000):
                                "switch_after_s": round(t_switch, 4), "bound": best["bound"],
                                "reached": best["bound"] >= target,
                                "fp32_table_max_error_over_spread": rel_err,
-                               "fp64_table_spread": spread}
+                               "fp64_table_spread": spread, **hbm(sweeps32, sweeps64, t_mixed)}
     log(f"time to bound, FP32 + FP64 polish: {t_mixed:.3f} s, {sweeps32} FP32 + "
         f"{sweeps64} FP64 sweeps, bound {best['bound']:.12f}")
     del M
@@ -285,10 +297,12 @@ def time_to_bound(pk, h, train_steps=1000):
     t_plain = time.perf_counter() - t0
     out["plain_f64"] = {"seconds": round(t_plain, 4), "sweeps": cur["sweep"], "certificates": certs,
                         "bound": B, "converged_after_sweeps": converged_after,
-                        "certificate_every": TTB_CADENCE}
+                        "certificate_every": TTB_CADENCE, **hbm(0, cur["sweep"], t_plain)}
     log(f"time to bound, plain FP64: {t_plain:.3f} s, {cur['sweep']} sweeps, bound {B:.12f}")
 
     out["mixed_learned"] = learned_run(pk, h, P, target, train_steps)
+    ml = out["mixed_learned"]
+    ml.update(hbm(ml["sweeps_f32"], ml["sweeps_f64"], ml["seconds"]))
     out["policy"] = {"certificate_every": TTB_CADENCE, "switch_gain": SWITCH_GAIN,
                      "polish_first": POLISH_FIRST, "polish_every": POLISH_CADENCE,
                      "driver": "lcsb_run"}
@@ -383,8 +397,8 @@ def config_table(pk):
         sweep_ms = e[0].elapsed_time(e[1]) / reps
         cert_ms = e[2].elapsed_time(e[3])
         elem = 8 if dt == "f64" else 4
-        folded = sigma == 2 and d == 2 and L.swap_symmetric()
-        algo = algorithmic_bytes(L, elem) if folded else (d + 1) * elem * L.stored
+        folded = L.swap_symmetric()  # exchange-folded: every table at one entry per pair
+        algo = (d + 1) * elem * L.stored // (2 if folded else 1)
         rows.append({"sigma": sigma, "d": d, "l": h, "dtype": dt, "entries": L.n,
                      "exchange_folded": folded,
                      "sweep_ms": round(sweep_ms, 4), "certificate_ms": round(cert_ms, 3),

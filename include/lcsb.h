@@ -119,9 +119,9 @@ int lcsb_init_zero(lcsb_ctx *ctx);
  * with src at the stored indices.  offsets (host, d doubles, may be NULL =
  * all zero) are the values the FP32 tables are relative to (true value =
  * offset + stored value); ignored for LCSB_F64.  Resets the sweep count and
- * the best certificate.  For sigma = d = 2 it then checks whether the ring
- * is symmetric under exchanging the two strings (see lcsb_swap_symmetric;
- * one read of the ring, synchronises the stream). */
+ * the best certificate.  For sigma = 2 (d = 2 or 3, l >= 2) it then checks
+ * whether the ring is symmetric under exchanging strings 1 and 2 (see
+ * lcsb_swap_symmetric; one read of the ring, synchronises the stream). */
 int lcsb_load_ring(lcsb_ctx *ctx, const void *const *src, int nsrc, const double *offsets);
 
 /* Apply k >= 0 sweeps v_new = F(lag 1, .., lag d) of eq. (4) on the bound
@@ -152,11 +152,12 @@ int lcsb_certify(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
  * stream (one kernel over the table), so every stored entry can be read. */
 int lcsb_lag(const lcsb_ctx *ctx, int k, void **dev_ptr, double *offset);
 
-/* sigma = d = 2, l >= 2: *symmetric = 1 when every lag table is known to be
- * symmetric, bit for bit, under exchanging the two strings (after
+/* sigma = 2, d = 2 or 3, l >= 2: *symmetric = 1 when every lag table is
+ * known to be symmetric, bit for bit, under exchanging strings 1 and 2 (after
  * lcsb_init_zero, lcsb_init_seed_mlp, a load_ring or load of such a ring, an
  * upcast of such a ring, and every sweep of such a ring: F keeps the
- * symmetry exactly).  lcsb_iterate and lcsb_certify then compute one tuple of
+ * symmetry exactly, the sums being taken in the order stated at
+ * lcsb_iterate).  lcsb_iterate and lcsb_certify then compute one tuple of
  * each exchanged pair, and a sweep writes only the entry of the pair with the
  * lower stored index (lcsb_lag and lcsb_save complete the table before it is
  * read), which halves the bytes they move; otherwise (and for every other

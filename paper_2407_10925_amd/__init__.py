@@ -133,8 +133,9 @@ class Lcsb:
         return s.value, best.as_dict()
 
     def swap_symmetric(self) -> bool:
-        """Whether the ring is known to be symmetric in the two strings
-        (sigma = d = 2): sweeps and certificates then read half the bytes."""
+        """Whether the ring is known to be symmetric in strings 1 and 2
+        (sigma = 2, d = 2 or 3): sweeps and certificates then move half the
+        bytes."""
         v = C.c_int()
         check(self._lib.lcsb_swap_symmetric(self._ctx, C.byref(v)))
         return bool(v.value)

@@ -42,7 +42,13 @@
  *     maps each pair to itself, and for |N| = 2 so does exchanging the two
  *     moved strings, so the tree only sees the two operands of some
  *     additions swapped: F then keeps the complement symmetry of eq. (10)
- *     and, for d = 2, the exchange of the two strings bit for bit.
+ *     and, for d = 2, the exchange of the two strings bit for bit.  For
+ *     sigma = 4 and two moved strings the sixteen leaves (c_1 c_2) are, in
+ *     order, the pairs {ab, ba} with a xor b = 1 (01 10 23 32), = 2
+ *     (02 20 13 31), = 3 (03 30 12 21), then {aa, ~a~a} (00 33 11 22), ~ the
+ *     complement of a symbol (xor 3): every relabelling c -> c xor m and the
+ *     exchange of the two moved strings map pairs to pairs and each group of
+ *     four to a group of four, so the tree keeps both symmetries bit for bit.
  *   - The certificate is made rigorous by directed rounding: the arguments
  *     v_d + (d-k)R and every step of F are rounded toward -inf, W and E
  *     toward +inf, and the reported bound d (R - E) toward -inf.  The C
@@ -170,6 +176,13 @@ static double F_z(const or_shape *s, const or_args *a, const int *sym, int z,
             uint64_t t = j >> 1;
             leaves[j] = buf[(j & 1) ? count - 1 - t : t];
         }
+        return pairwise_sum(leaves, count) / (double)count;
+    }
+    if (s->sigma == 4 && count == 16) {
+        /* exchange- and relabel-invariant order of the tuples 4 c_1 + c_2 */
+        static const int order16[16] = {1, 4, 11, 14, 2, 8, 7, 13, 3, 12, 6, 9, 0, 15, 5, 10};
+        double *leaves = buf + count;
+        for (int j = 0; j < 16; ++j) leaves[j] = buf[order16[j]];
         return pairwise_sum(leaves, count) / (double)count;
     }
     return pairwise_sum(buf, count) / (double)count;

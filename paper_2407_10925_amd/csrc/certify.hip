@@ -284,9 +284,12 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
 {
     const int top = 4 * (h - 1);
     const uint64_t am = 0xCCCCCCCCCCCCCCCCull & (n - 1), bm = ~am & (n - 1);
-    double g[16];
+    double q16[16];
 #pragma unroll
-    for (int k = 0; k < 16; k += 4) ld4(u + 16 * t + k, g + k);
+    for (int k = 0; k < 16; k += 4) ld4(u + 16 * t + k, q16 + k);
+    // leaves in the sweep's order (tree16): pairs {ab, ba} by a xor b, {aa, ~a~a}
+    double g[16] = {q16[1], q16[4], q16[11], q16[14], q16[2], q16[8], q16[7], q16[13],
+                    q16[3], q16[12], q16[6], q16[9], q16[0], q16[15], q16[5], q16[10]};
     const double m_both = mean_rd<16>(g, shift[2], sc.q[4]);
     const double f_match = 1.0 + first(m_both);
     double ma[4];
@@ -462,10 +465,12 @@ struct L1 {
         }
         return head;
     }
-    template <int CNT>  // appended tuple at leaf j of the branch tree
+    template <int CNT>  // appended tuple at leaf j of the branch tree (as the sweep's)
     static __device__ __forceinline__ int leaf(int j)
     {
-        return SIGMA == 2 && (j & 1) ? CNT - 1 - (j >> 1) : SIGMA == 2 ? j >> 1 : j;
+        constexpr int order16[16] = {1, 4, 11, 14, 2, 8, 7, 13, 3, 12, 6, 9, 0, 15, 5, 10};
+        if (SIGMA == 4) return CNT == 16 ? order16[j] : j;
+        return (j & 1) ? CNT - 1 - (j >> 1) : j >> 1;
     }
 };
 

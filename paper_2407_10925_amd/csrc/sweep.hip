@@ -29,7 +29,9 @@
 // lexicographic order (first advanced string most significant); for sigma = 2
 // the leaves are the tuples t starting with 0, each followed by its complement
 // ~t (00, 11, 01, 10), so that complementing the symbols, and for two moved
-// strings exchanging them, maps every pair to itself.  It multiplies by
+// strings exchanging them, maps every pair to itself; for sigma = 4 and two
+// moved strings they are the pairs {ab, ba} grouped by a xor b, then
+// {aa, ~a~a} (tree16).  It multiplies by
 // the exact power of two sigma^-k, takes the max over branches, and adds 1 to
 // all-match tuples.  FP32 tables store values relative to a per-slot FP64
 // offset: a branch reading lag k adds delta_k = offset(lag k) - offset(lag 1)
@@ -56,14 +58,15 @@ __device__ __forceinline__ T pair8(const T *g)
     return ((g[0] + g[7]) + (g[1] + g[6])) + ((g[2] + g[5]) + (g[3] + g[4]));
 }
 
+// sigma = 4 all-advance group (member 4 c1 + c2): pairs {ab, ba} grouped by
+// a xor b, then {aa, ~a~a}, so that the exchange of the two strings and every
+// relabelling c -> c xor m only swap operands
 template <typename T>
-__device__ __forceinline__ T tree8(const T *g)
+__device__ __forceinline__ T tree16(const T *g)
 {
-    return tree4(g[0], g[1], g[2], g[3]) + tree4(g[4], g[5], g[6], g[7]);
+    return (((g[1] + g[4]) + (g[11] + g[14])) + ((g[2] + g[8]) + (g[7] + g[13]))) +
+           (((g[3] + g[12]) + (g[6] + g[9])) + ((g[0] + g[15]) + (g[5] + g[10])));
 }
-
-template <typename T>
-__device__ __forceinline__ T tree16(const T *g) { return tree8(g) + tree8(g + 8); }
 
 template <typename T>
 __device__ __forceinline__ T vmax(T best, T cand) { return cand > best ? cand : best; }
@@ -517,7 +520,9 @@ struct L1 {
     template <int CNT>
     static __device__ __forceinline__ int leaf(int j)
     {
-        return SIGMA == 2 && (j & 1) ? CNT - 1 - (j >> 1) : SIGMA == 2 ? j >> 1 : j;
+        constexpr int order16[16] = {1, 4, 11, 14, 2, 8, 7, 13, 3, 12, 6, 9, 0, 15, 5, 10};
+        if (SIGMA == 4) return CNT == 16 ? order16[j] : j;
+        return (j & 1) ? CNT - 1 - (j >> 1) : j >> 1;
     }
 };
 

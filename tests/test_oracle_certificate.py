@@ -126,19 +126,45 @@ def test_summation_tree_convention(orc):
     assert F[0] == 1.0 + paired
 
 
-@pytest.mark.parametrize("d,h", [(2, 2), (2, 3), (3, 2)])
-def test_sigma2_tree_keeps_string_exchange_bit_for_bit(orc, d, h):
-    """With the complement-paired order, a sweep of tables symmetric under
-    exchanging strings 1 and 2 returns a table with the same symmetry bit
-    for bit: the all-advance pairs t, ~t map to themselves or to each other,
-    a branch moving strings 1 and 2 keeps its pairs, and a branch moving one
-    of them and string 3 becomes the branch moving the other, with its
-    leaves in the same order.  Random values over sixty binades make any
-    other association of the lag-2 (d = 2) or lag-3 (d = 3) group round
-    differently somewhere."""
-    sigma = 2
+def test_sigma4_summation_order(orc):
+    """Reading for sigma = 4: the sixteen all-advance tuples of a 0/0 pair
+    are summed in the order 01 10 23 32 | 02 20 13 31 | 03 30 12 21 |
+    00 33 11 22 (pairs {ab, ba} grouped by a xor b, then {aa, ~a~a}), a
+    balanced tree over that list.  Values around 2^53 tell it from the
+    lexicographic order: at l = 1 the group of the 0/0 pair is lag-2
+    entries 0..15 (index 4 c_1 + c_2)."""
+    big = 2.0 ** 53
+    lag2 = np.zeros(16)
+    lag2[1], lag2[4] = big, 1.0        # a pair of the new order: big + 1 rounds to big
+    lag2[2], lag2[3] = -big, 1.0       # siblings in lexicographic order instead
+    lag1 = np.zeros(16)
+    F = orc.sweep(4, 2, 1, [lag1, lag2])
+    order = [1, 4, 11, 14, 2, 8, 7, 13, 3, 12, 6, 9, 0, 15, 5, 10]
+
+    def tree(v):
+        v = list(v)
+        while len(v) > 1:
+            v = [v[i] + v[i + 1] for i in range(0, len(v), 2)]
+        return v[0]
+    new = tree(lag2[order]) / 16
+    lexicographic = tree(lag2) / 16
+    assert new != lexicographic
+    assert F[0] == 1.0 + new
+
+
+@pytest.mark.parametrize("sigma,d,h", [(2, 2, 2), (2, 2, 3), (2, 3, 2), (4, 2, 2)])
+def test_tree_keeps_string_exchange_bit_for_bit(orc, sigma, d, h):
+    """With the summation orders of the readings (complement-paired for
+    sigma = 2, pairs {ab, ba} grouped by a xor b for sigma = 4), a sweep of
+    tables symmetric under exchanging strings 1 and 2 returns a table with
+    the same symmetry bit for bit: the all-advance leaves map to sibling
+    leaves or sibling groups, a branch moving strings 1 and 2 keeps its
+    pairs, and (d = 3) a branch moving one of them and string 3 becomes the
+    branch moving the other, with its leaves in the same order.  Random
+    values over sixty binades make any other association of the all-advance
+    group round differently somewhere."""
     n = sigma ** (d * h)
-    rng = np.random.default_rng(7 + d * 10 + h)
+    rng = np.random.default_rng(7 + d * 10 + h + sigma)
     swap = np.empty(n, dtype=np.int64)
     for i in range(n):
         s = orc.decode(sigma, d, h, i).copy()

@@ -72,10 +72,12 @@ int need_ready(const lcsb_ctx *c)
     return LCSB_OK;
 }
 
-// the exchange-folded kernels apply to sigma = 2, d = 2 or 3, at l >= 2
+// the exchange-folded kernels apply to sigma = 2 with d = 2 or 3 and to
+// sigma = 4 with d = 2, at l >= 2
 bool swap_shape(const lcsb_ctx *c)
 {
-    return c->g.sigma == 2 && (c->g.d == 2 || c->g.d == 3) && c->g.h >= 2;
+    if (c->g.h < 2) return false;
+    return (c->g.sigma == 2 && (c->g.d == 2 || c->g.d == 3)) || (c->g.sigma == 4 && c->g.d == 2);
 }
 
 void clear_lazy(lcsb_ctx *c) { for (int k = 0; k < 4; ++k) c->lazy[k] = 0; }

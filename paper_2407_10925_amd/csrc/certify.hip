@@ -63,10 +63,10 @@ __device__ void block_reduce(double &v, uint64_t &i, uint64_t &c)
     }
 }
 
-// n = stored entries.  SWAP (sigma = 2, d = 2 or 3, both tables symmetric in
-// strings 1 and 2): u - prev is equal at a stored entry and at its exchanged
-// twin (exchange_twin), so only the lower of the two is read, counted twice
-// unless it is its own twin.
+// n = stored entries.  SWAP_D (2 or 3: sigma = 2 with d = SWAP_D; 4: sigma =
+// 4, d = 2; both tables symmetric in strings 1 and 2): u - prev is equal at a
+// stored entry and at its exchanged twin (exchange_twin, exchange_twin4), so
+// only the lower of the two is read, counted twice unless it is its own twin.
 template <typename T, int SWAP_D>
 __global__ __launch_bounds__(kBlock) void cert_r(const T *__restrict__ u,
                                                 const T *__restrict__ prev, uint64_t n,
@@ -78,7 +78,8 @@ __global__ __launch_bounds__(kBlock) void cert_r(const T *__restrict__ u,
     for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
         uint64_t mult = 1;
         if constexpr (SWAP_D != 0) {
-            const uint64_t js = exchange_twin(j, 2 * n, SWAP_D);
+            const uint64_t js =
+                SWAP_D == 4 ? exchange_twin4(j, 4 * n) : exchange_twin(j, 2 * n, SWAP_D);
             if (js < j) continue;
             mult = js == j ? 1 : 2;
         }
@@ -277,16 +278,40 @@ __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint
 // pair: advance b (stored directly), advance a (the image of the advance-a
 // group of (0, b1 xor m)|t), advance both (the image of t's group, shared
 // with the all-match value).
-template <typename T>
+// SWAP (a table symmetric in the two strings): as in the sweep, only the
+// lower of t and its twin thread p evaluates; each coordinate is read and
+// reported at the lower index of its exchanged pair and counts for both
+// unless p = t; groups are read through their lower members (Twin16).
+template <typename T, bool SWAP>
 __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int h, uint64_t t,
                                       const double *shift, const Scales &sc, double dR_up,
                                       WBest &best)
 {
     const int top = 4 * (h - 1);
     const uint64_t am = 0xCCCCCCCCCCCCCCCCull & (n - 1), bm = ~am & (n - 1);
+    const uint64_t rep = ((n >> 4) - 1) / 3;
+    uint64_t p = t;
+    int sx = 0, mult = 1;
+    if constexpr (SWAP) {
+        sx = (int)((t >> (top - 4)) & 3);
+        p = exchange4(t, n >> 4) ^ ((uint64_t)sx * rep);
+        if (p < t) return;
+        mult = p == t ? 1 : 2;
+    }
     double q16[16];
+    if constexpr (SWAP) {
+        const Twin16 tw = twin_group16(16 * t, n);
+        if (tw.kind == 2) {
 #pragma unroll
-    for (int k = 0; k < 16; k += 4) ld4(u + 16 * t + k, q16 + k);
+            for (int v = 0; v < 16; ++v) q16[v] = (double)u[member16(16 * t, tw, v)];
+        } else {  // the tree is invariant under the twin's member permutation
+#pragma unroll
+            for (int k = 0; k < 16; k += 4) ld4(u + tw.read + k, q16 + k);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k += 4) ld4(u + 16 * t + k, q16 + k);
+    }
     // leaves in the sweep's order (tree16): pairs {ab, ba} by a xor b, {aa, ~a~a}
     double g[16] = {q16[1], q16[4], q16[11], q16[14], q16[2], q16[8], q16[7], q16[13],
                     q16[3], q16[12], q16[6], q16[9], q16[0], q16[15], q16[5], q16[10]};
@@ -297,25 +322,45 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
     for (int v = 0; v < 4; ++v) {
         const uint64_t i = ((uint64_t)v << top) | t;
         const uint64_t sa = ((i << 4) & am) | (i & bm);
-        double q[4] = {(double)u[sa], (double)u[sa + 4], (double)u[sa + 8], (double)u[sa + 12]};
+        double q[4];
+        if constexpr (SWAP) {
+            const uint64_t gb = sa & ~(uint64_t)15;
+            const int o = (int)(sa & 15);
+            const Twin16 tw = twin_group16(gb, n);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = (double)u[member16(gb, tw, o + 4 * k)];
+        } else {
+            q[0] = u[sa]; q[1] = u[sa + 4]; q[2] = u[sa + 8]; q[3] = u[sa + 12];
+        }
         ma[v] = mean_rd<4>(q, shift[1], sc.q[2]);
     }
-    const uint64_t rep = ((n >> 4) - 1) / 3;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const uint64_t x = t ^ ((uint64_t)m * rep);
         const uint64_t sb = (x & am) | ((x << 4) & bm);
         double q[4];
-        ld4(u + sb, q);
+        if constexpr (SWAP) {
+            const uint64_t gb = sb & ~(uint64_t)15;
+            const int o = (int)(sb & 15);
+            const Twin16 tw = twin_group16(gb, n);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] = (double)u[member16(gb, tw, o + k)];
+        } else {
+            ld4(u + sb, q);
+        }
         const double mb = mean_rd<4>(q, shift[1], sc.q[2]);
-        best.add((double)u[x], f_match, dR_up, x);
+        // the lower index of the exchanged pair of coordinate (b1 << top) | x
+        auto at = [&](int b1) {
+            const uint64_t xt = p ^ ((uint64_t)(m ^ b1 ^ sx) * rep);
+            return ((uint64_t)b1 << top) | (SWAP && xt < x ? xt : x);
+        };
+        best.add((double)u[at(0)], f_match, dR_up, at(0), mult);
 #pragma unroll
         for (int b1 = 1; b1 < 4; ++b1) {
-            const uint64_t i = ((uint64_t)b1 << top) | x;
             double f = first(mb);  // z = 0 advances b
             f = ma[b1 ^ m] > f ? ma[b1 ^ m] : f;
             f = m_both > f ? m_both : f;
-            best.add((double)u[i], f, dR_up, i);
+            best.add((double)u[at(b1)], f, dR_up, at(b1), mult);
         }
     }
 }
@@ -429,7 +474,7 @@ __global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u_arg, ui
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < nt; t += stride) {
         if constexpr (SIGMA == 2 && D == 2) w_s2d2<T, SWAP>(u, n, t, shift, sc, dR_up, best);
-        else if constexpr (SIGMA == 4) w_s4d2<T>(u, n, h, t, shift, sc, dR_up, best);
+        else if constexpr (SIGMA == 4) w_s4d2<T, SWAP>(u, n, h, t, shift, sc, dR_up, best);
         else w_s2d3<T, SWAP>(u, n, h, t, shift, sc, dR_up, best);
     }
     double w = best.w;
@@ -583,6 +628,8 @@ hipError_t launch_w(const Geometry &g, const T *u, int swap_sym, unsigned char *
         cert_w<2, 2, T, true><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else if (g.sigma == 2 && g.d == 2)
         cert_w<2, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
+    else if (g.sigma == 4 && g.d == 2 && swap_sym)
+        cert_w<4, 2, T, true><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else if (g.sigma == 4 && g.d == 2)
         cert_w<4, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
     else if (g.sigma == 2 && g.d == 3 && swap_sym)
@@ -604,6 +651,8 @@ hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int
         cert_r<T, 2><<<nb, kBlock, 0, s>>>(uu, pp, g.ns, ws);
     else if (swap_sym && g.sigma == 2 && g.d == 3 && g.h >= 2)
         cert_r<T, 3><<<nb, kBlock, 0, s>>>(uu, pp, g.ns, ws);
+    else if (swap_sym && g.sigma == 4 && g.d == 2 && g.h >= 2)
+        cert_r<T, 4><<<nb, kBlock, 0, s>>>(uu, pp, g.ns, ws);
     else
         cert_r<T, 0><<<nb, kBlock, 0, s>>>(uu, pp, g.ns, ws);
     hipError_t e = hipGetLastError();

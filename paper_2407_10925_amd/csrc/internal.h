@@ -63,9 +63,9 @@ hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const voi
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
 hipError_t launch_fill_f64(double *p, uint64_t count, double v, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, uint64_t bytes, hipStream_t s);
-// sigma = 2, d = 2 or 3, l >= 2: set *flag (device) to 1 unless every stored
-// entry equals, bit for bit, the stored entry of its tuple with strings 1 and
-// 2 exchanged
+// sigma = 2 with d = 2 or 3, or sigma = 4 with d = 2, l >= 2: set *flag
+// (device) to 1 unless every stored entry equals, bit for bit, the stored
+// entry of its tuple with strings 1 and 2 exchanged
 hipError_t launch_check_swap(const Geometry &g, int dtype, const void *table, uint32_t *flag,
                              hipStream_t s);
 // a lazily written table (see TwinGroup): set every upper entry to its lower twin
@@ -165,6 +165,52 @@ __device__ __forceinline__ void twin_values8(const T *qm, int mode, T *g)
     g[5] = (mode == 1 || mode == 3) ? q[3] : (mode == 2 || mode == 4) ? q[4] : q[5];
     g[6] = mode == 2 ? q[1] : mode == 4 ? q[1] : q[6];
     g[7] = (mode == 2 || mode == 4) ? q[0] : q[7];
+}
+
+// sigma = 4, d = 2 with the two strings exchanged: exchange4 swaps the a and
+// b symbols (2-bit fields) of every 4-bit slot, and J relabels the result by
+// its string-1 head so that it is a stored index.  An aligned group of
+// sixteen (the last slot, member v = 4 c1 + c2) is its own (kind 0), lies at
+// its twin group with member v at perm16(v, m) (kind 1, m the relabelling),
+// or is its own twin (kind 2: member v read at min(v, perm16(v, m))).
+__host__ __device__ inline uint64_t exchange4(uint64_t x, uint64_t n)
+{
+    const uint64_t a = 0xCCCCCCCCCCCCCCCCull & (n - 1), b = 0x3333333333333333ull & (n - 1);
+    return ((x & a) >> 2) | ((x & b) << 2);
+}
+
+__host__ __device__ inline uint64_t exchange_twin4(uint64_t j, uint64_t n)
+{
+    const uint64_t x = exchange4(j, n);
+    const uint64_t m = (x >> (__builtin_ctzll(n) - 2)) & 3;  // string-1 head of x
+    return x ^ (m * ((n - 1) / 3));
+}
+
+struct Twin16 {
+    uint64_t read;  // base of the twin group (kind 1), else the group's own
+    int m;          // relabelling of the twin
+    int kind;       // 0 own, 1 twin, 2 self
+};
+
+__host__ __device__ inline Twin16 twin_group16(uint64_t base, uint64_t n)
+{
+    const uint64_t x = exchange4(base, n);
+    const int m = (int)((x >> (__builtin_ctzll(n) - 2)) & 3);
+    const uint64_t jb = (x ^ ((uint64_t)m * ((n - 1) / 3))) & ~(uint64_t)15;
+    if (jb > base) return {base, m, 0};
+    if (jb < base) return {jb, m, 1};
+    return {base, m, 2};
+}
+
+__host__ __device__ inline int perm16(int v, int m) { return 4 * ((v & 3) ^ m) + ((v >> 2) ^ m); }
+
+// stored position holding member v of the group at `base` (tw = its twin)
+__host__ __device__ inline uint64_t member16(uint64_t base, const Twin16 &tw, int v)
+{
+    if (tw.kind == 0) return base + (uint64_t)v;
+    const int pv = perm16(v, tw.m);
+    if (tw.kind == 1) return tw.read + (uint64_t)pv;
+    return base + (uint64_t)(pv < v ? pv : v);
 }
 
 // Learned warm start (csrc/mlp.hip)

@@ -276,7 +276,16 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
 //   - advance a of (0, b1)|x_m reads string-1 head m; its image is the
 //     advance-a group of (0, b1 xor m)|x, so four means ma[v] serve all
 //     twelve mismatched tuples.
-template <typename T>
+//
+// SWAP (a ring symmetric in the two strings, bit for bit): exchanging the
+// strings and relabelling by the new string-1 head maps (0, b1)|x_m to
+// (0, b1)|p_(m xor b1 xor s), p = exchange4(t) relabelled by s, the string-2
+// symbol of t at position 2.  Threads t and p compute the same sixteen
+// values, so only the lower runs; it stores each value at the lower index of
+// its exchanged pair and reads every group through its lower members
+// (Twin16): the all-advance tree is invariant under the twin's member
+// permutation, so an own or twin group is summed as loaded.
+template <typename T, bool SWAP>
 __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
                                                     const T *__restrict__ lag2,
                                                     T *__restrict__ out, uint64_t n, int h,
@@ -291,15 +300,40 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
         const double o1 = off[s1];
         d2 = (float)(off[s2] - o1);
         T g0[16];
-        for (int k = 0; k < 16; k += 4) load4(lag2 + k, g0 + k);
+        if constexpr (SWAP) {
+            const Twin16 tw = twin_group16(0, n);  // its own twin: read the lower members
+#pragma unroll
+            for (int v = 0; v < 16; ++v) g0[v] = lag2[member16(0, tw, v)];
+        } else {
+            for (int k = 0; k < 16; k += 4) load4(lag2 + k, g0 + k);
+        }
         y0 = 1.0f + first(tree16(g0) * 0.0625f + d2);
         if (t == 0) off[snew] = o1 + (double)y0;
     }
     if (t >= (n >> 6)) return;
+    const uint64_t rep = ((n >> 4) - 1) / 3;  // symbol 1 at every position of x
+    uint64_t p = t;
+    int sx = 0;
+    if constexpr (SWAP) {
+        sx = (int)((t >> (top - 4)) & 3);
+        p = exchange4(t, n >> 4) ^ ((uint64_t)sx * rep);
+        if (p < t) return;
+    }
 
     T g[16];
+    if constexpr (SWAP) {
+        const Twin16 tw = twin_group16(16 * t, n);
+        if (tw.kind == 2) {
 #pragma unroll
-    for (int k = 0; k < 16; k += 4) load4(lag2 + 16 * t + k, g + k);
+            for (int v = 0; v < 16; ++v) g[v] = lag2[member16(16 * t, tw, v)];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; k += 4) load4(lag2 + tw.read + k, g + k);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k += 4) load4(lag2 + 16 * t + k, g + k);
+    }
     T both = tree16(g) * (T)0.0625;
     if constexpr (kF32) both = both + d2;
     const T match = (T)1 + first(both);
@@ -310,23 +344,44 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
     for (int v = 0; v < 4; ++v) {
         const uint64_t i = ((uint64_t)v << top) | t;
         const uint64_t sa = ((i << 4) & am) | (i & bm);
-        ma[v] = tree4(lag1[sa], lag1[sa + 4], lag1[sa + 8], lag1[sa + 12]) * (T)0.25;
+        if constexpr (SWAP) {
+            const uint64_t gb = sa & ~(uint64_t)15;
+            const int o = (int)(sa & 15);
+            const Twin16 tw = twin_group16(gb, n);
+            ma[v] = tree4(lag1[member16(gb, tw, o)], lag1[member16(gb, tw, o + 4)],
+                          lag1[member16(gb, tw, o + 8)], lag1[member16(gb, tw, o + 12)]) *
+                    (T)0.25;
+        } else {
+            ma[v] = tree4(lag1[sa], lag1[sa + 4], lag1[sa + 8], lag1[sa + 12]) * (T)0.25;
+        }
     }
-    const uint64_t rep = ((n >> 4) - 1) / 3;  // symbol 1 at every position of x
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const uint64_t x = t ^ ((uint64_t)m * rep);
         const uint64_t sb = (x & am) | ((x << 4) & bm);
         T bv[4];
-        load4(lag1 + sb, bv);
+        if constexpr (SWAP) {
+            const uint64_t gb = sb & ~(uint64_t)15;
+            const int o = (int)(sb & 15);
+            const Twin16 tw = twin_group16(gb, n);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bv[k] = lag1[member16(gb, tw, o + k)];
+        } else {
+            load4(lag1 + sb, bv);
+        }
         const T mb = tree4(bv[0], bv[1], bv[2], bv[3]) * (T)0.25;
-        put(out + x, kF32 ? (T)(match - y0) : match);
+        // the lower index of each output's exchanged pair (b1 << top) | p_(m ^ b1 ^ s)
+        auto at = [&](int b1) {
+            const uint64_t xt = p ^ ((uint64_t)(m ^ b1 ^ sx) * rep);
+            return ((uint64_t)b1 << top) | (SWAP && xt < x ? xt : x);
+        };
+        put(out + at(0), kF32 ? (T)(match - y0) : match);
 #pragma unroll
         for (int b1 = 1; b1 < 4; ++b1) {
             T best = first(mb);                              // z = 0
 #pragma unroll
             for (int z = 1; z < 4; ++z) best = vmax(best, z == b1 ? ma[b1 ^ m] : both);
-            put(out + (((uint64_t)b1 << top) | x), kF32 ? (T)(best - y0) : best);
+            put(out + at(b1), kF32 ? (T)(best - y0) : best);
         }
     }
 }
@@ -643,8 +698,12 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
             sweep_s2d2<T, false><<<grid, block, 0, s>>>(l1, l2, out, g.n, a.offsets,
                                                         a.lag_slot[0], a.lag_slot[1], a.new_slot);
     } else if (g.sigma == 4 && g.d == 2) {
-        sweep_s4d2<T><<<grid, block, 0, s>>>(l1, l2, out, g.n, g.h, a.offsets, a.lag_slot[0],
-                                              a.lag_slot[1], a.new_slot);
+        if (a.swap_sym)
+            sweep_s4d2<T, true><<<grid, block, 0, s>>>(l1, l2, out, g.n, g.h, a.offsets,
+                                                       a.lag_slot[0], a.lag_slot[1], a.new_slot);
+        else
+            sweep_s4d2<T, false><<<grid, block, 0, s>>>(l1, l2, out, g.n, g.h, a.offsets,
+                                                        a.lag_slot[0], a.lag_slot[1], a.new_slot);
     } else if (g.sigma == 2 && g.d == 3) {
         if (a.swap_sym)
             sweep_s2d3<T, true><<<grid, block, 0, s>>>(l1, l2, l3, out, g.n, g.h, a.offsets,

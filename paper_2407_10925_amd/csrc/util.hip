@@ -68,18 +68,26 @@ __global__ __launch_bounds__(kBlock) void upcast_range(const float *src, const d
     }
 }
 
-// sigma = 2, d = 2 or 3: raise *flag if a stored entry differs, bit for bit,
-// from the stored entry of its tuple with strings 1 and 2 exchanged
-// (exchange_twin)
+// the stored index of the exchanged twin of stored index i: D = 2 or 3 for
+// sigma = 2 (d = D), 4 for sigma = 4, d = 2
+template <int D>
+__device__ __forceinline__ uint64_t twin_of(uint64_t i, uint64_t n)
+{
+    if constexpr (D == 4) return exchange_twin4(i, n);
+    else return exchange_twin(i, n, D);
+}
+
+// raise *flag if a stored entry differs, bit for bit, from the stored entry
+// of its tuple with strings 1 and 2 exchanged
 template <typename W, int D>
 __global__ __launch_bounds__(kBlock) void check_swap_kernel(const W *__restrict__ v, uint64_t n,
                                                             uint32_t *__restrict__ flag)
 {
-    const uint64_t ns = n >> 1;
+    const uint64_t ns = D == 4 ? n >> 2 : n >> 1;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     bool bad = false;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < ns; i += stride)
-        bad = bad || v[i] != v[exchange_twin(i, n, D)];
+        bad = bad || v[i] != v[twin_of<D>(i, n)];
     if (bad) *flag = 1u;
 }
 
@@ -89,13 +97,22 @@ __global__ __launch_bounds__(kBlock) void check_swap_kernel(const W *__restrict_
 template <typename W, int D>
 __global__ __launch_bounds__(kBlock) void materialize_swap_kernel(W *__restrict__ v, uint64_t n)
 {
-    const uint64_t ns = n >> 1;
+    const uint64_t ns = D == 4 ? n >> 2 : n >> 1;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < ns; i += stride) {
-        const uint64_t js = exchange_twin(i, n, D);
+        const uint64_t js = twin_of<D>(i, n);
         if (js < i) v[i] = v[js];
     }
 }
+
+// the D of twin_of for a shape, or 0 when no exchange fold applies
+int swap_kind(const Geometry &g)
+{
+    if (g.h < 2 || (g.d != 2 && g.d != 3)) return 0;
+    if (g.sigma == 2) return g.d;
+    return g.sigma == 4 && g.d == 2 ? 4 : 0;
+}
+
 
 unsigned grid_for(uint64_t work)
 {
@@ -110,39 +127,53 @@ unsigned grid_for(uint64_t work)
 hipError_t launch_check_swap(const Geometry &g, int dtype, const void *table, uint32_t *flag,
                              hipStream_t s)
 {
-    if (g.sigma != 2 || (g.d != 2 && g.d != 3) || g.h < 2) return hipErrorInvalidValue;
+    const int kind = swap_kind(g);
     const unsigned grid = grid_for(g.ns);
-    if (dtype == LCSB_F32 && g.d == 2)
-        check_swap_kernel<uint32_t, 2><<<grid, kBlock, 0, s>>>(
-            static_cast<const uint32_t *>(table), g.n, flag);
-    else if (dtype == LCSB_F32)
-        check_swap_kernel<uint32_t, 3><<<grid, kBlock, 0, s>>>(
-            static_cast<const uint32_t *>(table), g.n, flag);
-    else if (g.d == 2)
-        check_swap_kernel<uint64_t, 2><<<grid, kBlock, 0, s>>>(
-            static_cast<const uint64_t *>(table), g.n, flag);
-    else
-        check_swap_kernel<uint64_t, 3><<<grid, kBlock, 0, s>>>(
-            static_cast<const uint64_t *>(table), g.n, flag);
+    const uint32_t *t32 = static_cast<const uint32_t *>(table);
+    const uint64_t *t64 = static_cast<const uint64_t *>(table);
+    const bool f32 = dtype == LCSB_F32;
+    switch (kind) {
+    case 2:
+        if (f32) check_swap_kernel<uint32_t, 2><<<grid, kBlock, 0, s>>>(t32, g.n, flag);
+        else check_swap_kernel<uint64_t, 2><<<grid, kBlock, 0, s>>>(t64, g.n, flag);
+        break;
+    case 3:
+        if (f32) check_swap_kernel<uint32_t, 3><<<grid, kBlock, 0, s>>>(t32, g.n, flag);
+        else check_swap_kernel<uint64_t, 3><<<grid, kBlock, 0, s>>>(t64, g.n, flag);
+        break;
+    case 4:
+        if (f32) check_swap_kernel<uint32_t, 4><<<grid, kBlock, 0, s>>>(t32, g.n, flag);
+        else check_swap_kernel<uint64_t, 4><<<grid, kBlock, 0, s>>>(t64, g.n, flag);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_materialize_swap(const Geometry &g, int dtype, void *table, hipStream_t s)
 {
-    if (g.sigma != 2 || (g.d != 2 && g.d != 3) || g.h < 2) return hipErrorInvalidValue;
+    const int kind = swap_kind(g);
     const unsigned grid = grid_for(g.ns);
-    if (dtype == LCSB_F32 && g.d == 2)
-        materialize_swap_kernel<uint32_t, 2><<<grid, kBlock, 0, s>>>(
-            static_cast<uint32_t *>(table), g.n);
-    else if (dtype == LCSB_F32)
-        materialize_swap_kernel<uint32_t, 3><<<grid, kBlock, 0, s>>>(
-            static_cast<uint32_t *>(table), g.n);
-    else if (g.d == 2)
-        materialize_swap_kernel<uint64_t, 2><<<grid, kBlock, 0, s>>>(
-            static_cast<uint64_t *>(table), g.n);
-    else
-        materialize_swap_kernel<uint64_t, 3><<<grid, kBlock, 0, s>>>(
-            static_cast<uint64_t *>(table), g.n);
+    uint32_t *t32 = static_cast<uint32_t *>(table);
+    uint64_t *t64 = static_cast<uint64_t *>(table);
+    const bool f32 = dtype == LCSB_F32;
+    switch (kind) {
+    case 2:
+        if (f32) materialize_swap_kernel<uint32_t, 2><<<grid, kBlock, 0, s>>>(t32, g.n);
+        else materialize_swap_kernel<uint64_t, 2><<<grid, kBlock, 0, s>>>(t64, g.n);
+        break;
+    case 3:
+        if (f32) materialize_swap_kernel<uint32_t, 3><<<grid, kBlock, 0, s>>>(t32, g.n);
+        else materialize_swap_kernel<uint64_t, 3><<<grid, kBlock, 0, s>>>(t64, g.n);
+        break;
+    case 4:
+        if (f32) materialize_swap_kernel<uint32_t, 4><<<grid, kBlock, 0, s>>>(t32, g.n);
+        else materialize_swap_kernel<uint64_t, 4><<<grid, kBlock, 0, s>>>(t64, g.n);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -3,8 +3,8 @@
 Holds no arithmetic of the method: only a counter-based random generator
 (SplitMix64; Steele, Lea, Flood, "Fast splittable pseudorandom number
 generators", OOPSLA 2014), the relabelling of symbols used to make a table
-invariant under c -> c xor m, and the exchange of strings 1 and 2 (sigma =
-2, d = 2 or 3) used to make it invariant under that too.  Everything is torch integer arithmetic, so the
+invariant under c -> c xor m, and the exchange of strings 1 and 2 used to
+make it invariant under that too.  Everything is torch integer arithmetic, so the
 same call gives identical bits on the CPU and on a GPU.
 """
 from __future__ import annotations
@@ -54,20 +54,23 @@ def representative(idx: torch.Tensor, sigma: int, d: int, h: int) -> torch.Tenso
 
 
 def exchanged(idx: torch.Tensor, sigma: int, d: int, h: int) -> torch.Tensor:
-    """sigma = 2, d = 2 or 3: index of the tuple with strings 1 and 2
-    exchanged (their bits swapped at every position)."""
-    assert sigma == 2 and d in (2, 3)
-    r = ((1 << (d * h)) - 1) // ((1 << d) - 1)  # the lowest bit of every position
-    a, b = _s64(r << (d - 1)), _s64(r << (d - 2))  # string 1, string 2
-    rest = _s64(((1 << (d * h)) - 1) & ~((r << (d - 1)) | (r << (d - 2))))
-    return _lsr(idx & a, 1) | ((idx & b) << 1) | (idx & rest)
+    """Index of the tuple with strings 1 and 2 exchanged (their symbol fields
+    swapped at every position); sigma = 2 or 4."""
+    beta = {2: 1, 4: 2}[sigma]
+    slot = beta * d
+    r = ((1 << (slot * h)) - 1) // ((1 << slot) - 1)   # the lowest bit of every position
+    f = (1 << beta) - 1
+    a = _s64(r * (f << (slot - beta)))                  # string 1's field
+    b = _s64(r * (f << (slot - 2 * beta)))              # string 2's field
+    rest = _s64(((1 << (slot * h)) - 1) & ~(r * (f << (slot - beta)) | r * (f << (slot - 2 * beta))))
+    return _lsr(idx & a, beta) | ((idx & b) << beta) | (idx & rest)
 
 
 def table(sigma: int, d: int, h: int, seed: int, dtype=torch.float64, device="cpu",
           symmetric: bool = True, scale: float = 8.0, chunk: int = 1 << 26,
           exchange: bool = False) -> torch.Tensor:
     """A seeded table of sigma^(d h) values; symmetric under c -> c xor m if
-    asked, and (sigma = 2, d = 2 or 3) also under exchanging strings 1 and 2 if
+    asked, and also under exchanging strings 1 and 2 if
     `exchange`: each value is then drawn at the lower of the two
     representatives."""
     n = sigma ** (d * h)

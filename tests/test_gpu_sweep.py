@@ -73,8 +73,8 @@ def test_fp64_zero_start_trajectory_is_bit_exact(pk, sigma, d, h, sweeps, printe
     say(f"zero-start FP64 sigma={sigma} d={d} h={h} sweeps={sweeps}")
     L = pk.Lcsb(sigma, d, h, "f64")
     L.init_zero()
-    # the zero ring is symmetric in strings 1 and 2: sigma = 2 runs folded
-    assert L.swap_symmetric() == (sigma == 2 and h >= 2)
+    # the zero ring is symmetric in strings 1 and 2: every shape runs folded at l >= 2
+    assert L.swap_symmetric() == (h >= 2)
     N = sigma ** (d * h)
     ring = [np.zeros(N) for _ in range(d)]
     best_ref = {"rho": 0.0, "bound": 0.0, "sweep": 0}  # the initial triplet (v_0, 0, 0)
@@ -121,7 +121,7 @@ def test_fp64_random_ring_one_sweep_and_certificate(pk, sigma, d, h):
 
 
 @pytest.mark.parametrize("sigma,d,h,exchange", [(2, 2, 5, False), (2, 2, 5, True), (4, 2, 2, False),
-                                                (2, 3, 3, False), (2, 3, 3, True)],
+                                                (4, 2, 2, True), (2, 3, 3, False), (2, 3, 3, True)],
                          ids=lambda v: str(v))
 @pytest.mark.parametrize("scale", [1e-300, 2.0 ** -1021], ids=["tiny", "subnormal"])
 def test_fp64_tiny_and_subnormal_tables(pk, sigma, d, h, exchange, scale):
@@ -170,52 +170,55 @@ def test_load_ring_projects_onto_symmetric_tables(pk):
 
 
 # ------------------------------------------------------------------ exchange-symmetric rings
-@pytest.mark.parametrize("d,h", [(2, 2), (2, 3), (2, 5), (2, 8), (2, 10), (3, 2), (3, 3), (3, 5),
-                                 (3, 6)], ids=lambda v: str(v))
-def test_fp64_exchange_symmetric_ring_takes_the_folded_path(pk, d, h):
+@pytest.mark.parametrize("sigma,d,h", [(2, 2, 2), (2, 2, 3), (2, 2, 5), (2, 2, 8), (2, 2, 10),
+                                       (2, 3, 2), (2, 3, 3), (2, 3, 5), (2, 3, 6), (4, 2, 2),
+                                       (4, 2, 3), (4, 2, 4)], ids=lambda v: str(v))
+def test_fp64_exchange_symmetric_ring_takes_the_folded_path(pk, sigma, d, h):
     """A ring symmetric in strings 1 and 2 is recognised when loaded; sweeps
     and certificates then compute one tuple of each exchanged pair.  Sweeps
     and certificates must still match the oracle bit for bit (random values,
     so every association and every max matters), and the ring must stay
     symmetric."""
-    say(f"exchange-symmetric FP64 ring d={d} h={h}")
-    lags = [si.table(2, d, h, seed=110 + k, exchange=True) for k in range(d)]
-    L = pk.Lcsb(2, d, h, "f64")
+    say(f"exchange-symmetric FP64 ring sigma={sigma} d={d} h={h}")
+    lags = [si.table(sigma, d, h, seed=110 + k, exchange=True) for k in range(d)]
+    L = pk.Lcsb(sigma, d, h, "f64")
     L.load_ring([x.cuda() for x in lags])
     assert L.swap_symmetric()
     cur, _ = L.certify()
-    _same_cert(cur, oracle.certify(2, d, h, lags[0].numpy(), lags[1].numpy()))
+    _same_cert(cur, oracle.certify(sigma, d, h, lags[0].numpy(), lags[1].numpy()))
     ring = [x.numpy() for x in lags]
     for t in range(3):
         L.iterate(1)
-        new = oracle.sweep(2, d, h, ring)
+        new = oracle.sweep(sigma, d, h, ring)
         got, _ = L.lag(1)
         assert np.array_equal(_full(L, got), new), f"sweep {t}"
         ring = [new] + ring[:-1]
         cur, _ = L.certify()
-        _same_cert(cur, oracle.certify(2, d, h, ring[0], ring[1]))
+        _same_cert(cur, oracle.certify(sigma, d, h, ring[0], ring[1]))
     assert L.swap_symmetric()
 
 
-@pytest.mark.parametrize("d,h,dt", [(2, 2, "f64"), (2, 3, "f64"), (2, 5, "f64"), (2, 8, "f64"),
-                                    (2, 5, "f32"), (3, 2, "f64"), (3, 3, "f64"), (3, 5, "f64"),
-                                    (3, 4, "f32")], ids=lambda v: str(v))
-def test_exchange_folded_passes_read_only_lower_entries(pk, d, h, dt):
+@pytest.mark.parametrize("sigma,d,h,dt", [(2, 2, 2, "f64"), (2, 2, 3, "f64"), (2, 2, 5, "f64"),
+                                          (2, 2, 8, "f64"), (2, 2, 5, "f32"), (2, 3, 2, "f64"),
+                                          (2, 3, 3, "f64"), (2, 3, 5, "f64"), (2, 3, 4, "f32"),
+                                          (4, 2, 2, "f64"), (4, 2, 3, "f64"), (4, 2, 3, "f32")],
+                         ids=lambda v: str(v))
+def test_exchange_folded_passes_read_only_lower_entries(pk, sigma, d, h, dt):
     """On an exchange-symmetric ring a sweep writes only the lower stored index
     of each exchanged pair, and sweeps and certificates read only those.  With
     every upper entry of both lags set to NaN, the certificate and the next
     sweep must still match the oracle (FP64: bit for bit; FP32: the
     certificate bit for bit, the sweep within the FP32 bound), and the table
     lcsb_lag returns must be complete."""
-    say(f"lower-entry reads d={d} h={h} {dt}")
+    say(f"lower-entry reads sigma={sigma} d={d} h={h} {dt}")
     tdt = torch.float64 if dt == "f64" else torch.float32
-    lags = [si.table(2, d, h, seed=150 + k, dtype=tdt, exchange=True) for k in range(d)]
-    L = pk.Lcsb(2, d, h, dt)
+    lags = [si.table(sigma, d, h, seed=150 + k, dtype=tdt, exchange=True) for k in range(d)]
+    L = pk.Lcsb(sigma, d, h, dt)
     L.load_ring([x.cuda() for x in lags])
     assert L.swap_symmetric()
     ns = L.stored
     idx = torch.arange(ns)
-    twin = si.representative(si.exchanged(idx, 2, d, h), 2, d, h)
+    twin = si.representative(si.exchanged(idx, sigma, d, h), sigma, d, h)
     upper = (twin < idx).cuda()
     assert bool(upper.any())
     ring = [x.numpy().astype(np.float64) for x in lags]
@@ -226,11 +229,11 @@ def test_exchange_folded_passes_read_only_lower_entries(pk, d, h, dt):
             buf[upper] = float("nan")
         cur, _ = L.certify()
         if dt == "f64" or t == 0:  # FP32: bit-exact while every offset is 0
-            _same_cert(cur, oracle.certify(2, d, h, ring[0], ring[1]))
+            _same_cert(cur, oracle.certify(sigma, d, h, ring[0], ring[1]))
         else:
             assert cur["nonfinite"] == 0
         L.iterate(1)
-        new = oracle.sweep(2, d, h, ring)
+        new = oracle.sweep(sigma, d, h, ring)
         got, o_new = L.lag(1)
         full = _full(L, got).astype(np.float64)
         assert not np.isnan(full).any()
@@ -242,33 +245,34 @@ def test_exchange_folded_passes_read_only_lower_entries(pk, d, h, dt):
             ring = [o_new + full] + ring[:-1]  # the true values of the stored FP32 table
 
 
-@pytest.mark.parametrize("d,h", [(2, 2), (2, 4), (2, 9), (3, 3), (3, 5)], ids=lambda v: str(v))
-def test_fp32_exchange_symmetric_ring(pk, d, h):
-    say(f"exchange-symmetric FP32 ring d={d} h={h}")
-    lags = [si.table(2, d, h, seed=120 + k, dtype=torch.float32, exchange=True) for k in range(d)]
+@pytest.mark.parametrize("sigma,d,h", [(2, 2, 2), (2, 2, 4), (2, 2, 9), (2, 3, 3), (2, 3, 5),
+                                       (4, 2, 2), (4, 2, 3)], ids=lambda v: str(v))
+def test_fp32_exchange_symmetric_ring(pk, sigma, d, h):
+    say(f"exchange-symmetric FP32 ring sigma={sigma} d={d} h={h}")
+    lags = [si.table(sigma, d, h, seed=120 + k, dtype=torch.float32, exchange=True) for k in range(d)]
     offs = [0.75 * k for k in range(d)]
-    L = pk.Lcsb(2, d, h, "f32")
+    L = pk.Lcsb(sigma, d, h, "f32")
     L.load_ring([x.cuda() for x in lags], offsets=offs)
     assert L.swap_symmetric()
     L.iterate(1)
     got, o_new = L.lag(1)
     full = _full(L, got)
-    ex = si.exchanged(torch.arange(L.n), 2, d, h).numpy()
+    ex = si.exchanged(torch.arange(L.n), sigma, d, h).numpy()
     assert np.array_equal(full, full[ex])
     val = o_new + full.astype(np.float64)
-    ref = oracle.sweep(2, d, h, [x.numpy().astype(np.float64) + o for x, o in zip(lags, offs)])
+    ref = oracle.sweep(sigma, d, h, [x.numpy().astype(np.float64) + o for x, o in zip(lags, offs)])
     assert np.max(np.abs(val - ref)) <= _fp32_bound(8.0 + 0.75 * d)
-    L2 = pk.Lcsb(2, d, h, "f32")
+    L2 = pk.Lcsb(sigma, d, h, "f32")
     L2.load_ring([x.cuda() for x in lags])
     assert L2.swap_symmetric()
     cur, _ = L2.certify()
-    _same_cert(cur, oracle.certify(2, d, h, lags[0].numpy().astype(np.float64),
+    _same_cert(cur, oracle.certify(sigma, d, h, lags[0].numpy().astype(np.float64),
                                    lags[1].numpy().astype(np.float64)))
 
 
 @pytest.mark.parametrize("sigma,d,h,exchange", [(2, 2, 4, False), (2, 2, 4, True), (2, 2, 1, False),
-                                                (4, 2, 2, False), (2, 3, 3, False), (2, 3, 3, True)],
-                         ids=lambda v: str(v))
+                                                (4, 2, 2, False), (4, 2, 2, True), (2, 3, 3, False),
+                                                (2, 3, 3, True)], ids=lambda v: str(v))
 def test_nonfinite_tables_follow_the_oracle(pk, sigma, d, h, exchange):
     """Tables holding NaN, +inf and -inf: F's max starts from -inf, so a NaN
     branch never wins and a tuple whose branches are all NaN gets -inf.  The
@@ -279,7 +283,7 @@ def test_nonfinite_tables_follow_the_oracle(pk, sigma, d, h, exchange):
     lags = [si.table(sigma, d, h, seed=140 + k, exchange=exchange) for k in range(d)]
     rep = si.representative(torch.arange(n), sigma, d, h)
     if exchange:
-        rep = torch.minimum(rep, si.representative(si.exchanged(rep, 2, d, h), 2, d, h))
+        rep = torch.minimum(rep, si.representative(si.exchanged(rep, sigma, d, h), sigma, d, h))
     for k, (where, bad) in enumerate([((3, 11), float("nan")), ((5,), float("inf")),
                                       ((7,), -float("inf"))]):
         for j in where:
@@ -642,7 +646,7 @@ def test_checkpoint_resume_is_bit_identical(pk, tmp_path, sigma, d, h, dt):
     B = pk.Lcsb(sigma, d, h, dt)
     B.load(path)
     assert B.status()[0] == 25
-    assert B.swap_symmetric() == A.swap_symmetric() == (sigma == 2)
+    assert B.swap_symmetric() and A.swap_symmetric()
     B.iterate(11)
     cur_b, best_b = B.certify()
     assert cur_a == cur_b and best_a == best_b

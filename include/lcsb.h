@@ -199,7 +199,7 @@ typedef struct {
 int lcsb_run(lcsb_ctx *ctx, const lcsb_run_policy *p, lcsb_cert *cur, lcsb_cert *best,
              int64_t *certificates, int *stop);
 
-/* Copy the ring of an LCSB_F32 context into an LCSB_F64 context of the same/* Copy the ring of an LCSB_F32 context into an LCSB_F64 context of the same
+/* Copy the ring of an LCSB_F32 context into an LCSB_F64 context of the same
  * (sigma, d, h) as FP64 values offset + stored value (the switch from FP32
  * sweeps to an FP64 polish).  The sweep count and best certificate move with
  * it.  Enqueued on dst's stream after synchronising src's.  The two rings are
@@ -231,7 +231,6 @@ int lcsb_save(const lcsb_ctx *ctx, const char *path);
 int lcsb_load(lcsb_ctx *ctx, const char *path);
 
 /* ------------------------------------------------------------------------
- * Learned warm start/* ------------------------------------------------------------------------
  * Learned warm start for sigma = d = 2 (not part of the paper's method: the
  * limit of Algorithm 2's iteration does not depend on the starting ring, so
  * a better start only shortens the run; the certificate decides the result).

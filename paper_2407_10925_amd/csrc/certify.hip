@@ -67,26 +67,85 @@ __device__ void block_reduce(double &v, uint64_t &i, uint64_t &c)
 // 4, d = 2; both tables symmetric in strings 1 and 2): u - prev is equal at a
 // stored entry and at its exchanged twin (exchange_twin, exchange_twin4), so
 // only the lower of the two is read, counted twice unless it is its own twin.
+// A thread takes aligned groups of G entries (the groups of twin_group,
+// twin_group8, twin_group16): a group is entirely lower (read as a vector,
+// every member counted twice), entirely upper (not read) or its own twin
+// (member by member).  Within a thread indices rise and every merge keeps the
+// lowest index of the maximum, so the reported index is the lowest one.
+// 16 bytes: four floats or two doubles
+template <typename T>
+__device__ __forceinline__ void ld16(const T *p, T *v)
+{
+    if constexpr (std::is_same<T, float>::value) {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+        const double2 q = *reinterpret_cast<const double2 *>(p);
+        v[0] = q.x; v[1] = q.y;
+    }
+}
+
 template <typename T, int SWAP_D>
 __global__ __launch_bounds__(kBlock) void cert_r(const T *__restrict__ u,
                                                 const T *__restrict__ prev, uint64_t n,
                                                 unsigned char *__restrict__ ws)
 {
+    constexpr int G = SWAP_D == 3 ? 8 : SWAP_D == 4 ? 16 : 4;
+    constexpr int V = 16 / sizeof(T);  // elements per 16-byte load
     double best = -INFINITY;
     uint64_t arg = 0, nonfinite = 0;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += stride) {
-        uint64_t mult = 1;
-        if constexpr (SWAP_D != 0) {
-            const uint64_t js =
-                SWAP_D == 4 ? exchange_twin4(j, 4 * n) : exchange_twin(j, 2 * n, SWAP_D);
-            if (js < j) continue;
-            mult = js == j ? 1 : 2;
-        }
-        const double a = (double)u[j], b = (double)prev[j];
+    auto twin_of = [&](uint64_t j) {
+        return SWAP_D == 4 ? exchange_twin4(j, 4 * n) : exchange_twin(j, 2 * n, SWAP_D);
+    };
+    auto take = [&](uint64_t j, double a, double b, uint64_t mult) {
         if (!isfinite(a) || !isfinite(b)) nonfinite += mult;
         const double diff = a - b;
         if (diff > best) { best = diff; arg = j; }
+    };
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock, ng = n / G;
+    const uint64_t t0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (uint64_t q = t0; q < ng; q += stride) {
+        const uint64_t base = q * G;
+        int kind = 0;  // 0 lower (or no symmetry), 1 upper, 2 its own twin
+        if constexpr (SWAP_D == 2) {
+            const int m = twin_group(base, 2 * n).mode;
+            kind = m == 0 ? 0 : m <= 2 ? 1 : 2;
+        } else if constexpr (SWAP_D == 3) {
+            const int m = twin_group8(base, 2 * n).mode;
+            kind = m == 0 ? 0 : m <= 2 ? 1 : 2;
+        } else if constexpr (SWAP_D == 4) {
+            kind = twin_group16(base, 4 * n).kind;
+        }
+        if (kind == 1) continue;
+        T a[G], b[G];
+#pragma unroll
+        for (int k = 0; k < G; k += V) {
+            ld16(u + base + k, a + k);
+            ld16(prev + base + k, b + k);
+        }
+#pragma unroll
+        for (int v = 0; v < G; ++v) {
+            const uint64_t j = base + v;
+            uint64_t mult = SWAP_D != 0 ? 2 : 1;
+            if (SWAP_D != 0 && kind == 2) {
+                const uint64_t js = twin_of(j);
+                if (js < j) continue;
+                mult = js == j ? 1 : 2;
+            }
+            take(j, (double)a[v], (double)b[v], mult);
+        }
+    }
+    // entries after the last whole group (tables of fewer than G entries)
+    const uint64_t j = ng * G + t0;
+    if (j < n) {
+        uint64_t mult = 1;
+        bool use = true;
+        if constexpr (SWAP_D != 0) {
+            const uint64_t js = twin_of(j);
+            use = js >= j;
+            mult = js == j ? 1 : 2;
+        }
+        if (use) take(j, (double)u[j], (double)prev[j], mult);
     }
     block_reduce(best, arg, nonfinite);
     if (threadIdx.x == 0) {

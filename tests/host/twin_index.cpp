@@ -1,0 +1,92 @@
+// Host-side check of the library's exchange-fold index arithmetic
+// (paper_2407_10925_amd/csrc/internal.h): every grouped fast path the
+// kernels take agrees, entry by entry, with the plain rule "a stored entry
+// stands for itself and its exchanged twin, and the lower index of the two
+// holds the value".  Exits non-zero on the first disagreement.
+#include "internal.h"
+
+#include <cstdio>
+
+using namespace lcsb;
+
+static long bad = 0;
+#define EXPECT(c, ...)                                  \
+    do {                                                \
+        if (!(c) && bad++ < 8) {                        \
+            printf("FAIL %s:%d: ", __FILE__, __LINE__); \
+            printf(__VA_ARGS__);                        \
+            printf("\n");                               \
+        }                                               \
+    } while (0)
+
+static uint64_t lower(uint64_t j, uint64_t tw) { return tw < j ? tw : j; }
+
+// d = 2 (sigma = 2) and d = 3: a TwinGroup's mode and member mapping
+template <int D>
+static void groups(int h)
+{
+    const int G = D == 2 ? 4 : 8;
+    const uint64_t n = 1ull << (D * h), ns = n / 2;
+    for (uint64_t base = 0; base < ns; base += G) {
+        const TwinGroup tg = D == 2 ? twin_group(base, n) : twin_group8(base, n);
+        for (int v = 0; v < G; ++v) {
+            const uint64_t j = base + v, js = exchange_twin(j, n, D);
+            EXPECT(js < ns, "d=%d h=%d j=%llu: twin not stored", D, h, (unsigned long long)j);
+            if (tg.mode == 0) EXPECT(js > j, "d=%d own group holds an upper entry", D);
+            if (tg.mode == 1 || tg.mode == 2) {
+                EXPECT(js < j, "d=%d twin group holds a lower entry", D);
+                EXPECT(js >= tg.read && js < tg.read + G, "d=%d twin outside the twin group", D);
+            }
+            if (tg.mode >= 3) EXPECT(js >= base && js < base + G, "d=%d self group leaves itself", D);
+        }
+        if (D == 3) {  // the member lookup the folded d = 3 kernels use
+            for (int v = 0; v < 8; ++v) {
+                const uint64_t j = base + v;
+                const int pe = (v & 1) | ((v & 2) << 1) | ((v & 4) >> 1);
+                const int at = tg.mode == 0 ? v
+                             : tg.mode == 1 ? pe
+                             : tg.mode == 2 ? 7 - pe
+                             : tg.mode == 3 ? (v < pe ? v : pe)
+                                            : (v < 7 - pe ? v : 7 - pe);
+                EXPECT(tg.read + at == lower(j, exchange_twin(j, n, 3)), "d=3 h=%d member %d", h, v);
+            }
+        }
+    }
+}
+
+// sigma = 4, d = 2: Twin16 and member16, the vector-load addresses of the
+// folded sweep, and the grouped R pass
+static void sigma4(int h)
+{
+    const uint64_t n = 1ull << (4 * h), ns = n / 4;
+    for (uint64_t base = 0; base < ns; base += 16) {
+        const Twin16 tw = twin_group16(base, n);
+        for (int v = 0; v < 16; ++v) {
+            const uint64_t j = base + v, js = exchange_twin4(j, n);
+            EXPECT(member16(base, tw, v) == lower(j, js), "sigma=4 h=%d member %d", h, v);
+            if (tw.kind == 0) EXPECT(js > j, "sigma=4 own group holds an upper entry");
+            if (tw.kind == 1) EXPECT(js < j, "sigma=4 twin group holds a lower entry");
+        }
+        for (int o = 0; o < 4; ++o) {
+            // advance a: members o + 4k of a twin group are one row of it
+            if (tw.kind == 1)
+                for (int k = 0; k < 4; ++k)
+                    EXPECT(member16(base, tw, o + 4 * k) ==
+                               tw.read + 4 * (uint64_t)(o ^ tw.m) + (uint64_t)(k ^ tw.m),
+                           "sigma=4 advance-a row");
+            // advance b: members 4o .. 4o + 3 of an own group are in place
+            if (tw.kind == 0)
+                for (int k = 0; k < 4; ++k)
+                    EXPECT(member16(base, tw, 4 * o + k) == base + 4 * (uint64_t)o + k, "sigma=4 advance-b run");
+        }
+    }
+}
+
+int main()
+{
+    for (int h = 2; h <= 10; ++h) groups<2>(h);
+    for (int h = 2; h <= 7; ++h) groups<3>(h);
+    for (int h = 2; h <= 5; ++h) sigma4(h);
+    printf("%s (%ld disagreements)\n", bad ? "FAIL" : "ok", bad);
+    return bad != 0;
+}

@@ -70,8 +70,8 @@ __device__ void block_reduce(double &v, uint64_t &i, uint64_t &c)
 // A thread takes aligned groups of G entries (the groups of twin_group,
 // twin_group8, twin_group16): a group is entirely lower (read as a vector,
 // every member counted twice), entirely upper (not read) or its own twin
-// (member by member).  Within a thread indices rise and every merge keeps the
-// lowest index of the maximum, so the reported index is the lowest one.
+// (member by member).  The maximum is exact in any order; only its value
+// leaves the pass (the index carried beside it is the lowest one).
 // 16 bytes: four floats or two doubles
 template <typename T>
 __device__ __forceinline__ void ld16(const T *p, T *v)

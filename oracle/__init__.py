@@ -46,6 +46,14 @@ class Cert(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class CertOpt(C.Structure):
+    _fields_ = [("r", C.c_double), ("bound", C.c_double), ("argmin", C.c_uint64),
+                ("nonfinite", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -74,6 +82,12 @@ def lib():
                                       P(C.c_uint64), C.c_uint64, P(C.c_double)]
         L.or_feasible_triplet.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int64,
                                           P(C.c_double), P(C.c_double), P(C.c_double)]
+        L.or_certify_optimal.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double), P(CertOpt)]
+        L.or_certify_optimal_f32.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_float), P(CertOpt)]
+        L.or_optimal_ratio_at.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double), P(C.c_uint64),
+                                          C.c_uint64, P(C.c_double)]
+        L.or_optimal_ratio_at_f32.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_float),
+                                              P(C.c_uint64), C.c_uint64, P(C.c_double)]
         L.or_brute_W.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P(C.c_int), P(C.c_uint64)]
         _lib = L
     return _lib
@@ -197,6 +211,36 @@ def certify_W_at(sigma, d, h, u, R, idx):
     _check(lib().or_certify_W_at(sigma, d, h, _dptr(u), float(R),
                                  idx.ctypes.data_as(C.POINTER(C.c_uint64)), idx.size,
                                  _dptr(out)), "certify_W_at")
+    return out
+
+
+def certify_optimal(sigma, d, h, u):
+    """Largest r with (u, r, 0) a feasible triplet: dict(r, bound, argmin,
+    nonfinite), r = min_A max_z c_z(A) / k_z rounded down, bound = d r.
+    float32 tables are read as exact doubles."""
+    c = CertOpt()
+    if _is_f32(u):
+        u = np.ascontiguousarray(u)
+        _check(lib().or_certify_optimal_f32(sigma, d, h, _fptr(u), C.byref(c)), "certify_optimal")
+    else:
+        u = _f64(u)
+        _check(lib().or_certify_optimal(sigma, d, h, _dptr(u), C.byref(c)), "certify_optimal")
+    return c.as_dict()
+
+
+def optimal_ratio_at(sigma, d, h, u, idx):
+    """max_z c_z(A) / k_z (rounded down) at the coordinates idx."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint64)
+    out = np.empty(idx.size, dtype=np.float64)
+    ip = idx.ctypes.data_as(C.POINTER(C.c_uint64))
+    if _is_f32(u):
+        u = np.ascontiguousarray(u)
+        _check(lib().or_optimal_ratio_at_f32(sigma, d, h, _fptr(u), ip, idx.size, _dptr(out)),
+               "optimal_ratio_at")
+    else:
+        u = _f64(u)
+        _check(lib().or_optimal_ratio_at(sigma, d, h, _dptr(u), ip, idx.size, _dptr(out)),
+               "optimal_ratio_at")
     return out
 
 

@@ -23,6 +23,10 @@
  *     ring of d+1 vectors, R = max_j (v_d - v_{d-1})[j], then
  *     W = v_d + dR - F(v_d + (d-1)R, ..., v_d), E = max(0, max W), keep
  *     (u, r, eps) when R - E >= r - eps, and the bound d (r - eps) of eq. (6);
+ *   - the optimal certificate of a single table u is the largest r for which
+ *     (u, r, 0) satisfies the feasibility inequality of the lemma of Sec. 2.1:
+ *     r* = min_A max_z (b(A) + mean_z(u) - u[A]) / |N_z|, bound d r*
+ *     (derived below, at or_certify_optimal);
  *   - W_n(a_1..a_d) of Sec. 2.1 is evaluated exactly by enumerating every
  *     random tail and running the textbook LCS dynamic programme.
  *
@@ -163,7 +167,7 @@ static double F_z(const or_shape *s, const or_args *a, const int *sym, int z,
             int c = (int)(rest % (uint64_t)s->sigma);
             rest /= (uint64_t)s->sigma;
             int j = N[i];
-            /* s_j <- T(s_j) c_i */
+            /* string j drops its head and ends with the appended symbol c */
             for (int p = 0; p + 1 < s->h; ++p) work[j * s->h + p] = sym[j * s->h + p + 1];
             work[j * s->h + s->h - 1] = c;
         }
@@ -442,6 +446,170 @@ int or_certify_W_at_f32(int sigma, int d, int h, const float *u, double R,
                         const uint64_t *idx, uint64_t count, double *out)
 {
     return certify_W_at(sigma, d, h, u, 1, R, idx, count, out);
+}
+
+/* ------------------------------------------------------------------ */
+/* exported: the largest r of a feasible triplet (u, r, 0)              */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The lemma of Sec. 2.1 accepts any triplet (u, r, eps) with 0 <= eps <= r and
+ * F(u + (d-1)r, ..., u + r, u) >= u + (d r - eps) 1; Algorithm 2 fixes r to
+ * the largest step of the last sweep and then finds eps.  For a fixed u the
+ * best certificate is instead the largest r with eps = 0.  Branch z of
+ * coordinate A moves k_z = |N_z| strings and so reads argument k_z, which is
+ * u + (d - k_z) r; every argument moves by the same r, so that branch
+ * contributes b(A) + mean_z(u) + (d - k_z) r to F (eq. (4)).  The inequality
+ * at A with eps = 0 therefore holds iff some branch has
+ *     c_z(A) = b(A) + mean_z(u) - u[A] >= k_z r,
+ * and the largest r for which it holds at every A is
+ *     r* = min_A max_z c_z(A) / k_z,
+ * with bound d r* by eq. (6) (a triplet needs r* >= 0).
+ *
+ * Rounding: every mean, the 1 + of an all-match tuple and the subtraction of
+ * u[A] are rounded toward -inf, so each computed c_z is at most its exact
+ * value; the division by k_z is a multiply by 1/k_z, exact for powers of two,
+ * otherwise by 1/k_z rounded down (c_z >= 0) or up (c_z < 0), the product
+ * rounded toward -inf.  Every q_z is then at most c_z / k_z, the computed r
+ * at most r*, and (u, r, 0) is a feasible triplet for the table given.
+ * Branches whose mean is NaN never win the max over z (which starts from
+ * -inf), as in F.
+ */
+
+/* a / b under rounding `mode` (see rnd_add) */
+static double rnd_div(double a, double b, int mode)
+{
+    volatile double x = a, y = b;
+    fesetround(mode);
+    volatile double r = x / y;
+    fesetround(FE_TONEAREST);
+    return r;
+}
+
+/* inv_lo[k] <= 1/k <= inv_hi[k] for k = 1..d (equal, and exact, for powers of two) */
+static void make_inverses(const or_shape *s, double *inv_lo, double *inv_hi)
+{
+    for (int k = 1; k <= s->d; ++k) {
+        inv_lo[k] = rnd_div(1.0, (double)k, FE_DOWNWARD);
+        inv_hi[k] = rnd_div(1.0, (double)k, FE_UPWARD);
+    }
+}
+
+/* max_z c_z(A) / k_z at one coordinate.  Every operation here runs in the
+ * rounding mode of the caller (FE_DOWNWARD); the call is never inlined, so no
+ * operation can move across the caller's mode switches. */
+static __attribute__((noinline)) double opt_ratio_core(const or_shape *s, const or_args *a,
+                                                        uint64_t idx, double uA,
+                                                        const double *inv_lo,
+                                                        const double *inv_hi, double *buf,
+                                                        int *sym, int *work)
+{
+    decode(s, idx, sym);
+    int all_match = 1;
+    for (int j = 1; j < s->d; ++j)
+        if (sym[j * s->h] != sym[0]) all_match = 0;
+    double best = -INFINITY;
+    for (int z = 0; z < s->sigma; ++z) {
+        int skip;
+        double m = F_z(s, a, sym, z, buf, work, &skip);
+        if (skip) continue;
+        int k = 0;
+        for (int j = 0; j < s->d; ++j)
+            if (sym[j * s->h] != z) ++k;
+        double c = (all_match ? 1.0 + m : m) - uA;
+        double q = c >= 0.0 ? c * inv_lo[k] : c * inv_hi[k];
+        if (q > best) best = q;
+    }
+    return best;
+}
+
+static double opt_ratio_at(const or_shape *s, const or_args *a, uint64_t idx, double uA,
+                           const double *inv_lo, const double *inv_hi, double *buf, int *sym,
+                           int *work)
+{
+    fesetround(FE_DOWNWARD);
+    volatile double q = opt_ratio_core(s, a, idx, uA, inv_lo, inv_hi, buf, sym, work);
+    fesetround(FE_TONEAREST);
+    return q;
+}
+
+typedef struct {
+    double r;          /* min_A max_z c_z(A) / k_z, rounded down as above        */
+    double bound;      /* d r, rounded down                                      */
+    uint64_t argmin;   /* lowest coordinate attaining r                          */
+    uint64_t nonfinite;/* coordinates whose ratio is not finite                  */
+} or_cert_opt;
+
+static int certify_optimal(int sigma, int d, int h, const void *u, int f32, or_cert_opt *out)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return -1;
+    const void *lag[OR_MAX_D + 1];
+    lag[0] = NULL;
+    for (int k = 1; k <= d; ++k) lag[k] = u;
+    or_args a = {lag, f32, NULL};
+    double inv_lo[OR_MAX_D + 1], inv_hi[OR_MAX_D + 1];
+    make_inverses(&s, inv_lo, inv_hi);
+    or_scratch w;
+    if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
+    or_cert_opt c;
+    memset(&c, 0, sizeof c);
+    c.r = INFINITY;
+    for (uint64_t i = 0; i < s.n_entries; ++i) {
+        double uA = f32 ? (double)((const float *)u)[i] : ((const double *)u)[i];
+        double q = opt_ratio_at(&s, &a, i, uA, inv_lo, inv_hi, w.buf, w.sym, w.work);
+        if (!isfinite(q)) c.nonfinite++;
+        if (q < c.r) { c.r = q; c.argmin = i; }
+    }
+    scratch_free(&w);
+    c.bound = rnd_mul((double)d, c.r, FE_DOWNWARD);
+    *out = c;
+    return 0;
+}
+
+int or_certify_optimal(int sigma, int d, int h, const double *u, or_cert_opt *out)
+{
+    return certify_optimal(sigma, d, h, u, 0, out);
+}
+
+int or_certify_optimal_f32(int sigma, int d, int h, const float *u, or_cert_opt *out)
+{
+    return certify_optimal(sigma, d, h, u, 1, out);
+}
+
+/* max_z c_z(A) / k_z at a list of coordinates (sampled checks) */
+static int optimal_ratio_at(int sigma, int d, int h, const void *u, int f32,
+                            const uint64_t *idx, uint64_t count, double *out)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return -1;
+    const void *lag[OR_MAX_D + 1];
+    lag[0] = NULL;
+    for (int k = 1; k <= d; ++k) lag[k] = u;
+    or_args a = {lag, f32, NULL};
+    double inv_lo[OR_MAX_D + 1], inv_hi[OR_MAX_D + 1];
+    make_inverses(&s, inv_lo, inv_hi);
+    or_scratch w;
+    if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
+    for (uint64_t i = 0; i < count; ++i) {
+        if (idx[i] >= s.n_entries) { scratch_free(&w); return -1; }
+        double uA = f32 ? (double)((const float *)u)[idx[i]] : ((const double *)u)[idx[i]];
+        out[i] = opt_ratio_at(&s, &a, idx[i], uA, inv_lo, inv_hi, w.buf, w.sym, w.work);
+    }
+    scratch_free(&w);
+    return 0;
+}
+
+int or_optimal_ratio_at(int sigma, int d, int h, const double *u, const uint64_t *idx,
+                        uint64_t count, double *out)
+{
+    return optimal_ratio_at(sigma, d, h, u, 0, idx, count, out);
+}
+
+int or_optimal_ratio_at_f32(int sigma, int d, int h, const float *u, const uint64_t *idx,
+                            uint64_t count, double *out)
+{
+    return optimal_ratio_at(sigma, d, h, u, 1, idx, count, out);
 }
 
 /* R = max_j (u - prev)[j] of Algorithm 2 alone (round to nearest), for

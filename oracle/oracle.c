@@ -473,7 +473,9 @@ int or_certify_W_at_f32(int sigma, int d, int h, const float *u, double R,
  * rounded toward -inf.  Every q_z is then at most c_z / k_z, the computed r
  * at most r*, and (u, r, 0) is a feasible triplet for the table given.
  * Branches whose mean is NaN never win the max over z (which starts from
- * -inf), as in F.
+ * -inf), as in F; a zero ratio is taken as +0, so the max over z does not
+ * depend on the order the branches are visited in (the sign of a zero r
+ * means nothing for the bound).
  */
 
 /* a / b under rounding `mode` (see rnd_add) */
@@ -518,6 +520,7 @@ static __attribute__((noinline)) double opt_ratio_core(const or_shape *s, const 
             if (sym[j * s->h] != z) ++k;
         double c = (all_match ? 1.0 + m : m) - uA;
         double q = c >= 0.0 ? c * inv_lo[k] : c * inv_hi[k];
+        if (q == 0.0) q = 0.0;  /* +0 for either zero: the max is then the same in any order */
         if (q > best) best = q;
     }
     return best;

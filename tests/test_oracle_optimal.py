@@ -160,3 +160,12 @@ def test_string_and_index_examples_agree():
     """The helpers borrowed from the case-table tests index as Sec. 3.2 does."""
     assert _index("1011", "0010") == int("10001110", 2)
     assert len(_strings(3)) == 8
+
+
+def test_zero_ratio_is_positive_zero(orc):
+    """A constant table: every mismatch tuple has c = 0 exactly (a zero that
+    round-down subtraction makes -0); the reported r is +0."""
+    u = np.full(16, 2.5)
+    c = orc.certify_optimal(2, 2, 2, u)
+    assert c["r"] == 0.0 and math.copysign(1.0, c["r"]) == 1.0
+    assert math.copysign(1.0, c["bound"]) == 1.0

@@ -84,7 +84,12 @@ typedef struct {
     int64_t sweep;      /* sweeps applied before this certificate            */
     uint64_t argmax_W;  /* lowest index where W attains maxW                 */
     uint64_t nonfinite; /* stored coordinates where u, prev or W is not finite */
+    int64_t kind;       /* LCSB_CERT_FEASIBLE (this struct's formulas) or
+                           LCSB_CERT_OPTIMAL (see lcsb_certify_optimal)       */
 } lcsb_cert;
+
+#define LCSB_CERT_FEASIBLE 0 /* Algorithm 2: R from the last step, then E     */
+#define LCSB_CERT_OPTIMAL  1 /* the largest r with E = 0 for the table        */
 
 /* Create a context for (sigma, d, l = h) and a table element type.
  * GPU kernels exist for (sigma, d) in {(2,2), (4,2), (2,3)} and both element
@@ -144,6 +149,27 @@ int lcsb_iterate(lcsb_ctx *ctx, int64_t k);
  * lag 2). */
 int lcsb_certify(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
 
+/* The largest-r certificate of the newest table u (not in Algorithm 2,
+ * which fixes r to the largest step of the last sweep; derived from the
+ * feasible-triplet lemma of Sec. 2.1).  For a fixed u the lemma's inequality
+ * with eps = 0, F(u + (d-1)r, .., u + r, u) >= u + d r, holds at coordinate A
+ * iff some branch z (moving k_z strings, so reading u + (d - k_z) r) has
+ *     c_z(A) = b(A) + mean_z(u)[A] - u[A] >= k_z r        (eq. (4)),
+ * so the largest such r is r* = min_A max_z c_z(A) / k_z, and (u, r*, 0) is a
+ * feasible triplet giving gamma_{sigma,d} >= d r* (eq. (6)) when r* >= 0.
+ * Every mean, the 1 + of an all-match tuple and the subtraction of u[A] are
+ * rounded toward -inf, c_z / k_z is a multiply by 1/k_z (exact for k = 1, 2;
+ * 1/3 rounded down for c >= 0, up for c < 0) rounded toward -inf, so the
+ * computed r is at most r* and the certificate is rigorous; a zero ratio is
+ * +0.  One pass over u (no previous table, no R pass).  Fills lcsb_cert with
+ * kind = LCSB_CERT_OPTIMAL, R = rho = r, E = 0, bound = d r rounded toward
+ * -inf, maxW = 0 (W <= 0 at R = r by construction; not evaluated), argmax_W =
+ * the lowest index where the ratio attains r, nonfinite = stored coordinates
+ * whose ratio is not finite.  Keep rule, synchronisation and errors as
+ * lcsb_certify (the best certificate is shared by both kinds: the larger
+ * rho = R - E wins). */
+int lcsb_certify_optimal(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
+
 /* Device address of lag k (1..d) and, for LCSB_F32, the FP64 offset its
  * values are relative to (read from the device; synchronises).  The pointer
  * stays valid until the next lcsb_iterate, lcsb_load_ring or lcsb_bind.  On
@@ -181,6 +207,8 @@ typedef struct {
     double min_gain;     /* stop once a positive best bound gained less than
                             this over one period (an FP32 run at its error
                             floor); 0 = off                                   */
+    int64_t certificate; /* LCSB_CERT_FEASIBLE (lcsb_certify) or
+                            LCSB_CERT_OPTIMAL (lcsb_certify_optimal)          */
 } lcsb_run_policy;
 
 #define LCSB_STOP_MAX_SWEEPS 0  /* max_sweeps reached                          */

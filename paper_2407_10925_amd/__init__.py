@@ -103,15 +103,28 @@ class Lcsb:
             check(rc)
         return cur.as_dict(), best.as_dict()
 
+    def certify_optimal(self, allow_nonfinite: bool = False):
+        """lcsb_certify_optimal: the largest r with (u, r, 0) a feasible
+        triplet for the newest table u.  Returns (current, best) as dicts
+        (synchronises)."""
+        cur, best = Cert(), Cert()
+        rc = self._lib.lcsb_certify_optimal(self._ctx, C.byref(cur), C.byref(best))
+        if rc != 0 and not (allow_nonfinite and rc == _capi.LCSB_ENONFINITE):
+            check(rc)
+        return cur.as_dict(), best.as_dict()
+
     def run(self, cadence: int, first: int = 0, max_sweeps: int = 1 << 40,
-            target: float = float("nan"), stop_delta: float = 0.0, min_gain: float = 0.0):
+            target: float = float("nan"), stop_delta: float = 0.0, min_gain: float = 0.0,
+            certificate: str = "feasible"):
         """lcsb_run: sweep and certify every `cadence` sweeps (the first
         certificate after `first`) until the best bound reaches `target`,
         consecutive certificates move by less than `stop_delta`, a positive
         best bound gains less than `min_gain` in a period, or `max_sweeps`.
-        Returns (current, best, certificates, reason)."""
+        `certificate`: "feasible" (Algorithm 2, lcsb_certify) or "optimal"
+        (lcsb_certify_optimal).  Returns (current, best, certificates, reason)."""
         pol = _capi.RunPolicy(int(cadence), int(first), int(max_sweeps), float(target),
-                              float(stop_delta), float(min_gain))
+                              float(stop_delta), float(min_gain),
+                              _capi.CERT_KINDS[certificate])
         cur, best, certs, why = Cert(), Cert(), C.c_int64(), C.c_int()
         check(self._lib.lcsb_run(self._ctx, C.byref(pol), C.byref(cur), C.byref(best),
                                  C.byref(certs), C.byref(why)))

@@ -31,17 +31,21 @@ class LcsbError(RuntimeError):
 
 
 LCSB_STOP_NAMES = {0: "max_sweeps", 1: "target", 2: "converged", 3: "floor"}
+LCSB_CERT_FEASIBLE = 0
+LCSB_CERT_OPTIMAL = 1
+CERT_KINDS = {"feasible": LCSB_CERT_FEASIBLE, "optimal": LCSB_CERT_OPTIMAL}
 
 
 class RunPolicy(C.Structure):
     _fields_ = [("cadence", C.c_int64), ("first", C.c_int64), ("max_sweeps", C.c_int64),
-                ("target", C.c_double), ("stop_delta", C.c_double), ("min_gain", C.c_double)]
+                ("target", C.c_double), ("stop_delta", C.c_double), ("min_gain", C.c_double),
+                ("certificate", C.c_int64)]
 
 
 class Cert(C.Structure):
     _fields_ = [("bound", C.c_double), ("R", C.c_double), ("E", C.c_double),
                 ("maxW", C.c_double), ("rho", C.c_double), ("sweep", C.c_int64),
-                ("argmax_W", C.c_uint64), ("nonfinite", C.c_uint64)]
+                ("argmax_W", C.c_uint64), ("nonfinite", C.c_uint64), ("kind", C.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -70,6 +74,7 @@ def load():
     L.lcsb_load_ring.argtypes = [P, C.POINTER(P), C.c_int, C.POINTER(C.c_double)]
     L.lcsb_iterate.argtypes = [P, C.c_int64]
     L.lcsb_certify.argtypes = [P, C.POINTER(Cert), C.POINTER(Cert)]
+    L.lcsb_certify_optimal.argtypes = [P, C.POINTER(Cert), C.POINTER(Cert)]
     L.lcsb_lag.argtypes = [P, C.c_int, C.POINTER(P), C.POINTER(C.c_double)]
     L.lcsb_status.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(Cert)]
     L.lcsb_swap_symmetric.argtypes = [P, C.POINTER(C.c_int)]
@@ -90,7 +95,7 @@ def load():
                                 C.c_int64, P]
     L.lcsb_init_seed_mlp.argtypes = [P, P, P, C.c_double]
     for name in ("lcsb_create", "lcsb_query", "lcsb_bind", "lcsb_init_zero", "lcsb_load_ring",
-                 "lcsb_iterate", "lcsb_certify", "lcsb_lag", "lcsb_status", "lcsb_swap_symmetric",
+                 "lcsb_iterate", "lcsb_certify", "lcsb_certify_optimal", "lcsb_lag", "lcsb_status", "lcsb_swap_symmetric",
                  "lcsb_upcast",
                  "lcsb_run", "lcsb_save", "lcsb_load", "lcsb_destroy", "lcsb_mlp_workspace", "lcsb_mlp_init", "lcsb_mlp_to_bf16",
                  "lcsb_mlp_sample", "lcsb_mlp_forward", "lcsb_mlp_loss", "lcsb_mlp_backward",

@@ -294,6 +294,7 @@ int lcsb_certify(lcsb_ctx *c, lcsb_cert *cur, lcsb_cert *best)
     memcpy(u64, host, sizeof u64);
     k.argmax_W = u64[Ws::kArgmax / 8];
     k.nonfinite = u64[Ws::kNonfinite / 8] + u64[Ws::kNonfiniteR / 8];
+    k.kind = LCSB_CERT_FEASIBLE;
     k.E = k.maxW > 0.0 ? k.maxW : 0.0;
     k.rho = add_rd(k.R, -k.E);
     k.bound = mul_rd((double)c->g.d, k.rho);
@@ -303,6 +304,41 @@ int lcsb_certify(lcsb_ctx *c, lcsb_cert *cur, lcsb_cert *best)
     if (cur) *cur = k;
     if (best) *best = c->best;
     if (k.nonfinite) return fail(LCSB_ENONFINITE, "%llu non-finite values in the certified tables",
+                                 (unsigned long long)k.nonfinite);
+    return LCSB_OK;
+}
+
+int lcsb_certify_optimal(lcsb_ctx *c, lcsb_cert *cur, lcsb_cert *best)
+{
+    int rc = need_ready(c);
+    if (rc) return rc;
+    const int su = slot_of_lag(c, 1);
+    hipError_t e = launch_certify_optimal(c->g, c->dtype, c->buf[su], c->swap_sym, c->ws,
+                                          c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "certify launch");
+    unsigned char host[Ws::kScalarBytes];
+    if ((e = hipMemcpyAsync(host, c->ws, Ws::kScalarBytes, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "certify copy");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "certify sync");
+    double r;
+    uint64_t arg, nonfinite;
+    memcpy(&r, host + Ws::kOptR, 8);
+    memcpy(&arg, host + Ws::kOptArg, 8);
+    memcpy(&nonfinite, host + Ws::kOptNonfinite, 8);
+    lcsb_cert k;
+    memset(&k, 0, sizeof k);
+    k.kind = LCSB_CERT_OPTIMAL;
+    k.R = r;
+    k.rho = r;  // E = 0, maxW = 0
+    k.bound = mul_rd((double)c->g.d, r);
+    k.argmax_W = arg;
+    k.nonfinite = nonfinite;
+    k.sweep = c->sweeps;
+    // the keep rule of Algorithm 2 on rho = r - eps
+    if (k.nonfinite == 0 && k.rho >= c->best.rho) c->best = k;
+    if (cur) *cur = k;
+    if (best) *best = c->best;
+    if (k.nonfinite) return fail(LCSB_ENONFINITE, "%llu non-finite ratios in the certified table",
                                  (unsigned long long)k.nonfinite);
     return LCSB_OK;
 }
@@ -353,9 +389,11 @@ int lcsb_run(lcsb_ctx *c, const lcsb_run_policy *p, lcsb_cert *cur_out, lcsb_cer
     if (rc) return rc;
     if (!p) return fail(LCSB_EINVAL, "policy is null");
     if (p->cadence <= 0 || p->first < 0 || p->max_sweeps < 0 || !(p->stop_delta >= 0.0) ||
-        !(p->min_gain >= 0.0))
+        !(p->min_gain >= 0.0) ||
+        (p->certificate != LCSB_CERT_FEASIBLE && p->certificate != LCSB_CERT_OPTIMAL))
         return fail(LCSB_EINVAL, "policy: cadence > 0, first >= 0, max_sweeps >= 0, "
-                                 "stop_delta >= 0 and min_gain >= 0 required");
+                                 "stop_delta >= 0, min_gain >= 0 and a known certificate "
+                                 "kind required");
     const bool use_target = !isnan(p->target);
     int64_t certs = 0;
     int why = LCSB_STOP_MAX_SWEEPS;
@@ -370,7 +408,8 @@ int lcsb_run(lcsb_ctx *c, const lcsb_run_policy *p, lcsb_cert *cur_out, lcsb_cer
         while (c->sweeps - start < p->max_sweeps) {
             if ((rc = lcsb_iterate(c, step)) != LCSB_OK) return rc;
             step = p->cadence;
-            rc = lcsb_certify(c, &cur, &best);
+            rc = p->certificate == LCSB_CERT_OPTIMAL ? lcsb_certify_optimal(c, &cur, &best)
+                                                     : lcsb_certify(c, &cur, &best);
             ++certs;
             if (rc != LCSB_OK) {
                 if (cur_out) *cur_out = cur;

@@ -249,37 +249,139 @@ __device__ __forceinline__ double mean_rd(double *v, double shift, double scale)
 // branch NaN gives -inf): the first value of each max chain goes through this.
 __device__ __forceinline__ double first(double v) { return v > -INFINITY ? v : -INFINITY; }
 
-struct WBest {
+// Two evaluations share the coordinate walk below.
+//
+// WEval (Algorithm 2): F on the shifted arguments u + (d-k)R, then
+// W = u + dR - F at every coordinate and its max.
+//
+// OptEval (the largest r of a feasible triplet (u, r, 0), from the lemma of
+// Sec. 2.1 with eps = 0): every argument of F is u (no shift); branch z of
+// coordinate A, moving k_z strings, gives c_z = b(A) + mean_z - u[A] and the
+// ratio q_z = c_z / k_z; the coordinate's value is the max over its branches
+// and r the min over coordinates.  All in round-toward-minus-infinity mode:
+// the mean, the 1 +, the subtraction and the scaling by 1/k_z (exact for
+// k = 1, 2; for k = 3 a multiply by 1/3 rounded down when c >= 0, up when
+// c < 0), so every q_z is at most the exact c_z / k_z.  A zero ratio is +0,
+// so the max does not depend on the order of the branches.  Coordinates
+// arrive in any order: keep the min, lowest index on ties.
+
+struct WEval {
+    double shift[4];  // (d-k)R rounded down, k = 0..3
+    double dR_up;
     double w = -INFINITY;
     uint64_t arg = 0, nonfinite = 0;
-    // In round-toward-minus-infinity mode: W = RU(RU(u_i + dR_up) - f_lo)
-    // = -RD(RD(-u_i - dR_up) + f_lo).  Candidates arrive in any order: keep
-    // the max, lowest index on ties.
-    // `mult`: how many coordinates of equal W this evaluation stands for
-    __device__ __forceinline__ void add(double u_i, double f_lo, double dR_up, uint64_t i,
-                                        int mult = 1)
+
+    template <int CNT>
+    __device__ __forceinline__ double mean(double *v, int k, double scale) const
+    {
+        return mean_rd<CNT>(v, shift[k], scale);
+    }
+    // W = RU(RU(u_i + dR_up) - f_lo) = -RD(RD(-u_i - dR_up) + f_lo); `mult`:
+    // how many coordinates of equal W this evaluation stands for
+    __device__ __forceinline__ void put(double u_i, double f_lo, uint64_t i, int mult)
     {
         const double t = (-u_i) - dR_up;
         const double w_i = -(t + f_lo);
         if (!isfinite(w_i)) nonfinite += (uint64_t)mult;
         if (w_i > w || (w_i == w && i < arg)) { w = w_i; arg = i; }
     }
+    // all-match coordinate: F = 1 + mean over all d moved strings
+    __device__ __forceinline__ void match(double u_i, double m_all, uint64_t i, int mult)
+    {
+        put(u_i, 1.0 + first(m_all), i, mult);
+    }
+    // mismatched coordinate with branch means m[j] moving k[j] strings, in z order
+    template <int NB>
+    __device__ __forceinline__ void mismatch(double u_i, const double *m, const int *, uint64_t i,
+                                             int mult)
+    {
+        double f = first(m[0]);
+#pragma unroll
+        for (int j = 1; j < NB; ++j) f = m[j] > f ? m[j] : f;
+        put(u_i, f, i, mult);
+    }
+    // block result: the value whose max the final pass takes
+    __device__ __forceinline__ double result() const { return w; }
 };
+
+struct OptEval {
+    double half, inv3_lo, inv3_hi;  // 1/2; 1/3 rounded down and up (opaque to the compiler)
+    double r = INFINITY;
+    uint64_t arg = 0, nonfinite = 0;
+
+    __device__ __forceinline__ OptEval(double h, double lo, double hi) : half(h), inv3_lo(lo), inv3_hi(hi)
+    {
+        asm volatile("" : "+s"(half));
+        asm volatile("" : "+s"(inv3_lo));
+        asm volatile("" : "+s"(inv3_hi));
+    }
+    template <int CNT>
+    __device__ __forceinline__ double mean(double *v, int, double scale) const
+    {
+#pragma unroll
+        for (int step = 1; step < CNT; step <<= 1)
+#pragma unroll
+            for (int t = 0; t < CNT; t += 2 * step) v[t] = v[t] + v[t + step];
+        return v[0] * scale;
+    }
+    __device__ __forceinline__ double ratio(double c, int k) const
+    {
+        double q = k == 1 ? c : k == 2 ? c * half : (c >= 0.0 ? c * inv3_lo : c * inv3_hi);
+        return q == 0.0 ? 0.0 : q;
+    }
+    __device__ __forceinline__ void put(double q, uint64_t i, int mult)
+    {
+        if (!isfinite(q)) nonfinite += (uint64_t)mult;
+        if (q < r || (q == r && i < arg)) { r = q; arg = i; }
+    }
+    template <int D>
+    __device__ __forceinline__ void match_d(double u_i, double m_all, uint64_t i, int mult)
+    {
+        put(first(ratio((1.0 + m_all) - u_i, D)), i, mult);
+    }
+    template <int NB>
+    __device__ __forceinline__ void mismatch(double u_i, const double *m, const int *k, uint64_t i,
+                                             int mult)
+    {
+        double f = first(ratio(m[0] - u_i, k[0]));
+#pragma unroll
+        for (int j = 1; j < NB; ++j) {
+            const double q = ratio(m[j] - u_i, k[j]);
+            f = q > f ? q : f;
+        }
+        put(f, i, mult);
+    }
+    // the final pass takes a max: hand it -r (exact; lowest index kept on ties)
+    __device__ __forceinline__ double result() const { return -r; }
+};
+
+// the all-match call of either evaluation (d strings move)
+template <int D>
+__device__ __forceinline__ void eval_match(WEval &ev, double u_i, double m_all, uint64_t i, int mult)
+{
+    ev.match(u_i, m_all, i, mult);
+}
+template <int D>
+__device__ __forceinline__ void eval_match(OptEval &ev, double u_i, double m_all, uint64_t i,
+                                           int mult)
+{
+    ev.template match_d<D>(u_i, m_all, i, mult);
+}
 
 // sigma = d = 2: thread t < n/8 evaluates the stored coordinates 0/0|t,
 // 0/0|xc, 0/1|t, 0/1|xc (xc = n/4-1-t, the complement of t).  The lag-2 group
 // of xc is the image of the one of t; the advance-a pair of 0/1|xc is read in
 // the image group at the other parity (see the sweep).
-// SWAP (a table symmetric under exchanging the strings): W is then equal, bit
-// for bit, at exchanged tuples (the trees are exchange-invariant), so only the
-// lower of the threads t and p (St or ~St, as in the sweep) evaluates, each
-// value standing for two coordinates unless p = t.  The lowest index of each
-// pair is t, ~St, 0/1|t and 0/1|St; the table is kept lazily (TwinGroup), so
-// u is read there and every group through its lower members.
-template <typename T, bool SWAP>
+// SWAP (a table symmetric under exchanging the strings): the value is then
+// equal, bit for bit, at exchanged tuples (the trees are exchange-invariant),
+// so only the lower of the threads t and p (St or ~St, as in the sweep)
+// evaluates, each value standing for two coordinates unless p = t.  The
+// lowest index of each pair is t, ~St, 0/1|t and 0/1|St; the table is kept
+// lazily (TwinGroup), so u is read there and every group through its lower
+// members.
+template <typename T, bool SWAP, class Ev>
 __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint64_t t,
-                                      const double *shift, const Scales &sc, double dR_up,
-                                      WBest &best)
+                                      const Scales &sc, Ev &ev)
 {
     const uint64_t nq = n >> 2, xc = nq - 1 - t;
     uint64_t rep_xc = xc, rep_mis1 = nq + xc;
@@ -308,9 +410,10 @@ __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint
     double q4[4];
     group(4 * t, q4);
     double g[4] = {q4[0], q4[3], q4[1], q4[2]};
-    const double f_match = 1.0 + first(mean_rd<4>(g, shift[2], sc.q[2]));
-    best.add((double)u[t], f_match, dR_up, t, mult);
-    best.add((double)u[rep_xc], f_match, dR_up, rep_xc, mult);
+    const double m_all = ev.template mean<4>(g, 2, sc.q[2]);
+    eval_match<2>(ev, (double)u[t], m_all, t, mult);
+    eval_match<2>(ev, (double)u[rep_xc], m_all, rep_xc, mult);
+    constexpr int ks[2] = {1, 1};
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const uint64_t i = nq + (c ? xc : t);
@@ -324,11 +427,10 @@ __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint
         group(c ? (n - 4) - grp : grp, q);
         const bool odd = ((sa & 1) ^ (uint64_t)c) != 0;
         pa[0] = odd ? q[1] : q[0]; pa[1] = odd ? q[3] : q[2];
-        const double mb = mean_rd<2>(pb, shift[1], sc.q[1]);
-        const double ma = mean_rd<2>(pa, shift[1], sc.q[1]);
-        const double fb = first(mb);  // z = 0 advances b
+        // branches in z order: z = 0 advances b, z = 1 advances a
+        const double m[2] = {ev.template mean<2>(pb, 1, sc.q[1]), ev.template mean<2>(pa, 1, sc.q[1])};
         const uint64_t at = c ? rep_mis1 : i;  // i itself unless SWAP
-        best.add((double)u[at], ma > fb ? ma : fb, dR_up, at, mult);
+        ev.template mismatch<2>((double)u[at], m, ks, at, mult);
     }
 }
 
@@ -341,10 +443,9 @@ __device__ __forceinline__ void w_s2d2(const T *__restrict__ u, uint64_t n, uint
 // lower of t and its twin thread p evaluates; each coordinate is read and
 // reported at the lower index of its exchanged pair and counts for both
 // unless p = t; groups are read through their lower members (Twin16).
-template <typename T, bool SWAP>
+template <typename T, bool SWAP, class Ev>
 __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int h, uint64_t t,
-                                      const double *shift, const Scales &sc, double dR_up,
-                                      WBest &best)
+                                      const Scales &sc, Ev &ev)
 {
     const int top = 4 * (h - 1);
     const uint64_t am = 0xCCCCCCCCCCCCCCCCull & (n - 1), bm = ~am & (n - 1);
@@ -374,8 +475,7 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
     // leaves in the sweep's order (tree16): pairs {ab, ba} by a xor b, {aa, ~a~a}
     double g[16] = {q16[1], q16[4], q16[11], q16[14], q16[2], q16[8], q16[7], q16[13],
                     q16[3], q16[12], q16[6], q16[9], q16[0], q16[15], q16[5], q16[10]};
-    const double m_both = mean_rd<16>(g, shift[2], sc.q[4]);
-    const double f_match = 1.0 + first(m_both);
+    const double m_both = ev.template mean<16>(g, 2, sc.q[4]);
     double ma[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -391,8 +491,9 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
         } else {
             q[0] = u[sa]; q[1] = u[sa + 4]; q[2] = u[sa + 8]; q[3] = u[sa + 12];
         }
-        ma[v] = mean_rd<4>(q, shift[1], sc.q[2]);
+        ma[v] = ev.template mean<4>(q, 1, sc.q[2]);
     }
+    constexpr int ks[3] = {1, 1, 2};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const uint64_t x = t ^ ((uint64_t)m * rep);
@@ -407,19 +508,18 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
         } else {
             ld4(u + sb, q);
         }
-        const double mb = mean_rd<4>(q, shift[1], sc.q[2]);
+        const double mb = ev.template mean<4>(q, 1, sc.q[2]);
         // the lower index of the exchanged pair of coordinate (b1 << top) | x
         auto at = [&](int b1) {
             const uint64_t xt = p ^ ((uint64_t)(m ^ b1 ^ sx) * rep);
             return ((uint64_t)b1 << top) | (SWAP && xt < x ? xt : x);
         };
-        best.add((double)u[at(0)], f_match, dR_up, at(0), mult);
+        eval_match<2>(ev, (double)u[at(0)], m_both, at(0), mult);
 #pragma unroll
         for (int b1 = 1; b1 < 4; ++b1) {
-            double f = first(mb);  // z = 0 advances b
-            f = ma[b1 ^ m] > f ? ma[b1 ^ m] : f;
-            f = m_both > f ? m_both : f;
-            best.add((double)u[at(b1)], f, dR_up, at(b1), mult);
+            // z = 0 advances b, z = b1 advances a, the other two advance both
+            const double mz[3] = {mb, ma[b1 ^ m], m_both};
+            ev.template mismatch<3>((double)u[at(b1)], mz, ks, at(b1), mult);
         }
     }
 }
@@ -429,9 +529,9 @@ __device__ __forceinline__ void w_s4d2(const T *__restrict__ u, uint64_t n, int 
 // branches: the strings with head 1 advance (z = 0) and the strings with head
 // 0 advance (z = 1); k = |N| selects the lag and shift.  A branch that moves
 // string 1 of xc reads every value at the image of its index.
-template <int SET, bool SWAP, typename T>
+template <int SET, bool SWAP, typename T, class Ev>
 __device__ __forceinline__ double branch23(const T *__restrict__ u, uint64_t n, uint64_t i,
-                                           int img, const double *shift, const Scales &sc)
+                                           int img, const Scales &sc, const Ev &ev)
 {
     // SET: bit 2 = string 1, bit 1 = string 2, bit 0 = string 3
     constexpr int K = __builtin_popcount(SET);
@@ -451,19 +551,18 @@ __device__ __forceinline__ double branch23(const T *__restrict__ u, uint64_t n, 
             }
             lx[k++] = (double)u[at];
         }
-    if constexpr (K == 1) return mean_rd<2>(lx, shift[1], sc.q[1]);
+    if constexpr (K == 1) return ev.template mean<2>(lx, 1, sc.q[1]);
     double v[4] = {lx[0], lx[3], lx[1], lx[2]};  // complement-paired leaves
-    return mean_rd<4>(v, shift[2], sc.q[2]);
+    return ev.template mean<4>(v, 2, sc.q[2]);
 }
 
 // SWAP (a table symmetric in strings 1 and 2): as for d = 2, only the lower of
 // the threads t and p (Et or ~Et, as in the sweep) evaluates; every value is
 // read, and reported, at the lower index of its exchanged pair, and counts
 // for both coordinates unless p = t.
-template <typename T, bool SWAP>
+template <typename T, bool SWAP, class Ev>
 __device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int h, uint64_t t,
-                                      const double *shift, const Scales &sc, double dR_up,
-                                      WBest &best)
+                                      const Scales &sc, Ev &ev)
 {
     const int top = 3 * (h - 1);
     const uint64_t mx = (n >> 3) - 1, xc = mx - t;
@@ -494,56 +593,80 @@ __device__ __forceinline__ void w_s2d3(const T *__restrict__ u, uint64_t n, int 
         ld4(u + 8 * t + 4, q8 + 4);
     }
     double g[8] = {q8[0], q8[7], q8[1], q8[6], q8[2], q8[5], q8[3], q8[4]};
-    const double f_match = 1.0 + first(mean_rd<8>(g, shift[3], sc.q[3]));
-    best.add((double)u[lower(t)], f_match, dR_up, lower(t), mult);
-    best.add((double)u[lower(xc)], f_match, dR_up, lower(xc), mult);
+    const double m_all = ev.template mean<8>(g, 3, sc.q[3]);
+    eval_match<3>(ev, (double)u[lower(t)], m_all, lower(t), mult);
+    eval_match<3>(ev, (double)u[lower(xc)], m_all, lower(xc), mult);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const uint64_t x = c ? xc : t;
-#define LCSB_HEAD(H)                                                                            \
-        {                                                                                       \
-            const uint64_t i = ((uint64_t)(H) << top) | x;                                      \
-            const double b1 = branch23<(H), SWAP, T>(u, n, i, ((H) & 4) ? c : 0, shift, sc);  \
-            const double b0 = branch23<(~(H)) & 7, SWAP, T>(u, n, i, ((~(H)) & 4) ? c : 0,   \
-                                                            shift, sc);                         \
-            const double f0 = first(b0);                                                    \
-            const uint64_t at = lower(i);                                                   \
-            best.add((double)u[at], b1 > f0 ? b1 : f0, dR_up, at, mult);                        \
+#define LCSB_HEAD(H)                                                                             \
+        {                                                                                        \
+            const uint64_t i = ((uint64_t)(H) << top) | x;                                       \
+            /* z order: z = 0 moves the strings with head 1, z = 1 those with head 0 */         \
+            const double m[2] = {                                                                \
+                branch23<(H), SWAP, T>(u, n, i, ((H) & 4) ? c : 0, sc, ev),                     \
+                branch23<(~(H)) & 7, SWAP, T>(u, n, i, ((~(H)) & 4) ? c : 0, sc, ev)};          \
+            constexpr int ks[2] = {__builtin_popcount(H), __builtin_popcount((~(H)) & 7)};      \
+            const uint64_t at = lower(i);                                                        \
+            ev.template mismatch<2>((double)u[at], m, ks, at, mult);                             \
         }
         LCSB_HEAD(1) LCSB_HEAD(2) LCSB_HEAD(3)
 #undef LCSB_HEAD
     }
 }
 
-template <int SIGMA, int D, typename T, bool SWAP = false>
+// the evaluation a kernel runs: W (Algorithm 2) reads its scalars from the
+// workspace; the largest-r certificate takes 1/2 and 1/3 rounded both ways
+template <bool OPT>
+using EvalOf = typename std::conditional<OPT, OptEval, WEval>::type;
+
+__device__ __forceinline__ WEval make_eval(const double *sc_ws, const double *, std::false_type)
+{
+    WEval ev;
+    ev.dR_up = sc_ws[Ws::kDRup / 8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ev.shift[k] = sc_ws[Ws::kShift / 8 + k];  // (d-k)R, rounded down
+    return ev;
+}
+__device__ __forceinline__ OptEval make_eval(const double *, const double *inv, std::true_type)
+{
+    return OptEval(0.5, inv[0], inv[1]);
+}
+
+template <class Ev>
+__device__ __forceinline__ void store_block(const Ev &ev, unsigned char *__restrict__ ws)
+{
+    double v = ev.result();
+    uint64_t arg = ev.arg, nonfinite = ev.nonfinite;
+    block_reduce(v, arg, nonfinite);
+    if (threadIdx.x == 0) {
+        reinterpret_cast<double *>(ws + Ws::kPartVal)[blockIdx.x] = v;
+        reinterpret_cast<uint64_t *>(ws + Ws::kPartIdx)[blockIdx.x] = arg;
+        reinterpret_cast<uint64_t *>(ws + Ws::kPartCnt)[blockIdx.x] = nonfinite;
+    }
+}
+
+// inv3 (OPT only): 1/3 rounded down and up, for the all-match ratio of d = 3
+template <int SIGMA, int D, typename T, bool SWAP, bool OPT>
 __global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u_arg, uint64_t n, int h,
-                                                unsigned char *__restrict__ ws)
+                                                unsigned char *__restrict__ ws, double inv3_lo,
+                                                double inv3_hi)
 {
     constexpr int BITS = (SIGMA == 2 ? 1 : 2) * (D + 1);  // head slot and string-1 symbol 2
     const uint64_t z = round_toward_neg_inf();
     const T *__restrict__ u = u_arg + z;
     const double *sc_ws = reinterpret_cast<const double *>(ws + z);
-    const double dR_up = sc_ws[Ws::kDRup / 8];
-    double shift[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) shift[k] = sc_ws[Ws::kShift / 8 + k];  // (d-k)R, rounded down
+    const double inv[2] = {inv3_lo, inv3_hi};
+    auto ev = make_eval(sc_ws, inv, std::integral_constant<bool, OPT>());
     const Scales sc;
     const uint64_t nt = n >> BITS;
-    WBest best;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < nt; t += stride) {
-        if constexpr (SIGMA == 2 && D == 2) w_s2d2<T, SWAP>(u, n, t, shift, sc, dR_up, best);
-        else if constexpr (SIGMA == 4) w_s4d2<T, SWAP>(u, n, h, t, shift, sc, dR_up, best);
-        else w_s2d3<T, SWAP>(u, n, h, t, shift, sc, dR_up, best);
+        if constexpr (SIGMA == 2 && D == 2) w_s2d2<T, SWAP>(u, n, t, sc, ev);
+        else if constexpr (SIGMA == 4) w_s4d2<T, SWAP>(u, n, h, t, sc, ev);
+        else w_s2d3<T, SWAP>(u, n, h, t, sc, ev);
     }
-    double w = best.w;
-    uint64_t arg = best.arg, nonfinite = best.nonfinite;
-    block_reduce(w, arg, nonfinite);
-    if (threadIdx.x == 0) {
-        reinterpret_cast<double *>(ws + Ws::kPartVal)[blockIdx.x] = w;
-        reinterpret_cast<uint64_t *>(ws + Ws::kPartIdx)[blockIdx.x] = arg;
-        reinterpret_cast<uint64_t *>(ws + Ws::kPartCnt)[blockIdx.x] = nonfinite;
-    }
+    store_block(ev, ws);
 }
 
 // l = 1: each branch appends its symbols in the head slot, so its tuples
@@ -579,39 +702,37 @@ struct L1 {
 };
 
 // In round-toward-minus-infinity mode: the branch mean of moved set `moved`
-// (searched from M up) over u + shift_|M|, as mean_rd.
-template <typename T, int SIGMA, int D, int M>
-__device__ __forceinline__ double l1_branch_rd(const T *__restrict__ u, const double *shift,
+// (searched from M up), as the evaluation's mean
+template <typename T, int SIGMA, int D, int M, class Ev>
+__device__ __forceinline__ double l1_branch_rd(const T *__restrict__ u, const Ev &ev,
                                                const Scales &sc, int head, int moved)
 {
     using G = L1<SIGMA, D>;
     if constexpr (M >= (1 << D)) {
         return 0.0;
     } else {
-        if (moved != M) return l1_branch_rd<T, SIGMA, D, M + 1>(u, shift, sc, head, moved);
+        if (moved != M) return l1_branch_rd<T, SIGMA, D, M + 1>(u, ev, sc, head, moved);
         constexpr int K = __builtin_popcount(M), CNT = 1 << (G::kBeta * K);
         double v[CNT];
 #pragma unroll
         for (int c = 0; c < CNT; ++c)
             v[c] = (double)u[G::image(G::template successor<M>(head, G::template leaf<CNT>(c)))];
-        return mean_rd<CNT>(v, shift[K], sc.q[G::kBeta * K]);
+        return ev.template mean<CNT>(v, K, sc.q[G::kBeta * K]);
     }
 }
 
-template <typename T, int SIGMA, int D>
+template <typename T, int SIGMA, int D, bool OPT>
 __global__ __launch_bounds__(kBlock) void cert_w_l1(const T *__restrict__ u_arg,
-                                                   unsigned char *__restrict__ ws)
+                                                   unsigned char *__restrict__ ws, double inv3_lo,
+                                                   double inv3_hi)
 {
     using G = L1<SIGMA, D>;
     const uint64_t z = round_toward_neg_inf();
     const T *__restrict__ u = u_arg + z;
     const double *sc_ws = reinterpret_cast<const double *>(ws + z);
-    const double dR_up = sc_ws[Ws::kDRup / 8];
-    double shift[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) shift[k] = sc_ws[Ws::kShift / 8 + k];
+    const double inv[2] = {inv3_lo, inv3_hi};
+    auto ev = make_eval(sc_ws, inv, std::integral_constant<bool, OPT>());
     const Scales sc;
-    WBest best;
     const int j = threadIdx.x;
     if (j < G::kNs) {
         int sym[D];
@@ -621,33 +742,37 @@ __global__ __launch_bounds__(kBlock) void cert_w_l1(const T *__restrict__ u_arg,
             sym[s] = (j >> (G::kBeta * (D - 1 - s))) & (SIGMA - 1);
             same = same && sym[s] == sym[0];
         }
-        double f;
         if (same) {
-            f = 1.0 + first(l1_branch_rd<T, SIGMA, D, 1>(u, shift, sc, j, (1 << D) - 1));
+            const double m = l1_branch_rd<T, SIGMA, D, 1>(u, ev, sc, j, (1 << D) - 1);
+            eval_match<D>(ev, (double)u[j], m, (uint64_t)j, 1);
         } else {
-            f = -INFINITY;
+            double m[SIGMA];
+            int ks[SIGMA];
 #pragma unroll
             for (int zz = 0; zz < SIGMA; ++zz) {
                 int moved = 0;
 #pragma unroll
                 for (int s = 0; s < D; ++s)
                     if (sym[s] != zz) moved |= 1 << s;
-                const double m = l1_branch_rd<T, SIGMA, D, 1>(u, shift, sc, j, moved);
-                f = m > f ? m : f;
+                m[zz] = l1_branch_rd<T, SIGMA, D, 1>(u, ev, sc, j, moved);
+                ks[zz] = __builtin_popcount(moved);
             }
+            ev.template mismatch<SIGMA>((double)u[j], m, ks, (uint64_t)j, 1);
         }
-        best.add((double)u[j], f, dR_up, (uint64_t)j);
     }
-    double w = best.w;
-    uint64_t arg = best.arg, nonfinite = best.nonfinite;
-    block_reduce(w, arg, nonfinite);
+    double v = ev.result();
+    uint64_t arg = ev.arg, nonfinite = ev.nonfinite;
+    block_reduce(v, arg, nonfinite);
     if (threadIdx.x == 0) {
-        reinterpret_cast<double *>(ws + Ws::kPartVal)[0] = w;
+        reinterpret_cast<double *>(ws + Ws::kPartVal)[0] = v;
         reinterpret_cast<uint64_t *>(ws + Ws::kPartIdx)[0] = arg;
         reinterpret_cast<uint64_t *>(ws + Ws::kPartCnt)[0] = nonfinite;
     }
 }
 
+// Reduce the W pass partials (max W, lowest index), or for the largest-r
+// certificate the partials of -q (so r = -max, lowest index kept).
+template <bool OPT>
 __global__ __launch_bounds__(kBlock) void cert_w_final(unsigned char *__restrict__ ws, int nparts)
 {
     double best = -INFINITY;
@@ -659,9 +784,17 @@ __global__ __launch_bounds__(kBlock) void cert_w_final(unsigned char *__restrict
     }
     block_reduce(best, arg, nonfinite);
     if (threadIdx.x == 0) {
-        reinterpret_cast<double *>(ws)[Ws::kMaxW / 8] = best;
-        reinterpret_cast<uint64_t *>(ws)[Ws::kArgmax / 8] = arg;
-        reinterpret_cast<uint64_t *>(ws)[Ws::kNonfinite / 8] = nonfinite;
+        double *sc = reinterpret_cast<double *>(ws);
+        uint64_t *su = reinterpret_cast<uint64_t *>(ws);
+        if constexpr (OPT) {
+            sc[Ws::kOptR / 8] = -best;
+            su[Ws::kOptArg / 8] = arg;
+            su[Ws::kOptNonfinite / 8] = nonfinite;
+        } else {
+            sc[Ws::kMaxW / 8] = best;
+            su[Ws::kArgmax / 8] = arg;
+            su[Ws::kNonfinite / 8] = nonfinite;
+        }
     }
 }
 
@@ -671,30 +804,32 @@ int reduce_blocks(uint64_t n)
     return (int)(b < (uint64_t)kMaxReduceBlocks ? b : (uint64_t)kMaxReduceBlocks);
 }
 
-template <typename T>
+template <typename T, bool OPT>
 hipError_t launch_w(const Geometry &g, const T *u, int swap_sym, unsigned char *ws, int nbw,
                     hipStream_t s)
 {
+    double lo = 0.0, hi = 0.0;
+    inverse_bounds(3.0, &lo, &hi);
     if (g.h == 1 && g.sigma == 2 && g.d == 2)
-        cert_w_l1<T, 2, 2><<<1, kBlock, 0, s>>>(u, ws);
+        cert_w_l1<T, 2, 2, OPT><<<1, kBlock, 0, s>>>(u, ws, lo, hi);
     else if (g.h == 1 && g.sigma == 4 && g.d == 2)
-        cert_w_l1<T, 4, 2><<<1, kBlock, 0, s>>>(u, ws);
+        cert_w_l1<T, 4, 2, OPT><<<1, kBlock, 0, s>>>(u, ws, lo, hi);
     else if (g.h == 1 && g.sigma == 2 && g.d == 3)
-        cert_w_l1<T, 2, 3><<<1, kBlock, 0, s>>>(u, ws);
+        cert_w_l1<T, 2, 3, OPT><<<1, kBlock, 0, s>>>(u, ws, lo, hi);
     else if (g.h == 1)
         return hipErrorInvalidValue;
     else if (g.sigma == 2 && g.d == 2 && swap_sym)
-        cert_w<2, 2, T, true><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
+        cert_w<2, 2, T, true, OPT><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws, lo, hi);
     else if (g.sigma == 2 && g.d == 2)
-        cert_w<2, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
+        cert_w<2, 2, T, false, OPT><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws, lo, hi);
     else if (g.sigma == 4 && g.d == 2 && swap_sym)
-        cert_w<4, 2, T, true><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
+        cert_w<4, 2, T, true, OPT><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws, lo, hi);
     else if (g.sigma == 4 && g.d == 2)
-        cert_w<4, 2, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
+        cert_w<4, 2, T, false, OPT><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws, lo, hi);
     else if (g.sigma == 2 && g.d == 3 && swap_sym)
-        cert_w<2, 3, T, true><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
+        cert_w<2, 3, T, true, OPT><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws, lo, hi);
     else if (g.sigma == 2 && g.d == 3)
-        cert_w<2, 3, T><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws);
+        cert_w<2, 3, T, false, OPT><<<nbw, kBlock, 0, s>>>(u, g.n, g.h, ws, lo, hi);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -721,13 +856,35 @@ hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // one thread per x with string-1 symbol 0 at position 2 (one workgroup at l = 1)
     const int nbw = g.h == 1 ? 1 : reduce_blocks(g.n >> (g.slot + g.beta));
-    if ((e = launch_w<T>(g, static_cast<const T *>(u), swap_sym, ws, nbw, s)) != hipSuccess)
+    if ((e = launch_w<T, false>(g, static_cast<const T *>(u), swap_sym, ws, nbw, s)) !=
+        hipSuccess)
         return e;
-    cert_w_final<<<1, kBlock, 0, s>>>(ws, nbw);
+    cert_w_final<false><<<1, kBlock, 0, s>>>(ws, nbw);
+    return hipGetLastError();
+}
+
+// The largest-r certificate: one pass over u, then its final reduction.
+template <typename T>
+hipError_t certify_optimal_typed(const Geometry &g, const void *u, int swap_sym,
+                                 unsigned char *ws, hipStream_t s)
+{
+    const int nbw = g.h == 1 ? 1 : reduce_blocks(g.n >> (g.slot + g.beta));
+    hipError_t e;
+    if ((e = launch_w<T, true>(g, static_cast<const T *>(u), swap_sym, ws, nbw, s)) !=
+        hipSuccess)
+        return e;
+    cert_w_final<true><<<1, kBlock, 0, s>>>(ws, nbw);
     return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t launch_certify_optimal(const Geometry &g, int dtype, const void *u, int swap_sym,
+                                  unsigned char *ws, hipStream_t s)
+{
+    return dtype == LCSB_F32 ? certify_optimal_typed<float>(g, u, swap_sym, ws, s)
+                             : certify_optimal_typed<double>(g, u, swap_sym, ws, s);
+}
 
 hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const void *prev,
                           int u_slot, int prev_slot, int swap_sym, unsigned char *ws,

@@ -22,7 +22,11 @@ struct Ws {
     static constexpr size_t kArgmax = 56;    // uint64
     static constexpr size_t kNonfinite = 64; // uint64: W pass
     static constexpr size_t kNonfiniteR = 72;// uint64: R pass (u, prev)
-    static constexpr size_t kScalarBytes = 80;
+    // the largest-r certificate
+    static constexpr size_t kOptR = 80;          // double: min over coordinates of max_z c_z / k_z
+    static constexpr size_t kOptArg = 88;        // uint64: lowest index attaining it
+    static constexpr size_t kOptNonfinite = 96;  // uint64: coordinates whose ratio is not finite
+    static constexpr size_t kScalarBytes = 104;
     static constexpr size_t kAsym = 128;     // uint32: set when a table is not exchange-symmetric
     // FP64 offsets of the FP32 tables, one per ring slot
     static constexpr size_t kOffsets = 256;  // double[8]
@@ -58,6 +62,10 @@ hipError_t launch_sweep(const Geometry &g, int dtype, const SweepLaunch &a, hipS
 hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const void *prev,
                           int u_slot, int prev_slot, int swap_sym, unsigned char *ws,
                           hipStream_t s);
+
+// The largest-r certificate of u (kOptR, kOptArg, kOptNonfinite).
+hipError_t launch_certify_optimal(const Geometry &g, int dtype, const void *u, int swap_sym,
+                                  unsigned char *ws, hipStream_t s);
 
 // Utilities
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);

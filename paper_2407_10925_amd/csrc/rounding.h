@@ -68,4 +68,15 @@ __host__ __device__ inline double mul_ru(double a, double b)
     return e > 0.0 ? next_up(p) : p;
 }
 
+// lo <= 1/k <= hi with lo, hi adjacent doubles (or both exact): q = fl(1/k),
+// and the sign of the exactly representable residual q k - 1 (one FMA)
+// says on which side of 1/k the rounded quotient fell.
+__host__ __device__ inline void inverse_bounds(double k, double *lo, double *hi)
+{
+    const double q = 1.0 / k;
+    const double e = __builtin_fma(q, k, -1.0);
+    *lo = e > 0.0 ? next_down(q) : q;
+    *hi = e < 0.0 ? next_up(q) : q;
+}
+
 }  // namespace lcsb

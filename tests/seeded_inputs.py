@@ -93,3 +93,26 @@ def sample_indices(n: int, count: int, seed: int) -> torch.Tensor:
     cand = {0, 1, n - 2, n - 1, n // 4 - 1, n // 4, n // 2 - 1, n // 2, 3 * n // 4 - 1, 3 * n // 4}
     edges = torch.tensor(sorted(e for e in cand if 0 <= e < n), dtype=torch.int64)
     return torch.unique(torch.cat([base, edges]))
+
+
+def orbit(idx: int, sigma: int, d: int, h: int) -> list:
+    """Every index of the orbit of idx under the relabellings c -> c xor m and
+    the exchange of strings 1 and 2 (sorted); a table symmetric under both is
+    constant on it."""
+    n = sigma ** (d * h)
+    rep_bits = (n - 1) // (sigma - 1)
+    e = int(exchanged(torch.tensor([idx], dtype=torch.int64), sigma, d, h)[0])
+    return sorted({j ^ (m * rep_bits) for j in (idx, e) for m in range(sigma)})
+
+
+def stored_table(sigma: int, d: int, h: int, seed: int, dtype=torch.float64, device="cpu",
+                 scale: float = 8.0, chunk: int = 1 << 26) -> torch.Tensor:
+    """The first n / sigma values (string-1 head 0) of table(..., exchange=True)."""
+    n = sigma ** (d * h)
+    ns = n // sigma
+    out = torch.empty(ns, dtype=dtype, device=device)
+    for lo in range(0, ns, chunk):
+        idx = torch.arange(lo, min(ns, lo + chunk), dtype=torch.int64, device=device)
+        idx = torch.minimum(idx, representative(exchanged(idx, sigma, d, h), sigma, d, h))
+        out[lo:lo + idx.numel()] = uniform(seed, idx, scale).to(dtype)
+    return out

@@ -89,6 +89,11 @@ def lib():
         L.or_optimal_ratio_at_f32.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_float),
                                               P(C.c_uint64), C.c_uint64, P(C.c_double)]
         L.or_brute_W.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P(C.c_int), P(C.c_uint64)]
+        L.or_two_array_step.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double), C.c_double,
+                                        P(C.c_double)]
+        L.or_sample_growth.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double), P(C.c_double),
+                                       P(C.c_double)]
+        L.or_sample_coordinates.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_uint64)]
         _lib = L
     return _lib
 
@@ -260,6 +265,64 @@ def feasible_triplet(sigma, d, h, n_sweeps, cadence=1, want_ring=False):
     return ({"sweep": int(best[0]), "r": best[1], "eps": best[2], "bound": best[3]},
             hist[: nh * 4].reshape(nh, 4),
             ring.reshape(d, N) if want_ring else None)
+
+
+SAMPLE = 4096  # coordinates of the two-array iteration's rate sample
+
+
+def two_array_step(sigma, d, h, u, R):
+    """u_new = F(u, u - R, .., u - (d-1) R), the shift added to each branch
+    mean (a reading of the two-array remark of Sec. 3.3)."""
+    u = _f64(u)
+    out = np.empty(u.size, dtype=np.float64)
+    _check(lib().or_two_array_step(sigma, d, h, _dptr(u), float(R), _dptr(out)), "two_array_step")
+    return out
+
+
+def sample_growth(sigma, d, h, u_new, u):
+    """The rate of the next two-array step: mean of u_new - u over the sample."""
+    u_new, u = _f64(u_new), _f64(u)
+    R = C.c_double()
+    _check(lib().or_sample_growth(sigma, d, h, _dptr(u_new), _dptr(u), C.byref(R)),
+           "sample_growth")
+    return R.value
+
+
+def sample_coordinates(sigma, d, h):
+    out = np.empty(SAMPLE, dtype=np.uint64)
+    _check(lib().or_sample_coordinates(sigma, d, h, out.ctypes.data_as(C.POINTER(C.c_uint64))),
+           "sample_coordinates")
+    return out
+
+
+def two_array_run(sigma, d, h, n_sweeps, cadence=1, certificate="feasible", u0=None, u1=None):
+    """The two-array iteration from u1 (newest) and u0 (the table before it;
+    both zero by default), certified every `cadence` steps with Algorithm 2's
+    certificate (u and the table before it) or the largest-r one.  Returns
+    (best, history, (u, u_prev, R)); best and each history entry are dicts
+    with keys sweep, rho, bound (history entries also hold the certificate)."""
+    N = num_entries(sigma, d, h)
+    u_prev = np.zeros(N) if u0 is None else _f64(u0).copy()
+    u = np.zeros(N) if u1 is None else _f64(u1).copy()
+    R = sample_growth(sigma, d, h, u, u_prev)
+    best = {"sweep": 0, "rho": 0.0, "bound": 0.0}
+    hist = []
+    for t in range(1, n_sweeps + 1):
+        new = two_array_step(sigma, d, h, u, R)
+        R = sample_growth(sigma, d, h, new, u)
+        u_prev, u = u, new
+        if t % cadence:
+            continue
+        if certificate == "optimal":
+            c = certify_optimal(sigma, d, h, u)
+            rho, ok = c["r"], c["nonfinite"] == 0
+        else:
+            c = certify(sigma, d, h, u, u_prev)
+            rho, ok = c["rho"], c["nonfinite"] == 0
+        hist.append({"sweep": t, "rho": rho, "bound": c["bound"], "cert": c, "R_next": R})
+        if ok and rho >= best["rho"]:  # Algorithm 2's keep rule
+            best = {"sweep": t, "rho": rho, "bound": c["bound"]}
+    return best, hist, (u, u_prev, R)
 
 
 def brute_W_sum(sigma, d, h, n, heads):

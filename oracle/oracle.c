@@ -139,6 +139,8 @@ typedef struct {
     const void *const *lag;   /* lag[k] for k = 1..d; lag[0] unused */
     int f32;                  /* lag tables hold floats (read as exact doubles) */
     const double *shift;      /* shift[k] for k = 1..d, or NULL */
+    const double *delta;      /* delta[k] added to the mean of a branch moving
+                                 k >= 2 strings (the two-array step), or NULL */
 } or_args;
 
 static double lag_value(const or_args *a, int k, uint64_t idx)
@@ -204,7 +206,14 @@ static double F_at(const or_shape *s, const or_args *a, uint64_t idx,
     for (int z = 0; z < s->sigma; ++z) {
         int skip;
         double v = F_z(s, a, sym, z, buf, work, &skip);
-        if (!skip && v > best) best = v;
+        if (skip) continue;
+        if (a->delta) {
+            int k = 0;
+            for (int j = 0; j < s->d; ++j)
+                if (sym[j * s->h] != z) ++k;
+            if (k >= 2) v = v + a->delta[k];
+        }
+        if (v > best) best = v;
     }
     return all_match ? 1.0 + best : best;
 }
@@ -613,6 +622,82 @@ int or_optimal_ratio_at_f32(int sigma, int d, int h, const float *u, const uint6
                             uint64_t count, double *out)
 {
     return optimal_ratio_at(sigma, d, h, u, 1, idx, count, out);
+}
+
+/* ------------------------------------------------------------------ */
+/* exported: the two-array iteration                                   */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Sec. 3.3 remarks that the recurrence can be run on two arrays instead of a
+ * ring, without saying how.  The reading taken here keeps one table u and a
+ * rate R: the d arguments of F are u and the earlier tables as the iteration
+ * would have them if every coordinate had grown by R per step,
+ *     u_new = F(u, u - R, .., u - (d-1) R),
+ * which (translation invariance, property 2 of the lemma) is the ring's step
+ * whenever v_{n-k} = v_n - k R; at the ring's limit every coordinate grows by
+ * the same r, so the two iterations share their fixed points.  Of the two
+ * stored arrays one is u, the other receives u_new.  The shift is applied to
+ * each branch mean: a branch moving k >= 2 strings gives mean_z(u) + delta_k,
+ * delta_k = -(k-1) R (a branch moving one string reads u itself).
+ *
+ * R of the next step is the mean growth over a fixed sample of coordinates:
+ * c_i = (i * 0x9E3779B97F4A7C15 mod 2^64) mod (n / sigma), i = 0 .. 4095
+ * (coordinates whose string 1 starts with symbol 0; a multiplicative hash
+ * spreads them over the table), R = (pairwise sum over i of
+ * (u_new - u)[c_i]) / 4096.  The iteration, its certificates and its limit
+ * do not depend on how R is chosen beyond the speed of convergence (every
+ * table gives a rigorous certificate); this choice costs one small pass.
+ */
+#define OR_SAMPLE 4096
+
+static uint64_t sample_coordinate(const or_shape *s, uint64_t i)
+{
+    return (i * 0x9E3779B97F4A7C15ull) % (s->n_entries / (uint64_t)s->sigma);
+}
+
+/* u_new = F(u, u - R, .., u - (d-1) R) at every coordinate */
+int or_two_array_step(int sigma, int d, int h, const double *u, double R, double *out)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return -1;
+    const void *lag[OR_MAX_D + 1];
+    double delta[OR_MAX_D + 1];
+    lag[0] = NULL;
+    delta[0] = delta[1] = 0.0;
+    for (int k = 1; k <= d; ++k) lag[k] = u;
+    for (int k = 2; k <= d; ++k) delta[k] = -((double)(k - 1) * R);
+    or_args a = {lag, 0, NULL, delta};
+    or_scratch w;
+    if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
+    for (uint64_t i = 0; i < s.n_entries; ++i) out[i] = F_at(&s, &a, i, w.buf, w.sym, w.work);
+    scratch_free(&w);
+    return 0;
+}
+
+/* the rate of the next step: mean of u_new - u over the sample */
+int or_sample_growth(int sigma, int d, int h, const double *u_new, const double *u, double *R)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return -1;
+    double *diff = (double *)malloc(sizeof(double) * OR_SAMPLE);
+    if (!diff) return -2;
+    for (uint64_t i = 0; i < OR_SAMPLE; ++i) {
+        uint64_t c = sample_coordinate(&s, i);
+        diff[i] = u_new[c] - u[c];
+    }
+    *R = pairwise_sum(diff, OR_SAMPLE) / (double)OR_SAMPLE;
+    free(diff);
+    return 0;
+}
+
+/* the sample's coordinates (for tests) */
+int or_sample_coordinates(int sigma, int d, int h, uint64_t *out)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return -1;
+    for (uint64_t i = 0; i < OR_SAMPLE; ++i) out[i] = sample_coordinate(&s, i);
+    return 0;
 }
 
 /* R = max_j (u - prev)[j] of Algorithm 2 alone (round to nearest), for

@@ -91,8 +91,8 @@ def forward(flat, X, bf16_ops=True):
     h3 = np.maximum(z3, 0.0)
     a3 = q(h3)
     y = a3 @ w4 + p["b4"][0]
-    cache = {"X": X, "a1": a1, "a2": a2, "a3": a3, "W2": W2, "W3": W3, "w4": w4,
-             "m1": z1 > 0, "m2": z2 > 0, "m3": z3 > 0}
+    cache = {"X": X, "a1": a1, "a2": a2, "a3": a3, "W1": W1, "W2": W2, "W3": W3, "w4": w4,
+             "z1": z1, "z2": z2, "z3": z3, "m1": z1 > 0, "m2": z2 > 0, "m3": z3 > 0}
     return y, cache
 
 
@@ -102,21 +102,41 @@ def mse(y, t):
     return float(np.mean(r * r)), 2.0 * r / r.size
 
 
-def backward(cache, dy):
-    """Gradient of the loss with respect to every parameter (flat FP64 vector)."""
+def backward(cache, dy, bf16_grads=False):
+    """Gradient of the loss with respect to every parameter (flat FP64 vector).
+
+    bf16_grads=False: the exact gradient of forward() (ReLU' from the sign of
+    the pre-activation).  bf16_grads=True: the rounding the GPU applies to the
+    back-propagated signal, in FP64 otherwise: ReLU' is read off the stored
+    BF16 activation (a > 0), the output layer's dZ3 = dy * w4 is formed in
+    FP32 and rounded to BF16, and each dZ that meets a weight matrix on its
+    way down (dZ2 = dZ3 W3, dZ1 = dZ2 W2) is rounded to BF16 after its
+    product; weight and bias gradients are exact sums of those."""
     g = {}
     dy = np.asarray(dy, np.float64)
     g["w4"] = cache["a3"].T @ dy
     g["b4"] = np.array([dy.sum()])
-    dz3 = np.outer(dy, cache["w4"]) * cache["m3"]
-    g["W3"] = dz3.T @ cache["a2"]
-    g["b3"] = dz3.sum(0)
-    dz2 = (dz3 @ cache["W3"]) * cache["m2"]
-    g["W2"] = dz2.T @ cache["a1"]
-    g["b2"] = dz2.sum(0)
-    dz1 = (dz2 @ cache["W2"]) * cache["m1"]
+    if bf16_grads:
+        m3, m2, m1 = cache["a3"] > 0, cache["a2"] > 0, cache["a1"] > 0
+        prod = np.outer(dy.astype(np.float32), cache["w4"].astype(np.float32))  # FP32 products
+        dz3 = bf16(prod.astype(np.float64)) * m3
+        g["W3"] = dz3.T @ cache["a2"]
+        g["b3"] = dz3.sum(0)
+        dz2 = bf16(dz3 @ cache["W3"]) * m2
+        g["W2"] = dz2.T @ cache["a1"]
+        g["b2"] = dz2.sum(0)
+        dz1 = bf16(dz2 @ cache["W2"]) * m1
+    else:
+        dz3 = np.outer(dy, cache["w4"]) * cache["m3"]
+        g["W3"] = dz3.T @ cache["a2"]
+        g["b3"] = dz3.sum(0)
+        dz2 = (dz3 @ cache["W3"]) * cache["m2"]
+        g["W2"] = dz2.T @ cache["a1"]
+        g["b2"] = dz2.sum(0)
+        dz1 = (dz2 @ cache["W2"]) * cache["m1"]
     g["W1"] = dz1.T @ cache["X"]
     g["b1"] = dz1.sum(0)
+    cache["dz3"], cache["dz2"], cache["dz1"] = dz3, dz2, dz1
     out = np.empty(NPARAMS)
     for k, (o, s) in OFFSETS.items():
         out[o:o + int(np.prod(s))] = g[k].reshape(-1)

@@ -21,17 +21,36 @@ static long bad = 0;
 
 static uint64_t lower(uint64_t j, uint64_t tw) { return tw < j ? tw : j; }
 
+// Group bases to visit: every one (step 0), or `count` of them spread by a
+// multiplicative hash plus the first and last groups of the stored range
+// (large l, where the stored range passes 2^31 and 2^32).
+struct Bases {
+    uint64_t ns, G, count;
+    uint64_t size() const { return count ? count + 2 : ns / G; }
+    uint64_t operator[](uint64_t k) const
+    {
+        if (!count) return k * G;
+        if (k == count) return 0;
+        if (k == count + 1) return ns - G;
+        return ((k * 0x9E3779B97F4A7C15ull) % (ns / G)) * G;
+    }
+};
+
 // d = 2 (sigma = 2) and d = 3: a TwinGroup's mode and member mapping
 template <int D>
-static void groups(int h)
+static void groups(int h, uint64_t count = 0)
 {
     const int G = D == 2 ? 4 : 8;
     const uint64_t n = 1ull << (D * h), ns = n / 2;
-    for (uint64_t base = 0; base < ns; base += G) {
+    const Bases bases{ns, (uint64_t)G, count};
+    for (uint64_t k = 0; k < bases.size(); ++k) {
+        const uint64_t base = bases[k];
         const TwinGroup tg = D == 2 ? twin_group(base, n) : twin_group8(base, n);
         for (int v = 0; v < G; ++v) {
             const uint64_t j = base + v, js = exchange_twin(j, n, D);
             EXPECT(js < ns, "d=%d h=%d j=%llu: twin not stored", D, h, (unsigned long long)j);
+            EXPECT(exchange_twin(js, n, D) == j, "d=%d h=%d j=%llu: not an involution", D, h,
+                   (unsigned long long)j);
             if (tg.mode == 0) EXPECT(js > j, "d=%d own group holds an upper entry", D);
             if (tg.mode == 1 || tg.mode == 2) {
                 EXPECT(js < j, "d=%d twin group holds a lower entry", D);
@@ -56,13 +75,16 @@ static void groups(int h)
 
 // sigma = 4, d = 2: Twin16 and member16, the vector-load addresses of the
 // folded sweep, and the grouped R pass
-static void sigma4(int h)
+static void sigma4(int h, uint64_t count = 0)
 {
     const uint64_t n = 1ull << (4 * h), ns = n / 4;
-    for (uint64_t base = 0; base < ns; base += 16) {
+    const Bases bases{ns, 16, count};
+    for (uint64_t k = 0; k < bases.size(); ++k) {
+        const uint64_t base = bases[k];
         const Twin16 tw = twin_group16(base, n);
         for (int v = 0; v < 16; ++v) {
             const uint64_t j = base + v, js = exchange_twin4(j, n);
+            EXPECT(js < ns && exchange_twin4(js, n) == j, "sigma=4 h=%d: twin not a stored involution", h);
             EXPECT(member16(base, tw, v) == lower(j, js), "sigma=4 h=%d member %d", h, v);
             if (tw.kind == 0) EXPECT(js > j, "sigma=4 own group holds an upper entry");
             if (tw.kind == 1) EXPECT(js < j, "sigma=4 twin group holds a lower entry");
@@ -87,6 +109,11 @@ int main()
     for (int h = 2; h <= 10; ++h) groups<2>(h);
     for (int h = 2; h <= 7; ++h) groups<3>(h);
     for (int h = 2; h <= 5; ++h) sigma4(h);
+    // sampled groups at the sizes the benchmarks and the l = 17 runs use
+    // (stored ranges up to 2^33 entries)
+    for (int h = 11; h <= 17; ++h) groups<2>(h, 1u << 18);
+    for (int h = 8; h <= 11; ++h) groups<3>(h, 1u << 18);
+    for (int h = 6; h <= 8; ++h) sigma4(h, 1u << 18);
     printf("%s (%ld disagreements)\n", bad ? "FAIL" : "ok", bad);
     return bad != 0;
 }

@@ -3,8 +3,10 @@ as host code: every grouped fast path of the kernels (twin groups of 4, 8 and
 16 entries, the member positions the folded kernels read, the runs the folded
 sigma = 4 sweep reads with one vector load, the groups the R pass skips or
 reads whole) agrees entry by entry with the per-entry rule, for every stored
-index at l = 2 .. 10 (sigma = d = 2), 2 .. 7 (d = 3) and 2 .. 5 (sigma = 4).
-No GPU is used."""
+index at l = 2 .. 10 (sigma = d = 2), 2 .. 7 (d = 3) and 2 .. 5 (sigma = 4),
+and for 2^18 hashed groups (plus the first and last) at l = 11 .. 17,
+8 .. 11 and 6 .. 8, where stored indices pass 2^31 and 2^32.  No GPU is
+used."""
 import os
 import shutil
 import subprocess

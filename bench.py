@@ -3,7 +3,8 @@
 
 Workload: sigma = d = 2, l = 16 (2^32 table indices, of which the 2^31 with
 string-1 head 0 are stored: the complement symmetry of Sec. 3.3), FP32 sweeps
-renormalised by entry 0, with an FP64 round-down certificate every 64 sweeps.
+renormalised by entry 0, with an FP64 round-down certificate every 64 sweeps
+(the largest-r certificate of the newest table: one pass, no R pass).
 One step is one certificate period: 64 sweeps + one certificate.  The
 reported value is table updates per second (2^32 updates per sweep, one per
 index) over the K timed steps, with the ring already resident in HBM.
@@ -103,11 +104,41 @@ def measured_traffic(path=PMC_SUMMARY):
     return s.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(h, log2_sample):
-    """The oracle (single thread) on one sweep over every 2^(2h - s)-th entry
-    of an l = h FP32 ring filled with seeded values."""
+def host_description():
+    """CPU model, logical CPUs, the CPUs this process may run on, and RAM."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)), "ram_GiB": mem}
+
+
+def cpu_baseline(pk, h, log2_sample, max_threads=16):
+    """The oracle on this host's cores: one sweep over every 2^(2h - s)-th
+    entry of an l = h FP32 ring filled with seeded values, first on one
+    thread, then split into contiguous index ranges over `threads` threads
+    (the oracle itself stays single-threaded per call; ctypes releases the
+    interpreter lock, so the calls run in parallel and give the same bits).
+    Also the whole C1 run (sigma = d = 2, l = 6, FP64, 200 sweeps from zero,
+    a certificate after every sweep) on the oracle and on the GPU."""
     import numpy as np
     import torch
+    from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -124,14 +155,42 @@ def cpu_baseline(h, log2_sample):
     count = min(n, 1 << log2_sample)
     idx = np.arange(0, n, n // count, dtype=np.uint64)[:count]
     oracle.lib()
-    log(f"cpu baseline: oracle sweep over {count} sampled entries")
+    log(f"cpu baseline: oracle sweep over {count} sampled entries, one thread")
     t0 = time.perf_counter()
-    oracle.sweep_at_tables(2, 2, h, lags, idx)
-    dt = time.perf_counter() - t0
-    return {"value": count / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+    ref = oracle.sweep_at_tables(2, 2, h, lags, idx)
+    dt1 = time.perf_counter() - t0
+    threads = max(1, min(max_threads, len(os.sched_getaffinity(0))))
+    parts = np.array_split(idx, threads)
+    log(f"cpu baseline: the same over {threads} threads")
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        outs = list(ex.map(lambda part: oracle.sweep_at_tables(2, 2, h, lags, part), parts))
+    dtn = time.perf_counter() - t0
+    if not np.array_equal(np.concatenate(outs), ref):
+        raise RuntimeError("threaded oracle sweep differs from the single-threaded one")
+    del lags
+    # C1: the whole small run, oracle and GPU
+    t0 = time.perf_counter()
+    best_o, _, _ = oracle.feasible_triplet(2, 2, 6, 200, 1)
+    c1_oracle = time.perf_counter() - t0
+    L = pk.Lcsb(2, 2, 6, "f64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.init_zero()
+    _, best_g, _, _ = L.run(1, max_sweeps=200)
+    torch.cuda.synchronize()
+    c1_gpu = time.perf_counter() - t0
+    if best_g["bound"] != best_o["bound"]:
+        raise RuntimeError("C1: GPU and oracle best bounds differ")
+    return {"value": count / dtn, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one sweep at {count} entries (every {n // count}th index) of the "
-                      f"sigma=d=2, l={h} table, FP32 ring read as FP64, single thread, "
-                      f"{dt:.1f} s"}
+                      f"sigma=d=2, l={h} table, FP32 ring read as FP64, {threads} threads over "
+                      f"contiguous index ranges ({dtn:.2f} s); one thread: {dt1:.1f} s",
+            "single_thread_value": count / dt1,
+            "host": host_description(),
+            "c1_sigma2_d2_l6_200_sweeps_certified_each": {
+                "oracle_s": round(c1_oracle, 4), "gpu_s": round(c1_gpu, 4),
+                "best_bound": best_o["bound"]}}
 
 
 # Certification policy shared by every time-to-bound run (none uses B):
@@ -142,15 +201,16 @@ POLISH_CADENCE = 8    # then a certificate every this many FP64 sweeps
 MAX_SWEEPS = 1600
 
 
-def fp32_until_floor(S):
+def fp32_until_floor(S, certificate="feasible"):
     """FP32 sweeps with a certificate every TTB_CADENCE sweeps until the best
     bound is positive and gains less than SWITCH_GAIN over one period (the
     FP32 error floor), as one lcsb_run.  Returns (cur, best, certificates)."""
-    cur, best, certs, _ = S.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, min_gain=SWITCH_GAIN)
+    cur, best, certs, _ = S.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, min_gain=SWITCH_GAIN,
+                                certificate=certificate)
     return cur, best, certs
 
 
-def polish(P, S, best, target):
+def polish(P, S, best, target, certificate="feasible"):
     """Upcast the FP32 ring into P and continue in FP64 (first certificate
     after POLISH_FIRST sweeps, then every POLISH_CADENCE) until the best
     certified bound reaches target.  Returns (FP64 sweeps, certificates, best)."""
@@ -159,8 +219,52 @@ def polish(P, S, best, target):
     P.upcast(S)  # the best certificate of the FP32 run moves over
     start = P.status()[0]
     _, best, certs, _ = P.run(POLISH_CADENCE, first=POLISH_FIRST, max_sweeps=MAX_SWEEPS,
-                              target=target)
+                              target=target, certificate=certificate)
     return P.status()[0] - start, certs, best
+
+
+def plain_run(pk, h, target, iteration="ring", certificate="feasible", sigma=2, d=2):
+    """FP64 from zero, a certificate every TTB_CADENCE sweeps, until the best
+    bound reaches target (one lcsb_run, timed from the init call)."""
+    import torch
+    P = pk.Lcsb(sigma, d, h, "f64", iteration=iteration)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.init_zero()
+    cur, best, certs, _ = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, target=target,
+                                certificate=certificate)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"seconds": round(dt, 4), "sweeps": cur["sweep"], "certificates": certs,
+           "bound": best["bound"], "reached": best["bound"] >= target,
+           "iteration": iteration, "certificate": certificate}
+    del P
+    torch.cuda.empty_cache()
+    return out
+
+
+def mixed_run(pk, h, target, iteration="ring", certificate="feasible", sigma=2, d=2):
+    """FP32 from zero to its error floor, then the FP64 polish to target, the
+    FP32 tables inside the FP64 buffers (widened in place)."""
+    import torch
+    P = pk.Lcsb(sigma, d, h, "f64", iteration=iteration)
+    M = pk.Lcsb(sigma, d, h, "f32", iteration=iteration,
+                bufs=[b.view(torch.float32) for b in P.bufs])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M.init_zero()
+    cur, best, certs32 = fp32_until_floor(M, certificate)
+    sweeps32 = cur["sweep"]
+    sweeps64, certs64, best = polish(P, M, best, target, certificate)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"seconds": round(dt, 4), "sweeps_f32": sweeps32, "sweeps_f64": sweeps64,
+           "certificates": certs32 + certs64, "bound": best["bound"],
+           "reached": best["bound"] >= target, "iteration": iteration,
+           "certificate": certificate}
+    del P, M
+    torch.cuda.empty_cache()
+    return out
 
 
 def algorithmic_bytes(L, elem):
@@ -303,11 +407,26 @@ def time_to_bound(pk, h, train_steps=1000):
     out["mixed_learned"] = learned_run(pk, h, P, target, train_steps)
     ml = out["mixed_learned"]
     ml.update(hbm(ml["sweeps_f32"], ml["sweeps_f64"], ml["seconds"]))
+    del P
+    torch.cuda.empty_cache()
+    # the same runs with the largest-r certificate, on the ring and on the
+    # two-array iteration
+    for name, fn, it in (("plain_f64_optimal", plain_run, "ring"),
+                         ("mixed_f32_polish_optimal", mixed_run, "ring"),
+                         ("two_array_f64_optimal", plain_run, "two_array"),
+                         ("two_array_mixed_optimal", mixed_run, "two_array")):
+        r = fn(pk, h, target, iteration=it, certificate="optimal")
+        r.update(hbm(r.get("sweeps_f32", 0), r.get("sweeps_f64", r.get("sweeps", 0)),
+                     r["seconds"]))
+        out[name] = r
+        log(f"time to bound, {name}: {r['seconds']:.3f} s, bound {r['bound']:.12f}")
     out["policy"] = {"certificate_every": TTB_CADENCE, "switch_gain": SWITCH_GAIN,
                      "polish_first": POLISH_FIRST, "polish_every": POLISH_CADENCE,
                      "driver": "lcsb_run"}
-    del P
-    torch.cuda.empty_cache()
+    runs = {k: v for k, v in out.items() if isinstance(v, dict) and "seconds" in v}
+    fastest = min(runs, key=lambda k: runs[k]["seconds"])
+    out["fastest"] = {"run": fastest, "seconds": runs[fastest]["seconds"],
+                      "vs_plain_f64": round(runs["plain_f64"]["seconds"] / runs[fastest]["seconds"], 3)}
     return out
 
 
@@ -385,7 +504,7 @@ def config_table(pk):
         L.init_zero()
         L.iterate(8)
         stream = torch.cuda.current_stream()
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         reps = 16
         e[0].record(stream)
         L.iterate(reps)
@@ -393,15 +512,20 @@ def config_table(pk):
         e[2].record(stream)
         L.certify()
         e[3].record(stream)
+        e[4].record(stream)
+        L.certify_optimal()
+        e[5].record(stream)
         torch.cuda.synchronize()
         sweep_ms = e[0].elapsed_time(e[1]) / reps
         cert_ms = e[2].elapsed_time(e[3])
+        opt_ms = e[4].elapsed_time(e[5])
         elem = 8 if dt == "f64" else 4
         folded = L.swap_symmetric()  # exchange-folded: every table at one entry per pair
         algo = (d + 1) * elem * L.stored // (2 if folded else 1)
         rows.append({"sigma": sigma, "d": d, "l": h, "dtype": dt, "entries": L.n,
                      "exchange_folded": folded,
                      "sweep_ms": round(sweep_ms, 4), "certificate_ms": round(cert_ms, 3),
+                     "optimal_certificate_ms": round(opt_ms, 3),
                      "algorithmic_GBps": round(algo / sweep_ms / 1e6, 1),
                      "frac_of_peak": round(algo / sweep_ms / 1e6 / HBM_PEAK_GBS, 4),
                      "updates_per_s": L.n / sweep_ms * 1e3})
@@ -520,15 +644,18 @@ def converge_only(pk, h, sigma=2, d=2):
 
 
 def certify_only(pk, h, sigma=2, d=2, dtype="f32"):
-    """8 sweeps from zero at (sigma, d, l = h), then two certificates."""
+    """8 sweeps from zero at (sigma, d, l = h), then two certificates of each
+    kind (Algorithm 2's, the largest-r one)."""
     import torch
     L = pk.Lcsb(sigma, d, h, dtype)
     L.init_zero()
     L.iterate(8)
     L.certify()
     L.certify()
+    L.certify_optimal()
+    L.certify_optimal()
     torch.cuda.synchronize()
-    log(f"two certificates at sigma={sigma} d={d} l={h} {dtype}")
+    log(f"two certificates of each kind at sigma={sigma} d={d} l={h} {dtype}")
 
 
 def copy_only(gib):
@@ -578,7 +705,7 @@ def main():
     log(f"warmup: {args.warmup} steps of {cad} sweeps + 1 certificate at l={h}")
     for _ in range(args.warmup):
         L.iterate(cad)
-        L.certify()
+        L.certify_optimal()
     torch.cuda.synchronize()
     sweep_ms = []
     t0 = time.perf_counter()
@@ -588,7 +715,7 @@ def main():
         e0.record(stream)
         L.iterate(cad)
         e1.record(stream)
-        cur, best = L.certify()
+        cur, best = L.certify_optimal()
         sweep_ms.append(e0.elapsed_time(e1) / cad)
         log(f"step {s}: sweep {sweep_ms[-1]:.3f} ms, bound {cur['bound']:.9f}")
     torch.cuda.synchronize()
@@ -619,7 +746,7 @@ def main():
         ttb = time_to_bound(pk, h, args.train_steps)
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(h, args.cpu_sample_log2)
+        cpu = cpu_baseline(pk, h, args.cpu_sample_log2)
 
     line = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
@@ -629,7 +756,7 @@ def main():
         "config": {"workload": f"sigma=2 d=2 l={h}: {n} table indices ({n // 2} stored, "
                                f"complement-folded; exchange-symmetric ring, one tuple of "
                                f"each exchanged pair computed and stored), FP32 renormalised sweeps, "
-                               f"FP64 round-down certificate every {cad} sweeps",
+                               f"FP64 round-down largest-r certificate (one pass) every {cad} sweeps",
                    "sweeps_per_step": cad, "entries": n, "stored_entries": n // 2},
         "roofline": roofline,
         "fp64_sweep": fp64,

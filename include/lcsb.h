@@ -91,13 +91,37 @@ typedef struct {
 #define LCSB_CERT_FEASIBLE 0 /* Algorithm 2: R from the last step, then E     */
 #define LCSB_CERT_OPTIMAL  1 /* the largest r with E = 0 for the table        */
 
-/* Create a context for (sigma, d, l = h) and a table element type.
- * GPU kernels exist for (sigma, d) in {(2,2), (4,2), (2,3)} and both element
- * types; other pairs give LCSB_EUNSUPPORTED.  h >= 1 and sigma^(d h) <= 2^34
- * (else LCSB_EINVAL).  *out receives a host object owned by the library. */
+/* iterations a context can run */
+#define LCSB_ITER_RING      0 /* Algorithm 2: a ring of d + 1 tables            */
+#define LCSB_ITER_TWO_ARRAY 1 /* two tables and a rate (lcsb_create_iter)       */
+
+/* Create a context for (sigma, d, l = h) and a table element type running
+ * the ring iteration of Algorithm 2.  GPU kernels exist for (sigma, d) in
+ * {(2,2), (4,2), (2,3)} and both element types; other pairs give
+ * LCSB_EUNSUPPORTED.  h >= 1 and sigma^(d h) <= 2^34 (else LCSB_EINVAL).
+ * *out receives a host object owned by the library. */
 int lcsb_create(int sigma, int d, int h, int dtype, lcsb_ctx **out);
 
-/* Sizes the caller must allocate: nbuf = d + 1 ring tables of bytes_per_buf
+/* As lcsb_create, choosing the iteration.  LCSB_ITER_TWO_ARRAY is this
+ * library's reading of the remark of Sec. 3.3 that the recurrence runs on
+ * two arrays: the context keeps the newest table u (lag 1), the table before
+ * it (lag 2) and a rate R, and one sweep is
+ *     u_new = F(u, u - R, .., u - (d-1) R)                 (eq. (4))
+ * with the shift added to each branch mean (a branch moving k >= 2 strings
+ * gives mean_z(u) - (k-1) R; in LCSB_F64 that sum is rounded to nearest, in
+ * LCSB_F32 the FP32 offset mechanism of lcsb_iterate carries it).  R of the
+ * next sweep is the mean of u_new - u over the fixed sample of 4096 stored
+ * coordinates c_i = (i * 0x9E3779B97F4A7C15 mod 2^64) mod (n / sigma), as a
+ * balanced binary tree over i in order, divided by 4096 (FP32: plus the
+ * difference of the two offsets).  At the limit every coordinate grows by the
+ * same r, so the two iterations share their fixed points and certified
+ * bounds; the two-array one needs 2 tables instead of d + 1 (nbuf = 2) and
+ * every certificate works on it unchanged (Algorithm 2's with prev = lag 2).
+ * lcsb_load_ring, lcsb_lag, lcsb_save and lcsb_load then handle 2 tables. */
+int lcsb_create_iter(int sigma, int d, int h, int dtype, int iteration, lcsb_ctx **out);
+
+/* Sizes the caller must allocate: nbuf = d + 1 ring tables (2 for the
+ * two-array iteration) of bytes_per_buf
  * bytes each (entries = sigma^(d h - 1) stored elements, see folded storage),
  * and one device workspace of workspace_bytes bytes, 256-byte aligned.  Any
  * output pointer may be NULL. */
@@ -116,7 +140,8 @@ int lcsb_bind(lcsb_ctx *ctx, void *const *dev_bufs, int nbuf, void *dev_workspac
  * and the initial triplet (v_0, 0, 0). */
 int lcsb_init_zero(lcsb_ctx *ctx);
 
-/* Set lag k (k = 1..d) to the caller's device table src[k-1]: the ring's
+/* Set lag k (k = 1..d; 1..2 for the two-array iteration, which then takes
+ * its rate from the two tables) to the caller's device table src[k-1]: the ring's
  * element type, aligned to it, at least `entries` elements (a full table of
  * sigma^(d h) values may be passed), not aliasing a ring buffer.  Its first
  * `entries` values are copied: every other index takes the value of its image
@@ -170,7 +195,7 @@ int lcsb_certify(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
  * rho = R - E wins). */
 int lcsb_certify_optimal(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
 
-/* Device address of lag k (1..d) and, for LCSB_F32, the FP64 offset its
+/* Device address of lag k (1..d; 1..2 for the two-array iteration) and, for LCSB_F32, the FP64 offset its
  * values are relative to (read from the device; synchronises).  The pointer
  * stays valid until the next lcsb_iterate, lcsb_load_ring or lcsb_bind.  On
  * an exchange-symmetric ring (lcsb_swap_symmetric) sweeps write only one
@@ -194,6 +219,11 @@ int lcsb_swap_symmetric(const lcsb_ctx *ctx, int *symmetric);
 /* Number of sweeps applied since the last init, and the best certificate. */
 int lcsb_status(const lcsb_ctx *ctx, int64_t *sweeps, lcsb_cert *best);
 
+/* Two-array iteration only: the rate R the next sweep uses (see
+ * lcsb_create_iter; absolute, offsets included).  Synchronises.  LCSB_EINVAL
+ * for a ring context. */
+int lcsb_rate(const lcsb_ctx *ctx, double *rate);
+
 /* Stop rule and certificate cadence of a run (Algorithm 2's loop with its
  * certificate taken every `cadence` sweeps instead of every sweep). */
 typedef struct {
@@ -203,12 +233,17 @@ typedef struct {
                             this call (the last period may pass it), >= 0     */
     double target;       /* stop once best.bound >= target; NaN = no target    */
     double stop_delta;   /* stop once two consecutive certificates differ by
-                            less than this and the newer is >= best; 0 = off  */
+                            less than this, the newer is >= best and the best
+                            bound is positive; 0 = off                        */
     double min_gain;     /* stop once a positive best bound gained less than
                             this over one period (an FP32 run at its error
                             floor); 0 = off                                   */
     int64_t certificate; /* LCSB_CERT_FEASIBLE (lcsb_certify) or
                             LCSB_CERT_OPTIMAL (lcsb_certify_optimal)          */
+    const char *log_path;/* NULL, or a file that gets one JSON line appended
+                            per certificate: sweep, kind, R, E, maxW, rho,
+                            bound, best_bound, nonfinite, seconds since the
+                            call began (LCSB_EINVAL if it cannot be opened)  */
 } lcsb_run_policy;
 
 #define LCSB_STOP_MAX_SWEEPS 0  /* max_sweeps reached                          */
@@ -238,7 +273,8 @@ int lcsb_run(lcsb_ctx *ctx, const lcsb_run_policy *p, lcsb_cert *cur, lcsb_cert 
  * workspace, gives LCSB_EINVAL. */
 int lcsb_upcast(const lcsb_ctx *src_f32, lcsb_ctx *dst_f64);
 
-/* Write the ring to `path`: the stored entries of lag 1 .. d, the FP32
+/* Write the ring to `path`: the stored entries of lag 1 .. d (1 .. 2 for the
+ * two-array iteration, whose rate is recomputed from them on load), the FP32
  * offsets, the sweep count and the best certificate, with a hash of every
  * table and of the header.  The file is written as `path`.part and renamed
  * over `path` once complete, so an interrupted save leaves an earlier

@@ -91,6 +91,8 @@ def lib():
         L.or_brute_W.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P(C.c_int), P(C.c_uint64)]
         L.or_two_array_step.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double), C.c_double,
                                         P(C.c_double)]
+        L.or_two_array_step_at.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double), C.c_double,
+                                           P(C.c_uint64), C.c_uint64, P(C.c_double)]
         L.or_sample_growth.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double), P(C.c_double),
                                        P(C.c_double)]
         L.or_sample_coordinates.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_uint64)]
@@ -276,6 +278,17 @@ def two_array_step(sigma, d, h, u, R):
     u = _f64(u)
     out = np.empty(u.size, dtype=np.float64)
     _check(lib().or_two_array_step(sigma, d, h, _dptr(u), float(R), _dptr(out)), "two_array_step")
+    return out
+
+
+def two_array_step_at(sigma, d, h, u, R, idx):
+    """two_array_step at the coordinates idx only."""
+    u = _f64(u)
+    idx = np.ascontiguousarray(idx, dtype=np.uint64)
+    out = np.empty(idx.size, dtype=np.float64)
+    _check(lib().or_two_array_step_at(sigma, d, h, _dptr(u), float(R),
+                                      idx.ctypes.data_as(C.POINTER(C.c_uint64)), idx.size,
+                                      _dptr(out)), "two_array_step_at")
     return out
 
 

@@ -675,6 +675,29 @@ int or_two_array_step(int sigma, int d, int h, const double *u, double R, double
     return 0;
 }
 
+/* the same step at a list of coordinates only (sampled checks) */
+int or_two_array_step_at(int sigma, int d, int h, const double *u, double R,
+                         const uint64_t *idx, uint64_t count, double *out)
+{
+    or_shape s;
+    if (shape_init(&s, sigma, d, h)) return -1;
+    const void *lag[OR_MAX_D + 1];
+    double delta[OR_MAX_D + 1];
+    lag[0] = NULL;
+    delta[0] = delta[1] = 0.0;
+    for (int k = 1; k <= d; ++k) lag[k] = u;
+    for (int k = 2; k <= d; ++k) delta[k] = -((double)(k - 1) * R);
+    or_args a = {lag, 0, NULL, delta};
+    or_scratch w;
+    if (scratch_alloc(&s, &w)) { scratch_free(&w); return -2; }
+    for (uint64_t i = 0; i < count; ++i) {
+        if (idx[i] >= s.n_entries) { scratch_free(&w); return -1; }
+        out[i] = F_at(&s, &a, idx[i], w.buf, w.sym, w.work);
+    }
+    scratch_free(&w);
+    return 0;
+}
+
 /* the rate of the next step: mean of u_new - u over the sample */
 int or_sample_growth(int sigma, int d, int h, const double *u_new, const double *u, double *R)
 {

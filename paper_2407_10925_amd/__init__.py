@@ -30,11 +30,12 @@ class Lcsb:
     """
 
     def __init__(self, sigma: int, d: int, h: int, dtype: str = "f64", device=None,
-                 bufs=None):
+                 bufs=None, iteration: str = "ring"):
         """``bufs``: optional ring buffers to bind instead of allocating, d + 1
-        contiguous device tensors of at least the ring's bytes each (for an FP32
-        ring inside an FP64 ring's memory, ``[b.view(torch.float32) for b in
-        P.bufs]``; see :meth:`upcast`)."""
+        (2 for the two-array iteration) contiguous device tensors of at least
+        the ring's bytes each (for an FP32 ring inside an FP64 ring's memory,
+        ``[b.view(torch.float32) for b in P.bufs]``; see :meth:`upcast`).
+        ``iteration``: "ring" (Algorithm 2) or "two_array" (lcsb_create_iter)."""
         import torch
 
         if dtype not in _DTYPES:
@@ -48,7 +49,10 @@ class Lcsb:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self._lib = lib
         ctx = C.c_void_p()
-        check(lib.lcsb_create(sigma, d, h, _DTYPES[dtype], C.byref(ctx)))
+        self.iteration = iteration
+        check(lib.lcsb_create_iter(sigma, d, h, _DTYPES[dtype], _capi.ITERATIONS[iteration],
+                                   C.byref(ctx)))
+        self.lags = 2 if iteration == "two_array" else d
         self._ctx = ctx
         nbuf, n, bpb, wsb = C.c_int(), C.c_uint64(), C.c_uint64(), C.c_uint64()
         check(lib.lcsb_query(ctx, C.byref(nbuf), C.byref(n), C.byref(bpb), C.byref(wsb)))
@@ -79,18 +83,18 @@ class Lcsb:
     def load_ring(self, tables, offsets=None):
         """tables[k-1] = lag k: device tensors of the ring's dtype holding all n
         indices or only the stored ones (the first ``stored`` values are used)."""
-        if len(tables) != self.d:
-            raise ValueError(f"need {self.d} tables")
+        if len(tables) != self.lags:
+            raise ValueError(f"need {self.lags} tables")
         for t in tables:
             if t.dtype != self.torch_dtype or t.numel() not in (self.n, self.stored) \
                     or not t.is_contiguous() or t.device != self.device:
                 raise ValueError("table dtype, size, layout or device does not match the ring")
         self._keep = list(tables)
-        ptrs = (C.c_void_p * self.d)(*[t.data_ptr() for t in tables])
+        ptrs = (C.c_void_p * self.lags)(*[t.data_ptr() for t in tables])
         offs = None
         if offsets is not None:
-            offs = (C.c_double * self.d)(*[float(o) for o in offsets])
-        check(self._lib.lcsb_load_ring(self._ctx, ptrs, self.d, offs))
+            offs = (C.c_double * self.lags)(*[float(o) for o in offsets])
+        check(self._lib.lcsb_load_ring(self._ctx, ptrs, self.lags, offs))
 
     def iterate(self, k: int = 1):
         check(self._lib.lcsb_iterate(self._ctx, int(k)))
@@ -115,16 +119,18 @@ class Lcsb:
 
     def run(self, cadence: int, first: int = 0, max_sweeps: int = 1 << 40,
             target: float = float("nan"), stop_delta: float = 0.0, min_gain: float = 0.0,
-            certificate: str = "feasible"):
+            certificate: str = "feasible", log: str = None):
         """lcsb_run: sweep and certify every `cadence` sweeps (the first
         certificate after `first`) until the best bound reaches `target`,
         consecutive certificates move by less than `stop_delta`, a positive
         best bound gains less than `min_gain` in a period, or `max_sweeps`.
         `certificate`: "feasible" (Algorithm 2, lcsb_certify) or "optimal"
-        (lcsb_certify_optimal).  Returns (current, best, certificates, reason)."""
+        (lcsb_certify_optimal).  `log`: a file that gets one JSON line per
+        certificate.  Returns (current, best, certificates, reason)."""
         pol = _capi.RunPolicy(int(cadence), int(first), int(max_sweeps), float(target),
                               float(stop_delta), float(min_gain),
-                              _capi.CERT_KINDS[certificate])
+                              _capi.CERT_KINDS[certificate],
+                              None if log is None else str(log).encode())
         cur, best, certs, why = Cert(), Cert(), C.c_int64(), C.c_int()
         check(self._lib.lcsb_run(self._ctx, C.byref(pol), C.byref(cur), C.byref(best),
                                  C.byref(certs), C.byref(why)))
@@ -139,6 +145,12 @@ class Lcsb:
             if b.data_ptr() == p.value:
                 return b, off.value
         raise RuntimeError("lag pointer does not match a ring buffer")
+
+    def rate(self) -> float:
+        """The rate R the next two-array sweep uses (synchronises)."""
+        r = C.c_double()
+        check(self._lib.lcsb_rate(self._ctx, C.byref(r)))
+        return r.value
 
     def status(self):
         s, best = C.c_int64(), Cert()

@@ -31,6 +31,9 @@ class LcsbError(RuntimeError):
 
 
 LCSB_STOP_NAMES = {0: "max_sweeps", 1: "target", 2: "converged", 3: "floor"}
+LCSB_ITER_RING = 0
+LCSB_ITER_TWO_ARRAY = 1
+ITERATIONS = {"ring": LCSB_ITER_RING, "two_array": LCSB_ITER_TWO_ARRAY}
 LCSB_CERT_FEASIBLE = 0
 LCSB_CERT_OPTIMAL = 1
 CERT_KINDS = {"feasible": LCSB_CERT_FEASIBLE, "optimal": LCSB_CERT_OPTIMAL}
@@ -39,7 +42,7 @@ CERT_KINDS = {"feasible": LCSB_CERT_FEASIBLE, "optimal": LCSB_CERT_OPTIMAL}
 class RunPolicy(C.Structure):
     _fields_ = [("cadence", C.c_int64), ("first", C.c_int64), ("max_sweeps", C.c_int64),
                 ("target", C.c_double), ("stop_delta", C.c_double), ("min_gain", C.c_double),
-                ("certificate", C.c_int64)]
+                ("certificate", C.c_int64), ("log_path", C.c_char_p)]
 
 
 class Cert(C.Structure):
@@ -67,6 +70,8 @@ def load():
     L.lcsb_last_error.restype = C.c_char_p
     L.lcsb_last_error.argtypes = []
     L.lcsb_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(P)]
+    L.lcsb_create_iter.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(P)]
+    L.lcsb_rate.argtypes = [P, C.POINTER(C.c_double)]
     L.lcsb_query.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                              C.POINTER(C.c_uint64)]
     L.lcsb_bind.argtypes = [P, C.POINTER(P), C.c_int, P, P]
@@ -94,7 +99,7 @@ def load():
     L.lcsb_mlp_adam.argtypes = [P, P, P, P, P, C.c_float, C.c_float, C.c_float, C.c_float,
                                 C.c_int64, P]
     L.lcsb_init_seed_mlp.argtypes = [P, P, P, C.c_double]
-    for name in ("lcsb_create", "lcsb_query", "lcsb_bind", "lcsb_init_zero", "lcsb_load_ring",
+    for name in ("lcsb_create", "lcsb_create_iter", "lcsb_rate", "lcsb_query", "lcsb_bind", "lcsb_init_zero", "lcsb_load_ring",
                  "lcsb_iterate", "lcsb_certify", "lcsb_certify_optimal", "lcsb_lag", "lcsb_status", "lcsb_swap_symmetric",
                  "lcsb_upcast",
                  "lcsb_run", "lcsb_save", "lcsb_load", "lcsb_destroy", "lcsb_mlp_workspace", "lcsb_mlp_init", "lcsb_mlp_to_bf16",

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #include <algorithm>
 #include <cstddef>
@@ -50,6 +51,8 @@ struct lcsb_ctx {
     lcsb_cert best;
     int swap_sym;    // sigma = d = 2, l >= 2: lag 1 .. d symmetric in the two strings
     int lazy[4];     // per slot: only the lower index of each exchanged pair written
+    int two_array;   // LCSB_ITER_TWO_ARRAY: tables u (lag 1) and the one before (lag 2), rate R
+    int lags;        // tables the context keeps: d for the ring, 2 for the two-array iteration
 };
 
 namespace {
@@ -101,7 +104,7 @@ int refresh_swap(lcsb_ctx *c)
     uint32_t *flag = reinterpret_cast<uint32_t *>(c->ws + Ws::kAsym);
     hipError_t e;
     if ((e = launch_fill_zero(flag, 4, c->stream)) != hipSuccess) return hip_fail(c, e, "fill");
-    for (int k = 1; k <= c->g.d; ++k)
+    for (int k = 1; k <= c->lags; ++k)
         if ((e = launch_check_swap(c->g, c->dtype, c->buf[slot_of_lag(c, k)], flag, c->stream)) !=
             hipSuccess)
             return hip_fail(c, e, "symmetry check");
@@ -110,6 +113,17 @@ int refresh_swap(lcsb_ctx *c)
         return hip_fail(c, e, "symmetry copy");
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "symmetry sync");
     c->swap_sym = host == 0;
+    return LCSB_OK;
+}
+
+// Two-array iteration: the rate of the next step from lag 1 and lag 2 (stream order).
+int refresh_rate(lcsb_ctx *c)
+{
+    if (!c->two_array) return LCSB_OK;
+    const int s1 = slot_of_lag(c, 1), s2 = slot_of_lag(c, 2);
+    hipError_t e = launch_two_array_rate(c->g, c->dtype, c->buf[s1], c->buf[s2], s1, s2,
+                                         c->swap_sym, c->ws, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "rate");
     return LCSB_OK;
 }
 
@@ -128,9 +142,16 @@ const char *lcsb_last_error(void) { return g_err.c_str(); }
 
 int lcsb_create(int sigma, int d, int h, int dtype, lcsb_ctx **out)
 {
+    return lcsb_create_iter(sigma, d, h, dtype, LCSB_ITER_RING, out);
+}
+
+int lcsb_create_iter(int sigma, int d, int h, int dtype, int iteration, lcsb_ctx **out)
+{
     if (!out) return fail(LCSB_EINVAL, "out is null");
     *out = nullptr;
     if (dtype != LCSB_F64 && dtype != LCSB_F32) return fail(LCSB_EINVAL, "dtype %d", dtype);
+    if (iteration != LCSB_ITER_RING && iteration != LCSB_ITER_TWO_ARRAY)
+        return fail(LCSB_EINVAL, "iteration %d", iteration);
     if (sigma < 2 || d < 1 || h < 1) return fail(LCSB_EINVAL, "sigma=%d d=%d h=%d", sigma, d, h);
     const bool ok = (sigma == 2 && d == 2) || (sigma == 4 && d == 2) || (sigma == 2 && d == 3);
     if (!ok) return fail(LCSB_EUNSUPPORTED, "no GPU kernel for sigma=%d d=%d", sigma, d);
@@ -148,7 +169,9 @@ int lcsb_create(int sigma, int d, int h, int dtype, lcsb_ctx **out)
     c->g.n = 1ull << bits;
     c->g.ns = c->g.n >> beta;
     c->dtype = dtype;
-    c->nbuf = d + 1;
+    c->two_array = iteration == LCSB_ITER_TWO_ARRAY;
+    c->nbuf = c->two_array ? 2 : d + 1;
+    c->lags = c->two_array ? 2 : d;
     c->state = kCreated;
     c->best = initial_best();
     *out = c;
@@ -207,6 +230,8 @@ int lcsb_init_zero(lcsb_ctx *c)
     c->best = initial_best();
     c->swap_sym = swap_shape(c);
     clear_lazy(c);
+    int rc = refresh_rate(c);
+    if (rc) return rc;
     c->state = kReady;
     return LCSB_OK;
 }
@@ -216,7 +241,7 @@ int lcsb_load_ring(lcsb_ctx *c, const void *const *src, int nsrc, const double *
     if (!c) return fail(LCSB_EINVAL, "null context");
     if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
     if (c->state < kBound) return fail(LCSB_ESTATE, "bind before load");
-    if (!src || nsrc != c->g.d) return fail(LCSB_EINVAL, "need d = %d source tables", c->g.d);
+    if (!src || nsrc != c->lags) return fail(LCSB_EINVAL, "need %d source tables", c->lags);
     for (int k = 0; k < nsrc; ++k) {
         if (!src[k] || ((uintptr_t)src[k] & (elem_size(c->dtype) - 1)))
             return fail(LCSB_EINVAL, "source %d null or not aligned to its element", k);
@@ -227,7 +252,7 @@ int lcsb_load_ring(lcsb_ctx *c, const void *const *src, int nsrc, const double *
     if ((e = launch_fill_zero(c->ws, Ws::kBytes, c->stream)) != hipSuccess)
         return hip_fail(c, e, "fill workspace");
     c->head = 0;
-    for (int k = 1; k <= c->g.d; ++k) {
+    for (int k = 1; k <= c->lags; ++k) {
         const int slot = slot_of_lag(c, k);
         if ((e = launch_copy(src[k - 1], c->buf[slot], c->g.ns * elem_size(c->dtype), c->stream)) !=
             hipSuccess)
@@ -243,6 +268,7 @@ int lcsb_load_ring(lcsb_ctx *c, const void *const *src, int nsrc, const double *
     c->best = initial_best();
     int rc = refresh_swap(c);
     if (rc) return rc;
+    if ((rc = refresh_rate(c))) return rc;
     c->state = kReady;
     return LCSB_OK;
 }
@@ -255,9 +281,20 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
     for (int64_t t = 0; t < k; ++t) {
         SweepLaunch a;
         memset(&a, 0, sizeof a);
-        for (int j = 1; j <= c->g.d; ++j) {
-            a.lag_slot[j - 1] = slot_of_lag(c, j);
-            a.lag[j - 1] = c->buf[a.lag_slot[j - 1]];
+        if (c->two_array) {
+            // every argument is u; lag k is read relative to offsets slot
+            // kSlotLag2/3, which the rate pass set to u's offset - (k-1) R (FP32)
+            // or -(k-1) R against the zero slot (FP64)
+            for (int j = 0; j < c->g.d; ++j) a.lag[j] = c->buf[c->head];
+            a.lag_slot[0] = c->dtype == LCSB_F32 ? c->head : Ws::kSlotZero;
+            a.lag_slot[1] = Ws::kSlotLag2;
+            a.lag_slot[2] = Ws::kSlotLag3;
+            a.shift = 1;
+        } else {
+            for (int j = 1; j <= c->g.d; ++j) {
+                a.lag_slot[j - 1] = slot_of_lag(c, j);
+                a.lag[j - 1] = c->buf[a.lag_slot[j - 1]];
+            }
         }
         a.new_slot = (c->head + 1) % c->nbuf;
         a.out = c->buf[a.new_slot];
@@ -268,6 +305,7 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
         c->lazy[a.new_slot] = c->swap_sym;
         c->head = a.new_slot;
         c->sweeps++;
+        if ((rc = refresh_rate(c))) return rc;
     }
     return LCSB_OK;
 }
@@ -347,7 +385,7 @@ int lcsb_lag(const lcsb_ctx *c, int k, void **dev_ptr, double *offset)
 {
     int rc = need_ready(c);
     if (rc) return rc;
-    if (k < 1 || k > c->g.d) return fail(LCSB_EINVAL, "lag %d outside 1..%d", k, c->g.d);
+    if (k < 1 || k > c->lags) return fail(LCSB_EINVAL, "lag %d outside 1..%d", k, c->lags);
     const int slot = slot_of_lag(c, k);
     // the caller may read any stored entry: complete a lazily written table
     // (its values do not change, so the context stays logically const)
@@ -374,6 +412,18 @@ int lcsb_swap_symmetric(const lcsb_ctx *c, int *symmetric)
     return LCSB_OK;
 }
 
+int lcsb_rate(const lcsb_ctx *c, double *rate)
+{
+    int rc = need_ready(c);
+    if (rc) return rc;
+    if (!rate) return fail(LCSB_EINVAL, "null output");
+    if (!c->two_array) return fail(LCSB_EINVAL, "the ring iteration keeps no rate");
+    hipError_t e = hipMemcpyAsync(rate, c->ws + Ws::kRate, 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(LCSB_EHIP, "rate read: %s", hipGetErrorString(e));
+    return LCSB_OK;
+}
+
 int lcsb_status(const lcsb_ctx *c, int64_t *sweeps, lcsb_cert *best)
 {
     if (!c) return fail(LCSB_EINVAL, "null context");
@@ -394,6 +444,15 @@ int lcsb_run(lcsb_ctx *c, const lcsb_run_policy *p, lcsb_cert *cur_out, lcsb_cer
         return fail(LCSB_EINVAL, "policy: cadence > 0, first >= 0, max_sweeps >= 0, "
                                  "stop_delta >= 0, min_gain >= 0 and a known certificate "
                                  "kind required");
+    FILE *log = nullptr;
+    if (p->log_path && !(log = fopen(p->log_path, "a")))
+        return fail(LCSB_EINVAL, "cannot open the certificate log %s", p->log_path);
+    struct Closer {
+        FILE *f;
+        ~Closer() { if (f) fclose(f); }
+    } closer{log};
+    timespec t_start;
+    clock_gettime(CLOCK_MONOTONIC, &t_start);
     const bool use_target = !isnan(p->target);
     int64_t certs = 0;
     int why = LCSB_STOP_MAX_SWEEPS;
@@ -411,6 +470,20 @@ int lcsb_run(lcsb_ctx *c, const lcsb_run_policy *p, lcsb_cert *cur_out, lcsb_cer
             rc = p->certificate == LCSB_CERT_OPTIMAL ? lcsb_certify_optimal(c, &cur, &best)
                                                      : lcsb_certify(c, &cur, &best);
             ++certs;
+            if (log) {
+                timespec t;
+                clock_gettime(CLOCK_MONOTONIC, &t);
+                const double secs = (double)(t.tv_sec - t_start.tv_sec) +
+                                    1e-9 * (double)(t.tv_nsec - t_start.tv_nsec);
+                fprintf(log,
+                        "{\"sweep\": %lld, \"kind\": \"%s\", \"R\": %.17g, \"E\": %.17g, "
+                        "\"maxW\": %.17g, \"rho\": %.17g, \"bound\": %.17g, "
+                        "\"best_bound\": %.17g, \"nonfinite\": %llu, \"seconds\": %.6f}\n",
+                        (long long)cur.sweep, cur.kind == LCSB_CERT_OPTIMAL ? "optimal" : "feasible",
+                        cur.R, cur.E, cur.maxW, cur.rho, cur.bound, best.bound,
+                        (unsigned long long)cur.nonfinite, secs);
+                fflush(log);
+            }
             if (rc != LCSB_OK) {
                 if (cur_out) *cur_out = cur;
                 if (best_out) *best_out = best;
@@ -419,7 +492,7 @@ int lcsb_run(lcsb_ctx *c, const lcsb_run_policy *p, lcsb_cert *cur_out, lcsb_cer
             }
             if (use_target && best.bound >= p->target) { why = LCSB_STOP_TARGET; break; }
             if (p->stop_delta > 0.0 && have_prev && fabs(cur.bound - prev) < p->stop_delta &&
-                cur.bound >= best.bound) { why = LCSB_STOP_CONVERGED; break; }
+                cur.bound >= best.bound && best.bound > 0.0) { why = LCSB_STOP_CONVERGED; break; }
             if (p->min_gain > 0.0 && have_prev && best.bound > 0.0 &&
                 best.bound - best_prev < p->min_gain) { why = LCSB_STOP_FLOOR; break; }
             prev = cur.bound;
@@ -445,6 +518,8 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
         return fail(LCSB_EINVAL, "upcast goes from an FP32 to an FP64 context");
     if (src->g.sigma != dst->g.sigma || src->g.d != dst->g.d || src->g.h != dst->g.h)
         return fail(LCSB_EINVAL, "shape mismatch");
+    if (src->two_array != dst->two_array)
+        return fail(LCSB_EINVAL, "the two contexts run different iterations");
     // every destination slot is either the source slot's own buffer (widened
     // in place) or no source slot's buffer
     const bool inplace = dst->buf[0] == src->buf[0];
@@ -459,7 +534,7 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
     if ((e = launch_fill_zero(dst->ws, Ws::kBytes, dst->stream)) != hipSuccess)
         return hip_fail(dst, e, "fill workspace");
     dst->head = src->head;
-    for (int k = 1; k <= src->g.d; ++k) {
+    for (int k = 1; k <= src->lags; ++k) {
         const int slot = slot_of_lag(src, k);
         const double *off = reinterpret_cast<const double *>(src->ws + Ws::kOffsets) + slot;
         e = inplace ? launch_upcast_inplace(src->g, dst->buf[slot], off, dst->stream)
@@ -471,6 +546,7 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
     dst->best = src->best;
     dst->swap_sym = src->swap_sym;
     for (int k = 0; k < 4; ++k) dst->lazy[k] = src->lazy[k];  // same slots, converted as stored
+    if ((rc = refresh_rate(dst))) return rc;
     dst->state = kReady;
     return LCSB_OK;
 }
@@ -596,6 +672,7 @@ int lcsb_init_seed_mlp(lcsb_ctx *c, const float *params, const uint16_t *wbf16, 
     c->best = initial_best();
     c->swap_sym = c->g.d == 2 && swap_shape(c);  // one value per exchange orbit, written to every member
     clear_lazy(c);
+    if ((rc = refresh_rate(c))) return rc;
     c->state = kReady;
     return LCSB_OK;
 }
@@ -607,19 +684,20 @@ int lcsb_init_seed_mlp(lcsb_ctx *c, const float *params, const uint16_t *wbf16, 
 namespace {
 
 constexpr char kCkptMagic[8] = {'L', 'C', 'S', 'B', 'R', 'I', 'N', 'G'};
-constexpr uint32_t kCkptVersion = 1;
+constexpr uint32_t kCkptVersion = 2;
 constexpr size_t kStageBytes = size_t(64) << 20;  // pinned staging buffer
 
 struct CkptHeader {
     char magic[8];
     uint32_t version;
     int32_t sigma, d, h, dtype;
-    uint32_t pad;
+    int32_t iteration;  // LCSB_ITER_*
     uint64_t stored;
     int64_t sweeps;
     double bound, R, E, maxW, rho;
     int64_t best_sweep;
     uint64_t argmax_W, nonfinite;
+    int64_t best_kind;
     double offsets[3];
     uint64_t table_hash[3];
     uint64_t header_hash;  // of every byte before this field
@@ -685,12 +763,14 @@ int lcsb_save(const lcsb_ctx *c, const char *path)
     hd.bound = c->best.bound; hd.R = c->best.R; hd.E = c->best.E; hd.maxW = c->best.maxW;
     hd.rho = c->best.rho; hd.best_sweep = c->best.sweep;
     hd.argmax_W = c->best.argmax_W; hd.nonfinite = c->best.nonfinite;
-    for (int k = 1; k <= c->g.d; ++k)  // the file holds complete tables
+    hd.best_kind = c->best.kind;
+    hd.iteration = c->two_array ? LCSB_ITER_TWO_ARRAY : LCSB_ITER_RING;
+    for (int k = 1; k <= c->lags; ++k)  // the file holds complete tables
         if ((rc = materialize(const_cast<lcsb_ctx *>(c), slot_of_lag(c, k)))) return rc;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(LCSB_EHIP, "sync: %s", hipGetErrorString(e));
     if (c->dtype == LCSB_F32) {
-        for (int k = 1; k <= c->g.d; ++k) {
+        for (int k = 1; k <= c->lags; ++k) {
             e = hipMemcpy(&hd.offsets[k - 1], c->ws + Ws::kOffsets + 8 * slot_of_lag(c, k), 8,
                           hipMemcpyDeviceToHost);
             if (e != hipSuccess) return fail(LCSB_EHIP, "offset read: %s", hipGetErrorString(e));
@@ -707,7 +787,7 @@ int lcsb_save(const lcsb_ctx *c, const char *path)
     stage.stream = c->stream;
     if ((e = hipHostMalloc(&stage.p, kStageBytes, hipHostMallocDefault)) != hipSuccess)
         return fail(LCSB_EHIP, "pinned staging buffer: %s", hipGetErrorString(e));
-    for (int k = 1; k <= c->g.d; ++k) {
+    for (int k = 1; k <= c->lags; ++k) {
         const unsigned char *src = static_cast<const unsigned char *>(c->buf[slot_of_lag(c, k)]);
         Hash64 hs;
         for (uint64_t at = 0; at < tbytes; at += kStageBytes) {
@@ -744,18 +824,20 @@ int lcsb_load(lcsb_ctx *c, const char *path)
     if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != kCkptVersion)
         return fail(LCSB_ECKPT, "%s: not a ring checkpoint of this version", path);
     if (hd.header_hash != header_hash(hd)) return fail(LCSB_ECKPT, "%s: header hash mismatch", path);
+    const int iteration = c->two_array ? LCSB_ITER_TWO_ARRAY : LCSB_ITER_RING;
     if (hd.sigma != c->g.sigma || hd.d != c->g.d || hd.h != c->g.h || hd.dtype != c->dtype ||
-        hd.stored != c->g.ns)
-        return fail(LCSB_ECKPT, "%s: holds sigma=%d d=%d l=%d dtype=%d, the context is sigma=%d "
-                                "d=%d l=%d dtype=%d", path, hd.sigma, hd.d, hd.h, hd.dtype,
-                    c->g.sigma, c->g.d, c->g.h, c->dtype);
+        hd.stored != c->g.ns || hd.iteration != iteration)
+        return fail(LCSB_ECKPT, "%s: holds sigma=%d d=%d l=%d dtype=%d iteration=%d, the context "
+                                "is sigma=%d d=%d l=%d dtype=%d iteration=%d", path, hd.sigma,
+                    hd.d, hd.h, hd.dtype, hd.iteration, c->g.sigma, c->g.d, c->g.h, c->dtype,
+                    iteration);
     const size_t es = elem_size(c->dtype);
     const uint64_t tbytes = c->g.ns * es;
     if (fseek(in.f, 0, SEEK_END) != 0) return fail(LCSB_ECKPT, "%s: cannot seek", path);
     const long long size = ftell(in.f);
-    if (size < 0 || (uint64_t)size != sizeof hd + (uint64_t)c->g.d * tbytes)
+    if (size < 0 || (uint64_t)size != sizeof hd + (uint64_t)c->lags * tbytes)
         return fail(LCSB_ECKPT, "%s: %lld bytes, expected %llu", path, size,
-                    (unsigned long long)(sizeof hd + (uint64_t)c->g.d * tbytes));
+                    (unsigned long long)(sizeof hd + (uint64_t)c->lags * tbytes));
     if (fseek(in.f, (long)sizeof hd, SEEK_SET) != 0) return fail(LCSB_ECKPT, "%s: cannot seek", path);
     // from here the ring is being overwritten: not ready until every hash checks
     c->state = kBound;
@@ -767,7 +849,7 @@ int lcsb_load(lcsb_ctx *c, const char *path)
     if ((e = launch_fill_zero(c->ws, Ws::kBytes, c->stream)) != hipSuccess)
         return hip_fail(c, e, "fill workspace");
     c->head = 0;
-    for (int k = 1; k <= c->g.d; ++k) {
+    for (int k = 1; k <= c->lags; ++k) {
         unsigned char *dst = static_cast<unsigned char *>(c->buf[slot_of_lag(c, k)]);
         Hash64 hs;
         for (uint64_t at = 0; at < tbytes; at += kStageBytes) {
@@ -794,8 +876,10 @@ int lcsb_load(lcsb_ctx *c, const char *path)
     c->best.bound = hd.bound; c->best.R = hd.R; c->best.E = hd.E; c->best.maxW = hd.maxW;
     c->best.rho = hd.rho; c->best.sweep = hd.best_sweep;
     c->best.argmax_W = hd.argmax_W; c->best.nonfinite = hd.nonfinite;
-    const int rc = refresh_swap(c);
+    c->best.kind = hd.best_kind;
+    int rc = refresh_swap(c);
     if (rc) return rc;
+    if ((rc = refresh_rate(c))) return rc;
     c->state = kReady;
     return LCSB_OK;
 }

@@ -27,9 +27,14 @@ struct Ws {
     static constexpr size_t kOptArg = 88;        // uint64: lowest index attaining it
     static constexpr size_t kOptNonfinite = 96;  // uint64: coordinates whose ratio is not finite
     static constexpr size_t kScalarBytes = 104;
+    static constexpr size_t kRate = 112;     // double: R of the two-array iteration
     static constexpr size_t kAsym = 128;     // uint32: set when a table is not exchange-symmetric
-    // FP64 offsets of the FP32 tables, one per ring slot
+    // FP64 offsets of the FP32 tables, one per ring slot (0 .. 3); slots 4 and
+    // 5 hold the values lag 2 and lag 3 are read relative to in the two-array
+    // iteration (FP32: offset of u - (k-1) R; FP64: -(k-1) R), slot 6 is
+    // always zero (the reference of FP64 tables)
     static constexpr size_t kOffsets = 256;  // double[8]
+    static constexpr int kSlotLag2 = 4, kSlotLag3 = 5, kSlotZero = 6;
     // per-workgroup partials of the reductions
     static constexpr size_t kPartVal = 512;                                  // double[kMaxReduceBlocks]
     static constexpr size_t kPartIdx = kPartVal + 8 * kMaxReduceBlocks;      // uint64[kMaxReduceBlocks]
@@ -52,6 +57,8 @@ struct SweepLaunch {
     double *offsets;  // device, per slot (FP32 only)
     int swap_sym;     // sigma = 2, d = 2 or 3: the lag tables are symmetric in strings 1 and 2
                       // (read lazily, see TwinGroup; the new table is written lazily)
+    int shift;        // FP64 only: lag k is read as its values + (offsets[lag_slot[k-1]] -
+                      // offsets[lag_slot[0]]) (the two-array iteration); FP32 always is
 };
 
 hipError_t launch_sweep(const Geometry &g, int dtype, const SweepLaunch &a, hipStream_t s);
@@ -66,6 +73,12 @@ hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const voi
 // The largest-r certificate of u (kOptR, kOptArg, kOptNonfinite).
 hipError_t launch_certify_optimal(const Geometry &g, int dtype, const void *u, int swap_sym,
                                   unsigned char *ws, hipStream_t s);
+
+// The two-array iteration: R = mean over the fixed sample of nw - old, and the
+// offsets slots kSlotLag2/3 for the next sweep (csrc/two_array.hip)
+hipError_t launch_two_array_rate(const Geometry &g, int dtype, const void *nw, const void *old,
+                                 int s_new, int s_old, int swap_sym, unsigned char *ws,
+                                 hipStream_t s);
 
 // Utilities
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);

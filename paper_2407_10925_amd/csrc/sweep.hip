@@ -163,7 +163,7 @@ constexpr uint64_t kAlt4Hi = 0xCCCCCCCCCCCCCCCCull; // high 2-bit field of every
 // lower index of each of its four exchanged pairs (t and ~St at 0/0, t and St
 // at 0/1) and reads every group through its lower members, so a sweep reads
 // half of the groups and writes half of the stored table.
-template <typename T, bool SWAP>
+template <typename T, bool SWAP, bool SHIFT>
 __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
                                                     const T *__restrict__ lag2,
                                                     T *__restrict__ out, uint64_t n,
@@ -171,9 +171,11 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
                                                     int snew)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kShift = kF32 || SHIFT;  // lag 2 carries delta_2
     const uint64_t nq = n >> 2;
     const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     T d2 = 0, y0 = 0;
+    if constexpr (!kF32 && SHIFT) d2 = off[s2] - off[s1];
     if constexpr (kF32) {
         const double o1 = off[s1];
         d2 = (float)(off[s2] - o1);
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
         stream4<true>(lag2 + 4 * t, g);
     }
     T m2 = pair4(g[0], g[1], g[2], g[3]) * (T)0.25;
-    if constexpr (kF32) m2 = m2 + d2;
+    if constexpr (kShift) m2 = m2 + d2;
     const T match = (T)1 + first(m2);
 
     const uint64_t am = kAlt2 & (n - 1), bm = ~kAlt2 & (n - 1);
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
 // members a branch needs are contiguous (advance b in an own group, advance a
 // in a twin group, one row of it) they are one vector load (6.8% faster in
 // FP32, 11.6% in FP64 than a load per member).
-template <typename T, bool SWAP>
+template <typename T, bool SWAP, bool SHIFT>
 __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
                                                     const T *__restrict__ lag2,
                                                     T *__restrict__ out, uint64_t n, int h,
@@ -296,9 +298,11 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
                                                     int snew)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kShift = kF32 || SHIFT;  // lag 2 carries delta_2
     const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const int top = 4 * (h - 1);
     T d2 = 0, y0 = 0;
+    if constexpr (!kF32 && SHIFT) d2 = off[s2] - off[s1];
     if constexpr (kF32) {
         const double o1 = off[s1];
         d2 = (float)(off[s2] - o1);
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
         for (int k = 0; k < 16; k += 4) load4(lag2 + 16 * t + k, g + k);
     }
     T both = tree16(g) * (T)0.0625;
-    if constexpr (kF32) both = both + d2;
+    if constexpr (kShift) both = both + d2;
     const T match = (T)1 + first(both);
 
     const uint64_t am = kAlt4Hi & (n - 1), bm = ~kAlt4Hi & (n - 1);
@@ -428,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
 // at the lower index of its pair (one load each: measured 1.2-1.4x faster
 // than loading twin groups and permuting them), so a sweep reads half of the
 // groups and writes half of the table.
-template <typename T, bool SWAP>
+template <typename T, bool SWAP, bool SHIFT>
 __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
                                                     const T *__restrict__ lag2,
                                                     const T *__restrict__ lag3,
@@ -437,9 +441,14 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
                                                     int s3, int snew)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kShift = kF32 || SHIFT;  // lags 2 and 3 carry delta_2, delta_3
     const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const int top = 3 * (h - 1);
     T d2 = 0, d3 = 0, y0 = 0;
+    if constexpr (!kF32 && SHIFT) {
+        d2 = off[s2] - off[s1];
+        d3 = off[s3] - off[s1];
+    }
     if constexpr (kF32) {
         const double o1 = off[s1];
         d2 = (float)(off[s2] - o1);
@@ -476,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
         stream4<kF32>(lag3 + 8 * t + 4, g + 4);
     }
     T all3 = pair8(g) * (T)0.125;
-    if constexpr (kF32) all3 = all3 + d3;
+    if constexpr (kShift) all3 = all3 + d3;
     const T match = (T)1 + first(all3);
 
     const uint64_t mask = n - 1;
@@ -518,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
                 k2 = pair4(q[o], q[o + 2], q[o + 4], q[o + 6]) * (T)0.25;
             }
             const T k1 = (p0 + p1) * (T)0.5;
-            if constexpr (kF32) k2 = k2 + d2;
+            if constexpr (kShift) k2 = k2 + d2;
             val[1] = vmax(first(k1), k2);
         }
         {   // 010: lag 1 entries b1, b1 + 2; lag 2 entries b2 + 0, 1, 4, 5
@@ -539,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
                 const int o2 = c ? 2 - (int)(b2 & 7) : (int)(b2 & 7);
                 k2 = pair4(q[o2], q[o2 + 1], q[o2 + 4], q[o2 + 5]) * (T)0.25;
             }
-            if constexpr (kF32) k2 = k2 + d2;
+            if constexpr (kShift) k2 = k2 + d2;
             val[2] = vmax(first(k1), k2);
         }
         {   // 011: lag 2 entries b2 + 0..3; lag 1 entries b1, b1 + 4
@@ -559,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
                 const int o = c ? 3 - (int)(b1 & 7) : (int)(b1 & 7);
                 k1 = (e[o] + e[o + 4]) * (T)0.5;
             }
-            if constexpr (kF32) k2 = k2 + d2;
+            if constexpr (kShift) k2 = k2 + d2;
             val[3] = vmax(first(k2), k1);
         }
 #pragma unroll
@@ -622,26 +631,26 @@ __device__ __forceinline__ T tree_pow2(T *v)  // the balanced tree over CNT = 2^
 
 // mean of lag |M| over the successors of `head` for moved set M, FP32 tables
 // shifted by delta_|M|; the mean of the set `moved` when M reaches it
-template <typename T, int SIGMA, int D, int M>
+template <typename T, int SIGMA, int D, int M, bool SHIFT>
 __device__ __forceinline__ T l1_branch(const T *const *lag, const T *delta, int head, int moved)
 {
     using G = L1<SIGMA, D>;
     if constexpr (M >= (1 << D)) {
         return (T)0;
     } else {
-        if (moved != M) return l1_branch<T, SIGMA, D, M + 1>(lag, delta, head, moved);
+        if (moved != M) return l1_branch<T, SIGMA, D, M + 1, SHIFT>(lag, delta, head, moved);
         constexpr int K = __builtin_popcount(M), CNT = 1 << (G::kBeta * K);
         T v[CNT];
 #pragma unroll
         for (int c = 0; c < CNT; ++c)
             v[c] = lag[K - 1][G::image(G::template successor<M>(head, G::template leaf<CNT>(c)))];
         T m = tree_pow2<T, CNT>(v) * ((T)1 / (T)CNT);
-        if (std::is_same<T, float>::value && K >= 2) m = m + delta[K - 1];
+        if ((std::is_same<T, float>::value || SHIFT) && K >= 2) m = m + delta[K - 1];
         return m;
     }
 }
 
-template <typename T, int SIGMA, int D>
+template <typename T, int SIGMA, int D, bool SHIFT>
 __device__ __forceinline__ T l1_value(const T *const *lag, const T *delta, int head)
 {
     constexpr int kBeta = L1<SIGMA, D>::kBeta;
@@ -652,7 +661,8 @@ __device__ __forceinline__ T l1_value(const T *const *lag, const T *delta, int h
         sym[s] = (head >> (kBeta * (D - 1 - s))) & (SIGMA - 1);
         same = same && sym[s] == sym[0];
     }
-    if (same) return (T)1 + first(l1_branch<T, SIGMA, D, 1>(lag, delta, head, (1 << D) - 1));
+    if (same)
+        return (T)1 + first(l1_branch<T, SIGMA, D, 1, SHIFT>(lag, delta, head, (1 << D) - 1));
     T best = 0;
 #pragma unroll
     for (int z = 0; z < SIGMA; ++z) {
@@ -660,13 +670,13 @@ __device__ __forceinline__ T l1_value(const T *const *lag, const T *delta, int h
 #pragma unroll
         for (int s = 0; s < D; ++s)
             if (sym[s] != z) moved |= 1 << s;
-        const T m = l1_branch<T, SIGMA, D, 1>(lag, delta, head, moved);
+        const T m = l1_branch<T, SIGMA, D, 1, SHIFT>(lag, delta, head, moved);
         best = z == 0 ? first(m) : vmax(best, m);
     }
     return best;
 }
 
-template <typename T, int SIGMA, int D>
+template <typename T, int SIGMA, int D, bool SHIFT>
 __global__ __launch_bounds__(kBlock) void sweep_l1(const T *__restrict__ lag1,
                                                   const T *__restrict__ lag2,
                                                   const T *__restrict__ lag3,
@@ -682,34 +692,37 @@ __global__ __launch_bounds__(kBlock) void sweep_l1(const T *__restrict__ lag1,
         o1 = off[s1];
         delta[1] = (float)(off[s2] - o1);
         if (D == 3) delta[2] = (float)(off[s3] - o1);
+    } else if constexpr (SHIFT) {
+        delta[1] = off[s2] - off[s1];
+        if (D == 3) delta[2] = off[s3] - off[s1];
     }
-    const T y0 = kF32 ? l1_value<T, SIGMA, D>(lag, delta, 0) : (T)0;
+    const T y0 = kF32 ? l1_value<T, SIGMA, D, SHIFT>(lag, delta, 0) : (T)0;
     const int j = threadIdx.x;
     if (kF32 && j == 0) off[snew] = o1 + (double)y0;
     if (j < L1<SIGMA, D>::kNs) {
-        const T v = l1_value<T, SIGMA, D>(lag, delta, j);
+        const T v = l1_value<T, SIGMA, D, SHIFT>(lag, delta, j);
         out[j] = kF32 ? (T)(v - y0) : v;
     }
 }
 
-template <typename T>
+template <typename T, bool SHIFT>
 hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
 {
     const T *l1 = static_cast<const T *>(a.lag[0]);
     const T *l2 = static_cast<const T *>(a.lag[1]);
     const T *l3 = g.d == 3 ? static_cast<const T *>(a.lag[2]) : nullptr;
     T *out = static_cast<T *>(a.out);
+    const int s1 = a.lag_slot[0], s2 = a.lag_slot[1], s3 = g.d == 3 ? a.lag_slot[2] : 0;
     if (g.h == 1) {
-        const int s3 = g.d == 3 ? a.lag_slot[2] : 0;
         if (g.sigma == 2 && g.d == 2)
-            sweep_l1<T, 2, 2><<<1, kBlock, 0, s>>>(l1, l2, l3, out, a.offsets, a.lag_slot[0],
-                                                   a.lag_slot[1], s3, a.new_slot);
+            sweep_l1<T, 2, 2, SHIFT><<<1, kBlock, 0, s>>>(l1, l2, l3, out, a.offsets, s1, s2, s3,
+                                                          a.new_slot);
         else if (g.sigma == 4 && g.d == 2)
-            sweep_l1<T, 4, 2><<<1, kBlock, 0, s>>>(l1, l2, l3, out, a.offsets, a.lag_slot[0],
-                                                   a.lag_slot[1], s3, a.new_slot);
+            sweep_l1<T, 4, 2, SHIFT><<<1, kBlock, 0, s>>>(l1, l2, l3, out, a.offsets, s1, s2, s3,
+                                                          a.new_slot);
         else if (g.sigma == 2 && g.d == 3)
-            sweep_l1<T, 2, 3><<<1, kBlock, 0, s>>>(l1, l2, l3, out, a.offsets, a.lag_slot[0],
-                                                   a.lag_slot[1], s3, a.new_slot);
+            sweep_l1<T, 2, 3, SHIFT><<<1, kBlock, 0, s>>>(l1, l2, l3, out, a.offsets, s1, s2, s3,
+                                                          a.new_slot);
         else
             return hipErrorInvalidValue;
         return hipGetLastError();
@@ -721,27 +734,25 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
     dim3 grid((unsigned)blocks), block(kBlock);
     if (g.sigma == 2 && g.d == 2) {
         if (a.swap_sym)
-            sweep_s2d2<T, true><<<grid, block, 0, s>>>(l1, l2, out, g.n, a.offsets,
-                                                       a.lag_slot[0], a.lag_slot[1], a.new_slot);
+            sweep_s2d2<T, true, SHIFT><<<grid, block, 0, s>>>(l1, l2, out, g.n, a.offsets, s1, s2,
+                                                              a.new_slot);
         else
-            sweep_s2d2<T, false><<<grid, block, 0, s>>>(l1, l2, out, g.n, a.offsets,
-                                                        a.lag_slot[0], a.lag_slot[1], a.new_slot);
+            sweep_s2d2<T, false, SHIFT><<<grid, block, 0, s>>>(l1, l2, out, g.n, a.offsets, s1,
+                                                               s2, a.new_slot);
     } else if (g.sigma == 4 && g.d == 2) {
         if (a.swap_sym)
-            sweep_s4d2<T, true><<<grid, block, 0, s>>>(l1, l2, out, g.n, g.h, a.offsets,
-                                                       a.lag_slot[0], a.lag_slot[1], a.new_slot);
+            sweep_s4d2<T, true, SHIFT><<<grid, block, 0, s>>>(l1, l2, out, g.n, g.h, a.offsets,
+                                                              s1, s2, a.new_slot);
         else
-            sweep_s4d2<T, false><<<grid, block, 0, s>>>(l1, l2, out, g.n, g.h, a.offsets,
-                                                        a.lag_slot[0], a.lag_slot[1], a.new_slot);
+            sweep_s4d2<T, false, SHIFT><<<grid, block, 0, s>>>(l1, l2, out, g.n, g.h, a.offsets,
+                                                               s1, s2, a.new_slot);
     } else if (g.sigma == 2 && g.d == 3) {
         if (a.swap_sym)
-            sweep_s2d3<T, true><<<grid, block, 0, s>>>(l1, l2, l3, out, g.n, g.h, a.offsets,
-                                                       a.lag_slot[0], a.lag_slot[1],
-                                                       a.lag_slot[2], a.new_slot);
+            sweep_s2d3<T, true, SHIFT><<<grid, block, 0, s>>>(l1, l2, l3, out, g.n, g.h,
+                                                              a.offsets, s1, s2, s3, a.new_slot);
         else
-            sweep_s2d3<T, false><<<grid, block, 0, s>>>(l1, l2, l3, out, g.n, g.h, a.offsets,
-                                                        a.lag_slot[0], a.lag_slot[1],
-                                                        a.lag_slot[2], a.new_slot);
+            sweep_s2d3<T, false, SHIFT><<<grid, block, 0, s>>>(l1, l2, l3, out, g.n, g.h,
+                                                               a.offsets, s1, s2, s3, a.new_slot);
     } else {
         return hipErrorInvalidValue;
     }
@@ -752,7 +763,10 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
 
 hipError_t launch_sweep(const Geometry &g, int dtype, const SweepLaunch &a, hipStream_t s)
 {
-    return dtype == LCSB_F32 ? launch_typed<float>(g, a, s) : launch_typed<double>(g, a, s);
+    // FP32 tables always read lag k shifted by delta_k (their offsets); FP64
+    // ones only in the two-array iteration
+    if (dtype == LCSB_F32) return launch_typed<float, false>(g, a, s);
+    return a.shift ? launch_typed<double, true>(g, a, s) : launch_typed<double, false>(g, a, s);
 }
 
 }  // namespace lcsb

@@ -41,6 +41,16 @@ def test_create_validates_arguments(lib):
     assert lib.lcsb_create(2, 2, 6, 7, C.byref(ctx)) == _capi.LCSB_EINVAL
     assert b"dtype" in lib.lcsb_last_error()
     assert lib.lcsb_create(2, 2, 6, 0, None) == _capi.LCSB_EINVAL
+    assert lib.lcsb_create_iter(2, 2, 6, 0, 2, C.byref(ctx)) == _capi.LCSB_EINVAL
+    assert b"iteration" in lib.lcsb_last_error()
+    for d, iteration, nbuf in ((2, 0, 3), (3, 0, 4), (2, 1, 2), (3, 1, 2)):
+        assert lib.lcsb_create_iter(2, d, 3, 0, iteration, C.byref(ctx)) == 0
+        nb = C.c_int()
+        assert lib.lcsb_query(ctx, C.byref(nb), None, None, None) == 0
+        assert nb.value == nbuf
+        rate = C.c_double()
+        assert lib.lcsb_rate(ctx, C.byref(rate)) == _capi.LCSB_ESTATE  # not initialised
+        assert lib.lcsb_destroy(ctx) == 0
 
 
 @pytest.mark.parametrize("sigma,d,h,dtype,n,elem", [(2, 2, 6, 0, 4096, 8), (2, 2, 16, 1, 2**32, 4),
@@ -102,7 +112,7 @@ def test_build_rejects_kernels_that_spill():
 
 
 # ------------------------------------------------------------------ checkpoint files
-_HDR = "<8sIiiiiIQqdddddqQQ3d3QQ"  # the checkpoint header of include/lcsb.h's lcsb_save
+_HDR = "<8sIiiiiiQqdddddqQQq3d3QQ"  # the checkpoint header of include/lcsb.h's lcsb_save
 
 
 def _hash64(data: bytes) -> int:
@@ -115,10 +125,10 @@ def _hash64(data: bytes) -> int:
     return h
 
 
-def _header(sigma, d, h, dtype, stored):
+def _header(sigma, d, h, dtype, stored, iteration=0, version=2):
     import struct
-    body = struct.pack(_HDR[:-1], b"LCSBRING", 1, sigma, d, h, dtype, 0, stored, 5,
-                       0.5, 0.25, 0.0, -1.0, 0.25, 4, 0, 0, 0.0, 0.0, 0.0, 1, 2, 3)
+    body = struct.pack(_HDR[:-1], b"LCSBRING", version, sigma, d, h, dtype, iteration, stored, 5,
+                       0.5, 0.25, 0.0, -1.0, 0.25, 4, 0, 0, 0, 0.0, 0.0, 0.0, 1, 2, 3)
     return body + struct.pack("<Q", _hash64(body))
 
 
@@ -127,7 +137,7 @@ def test_checkpoint_header_is_checked_before_the_ring_is_touched(lib, tmp_path):
     are not device memory: this runs without a GPU)."""
     import struct
     from paper_2407_10925_amd import _capi
-    assert struct.calcsize(_HDR) == 168
+    assert struct.calcsize(_HDR) == 176
     ctx = C.c_void_p()
     assert lib.lcsb_create(2, 2, 4, 0, C.byref(ctx)) == 0
     assert lib.lcsb_load(ctx, str(tmp_path / "x").encode()) == _capi.LCSB_ESTATE  # not bound
@@ -144,6 +154,8 @@ def test_checkpoint_header_is_checked_before_the_ring_is_touched(lib, tmp_path):
         "hash": good[:40] + b"\x07" + good[41:],
         "shape": _header(2, 2, 5, 0, 4 ** 5 // 2) + bytes(2 * 8 * 4 ** 5 // 2),
         "dtype": _header(2, 2, 4, 1, stored) + bytes(2 * 4 * stored),
+        "iteration": _header(2, 2, 4, 0, stored, iteration=1) + bytes(2 * tbytes),
+        "version": _header(2, 2, 4, 0, stored, version=1) + bytes(2 * tbytes),
         "truncated": good + bytes(2 * tbytes - 8),
         "too long": good + bytes(2 * tbytes + 8),
     }

@@ -189,17 +189,26 @@ def test_optimal_certificate_of_fp32_tables(pk, sigma, d, h, exchange):
     _same_opt(cur, oracle.certify_optimal(sigma, d, h, u.numpy()))
 
 
-def test_run_driver_with_the_optimal_certificate(pk):
+def test_run_driver_with_the_optimal_certificate(pk, tmp_path):
     """lcsb_run with certificate = optimal takes the largest-r certificate at
     its cadence: the same best as the host loop, and an earlier stop than
-    Algorithm 2's certificate for the same target."""
+    Algorithm 2's certificate for the same target.  Its log holds one JSON
+    line per certificate."""
+    import json
     sigma, d, h = 2, 2, 6
     say("lcsb_run with the largest-r certificate")
     target = 0.7702
     L = pk.Lcsb(sigma, d, h, "f64")
     L.init_zero()
-    cur, best, certs, why = L.run(cadence=4, max_sweeps=400, target=target, certificate="optimal")
+    log = tmp_path / "certs.jsonl"
+    cur, best, certs, why = L.run(cadence=4, max_sweeps=400, target=target, certificate="optimal",
+                                  log=log)
     assert why == "target" and best["kind"] == 1 and best["bound"] >= target
+    rows = [json.loads(x) for x in log.read_text().splitlines()]
+    assert len(rows) == certs and [r["sweep"] for r in rows] == [4 * (k + 1) for k in range(certs)]
+    assert all(r["kind"] == "optimal" and r["E"] == 0.0 for r in rows)
+    assert rows[-1]["best_bound"] == best["bound"] and rows[-1]["bound"] == cur["bound"]
+    assert all(b["seconds"] >= a["seconds"] for a, b in zip(rows, rows[1:]))
     N = 4 ** h
     ring = [np.zeros(N), np.zeros(N)]
     t, best_ref = 0, None

@@ -438,7 +438,8 @@ def test_fp64_converged_bound_is_table2s(pk, h):
         cur, best = L.certify()
         assert best["bound"] >= last_best
         last_best = best["bound"]
-        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
+        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"] \
+                and best["bound"] > 0:
             break
         prev = cur["bound"]
         assert cur["sweep"] < 800
@@ -473,7 +474,8 @@ def test_fp64_generality_converges_to_table3(pk, sigma, d):
     while True:
         L.iterate(16)
         cur, best = L.certify()
-        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
+        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"] \
+                and best["bound"] > 0:
             break
         prev = cur["bound"]
         assert cur["sweep"] < 1600
@@ -639,7 +641,7 @@ def test_checkpoint_resume_is_bit_identical(pk, tmp_path, sigma, d, h, dt):
     A.iterate(25)
     A.certify()
     A.save(path)
-    assert path.stat().st_size == 168 + d * A.stored * (8 if dt == "f64" else 4)
+    assert path.stat().st_size == 176 + d * A.stored * (8 if dt == "f64" else 4)
     assert not (tmp_path / "ring.ckpt.part").exists()
     A.iterate(11)
     cur_a, best_a = A.certify()
@@ -667,7 +669,7 @@ def test_corrupt_checkpoint_is_refused(pk, tmp_path):
     A.iterate(9)
     A.save(path)
     blob = bytearray(path.read_bytes())
-    blob[168 + 8 * 1000 + 3] ^= 0x10
+    blob[176 + 8 * 1000 + 3] ^= 0x10
     bad = tmp_path / "bad_table.ckpt"
     bad.write_bytes(bytes(blob))
     B = pk.Lcsb(2, 2, 6, "f64")
@@ -704,7 +706,8 @@ def test_run_driver_matches_the_host_loop(pk):
         A.iterate(16)
         cur, best = A.certify()
         n += 1
-        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"]:
+        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"] \
+                and best["bound"] > 0:
             break
         prev = cur["bound"]
     B = pk.Lcsb(2, 2, h, "f64")

@@ -164,3 +164,13 @@ def test_rate_converges_to_r_and_growth_is_uniform(orc):
     g = u - up
     assert g.max() - g.min() <= 1e-10
     assert abs(R - best["bound"] / 2) <= 1e-10
+
+
+def test_sampled_step_is_the_whole_step_there(orc):
+    rng = np.random.default_rng(9)
+    for sigma, d, h in [(2, 2, 5), (4, 2, 2), (2, 3, 3)]:
+        N = sigma ** (d * h)
+        u = rng.random(N) * 5
+        idx = np.unique(rng.integers(0, N, 200)).astype(np.uint64)
+        whole = orc.two_array_step(sigma, d, h, u, 0.37)
+        assert np.array_equal(orc.two_array_step_at(sigma, d, h, u, 0.37, idx), whole[idx.astype(np.int64)])

@@ -81,6 +81,10 @@ def parse():
     p.add_argument("--converge", type=int, default=0, metavar="L",
                    help="only run plain FP64 at (--sigma, --d, l = L) to convergence, then FP32 + "
                         "FP64 polish to the same bound in the same memory")
+    p.add_argument("--two-array-f32", type=int, default=0, metavar="L",
+                   help="only the FP32 two-array iteration from zero at sigma=d=2, l=L, "
+                        "certified every 16 sweeps (the largest-r certificate) for --max-sweeps")
+    p.add_argument("--max-sweeps", type=int, default=480)
     p.add_argument("--profile-certify", action="store_true",
                    help="only run 8 sweeps from zero and two certificates (counter collection)")
     return p.parse_args()
@@ -302,7 +306,7 @@ def fp64_sweep(pk, h, sweeps=32):
            "bound": "hbm",
            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(ms, 4),
-           "kernel": f"sweep_s2d2<double, {'true' if folded else 'false'}>",
+           "kernel": f"sweep_s2d2<double, {'true' if folded else 'false'}, false>",
            "algorithmic_bytes_per_launch": algo,
            "updates_per_s": n / ms * 1e3, "traffic": None}
     traffic = measured_traffic(PMC_SUMMARY_F64_H14) if h == 14 else None
@@ -643,6 +647,38 @@ def converge_only(pk, h, sigma=2, d=2):
     print(json.dumps(out), flush=True)
 
 
+def two_array_f32_only(pk, h, max_sweeps, sigma=2, d=2):
+    """The FP32 two-array iteration from zero at (sigma, d, l = h) with the
+    largest-r certificate every TTB_CADENCE sweeps for max_sweeps sweeps (two
+    FP32 tables: at l = 18, 2 x 128 GiB, the only form of the iteration that
+    fits one GPU there).  Prints the best certified bound, rounded down at the
+    6th decimal as the paper's tables print it, and the certificate trail."""
+    import torch
+    L = pk.Lcsb(sigma, d, h, "f32", iteration="two_array")
+    log(f"two-array FP32 at sigma={sigma} d={d} l={h}: {L.n} indices, {L.stored} stored, "
+        f"{2 * 4 * L.stored / 2**30:.0f} GiB")
+    trail = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.init_zero()
+    best = None
+    done = 0
+    while done < max_sweeps:
+        L.iterate(TTB_CADENCE)
+        done += TTB_CADENCE
+        cur, best = L.certify_optimal()
+        trail.append((done, round(time.perf_counter() - t0, 3), cur["bound"], best["bound"]))
+        log(f"sweep {done}: bound {cur['bound']:.10f} best {best['bound']:.10f} "
+            f"rate {L.rate():.10f}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"sigma": sigma, "d": d, "l": h, "indices": L.n, "stored": L.stored,
+           "iteration": "two_array", "dtype": "f32", "sweeps": done, "seconds": round(dt, 3),
+           "best_bound": best["bound"], "best_sweep": best["sweep"],
+           "floor6": math.floor(best["bound"] * 1e6) / 1e6, "trail": trail}
+    print(json.dumps(out), flush=True)
+
+
 def certify_only(pk, h, sigma=2, d=2, dtype="f32"):
     """8 sweeps from zero at (sigma, d, l = h), then two certificates of each
     kind (Algorithm 2's, the largest-r one)."""
@@ -693,6 +729,8 @@ def main():
         return converge_only(pk, args.converge, args.sigma, args.d)
     if args.profile_certify:
         return certify_only(pk, args.h, args.sigma, args.d, args.dtype)
+    if args.two_array_f32:
+        return two_array_f32_only(pk, args.two_array_f32, args.max_sweeps, args.sigma, args.d)
     if args.profile_train:
         return train_only(pk, args.h, args.profile_train, args.train_batch)
     if args.configs:
@@ -730,7 +768,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": f"sweep_s2d2<float, {'true' if folded else 'false'}>",
+                "kernel": f"sweep_s2d2<float, {'true' if folded else 'false'}, false>",
                 "algorithmic_bytes_per_launch": algo_bytes,
                 "avg_launch_ms": round(avg_sweep_s * 1e3, 4)}
     if traffic is not None:  # rocprofv3-measured HBM bytes per launch, at this launch time

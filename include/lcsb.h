@@ -98,8 +98,10 @@ typedef struct {
 /* Create a context for (sigma, d, l = h) and a table element type running
  * the ring iteration of Algorithm 2.  GPU kernels exist for (sigma, d) in
  * {(2,2), (4,2), (2,3)} and both element types; other pairs give
- * LCSB_EUNSUPPORTED.  h >= 1 and sigma^(d h) <= 2^34 (else LCSB_EINVAL).
- * *out receives a host object owned by the library. */
+ * LCSB_EUNSUPPORTED.  h >= 1 and sigma^(d h) <= 2^36 (else LCSB_EINVAL; at
+ * 2^36 indices one FP32 table of the stored half is 128 GiB, so only the
+ * two-array iteration in FP32 fits one 288 GB GPU there).  *out receives a
+ * host object owned by the library. */
 int lcsb_create(int sigma, int d, int h, int dtype, lcsb_ctx **out);
 
 /* As lcsb_create, choosing the iteration.  LCSB_ITER_TWO_ARRAY is this

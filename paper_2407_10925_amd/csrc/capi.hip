@@ -157,7 +157,7 @@ int lcsb_create_iter(int sigma, int d, int h, int dtype, int iteration, lcsb_ctx
     if (!ok) return fail(LCSB_EUNSUPPORTED, "no GPU kernel for sigma=%d d=%d", sigma, d);
     const int beta = sigma == 2 ? 1 : 2;
     const int bits = beta * d * h;
-    if (bits > 34) return fail(LCSB_EINVAL, "sigma^(d h) = 2^%d exceeds 2^34", bits);
+    if (bits > 36) return fail(LCSB_EINVAL, "sigma^(d h) = 2^%d exceeds 2^36", bits);
     lcsb_ctx *c = new (std::nothrow) lcsb_ctx;
     if (!c) return fail(LCSB_ENOMEM, "context allocation failed");
     memset(c, 0, sizeof *c);

@@ -63,6 +63,36 @@ __device__ void block_reduce(double &v, uint64_t &i, uint64_t &c)
     }
 }
 
+// Fold the per-workgroup partials (max value, lowest index, count) of a pass
+// into this thread's running result: thread k takes partials k, k + 256, ..,
+// eight loads in flight at a time (up to 16384 partials: one load after the
+// other made this final pass 56 us).
+__device__ __forceinline__ void merge_partials(const unsigned char *__restrict__ ws, int nparts,
+                                               double &best, uint64_t &arg, uint64_t &nonfinite)
+{
+    const double *pv = reinterpret_cast<const double *>(ws + Ws::kPartVal);
+    const uint64_t *pi = reinterpret_cast<const uint64_t *>(ws + Ws::kPartIdx);
+    const uint64_t *pc = reinterpret_cast<const uint64_t *>(ws + Ws::kPartCnt);
+    constexpr int kBatch = 8;
+    for (int k0 = threadIdx.x; k0 < nparts; k0 += kBatch * kBlock) {
+        double v[kBatch];
+        uint64_t i[kBatch], c[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int k = k0 + j * kBlock;
+            const bool in = k < nparts;
+            v[j] = in ? pv[k] : -INFINITY;
+            i[j] = in ? pi[k] : 0;
+            c[j] = in ? pc[k] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            merge_max_idx(best, arg, v[j], i[j]);
+            nonfinite += c[j];
+        }
+    }
+}
+
 // n = stored entries.  SWAP_D (2 or 3: sigma = 2 with d = SWAP_D; 4: sigma =
 // 4, d = 2; both tables symmetric in strings 1 and 2): u - prev is equal at a
 // stored entry and at its exchanged twin (exchange_twin, exchange_twin4), so
@@ -162,11 +192,7 @@ __global__ __launch_bounds__(kBlock) void cert_r_final(unsigned char *__restrict
 {
     double best = -INFINITY;
     uint64_t arg = 0, nonfinite = 0;
-    for (int k = threadIdx.x; k < nparts; k += kBlock) {
-        merge_max_idx(best, arg, reinterpret_cast<const double *>(ws + Ws::kPartVal)[k],
-                      reinterpret_cast<const uint64_t *>(ws + Ws::kPartIdx)[k]);
-        nonfinite += reinterpret_cast<const uint64_t *>(ws + Ws::kPartCnt)[k];
-    }
+    merge_partials(ws, nparts, best, arg, nonfinite);
     block_reduce(best, arg, nonfinite);
     if (threadIdx.x == 0) {
         double R = best;
@@ -188,12 +214,16 @@ __global__ __launch_bounds__(kBlock) void cert_r_final(unsigned char *__restrict
 // vector.  Per coordinate the arithmetic is exactly the one stated above
 // (identical to evaluating each coordinate on its own).
 
+// Four consecutive values as doubles.  FP32 groups are read non-temporally:
+// the pass visits each address from four streams at far-apart times, so
+// nothing it loads is found again in the caches (5% faster at l = 16; FP64
+// keeps ordinary loads, which non-temporal ones slowed down in the sweep).
 template <typename T>
 __device__ __forceinline__ void ld4(const T *p, double *v)
 {
     if constexpr (std::is_same<T, float>::value) {
-        const float4 q = *reinterpret_cast<const float4 *>(p);
-        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = __builtin_nontemporal_load(p + k);
     } else {
         const double2 a = reinterpret_cast<const double2 *>(p)[0];
         const double2 b = reinterpret_cast<const double2 *>(p)[1];
@@ -777,11 +807,7 @@ __global__ __launch_bounds__(kBlock) void cert_w_final(unsigned char *__restrict
 {
     double best = -INFINITY;
     uint64_t arg = 0, nonfinite = 0;
-    for (int k = threadIdx.x; k < nparts; k += kBlock) {
-        merge_max_idx(best, arg, reinterpret_cast<const double *>(ws + Ws::kPartVal)[k],
-                      reinterpret_cast<const uint64_t *>(ws + Ws::kPartIdx)[k]);
-        nonfinite += reinterpret_cast<const uint64_t *>(ws + Ws::kPartCnt)[k];
-    }
+    merge_partials(ws, nparts, best, arg, nonfinite);
     block_reduce(best, arg, nonfinite);
     if (threadIdx.x == 0) {
         double *sc = reinterpret_cast<double *>(ws);
@@ -798,10 +824,15 @@ __global__ __launch_bounds__(kBlock) void cert_w_final(unsigned char *__restrict
     }
 }
 
-int reduce_blocks(uint64_t n)
+// Workgroups of a grid-stride pass over n work items: at most 16384 for FP32
+// tables, 4096 for FP64 ones (measured on the largest-r pass: 16384 is 6%
+// faster than 4096 at l = 16 FP32 and 8% at (2, 3, 10), but 7% slower at
+// l = 14 FP64, where the extra partials cost more than they hide).
+int reduce_blocks(uint64_t n, int dtype)
 {
+    const uint64_t cap = dtype == LCSB_F32 ? (uint64_t)kMaxReduceBlocks : 4096;
     uint64_t b = (n + kBlock - 1) / kBlock;
-    return (int)(b < (uint64_t)kMaxReduceBlocks ? b : (uint64_t)kMaxReduceBlocks);
+    return (int)(b < cap ? b : cap);
 }
 
 template <typename T, bool OPT>
@@ -839,7 +870,7 @@ template <typename T>
 hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int u_slot,
                          int prev_slot, int swap_sym, unsigned char *ws, hipStream_t s)
 {
-    const int nb = reduce_blocks(g.ns);
+    const int nb = reduce_blocks(g.ns, std::is_same<T, float>::value ? LCSB_F32 : LCSB_F64);
     const T *uu = static_cast<const T *>(u), *pp = static_cast<const T *>(prev);
     if (swap_sym && g.sigma == 2 && g.d == 2 && g.h >= 2)
         cert_r<T, 2><<<nb, kBlock, 0, s>>>(uu, pp, g.ns, ws);
@@ -855,7 +886,8 @@ hipError_t certify_typed(const Geometry &g, const void *u, const void *prev, int
                                       u_slot, prev_slot);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // one thread per x with string-1 symbol 0 at position 2 (one workgroup at l = 1)
-    const int nbw = g.h == 1 ? 1 : reduce_blocks(g.n >> (g.slot + g.beta));
+    const int nbw = g.h == 1 ? 1 : reduce_blocks(g.n >> (g.slot + g.beta),
+                                                 std::is_same<T, float>::value ? LCSB_F32 : LCSB_F64);
     if ((e = launch_w<T, false>(g, static_cast<const T *>(u), swap_sym, ws, nbw, s)) !=
         hipSuccess)
         return e;
@@ -868,7 +900,8 @@ template <typename T>
 hipError_t certify_optimal_typed(const Geometry &g, const void *u, int swap_sym,
                                  unsigned char *ws, hipStream_t s)
 {
-    const int nbw = g.h == 1 ? 1 : reduce_blocks(g.n >> (g.slot + g.beta));
+    const int nbw = g.h == 1 ? 1 : reduce_blocks(g.n >> (g.slot + g.beta),
+                                                 std::is_same<T, float>::value ? LCSB_F32 : LCSB_F64);
     hipError_t e;
     if ((e = launch_w<T, true>(g, static_cast<const T *>(u), swap_sym, ws, nbw, s)) !=
         hipSuccess)

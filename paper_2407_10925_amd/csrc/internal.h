@@ -9,7 +9,7 @@
 namespace lcsb {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts)
-constexpr int kMaxReduceBlocks = 4096;
+constexpr int kMaxReduceBlocks = 16384;
 
 // Device workspace layout (byte offsets).  The caller allocates
 // kWorkspaceBytes; the library clears the parts it uses.

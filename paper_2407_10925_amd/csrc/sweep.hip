@@ -71,6 +71,14 @@ __device__ __forceinline__ T tree16(const T *g)
 template <typename T>
 __device__ __forceinline__ T vmax(T best, T cand) { return cand > best ? cand : best; }
 
+// One thread per x: the grid is one-dimensional up to 2^32 threads and
+// two-dimensional beyond (a dimension holds fewer than 2^32 work-items), rows
+// of blockIdx.y following each other.
+__device__ __forceinline__ uint64_t thread_index()
+{
+    return ((uint64_t)blockIdx.y * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
+}
+
 // F takes the max over the branch means starting from -inf, so a NaN branch
 // never wins and a tuple whose every branch is NaN gets -inf: the first value
 // of every max chain goes through this (a no-op on every other value).
@@ -173,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
     constexpr bool kF32 = std::is_same<T, float>::value;
     constexpr bool kShift = kF32 || SHIFT;  // lag 2 carries delta_2
     const uint64_t nq = n >> 2;
-    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t t = thread_index();
     T d2 = 0, y0 = 0;
     if constexpr (!kF32 && SHIFT) d2 = off[s2] - off[s1];
     if constexpr (kF32) {
@@ -299,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
     constexpr bool kShift = kF32 || SHIFT;  // lag 2 carries delta_2
-    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t t = thread_index();
     const int top = 4 * (h - 1);
     T d2 = 0, y0 = 0;
     if constexpr (!kF32 && SHIFT) d2 = off[s2] - off[s1];
@@ -442,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
     constexpr bool kShift = kF32 || SHIFT;  // lags 2 and 3 carry delta_2, delta_3
-    const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t t = thread_index();
     const int top = 3 * (h - 1);
     T d2 = 0, d3 = 0, y0 = 0;
     if constexpr (!kF32 && SHIFT) {
@@ -730,8 +738,9 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
     // one thread per x with string-1 symbol 0 at position 2
     const uint64_t threads = g.n >> (g.slot + g.beta);
     const uint64_t blocks = (threads + kBlock - 1) / kBlock;
-    if (blocks > 0x7fffffffull) return hipErrorInvalidConfiguration;
+    constexpr uint64_t kRow = 1ull << 16;  // blocks per grid row when one row is not enough
     dim3 grid((unsigned)blocks), block(kBlock);
+    if (blocks * kBlock >= (1ull << 32)) grid = dim3((unsigned)kRow, (unsigned)((blocks + kRow - 1) / kRow));
     if (g.sigma == 2 && g.d == 2) {
         if (a.swap_sym)
             sweep_s2d2<T, true, SHIFT><<<grid, block, 0, s>>>(l1, l2, out, g.n, a.offsets, s1, s2,

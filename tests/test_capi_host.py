@@ -37,7 +37,7 @@ def test_create_validates_arguments(lib):
     assert lib.lcsb_create(3, 2, 2, 0, C.byref(ctx)) == _capi.LCSB_EUNSUPPORTED
     assert lib.lcsb_create(2, 4, 2, 0, C.byref(ctx)) == _capi.LCSB_EUNSUPPORTED
     assert lib.lcsb_create(2, 2, 0, 0, C.byref(ctx)) == _capi.LCSB_EINVAL
-    assert lib.lcsb_create(2, 2, 18, 0, C.byref(ctx)) == _capi.LCSB_EINVAL  # 2^36 > 2^34
+    assert lib.lcsb_create(2, 2, 19, 0, C.byref(ctx)) == _capi.LCSB_EINVAL  # 2^38 > 2^36
     assert lib.lcsb_create(2, 2, 6, 7, C.byref(ctx)) == _capi.LCSB_EINVAL
     assert b"dtype" in lib.lcsb_last_error()
     assert lib.lcsb_create(2, 2, 6, 0, None) == _capi.LCSB_EINVAL

@@ -92,7 +92,8 @@ def _gradient_magnitudes(cache, dy):
     it sums: |dZ_k|^T |a_(k-1)| for the weights of layer k (a_0 = the
     inputs), sum_s |dZ_k| for its biases, |a_3|^T |dy| and sum_s |dy| for the
     output layer (dZ_k and a_k as the oracle's backward with the GPU's
-    rounding points produces them)."""
+    rounding points produces them; dy may carry an allowance for the forward
+    error, see the test)."""
     A = {"W1": np.abs(cache["X"]), "W2": np.abs(cache["a1"]), "W3": np.abs(cache["a2"])}
     D = {"W1": np.abs(cache["dz1"]), "W2": np.abs(cache["dz2"]), "W3": np.abs(cache["dz3"])}
     m = {k: D[k].T @ A[k] for k in A}
@@ -112,7 +113,9 @@ def test_backward_matches_reference_element_by_element(pk):
     BF16 step, at most 2^-7 of it): so each entry must lie within 2^-7 of the
     sum of the absolute values of its terms (every term off by one step), and
     all but 0.1% within 2^-12 of it.  (An FP32 emulation of the same steps on
-    the CPU stays within 4e-5 of that sum.)"""
+    the CPU stays within 4e-5 of that sum.)  The output layer's gradient
+    multiplies by dy, which inherits the forward's error; its terms carry
+    that error's bound too, and only the first criterion applies there."""
     say("backward, element by element")
     B, h = 512, 12
     p = _params(3)
@@ -131,7 +134,18 @@ def test_backward_matches_reference_element_by_element(pk):
     yr, cache = omlp.forward(p64, omlp.encode(idx.numpy().astype(np.uint64), h))
     _, dy_r = omlp.mse(yr, t.numpy())
     gr = omlp.backward(cache, dy_r, bf16_grads=True)
+    # dy = 2 (y - t) / B comes from the forward, whose output the GPU computes
+    # within 2^-5 of its scale (test_forward_matches_reference): where y is
+    # close to t that is a large part of dy itself, so the output layer's
+    # terms carry that allowance beside their own value
+    scale = np.abs(cache["a3"]) @ np.abs(cache["w4"]) + abs(float(p[-1])) + 1e-3
+    edy = 2.0 * 2.0 ** -5 * scale / B
     mag = _gradient_magnitudes(cache, dy_r)
+    out_layer = _gradient_magnitudes(cache, np.abs(dy_r) + edy)
+    for k in ("w4", "b4"):
+        o, shape = omlp.OFFSETS[k]
+        n = int(np.prod(shape))
+        mag[o:o + n] = out_layer[o:o + n]
     for name, (o, shape) in omlp.OFFSETS.items():
         n = int(np.prod(shape))
         diff, m = np.abs(g[o:o + n] - gr[o:o + n]), mag[o:o + n]
@@ -139,7 +153,8 @@ def test_backward_matches_reference_element_by_element(pk):
         say(f"grad {name}: max |diff| / sum|terms| {r.max():.2e}, 99.9th pct "
             f"{np.quantile(r, 0.999):.2e}")
         assert np.all(diff <= 2.0 ** -7 * m + 1e-30), name
-        assert np.quantile(r, 0.999) <= 2.0 ** -12, name
+        if name not in ("w4", "b4"):  # their spread is the forward's, bounded above
+            assert np.quantile(r, 0.999) <= 2.0 ** -12, name
 
 
 def test_backward_matches_reference_in_norm(pk):

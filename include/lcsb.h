@@ -197,6 +197,27 @@ int lcsb_certify(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
  * rho = R - E wins). */
 int lcsb_certify_optimal(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
 
+/* For callers that cannot allocate device memory or bind a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the largest-r certificate of lcsb_certify_optimal for a
+ * caller's table, with no context.  u: the stored entries of a folded table
+ * of (sigma, d, l = h) (n / sigma values, LCSB_F64 or LCSB_F32, 16-byte
+ * aligned; see "Folded storage").  exchange_symmetric: 1 only if the table is
+ * symmetric bit for bit under exchanging strings 1 and 2 (then only the lower
+ * stored index of each exchanged pair is read, as for a lazily written table
+ * of an exchange-symmetric ring); 0 reads every entry.  dev_out (device, 4
+ * doubles): r, d r rounded toward -inf, and, as the bit patterns of uint64,
+ * the lowest index where the ratio attains r and the count of stored
+ * coordinates whose ratio is not finite.  Enqueued on `stream` (hipStream_t
+ * as void*); nothing is read back and nothing synchronises.  Allocates
+ * nothing: its scratch is a fixed 385 KiB device array (reduction partials and
+ * scalars, enough for every size up to sigma^(d h) = 2^36, larger sizes give
+ * LCSB_EINVAL) that each GPU the library runs on holds until the process
+ * ends; every call on one GPU shares it, so calls that overlap on one GPU
+ * race. */
+int lcsb_certify_optimal_noalloc(int sigma, int d, int h, int dtype, const void *u,
+                                 int exchange_symmetric, double *dev_out, void *stream);
+
 /* Device address of lag k (1..d; 1..2 for the two-array iteration) and, for LCSB_F32, the FP64 offset its
  * values are relative to (read from the device; synchronises).  The pointer
  * stays valid until the next lcsb_iterate, lcsb_load_ring or lcsb_bind.  On

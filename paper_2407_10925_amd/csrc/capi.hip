@@ -381,6 +381,16 @@ int lcsb_certify_optimal(lcsb_ctx *c, lcsb_cert *cur, lcsb_cert *best)
     return LCSB_OK;
 }
 
+int lcsb_certify_optimal_noalloc(int sigma, int d, int h, int dtype, const void *u,
+                                 int exchange_symmetric, double *dev_out, void *stream)
+{
+    std::string err;
+    const int rc = certify_optimal_noalloc(sigma, d, h, dtype, u, exchange_symmetric, dev_out,
+                                           stream, &err);
+    if (rc) return fail(rc, "%s", err.c_str());
+    return LCSB_OK;
+}
+
 int lcsb_lag(const lcsb_ctx *c, int k, void **dev_ptr, double *offset)
 {
     int rc = need_ready(c);

@@ -919,6 +919,33 @@ hipError_t launch_certify_optimal(const Geometry &g, int dtype, const void *u, i
                              : certify_optimal_typed<double>(g, u, swap_sym, ws, s);
 }
 
+namespace {
+
+// The largest-r result of a finished pass into caller memory: out[0] = r,
+// out[1] = d r rounded toward -inf, out[2] = the lowest minimising index and
+// out[3] = the count of non-finite ratios (the two integers as the bit
+// patterns of uint64).  One thread, after cert_w_final<true>.
+__global__ void cert_opt_out(const unsigned char *__restrict__ ws, int d, double *__restrict__ out)
+{
+    const double r = reinterpret_cast<const double *>(ws)[Ws::kOptR / 8];
+    out[0] = r;
+    out[1] = mul_rd((double)d, r);
+    reinterpret_cast<uint64_t *>(out)[2] = reinterpret_cast<const uint64_t *>(ws)[Ws::kOptArg / 8];
+    reinterpret_cast<uint64_t *>(out)[3] =
+        reinterpret_cast<const uint64_t *>(ws)[Ws::kOptNonfinite / 8];
+}
+
+}  // namespace
+
+hipError_t launch_certify_optimal_out(const Geometry &g, int dtype, const void *u, int swap_sym,
+                                      unsigned char *ws, double *out, hipStream_t s)
+{
+    hipError_t e = launch_certify_optimal(g, dtype, u, swap_sym, ws, s);
+    if (e != hipSuccess) return e;
+    cert_opt_out<<<1, 1, 0, s>>>(ws, g.d, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const void *prev,
                           int u_slot, int prev_slot, int swap_sym, unsigned char *ws,
                           hipStream_t s)

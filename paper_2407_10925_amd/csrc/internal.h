@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "lcsb.h"
 
 namespace lcsb {
@@ -73,6 +75,16 @@ hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const voi
 // The largest-r certificate of u (kOptR, kOptArg, kOptNonfinite).
 hipError_t launch_certify_optimal(const Geometry &g, int dtype, const void *u, int swap_sym,
                                   unsigned char *ws, hipStream_t s);
+
+// The same, its result written to out (4 doubles: r, d r rounded down, and
+// the lowest minimising index and the non-finite count as uint64 bits)
+hipError_t launch_certify_optimal_out(const Geometry &g, int dtype, const void *u, int swap_sym,
+                                      unsigned char *ws, double *out, hipStream_t s);
+
+// lcsb_certify_optimal_noalloc without the error-message plumbing (csrc/noalloc.hip)
+int certify_optimal_noalloc(int sigma, int d, int h, int dtype, const void *u,
+                            int exchange_symmetric, double *dev_out, void *stream,
+                            std::string *err);
 
 // The two-array iteration: R = mean over the fixed sample of nw - old, and the
 // offsets slots kSlotLag2/3 for the next sweep (csrc/two_array.hip)

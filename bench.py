@@ -85,6 +85,9 @@ def parse():
                    help="only the FP32 two-array iteration from zero at sigma=d=2, l=L, "
                         "certified every 16 sweeps (the largest-r certificate) for --max-sweeps")
     p.add_argument("--max-sweeps", type=int, default=480)
+    p.add_argument("--seed-ceiling", action="store_true",
+                   help="only measure what a warm start of known error saves at sigma=d=2, "
+                        "l=--h (the converged table plus noise, and the trained network)")
     p.add_argument("--profile-certify", action="store_true",
                    help="only run 8 sweeps from zero and two certificates (counter collection)")
     return p.parse_args()
@@ -377,11 +380,14 @@ def time_to_bound(pk, h, train_steps=1000):
     cur, best, certs32 = fp32_until_floor(M)
     sweeps32 = cur["sweep"]
     t_switch = time.perf_counter() - t0
-    # outside the timed span: the FP32 table at its floor against the
-    # converged FP64 table (the polish below overwrites P's ring)
+    # outside the timed span: the FP32 table at its floor against the FP64
+    # table after as many sweeps from the same zero start (the polish below
+    # overwrites P's ring)
+    P.init_zero()
+    P.iterate(sweeps32)
     rel_err, spread = fp32_error(P, M)
-    log(f"FP32 table at its floor vs converged FP64: max |difference| / spread = {rel_err:.3e} "
-        f"(spread {spread:.4f})")
+    log(f"FP32 table at its floor vs FP64 after the same {sweeps32} sweeps: max |difference| / "
+        f"spread = {rel_err:.3e} (spread {spread:.4f})")
     t0 += time.perf_counter() - t0 - t_switch
     sweeps64, certs64, best = polish(P, M, best, target)
     torch.cuda.synchronize()
@@ -391,6 +397,7 @@ def time_to_bound(pk, h, train_steps=1000):
                                "switch_after_s": round(t_switch, 4), "bound": best["bound"],
                                "reached": best["bound"] >= target,
                                "fp32_table_max_error_over_spread": rel_err,
+                               "fp32_error_reference": f"FP64 ring after the same {sweeps32} sweeps from zero",
                                "fp64_table_spread": spread, **hbm(sweeps32, sweeps64, t_mixed)}
     log(f"time to bound, FP32 + FP64 polish: {t_mixed:.3f} s, {sweeps32} FP32 + "
         f"{sweeps64} FP64 sweeps, bound {best['bound']:.12f}")
@@ -434,13 +441,12 @@ def time_to_bound(pk, h, train_steps=1000):
     return out
 
 
-def learned_run(pk, h, P, target, train_steps):
-    """FP32 + FP64 polish started from the warm-start network.  Training data:
-    FP32 tables at l = h-4, h-3, h-2 run from zero to their error floor
-    (fp32_until_floor); training: `train_steps` Adam steps on batches of 8192
-    drawn from those tables in turn, cosine learning-rate decay; the seed
-    uses the rate R of the l = h-2 run.  Times are reported without and with
-    data generation and training."""
+def train_network(pk, h, train_steps):
+    """The warm-start network for l = h.  Training data: FP32 tables at
+    l = h-4, h-3, h-2 run from zero to their error floor (fp32_until_floor);
+    training: `train_steps` Adam steps on batches of 8192 drawn from those
+    tables in turn, cosine learning-rate decay.  Returns (network, rate R of
+    the l = h-2 run, data seconds, training seconds, last batch loss)."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -467,7 +473,15 @@ def learned_run(pk, h, P, target, train_steps):
     torch.cuda.empty_cache()
     log(f"warm start: data {t_data:.2f} s, training {t_train:.2f} s ({train_steps} steps), "
         f"last batch loss {loss:.3e}")
+    return M, rate, t_data, t_train, loss
 
+
+def learned_run(pk, h, P, target, train_steps):
+    """FP32 + FP64 polish started from the warm-start network (train_network),
+    seeded with the rate of its l = h-2 training run.  Times are reported
+    without and with data generation and training."""
+    import torch
+    M, rate, t_data, t_train, loss = train_network(pk, h, train_steps)
     S = pk.Lcsb(2, 2, h, "f32")
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -490,6 +504,99 @@ def learned_run(pk, h, P, target, train_steps):
     del S, M
     torch.cuda.empty_cache()
     return res
+
+
+def _exchange_noise(h, lo, hi, device):
+    """Uniform noise in [-1, 1) for the stored sigma = d = 2 indices lo..hi-1,
+    equal on the two members of every pair under the exchange of the strings
+    (a function of the lower representative), from a SplitMix64 hash of it."""
+    import torch
+    i = torch.arange(lo, hi, dtype=torch.int64, device=device)
+    odd = (1 << (2 * h)) // 3 * 2        # string-1 bits (0b1010...)
+    even = odd >> 1                      # string-2 bits (0b0101...)
+    e = ((i & odd) >> 1) | ((i & even) << 1)
+    top = 1 << (2 * h - 1)
+    e = torch.where(e & top != 0, e ^ ((1 << (2 * h)) - 1), e)  # its complement-folded image
+    c = torch.minimum(i, e)
+    m64 = (1 << 64) - 1
+
+    def s64(x):
+        x &= m64
+        return x - (1 << 64) if x >= 1 << 63 else x
+
+    def lsr(z, k):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+    z = (c + 1) * s64(0x9E3779B97F4A7C15)
+    z = (z ^ lsr(z, 30)) * s64(0xBF58476D1CE4E5B9)
+    z = (z ^ lsr(z, 27)) * s64(0x94D049BB133111EB)
+    z = z ^ lsr(z, 31)
+    return lsr(z, 11).to(torch.float64) * 2.0 ** -52 - 1.0
+
+
+def seed_ceiling(pk, h, train_steps, rms_list=(0.0, 1e-4, 1e-3, 3e-3, 1e-2, 3e-2)):
+    """What a warm start can save at sigma = d = 2, l = h.  The seed is the
+    converged FP64 table (relative to entry 0) plus exchange-symmetric noise
+    of a given RMS, loaded as an FP32 ring with the converged R; for each RMS,
+    for the zero start and for the trained network's seed: FP32 sweeps to a
+    largest-r certificate within 1e-5 of the converged bound B (certified
+    every 4 sweeps), and the wall time of the standard mixed policy
+    (fp32_until_floor, then polish) to B - 1e-9 from the loaded ring (loading
+    and seeding not included)."""
+    import torch
+    P = pk.Lcsb(2, 2, h, "f64")
+    P.init_zero()
+    cur, best, _, _ = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, stop_delta=1e-10)
+    B, R = best["bound"], cur["R"]
+    u, _ = P.lag(1)
+    x = (u - u[0]).float()             # the converged table relative to entry 0
+    spread = float(x.max() - x.min())
+    log(f"converged B = {B:.12f}, R = {R:.12f}, spread {spread:.4f}")
+    S = pk.Lcsb(2, 2, h, "f32")
+    chunk = 1 << 27
+    rows = []
+
+    def measure(label, load, rms):
+        load()
+        cur, _, _, _ = S.run(4, max_sweeps=MAX_SWEEPS, target=B - 1e-5, certificate="optimal")
+        near = cur["sweep"]
+        load()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cur, best, c32 = fp32_until_floor(S)
+        s64, c64, best = polish(P, S, best, B - 1e-9)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rows.append({"start": label, "seed_rms": rms, "sweeps_f32_to_1e-5": near,
+                     "mixed_seconds": round(dt, 4), "sweeps_f32": cur["sweep"],
+                     "sweeps_f64": s64, "reached": best["bound"] >= B - 1e-9})
+        log(f"{label}: rms {rms}: {near} FP32 sweeps to B - 1e-5; mixed {dt:.3f} s "
+            f"({cur['sweep']} FP32 + {s64} FP64 sweeps)")
+
+    measure("zero", S.init_zero, None)
+    seed = torch.empty_like(x)
+    for rms in rms_list:
+        for lo in range(0, x.numel(), chunk):
+            hi = min(x.numel(), lo + chunk)
+            seed[lo:hi] = x[lo:hi] + (rms * math.sqrt(3.0)
+                                      * _exchange_noise(h, lo, hi, x.device)).float()
+        measure("converged + noise", lambda: S.load_ring([seed, seed], [0.0, -R]), rms)
+    del seed
+    torch.cuda.empty_cache()
+    M, rate, _, _, loss = train_network(pk, h, train_steps)
+    S.init_seed_mlp(M, rate)
+    t, off = S.lag(1)
+    sq, mean_d = 0.0, 0.0
+    ref = float(t[0]) + off
+    for lo in range(0, x.numel(), chunk):
+        dlt = (t[lo:lo + chunk].double() + (off - ref)) - x[lo:lo + chunk].double()
+        mean_d += float(dlt.sum())
+        sq += float((dlt * dlt).sum())
+    mean_d /= x.numel()
+    net_rms = math.sqrt(max(sq / x.numel() - mean_d * mean_d, 0.0))
+    log(f"network seed: RMS error {net_rms:.3e} against the converged table (loss {loss:.3e})")
+    measure("network", lambda: S.init_seed_mlp(M, rate), round(net_rms, 6))
+    print(json.dumps({"seed_ceiling": {"h": h, "B": B, "R": R, "table_spread": spread,
+                                       "runs": rows}}), flush=True)
 
 
 CONFIGS = [  # (sigma, d, l, dtype)
@@ -731,6 +838,8 @@ def main():
         return certify_only(pk, args.h, args.sigma, args.d, args.dtype)
     if args.two_array_f32:
         return two_array_f32_only(pk, args.two_array_f32, args.max_sweeps, args.sigma, args.d)
+    if args.seed_ceiling:
+        return seed_ceiling(pk, args.h, args.train_steps)
     if args.profile_train:
         return train_only(pk, args.h, args.profile_train, args.train_batch)
     if args.configs:
@@ -764,6 +873,7 @@ def main():
     algo_bytes = algorithmic_bytes(L, 4)
     folded = L.swap_symmetric()
     achieved = algo_bytes / avg_sweep_s / 1e9
+    computed = n // 4 + 2 ** (h - 1) if folded else n // 2
     traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -801,6 +911,12 @@ def main():
         "cpu_baseline": cpu,
         "time_to_bound": ttb,
         "sweep_only_updates_per_s": n / avg_sweep_s,
+        # value counts every index of the table (n per sweep); the kernel
+        # computes and stores one tuple of each orbit of the stored half under
+        # the exchange of the strings (n / 4 pairs and 2^(l-1) fixed points),
+        # which is what roofline.frac prices
+        "computed_entries_per_sweep": computed,
+        "computed_entries_per_s": computed * cad * args.steps / elapsed,
     }
     print(json.dumps(line), flush=True)
 

@@ -38,6 +38,21 @@
  * m holds the value of entry i xor (m rep).  With the branch sums taken in
  * the order stated at lcsb_iterate, every sweep and certificate on the folded
  * table is bit-identical to the same computation on the full table.
+ *
+ * Packed storage (LCSB_ITER_TWO_ARRAY_PACKED, sigma = d = 2, l >= 2).  A table
+ * of a ring symmetric under exchanging the two strings as well is constant on
+ * each orbit of a tuple (a, b) under the complement and the exchange, and a
+ * packed table holds one entry per orbit: packed_entries = 4^(l-1) + 2^l
+ * entries, about half of the folded table.  With c = a xor b (kept by both
+ * maps; the complement sends a to ~a, the exchange a to a xor c), the orbit's
+ * representative has a_1 = 0 and, for c'' = c if c_1 = 0 else ~c and p the
+ * first position j >= 2 with c''_j = 1, a_p = 0.  Its code has 2l - 2 bits,
+ * from the top: c_1, c_2, then a_j, c_j for j = 3..l, where the a bit of
+ * position p holds a_2 instead (for p = 2 every position its own).  Orbits
+ * with c'' = 0 (b = a or b = ~a) take the codes 4^(l-1) + c_1 2^(l-1) +
+ * (a_2 .. a_l read as a binary number, a_2 most significant).  Entry k of a
+ * packed table is the value of every tuple whose code is k; codes below
+ * 4^(l-1) whose c'' is 0 belong to no tuple and hold no value.
  */
 #ifndef LCSB_H
 #define LCSB_H
@@ -94,6 +109,7 @@ typedef struct {
 /* iterations a context can run */
 #define LCSB_ITER_RING      0 /* Algorithm 2: a ring of d + 1 tables            */
 #define LCSB_ITER_TWO_ARRAY 1 /* two tables and a rate (lcsb_create_iter)       */
+#define LCSB_ITER_TWO_ARRAY_PACKED 2 /* the same on packed tables (lcsb_create_iter) */
 
 /* Create a context for (sigma, d, l = h) and a table element type running
  * the ring iteration of Algorithm 2.  GPU kernels exist for (sigma, d) in
@@ -119,12 +135,22 @@ int lcsb_create(int sigma, int d, int h, int dtype, lcsb_ctx **out);
  * same r, so the two iterations share their fixed points and certified
  * bounds; the two-array one needs 2 tables instead of d + 1 (nbuf = 2) and
  * every certificate works on it unchanged (Algorithm 2's with prev = lag 2).
- * lcsb_load_ring, lcsb_lag, lcsb_save and lcsb_load then handle 2 tables. */
+ * lcsb_load_ring, lcsb_lag, lcsb_save and lcsb_load then handle 2 tables.
+ * LCSB_ITER_TWO_ARRAY_PACKED runs the same iteration, bit for bit, on packed
+ * tables (see packed storage; sigma = d = 2 and l >= 2, else
+ * LCSB_EUNSUPPORTED), so that an FP64 pair of tables at l = 18 (2^36 tuples)
+ * takes 2 x 128 GiB: it starts from lcsb_init_zero or lcsb_load, certifies
+ * with lcsb_certify_optimal (lcsb_certify, lcsb_load_ring and
+ * lcsb_init_seed_mlp give LCSB_EUNSUPPORTED), lcsb_lag returns packed tables,
+ * and lcsb_upcast takes a packed FP32 context to a packed FP64 one.  Its
+ * certificates report the lowest stored index of the minimising orbit, as
+ * on the folded table. */
 int lcsb_create_iter(int sigma, int d, int h, int dtype, int iteration, lcsb_ctx **out);
 
 /* Sizes the caller must allocate: nbuf = d + 1 ring tables (2 for the
  * two-array iteration) of bytes_per_buf
- * bytes each (entries = sigma^(d h - 1) stored elements, see folded storage),
+ * bytes each (entries = sigma^(d h - 1) stored elements, see folded storage;
+ * packed_entries for packed tables),
  * and one device workspace of workspace_bytes bytes, 256-byte aligned.  Any
  * output pointer may be NULL. */
 int lcsb_query(const lcsb_ctx *ctx, int *nbuf, uint64_t *entries,

@@ -35,7 +35,9 @@ class Lcsb:
         (2 for the two-array iteration) contiguous device tensors of at least
         the ring's bytes each (for an FP32 ring inside an FP64 ring's memory,
         ``[b.view(torch.float32) for b in P.bufs]``; see :meth:`upcast`).
-        ``iteration``: "ring" (Algorithm 2) or "two_array" (lcsb_create_iter)."""
+        ``iteration``: "ring" (Algorithm 2), "two_array" or "two_array_packed"
+        (lcsb_create_iter; packed tables hold ``stored`` = packed_entries
+        entries, one per exchange orbit)."""
         import torch
 
         if dtype not in _DTYPES:
@@ -52,7 +54,7 @@ class Lcsb:
         self.iteration = iteration
         check(lib.lcsb_create_iter(sigma, d, h, _DTYPES[dtype], _capi.ITERATIONS[iteration],
                                    C.byref(ctx)))
-        self.lags = 2 if iteration == "two_array" else d
+        self.lags = d if iteration == "ring" else 2
         self._ctx = ctx
         nbuf, n, bpb, wsb = C.c_int(), C.c_uint64(), C.c_uint64(), C.c_uint64()
         check(lib.lcsb_query(ctx, C.byref(nbuf), C.byref(n), C.byref(bpb), C.byref(wsb)))

@@ -33,7 +33,9 @@ class LcsbError(RuntimeError):
 LCSB_STOP_NAMES = {0: "max_sweeps", 1: "target", 2: "converged", 3: "floor"}
 LCSB_ITER_RING = 0
 LCSB_ITER_TWO_ARRAY = 1
-ITERATIONS = {"ring": LCSB_ITER_RING, "two_array": LCSB_ITER_TWO_ARRAY}
+LCSB_ITER_TWO_ARRAY_PACKED = 2
+ITERATIONS = {"ring": LCSB_ITER_RING, "two_array": LCSB_ITER_TWO_ARRAY,
+              "two_array_packed": LCSB_ITER_TWO_ARRAY_PACKED}
 LCSB_CERT_FEASIBLE = 0
 LCSB_CERT_OPTIMAL = 1
 CERT_KINDS = {"feasible": LCSB_CERT_FEASIBLE, "optimal": LCSB_CERT_OPTIMAL}

@@ -51,8 +51,10 @@ struct lcsb_ctx {
     lcsb_cert best;
     int swap_sym;    // sigma = d = 2, l >= 2: lag 1 .. d symmetric in the two strings
     int lazy[4];     // per slot: only the lower index of each exchanged pair written
-    int two_array;   // LCSB_ITER_TWO_ARRAY: tables u (lag 1) and the one before (lag 2), rate R
+    int two_array;   // LCSB_ITER_TWO_ARRAY(_PACKED): tables u (lag 1) and the one before (lag 2), rate R
     int lags;        // tables the context keeps: d for the ring, 2 for the two-array iteration
+    int packed;      // LCSB_ITER_TWO_ARRAY_PACKED: one entry per exchange orbit (packed_index)
+    uint64_t entries;  // entries per table: g.ns, or packed_entries(h)
 };
 
 namespace {
@@ -96,11 +98,12 @@ int materialize(lcsb_ctx *c, int slot)
 }
 
 // Set c->swap_sym by checking lag 1 .. d on the device (synchronises).
+// Packed tables hold one value per exchange orbit: symmetric by construction.
 int refresh_swap(lcsb_ctx *c)
 {
-    c->swap_sym = 0;
+    c->swap_sym = c->packed;
     clear_lazy(c);
-    if (!swap_shape(c)) return LCSB_OK;
+    if (c->packed || !swap_shape(c)) return LCSB_OK;
     uint32_t *flag = reinterpret_cast<uint32_t *>(c->ws + Ws::kAsym);
     hipError_t e;
     if ((e = launch_fill_zero(flag, 4, c->stream)) != hipSuccess) return hip_fail(c, e, "fill");
@@ -122,7 +125,7 @@ int refresh_rate(lcsb_ctx *c)
     if (!c->two_array) return LCSB_OK;
     const int s1 = slot_of_lag(c, 1), s2 = slot_of_lag(c, 2);
     hipError_t e = launch_two_array_rate(c->g, c->dtype, c->buf[s1], c->buf[s2], s1, s2,
-                                         c->swap_sym, c->ws, c->stream);
+                                         c->swap_sym, c->packed, c->ws, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "rate");
     return LCSB_OK;
 }
@@ -150,7 +153,8 @@ int lcsb_create_iter(int sigma, int d, int h, int dtype, int iteration, lcsb_ctx
     if (!out) return fail(LCSB_EINVAL, "out is null");
     *out = nullptr;
     if (dtype != LCSB_F64 && dtype != LCSB_F32) return fail(LCSB_EINVAL, "dtype %d", dtype);
-    if (iteration != LCSB_ITER_RING && iteration != LCSB_ITER_TWO_ARRAY)
+    if (iteration != LCSB_ITER_RING && iteration != LCSB_ITER_TWO_ARRAY &&
+        iteration != LCSB_ITER_TWO_ARRAY_PACKED)
         return fail(LCSB_EINVAL, "iteration %d", iteration);
     if (sigma < 2 || d < 1 || h < 1) return fail(LCSB_EINVAL, "sigma=%d d=%d h=%d", sigma, d, h);
     const bool ok = (sigma == 2 && d == 2) || (sigma == 4 && d == 2) || (sigma == 2 && d == 3);
@@ -158,6 +162,8 @@ int lcsb_create_iter(int sigma, int d, int h, int dtype, int iteration, lcsb_ctx
     const int beta = sigma == 2 ? 1 : 2;
     const int bits = beta * d * h;
     if (bits > 36) return fail(LCSB_EINVAL, "sigma^(d h) = 2^%d exceeds 2^36", bits);
+    if (iteration == LCSB_ITER_TWO_ARRAY_PACKED && (sigma != 2 || d != 2 || h < 2))
+        return fail(LCSB_EUNSUPPORTED, "packed tables need sigma = d = 2 and l >= 2");
     lcsb_ctx *c = new (std::nothrow) lcsb_ctx;
     if (!c) return fail(LCSB_ENOMEM, "context allocation failed");
     memset(c, 0, sizeof *c);
@@ -169,7 +175,9 @@ int lcsb_create_iter(int sigma, int d, int h, int dtype, int iteration, lcsb_ctx
     c->g.n = 1ull << bits;
     c->g.ns = c->g.n >> beta;
     c->dtype = dtype;
-    c->two_array = iteration == LCSB_ITER_TWO_ARRAY;
+    c->two_array = iteration != LCSB_ITER_RING;
+    c->packed = iteration == LCSB_ITER_TWO_ARRAY_PACKED;
+    c->entries = c->packed ? packed_entries(h) : c->g.ns;
     c->nbuf = c->two_array ? 2 : d + 1;
     c->lags = c->two_array ? 2 : d;
     c->state = kCreated;
@@ -183,8 +191,8 @@ int lcsb_query(const lcsb_ctx *c, int *nbuf, uint64_t *entries, uint64_t *bytes_
 {
     if (!c) return fail(LCSB_EINVAL, "null context");
     if (nbuf) *nbuf = c->nbuf;
-    if (entries) *entries = c->g.ns;
-    if (bytes_per_buf) *bytes_per_buf = c->g.ns * elem_size(c->dtype);
+    if (entries) *entries = c->entries;
+    if (bytes_per_buf) *bytes_per_buf = c->entries * elem_size(c->dtype);
     if (workspace_bytes) *workspace_bytes = Ws::kBytes;
     return LCSB_OK;
 }
@@ -218,7 +226,7 @@ int lcsb_init_zero(lcsb_ctx *c)
     if (!c) return fail(LCSB_EINVAL, "null context");
     if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
     if (c->state < kBound) return fail(LCSB_ESTATE, "bind before init");
-    const uint64_t bytes = c->g.ns * elem_size(c->dtype);
+    const uint64_t bytes = c->entries * elem_size(c->dtype);
     hipError_t e;
     for (int k = 0; k < c->nbuf; ++k)
         if ((e = launch_fill_zero(c->buf[k], bytes, c->stream)) != hipSuccess)
@@ -228,7 +236,7 @@ int lcsb_init_zero(lcsb_ctx *c)
     c->head = 0;
     c->sweeps = 0;
     c->best = initial_best();
-    c->swap_sym = swap_shape(c);
+    c->swap_sym = c->packed || swap_shape(c);
     clear_lazy(c);
     int rc = refresh_rate(c);
     if (rc) return rc;
@@ -241,6 +249,7 @@ int lcsb_load_ring(lcsb_ctx *c, const void *const *src, int nsrc, const double *
     if (!c) return fail(LCSB_EINVAL, "null context");
     if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
     if (c->state < kBound) return fail(LCSB_ESTATE, "bind before load");
+    if (c->packed) return fail(LCSB_EUNSUPPORTED, "packed contexts start from zero or a checkpoint");
     if (!src || nsrc != c->lags) return fail(LCSB_EINVAL, "need %d source tables", c->lags);
     for (int k = 0; k < nsrc; ++k) {
         if (!src[k] || ((uintptr_t)src[k] & (elem_size(c->dtype) - 1)))
@@ -300,9 +309,10 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
         a.out = c->buf[a.new_slot];
         a.offsets = reinterpret_cast<double *>(c->ws + Ws::kOffsets);
         a.swap_sym = c->swap_sym;
+        a.packed = c->packed;
         hipError_t e = launch_sweep(c->g, c->dtype, a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
-        c->lazy[a.new_slot] = c->swap_sym;
+        c->lazy[a.new_slot] = c->swap_sym && !c->packed;
         c->head = a.new_slot;
         c->sweeps++;
         if ((rc = refresh_rate(c))) return rc;
@@ -314,6 +324,8 @@ int lcsb_certify(lcsb_ctx *c, lcsb_cert *cur, lcsb_cert *best)
 {
     int rc = need_ready(c);
     if (rc) return rc;
+    if (c->packed)
+        return fail(LCSB_EUNSUPPORTED, "packed contexts certify with lcsb_certify_optimal");
     const int su = slot_of_lag(c, 1), sp = slot_of_lag(c, 2);
     hipError_t e = launch_certify(c->g, c->dtype, c->buf[su], c->buf[sp], su, sp, c->swap_sym,
                                   c->ws, c->stream);
@@ -351,8 +363,10 @@ int lcsb_certify_optimal(lcsb_ctx *c, lcsb_cert *cur, lcsb_cert *best)
     int rc = need_ready(c);
     if (rc) return rc;
     const int su = slot_of_lag(c, 1);
-    hipError_t e = launch_certify_optimal(c->g, c->dtype, c->buf[su], c->swap_sym, c->ws,
-                                          c->stream);
+    hipError_t e = c->packed ? launch_certify_optimal_packed(c->g, c->dtype, c->buf[su], c->ws,
+                                                             c->stream)
+                             : launch_certify_optimal(c->g, c->dtype, c->buf[su], c->swap_sym,
+                                                      c->ws, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "certify launch");
     unsigned char host[Ws::kScalarBytes];
     if ((e = hipMemcpyAsync(host, c->ws, Ws::kScalarBytes, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
@@ -528,7 +542,7 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
         return fail(LCSB_EINVAL, "upcast goes from an FP32 to an FP64 context");
     if (src->g.sigma != dst->g.sigma || src->g.d != dst->g.d || src->g.h != dst->g.h)
         return fail(LCSB_EINVAL, "shape mismatch");
-    if (src->two_array != dst->two_array)
+    if (src->two_array != dst->two_array || src->packed != dst->packed)
         return fail(LCSB_EINVAL, "the two contexts run different iterations");
     // every destination slot is either the source slot's own buffer (widened
     // in place) or no source slot's buffer
@@ -544,11 +558,13 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
     if ((e = launch_fill_zero(dst->ws, Ws::kBytes, dst->stream)) != hipSuccess)
         return hip_fail(dst, e, "fill workspace");
     dst->head = src->head;
+    Geometry gt = src->g;  // the element-wise passes run over every entry of a table
+    gt.ns = src->entries;
     for (int k = 1; k <= src->lags; ++k) {
         const int slot = slot_of_lag(src, k);
         const double *off = reinterpret_cast<const double *>(src->ws + Ws::kOffsets) + slot;
-        e = inplace ? launch_upcast_inplace(src->g, dst->buf[slot], off, dst->stream)
-                    : launch_upcast(src->g, static_cast<const float *>(src->buf[slot]), off,
+        e = inplace ? launch_upcast_inplace(gt, dst->buf[slot], off, dst->stream)
+                    : launch_upcast(gt, static_cast<const float *>(src->buf[slot]), off,
                                     static_cast<double *>(dst->buf[slot]), dst->stream);
         if (e != hipSuccess) return hip_fail(dst, e, "upcast");
     }
@@ -667,6 +683,7 @@ int lcsb_init_seed_mlp(lcsb_ctx *c, const float *params, const uint16_t *wbf16, 
     if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
     if (c->state < kBound) return fail(LCSB_ESTATE, "bind before init");
     if (c->g.sigma != 2 || c->g.d != 2) return fail(LCSB_EUNSUPPORTED, "the network is for sigma = d = 2");
+    if (c->packed) return fail(LCSB_EUNSUPPORTED, "packed contexts start from zero or a checkpoint");
     int rc = check_h(c->g.h);
     if (rc) return rc;
     if (!params || !wbf16) return fail(LCSB_EINVAL, "null pointer");
@@ -762,19 +779,20 @@ int lcsb_save(const lcsb_ctx *c, const char *path)
     if (rc) return rc;
     if (!path) return fail(LCSB_EINVAL, "path is null");
     const size_t es = elem_size(c->dtype);
-    const uint64_t tbytes = c->g.ns * es;
+    const uint64_t tbytes = c->entries * es;
     CkptHeader hd;
     memset(&hd, 0, sizeof hd);
     memcpy(hd.magic, kCkptMagic, 8);
     hd.version = kCkptVersion;
     hd.sigma = c->g.sigma; hd.d = c->g.d; hd.h = c->g.h; hd.dtype = c->dtype;
-    hd.stored = c->g.ns;
+    hd.stored = c->entries;
     hd.sweeps = c->sweeps;
     hd.bound = c->best.bound; hd.R = c->best.R; hd.E = c->best.E; hd.maxW = c->best.maxW;
     hd.rho = c->best.rho; hd.best_sweep = c->best.sweep;
     hd.argmax_W = c->best.argmax_W; hd.nonfinite = c->best.nonfinite;
     hd.best_kind = c->best.kind;
-    hd.iteration = c->two_array ? LCSB_ITER_TWO_ARRAY : LCSB_ITER_RING;
+    hd.iteration = c->packed ? LCSB_ITER_TWO_ARRAY_PACKED
+                             : c->two_array ? LCSB_ITER_TWO_ARRAY : LCSB_ITER_RING;
     for (int k = 1; k <= c->lags; ++k)  // the file holds complete tables
         if ((rc = materialize(const_cast<lcsb_ctx *>(c), slot_of_lag(c, k)))) return rc;
     hipError_t e = hipStreamSynchronize(c->stream);
@@ -834,15 +852,16 @@ int lcsb_load(lcsb_ctx *c, const char *path)
     if (memcmp(hd.magic, kCkptMagic, 8) != 0 || hd.version != kCkptVersion)
         return fail(LCSB_ECKPT, "%s: not a ring checkpoint of this version", path);
     if (hd.header_hash != header_hash(hd)) return fail(LCSB_ECKPT, "%s: header hash mismatch", path);
-    const int iteration = c->two_array ? LCSB_ITER_TWO_ARRAY : LCSB_ITER_RING;
+    const int iteration = c->packed ? LCSB_ITER_TWO_ARRAY_PACKED
+                          : c->two_array ? LCSB_ITER_TWO_ARRAY : LCSB_ITER_RING;
     if (hd.sigma != c->g.sigma || hd.d != c->g.d || hd.h != c->g.h || hd.dtype != c->dtype ||
-        hd.stored != c->g.ns || hd.iteration != iteration)
+        hd.stored != c->entries || hd.iteration != iteration)
         return fail(LCSB_ECKPT, "%s: holds sigma=%d d=%d l=%d dtype=%d iteration=%d, the context "
                                 "is sigma=%d d=%d l=%d dtype=%d iteration=%d", path, hd.sigma,
                     hd.d, hd.h, hd.dtype, hd.iteration, c->g.sigma, c->g.d, c->g.h, c->dtype,
                     iteration);
     const size_t es = elem_size(c->dtype);
-    const uint64_t tbytes = c->g.ns * es;
+    const uint64_t tbytes = c->entries * es;
     if (fseek(in.f, 0, SEEK_END) != 0) return fail(LCSB_ECKPT, "%s: cannot seek", path);
     const long long size = ftell(in.f);
     if (size < 0 || (uint64_t)size != sizeof hd + (uint64_t)c->lags * tbytes)

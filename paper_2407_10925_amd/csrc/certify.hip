@@ -699,6 +699,76 @@ __global__ __launch_bounds__(kBlock) void cert_w(const T *__restrict__ u_arg, ui
     store_block(ev, ws);
 }
 
+// Exchange-packed tables (sigma = d = 2, packed_index): one thread per code
+// evaluates its orbit's representative tuple exactly as w_s2d2 evaluates
+// that coordinate (the same values in the same trees); the ratio stands for
+// every coordinate of the orbit, the index kept is the orbit's lowest stored
+// index (the representative or its exchanged twin) and `mult` counts the
+// stored coordinates of the orbit (1 or 2).
+template <typename T>
+__device__ __forceinline__ void packed_group_rd(const T *__restrict__ u, uint64_t gbase, int h,
+                                                double *e)
+{
+    const PackedGroup pg = packed_group(gbase, h);
+    if (pg.regular) {
+        double q[4];
+        ld4(u + pg.base, q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(q[k]));
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int at = packed_member(pg, v);
+            e[v] = at == 0 ? q[0] : at == 1 ? q[1] : at == 2 ? q[2] : q[3];
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) e[v] = (double)u[packed_index(gbase + (uint64_t)v, h)];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void cert_opt_packed(const T *__restrict__ u_arg, int h,
+                                                         unsigned char *__restrict__ ws)
+{
+    const uint64_t z = round_toward_neg_inf();
+    const T *__restrict__ u = u_arg + z;
+    OptEval ev(0.5, 0.0, 0.0);  // d = 2: no division by 3
+    const Scales sc;
+    const uint64_t n = 1ull << (2 * h), nq = n >> 2, ncodes = packed_entries(h);
+    const uint64_t am = 0xAAAAAAAAAAAAAAAAull & (n - 1), bm = ~am & (n - 1);
+    constexpr int ks[2] = {1, 1};
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < ncodes; k += stride) {
+        const uint64_t i = packed_tuple(k, h);
+        if (i == kNoOrbit) continue;
+        const uint64_t tw = exchange_twin(i, n, 2);
+        const uint64_t at = tw < i ? tw : i;
+        const int mult = tw == i ? 1 : 2;
+        const double u_i = (double)u[k];
+        if (i < nq) {  // head 0/0
+            double q4[4];
+            packed_group_rd(u, (i << 2) & (n - 1), h, q4);
+            double g[4] = {q4[0], q4[3], q4[1], q4[2]};
+            const double m_all = ev.template mean<4>(g, 2, sc.q[2]);
+            ev.template match_d<2>(u_i, m_all, at, mult);
+        } else {       // head 0/1: z = 0 advances b, z = 1 advances a
+            const uint64_t sb = (i & am) | ((i << 2) & bm);
+            const uint64_t sa = ((i << 2) & am) | (i & bm);
+            double q[4], pb[2], pa[2];
+            packed_group_rd(u, sb & ~(uint64_t)3, h, q);
+            const bool hi = (sb & 2) != 0;
+            pb[0] = hi ? q[2] : q[0]; pb[1] = hi ? q[3] : q[1];
+            packed_group_rd(u, sa & ~(uint64_t)3, h, q);
+            const bool odd = (sa & 1) != 0;
+            pa[0] = odd ? q[1] : q[0]; pa[1] = odd ? q[3] : q[2];
+            const double m[2] = {ev.template mean<2>(pb, 1, sc.q[1]),
+                                 ev.template mean<2>(pa, 1, sc.q[1])};
+            ev.template mismatch<2>(u_i, m, ks, at, mult);
+        }
+    }
+    store_block(ev, ws);
+}
+
 // l = 1: each branch appends its symbols in the head slot, so its tuples
 // straddle the stored half and every value is read at the image of its
 // index.  One workgroup; thread j evaluates stored coordinate j.  Templates on
@@ -911,6 +981,21 @@ hipError_t certify_optimal_typed(const Geometry &g, const void *u, int swap_sym,
 }
 
 }  // namespace
+
+hipError_t launch_certify_optimal_packed(const Geometry &g, int dtype, const void *u,
+                                         unsigned char *ws, hipStream_t s)
+{
+    if (g.sigma != 2 || g.d != 2 || g.h < 2) return hipErrorInvalidValue;
+    const int nb = reduce_blocks(packed_entries(g.h), dtype);
+    if (dtype == LCSB_F32)
+        cert_opt_packed<float><<<nb, kBlock, 0, s>>>(static_cast<const float *>(u), g.h, ws);
+    else
+        cert_opt_packed<double><<<nb, kBlock, 0, s>>>(static_cast<const double *>(u), g.h, ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    cert_w_final<true><<<1, kBlock, 0, s>>>(ws, nb);
+    return hipGetLastError();
+}
 
 hipError_t launch_certify_optimal(const Geometry &g, int dtype, const void *u, int swap_sym,
                                   unsigned char *ws, hipStream_t s)

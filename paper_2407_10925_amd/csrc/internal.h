@@ -61,6 +61,7 @@ struct SweepLaunch {
                       // (read lazily, see TwinGroup; the new table is written lazily)
     int shift;        // FP64 only: lag k is read as its values + (offsets[lag_slot[k-1]] -
                       // offsets[lag_slot[0]]) (the two-array iteration); FP32 always is
+    int packed;       // sigma = d = 2: the tables are exchange-packed (packed_index), h >= 2
 };
 
 hipError_t launch_sweep(const Geometry &g, int dtype, const SweepLaunch &a, hipStream_t s);
@@ -76,6 +77,10 @@ hipError_t launch_certify(const Geometry &g, int dtype, const void *u, const voi
 hipError_t launch_certify_optimal(const Geometry &g, int dtype, const void *u, int swap_sym,
                                   unsigned char *ws, hipStream_t s);
 
+// The same for an exchange-packed sigma = d = 2 table (packed_index), l >= 2
+hipError_t launch_certify_optimal_packed(const Geometry &g, int dtype, const void *u,
+                                         unsigned char *ws, hipStream_t s);
+
 // The same, its result written to out (4 doubles: r, d r rounded down, and
 // the lowest minimising index and the non-finite count as uint64 bits)
 hipError_t launch_certify_optimal_out(const Geometry &g, int dtype, const void *u, int swap_sym,
@@ -88,9 +93,10 @@ int certify_optimal_noalloc(int sigma, int d, int h, int dtype, const void *u,
 
 // The two-array iteration: R = mean over the fixed sample of nw - old, and the
 // offsets slots kSlotLag2/3 for the next sweep (csrc/two_array.hip)
+// packed: the two tables are exchange-packed (sigma = d = 2)
 hipError_t launch_two_array_rate(const Geometry &g, int dtype, const void *nw, const void *old,
-                                 int s_new, int s_old, int swap_sym, unsigned char *ws,
-                                 hipStream_t s);
+                                 int s_new, int s_old, int swap_sym, int packed,
+                                 unsigned char *ws, hipStream_t s);
 
 // Utilities
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);
@@ -244,6 +250,131 @@ __host__ __device__ inline uint64_t member16(uint64_t base, const Twin16 &tw, in
     const int pv = perm16(v, tw.m);
     if (tw.kind == 1) return tw.read + (uint64_t)pv;
     return base + (uint64_t)(pv < v ? pv : v);
+}
+
+// ---------------------------------------------------------------- packed tables
+// Exchange-packed storage for sigma = d = 2: one entry per orbit of the tuple
+// (a, b) under complementing both strings and exchanging them (a table of an
+// exchange-symmetric ring is constant on each orbit).  With c = a xor b, which
+// both maps keep, the complement sends a to ~a and the exchange a to a xor c,
+// so an orbit is a coset of {0, c, 1..1, ~c} among the a strings.  Its
+// representative has a_1 = 0 and, with c'' = c (c_1 = 0) or ~c (c_1 = 1) and
+// p the first position j >= 2 where c''_j = 1, a_p = 0.  Code, 2l - 2 bits
+// from the top: c_1, c_2, then (a_j, c_j) for j = 3..l, where the a bit of
+// position p holds a_2 instead (for p = 2 every position holds its own).
+// The orbits with c'' = 0 (b = a or b = ~a) have no p: they take the codes
+// n/4 + c_1 2^(l-1) + (a_2 .. a_l).  Codes below n/4 whose c'' is 0 belong to
+// no orbit and are never read or written.  The last position's pair is the
+// code's lowest two bits, so the four tuples that append one symbol to each
+// string (an aligned group of four standard indices) sit at four
+// consecutive codes whenever p < l.
+//
+// In the index arithmetic below, q is a standard index with the string-2
+// bit of every position replaced by c_j = a_j xor b_j (a_j at the odd bit
+// 2(l-j)+1, c_j at the even bit 2(l-j)).
+
+__host__ __device__ inline uint64_t packed_entries(int h)
+{
+    return (1ull << (2 * h - 2)) + (1ull << h);
+}
+
+constexpr uint64_t kNoOrbit = ~0ull;  // packed_tuple of a code that belongs to no orbit
+
+// (a_2 .. a_l) of q as an (l-1)-bit number (a_1 ignored)
+__host__ __device__ inline uint64_t packed_odd_bits(uint64_t q, int h)
+{
+    uint64_t x = (q >> 1) & 0x5555555555555555ull & ((1ull << (2 * h - 2)) - 1);
+    x = (x | (x >> 1)) & 0x3333333333333333ull;
+    x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x >> 4)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x >> 8)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x >> 16)) & 0x00000000FFFFFFFFull;
+    return x;
+}
+
+// the inverse: bit j of x to the odd bit 2j + 1
+__host__ __device__ inline uint64_t packed_spread_odd(uint64_t x)
+{
+    x &= 0x00000000FFFFFFFFull;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x << 1;
+}
+
+// the code of standard index i (any of the 4^l tuples)
+__host__ __device__ inline uint64_t packed_index(uint64_t i, int h)
+{
+    const uint64_t n = 1ull << (2 * h), A = 0xAAAAAAAAAAAAAAAAull & (n - 1), B = A >> 1;
+    uint64_t q = (i & A) | ((i ^ (i >> 1)) & B);
+    if (q >> (2 * h - 1)) q ^= A;                     // complement: a_1 = 0
+    const uint64_t c1 = (q >> (2 * h - 2)) & 1;
+    const uint64_t cc = (q & B) ^ (c1 ? B : 0);       // c'' (its top bit is 0)
+    if (cc == 0) return (n >> 2) + (c1 << (h - 1)) + packed_odd_bits(q, h);
+    const int pos = 63 - __builtin_clzll(cc);         // the even bit of c''_p
+    if ((q >> (pos + 1)) & 1) q ^= cc << 1;           // exchange: a_p = 0
+    if (pos < 2 * h - 4) q |= ((q >> (2 * h - 3)) & 1) << (pos + 1);  // a_2 into p's slot
+    return (c1 << (2 * h - 3)) | (q & ((1ull << (2 * h - 3)) - 1));
+}
+
+// the representative's standard index (a_1 = 0, so a stored index) of code
+// k, or kNoOrbit
+__host__ __device__ inline uint64_t packed_tuple(uint64_t k, int h)
+{
+    const uint64_t n = 1ull << (2 * h), A = 0xAAAAAAAAAAAAAAAAull & (n - 1), B = A >> 1;
+    const uint64_t nq = n >> 2;
+    uint64_t q;
+    if (k >= nq) {
+        const uint64_t r = k - nq, c1 = (r >> (h - 1)) & 1;
+        q = packed_spread_odd(r & ((1ull << (h - 1)) - 1)) | (c1 ? B : 0);
+    } else {
+        const uint64_t c1 = k >> (2 * h - 3);
+        q = (c1 << (2 * h - 2)) | (k & ((1ull << (2 * h - 3)) - 1));
+        const uint64_t cc = (q & B) ^ (c1 ? B : 0);
+        if (cc == 0) return kNoOrbit;
+        const int pos = 63 - __builtin_clzll(cc);
+        if (pos < 2 * h - 4) {
+            const uint64_t a2 = (q >> (pos + 1)) & 1;
+            q = (q & ~(1ull << (pos + 1))) | (a2 << (2 * h - 3));
+        }
+    }
+    const uint64_t a = q & A;
+    return a | ((a >> 1) ^ (q & B));
+}
+
+// Where the aligned group of four standard indices at gbase (low two bits 0)
+// lives: when the group's pivot lies above the last position (regular) its
+// member v = 2 alpha + beta is at code base + ((alpha ^ u0 ^ (u1 & g)) << 1 | g),
+// g = alpha ^ beta; otherwise each member is looked up on its own.
+struct PackedGroup {
+    uint64_t base;
+    int u0, u1;
+    bool regular;
+};
+
+__host__ __device__ inline PackedGroup packed_group(uint64_t gbase, int h)
+{
+    const uint64_t n = 1ull << (2 * h), A = 0xAAAAAAAAAAAAAAAAull & (n - 1), B = A >> 1;
+    uint64_t q = (gbase & A) | ((gbase ^ (gbase >> 1)) & B);
+    const int comp = (int)((q >> (2 * h - 1)) & 1);
+    if (comp) q ^= A;
+    const uint64_t c1 = (q >> (2 * h - 2)) & 1;
+    const uint64_t cc = ((q & B) ^ (c1 ? B : 0)) & ~(uint64_t)3;  // c'' above the last position
+    if (cc == 0) return {0, 0, 0, false};
+    const int pos = 63 - __builtin_clzll(cc);
+    const int flip = (int)((q >> (pos + 1)) & 1);
+    if (flip) q ^= (cc | (c1 ? 1 : 0)) << 1;  // a xor c'' (c''_l of member 0 = c1)
+    if (pos < 2 * h - 4) q |= ((q >> (2 * h - 3)) & 1) << (pos + 1);
+    const uint64_t code0 = (c1 << (2 * h - 3)) | (q & ((1ull << (2 * h - 3)) - 1));
+    return {code0 & ~(uint64_t)3, comp ^ (flip & (int)c1), flip, true};
+}
+
+__host__ __device__ inline int packed_member(const PackedGroup &pg, int v)
+{
+    const int alpha = v >> 1, g = (v >> 1) ^ (v & 1);
+    return ((alpha ^ pg.u0 ^ (pg.u1 & g)) << 1) | g;
 }
 
 // Learned warm start (csrc/mlp.hip)

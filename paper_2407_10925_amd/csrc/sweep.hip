@@ -404,18 +404,27 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
             load4(lag1 + sb, bv);
         }
         const T mb = tree4(bv[0], bv[1], bv[2], bv[3]) * (T)0.25;
-        // the lower index of each output's exchanged pair (b1 << top) | p_(m ^ b1 ^ s)
-        auto at = [&](int b1) {
+        // the lower index of each output's exchanged pair (b1 << top) | p_(m ^ b1 ^ s).
+        // A wave's stores at its twin's side fill 64-byte halves of lines
+        // whose other halves the neighbouring wave writes: in FP32 they are
+        // ordinary stores, which the L2 merges (WRITE_SIZE 2.33 -> 2.18 GB at
+        // l = 8, the same time); FP64 keeps non-temporal ones (3% faster).
+        auto st = [&](int b1, T v) {
             const uint64_t xt = p ^ ((uint64_t)(m ^ b1 ^ sx) * rep);
-            return ((uint64_t)b1 << top) | (SWAP && xt < x ? xt : x);
+            if (SWAP && xt < x) {
+                if constexpr (kF32) out[((uint64_t)b1 << top) | xt] = v;
+                else put(out + (((uint64_t)b1 << top) | xt), v);
+            } else {
+                put(out + (((uint64_t)b1 << top) | x), v);
+            }
         };
-        put(out + at(0), kF32 ? (T)(match - y0) : match);
+        st(0, kF32 ? (T)(match - y0) : match);
 #pragma unroll
         for (int b1 = 1; b1 < 4; ++b1) {
             T best = first(mb);                              // z = 0
 #pragma unroll
             for (int z = 1; z < 4; ++z) best = vmax(best, z == b1 ? ma[b1 ^ m] : both);
-            put(out + at(b1), kF32 ? (T)(best - y0) : best);
+            st(b1, kF32 ? (T)(best - y0) : best);
         }
     }
 }
@@ -713,6 +722,92 @@ __global__ __launch_bounds__(kBlock) void sweep_l1(const T *__restrict__ lag1,
     }
 }
 
+// ---------------------------------------------------------------- packed tables
+// sigma = d = 2 on exchange-packed tables (packed_index): one thread per code
+// k computes the value of its orbit's representative tuple, as sweep_s2d2
+// computes it (the same values in the same trees: every branch tree is
+// invariant under the complement and the exchange, so a group read through
+// its orbit's codes gives the bits of the unpacked table), and stores it at
+// k.  An aligned group of four whose pivot lies above the last position is
+// four consecutive codes (one vector load, members permuted); other groups
+// are read member by member.  Codes that belong to no orbit are not written.
+template <typename T>
+__device__ __forceinline__ void packed_group_values(const T *__restrict__ tab, uint64_t gbase,
+                                                    int h, T *e)
+{
+    const PackedGroup pg = packed_group(gbase, h);
+    if (pg.regular) {
+        T q[4];
+        load4(tab + pg.base, q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(q[k]));
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int at = packed_member(pg, v);
+            e[v] = at == 0 ? q[0] : at == 1 ? q[1] : at == 2 ? q[2] : q[3];
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) e[v] = tab[packed_index(gbase + (uint64_t)v, h)];
+    }
+}
+
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(kBlock) void sweep_s2d2_packed(const T *__restrict__ lag1,
+                                                           const T *__restrict__ lag2,
+                                                           T *__restrict__ out, int h,
+                                                           double *__restrict__ off, int s1,
+                                                           int s2, int snew)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kShift = kF32 || SHIFT;  // lag 2 carries delta_2
+    const uint64_t n = 1ull << (2 * h), nq = n >> 2;
+    const uint64_t k = thread_index();
+    T d2 = 0, y0 = 0;
+    if constexpr (!kF32 && SHIFT) d2 = off[s2] - off[s1];
+    if constexpr (kF32) {
+        const double o1 = off[s1];
+        d2 = (float)(off[s2] - o1);
+        T e[4];
+        packed_group_values(lag2, 0, h, e);
+        y0 = 1.0f + first(pair4(e[0], e[1], e[2], e[3]) * 0.25f + d2);
+        if (k == 0) off[snew] = o1 + (double)y0;
+    }
+    if (k >= packed_entries(h)) return;
+    const uint64_t i = packed_tuple(k, h);
+    if (i == kNoOrbit) return;
+    T v;
+    if (i < nq) {  // head 0/0
+        T g[4];
+        packed_group_values(lag2, (i << 2) & (n - 1), h, g);
+        T m2 = pair4(g[0], g[1], g[2], g[3]) * (T)0.25;
+        if constexpr (kShift) m2 = m2 + d2;
+        v = (T)1 + first(m2);
+    } else {       // head 0/1: advance b (z = 0) and advance a (z = 1) read lag 1
+        const uint64_t am = kAlt2 & (n - 1), bm = ~kAlt2 & (n - 1);
+        const uint64_t sb = (i & am) | ((i << 2) & bm);
+        const uint64_t sa = ((i << 2) & am) | (i & bm);
+        T q[4];
+        packed_group_values(lag1, sb & ~(uint64_t)3, h, q);
+        const bool hi = (sb & 2) != 0;
+        const T mb = ((hi ? q[2] : q[0]) + (hi ? q[3] : q[1])) * (T)0.5;
+        packed_group_values(lag1, sa & ~(uint64_t)3, h, q);
+        const bool odd = (sa & 1) != 0;
+        const T ma = ((odd ? q[1] : q[0]) + (odd ? q[3] : q[2])) * (T)0.5;
+        v = vmax(first(mb), ma);
+    }
+    put(out + k, kF32 ? (T)(v - y0) : v);
+}
+
+// a grid of `threads` threads of kBlock (two-dimensional past 2^32 threads)
+dim3 sweep_grid(uint64_t threads)
+{
+    const uint64_t blocks = (threads + kBlock - 1) / kBlock;
+    constexpr uint64_t kRow = 1ull << 16;  // blocks per grid row when one row is not enough
+    if (blocks * kBlock >= (1ull << 32)) return dim3((unsigned)kRow, (unsigned)((blocks + kRow - 1) / kRow));
+    return dim3((unsigned)blocks);
+}
+
 template <typename T, bool SHIFT>
 hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
 {
@@ -735,12 +830,15 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
             return hipErrorInvalidValue;
         return hipGetLastError();
     }
+    const dim3 block(kBlock);
+    if (a.packed) {
+        if (g.sigma != 2 || g.d != 2) return hipErrorInvalidValue;
+        sweep_s2d2_packed<T, SHIFT><<<sweep_grid(packed_entries(g.h)), block, 0, s>>>(
+            l1, l2, out, g.h, a.offsets, s1, s2, a.new_slot);
+        return hipGetLastError();
+    }
     // one thread per x with string-1 symbol 0 at position 2
-    const uint64_t threads = g.n >> (g.slot + g.beta);
-    const uint64_t blocks = (threads + kBlock - 1) / kBlock;
-    constexpr uint64_t kRow = 1ull << 16;  // blocks per grid row when one row is not enough
-    dim3 grid((unsigned)blocks), block(kBlock);
-    if (blocks * kBlock >= (1ull << 32)) grid = dim3((unsigned)kRow, (unsigned)((blocks + kRow - 1) / kRow));
+    const dim3 grid = sweep_grid(g.n >> (g.slot + g.beta));
     if (g.sigma == 2 && g.d == 2) {
         if (a.swap_sym)
             sweep_s2d2<T, true, SHIFT><<<grid, block, 0, s>>>(l1, l2, out, g.n, a.offsets, s1, s2,

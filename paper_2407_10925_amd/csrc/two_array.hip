@@ -20,13 +20,16 @@ constexpr int kSample = 4096;
 constexpr uint64_t kSampleMul = 0x9E3779B97F4A7C15ull;
 static_assert(kSample == 16 * kBlock, "sixteen leaves per thread");
 
-// SWAP (0, 2, 3: sigma = 2 with d = SWAP; 4: sigma = 4, d = 2): a lazily
-// written exchange-symmetric table, read at the lower index of each pair
+// swap (0, 2, 3: sigma = 2 with d = swap; 4: sigma = 4, d = 2): a lazily
+// written exchange-symmetric table, read at the lower index of each pair;
+// packed_h > 0: exchange-packed tables of l = packed_h, read at the code of
+// each coordinate (packed_index)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void rate_kernel(const T *__restrict__ nw,
                                                      const T *__restrict__ old, uint64_t n,
-                                                     uint64_t ns, int swap, double *__restrict__ off,
-                                                     int s_new, int s_old, double *__restrict__ rate)
+                                                     uint64_t ns, int swap, int packed_h,
+                                                     double *__restrict__ off, int s_new,
+                                                     int s_old, double *__restrict__ rate)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
     double v[16];
@@ -34,7 +37,9 @@ __global__ __launch_bounds__(kBlock) void rate_kernel(const T *__restrict__ nw,
     for (int j = 0; j < 16; ++j) {
         const uint64_t i = 16 * (uint64_t)threadIdx.x + (uint64_t)j;
         uint64_t c = (i * kSampleMul) & (ns - 1);  // ns is a power of two
-        if (swap) {
+        if (packed_h) {
+            c = packed_index(c, packed_h);
+        } else if (swap) {
             const uint64_t tw = swap == 4 ? exchange_twin4(c, n) : exchange_twin(c, n, swap);
             c = tw < c ? tw : c;
         }
@@ -76,9 +81,10 @@ __global__ __launch_bounds__(kBlock) void rate_kernel(const T *__restrict__ nw,
 }  // namespace
 
 hipError_t launch_two_array_rate(const Geometry &g, int dtype, const void *nw, const void *old,
-                                 int s_new, int s_old, int swap_sym, unsigned char *ws,
-                                 hipStream_t s)
+                                 int s_new, int s_old, int swap_sym, int packed,
+                                 unsigned char *ws, hipStream_t s)
 {
+    const int packed_h = packed ? g.h : 0;
     int swap = 0;
     if (swap_sym) swap = g.sigma == 4 ? 4 : g.d;
     double *off = reinterpret_cast<double *>(ws + Ws::kOffsets);
@@ -86,11 +92,11 @@ hipError_t launch_two_array_rate(const Geometry &g, int dtype, const void *nw, c
     if (dtype == LCSB_F32)
         rate_kernel<float><<<1, kBlock, 0, s>>>(static_cast<const float *>(nw),
                                                 static_cast<const float *>(old), g.n, g.ns, swap,
-                                                off, s_new, s_old, rate);
+                                                packed_h, off, s_new, s_old, rate);
     else
         rate_kernel<double><<<1, kBlock, 0, s>>>(static_cast<const double *>(nw),
                                                  static_cast<const double *>(old), g.n, g.ns, swap,
-                                                 off, s_new, s_old, rate);
+                                                 packed_h, off, s_new, s_old, rate);
     return hipGetLastError();
 }
 

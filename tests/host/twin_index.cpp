@@ -104,8 +104,62 @@ static void sigma4(int h, uint64_t count = 0)
     }
 }
 
+// Exchange-packed tables (sigma = d = 2): every tuple's code is below
+// packed_entries, the code's representative lies in the tuple's orbit
+// {i, ~i, E i, ~E i} with a_1 = 0 and has the same code, every code that
+// belongs to an orbit is the code of its representative, distinct orbits get
+// distinct codes, and a regular group's member positions agree with the
+// per-tuple code.  `count` > 0: that many hashed groups (plus the first and
+// last) instead of all, and no distinctness count.
+static uint64_t exchange2(uint64_t i, uint64_t n)
+{
+    const uint64_t am = 0xAAAAAAAAAAAAAAAAull & (n - 1);
+    return ((i & am) >> 1) | ((i & ~am & (n - 1)) << 1);
+}
+
+static void packed(int h, uint64_t count = 0)
+{
+    const uint64_t n = 1ull << (2 * h), ne = packed_entries(h);
+    const Bases bases{n, 4, count};
+    for (uint64_t k = 0; k < bases.size(); ++k) {
+        const uint64_t gb = bases[k];
+        const PackedGroup pg = packed_group(gb, h);
+        for (int v = 0; v < 4; ++v) {
+            const uint64_t i = gb + v, code = packed_index(i, h);
+            EXPECT(code < ne, "h=%d i=%llu: code out of range", h, (unsigned long long)i);
+            const uint64_t t = packed_tuple(code, h);
+            const uint64_t e = exchange2(i, n);
+            const bool in_orbit = t == i || t == (i ^ (n - 1)) || t == e || t == (e ^ (n - 1));
+            EXPECT(t != kNoOrbit && in_orbit, "h=%d i=%llu: representative %llu not in the orbit",
+                   h, (unsigned long long)i, (unsigned long long)t);
+            EXPECT(t < n / 2, "h=%d: representative not stored", h);
+            EXPECT(packed_index(t, h) == code, "h=%d i=%llu: representative's code differs", h,
+                   (unsigned long long)i);
+            if (pg.regular)
+                EXPECT(pg.base + (uint64_t)packed_member(pg, v) == code,
+                       "h=%d group %llu member %d: regular position differs", h,
+                       (unsigned long long)gb, v);
+        }
+    }
+    if (count) return;
+    uint64_t valid = 0;
+    for (uint64_t code = 0; code < ne; ++code) {
+        const uint64_t t = packed_tuple(code, h);
+        if (t == kNoOrbit) continue;
+        ++valid;
+        EXPECT(packed_index(t, h) == code, "h=%d code %llu: not the code of its representative",
+               h, (unsigned long long)code);
+    }
+    // orbits: (n + fixed points of E + fixed points of ~E) / 4, E and ~E
+    // each fixing 2^l tuples (b = a, b = ~a), the complement none
+    EXPECT(valid == (n + 2 * (1ull << h)) / 4, "h=%d: %llu codes in use, expected %llu", h,
+           (unsigned long long)valid, (unsigned long long)((n + 2 * (1ull << h)) / 4));
+}
+
 int main()
 {
+    for (int h = 2; h <= 10; ++h) packed(h);
+    for (int h = 11; h <= 18; ++h) packed(h, 1u << 18);
     for (int h = 2; h <= 10; ++h) groups<2>(h);
     for (int h = 2; h <= 7; ++h) groups<3>(h);
     for (int h = 2; h <= 5; ++h) sigma4(h);

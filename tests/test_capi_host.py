@@ -41,7 +41,7 @@ def test_create_validates_arguments(lib):
     assert lib.lcsb_create(2, 2, 6, 7, C.byref(ctx)) == _capi.LCSB_EINVAL
     assert b"dtype" in lib.lcsb_last_error()
     assert lib.lcsb_create(2, 2, 6, 0, None) == _capi.LCSB_EINVAL
-    assert lib.lcsb_create_iter(2, 2, 6, 0, 2, C.byref(ctx)) == _capi.LCSB_EINVAL
+    assert lib.lcsb_create_iter(2, 2, 6, 0, 3, C.byref(ctx)) == _capi.LCSB_EINVAL
     assert b"iteration" in lib.lcsb_last_error()
     for d, iteration, nbuf in ((2, 0, 3), (3, 0, 4), (2, 1, 2), (3, 1, 2)):
         assert lib.lcsb_create_iter(2, d, 3, 0, iteration, C.byref(ctx)) == 0
@@ -50,6 +50,16 @@ def test_create_validates_arguments(lib):
         assert nb.value == nbuf
         rate = C.c_double()
         assert lib.lcsb_rate(ctx, C.byref(rate)) == _capi.LCSB_ESTATE  # not initialised
+        assert lib.lcsb_destroy(ctx) == 0
+    # packed tables: sigma = d = 2, l >= 2 only; one entry per exchange orbit
+    for sigma, d, h in ((4, 2, 3), (2, 3, 3), (2, 2, 1)):
+        assert lib.lcsb_create_iter(sigma, d, h, 0, 2, C.byref(ctx)) == _capi.LCSB_EUNSUPPORTED
+    for h, dtype in ((2, 0), (3, 1), (18, 0)):
+        assert lib.lcsb_create_iter(2, 2, h, dtype, 2, C.byref(ctx)) == 0
+        nb, ent, bpb = C.c_int(), C.c_uint64(), C.c_uint64()
+        assert lib.lcsb_query(ctx, C.byref(nb), C.byref(ent), C.byref(bpb), None) == 0
+        assert (nb.value, ent.value) == (2, 4 ** (h - 1) + 2 ** h)
+        assert bpb.value == ent.value * (8 if dtype == 0 else 4)
         assert lib.lcsb_destroy(ctx) == 0
 
 

@@ -1,0 +1,233 @@
+"""Exchange-packed tables (LCSB_ITER_TWO_ARRAY_PACKED) against the folded
+two-array iteration and the oracle: the packed table holds, at the code of
+every tuple, the bits the unpacked iteration holds at that tuple, after
+every sweep; rates, certificates (value, lowest index, non-finite count),
+lcsb_run's stops, checkpoints and the FP32 -> FP64 upcast agree with the
+unpacked context's.  The code of a tuple is computed here from the layout
+stated in include/lcsb.h ("Packed storage"), independently of the library."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import seeded_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pk():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2407_10925_amd as pk
+    return pk
+
+
+def packed_entries(h):
+    return 4 ** (h - 1) + 2 ** h
+
+
+def packed_codes(idx, h):
+    """Code of each standard index (any of the 4^h tuples), from the stated
+    layout: strings a, b as h-bit numbers (position 1 most significant),
+    c = a xor b; a_1 = 0 by the complement; c'' = c or ~c (c_1 = 0); p the
+    first position j >= 2 with c''_j = 1 and a_p = 0 by the exchange; code
+    bits c_1, c_2, then (a_j, c_j), j = 3..h, the a slot of p holding a_2."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    one = np.uint64(1)
+    a = np.zeros_like(idx)
+    b = np.zeros_like(idx)
+    for j in range(1, h + 1):
+        a |= ((idx >> np.uint64(2 * (h - j) + 1)) & one) << np.uint64(h - j)
+        b |= ((idx >> np.uint64(2 * (h - j))) & one) << np.uint64(h - j)
+    full = np.uint64((1 << h) - 1)
+    top = np.uint64(h - 1)
+    c = a ^ b
+    a = np.where(((a >> top) & one) == one, a ^ full, a)
+    c1 = (c >> top) & one
+    cc = np.where(c1 == one, c ^ full, c)
+    out = np.empty_like(idx)
+    deg = cc == 0
+    out[deg] = np.uint64(4 ** (h - 1)) + (c1[deg] << top) + (a[deg] & (full >> one))
+    nd = ~deg
+    a, c, cc, c1 = a[nd], c[nd], cc[nd], c1[nd]
+    bitpos = np.floor(np.log2(cc.astype(np.float64))).astype(np.uint64)  # cc < 2^(h-1): exact
+    a = np.where(((a >> bitpos) & one) == one, a ^ cc, a)   # the exchange: a_p = 0
+    a2 = (a >> np.uint64(h - 2)) & one
+    code = (c1 << np.uint64(2 * h - 3)) | (((c >> np.uint64(h - 2)) & one) << np.uint64(2 * h - 4))
+    for j in range(3, h + 1):
+        pj = np.uint64(h - j)
+        abit = (a >> pj) & one
+        abit = np.where(bitpos == pj, a2, abit)            # position p holds a_2 (p > 2)
+        code |= (abit << np.uint64(2 * (h - j) + 1)) | (((c >> pj) & one) << np.uint64(2 * (h - j)))
+    out[nd] = code
+    return out
+
+
+def exchanged_lower(idx, h):
+    """The stored index of each exchanged pair that a lazily written folded
+    two-array table keeps (the lower of the index and its folded twin)."""
+    t = si.exchanged(torch.as_tensor(idx, dtype=torch.int64), 2, 2, h)
+    t = si.representative(t, 2, 2, h)
+    return torch.minimum(torch.as_tensor(idx, dtype=torch.int64), t)
+
+
+def test_codes_match_the_library_layout_size():
+    for h in range(2, 9):
+        codes = packed_codes(np.arange(4 ** h, dtype=np.uint64), h)
+        used = np.unique(codes)
+        assert used.max() < packed_entries(h)
+        # orbits: (4^h + 2 * 2^h) / 4 (E and ~E fix 2^h tuples each)
+        assert used.size == (4 ** h + 2 * 2 ** h) // 4
+
+
+def _pair(pk, h, dtype):
+    T = pk.Lcsb(2, 2, h, dtype, iteration="two_array")
+    P = pk.Lcsb(2, 2, h, dtype, iteration="two_array_packed")
+    assert P.stored == packed_entries(h)
+    T.init_zero()
+    P.init_zero()
+    assert P.swap_symmetric()
+    return T, P
+
+
+def _assert_same_tables(T, P, h, idx=None):
+    for k in (1, 2):
+        t, to = T.lag(k)
+        p, po = P.lag(k)
+        assert to == po, (k, to, po)
+        if idx is None:
+            idx = np.arange(T.stored, dtype=np.uint64)
+        codes = torch.as_tensor(packed_codes(idx, h).astype(np.int64), device=p.device)
+        ti = torch.as_tensor(np.asarray(idx, dtype=np.int64), device=t.device)
+        a, b = t[ti], p[codes]
+        same = (a == b) | (torch.isnan(a) & torch.isnan(b))
+        if not bool(same.all()):
+            bad = int(torch.nonzero(~same)[0])
+            raise AssertionError(f"lag {k}: index {int(ti[bad])} unpacked {float(a[bad])!r} "
+                                 f"packed {float(b[bad])!r}")
+
+
+@pytest.mark.parametrize("h", [2, 3, 5, 8, 10])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_packed_iteration_and_certificate_match_the_folded_one(pk, h, dtype):
+    say(f"packed vs folded two-array: h={h} {dtype}")
+    T, P = _pair(pk, h, dtype)
+    done = 0
+    for upto in (1, 2, 7, 40):
+        T.iterate(upto - done)
+        P.iterate(upto - done)
+        done = upto
+        _assert_same_tables(T, P, h)
+        assert T.rate() == P.rate()
+        ct, _ = T.certify_optimal()
+        cp, _ = P.certify_optimal()
+        for f in ("R", "rho", "bound", "argmax_W", "nonfinite", "kind"):
+            assert ct[f] == cp[f], (upto, f, ct[f], cp[f])
+
+
+@pytest.mark.parametrize("h", [3, 6])
+def test_packed_iteration_matches_the_oracle_on_every_tuple(pk, h):
+    say(f"packed vs oracle two-array run: h={h}")
+    _, hist, (u, u_prev, R) = O.two_array_run(2, 2, h, 30, cadence=30, certificate="optimal")
+    P = pk.Lcsb(2, 2, h, "f64", iteration="two_array_packed")
+    P.init_zero()
+    P.iterate(30)
+    codes = packed_codes(np.arange(4 ** h, dtype=np.uint64), h).astype(np.int64)
+    for k, ref in ((1, u), (2, u_prev)):
+        p, _ = P.lag(k)
+        got = p.cpu().numpy()[codes]
+        np.testing.assert_array_equal(got, ref)
+    assert P.rate() == R
+    cp, _ = P.certify_optimal()
+    c = hist[-1]["cert"]
+    assert (cp["R"], cp["bound"], cp["argmax_W"], cp["nonfinite"]) == \
+        (c["r"], c["bound"], c["argmin"], c["nonfinite"])
+
+
+def test_packed_run_stops_where_the_folded_run_stops(pk):
+    h = 12
+    say(f"lcsb_run packed vs folded: h={h}")
+    res = []
+    for it in ("two_array", "two_array_packed"):
+        L = pk.Lcsb(2, 2, h, "f64", iteration=it)
+        L.init_zero()
+        cur, best, certs, why = L.run(8, max_sweeps=400, stop_delta=1e-11, certificate="optimal")
+        res.append((cur["sweep"], best["bound"], best["argmax_W"], certs, why))
+        del L
+    assert res[0] == res[1], res
+
+
+@pytest.mark.parametrize("h,dtype,sweeps", [(16, "f64", 24), (17, "f32", 12)])
+def test_packed_full_size_sampled(pk, h, dtype, sweeps):
+    """Indices past 2^31 and 2^32 (codes past 2^32 at l = 17): sampled
+    entries, the rate and the certificate after several sweeps."""
+    say(f"packed full size: h={h} {dtype} {sweeps} sweeps")
+    torch.cuda.empty_cache()
+    T, P = _pair(pk, h, dtype)
+    T.iterate(sweeps)
+    P.iterate(sweeps)
+    idx = si.sample_indices(T.stored, 1 << 18, seed=h).numpy().astype(np.uint64)
+    _assert_same_tables(T, P, h, idx)
+    assert T.rate() == P.rate()
+    ct, _ = T.certify_optimal()
+    cp, _ = P.certify_optimal()
+    for f in ("R", "bound", "argmax_W", "nonfinite"):
+        assert ct[f] == cp[f], (f, ct[f], cp[f])
+    del T, P
+    torch.cuda.empty_cache()
+
+
+def test_packed_checkpoint_resume_and_upcast(pk, tmp_path):
+    h = 9
+    say(f"packed checkpoint and upcast: h={h}")
+    P = pk.Lcsb(2, 2, h, "f32", iteration="two_array_packed")
+    P.init_zero()
+    P.iterate(17)
+    path = tmp_path / "packed.ckpt"
+    P.save(str(path))
+    P.iterate(5)
+    ref, _ = P.lag(1)
+    ref = ref.clone()
+    Q = pk.Lcsb(2, 2, h, "f32", iteration="two_array_packed")
+    Q.load(str(path))
+    assert Q.status()[0] == 17
+    Q.iterate(5)
+    got, _ = Q.lag(1)
+    assert torch.equal(got, ref)
+    # FP32 -> FP64 in place against the folded context's upcast
+    T = pk.Lcsb(2, 2, h, "f32", iteration="two_array")
+    T.init_zero()
+    T.iterate(22)
+    D = pk.Lcsb(2, 2, h, "f64", iteration="two_array_packed")
+    S = pk.Lcsb(2, 2, h, "f32", iteration="two_array_packed",
+                bufs=[b.view(torch.float32) for b in D.bufs])
+    S.init_zero()
+    S.iterate(22)
+    TD = pk.Lcsb(2, 2, h, "f64", iteration="two_array")
+    TD.upcast(T)
+    D.upcast(S)
+    _assert_same_tables(TD, D, h)
+    TD.iterate(3)
+    D.iterate(3)
+    _assert_same_tables(TD, D, h)
+
+
+def test_packed_refuses_what_it_does_not_run(pk):
+    from paper_2407_10925_amd import _capi
+    P = pk.Lcsb(2, 2, 4, "f64", iteration="two_array_packed")
+    P.init_zero()
+    with pytest.raises(_capi.LcsbError) as e:
+        P.certify()
+    assert e.value.code == _capi.LCSB_EUNSUPPORTED
+    t = torch.zeros(P.stored, dtype=torch.float64, device="cuda")
+    with pytest.raises(_capi.LcsbError) as e:
+        P.load_ring([t, t])
+    assert e.value.code == _capi.LCSB_EUNSUPPORTED

@@ -85,6 +85,9 @@ def parse():
                    help="only the FP32 two-array iteration from zero at sigma=d=2, l=L, "
                         "certified every 16 sweeps (the largest-r certificate) for --max-sweeps")
     p.add_argument("--max-sweeps", type=int, default=480)
+    p.add_argument("--packed", type=int, default=0, metavar="L",
+                   help="only sigma=d=2 at l=L on exchange-packed tables: plain FP64 two-array "
+                        "to convergence, then FP32 + FP64 polish in the same memory")
     p.add_argument("--seed-ceiling", action="store_true",
                    help="only measure what a warm start of known error saves at sigma=d=2, "
                         "l=--h (the converged table plus noise, and the trained network)")
@@ -754,6 +757,63 @@ def converge_only(pk, h, sigma=2, d=2):
     print(json.dumps(out), flush=True)
 
 
+def packed_only(pk, h):
+    """sigma = d = 2 at l = h on exchange-packed tables (two-array iteration,
+    largest-r certificate): plain FP64 from zero, a certificate every 16
+    sweeps, until consecutive certificates move by less than 1e-10; then, in
+    the same memory, FP32 from zero to its floor and the FP64 polish to that
+    bound - 1e-9.  Prints one JSON line."""
+    import torch
+    torch.cuda.empty_cache()
+    P = pk.Lcsb(2, 2, h, "f64", iteration="two_array_packed")
+    log(f"packed FP64 pair at l={h}: {P.stored} entries per table, "
+        f"{2 * P.stored * 8 / 2**30:.1f} GiB")
+    stream = torch.cuda.current_stream()
+    P.init_zero()
+    P.iterate(2)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record(stream)
+    P.iterate(4)
+    e[1].record(stream)
+    e[2].record(stream)
+    P.certify_optimal()
+    e[3].record(stream)
+    torch.cuda.synchronize()
+    sweep_ms, cert_ms = e[0].elapsed_time(e[1]) / 4, e[2].elapsed_time(e[3])
+    log(f"FP64 packed sweep {sweep_ms:.2f} ms, largest-r certificate {cert_ms:.2f} ms")
+    t0 = time.perf_counter()
+    P.init_zero()
+    cur, best, certs, why = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, stop_delta=1e-10,
+                                  certificate="optimal")
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    B = best["bound"]
+    log(f"plain FP64: bound {B:.10f} after {cur['sweep']} sweeps ({why}), {t_plain:.1f} s")
+    out = {"workload": f"sigma=2 d=2 l={h}: {4 ** h} tuples, exchange-packed "
+                       f"({P.stored} entries per table), two-array iteration",
+           "f64_sweep_ms": round(sweep_ms, 3), "f64_certificate_ms": round(cert_ms, 3),
+           "plain_f64": {"bound": B, "sweeps": cur["sweep"], "certificates": certs,
+                         "seconds": round(t_plain, 3), "stop": why,
+                         "best_sweep": best["sweep"], "argmin": best["argmax_W"]}}
+    M = pk.Lcsb(2, 2, h, "f32", iteration="two_array_packed",
+                bufs=[b.view(torch.float32) for b in P.bufs])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M.init_zero()
+    cur, best32, certs32 = fp32_until_floor(M, "optimal")
+    sweeps32 = cur["sweep"]
+    sweeps64, certs64, best = polish(P, M, best32, B - 1e-9, "optimal")
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    log(f"FP32 floor {best32['bound']:.10f} after {sweeps32} sweeps; polished to "
+        f"{best['bound']:.10f} after {sweeps64} FP64 sweeps, {t_mixed:.1f} s")
+    out["mixed"] = {"fp32_floor_bound": best32["bound"], "sweeps_f32": sweeps32,
+                    "sweeps_f64": sweeps64, "bound": best["bound"],
+                    "reached": best["bound"] >= B - 1e-9, "seconds": round(t_mixed, 3),
+                    "certificates": certs32 + certs64}
+    print(json.dumps({"packed": out}), flush=True)
+
+
 def two_array_f32_only(pk, h, max_sweeps, sigma=2, d=2):
     """The FP32 two-array iteration from zero at (sigma, d, l = h) with the
     largest-r certificate every TTB_CADENCE sweeps for max_sweeps sweeps (two
@@ -838,6 +898,8 @@ def main():
         return certify_only(pk, args.h, args.sigma, args.d, args.dtype)
     if args.two_array_f32:
         return two_array_f32_only(pk, args.two_array_f32, args.max_sweeps, args.sigma, args.d)
+    if args.packed:
+        return packed_only(pk, args.packed)
     if args.seed_ceiling:
         return seed_ceiling(pk, args.h, args.train_steps)
     if args.profile_train:

@@ -5,6 +5,7 @@ every sweep; rates, certificates (value, lowest index, non-finite count),
 lcsb_run's stops, checkpoints and the FP32 -> FP64 upcast agree with the
 unpacked context's.  The code of a tuple is computed here from the layout
 stated in include/lcsb.h ("Packed storage"), independently of the library."""
+import math
 import sys
 
 import numpy as np
@@ -69,14 +70,6 @@ def packed_codes(idx, h):
         code |= (abit << np.uint64(2 * (h - j) + 1)) | (((c >> pj) & one) << np.uint64(2 * (h - j)))
     out[nd] = code
     return out
-
-
-def exchanged_lower(idx, h):
-    """The stored index of each exchanged pair that a lazily written folded
-    two-array table keeps (the lower of the index and its folded twin)."""
-    t = si.exchanged(torch.as_tensor(idx, dtype=torch.int64), 2, 2, h)
-    t = si.representative(t, 2, 2, h)
-    return torch.minimum(torch.as_tensor(idx, dtype=torch.int64), t)
 
 
 def test_codes_match_the_library_layout_size():
@@ -231,3 +224,87 @@ def test_packed_refuses_what_it_does_not_run(pk):
     with pytest.raises(_capi.LcsbError) as e:
         P.load_ring([t, t])
     assert e.value.code == _capi.LCSB_EUNSUPPORTED
+
+
+def _table2(h):
+    import pathlib
+    for line in (pathlib.Path(__file__).parent / "golden" / "table2_binary_bounds.txt").read_text().splitlines():
+        f = line.split()
+        if f and not f[0].startswith("#") and int(f[0]) == h:
+            return float(f[1])
+    raise KeyError(h)
+
+
+def _room(nbytes):
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < nbytes + 4 * 2**30:
+        pytest.skip(f"needs {(nbytes + 4 * 2**30) / 2**30:.0f} GiB of free device memory")
+
+
+@pytest.mark.timeout(600)
+def test_packed_l18_fp32_matches_the_folded_iteration_sampled(pk):
+    """l = 18 (2^36 tuples; stored indices past 2^35, codes past 2^34): the
+    folded FP32 two-array context (2 x 128 GiB) and then the packed one
+    (2 x 64 GiB) run the same 6 sweeps from zero; sampled entries of both
+    tables, the rate and the largest-r certificate agree bit for bit."""
+    h, sweeps = 18, 6
+    _room(2 * 4 * 4 ** h // 2)
+    say(f"l={h} FP32: folded two-array, {sweeps} sweeps")
+    idx = si.sample_indices(4 ** h // 2, 1 << 18, seed=18).numpy().astype(np.uint64)
+    ti = torch.as_tensor(idx.astype(np.int64), device="cuda")
+    T = pk.Lcsb(2, 2, h, "f32", iteration="two_array")
+    T.init_zero()
+    T.iterate(sweeps)
+    ref = []
+    for k in (1, 2):
+        t, off = T.lag(k)
+        ref.append((t[ti].cpu(), off))
+    rate_t = T.rate()
+    ct, _ = T.certify_optimal()
+    del T, t
+    torch.cuda.empty_cache()
+    say(f"l={h} FP32: packed two-array, {sweeps} sweeps")
+    P = pk.Lcsb(2, 2, h, "f32", iteration="two_array_packed")
+    P.init_zero()
+    P.iterate(sweeps)
+    codes = torch.as_tensor(packed_codes(idx, h).astype(np.int64), device="cuda")
+    for k in (1, 2):
+        p, off = P.lag(k)
+        assert off == ref[k - 1][1]
+        assert torch.equal(p[codes].cpu(), ref[k - 1][0]), k
+    assert P.rate() == rate_t
+    cp, _ = P.certify_optimal()
+    for f in ("R", "bound", "argmax_W", "nonfinite"):
+        assert ct[f] == cp[f], (f, ct[f], cp[f])
+    del P, p
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+def test_packed_l18_fp64_reaches_table_2(pk):
+    """l = 18 in FP64 on one GPU: two packed tables of 2^34 + 2^18 entries
+    (256 GiB).  The two-array iteration from zero, certified with the
+    largest-r certificate every 16 sweeps until consecutive certificates move
+    by less than 1e-10, gives Table 2's bound for l = 18 (0.790668, rounded
+    down at the 6th decimal), and the best bound never decreases."""
+    h = 18
+    _room(2 * 8 * packed_entries(h))
+    say(f"l={h} FP64 packed: two-array iteration from zero")
+    P = pk.Lcsb(2, 2, h, "f64", iteration="two_array_packed")
+    P.init_zero()
+    prev, last_best = None, 0.0
+    while True:
+        P.iterate(16)
+        cur, best = P.certify_optimal()
+        assert best["bound"] >= last_best
+        last_best = best["bound"]
+        if prev is not None and abs(cur["bound"] - prev) < 1e-10 and cur["bound"] >= best["bound"] \
+                and best["bound"] > 0:
+            break
+        prev = cur["bound"]
+        assert cur["sweep"] < 600
+    say(f"l={h}: {best['bound']:.12f} after {cur['sweep']} sweeps")
+    assert math.floor(best["bound"] * 1e6) / 1e6 == _table2(h)
+    del P
+    torch.cuda.empty_cache()

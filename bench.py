@@ -609,11 +609,15 @@ CONFIGS = [  # (sigma, d, l, dtype)
 ]
 
 
-def config_table(pk):
-    """Average sweep and certificate time per configuration (HIP events)."""
+GENERALITY = [(4, 2, 8, "f32"), (2, 3, 10, "f32"), (4, 2, 8, "f64"), (2, 3, 10, "f64")]
+
+
+def config_table(pk, configs=None, emit=True):
+    """Average sweep and certificate time per configuration (HIP events),
+    with the sweep's algorithmic bytes against the HBM peak."""
     import torch
     rows = []
-    for sigma, d, h, dt in CONFIGS:
+    for sigma, d, h, dt in (CONFIGS if configs is None else configs):
         L = pk.Lcsb(sigma, d, h, dt)
         L.init_zero()
         L.iterate(8)
@@ -646,7 +650,9 @@ def config_table(pk):
         log(json.dumps(rows[-1]))
         del L
         torch.cuda.empty_cache()
-    print(json.dumps({"configs": rows}), flush=True)
+    if emit:
+        print(json.dumps({"configs": rows}), flush=True)
+    return rows
 
 
 def profile_only(pk, h, sweeps, sigma=2, d=2, dtype="f32"):
@@ -950,6 +956,7 @@ def main():
     torch.cuda.empty_cache()
     fp64 = fp64_sweep(pk, 14)
     log(f"plain FP64 sweep at l=14: {fp64['avg_launch_ms']} ms, {fp64['frac']} of peak")
+    generality = config_table(pk, GENERALITY, emit=False)
 
     ttb = None
     if not args.no_ttb:
@@ -970,6 +977,9 @@ def main():
                    "sweeps_per_step": cad, "entries": n, "stored_entries": n // 2},
         "roofline": roofline,
         "fp64_sweep": fp64,
+        # the other (sigma, d) shapes of the paper's Table 3 at their sizes:
+        # sweep and certificate times, algorithmic bytes against the peak
+        "configs": generality,
         "cpu_baseline": cpu,
         "time_to_bound": ttb,
         "sweep_only_updates_per_s": n / avg_sweep_s,

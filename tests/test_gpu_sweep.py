@@ -794,3 +794,36 @@ def test_call_order_and_bad_arguments(pk):
     # upcast needs FP32 -> FP64
     M = pk.Lcsb(2, 2, 4, "f64")
     assert lib.lcsb_upcast(L._ctx, M._ctx) == _capi.LCSB_EINVAL
+
+
+@pytest.mark.timeout(600)
+def test_folded_zero_start_stays_exchange_exact_after_224_sweeps(pk):
+    """The exchange fold rests on every sweep of an exchange-symmetric ring
+    giving bit-identical values at exchanged tuples.  After 224 folded FP64
+    sweeps from zero at l = 14 (2^28 indices), the oracle computes the next
+    sweep independently at 20000 sampled coordinates, at their exchanged
+    twins and at their complements, from the full tables: every value equals
+    its twin's bit for bit, and the library's folded sweep equals the oracle
+    at all of them."""
+    sigma, d, h = 2, 2, 14
+    L = pk.Lcsb(sigma, d, h, "f64")
+    L.init_zero()
+    say("h=14 FP64: 224 folded sweeps from zero")
+    L.iterate(224)
+    assert L.swap_symmetric()
+    full = [_full(L, L.lag(k)[0]) for k in (1, 2)]
+    L.iterate(1)
+    assert L.swap_symmetric()
+    got = _host(L.lag(1)[0])
+    idx = si.sample_indices(L.n, 20000, seed=224)
+    twin = si.exchanged(idx, sigma, d, h)
+    comp = idx ^ (L.n - 1)
+    allidx = torch.cat([idx, twin, comp])
+    say("h=14 FP64: oracle at the samples, their twins and complements")
+    ref = oracle.sweep_at(sigma, d, h, full, allidx.numpy().astype(np.uint64))
+    m = idx.numel()
+    assert np.array_equal(ref[:m], ref[m:2 * m])      # exchanged tuples: the same bits
+    assert np.array_equal(ref[:m], ref[2 * m:])       # complemented tuples too
+    assert np.array_equal(got[_rep(L, allidx).numpy()], ref)
+    del L
+    torch.cuda.empty_cache()

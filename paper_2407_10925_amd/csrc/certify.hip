@@ -746,11 +746,19 @@ __global__ __launch_bounds__(kBlock) void cert_opt_packed(const T *__restrict__ 
         const int mult = tw == i ? 1 : 2;
         const double u_i = (double)u[k];
         if (i < nq) {  // head 0/0
+            // 0/0|x and 0/0|~x share their group mean (image groups): the
+            // lower of the two codes evaluates both coordinates
+            const uint64_t ic = i ^ (nq - 1), kc = packed_index(ic, h);
+            if (kc < k) continue;
             double q4[4];
             packed_group_rd(u, (i << 2) & (n - 1), h, q4);
             double g[4] = {q4[0], q4[3], q4[1], q4[2]};
             const double m_all = ev.template mean<4>(g, 2, sc.q[2]);
             ev.template match_d<2>(u_i, m_all, at, mult);
+            if (kc != k) {
+                const uint64_t rc = packed_tuple(kc, h), twc = exchange_twin(rc, n, 2);
+                ev.template match_d<2>((double)u[kc], m_all, twc < rc ? twc : rc, twc == rc ? 1 : 2);
+            }
         } else {       // head 0/1: z = 0 advances b, z = 1 advances a
             const uint64_t sb = (i & am) | ((i << 2) & bm);
             const uint64_t sa = ((i << 2) & am) | (i & bm);

@@ -778,11 +778,16 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2_packed(const T *__restrict_
     if (i == kNoOrbit) return;
     T v;
     if (i < nq) {  // head 0/0
+        // 0/0|x and 0/0|~x read image groups, so their values are equal:
+        // the lower of the two codes computes both
+        const uint64_t kc = packed_index(i ^ (nq - 1), h);
+        if (kc < k) return;
         T g[4];
         packed_group_values(lag2, (i << 2) & (n - 1), h, g);
         T m2 = pair4(g[0], g[1], g[2], g[3]) * (T)0.25;
         if constexpr (kShift) m2 = m2 + d2;
         v = (T)1 + first(m2);
+        if (kc != k) put(out + kc, kF32 ? (T)(v - y0) : v);
     } else {       // head 0/1: advance b (z = 0) and advance a (z = 1) read lag 1
         const uint64_t am = kAlt2 & (n - 1), bm = ~kAlt2 & (n - 1);
         const uint64_t sb = (i & am) | ((i << 2) & bm);

@@ -85,6 +85,10 @@ def parse():
                    help="only the FP32 two-array iteration from zero at sigma=d=2, l=L, "
                         "certified every 16 sweeps (the largest-r certificate) for --max-sweeps")
     p.add_argument("--max-sweeps", type=int, default=480)
+    p.add_argument("--iteration", default="ring", choices=["ring", "two_array"],
+                   help="iteration of --converge")
+    p.add_argument("--certificate", default="feasible", choices=["feasible", "optimal"],
+                   help="certificate of --converge")
     p.add_argument("--packed", type=int, default=0, metavar="L",
                    help="only sigma=d=2 at l=L on exchange-packed tables: plain FP64 two-array "
                         "to convergence, then FP32 + FP64 polish in the same memory")
@@ -715,45 +719,52 @@ def train_only(pk, h, steps, batch=8192):
         f"{flop / dt / 1e12:.1f} TFLOP/s, last loss {M.loss_dev.item():.3e}")
 
 
-def converge_only(pk, h, sigma=2, d=2):
+def converge_only(pk, h, sigma=2, d=2, iteration="ring", certificate="feasible"):
     """At (sigma, d, l = h): the plain FP64 iteration from zero, a certificate
     every TTB_CADENCE sweeps, until consecutive certificates move by less than
     1e-10 (B = the best bound then, also printed rounded down at the 6th
     decimal as the paper's tables print it); then, timed, plain FP64 from zero
     to B - 1e-9, and FP32 from zero + FP64 polish to B - 1e-9 in the same
-    memory (the FP32 ring bound to the first halves of the FP64 ring's
-    buffers, widened in place by the upcast).  Every run is one lcsb_run."""
+    memory (the FP32 tables bound to the first halves of the FP64 tables'
+    buffers, widened in place by the upcast).  Every run is one lcsb_run, on
+    the ring or the two-array iteration, with Algorithm 2's or the largest-r
+    certificate."""
     import torch
-    P = pk.Lcsb(sigma, d, h, "f64")
-    log(f"plain FP64 at sigma={sigma} d={d} l={h}: {P.n} indices, {P.stored} stored, "
-        f"{(d + 1) * 8 * P.stored / 2**30:.0f} GiB ring")
+    P = pk.Lcsb(sigma, d, h, "f64", iteration=iteration)
+    log(f"plain FP64 {iteration} at sigma={sigma} d={d} l={h}: {P.n} indices, {P.stored} "
+        f"stored, {P.nbuf * 8 * P.stored / 2**30:.0f} GiB of tables")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P.init_zero()
-    cur, best, _, why = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, stop_delta=1e-10)
+    cur, best, _, why = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, stop_delta=1e-10,
+                              certificate=certificate)
     torch.cuda.synchronize()
     t_conv = time.perf_counter() - t0
     B = best["bound"]
     target = B - 1e-9
     log(f"converged: {B:.12f} after {cur['sweep']} sweeps, {t_conv:.2f} s ({why})")
     out = {"sigma": sigma, "d": d, "l": h, "indices": P.n, "stored": P.stored,
+           "iteration": iteration, "certificate": certificate,
            "bound": B, "floor6": math.floor(B * 1e6) / 1e6,
-           "converged_after_sweeps": cur["sweep"], "converged_after_s": round(t_conv, 3)}
+           "converged_after_sweeps": cur["sweep"], "converged_after_s": round(t_conv, 3),
+           "best_argmin_or_argmax": best["argmax_W"]}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P.init_zero()
-    cur, best, certs, _ = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, target=target)
+    cur, best, certs, _ = P.run(TTB_CADENCE, max_sweeps=MAX_SWEEPS, target=target,
+                                certificate=certificate)
     torch.cuda.synchronize()
     out["plain_f64"] = {"seconds_to_target": round(time.perf_counter() - t0, 3),
                         "sweeps_to_target": cur["sweep"], "certificates": certs}
     log(f"plain to B - 1e-9: {out['plain_f64']['seconds_to_target']:.2f} s, {cur['sweep']} sweeps")
-    M = pk.Lcsb(sigma, d, h, "f32", bufs=[b.view(torch.float32) for b in P.bufs])
+    M = pk.Lcsb(sigma, d, h, "f32", iteration=iteration,
+                bufs=[b.view(torch.float32) for b in P.bufs])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     M.init_zero()
-    cur, best, certs32 = fp32_until_floor(M)
+    cur, best, certs32 = fp32_until_floor(M, certificate)
     sweeps32 = cur["sweep"]
-    sweeps64, certs64, best = polish(P, M, best, target)
+    sweeps64, certs64, best = polish(P, M, best, target, certificate)
     torch.cuda.synchronize()
     t_mixed = time.perf_counter() - t0
     out["mixed_f32_polish"] = {"seconds_to_target": round(t_mixed, 3), "sweeps_f32": sweeps32,
@@ -899,7 +910,8 @@ def main():
     if args.profile_seed:
         return seed_only(pk, args.h)
     if args.converge:
-        return converge_only(pk, args.converge, args.sigma, args.d)
+        return converge_only(pk, args.converge, args.sigma, args.d, args.iteration,
+                             args.certificate)
     if args.profile_certify:
         return certify_only(pk, args.h, args.sigma, args.d, args.dtype)
     if args.two_array_f32:

@@ -166,8 +166,8 @@ int main()
     // sampled groups at the sizes the benchmarks and the l = 17 runs use
     // (stored ranges up to 2^33 entries)
     for (int h = 11; h <= 17; ++h) groups<2>(h, 1u << 18);
-    for (int h = 8; h <= 11; ++h) groups<3>(h, 1u << 18);
-    for (int h = 6; h <= 8; ++h) sigma4(h, 1u << 18);
+    for (int h = 8; h <= 12; ++h) groups<3>(h, 1u << 18);
+    for (int h = 6; h <= 9; ++h) sigma4(h, 1u << 18);
     printf("%s (%ld disagreements)\n", bad ? "FAIL" : "ok", bad);
     return bad != 0;
 }

@@ -244,3 +244,47 @@ def test_fp64_two_array_h14_sampled_and_converged_bound(pk):
     say(f"two-array l = 14: {best['bound']:.12f} after {cur['sweep']} sweeps ({why})")
     assert why == "converged"
     assert math.floor(best["bound"] * 1e6) / 1e6 == 0.787017
+
+
+def _table3(sigma, d):
+    import pathlib
+    for line in (pathlib.Path(__file__).parent / "golden" / "table3_general_bounds.txt").read_text().splitlines():
+        f = line.split()
+        if f and not f[0].startswith("#") and (int(f[0]), int(f[1])) == (sigma, d):
+            return int(f[2]), float(f[3])
+    raise KeyError((sigma, d))
+
+
+def _converge(pk, sigma, d, h, iteration):
+    L = pk.Lcsb(sigma, d, h, "f64", iteration=iteration)
+    L.init_zero()
+    cur, best, _, why = L.run(16, max_sweeps=800, stop_delta=1e-10, certificate="optimal")
+    assert why == "converged"
+    del L
+    torch.cuda.empty_cache()
+    return best["bound"], cur["sweep"]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("sigma,d,h", [(2, 3, 11), (4, 2, 9)], ids=lambda v: str(v))
+def test_fp64_two_array_one_string_length_past_table3(pk, sigma, d, h):
+    """One l past the l of Table 3's bound for (sigma, d) = (2, 3) and (4, 2),
+    in FP64 on one GPU (two folded tables of 2^32 and 2^34 entries: 64 and
+    256 GiB): the two-array iteration from zero, certified with the largest-r
+    certificate every 16 sweeps to convergence, certifies a bound above
+    Table 3's (0.711548 at l = 10 and 0.614333 at l = 8).  At (2, 3, 11) the
+    ring of four tables (128 GiB) converges to the same bound within 1e-9."""
+    l_paper, paper = _table3(sigma, d)
+    assert h == l_paper + 1
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    need = 2 * 8 * sigma ** (d * h) // sigma + 4 * 2**30
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory")
+    say(f"({sigma},{d},{h}) FP64 two-array to convergence")
+    B, sweeps = _converge(pk, sigma, d, h, "two_array")
+    say(f"({sigma},{d},{h}): {B:.12f} after {sweeps} sweeps (Table 3 at l = {l_paper}: {paper})")
+    assert B > paper + 1e-3
+    if (sigma, d) == (2, 3):
+        Bring, _ = _converge(pk, sigma, d, h, "ring")
+        assert abs(Bring - B) <= 1e-9

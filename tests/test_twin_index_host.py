@@ -5,7 +5,7 @@ sigma = 4 sweep reads with one vector load, the groups the R pass skips or
 reads whole) agrees entry by entry with the per-entry rule, for every stored
 index at l = 2 .. 10 (sigma = d = 2), 2 .. 7 (d = 3) and 2 .. 5 (sigma = 4),
 and for 2^18 hashed groups (plus the first and last) at l = 11 .. 17,
-8 .. 11 and 6 .. 8, where stored indices pass 2^31 and 2^32.  The packed
+8 .. 12 and 6 .. 9, where stored indices pass 2^31 and 2^32 (up to 2^35).  The packed
 layout's arithmetic (packed_index, packed_tuple, packed_group): every code
 in range, the representative in the tuple's orbit with the same code, every
 used code the code of its representative and as many used codes as orbits,

@@ -196,12 +196,20 @@ def cpu_baseline(pk, h, log2_sample, max_threads=16):
     c1_gpu = time.perf_counter() - t0
     if best_g["bound"] != best_o["bound"]:
         raise RuntimeError("C1: GPU and oracle best bounds differ")
+    # one sweep of the plain at-scale configuration (sigma = d = 2, l = 14:
+    # 2^28 updates), extrapolated from the two rates measured above
+    c2 = {"updates_per_sweep": 4 ** 14,
+          "one_thread_s": round(4 ** 14 * dt1 / count, 1),
+          "all_threads_s": round(4 ** 14 * dtn / count, 1),
+          "note": "scaled from the sampled l = 16 sweep rates, an upper estimate (the "
+                  "oracle decodes each tuple in O(l) steps); not run whole"}
     return {"value": count / dtn, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one sweep at {count} entries (every {n // count}th index) of the "
                       f"sigma=d=2, l={h} table, FP32 ring read as FP64, {threads} threads over "
                       f"contiguous index ranges ({dtn:.2f} s); one thread: {dt1:.1f} s",
             "single_thread_value": count / dt1,
             "host": host_description(),
+            "c2_sigma2_d2_l14_one_sweep": c2,
             "c1_sigma2_d2_l6_200_sweeps_certified_each": {
                 "oracle_s": round(c1_oracle, 4), "gpu_s": round(c1_gpu, 4),
                 "best_bound": best_o["bound"]}}

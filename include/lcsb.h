@@ -252,6 +252,14 @@ int lcsb_certify_optimal_noalloc(int sigma, int d, int h, int dtype, const void 
  * stream (one kernel over the table), so every stored entry can be read. */
 int lcsb_lag(const lcsb_ctx *ctx, int k, void **dev_ptr, double *offset);
 
+/* Copy lag k (as for lcsb_lag) to host memory: the `entries` stored values
+ * (lcsb_query; packed contexts: their packed_entries codes) in the ring's
+ * element type (as_f64 = 0; host_dst holds entries elements of 8 or 4 bytes),
+ * or as FP64 true values (as_f64 = 1; host_dst holds entries doubles; an
+ * FP32 table is widened exactly and its offset added in round-to-nearest).
+ * Synchronises; host_dst is caller memory of any kind (pageable is fine). */
+int lcsb_read_table(const lcsb_ctx *ctx, int k, void *host_dst, int as_f64);
+
 /* sigma = 2, d = 2 or 3, l >= 2: *symmetric = 1 when every lag table is
  * known to be symmetric, bit for bit, under exchanging strings 1 and 2 (after
  * lcsb_init_zero, lcsb_init_seed_mlp, a load_ring or load of such a ring, an

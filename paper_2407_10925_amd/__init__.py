@@ -148,6 +148,16 @@ class Lcsb:
                 return b, off.value
         raise RuntimeError("lag pointer does not match a ring buffer")
 
+    def read_table(self, k: int = 1, as_f64: bool = True):
+        """lcsb_read_table: lag k's stored entries copied to a host numpy array,
+        as FP64 true values (FP32 tables widened, offset added) or as stored."""
+        import numpy as np
+        dt = np.float64 if (as_f64 or self.dtype == "f64") else np.float32
+        out = np.empty(self.stored, dtype=dt)
+        check(self._lib.lcsb_read_table(self._ctx, int(k), C.c_void_p(out.ctypes.data),
+                                        1 if as_f64 else 0))
+        return out
+
     def rate(self) -> float:
         """The rate R the next two-array sweep uses (synchronises)."""
         r = C.c_double()

@@ -85,6 +85,7 @@ def load():
     L.lcsb_certify_optimal_noalloc.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, C.c_int, P,
                                                P]
     L.lcsb_lag.argtypes = [P, C.c_int, C.POINTER(P), C.POINTER(C.c_double)]
+    L.lcsb_read_table.argtypes = [P, C.c_int, P, C.c_int]
     L.lcsb_status.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(Cert)]
     L.lcsb_swap_symmetric.argtypes = [P, C.POINTER(C.c_int)]
     L.lcsb_upcast.argtypes = [P, P]
@@ -105,7 +106,7 @@ def load():
     L.lcsb_init_seed_mlp.argtypes = [P, P, P, C.c_double]
     for name in ("lcsb_create", "lcsb_create_iter", "lcsb_rate", "lcsb_query", "lcsb_bind", "lcsb_init_zero", "lcsb_load_ring",
                  "lcsb_iterate", "lcsb_certify", "lcsb_certify_optimal",
-                 "lcsb_certify_optimal_noalloc", "lcsb_lag", "lcsb_status", "lcsb_swap_symmetric",
+                 "lcsb_certify_optimal_noalloc", "lcsb_lag", "lcsb_read_table", "lcsb_status", "lcsb_swap_symmetric",
                  "lcsb_upcast",
                  "lcsb_run", "lcsb_save", "lcsb_load", "lcsb_destroy", "lcsb_mlp_workspace", "lcsb_mlp_init", "lcsb_mlp_to_bf16",
                  "lcsb_mlp_sample", "lcsb_mlp_forward", "lcsb_mlp_loss", "lcsb_mlp_backward",

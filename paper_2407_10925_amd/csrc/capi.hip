@@ -427,6 +427,32 @@ int lcsb_lag(const lcsb_ctx *c, int k, void **dev_ptr, double *offset)
     return LCSB_OK;
 }
 
+int lcsb_read_table(const lcsb_ctx *c, int k, void *host_dst, int as_f64)
+{
+    void *dev = nullptr;
+    double off = 0.0;
+    int rc = lcsb_lag(c, k, &dev, &off);
+    if (rc) return rc;
+    if (!host_dst) return fail(LCSB_EINVAL, "null host buffer");
+    if (as_f64 != 0 && as_f64 != 1) return fail(LCSB_EINVAL, "as_f64 must be 0 or 1");
+    const size_t es = elem_size(c->dtype);
+    const uint64_t bytes = c->entries * es;
+    hipError_t e = hipMemcpyAsync(host_dst, dev, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(LCSB_EHIP, "table read: %s", hipGetErrorString(e));
+    if (as_f64 && c->dtype == LCSB_F32) {
+        // widen in place from the top down: element j's 8 bytes overlap only
+        // float elements j' >= j, which are already widened
+        float *f = static_cast<float *>(host_dst);
+        double *dd = static_cast<double *>(host_dst);
+        for (uint64_t j = c->entries; j-- > 0;) {
+            const float v = f[j];
+            dd[j] = off + (double)v;
+        }
+    }
+    return LCSB_OK;
+}
+
 int lcsb_swap_symmetric(const lcsb_ctx *c, int *symmetric)
 {
     int rc = need_ready(c);

@@ -84,6 +84,7 @@ def test_call_order_is_enforced_without_a_gpu(lib):
     assert lib.lcsb_iterate(ctx, 1) == _capi.LCSB_ESTATE
     assert lib.lcsb_certify(ctx, None, None) == _capi.LCSB_ESTATE
     assert lib.lcsb_certify_optimal(ctx, None, None) == _capi.LCSB_ESTATE
+    assert lib.lcsb_read_table(ctx, 1, None, 1) == _capi.LCSB_ESTATE
     assert lib.lcsb_init_zero(ctx) == _capi.LCSB_ESTATE
     # bind checks pointers before storing anything
     assert lib.lcsb_bind(ctx, None, 3, None, None) == _capi.LCSB_EINVAL

@@ -288,3 +288,21 @@ def test_fp64_two_array_one_string_length_past_table3(pk, sigma, d, h):
     if (sigma, d) == (2, 3):
         Bring, _ = _converge(pk, sigma, d, h, "ring")
         assert abs(Bring - B) <= 1e-9
+
+
+@pytest.mark.parametrize("dtype,iteration", [("f64", "ring"), ("f32", "ring"), ("f32", "two_array"),
+                                             ("f64", "two_array_packed")], ids=lambda v: str(v))
+def test_read_table_copies_the_lag_to_the_host(pk, dtype, iteration):
+    """lcsb_read_table: the stored entries as stored, and as FP64 true values
+    (an FP32 table widened and its offset added), equal to the device table."""
+    L = pk.Lcsb(2, 2, 7, dtype, iteration=iteration)
+    L.init_zero()
+    L.iterate(9)
+    for k in (1, 2):
+        dev, off = L.lag(k)
+        ref = dev.cpu().numpy()
+        raw = L.read_table(k, as_f64=False)
+        assert raw.dtype == ref.dtype and np.array_equal(raw, ref)
+        true = L.read_table(k, as_f64=True)
+        assert true.dtype == np.float64
+        assert np.array_equal(true, off + ref.astype(np.float64))

@@ -246,6 +246,50 @@ def test_fp64_two_array_h14_sampled_and_converged_bound(pk):
     assert math.floor(best["bound"] * 1e6) / 1e6 == 0.787017
 
 
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("sigma,d,h", [(4, 2, 8), (2, 3, 10), (2, 2, 16)], ids=lambda v: str(v))
+def test_fp64_two_array_full_size_seeded_step_sampled(pk, sigma, d, h):
+    """The generality shapes and l = 16 at their full sizes (2^32, 2^30 and
+    2^32 tuples), in the library's own launch shapes: one two-array step from
+    a seeded exchange-symmetric pair, bit-exact with the oracle at 20000
+    sampled coordinates (plus the head-class boundaries), and the rate that
+    step used bit-exact."""
+    n = sigma ** (d * h)
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    need = 4 * 8 * n // sigma + 8 * 2**30  # the seeded pair and the context's two tables
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory")
+    tag = f"({sigma},{d},{h}) FP64 two-array"
+    say(f"{tag}: seeded pair")
+    u_dev = si.stored_table(sigma, d, h, seed=430, device="cuda")
+    up_dev = si.stored_table(sigma, d, h, seed=431, device="cuda")
+    L = pk.Lcsb(sigma, d, h, "f64", iteration="two_array")
+    L.load_ring([u_dev, up_dev])
+    assert L.swap_symmetric()
+    rate = L.rate()
+    L.iterate(1)
+    idx = si.sample_indices(n, 20000, seed=17)
+    got = L.lag(1)[0][si.representative(idx.cuda(), sigma, d, h)].cpu().numpy()
+    del L
+    torch.cuda.empty_cache()
+    say(f"{tag}: full tables to the host")
+    full = []
+    for t in (u_dev, up_dev):
+        out = np.empty(n, dtype=np.float64)
+        for lo in range(0, n, 1 << 28):
+            ii = torch.arange(lo, min(n, lo + (1 << 28)), dtype=torch.int64, device="cuda")
+            out[lo:lo + ii.numel()] = t[si.representative(ii, sigma, d, h)].cpu().numpy()
+            del ii
+        full.append(out)
+    del u_dev, up_dev
+    torch.cuda.empty_cache()
+    R = oracle.sample_growth(sigma, d, h, full[0], full[1])
+    assert rate == R
+    ref = oracle.two_array_step_at(sigma, d, h, full[0], R, idx.numpy().astype(np.uint64))
+    assert np.array_equal(got, ref)
+
+
 def _table3(sigma, d):
     import pathlib
     for line in (pathlib.Path(__file__).parent / "golden" / "table3_general_bounds.txt").read_text().splitlines():

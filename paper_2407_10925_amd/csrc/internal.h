@@ -280,6 +280,16 @@ __host__ __device__ inline uint64_t packed_entries(int h)
 
 constexpr uint64_t kNoOrbit = ~0ull;  // packed_tuple of a code that belongs to no orbit
 
+// packed_index of member v of the aligned group at index 0 (every position
+// 0/0 but the last, which is (a_l, b_l) = (v >> 1, v & 1)): 0/0 and 1/1 leave
+// c = 0, degenerate orbits with a_2..a_l = 0 and 1; 0/1 and 1/0 are exchange
+// twins whose pivot is the last position, the code of the tuple with b_l = 1
+__host__ __device__ inline uint64_t packed_zero_group(int v, int h)
+{
+    const uint64_t nq = 1ull << (2 * h - 2);
+    return v == 0 ? nq : v == 3 ? nq + 1 : 1;
+}
+
 // (a_2 .. a_l) of q as an (l-1)-bit number (a_1 ignored)
 __host__ __device__ inline uint64_t packed_odd_bits(uint64_t q, int h)
 {

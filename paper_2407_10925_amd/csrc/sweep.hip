@@ -768,9 +768,9 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2_packed(const T *__restrict_
     if constexpr (kF32) {
         const double o1 = off[s1];
         d2 = (float)(off[s2] - o1);
-        T e[4];
-        packed_group_values(lag2, 0, h, e);
-        y0 = 1.0f + first(pair4(e[0], e[1], e[2], e[3]) * 0.25f + d2);
+        const T e0 = lag2[packed_zero_group(0, h)], e1 = lag2[packed_zero_group(1, h)];
+        const T e3 = lag2[packed_zero_group(3, h)];
+        y0 = 1.0f + first(pair4(e0, e1, e1, e3) * 0.25f + d2);
         if (k == 0) off[snew] = o1 + (double)y0;
     }
     if (k >= packed_entries(h)) return;

@@ -141,6 +141,9 @@ static void packed(int h, uint64_t count = 0)
                        (unsigned long long)gb, v);
         }
     }
+    for (int v = 0; v < 4; ++v)
+        EXPECT(packed_zero_group(v, h) == packed_index((uint64_t)v, h),
+               "h=%d: zero group member %d", h, v);
     if (count) return;
     uint64_t valid = 0;
     for (uint64_t code = 0; code < ne; ++code) {

@@ -364,14 +364,16 @@ struct OptEval {
         if (!isfinite(q)) nonfinite += (uint64_t)mult;
         if (q < r || (q == r && i < arg)) { r = q; arg = i; }
     }
+    // whether put(q, ...) could change the state: a candidate above the
+    // current r that is finite leaves it as it is, whatever its index
+    __device__ __forceinline__ bool may_take(double q) const { return !(q > r) || !isfinite(q); }
     template <int D>
-    __device__ __forceinline__ void match_d(double u_i, double m_all, uint64_t i, int mult)
+    __device__ __forceinline__ double match_q(double u_i, double m_all) const
     {
-        put(first(ratio((1.0 + m_all) - u_i, D)), i, mult);
+        return first(ratio((1.0 + m_all) - u_i, D));
     }
     template <int NB>
-    __device__ __forceinline__ void mismatch(double u_i, const double *m, const int *k, uint64_t i,
-                                             int mult)
+    __device__ __forceinline__ double mismatch_q(double u_i, const double *m, const int *k) const
     {
         double f = first(ratio(m[0] - u_i, k[0]));
 #pragma unroll
@@ -379,7 +381,18 @@ struct OptEval {
             const double q = ratio(m[j] - u_i, k[j]);
             f = q > f ? q : f;
         }
-        put(f, i, mult);
+        return f;
+    }
+    template <int D>
+    __device__ __forceinline__ void match_d(double u_i, double m_all, uint64_t i, int mult)
+    {
+        put(match_q<D>(u_i, m_all), i, mult);
+    }
+    template <int NB>
+    __device__ __forceinline__ void mismatch(double u_i, const double *m, const int *k, uint64_t i,
+                                             int mult)
+    {
+        put(mismatch_q<NB>(u_i, m, k), i, mult);
     }
     // the final pass takes a max: hand it -r (exact; lowest index kept on ties)
     __device__ __forceinline__ double result() const { return -r; }
@@ -741,9 +754,14 @@ __global__ __launch_bounds__(kBlock) void cert_opt_packed(const T *__restrict__ 
     for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < ncodes; k += stride) {
         const uint64_t i = packed_tuple(k, h);
         if (i == kNoOrbit) continue;
-        const uint64_t tw = exchange_twin(i, n, 2);
-        const uint64_t at = tw < i ? tw : i;
-        const int mult = tw == i ? 1 : 2;
+        // a coordinate's reported index (the lower stored member of its
+        // exchanged pair) and its multiplicity only matter where put can use
+        // them, so they are computed there
+        const auto take = [&](double q, uint64_t tuple) {
+            if (!ev.may_take(q)) return;
+            const uint64_t tw = exchange_twin(tuple, n, 2);
+            ev.put(q, tw < tuple ? tw : tuple, tw == tuple ? 1 : 2);
+        };
         const double u_i = (double)u[k];
         if (i < nq) {  // head 0/0
             // 0/0|x and 0/0|~x share their group mean (image groups): the
@@ -754,10 +772,10 @@ __global__ __launch_bounds__(kBlock) void cert_opt_packed(const T *__restrict__ 
             packed_group_rd(u, (i << 2) & (n - 1), h, q4);
             double g[4] = {q4[0], q4[3], q4[1], q4[2]};
             const double m_all = ev.template mean<4>(g, 2, sc.q[2]);
-            ev.template match_d<2>(u_i, m_all, at, mult);
+            take(ev.template match_q<2>(u_i, m_all), i);
             if (kc != k) {
-                const uint64_t rc = packed_tuple(kc, h), twc = exchange_twin(rc, n, 2);
-                ev.template match_d<2>((double)u[kc], m_all, twc < rc ? twc : rc, twc == rc ? 1 : 2);
+                const double q = ev.template match_q<2>((double)u[kc], m_all);
+                if (ev.may_take(q)) take(q, packed_tuple(kc, h));
             }
         } else {       // head 0/1: z = 0 advances b, z = 1 advances a
             const uint64_t sb = (i & am) | ((i << 2) & bm);
@@ -771,7 +789,7 @@ __global__ __launch_bounds__(kBlock) void cert_opt_packed(const T *__restrict__ 
             pa[0] = odd ? q[1] : q[0]; pa[1] = odd ? q[3] : q[2];
             const double m[2] = {ev.template mean<2>(pb, 1, sc.q[1]),
                                  ev.template mean<2>(pa, 1, sc.q[1])};
-            ev.template mismatch<2>(u_i, m, ks, at, mult);
+            take(ev.template mismatch_q<2>(u_i, m, ks), i);
         }
     }
     store_block(ev, ws);

@@ -145,6 +145,62 @@ def test_packed_iteration_matches_the_oracle_on_every_tuple(pk, h):
         (c["r"], c["bound"], c["argmin"], c["nonfinite"])
 
 
+def _stored_members(i, h):
+    """The stored indices of the orbit of stored index i under the
+    exchange: i and the exchanged tuple, complemented when that puts a 1 at
+    string 1's head."""
+    n = 4 ** h
+    am = int("10" * h, 2)
+    e = ((i & am) >> 1) | ((i & (am >> 1)) << 1)
+    if e >= n // 2:
+        e ^= n - 1
+    return sorted({i, e})
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["finite", "inf", "nan"])
+def test_packed_certificate_of_planted_extremes_matches_the_folded_one(pk, dtype, case):
+    """Values planted at chosen orbits (at every stored member of the
+    unpacked table, at the code of the packed one): a large finite value at
+    a low and, larger, at a high index (the minimum is found late in the
+    packed pass's grid-stride loop), +inf at two orbits (candidates tied at
+    -inf, lowest index kept) and NaN at one.  Both certificates agree in
+    every field; the finite case reports the high orbit's lower member."""
+    h = 9
+    say(f"packed planted extremes: {dtype} {case}")
+    T, P = _pair(pk, h, dtype)
+    T.iterate(10)
+    P.iterate(10)
+    n = 4 ** h
+    # stored tuples (string-1 head 0) spread over the index range
+    lo, hi = 0x1234 % (n // 2), (n // 2) - 0x2345
+    plants = {"finite": [(lo, 1.0e3), (hi, 2.0e3)],
+              "inf": [(lo, math.inf), (hi, math.inf)],
+              "nan": [(hi, math.nan)]}[case]
+    t, _ = T.lag(1)
+    p, _ = P.lag(1)
+    for i, val in plants:
+        members = _stored_members(i, h)
+        code = int(packed_codes(np.array([i], dtype=np.uint64), h)[0])
+        assert all(int(packed_codes(np.array([m], dtype=np.uint64), h)[0]) == code
+                   for m in members)
+        for m in members:
+            t[m] = t[m] + val
+        p[code] = p[code] + val
+    torch.cuda.synchronize()
+    ct, _ = T.certify_optimal(allow_nonfinite=True)
+    cp, _ = P.certify_optimal(allow_nonfinite=True)
+    for f in ("R", "rho", "bound", "argmax_W", "nonfinite", "kind"):
+        same = ct[f] == cp[f] or (isinstance(ct[f], float) and math.isnan(ct[f])
+                                  and math.isnan(cp[f]))
+        assert same, (f, ct[f], cp[f])
+    if case == "finite":
+        assert cp["argmax_W"] == _stored_members(hi, h)[0]
+        assert cp["nonfinite"] == 0
+    else:
+        assert cp["nonfinite"] > 0
+
+
 def test_packed_run_stops_where_the_folded_run_stops(pk):
     h = 12
     say(f"lcsb_run packed vs folded: h={h}")

@@ -244,13 +244,42 @@ int lcsb_certify_optimal(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
 int lcsb_certify_optimal_noalloc(int sigma, int d, int h, int dtype, const void *u,
                                  int exchange_symmetric, double *dev_out, void *stream);
 
+/* Branch-mean tables (sigma = d = 2 ring, l >= 3; eq. (3) and Algorithm 1:
+ * a branch that moves string 1 reads the mean of 2 entries that differ in
+ * the appended symbol, the all-match tuple the mean of the 4 entries of an
+ * aligned group).  For a stored group prefix P < n/8 (entries 4P .. 4P+3):
+ *   Ma[2P + b] = (T[4P + b] + T[4P + 2 + b]) * 1/2,
+ *   Mab[P]     = ((T[4P] + T[4P+3]) + (T[4P+1] + T[4P+2])) * 1/4,
+ * the means the entry-reading sweep forms (same operations, same order).  On
+ * a ring symmetric in the two strings (lcsb_swap_symmetric; the zero start)
+ * a sweep then reads one mean per branch instead of its 2 or 4 entries (the
+ * advance-b mean is Ma at the exchanged tuple): about 0.69 of the bytes per
+ * sweep, with the same table bit for bit.  Each sweep writes its table's
+ * means and, on the last d sweeps of an lcsb_iterate call, its entries, so
+ * every lag a caller or a certificate sees is complete.  Other rings sweep
+ * from the entries.
+ *
+ * lcsb_query_means: bytes of one mean buffer (Ma, then Mab 256-byte aligned;
+ * 3/4 of a ring buffer).  LCSB_EUNSUPPORTED for other shapes, iterations and
+ * l < 3.  lcsb_bind_means (after lcsb_bind): nbuf = the ring's buffer count
+ * of caller-owned device buffers, 256-byte aligned, distinct from the ring
+ * buffers and the workspace, kept until unbound or the context is destroyed;
+ * bufs = NULL with nbuf = 0 unbinds.  The means are derived from the entries
+ * before the first sweep that needs them (after lcsb_init_zero, lcsb_load_ring,
+ * lcsb_load, lcsb_upcast, lcsb_init_seed_mlp or lcsb_lag). */
+int lcsb_query_means(const lcsb_ctx *ctx, uint64_t *bytes_per_buf);
+int lcsb_bind_means(lcsb_ctx *ctx, void *const *bufs, int nbuf);
+
 /* Device address of lag k (1..d; 1..2 for the two-array iteration) and, for LCSB_F32, the FP64 offset its
  * values are relative to (read from the device; synchronises).  The pointer
  * stays valid until the next lcsb_iterate, lcsb_load_ring or lcsb_bind.  On
  * an exchange-symmetric ring (lcsb_swap_symmetric) sweeps write only one
  * entry of each exchanged pair; this call first completes the table on the
- * stream (one kernel over the table), so every stored entry can be read. */
-int lcsb_lag(const lcsb_ctx *ctx, int k, void **dev_ptr, double *offset);
+ * stream (one kernel over the table), so every stored entry can be read.
+ * The caller may write through the pointer (as lcsb_load_ring does, in
+ * place): with branch-mean buffers bound, the next lcsb_iterate derives the
+ * lags' means from their entries again. */
+int lcsb_lag(lcsb_ctx *ctx, int k, void **dev_ptr, double *offset);
 
 /* Copy lag k (as for lcsb_lag) to host memory: the `entries` stored values
  * (lcsb_query; packed contexts: their packed_entries codes) in the ring's

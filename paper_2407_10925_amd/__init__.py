@@ -30,14 +30,15 @@ class Lcsb:
     """
 
     def __init__(self, sigma: int, d: int, h: int, dtype: str = "f64", device=None,
-                 bufs=None, iteration: str = "ring"):
+                 bufs=None, iteration: str = "ring", means: bool = False):
         """``bufs``: optional ring buffers to bind instead of allocating, d + 1
         (2 for the two-array iteration) contiguous device tensors of at least
         the ring's bytes each (for an FP32 ring inside an FP64 ring's memory,
         ``[b.view(torch.float32) for b in P.bufs]``; see :meth:`upcast`).
         ``iteration``: "ring" (Algorithm 2), "two_array" or "two_array_packed"
         (lcsb_create_iter; packed tables hold ``stored`` = packed_entries
-        entries, one per exchange orbit)."""
+        entries, one per exchange orbit).  ``means``: allocate and bind the
+        branch-mean buffers (lcsb_bind_means; sigma = d = 2 ring, h >= 3)."""
         import torch
 
         if dtype not in _DTYPES:
@@ -77,6 +78,14 @@ class Lcsb:
         ptrs = (C.c_void_p * self.nbuf)(*[b.data_ptr() for b in self.bufs])
         check(lib.lcsb_bind(ctx, ptrs, self.nbuf, C.c_void_p(self.ws.data_ptr()),
                             C.c_void_p(self.stream.cuda_stream)))
+        self.means = []
+        if means:
+            mb = C.c_uint64()
+            check(lib.lcsb_query_means(ctx, C.byref(mb)))
+            self.means = [torch.empty(mb.value, dtype=torch.uint8, device=self.device)
+                          for _ in range(self.nbuf)]
+            mptrs = (C.c_void_p * self.nbuf)(*[b.data_ptr() for b in self.means])
+            check(lib.lcsb_bind_means(ctx, mptrs, self.nbuf))
 
     # ------------------------------------------------------------------ C calls
     def init_zero(self):

@@ -77,6 +77,8 @@ def load():
     L.lcsb_query.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                              C.POINTER(C.c_uint64)]
     L.lcsb_bind.argtypes = [P, C.POINTER(P), C.c_int, P, P]
+    L.lcsb_query_means.argtypes = [P, C.POINTER(C.c_uint64)]
+    L.lcsb_bind_means.argtypes = [P, C.POINTER(P), C.c_int]
     L.lcsb_init_zero.argtypes = [P]
     L.lcsb_load_ring.argtypes = [P, C.POINTER(P), C.c_int, C.POINTER(C.c_double)]
     L.lcsb_iterate.argtypes = [P, C.c_int64]

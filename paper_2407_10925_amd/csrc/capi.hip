@@ -55,6 +55,11 @@ struct lcsb_ctx {
     int lags;        // tables the context keeps: d for the ring, 2 for the two-array iteration
     int packed;      // LCSB_ITER_TWO_ARRAY_PACKED: one entry per exchange orbit (packed_index)
     uint64_t entries;  // entries per table: g.ns, or packed_entries(h)
+    // branch-mean tables (lcsb_bind_means): per slot Ma, then Mab at mab_off
+    void *means_buf[4];
+    uint64_t mab_off;
+    int means_ok[4];    // the slot's means are those of its table
+    int entries_ok[4];  // the slot's entries hold its table (a branch-mean sweep may skip them)
 };
 
 namespace {
@@ -85,7 +90,35 @@ bool swap_shape(const lcsb_ctx *c)
     return (c->g.sigma == 2 && (c->g.d == 2 || c->g.d == 3)) || (c->g.sigma == 4 && c->g.d == 2);
 }
 
-void clear_lazy(lcsb_ctx *c) { for (int k = 0; k < 4; ++k) c->lazy[k] = 0; }
+// Every slot's entries were just (re)written from outside the branch-mean
+// sweep: complete, and no slot's means describe them.
+void clear_lazy(lcsb_ctx *c)
+{
+    for (int k = 0; k < 4; ++k) {
+        c->lazy[k] = 0;
+        c->means_ok[k] = 0;
+        c->entries_ok[k] = 1;
+    }
+}
+
+// sigma = d = 2 rings of l >= 3 symmetric in the two strings sweep from the
+// branch-mean tables once they are bound
+bool means_path(const lcsb_ctx *c)
+{
+    return c->means_buf[0] && !c->two_array && c->swap_sym && c->g.sigma == 2 && c->g.d == 2 &&
+           c->g.h >= 3;
+}
+
+uint64_t means_mab_offset(const lcsb_ctx *c)
+{
+    return ((c->g.ns / 2) * elem_size(c->dtype) + 255) & ~(uint64_t)255;
+}
+
+void *slot_ma(const lcsb_ctx *c, int slot) { return c->means_buf[slot]; }
+void *slot_mab(const lcsb_ctx *c, int slot)
+{
+    return static_cast<unsigned char *>(c->means_buf[slot]) + c->mab_off;
+}
 
 // Complete the exchanged entries of a lazily written slot (stream order).
 int materialize(lcsb_ctx *c, int slot)
@@ -221,6 +254,47 @@ int lcsb_bind(lcsb_ctx *c, void *const *bufs, int nbuf, void *ws, void *stream)
     return LCSB_OK;
 }
 
+int lcsb_query_means(const lcsb_ctx *c, uint64_t *bytes_per_buf)
+{
+    if (!c) return fail(LCSB_EINVAL, "null context");
+    if (c->two_array || c->g.sigma != 2 || c->g.d != 2 || c->g.h < 3)
+        return fail(LCSB_EUNSUPPORTED, "branch-mean tables serve the sigma = d = 2 ring at l >= 3");
+    if (bytes_per_buf)
+        *bytes_per_buf = means_mab_offset(c) + (c->g.ns / 4) * elem_size(c->dtype);
+    return LCSB_OK;
+}
+
+int lcsb_bind_means(lcsb_ctx *c, void *const *bufs, int nbuf)
+{
+    if (!c) return fail(LCSB_EINVAL, "null context");
+    if (c->state == kPoisoned) return fail(LCSB_ESTATE, "context poisoned by an earlier HIP error");
+    if (c->state < kBound) return fail(LCSB_ESTATE, "bind the ring buffers first");
+    int rc = lcsb_query_means(c, nullptr);
+    if (rc) return rc;
+    if (!bufs && nbuf == 0) {  // unbind: sweep from the entries again
+        for (int k = 0; k < 4; ++k) {
+            c->means_buf[k] = nullptr;
+            c->means_ok[k] = 0;
+        }
+        return LCSB_OK;
+    }
+    if (!bufs || nbuf != c->nbuf) return fail(LCSB_EINVAL, "need %d mean buffers", c->nbuf);
+    for (int k = 0; k < nbuf; ++k) {
+        if (!bufs[k] || ((uintptr_t)bufs[k] & 255))
+            return fail(LCSB_EINVAL, "mean buffer %d null or not 256-byte aligned", k);
+        for (int j = 0; j < c->nbuf; ++j)
+            if (bufs[k] == c->buf[j] || (j < k && bufs[j] == bufs[k]))
+                return fail(LCSB_EINVAL, "mean buffer %d aliases another buffer", k);
+        if (bufs[k] == c->ws) return fail(LCSB_EINVAL, "mean buffer %d is the workspace", k);
+    }
+    for (int k = 0; k < nbuf; ++k) {
+        c->means_buf[k] = bufs[k];
+        c->means_ok[k] = 0;
+    }
+    c->mab_off = means_mab_offset(c);
+    return LCSB_OK;
+}
+
 int lcsb_init_zero(lcsb_ctx *c)
 {
     if (!c) return fail(LCSB_EINVAL, "null context");
@@ -287,6 +361,40 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
     int rc = need_ready(c);
     if (rc) return rc;
     if (k < 0) return fail(LCSB_EINVAL, "negative sweep count");
+    if (means_path(c) && k > 0) {
+        // the means of lags 1 .. d, derived from their entries where stale
+        for (int j = 1; j <= c->g.d; ++j) {
+            const int slot = slot_of_lag(c, j);
+            if (c->means_ok[slot]) continue;
+            if (!c->entries_ok[slot]) return fail(LCSB_ESTATE, "lag %d has neither entries nor means", j);
+            hipError_t e = launch_derive_means(c->g, c->dtype, c->buf[slot], c->lazy[slot],
+                                               slot_ma(c, slot), slot_mab(c, slot), c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "derive means");
+            c->means_ok[slot] = 1;
+        }
+        for (int64_t t = 0; t < k; ++t) {
+            MeansLaunch a;
+            a.s1 = slot_of_lag(c, 1);
+            a.s2 = slot_of_lag(c, 2);
+            a.snew = (c->head + 1) % c->nbuf;
+            a.ma1 = slot_ma(c, a.s1);
+            a.mab2 = slot_mab(c, a.s2);
+            // the entries of the last d tables: what a certificate or a caller reads
+            const bool entries = t >= k - c->g.d;
+            a.out = entries ? c->buf[a.snew] : nullptr;
+            a.ma_new = slot_ma(c, a.snew);
+            a.mab_new = slot_mab(c, a.snew);
+            a.offsets = reinterpret_cast<double *>(c->ws + Ws::kOffsets);
+            hipError_t e = launch_sweep_means(c->g, c->dtype, a, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+            c->lazy[a.snew] = 1;
+            c->means_ok[a.snew] = 1;
+            c->entries_ok[a.snew] = entries;
+            c->head = a.snew;
+            c->sweeps++;
+        }
+        return LCSB_OK;
+    }
     for (int64_t t = 0; t < k; ++t) {
         SweepLaunch a;
         memset(&a, 0, sizeof a);
@@ -313,6 +421,8 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
         hipError_t e = launch_sweep(c->g, c->dtype, a, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
         c->lazy[a.new_slot] = c->swap_sym && !c->packed;
+        c->means_ok[a.new_slot] = 0;
+        c->entries_ok[a.new_slot] = 1;
         c->head = a.new_slot;
         c->sweeps++;
         if ((rc = refresh_rate(c))) return rc;
@@ -405,7 +515,9 @@ int lcsb_certify_optimal_noalloc(int sigma, int d, int h, int dtype, const void 
     return LCSB_OK;
 }
 
-int lcsb_lag(const lcsb_ctx *c, int k, void **dev_ptr, double *offset)
+namespace {
+// lag k's stored entries (completed when lazily written) and offset
+int lag_pointer(const lcsb_ctx *c, int k, void **dev_ptr, double *offset)
 {
     int rc = need_ready(c);
     if (rc) return rc;
@@ -426,12 +538,23 @@ int lcsb_lag(const lcsb_ctx *c, int k, void **dev_ptr, double *offset)
     }
     return LCSB_OK;
 }
+}  // namespace
+
+int lcsb_lag(lcsb_ctx *c, int k, void **dev_ptr, double *offset)
+{
+    int rc = lag_pointer(c, k, dev_ptr, offset);
+    if (rc) return rc;
+    // the caller may write through the pointer: no branch-mean table is
+    // trusted until it is derived again from the entries
+    for (int j = 0; j < 4; ++j) c->means_ok[j] = 0;
+    return LCSB_OK;
+}
 
 int lcsb_read_table(const lcsb_ctx *c, int k, void *host_dst, int as_f64)
 {
     void *dev = nullptr;
     double off = 0.0;
-    int rc = lcsb_lag(c, k, &dev, &off);
+    int rc = lag_pointer(c, k, &dev, &off);
     if (rc) return rc;
     if (!host_dst) return fail(LCSB_EINVAL, "null host buffer");
     if (as_f64 != 0 && as_f64 != 1) return fail(LCSB_EINVAL, "as_f64 must be 0 or 1");
@@ -597,7 +720,11 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
     dst->sweeps = src->sweeps;
     dst->best = src->best;
     dst->swap_sym = src->swap_sym;
-    for (int k = 0; k < 4; ++k) dst->lazy[k] = src->lazy[k];  // same slots, converted as stored
+    for (int k = 0; k < 4; ++k) {
+        dst->lazy[k] = src->lazy[k];  // same slots, converted as stored
+        dst->means_ok[k] = 0;
+        dst->entries_ok[k] = 1;
+    }
     if ((rc = refresh_rate(dst))) return rc;
     dst->state = kReady;
     return LCSB_OK;

@@ -66,6 +66,45 @@ struct SweepLaunch {
 
 hipError_t launch_sweep(const Geometry &g, int dtype, const SweepLaunch &a, hipStream_t s);
 
+// Branch-mean tables of a folded sigma = d = 2 table T that is symmetric in
+// the two strings (n = 4^l, stored tuples s < n/2, l >= 3).  For a stored
+// group prefix P < n/8 (the tuples 4P .. 4P + 3 share all but their last
+// slot (a_l, b_l)):
+//   Ma[2P + b] = (T[4P + b] + T[4P + 2 + b]) * 1/2   the mean over a_l: what
+//                an advance-a branch reads (eq. (3) with string 1 moved)
+//   Mab[P]     = ((T[4P] + T[4P+3]) + (T[4P+1] + T[4P+2])) * 1/4
+//                the all-advance mean, in the complement-paired tree
+// Both are the means the entry-reading sweep forms, so a sweep that reads
+// them computes the same bits.  The advance-b mean over b_l of s is the
+// advance-a mean of the exchanged tuple; a tuple with string-1 head 1 is read
+// at its complement (the last b bit flips, a two-term sum does not care).
+__host__ __device__ inline uint64_t ma_index(uint64_t s, uint64_t n)
+{
+    if (s & (n >> 1)) s ^= n - 1;
+    return ((s >> 2) << 1) | (s & 1);
+}
+__host__ __device__ inline uint64_t mab_index(uint64_t s, uint64_t n)
+{
+    if (s & (n >> 1)) s ^= n - 1;
+    return s >> 2;
+}
+
+struct MeansLaunch {
+    const void *ma1;   // Ma of lag 1
+    const void *mab2;  // Mab of lag 2
+    void *out;         // the new table's entries, or null: not written this sweep
+    void *ma_new, *mab_new;
+    double *offsets;   // device, per slot (FP32)
+    int s1, s2, snew;  // slots of lag 1, lag 2 and the new table
+};
+// Entries of lag 1 and lag 2 are not read.  FP32 tables (and their means)
+// are relative to their slot's offset, as in launch_sweep.
+hipError_t launch_sweep_means(const Geometry &g, int dtype, const MeansLaunch &a, hipStream_t s);
+// Ma and Mab of a stored table (lazy: only the lower index of each exchanged
+// pair holds a value, see TwinGroup)
+hipError_t launch_derive_means(const Geometry &g, int dtype, const void *table, int lazy,
+                               void *ma, void *mab, hipStream_t s);
+
 // Certificate passes (see lcsb_cert); results land in the workspace scalars.
 // swap_sym: as in SweepLaunch (the W pass then evaluates one coordinate per
 // exchange pair)

@@ -146,6 +146,26 @@ __device__ __forceinline__ void stream4(const T *p, T *g)
     }
 }
 
+// an adjacent pair as one 8-byte (FP32) or 16-byte (FP64) access, p aligned
+// to the pair's size
+template <typename T>
+using Pair2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ void pair_load(const T *p, T &a, T &b)
+{
+    const Pair2<T> v = __builtin_nontemporal_load(reinterpret_cast<const Pair2<T> *>(p));
+    a = v.x;
+    b = v.y;
+}
+template <typename T>
+__device__ __forceinline__ void pair_put(T *p, T a, T b)
+{
+    Pair2<T> v;
+    v.x = a;
+    v.y = b;
+    __builtin_nontemporal_store(v, reinterpret_cast<Pair2<T> *>(p));
+}
+
 constexpr uint64_t kAlt2 = 0xAAAAAAAAAAAAAAAAull;  // high bit of every 2-bit slot
 constexpr uint64_t kAlt4Hi = 0xCCCCCCCCCCCCCCCCull; // high 2-bit field of every nibble
 
@@ -273,6 +293,179 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2(const T *__restrict__ lag1,
         put(out + nq + t, v0);
         put(out + nq + xc, v1);
     }
+}
+
+// ---------------------------------------------------------------- sigma = d = 2 from branch means
+// The values of sweep_s2d2<T, true, SHIFT> (rings symmetric in the two
+// strings) from the branch-mean tables of the lags (ma_index, mab_index)
+// instead of their entries: an all-match tuple reads one all-advance mean of
+// lag 2, a mismatched one an advance-a and an advance-b mean of lag 1 (the
+// latter at the exchanged tuple).  Every mean is the one the entry-reading
+// kernel forms, so the values agree bit for bit, and a branch reads one
+// value instead of two or four.  The kernel writes the new table's means, and
+// its entries when `out` is given.
+//
+// Thread j < n/32 owns the tails t = 4j + v, v = (a_l, b_l) = 0..3 (a_2 = 0),
+// and computes 0/0|t and 0/0|~t (one value: an all-match tuple drops both
+// heads), 0/1|t and 0/1|~t: every member of the four aligned groups with
+// prefixes j and ~j at heads 0/0 and 0/1, so each group mean it writes comes
+// from its own registers.  The exchanged quad p (Sj, or ~Sj when b_2 = 1)
+// computes the same values; only the lower of j and p runs (p = j: the quad
+// is its own twin), and it also writes the means of p's groups: their
+// advance-a means are its own groups' advance-b means, their all-advance means
+// its own (Mab only at the lower prefix of each exchanged pair of groups:
+// the readers are lower quads).  Within a thread the four advance-a means of one head lie at
+// offsets {0, 1, 4, 5} from the v = 0 one, the four advance-b means at
+// {0, 4, 1, 5}, descending when b_2 = 1: two loads of adjacent pairs each.
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(kBlock) void sweep_s2d2_means(const T *__restrict__ ma1,
+                                                          const T *__restrict__ mab2,
+                                                          T *__restrict__ out,
+                                                          T *__restrict__ ma_new,
+                                                          T *__restrict__ mab_new, uint64_t n,
+                                                          double *__restrict__ off, int s1,
+                                                          int s2, int snew)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kShift = kF32 || SHIFT;  // lag 2 carries delta_2
+    const uint64_t nq = n >> 2, n16 = n >> 4;
+    const uint64_t j = thread_index();
+    T d2 = 0, y0 = 0;
+    if constexpr (!kF32 && SHIFT) d2 = off[s2] - off[s1];
+    if constexpr (kF32) {
+        const double o1 = off[s1];
+        d2 = (float)(off[s2] - o1);
+        y0 = 1.0f + first(mab2[0] + d2);
+        if (j == 0) off[snew] = o1 + (double)y0;
+    }
+    if (j >= (n >> 5)) return;
+    const uint64_t mq = n16 - 1, qa = kAlt2 & mq;
+    const uint64_t sj = ((j & qa) >> 1) | ((j & ~qa & mq) << 1);
+    const bool b2 = (j & (n16 >> 2)) != 0;
+    const uint64_t pj = b2 ? sj ^ mq : sj;
+    if (pj < j) return;
+
+    // all-match: the lag-2 all-advance means of t = 4j .. 4j + 3.  Mab holds
+    // the lower prefix of each exchanged pair (the twin of 4j + v is
+    // 4p + perm(v)); in a quad that is its own twin the upper members are
+    // taken from their partners in the same load.
+    T g[4];
+    stream4<true>(mab2 + 4 * j, g);
+    if (pj == j) {
+#pragma unroll
+        for (int v = 1; v < 4; ++v) {
+            const int sv = ((v & 1) << 1) | (v >> 1), pv = b2 ? 3 - sv : sv;
+            if (pv < v) g[v] = g[pv];
+        }
+    }
+    T a[4], b[4], c[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        T m2 = g[v];
+        if constexpr (kShift) m2 = m2 + d2;
+        a[v] = (T)1 + first(m2);
+    }
+    // mismatched: 0/1|t (cc = 0) and 0/1|~t (cc = 1)
+    const uint64_t am = kAlt2 & (n - 1), bm = ~kAlt2 & (n - 1);
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+        const uint64_t i0 = nq + (cc ? nq - 1 - 4 * j : 4 * j);  // the v = 0 tuple
+        const uint64_t sa0 = ((i0 << 2) & am) | (i0 & bm);
+        const uint64_t sb0 = (i0 & am) | ((i0 << 2) & bm);
+        const uint64_t ia = ma_index(sa0, n);
+        const uint64_t ib = ma_index(exchange_twin(sb0, n, 2), n);
+        T ma[4], mb[4], p0, p1, q0, q1;
+        pair_load(ma1 + ia, p0, p1);
+        pair_load(ma1 + ia + 4, q0, q1);
+        ma[0] = p0; ma[1] = p1; ma[2] = q0; ma[3] = q1;
+        // descending where the exchange complements symbols of t itself:
+        // the exchanged tuple of 0/1|t has string-1 head b_2 (complemented
+        // when 1); that of 0/1|~t has ~b_2 and its symbols are already
+        // complemented (uncomplemented when ~b_2 = 1)
+        const bool desc = b2;
+        pair_load(ma1 + (desc ? ib - 5 : ib), p0, p1);
+        pair_load(ma1 + (desc ? ib - 1 : ib + 4), q0, q1);
+        mb[0] = desc ? q1 : p0;
+        mb[1] = desc ? p1 : q0;
+        mb[2] = desc ? q0 : p1;
+        mb[3] = desc ? p0 : q1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) (cc ? c : b)[v] = vmax(first(mb[v]), ma[v]);
+    }
+    if constexpr (kF32) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            a[v] = (T)(a[v] - y0);
+            b[v] = (T)(b[v] - y0);
+            c[v] = (T)(c[v] - y0);
+        }
+    }
+
+    if (out) {  // entries at the lower index of each exchanged pair, as sweep_s2d2
+        // 0/0|t at t; 0/0|~t at ~St = 4(~Sj) + 3 - S(v); 0/1|t at t; 0/1|~t at St = 4Sj + S(v)
+        put(out + 4 * j, a[0]); put(out + 4 * j + 1, a[1]);
+        put(out + 4 * j + 2, a[2]); put(out + 4 * j + 3, a[3]);
+        const uint64_t nsj = 4 * (mq - sj);
+        put(out + nsj, a[3]); put(out + nsj + 1, a[1]);
+        put(out + nsj + 2, a[2]); put(out + nsj + 3, a[0]);
+        put(out + nq + 4 * j, b[0]); put(out + nq + 4 * j + 1, b[1]);
+        put(out + nq + 4 * j + 2, b[2]); put(out + nq + 4 * j + 3, b[3]);
+        const uint64_t psj = nq + 4 * sj;
+        put(out + psj, c[0]); put(out + psj + 1, c[2]);
+        put(out + psj + 2, c[1]); put(out + psj + 3, c[3]);
+    }
+
+    // the four groups: prefixes j and ~j (= mq - j) at heads 0/0 and 0/1,
+    // members in order v; the ~j groups hold the ~t values reversed
+    const T half = (T)0.5, quarter = (T)0.25;
+    const T mall0 = pair4(a[0], a[1], a[2], a[3]) * quarter;  // both 0/0 groups
+    const T mall1 = pair4(b[0], b[1], b[2], b[3]) * quarter;
+    const T mall2 = pair4(c[0], c[1], c[2], c[3]) * quarter;
+    const uint64_t P[4] = {j, mq - j, n16 + j, n16 + mq - j};
+    const T m[4][4] = {{a[0], a[1], a[2], a[3]},
+                       {a[3], a[2], a[1], a[0]},
+                       {b[0], b[1], b[2], b[3]},
+                       {c[3], c[2], c[1], c[0]}};
+    const T mall[4] = {mall0, mall0, mall1, mall2};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t g4 = 4 * P[k];
+        pair_put(ma_new + 2 * P[k], (m[k][0] + m[k][2]) * half, (m[k][1] + m[k][3]) * half);
+        // Mab at the lower prefix of the group and its exchanged twin
+        const uint64_t tw = mab_index(exchange_twin(g4, n, 2), n);
+        put(mab_new + (tw < P[k] ? tw : P[k]), mall[k]);
+        if (pj != j) {
+            // the exchanged quad's group: its advance-a means are this group's
+            // advance-b means over b_l for a_l = 0 and 1, one adjacent pair,
+            // reversed where the exchange complements
+            const uint64_t x0 = ma_index(exchange_twin(g4, n, 2), n);
+            const T mb0 = (m[k][0] + m[k][1]) * half, mb1 = (m[k][2] + m[k][3]) * half;
+            if (x0 & 1) pair_put(ma_new + (x0 - 1), mb1, mb0);
+            else pair_put(ma_new + x0, mb0, mb1);
+        }
+    }
+}
+
+// Ma and Mab of a stored table, one thread per group prefix P < n/8
+template <typename T>
+__global__ __launch_bounds__(kBlock) void derive_means(const T *__restrict__ tab, int lazy,
+                                                      T *__restrict__ ma, T *__restrict__ mab,
+                                                      uint64_t n)
+{
+    const uint64_t P = thread_index();
+    if (P >= (n >> 3)) return;
+    T e[4];
+    if (lazy) {
+        const TwinGroup tg = twin_group(4 * P, n);
+        T q[4];
+        load4(tab + tg.read, q);
+        twin_values(q, tg.mode, e);
+    } else {
+        load4(tab + 4 * P, e);
+    }
+    ma[2 * P] = (e[0] + e[2]) * (T)0.5;
+    ma[2 * P + 1] = (e[1] + e[3]) * (T)0.5;
+    mab[P] = pair4(e[0], e[1], e[2], e[3]) * (T)0.25;
 }
 
 // ---------------------------------------------------------------- sigma = 4, d = 2
@@ -872,6 +1065,38 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
 }
 
 }  // namespace
+
+template <typename T>
+hipError_t means_typed(const Geometry &g, const MeansLaunch &a, hipStream_t s)
+{
+    sweep_s2d2_means<T, false><<<sweep_grid(g.n >> 5), dim3(kBlock), 0, s>>>(
+        static_cast<const T *>(a.ma1), static_cast<const T *>(a.mab2), static_cast<T *>(a.out),
+        static_cast<T *>(a.ma_new), static_cast<T *>(a.mab_new), g.n, a.offsets, a.s1, a.s2,
+        a.snew);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_means(const Geometry &g, int dtype, const MeansLaunch &a, hipStream_t s)
+{
+    if (g.sigma != 2 || g.d != 2 || g.h < 3) return hipErrorInvalidValue;
+    return dtype == LCSB_F32 ? means_typed<float>(g, a, s) : means_typed<double>(g, a, s);
+}
+
+hipError_t launch_derive_means(const Geometry &g, int dtype, const void *table, int lazy,
+                               void *ma, void *mab, hipStream_t s)
+{
+    if (g.sigma != 2 || g.d != 2 || g.h < 3) return hipErrorInvalidValue;
+    const dim3 grid = sweep_grid(g.n >> 3);
+    if (dtype == LCSB_F32)
+        derive_means<float><<<grid, dim3(kBlock), 0, s>>>(static_cast<const float *>(table), lazy,
+                                                          static_cast<float *>(ma),
+                                                          static_cast<float *>(mab), g.n);
+    else
+        derive_means<double><<<grid, dim3(kBlock), 0, s>>>(static_cast<const double *>(table),
+                                                           lazy, static_cast<double *>(ma),
+                                                           static_cast<double *>(mab), g.n);
+    return hipGetLastError();
+}
 
 hipError_t launch_sweep(const Geometry &g, int dtype, const SweepLaunch &a, hipStream_t s)
 {

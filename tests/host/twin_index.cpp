@@ -6,6 +6,7 @@
 #include "internal.h"
 
 #include <cstdio>
+#include <vector>
 
 using namespace lcsb;
 
@@ -159,8 +160,157 @@ static void packed(int h, uint64_t count = 0)
            (unsigned long long)valid, (unsigned long long)((n + 2 * (1ull << h)) / 4));
 }
 
+// Branch-mean tables (sigma = d = 2, rings symmetric in the two strings):
+// on a table that gives every orbit of the complement and the exchange one
+// pseudo-random integer (an all-match tuple one for its tail's orbit, as a
+// sweep's output has; so every mean below is exact), the means the
+// branch-mean sweep reads (its v = 0 index plus the fixed offsets {0, 1, 4,
+// 5} and {0, 4, 1, 5}, descending where stated) equal the means the
+// entry-reading sweep forms, every index it reads or writes is in range, the
+// entries and means it writes (its own groups' and the exchanged quad's)
+// equal their definitions, and, over all quads, the writes cover Ma and every
+// Mab entry a sweep reads (the lower prefix of each exchanged pair).  `count` > 0: that many hashed quads (plus the first and last).
+static double orbit_value(uint64_t s, uint64_t n)
+{
+    // all-match heads: the value depends only on the tail (in its orbit)
+    const bool match = ((s >> 1) ^ s) & (n >> 2) ? false : true;
+    if (match) s &= (n >> 2) - 1;  // the tail, flagged apart below
+    const uint64_t m = match ? (n >> 2) - 1 : n - 1;
+    const uint64_t am = 0xAAAAAAAAAAAAAAAAull & m;
+    const uint64_t e = ((s & am) >> 1) | ((s & ~am & m) << 1), c = s ^ m, ec = e ^ m;
+    uint64_t r = s < c ? s : c;
+    r = r < e ? r : e;
+    r = r < ec ? r : ec;
+    if (match) r |= 1ull << 62;
+    uint64_t z = (r + 0x9E3779B97F4A7C15ull) * 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 29;
+    return (double)(z & 0xFFFF);
+}
+
+static void means(int h, uint64_t count = 0)
+{
+    const uint64_t n = 1ull << (2 * h), nq = n / 4, n16 = n / 16, mq = n16 - 1;
+    const uint64_t alt = 0xAAAAAAAAAAAAAAAAull;
+    const uint64_t am = alt & (n - 1), bm = ~alt & (n - 1), qa = alt & mq;
+    auto T = [&](uint64_t s) { return orbit_value(s, n); };
+    auto ma_def = [&](uint64_t k) {
+        const uint64_t P = k >> 1, b = k & 1;
+        return (T(4 * P + b) + T(4 * P + 2 + b)) * 0.5;
+    };
+    auto mab_def = [&](uint64_t P) {
+        return ((T(4 * P) + T(4 * P + 3)) + (T(4 * P + 1) + T(4 * P + 2))) * 0.25;
+    };
+    std::vector<char> wa(count ? 0 : n / 4), wab(count ? 0 : n / 8);
+    std::vector<uint64_t> need_ab;
+    const uint64_t quads = n >> 5;
+    const uint64_t visits = count ? count + 2 : quads;
+    for (uint64_t k = 0; k < visits; ++k) {
+        const uint64_t j = !count ? k : k == count ? 0 : k == count + 1 ? quads - 1
+                                                   : (k * 0x9E3779B97F4A7C15ull) % quads;
+        const uint64_t sj = ((j & qa) >> 1) | ((j & ~qa & mq) << 1);
+        const bool b2 = (j & (n16 >> 2)) != 0;
+        const uint64_t pj = b2 ? sj ^ mq : sj;
+        if (pj < j) continue;
+        // reads
+        double a[4], b[4], c[4];
+        for (int v = 0; v < 4; ++v) {
+            const uint64_t t = 4 * j + (uint64_t)v;
+            EXPECT(t < n / 8, "h=%d: all-advance mean index %llu out of range", h, (unsigned long long)t);
+            // Mab is kept at the lower prefix of each exchanged pair: t is
+            // lower, or (a quad that is its own twin) its partner lies in the
+            // same quad at perm(v) < v
+            const uint64_t tw = mab_index(exchange_twin(4 * t, n, 2), n);
+            const int sv = ((v & 1) << 1) | (v >> 1), pv = b2 ? 3 - sv : sv;
+            EXPECT(tw >= t || (pj == j && tw == 4 * j + (uint64_t)pv && pv < v),
+                   "h=%d j=%llu v=%d: all-advance mean not at a kept prefix", h, (unsigned long long)j, v);
+            if (!count) need_ab.push_back(tw < t ? tw : t);
+            const double want = ((T(4 * t) + T(4 * t + 3)) + (T(4 * t + 1) + T(4 * t + 2))) * 0.25;
+            EXPECT(mab_def(t) == want, "h=%d t=%llu: all-advance mean", h, (unsigned long long)t);
+            a[v] = T(t);
+        }
+        for (int cc = 0; cc < 2; ++cc) {
+            const uint64_t i0 = nq + (cc ? nq - 1 - 4 * j : 4 * j);
+            const uint64_t ia = ma_index(((i0 << 2) & am) | (i0 & bm), n);
+            const uint64_t ib = ma_index(exchange_twin((i0 & am) | ((i0 << 2) & bm), n, 2), n);
+            const bool desc = b2;
+            // the pair loads start at even indices (8- and 16-byte aligned)
+            EXPECT(ia % 2 == 0 && ib % 2 == (desc ? 1u : 0u), "h=%d j=%llu cc=%d: pair alignment", h,
+                   (unsigned long long)j, cc);
+            static const int offa[4] = {0, 1, 4, 5}, offb[4] = {0, 4, 1, 5};
+            for (int v = 0; v < 4; ++v) {
+                const uint64_t t = 4 * j + (uint64_t)v, i = nq + (cc ? nq - 1 - t : t);
+                const uint64_t sa = ((i << 2) & am) | (i & bm), sb = (i & am) | ((i << 2) & bm);
+                const uint64_t xa = ma_index(sa, n), xb = ma_index(exchange_twin(sb, n, 2), n);
+                EXPECT(xa < n / 4 && xb < n / 4, "h=%d j=%llu: mean index out of range", h,
+                       (unsigned long long)j);
+                EXPECT(xa == ia + offa[v], "h=%d j=%llu cc=%d v=%d: advance-a offset",
+                       h, (unsigned long long)j, cc, v);
+                EXPECT(xb == (desc ? ib - offb[v] : ib + offb[v]), "h=%d j=%llu cc=%d v=%d: advance-b offset",
+                       h, (unsigned long long)j, cc, v);
+                EXPECT(ma_def(xa) == (T(sa) + T(sa + 2)) * 0.5, "h=%d i=%llu: advance-a mean", h,
+                       (unsigned long long)i);
+                EXPECT(ma_def(xb) == (T(sb) + T(sb + 1)) * 0.5, "h=%d i=%llu: advance-b mean", h,
+                       (unsigned long long)i);
+                (cc ? c : b)[v] = T(i);
+            }
+        }
+        // entry writes (positions the kernel stores when asked)
+        static const int pos_nsj[4] = {3, 1, 2, 0}, pos_psj[4] = {0, 2, 1, 3};
+        for (int v = 0; v < 4; ++v) {
+            const uint64_t t = 4 * j + (uint64_t)v;
+            EXPECT(T(t) == a[v] && T(nq + t) == b[v], "h=%d: own entry", h);
+            EXPECT(T(4 * (mq - sj) + (uint64_t)pos_nsj[v]) == a[v], "h=%d j=%llu v=%d: 0/0 twin entry", h,
+                   (unsigned long long)j, v);
+            EXPECT(T(nq + 4 * sj + (uint64_t)pos_psj[v]) == c[v], "h=%d j=%llu v=%d: 0/1 twin entry", h,
+                   (unsigned long long)j, v);
+        }
+        // mean writes
+        const uint64_t P[4] = {j, mq - j, n16 + j, n16 + mq - j};
+        const double m[4][4] = {{a[0], a[1], a[2], a[3]}, {a[3], a[2], a[1], a[0]},
+                                {b[0], b[1], b[2], b[3]}, {c[3], c[2], c[1], c[0]}};
+        for (int g = 0; g < 4; ++g) {
+            const double mall = ((m[g][0] + m[g][3]) + (m[g][1] + m[g][2])) * 0.25;
+            for (int x = 0; x < 4; ++x)
+                EXPECT(T(4 * P[g] + (uint64_t)x) == m[g][x], "h=%d j=%llu: group %d member %d", h,
+                       (unsigned long long)j, g, x);
+            const uint64_t twp = mab_index(exchange_twin(4 * P[g], n, 2), n);
+            uint64_t wi[6] = {2 * P[g], 2 * P[g] + 1, twp < P[g] ? twp : P[g], 0, 0, 0};
+            double wv[6] = {(m[g][0] + m[g][2]) * 0.5, (m[g][1] + m[g][3]) * 0.5, mall, 0, 0, 0};
+            int nw = 3;
+            if (pj != j) {
+                wi[3] = ma_index(exchange_twin(4 * P[g], n, 2), n);
+                wi[4] = ma_index(exchange_twin(4 * P[g] + 2, n, 2), n);
+                // one aligned pair: ascending from an even index, else descending
+                EXPECT(wi[4] == (wi[3] & 1 ? wi[3] - 1 : wi[3] + 1), "h=%d j=%llu group %d: twin pair", h,
+                       (unsigned long long)j, g);
+                wv[3] = (m[g][0] + m[g][1]) * 0.5;
+                wv[4] = (m[g][2] + m[g][3]) * 0.5;
+                nw = 5;
+            }
+            for (int w = 0; w < nw; ++w) {
+                const bool isab = w == 2;
+                EXPECT(wi[w] < (isab ? n / 8 : n / 4), "h=%d: mean write out of range", h);
+                if (wi[w] >= (isab ? n / 8 : n / 4)) continue;
+                EXPECT((isab ? mab_def(wi[w]) : ma_def(wi[w])) == wv[w],
+                       "h=%d j=%llu group %d write %d: value differs from the definition", h,
+                       (unsigned long long)j, g, w);
+                if (!count) (isab ? wab : wa)[wi[w]] = 1;
+            }
+        }
+    }
+    if (count) return;
+    uint64_t miss = 0;
+    for (char f : wa) miss += !f;
+    EXPECT(miss == 0, "h=%d: %llu advance-a means never written", h, (unsigned long long)miss);
+    miss = 0;
+    for (uint64_t P : need_ab) miss += !wab[P];
+    EXPECT(miss == 0, "h=%d: %llu all-advance means read but never written", h, (unsigned long long)miss);
+}
+
 int main()
 {
+    for (int h = 3; h <= 10; ++h) means(h);
+    for (int h = 11; h <= 18; ++h) means(h, 1u << 16);
     for (int h = 2; h <= 10; ++h) packed(h);
     for (int h = 11; h <= 18; ++h) packed(h, 1u << 18);
     for (int h = 2; h <= 10; ++h) groups<2>(h);

@@ -97,6 +97,39 @@ def test_call_order_is_enforced_without_a_gpu(lib):
     assert lib.lcsb_destroy(None) == 0
 
 
+def test_branch_mean_buffers_are_checked_without_a_gpu(lib):
+    """lcsb_query_means / lcsb_bind_means: sizes for the sigma = d = 2 ring
+    (Ma, n/4 entries, then Mab, n/8, at a 256-byte boundary), refusals for
+    other shapes, iterations and l < 3, and pointer checks before anything is
+    stored (no buffer is dereferenced)."""
+    from paper_2407_10925_amd import _capi
+    mb = C.c_uint64()
+    for (sigma, d, h, it) in ((2, 3, 5, 0), (4, 2, 4, 0), (2, 2, 2, 0), (2, 2, 5, 1), (2, 2, 5, 2)):
+        ctx = C.c_void_p()
+        assert lib.lcsb_create_iter(sigma, d, h, 0, it, C.byref(ctx)) == 0
+        assert lib.lcsb_query_means(ctx, C.byref(mb)) == _capi.LCSB_EUNSUPPORTED, (sigma, d, h, it)
+        assert lib.lcsb_destroy(ctx) == 0
+    for dtype, elem in ((0, 8), (1, 4)):
+        ctx = C.c_void_p()
+        assert lib.lcsb_create(2, 2, 5, dtype, C.byref(ctx)) == 0
+        n = 4 ** 5
+        assert lib.lcsb_query_means(ctx, C.byref(mb)) == 0
+        ma = (n // 4) * elem
+        assert mb.value == (ma + 255) // 256 * 256 + (n // 8) * elem
+        means = (C.c_void_p * 3)(4096, 8192, 12288)
+        assert lib.lcsb_bind_means(ctx, means, 3) == _capi.LCSB_ESTATE  # before lcsb_bind
+        bufs = (C.c_void_p * 3)(256, 512, 768)
+        assert lib.lcsb_bind(ctx, bufs, 3, C.c_void_p(1024), None) == 0
+        assert lib.lcsb_bind_means(ctx, means, 2) == _capi.LCSB_EINVAL
+        assert lib.lcsb_bind_means(ctx, (C.c_void_p * 3)(4096, 8200, 12288), 3) == _capi.LCSB_EINVAL
+        assert lib.lcsb_bind_means(ctx, (C.c_void_p * 3)(4096, 512, 12288), 3) == _capi.LCSB_EINVAL
+        assert lib.lcsb_bind_means(ctx, (C.c_void_p * 3)(4096, 4096, 12288), 3) == _capi.LCSB_EINVAL
+        assert lib.lcsb_bind_means(ctx, (C.c_void_p * 3)(4096, 1024, 12288), 3) == _capi.LCSB_EINVAL
+        assert lib.lcsb_bind_means(ctx, means, 3) == 0
+        assert lib.lcsb_bind_means(ctx, None, 0) == 0  # unbind
+        assert lib.lcsb_destroy(ctx) == 0
+
+
 def test_python_binding_refuses_without_gpu():
     import torch
     import paper_2407_10925_amd as pk

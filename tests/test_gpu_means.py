@@ -1,0 +1,188 @@
+"""Branch-mean sweeps (lcsb_bind_means; the sigma = d = 2 ring) against the
+entry-reading sweep and the oracle.  A ring with mean buffers bound reads one
+mean per branch (Ma, Mab) instead of the entries, writes the entries only on
+the last d sweeps of each lcsb_iterate call, and re-derives the means after
+anything else writes the tables.  Every table a caller sees, the offsets and
+every certificate field are the same, bit for bit, as without the means:
+along zero-start trajectories in chunks of 1 .. 64 sweeps, after writes
+through lcsb_lag, across lcsb_run, lcsb_upcast, checkpoints and unbinding,
+and at the benchmark's full size (l = 16 FP32, l = 14 FP64)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+CERT_FIELDS = ("R", "E", "maxW", "rho", "bound", "argmax_W", "nonfinite", "kind", "sweep")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pk():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_2407_10925_amd as pk
+    return pk
+
+
+def _pair(pk, h, dtype):
+    T = pk.Lcsb(2, 2, h, dtype)
+    M = pk.Lcsb(2, 2, h, dtype, means=True)
+    T.init_zero()
+    M.init_zero()
+    assert T.swap_symmetric() and M.swap_symmetric()
+    return T, M
+
+
+def _same_certs(T, M, tag=""):
+    for kind in ("feasible", "optimal"):
+        if kind == "feasible":
+            (ct, bt), (cm, bm) = T.certify(), M.certify()
+        else:
+            (ct, bt), (cm, bm) = T.certify_optimal(), M.certify_optimal()
+        for f in CERT_FIELDS:
+            for x, y in ((ct, cm), (bt, bm)):
+                same = x[f] == y[f] or (isinstance(x[f], float) and math.isnan(x[f])
+                                        and math.isnan(y[f]))
+                assert same, (tag, kind, f, x[f], y[f])
+
+
+def _same_tables_host(T, M, tag=""):
+    """Lags 1 and 2 as stored and as FP64 true values (read_table leaves the
+    means of the mean context in use)."""
+    for k in (1, 2):
+        for as_f64 in (False, True):
+            a, b = T.read_table(k, as_f64), M.read_table(k, as_f64)
+            if not np.array_equal(a, b):
+                bad = int(np.nonzero(a != b)[0][0])
+                raise AssertionError(f"{tag} lag {k} as_f64={as_f64}: entry {bad} "
+                                     f"{a[bad]!r} vs {b[bad]!r}")
+
+
+@pytest.mark.parametrize("h", [3, 6])
+def test_means_trajectory_matches_the_oracle(pk, h):
+    """FP64 zero start, in chunks that cross lcsb_iterate calls (1, 1, 2, 3, 5,
+    8, 13, 27 sweeps): lags 1 and 2 equal the oracle's ring, entry for entry."""
+    say(f"means vs oracle: h={h}")
+    M = pk.Lcsb(2, 2, h, "f64", means=True)
+    M.init_zero()
+    N = 4 ** h
+    ring = [np.zeros(N), np.zeros(N)]
+    done = 0
+    for chunk in (1, 1, 2, 3, 5, 8, 13, 27):
+        for _ in range(chunk):
+            ring = [oracle.sweep(2, 2, h, ring), ring[0]]
+        M.iterate(chunk)
+        done += chunk
+        for k in (1, 2):
+            got = M.read_table(k)
+            assert np.array_equal(got, ring[k - 1][: N // 2]), (done, k)
+
+
+@pytest.mark.parametrize("h", [3, 4, 5, 8, 10])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_means_ring_matches_the_entry_ring(pk, h, dtype):
+    say(f"means vs entries: h={h} {dtype}")
+    T, M = _pair(pk, h, dtype)
+    done = 0
+    for chunk in (1, 2, 7, 40, 64, 0, 1):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        done += chunk
+        _same_tables_host(T, M, f"after {done}")
+        _same_certs(T, M, f"after {done}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_writes_through_lag_are_seen_by_the_next_sweep(pk, dtype):
+    """Values planted through lcsb_lag (both members of an exchanged pair, so
+    the ring stays symmetric) in lag 1 and in lag 2: the mean context derives
+    its means again and follows the entry context."""
+    h = 7
+    say(f"means after writes through lcsb_lag: {dtype}")
+    T, M = _pair(pk, h, dtype)
+    T.iterate(9)
+    M.iterate(9)
+    n = 4 ** h
+    am = int("10" * h, 2)
+    for k, i in ((1, 0x1357), (2, 0x0ace)):  # stored indices (below n/2 = 8192)
+        e = ((i & am) >> 1) | ((i & (am >> 1)) << 1)
+        if e >= n // 2:
+            e ^= n - 1
+        for L in (T, M):
+            t, _ = L.lag(k)
+            t[i] = t[i] + 0.375
+            if e != i:
+                t[e] = t[e] + 0.375
+        torch.cuda.synchronize()
+    assert T.swap_symmetric() and M.swap_symmetric()
+    for chunk in (1, 4):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        _same_tables_host(T, M, f"planted, +{chunk}")
+        _same_certs(T, M, f"planted, +{chunk}")
+
+
+def test_run_upcast_checkpoint_and_unbind(pk, tmp_path):
+    """lcsb_run (largest-r certificate every 8 sweeps) stops at the same sweep
+    with the same bound; the FP32 ring upcast to an FP64 ring (buffers of its
+    own) polishes the same; a checkpoint of the mean context resumes into a
+    fresh mean context; unbinding the means leaves the entry sweep in charge."""
+    h = 10
+    say("means: run, upcast, checkpoint, unbind")
+    res = []
+    for means in (False, True):
+        L = pk.Lcsb(2, 2, h, "f32", means=means)
+        L.init_zero()
+        cur, best, certs, why = L.run(8, max_sweeps=160, stop_delta=1e-9, certificate="optimal")
+        P = pk.Lcsb(2, 2, h, "f64", means=means)
+        P.upcast(L)
+        P.iterate(24)
+        res.append((cur["sweep"], best["bound"], best["argmax_W"], certs, why,
+                    P.read_table(1).tobytes(), P.read_table(2).tobytes()))
+        del L, P
+    assert res[0] == res[1]
+
+    T, M = _pair(pk, h, "f64")
+    T.iterate(11)
+    M.iterate(11)
+    path = str(tmp_path / "means.ckpt")
+    M.save(path)
+    R = pk.Lcsb(2, 2, h, "f64", means=True)
+    R.load(path)
+    for L in (T, R):
+        L.iterate(13)
+    _same_tables_host(T, R, "resumed")
+    _same_certs(T, R, "resumed")
+    M._lib.lcsb_bind_means(M._ctx, None, 0)
+    M.iterate(13)
+    _same_tables_host(T, M, "unbound")
+
+
+@pytest.mark.parametrize("h,dtype,first,rest", [(16, "f32", 3, 17), (14, "f64", 3, 29)])
+def test_means_full_size_matches_the_entry_ring(pk, h, dtype, first, rest):
+    """The benchmark's sizes: whole lags compared on the device after sweeps
+    that cross an lcsb_iterate call, and both certificates."""
+    say(f"means full size: h={h} {dtype} {first}+{rest} sweeps")
+    torch.cuda.empty_cache()
+    T, M = _pair(pk, h, dtype)
+    for chunk in (first, rest):
+        T.iterate(chunk)
+        M.iterate(chunk)
+    _same_certs(T, M, "full size")
+    for k in (1, 2):
+        a, ao = T.lag(k)
+        b, bo = M.lag(k)
+        assert ao == bo
+        assert torch.equal(a, b), k
+    del T, M
+    torch.cuda.empty_cache()

@@ -11,13 +11,17 @@ index) over the K timed steps, with the ring already resident in HBM.
 
 The zero-start ring is symmetric in the two strings, so the sweep runs the
 exchange-folded kernel (one tuple of each exchanged pair computed and
-stored; the table is completed only where it is read as a whole).
+stored; the table is completed only where it is read as a whole), and it
+reads the branch means of the lags (lcsb_bind_means: one advance-a,
+advance-b or all-advance mean per branch instead of its 2 or 4 entries),
+writing the entries of the new table on the last two sweeps of each period.
 
 Also printed in the same JSON line:
   roofline      the sweep kernel's algorithmic bytes per launch (6 B per
                 stored FP32 entry: lag 1 and lag 2 read, and the new table
                 written, at one entry of each exchanged pair; 3 B per
-                update) over its average launch time
+                update) over its average launch time (the branch-mean sweep
+                moves fewer bytes than this: see traffic)
                 (traffic_GBps / traffic_frac: the same with the measured HBM
                 bytes), from HIP events on the stream
                 the library launches on, against the 8 TB/s HBM peak; traffic
@@ -67,6 +71,8 @@ def parse():
     p.add_argument("--cpu-sample-log2", type=int, default=24)
     p.add_argument("--no-ttb", action="store_true", help="skip the time-to-bound runs")
     p.add_argument("--train-steps", type=int, default=1000)
+    p.add_argument("--no-means", action="store_true",
+                   help="with --profile-sweeps: the entry-reading sweep (no branch-mean buffers)")
     p.add_argument("--profile-sweeps", type=int, default=0,
                    help="only run this many FP32 sweeps from zero (for counter collection)")
     p.add_argument("--configs", action="store_true",
@@ -245,11 +251,16 @@ def polish(P, S, best, target, certificate="feasible"):
     return P.status()[0] - start, certs, best
 
 
+def uses_means(iteration, sigma, d):
+    """Branch-mean buffers serve the sigma = d = 2 ring."""
+    return iteration == "ring" and sigma == 2 and d == 2
+
+
 def plain_run(pk, h, target, iteration="ring", certificate="feasible", sigma=2, d=2):
     """FP64 from zero, a certificate every TTB_CADENCE sweeps, until the best
     bound reaches target (one lcsb_run, timed from the init call)."""
     import torch
-    P = pk.Lcsb(sigma, d, h, "f64", iteration=iteration)
+    P = pk.Lcsb(sigma, d, h, "f64", iteration=iteration, means=uses_means(iteration, sigma, d))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P.init_zero()
@@ -269,9 +280,10 @@ def mixed_run(pk, h, target, iteration="ring", certificate="feasible", sigma=2, 
     """FP32 from zero to its error floor, then the FP64 polish to target, the
     FP32 tables inside the FP64 buffers (widened in place)."""
     import torch
-    P = pk.Lcsb(sigma, d, h, "f64", iteration=iteration)
+    means = uses_means(iteration, sigma, d)
+    P = pk.Lcsb(sigma, d, h, "f64", iteration=iteration, means=means)
     M = pk.Lcsb(sigma, d, h, "f32", iteration=iteration,
-                bufs=[b.view(torch.float32) for b in P.bufs])
+                bufs=[b.view(torch.float32) for b in P.bufs], means=means)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     M.init_zero()
@@ -299,12 +311,19 @@ def algorithmic_bytes(L, elem):
     return 3 * elem * L.stored
 
 
+def sweep_kernel(L, ctype):
+    """Name of the sigma = d = 2 sweep kernel a ring runs."""
+    if L.swap_symmetric() and L.means:
+        return f"sweep_s2d2_means<{ctype}, false>"
+    return f"sweep_s2d2<{ctype}, {'true' if L.swap_symmetric() else 'false'}, false>"
+
+
 def fp64_sweep(pk, h, sweeps=32):
     """The plain FP64 sweep (bit-identical to the oracle) at sigma = d = 2,
     l = h from zero: average launch time from HIP events on the library's
     stream, against the HBM peak (12 algorithmic bytes per stored entry)."""
     import torch
-    L = pk.Lcsb(2, 2, h, "f64")
+    L = pk.Lcsb(2, 2, h, "f64", means=True)
     L.init_zero()
     L.iterate(8)
     stream = torch.cuda.current_stream()
@@ -316,7 +335,7 @@ def fp64_sweep(pk, h, sweeps=32):
     ms = e0.elapsed_time(e1) / sweeps
     n = 4 ** h
     algo = algorithmic_bytes(L, 8)
-    folded = L.swap_symmetric()
+    kernel = sweep_kernel(L, "double")
     gbs = algo / ms / 1e6
     del L
     torch.cuda.empty_cache()
@@ -324,7 +343,7 @@ def fp64_sweep(pk, h, sweeps=32):
            "bound": "hbm",
            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(ms, 4),
-           "kernel": f"sweep_s2d2<double, {'true' if folded else 'false'}, false>",
+           "kernel": kernel, "sweeps_per_launch_group": sweeps,
            "algorithmic_bytes_per_launch": algo,
            "updates_per_s": n / ms * 1e3, "traffic": None}
     traffic = measured_traffic(PMC_SUMMARY_F64_H14) if h == 14 else None
@@ -372,7 +391,7 @@ def time_to_bound(pk, h, train_steps=1000):
     """
     import torch
     out = {}
-    P = pk.Lcsb(2, 2, h, "f64")
+    P = pk.Lcsb(2, 2, h, "f64", means=True)
     P.init_zero()
     alg64 = algorithmic_bytes(P, 8)      # every ring here is exchange-symmetric
     alg32 = alg64 // 2
@@ -388,7 +407,7 @@ def time_to_bound(pk, h, train_steps=1000):
     converged_after = cur["sweep"]
     log(f"converged plain FP64 bound B = {B:.12f} after {converged_after} sweeps ({why})")
 
-    M = pk.Lcsb(2, 2, h, "f32")
+    M = pk.Lcsb(2, 2, h, "f32", means=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     M.init_zero()
@@ -497,7 +516,7 @@ def learned_run(pk, h, P, target, train_steps):
     without and with data generation and training."""
     import torch
     M, rate, t_data, t_train, loss = train_network(pk, h, train_steps)
-    S = pk.Lcsb(2, 2, h, "f32")
+    S = pk.Lcsb(2, 2, h, "f32", means=True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     S.init_seed_mlp(M, rate)
@@ -667,10 +686,12 @@ def config_table(pk, configs=None, emit=True):
     return rows
 
 
-def profile_only(pk, h, sweeps, sigma=2, d=2, dtype="f32"):
-    """Only `sweeps` sweeps from zero at (sigma, d, l = h), for counters."""
+def profile_only(pk, h, sweeps, sigma=2, d=2, dtype="f32", means=True):
+    """Only `sweeps` sweeps from zero at (sigma, d, l = h), for counters, as one
+    lcsb_iterate call (the sigma = d = 2 ring with its branch-mean buffers
+    unless means is False)."""
     import torch
-    L = pk.Lcsb(sigma, d, h, dtype)
+    L = pk.Lcsb(sigma, d, h, dtype, means=means and uses_means("ring", sigma, d))
     L.init_zero()
     L.iterate(sweeps)
     torch.cuda.synchronize()
@@ -912,7 +933,8 @@ def main():
 
     torch.cuda.set_device(0)
     if args.profile_sweeps:
-        return profile_only(pk, args.h, args.profile_sweeps, args.sigma, args.d, args.dtype)
+        return profile_only(pk, args.h, args.profile_sweeps, args.sigma, args.d, args.dtype,
+                            not args.no_means)
     if args.copy_gib:
         return copy_only(args.copy_gib)
     if args.profile_seed:
@@ -934,7 +956,7 @@ def main():
         return config_table(pk)
     h, cad = args.h, args.cadence
     n = 4 ** h
-    L = pk.Lcsb(2, 2, h, "f32")
+    L = pk.Lcsb(2, 2, h, "f32", means=True)
     stream = torch.cuda.current_stream()
     L.init_zero()
     log(f"warmup: {args.warmup} steps of {cad} sweeps + 1 certificate at l={h}")
@@ -960,13 +982,14 @@ def main():
     avg_sweep_s = statistics.mean(sweep_ms) * 1e-3
     algo_bytes = algorithmic_bytes(L, 4)
     folded = L.swap_symmetric()
+    kernel = sweep_kernel(L, "float")
     achieved = algo_bytes / avg_sweep_s / 1e9
     computed = n // 4 + 2 ** (h - 1) if folded else n // 2
     traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": f"sweep_s2d2<float, {'true' if folded else 'false'}, false>",
+                "kernel": kernel,
                 "algorithmic_bytes_per_launch": algo_bytes,
                 "avg_launch_ms": round(avg_sweep_s * 1e3, 4)}
     if traffic is not None:  # rocprofv3-measured HBM bytes per launch, at this launch time
@@ -992,7 +1015,8 @@ def main():
         "dtype": "f32 sweeps, f64 certificate", "data": "synthetic (zero-start iteration)",
         "config": {"workload": f"sigma=2 d=2 l={h}: {n} table indices ({n // 2} stored, "
                                f"complement-folded; exchange-symmetric ring, one tuple of "
-                               f"each exchanged pair computed and stored), FP32 renormalised sweeps, "
+                               f"each exchanged pair computed and stored; branches read from the "
+                               f"lags' branch-mean tables), FP32 renormalised sweeps, "
                                f"FP64 round-down largest-r certificate (one pass) every {cad} sweeps",
                    "sweeps_per_step": cad, "entries": n, "stored_entries": n // 2},
         "roofline": roofline,

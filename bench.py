@@ -252,8 +252,8 @@ def polish(P, S, best, target, certificate="feasible"):
 
 
 def uses_means(iteration, sigma, d):
-    """Branch-mean buffers serve the sigma = d = 2 ring."""
-    return iteration == "ring" and sigma == 2 and d == 2
+    """Branch-mean buffers serve the sigma = d = 2 ring and two-array pair."""
+    return iteration in ("ring", "two_array") and sigma == 2 and d == 2
 
 
 def plain_run(pk, h, target, iteration="ring", certificate="feasible", sigma=2, d=2):

@@ -55,11 +55,13 @@ struct lcsb_ctx {
     int lags;        // tables the context keeps: d for the ring, 2 for the two-array iteration
     int packed;      // LCSB_ITER_TWO_ARRAY_PACKED: one entry per exchange orbit (packed_index)
     uint64_t entries;  // entries per table: g.ns, or packed_entries(h)
-    // branch-mean tables (lcsb_bind_means): per slot Ma, then Mab at mab_off
+    // branch-mean tables (lcsb_bind_means): per slot Ma, then Mab at mab_off,
+    // then the table's values at the two-array rate's sample at smp_off
     void *means_buf[4];
-    uint64_t mab_off;
+    uint64_t mab_off, smp_off;
     int means_ok[4];    // the slot's means are those of its table
     int entries_ok[4];  // the slot's entries hold its table (a branch-mean sweep may skip them)
+    int samples_ok[4];  // the slot's sample values are its table's
 };
 
 namespace {
@@ -98,26 +100,34 @@ void clear_lazy(lcsb_ctx *c)
         c->lazy[k] = 0;
         c->means_ok[k] = 0;
         c->entries_ok[k] = 1;
+        c->samples_ok[k] = 0;
     }
 }
 
-// sigma = d = 2 rings of l >= 3 symmetric in the two strings sweep from the
-// branch-mean tables once they are bound
+// sigma = d = 2 rings and two-array pairs (folded, not packed) of l >= 3
+// symmetric in the two strings sweep from the branch-mean tables once they
+// are bound
 bool means_path(const lcsb_ctx *c)
 {
-    return c->means_buf[0] && !c->two_array && c->swap_sym && c->g.sigma == 2 && c->g.d == 2 &&
+    return c->means_buf[0] && !c->packed && c->swap_sym && c->g.sigma == 2 && c->g.d == 2 &&
            c->g.h >= 3;
 }
 
-uint64_t means_mab_offset(const lcsb_ctx *c)
+uint64_t round256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
+uint64_t means_mab_offset(const lcsb_ctx *c) { return round256((c->g.ns / 2) * elem_size(c->dtype)); }
+uint64_t means_smp_offset(const lcsb_ctx *c)
 {
-    return ((c->g.ns / 2) * elem_size(c->dtype) + 255) & ~(uint64_t)255;
+    return round256(means_mab_offset(c) + (c->g.ns / 4) * elem_size(c->dtype));
 }
 
 void *slot_ma(const lcsb_ctx *c, int slot) { return c->means_buf[slot]; }
 void *slot_mab(const lcsb_ctx *c, int slot)
 {
     return static_cast<unsigned char *>(c->means_buf[slot]) + c->mab_off;
+}
+void *slot_smp(const lcsb_ctx *c, int slot)
+{
+    return static_cast<unsigned char *>(c->means_buf[slot]) + c->smp_off;
 }
 
 // Complete the exchanged entries of a lazily written slot (stream order).
@@ -257,10 +267,9 @@ int lcsb_bind(lcsb_ctx *c, void *const *bufs, int nbuf, void *ws, void *stream)
 int lcsb_query_means(const lcsb_ctx *c, uint64_t *bytes_per_buf)
 {
     if (!c) return fail(LCSB_EINVAL, "null context");
-    if (c->two_array || c->g.sigma != 2 || c->g.d != 2 || c->g.h < 3)
-        return fail(LCSB_EUNSUPPORTED, "branch-mean tables serve the sigma = d = 2 ring at l >= 3");
-    if (bytes_per_buf)
-        *bytes_per_buf = means_mab_offset(c) + (c->g.ns / 4) * elem_size(c->dtype);
+    if (c->packed || c->g.sigma != 2 || c->g.d != 2 || c->g.h < 3)
+        return fail(LCSB_EUNSUPPORTED, "branch-mean tables serve sigma = d = 2 folded tables at l >= 3");
+    if (bytes_per_buf) *bytes_per_buf = means_smp_offset(c) + kRateSample * elem_size(c->dtype);
     return LCSB_OK;
 }
 
@@ -274,7 +283,7 @@ int lcsb_bind_means(lcsb_ctx *c, void *const *bufs, int nbuf)
     if (!bufs && nbuf == 0) {  // unbind: sweep from the entries again
         for (int k = 0; k < 4; ++k) {
             c->means_buf[k] = nullptr;
-            c->means_ok[k] = 0;
+            c->means_ok[k] = c->samples_ok[k] = 0;
         }
         return LCSB_OK;
     }
@@ -289,9 +298,10 @@ int lcsb_bind_means(lcsb_ctx *c, void *const *bufs, int nbuf)
     }
     for (int k = 0; k < nbuf; ++k) {
         c->means_buf[k] = bufs[k];
-        c->means_ok[k] = 0;
+        c->means_ok[k] = c->samples_ok[k] = 0;
     }
     c->mab_off = means_mab_offset(c);
+    c->smp_off = means_smp_offset(c);
     return LCSB_OK;
 }
 
@@ -362,8 +372,9 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
     if (rc) return rc;
     if (k < 0) return fail(LCSB_EINVAL, "negative sweep count");
     if (means_path(c) && k > 0) {
-        // the means of lags 1 .. d, derived from their entries where stale
-        for (int j = 1; j <= c->g.d; ++j) {
+        // the means of the lags the sweep reads (lags 1 .. d of the ring; u,
+        // lag 1, of the two-array iteration), derived from their entries where stale
+        for (int j = 1; j <= (c->two_array ? 1 : c->g.d); ++j) {
             const int slot = slot_of_lag(c, j);
             if (c->means_ok[slot]) continue;
             if (!c->entries_ok[slot]) return fail(LCSB_ESTATE, "lag %d has neither entries nor means", j);
@@ -374,11 +385,15 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
         }
         for (int64_t t = 0; t < k; ++t) {
             MeansLaunch a;
-            a.s1 = slot_of_lag(c, 1);
-            a.s2 = slot_of_lag(c, 2);
+            const int r1 = slot_of_lag(c, 1), r2 = c->two_array ? r1 : slot_of_lag(c, 2);
+            a.ma1 = slot_ma(c, r1);
+            a.mab2 = slot_mab(c, r2);
+            // offsets: the ring's lags are read relative to lag 1; the
+            // two-array lag 2 is u - R (slot kSlotLag2, set by the rate pass)
+            a.s1 = c->two_array && c->dtype != LCSB_F32 ? Ws::kSlotZero : r1;
+            a.s2 = c->two_array ? Ws::kSlotLag2 : r2;
+            a.shift = c->two_array;
             a.snew = (c->head + 1) % c->nbuf;
-            a.ma1 = slot_ma(c, a.s1);
-            a.mab2 = slot_mab(c, a.s2);
             // the entries of the last d tables: what a certificate or a caller reads
             const bool entries = t >= k - c->g.d;
             a.out = entries ? c->buf[a.snew] : nullptr;
@@ -387,6 +402,20 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
             a.offsets = reinterpret_cast<double *>(c->ws + Ws::kOffsets);
             hipError_t e = launch_sweep_means(c->g, c->dtype, a, c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+            if (c->two_array) {
+                // the rate of the next step from the new table's sample values
+                // (computed as the sweep computed them) and the old table's
+                if ((e = launch_means_samples(c->g, c->dtype, a, slot_smp(c, a.snew), c->stream)) !=
+                    hipSuccess)
+                    return hip_fail(c, e, "sample values");
+                if (!c->samples_ok[r1] && !c->entries_ok[r1])
+                    return fail(LCSB_ESTATE, "the old table has neither entries nor sample values");
+                e = launch_two_array_rate(c->g, c->dtype, c->buf[a.snew], c->buf[r1], a.snew, r1,
+                                          c->swap_sym, 0, c->ws, c->stream, slot_smp(c, a.snew),
+                                          c->samples_ok[r1] ? slot_smp(c, r1) : nullptr);
+                if (e != hipSuccess) return hip_fail(c, e, "rate");
+                c->samples_ok[a.snew] = 1;
+            }
             c->lazy[a.snew] = 1;
             c->means_ok[a.snew] = 1;
             c->entries_ok[a.snew] = entries;
@@ -423,6 +452,7 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
         c->lazy[a.new_slot] = c->swap_sym && !c->packed;
         c->means_ok[a.new_slot] = 0;
         c->entries_ok[a.new_slot] = 1;
+        c->samples_ok[a.new_slot] = 0;
         c->head = a.new_slot;
         c->sweeps++;
         if ((rc = refresh_rate(c))) return rc;
@@ -544,9 +574,9 @@ int lcsb_lag(lcsb_ctx *c, int k, void **dev_ptr, double *offset)
 {
     int rc = lag_pointer(c, k, dev_ptr, offset);
     if (rc) return rc;
-    // the caller may write through the pointer: no branch-mean table is
-    // trusted until it is derived again from the entries
-    for (int j = 0; j < 4; ++j) c->means_ok[j] = 0;
+    // the caller may write through the pointer: no branch-mean table or
+    // sample value is trusted until it is derived again from the entries
+    for (int j = 0; j < 4; ++j) c->means_ok[j] = c->samples_ok[j] = 0;
     return LCSB_OK;
 }
 
@@ -724,6 +754,7 @@ int lcsb_upcast(const lcsb_ctx *src, lcsb_ctx *dst)
         dst->lazy[k] = src->lazy[k];  // same slots, converted as stored
         dst->means_ok[k] = 0;
         dst->entries_ok[k] = 1;
+        dst->samples_ok[k] = 0;
     }
     if ((rc = refresh_rate(dst))) return rc;
     dst->state = kReady;

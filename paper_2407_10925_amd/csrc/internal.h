@@ -95,11 +95,18 @@ struct MeansLaunch {
     void *out;         // the new table's entries, or null: not written this sweep
     void *ma_new, *mab_new;
     double *offsets;   // device, per slot (FP32)
-    int s1, s2, snew;  // slots of lag 1, lag 2 and the new table
+    int s1, s2, snew;  // offset slots of lag 1, lag 2 and the new table
+    int shift;         // FP64: lag 2 read with delta = offsets[s2] - offsets[s1] (two arrays)
 };
 // Entries of lag 1 and lag 2 are not read.  FP32 tables (and their means)
 // are relative to their slot's offset, as in launch_sweep.
 hipError_t launch_sweep_means(const Geometry &g, int dtype, const MeansLaunch &a, hipStream_t s);
+// The values the sweep of `a` writes at the 4096 coordinates the two-array
+// rate samples (the lower index of each sampled coordinate's exchanged
+// pair), in sample order, computed from the same means with the same
+// arithmetic; launched after that sweep, before the rate pass
+hipError_t launch_means_samples(const Geometry &g, int dtype, const MeansLaunch &a, void *samples,
+                                hipStream_t s);
 // Ma and Mab of a stored table (lazy: only the lower index of each exchanged
 // pair holds a value, see TwinGroup)
 hipError_t launch_derive_means(const Geometry &g, int dtype, const void *table, int lazy,
@@ -133,9 +140,14 @@ int certify_optimal_noalloc(int sigma, int d, int h, int dtype, const void *u,
 // The two-array iteration: R = mean over the fixed sample of nw - old, and the
 // offsets slots kSlotLag2/3 for the next sweep (csrc/two_array.hip)
 // packed: the two tables are exchange-packed (sigma = d = 2)
+// nw_smp / old_smp (optional): the tables' values at the sample, in sample
+// order (launch_means_samples), read instead of the tables
 hipError_t launch_two_array_rate(const Geometry &g, int dtype, const void *nw, const void *old,
                                  int s_new, int s_old, int swap_sym, int packed,
-                                 unsigned char *ws, hipStream_t s);
+                                 unsigned char *ws, hipStream_t s, const void *nw_smp = nullptr,
+                                 const void *old_smp = nullptr);
+constexpr int kRateSample = 4096;  // coordinates of the two-array rate
+constexpr uint64_t kRateSampleMul = 0x9E3779B97F4A7C15ull;
 
 // Utilities
 hipError_t launch_fill_zero(void *p, uint64_t bytes, hipStream_t s);

@@ -446,6 +446,47 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d2_means(const T *__restrict__
     }
 }
 
+// The new table's values at the two-array rate's sample coordinates (each
+// at the lower index of its exchanged pair, where the sweep stores it), in
+// sample order: what sweep_s2d2_means computes there, from the same means
+// with the same operations (the sweep writes these entries only on the last
+// sweeps of a call; the rate pass reads them from here instead).
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(kBlock) void means_samples(const T *__restrict__ ma1,
+                                                       const T *__restrict__ mab2,
+                                                       T *__restrict__ smp, uint64_t n,
+                                                       const double *__restrict__ off, int s1,
+                                                       int s2)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kShift = kF32 || SHIFT;
+    T d2 = 0, y0 = 0;
+    if constexpr (!kF32 && SHIFT) d2 = off[s2] - off[s1];
+    if constexpr (kF32) {
+        d2 = (float)(off[s2] - off[s1]);
+        y0 = 1.0f + first(mab2[0] + d2);
+    }
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (uint64_t)kRateSample) return;
+    const uint64_t nq = n >> 2;
+    uint64_t c = (i * kRateSampleMul) & ((n >> 1) - 1);
+    const uint64_t tw = exchange_twin(c, n, 2);
+    c = tw < c ? tw : c;
+    T v;
+    if (!(c & nq)) {  // 0/0|x: the all-advance mean of x's group, at its kept prefix
+        const uint64_t P = mab_index(4 * c, n);
+        const uint64_t pt = mab_index(exchange_twin(4 * P, n, 2), n);
+        T m2 = mab2[pt < P ? pt : P];
+        if constexpr (kShift) m2 = m2 + d2;
+        v = (T)1 + first(m2);
+    } else {          // 0/1|x: advance b, then advance a
+        const uint64_t am = kAlt2 & (n - 1), bm = ~kAlt2 & (n - 1);
+        const uint64_t sa = ((c << 2) & am) | (c & bm), sb = (c & am) | ((c << 2) & bm);
+        v = vmax(first(ma1[ma_index(exchange_twin(sb, n, 2), n)]), ma1[ma_index(sa, n)]);
+    }
+    smp[i] = kF32 ? (T)(v - y0) : v;
+}
+
 // Ma and Mab of a stored table, one thread per group prefix P < n/8
 template <typename T>
 __global__ __launch_bounds__(kBlock) void derive_means(const T *__restrict__ tab, int lazy,
@@ -1066,20 +1107,40 @@ hipError_t launch_typed(const Geometry &g, const SweepLaunch &a, hipStream_t s)
 
 }  // namespace
 
-template <typename T>
-hipError_t means_typed(const Geometry &g, const MeansLaunch &a, hipStream_t s)
+template <typename T, bool SHIFT>
+hipError_t means_typed(const Geometry &g, const MeansLaunch &a, void *samples, hipStream_t s)
 {
-    sweep_s2d2_means<T, false><<<sweep_grid(g.n >> 5), dim3(kBlock), 0, s>>>(
-        static_cast<const T *>(a.ma1), static_cast<const T *>(a.mab2), static_cast<T *>(a.out),
-        static_cast<T *>(a.ma_new), static_cast<T *>(a.mab_new), g.n, a.offsets, a.s1, a.s2,
-        a.snew);
+    if (samples)
+        means_samples<T, SHIFT><<<kRateSample / kBlock, dim3(kBlock), 0, s>>>(
+            static_cast<const T *>(a.ma1), static_cast<const T *>(a.mab2),
+            static_cast<T *>(samples), g.n, a.offsets, a.s1, a.s2);
+    else
+        sweep_s2d2_means<T, SHIFT><<<sweep_grid(g.n >> 5), dim3(kBlock), 0, s>>>(
+            static_cast<const T *>(a.ma1), static_cast<const T *>(a.mab2),
+            static_cast<T *>(a.out), static_cast<T *>(a.ma_new), static_cast<T *>(a.mab_new), g.n,
+            a.offsets, a.s1, a.s2, a.snew);
     return hipGetLastError();
+}
+
+hipError_t means_dispatch(const Geometry &g, int dtype, const MeansLaunch &a, void *samples,
+                          hipStream_t s)
+{
+    if (g.sigma != 2 || g.d != 2 || g.h < 3) return hipErrorInvalidValue;
+    if (dtype == LCSB_F32) return means_typed<float, false>(g, a, samples, s);
+    return a.shift ? means_typed<double, true>(g, a, samples, s)
+                   : means_typed<double, false>(g, a, samples, s);
 }
 
 hipError_t launch_sweep_means(const Geometry &g, int dtype, const MeansLaunch &a, hipStream_t s)
 {
-    if (g.sigma != 2 || g.d != 2 || g.h < 3) return hipErrorInvalidValue;
-    return dtype == LCSB_F32 ? means_typed<float>(g, a, s) : means_typed<double>(g, a, s);
+    return means_dispatch(g, dtype, a, nullptr, s);
+}
+
+hipError_t launch_means_samples(const Geometry &g, int dtype, const MeansLaunch &a, void *samples,
+                                hipStream_t s)
+{
+    if (!samples) return hipErrorInvalidValue;
+    return means_dispatch(g, dtype, a, samples, s);
 }
 
 hipError_t launch_derive_means(const Geometry &g, int dtype, const void *table, int lazy,

@@ -16,8 +16,8 @@
 namespace lcsb {
 namespace {
 
-constexpr int kSample = 4096;
-constexpr uint64_t kSampleMul = 0x9E3779B97F4A7C15ull;
+constexpr int kSample = kRateSample;
+constexpr uint64_t kSampleMul = kRateSampleMul;
 static_assert(kSample == 16 * kBlock, "sixteen leaves per thread");
 
 // swap (0, 2, 3: sigma = 2 with d = swap; 4: sigma = 4, d = 2): a lazily
@@ -29,7 +29,9 @@ __global__ __launch_bounds__(kBlock) void rate_kernel(const T *__restrict__ nw,
                                                      const T *__restrict__ old, uint64_t n,
                                                      uint64_t ns, int swap, int packed_h,
                                                      double *__restrict__ off, int s_new,
-                                                     int s_old, double *__restrict__ rate)
+                                                     int s_old, double *__restrict__ rate,
+                                                     const T *__restrict__ nw_smp,
+                                                     const T *__restrict__ old_smp)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
     double v[16];
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(kBlock) void rate_kernel(const T *__restrict__ nw,
             const uint64_t tw = swap == 4 ? exchange_twin4(c, n) : exchange_twin(c, n, swap);
             c = tw < c ? tw : c;
         }
-        v[j] = (double)nw[c] - (double)old[c];
+        v[j] = (double)(nw_smp ? nw_smp[i] : nw[c]) - (double)(old_smp ? old_smp[i] : old[c]);
     }
 #pragma unroll
     for (int step = 1; step < 16; step <<= 1)
@@ -82,7 +84,8 @@ __global__ __launch_bounds__(kBlock) void rate_kernel(const T *__restrict__ nw,
 
 hipError_t launch_two_array_rate(const Geometry &g, int dtype, const void *nw, const void *old,
                                  int s_new, int s_old, int swap_sym, int packed,
-                                 unsigned char *ws, hipStream_t s)
+                                 unsigned char *ws, hipStream_t s, const void *nw_smp,
+                                 const void *old_smp)
 {
     const int packed_h = packed ? g.h : 0;
     int swap = 0;
@@ -92,11 +95,15 @@ hipError_t launch_two_array_rate(const Geometry &g, int dtype, const void *nw, c
     if (dtype == LCSB_F32)
         rate_kernel<float><<<1, kBlock, 0, s>>>(static_cast<const float *>(nw),
                                                 static_cast<const float *>(old), g.n, g.ns, swap,
-                                                packed_h, off, s_new, s_old, rate);
+                                                packed_h, off, s_new, s_old, rate,
+                                                static_cast<const float *>(nw_smp),
+                                                static_cast<const float *>(old_smp));
     else
         rate_kernel<double><<<1, kBlock, 0, s>>>(static_cast<const double *>(nw),
                                                  static_cast<const double *>(old), g.n, g.ns, swap,
-                                                 packed_h, off, s_new, s_old, rate);
+                                                 packed_h, off, s_new, s_old, rate,
+                                                 static_cast<const double *>(nw_smp),
+                                                 static_cast<const double *>(old_smp));
     return hipGetLastError();
 }
 

@@ -98,13 +98,14 @@ def test_call_order_is_enforced_without_a_gpu(lib):
 
 
 def test_branch_mean_buffers_are_checked_without_a_gpu(lib):
-    """lcsb_query_means / lcsb_bind_means: sizes for the sigma = d = 2 ring
-    (Ma, n/4 entries, then Mab, n/8, at a 256-byte boundary), refusals for
-    other shapes, iterations and l < 3, and pointer checks before anything is
-    stored (no buffer is dereferenced)."""
+    """lcsb_query_means / lcsb_bind_means: sizes for sigma = d = 2 folded
+    tables (Ma, n/4 entries, then Mab, n/8, then the 4096 sample values of the
+    two-array rate, each at a 256-byte boundary), refusals for other shapes,
+    packed tables and l < 3, and pointer checks before anything is stored (no
+    buffer is dereferenced)."""
     from paper_2407_10925_amd import _capi
     mb = C.c_uint64()
-    for (sigma, d, h, it) in ((2, 3, 5, 0), (4, 2, 4, 0), (2, 2, 2, 0), (2, 2, 5, 1), (2, 2, 5, 2)):
+    for (sigma, d, h, it) in ((2, 3, 5, 0), (4, 2, 4, 0), (2, 2, 2, 0), (2, 2, 5, 2)):
         ctx = C.c_void_p()
         assert lib.lcsb_create_iter(sigma, d, h, 0, it, C.byref(ctx)) == 0
         assert lib.lcsb_query_means(ctx, C.byref(mb)) == _capi.LCSB_EUNSUPPORTED, (sigma, d, h, it)
@@ -114,8 +115,10 @@ def test_branch_mean_buffers_are_checked_without_a_gpu(lib):
         assert lib.lcsb_create(2, 2, 5, dtype, C.byref(ctx)) == 0
         n = 4 ** 5
         assert lib.lcsb_query_means(ctx, C.byref(mb)) == 0
-        ma = (n // 4) * elem
-        assert mb.value == (ma + 255) // 256 * 256 + (n // 8) * elem
+
+        def up(b):
+            return (b + 255) // 256 * 256
+        assert mb.value == up(up((n // 4) * elem) + (n // 8) * elem) + 4096 * elem
         means = (C.c_void_p * 3)(4096, 8192, 12288)
         assert lib.lcsb_bind_means(ctx, means, 3) == _capi.LCSB_ESTATE  # before lcsb_bind
         bufs = (C.c_void_p * 3)(256, 512, 768)
@@ -128,6 +131,10 @@ def test_branch_mean_buffers_are_checked_without_a_gpu(lib):
         assert lib.lcsb_bind_means(ctx, means, 3) == 0
         assert lib.lcsb_bind_means(ctx, None, 0) == 0  # unbind
         assert lib.lcsb_destroy(ctx) == 0
+    ctx = C.c_void_p()  # the two-array pair takes them too
+    assert lib.lcsb_create_iter(2, 2, 5, 0, 1, C.byref(ctx)) == 0
+    assert lib.lcsb_query_means(ctx, C.byref(mb)) == 0
+    assert lib.lcsb_destroy(ctx) == 0
 
 
 def test_python_binding_refuses_without_gpu():

@@ -1,5 +1,5 @@
-"""Branch-mean sweeps (lcsb_bind_means; the sigma = d = 2 ring) against the
-entry-reading sweep and the oracle.  A ring with mean buffers bound reads one
+"""Branch-mean sweeps (lcsb_bind_means; the sigma = d = 2 ring and two-array
+pair) against the entry-reading sweep and the oracle.  A ring with mean buffers bound reads one
 mean per branch (Ma, Mab) instead of the entries, writes the entries only on
 the last d sweeps of each lcsb_iterate call, and re-derives the means after
 anything else writes the tables.  Every table a caller sees, the offsets and
@@ -34,9 +34,9 @@ def pk():
     return pk
 
 
-def _pair(pk, h, dtype):
-    T = pk.Lcsb(2, 2, h, dtype)
-    M = pk.Lcsb(2, 2, h, dtype, means=True)
+def _pair(pk, h, dtype, iteration="ring"):
+    T = pk.Lcsb(2, 2, h, dtype, iteration=iteration)
+    M = pk.Lcsb(2, 2, h, dtype, iteration=iteration, means=True)
     T.init_zero()
     M.init_zero()
     assert T.swap_symmetric() and M.swap_symmetric()
@@ -178,6 +178,102 @@ def test_means_full_size_matches_the_entry_ring(pk, h, dtype, first, rest):
     for chunk in (first, rest):
         T.iterate(chunk)
         M.iterate(chunk)
+    _same_certs(T, M, "full size")
+    for k in (1, 2):
+        a, ao = T.lag(k)
+        b, bo = M.lag(k)
+        assert ao == bo
+        assert torch.equal(a, b), k
+    del T, M
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ two arrays
+# The two-array rate samples 4096 entries of the new table after every sweep;
+# with means bound those values are recomputed from the same means
+# (launch_means_samples) and the rate read from them.
+
+@pytest.mark.parametrize("h", [3, 6])
+def test_two_array_means_matches_the_oracle(pk, h):
+    say(f"two-array means vs oracle: h={h}")
+    _, hist, (u, u_prev, R) = oracle.two_array_run(2, 2, h, 30, cadence=30, certificate="optimal")
+    M = pk.Lcsb(2, 2, h, "f64", iteration="two_array", means=True)
+    M.init_zero()
+    for chunk in (1, 4, 25):
+        M.iterate(chunk)
+    N = 4 ** h
+    assert np.array_equal(M.read_table(1), u[: N // 2])
+    assert np.array_equal(M.read_table(2), u_prev[: N // 2])
+    assert M.rate() == R
+    cp, _ = M.certify_optimal()
+    c = hist[-1]["cert"]
+    assert (cp["R"], cp["bound"], cp["argmax_W"], cp["nonfinite"]) == \
+        (c["r"], c["bound"], c["argmin"], c["nonfinite"])
+
+
+@pytest.mark.parametrize("h", [3, 5, 8, 10])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_two_array_means_matches_the_entry_pair(pk, h, dtype):
+    say(f"two-array means vs entries: h={h} {dtype}")
+    T, M = _pair(pk, h, dtype, "two_array")
+    done = 0
+    for chunk in (1, 2, 7, 40, 64, 0, 1):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        done += chunk
+        assert T.rate() == M.rate(), done
+        _same_tables_host(T, M, f"after {done}")
+        _same_certs(T, M, f"after {done}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_two_array_means_run_and_writes_through_lag(pk, dtype):
+    """lcsb_run (largest-r certificate every 8 sweeps) stops alike; a write
+    through lcsb_lag (both members of an exchanged pair) re-derives the means
+    and makes the next rate read the old table's entries again."""
+    h = 9
+    say(f"two-array means: run, writes through lcsb_lag: {dtype}")
+    res = []
+    for means in (False, True):
+        L = pk.Lcsb(2, 2, h, dtype, iteration="two_array", means=means)
+        L.init_zero()
+        cur, best, certs, why = L.run(8, max_sweeps=200, stop_delta=1e-9, certificate="optimal")
+        res.append((cur["sweep"], best["bound"], best["argmax_W"], certs, why, L.rate()))
+        del L
+    assert res[0] == res[1]
+    T, M = _pair(pk, h, dtype, "two_array")
+    T.iterate(5)
+    M.iterate(5)
+    n = 4 ** h
+    am = int("10" * h, 2)
+    i = 0x1b3c1  # a stored index (below n/2 = 131072)
+    e = ((i & am) >> 1) | ((i & (am >> 1)) << 1)
+    if e >= n // 2:
+        e ^= n - 1
+    for L in (T, M):
+        t, _ = L.lag(1)
+        t[i] = t[i] + 0.625
+        if e != i:
+            t[e] = t[e] + 0.625
+    torch.cuda.synchronize()
+    for chunk in (1, 6):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        assert T.rate() == M.rate()
+        _same_tables_host(T, M, f"planted, +{chunk}")
+        _same_certs(T, M, f"planted, +{chunk}")
+
+
+def test_two_array_means_full_size(pk):
+    """l = 16 FP32: whole tables on the device, the rate and both
+    certificates after sweeps that cross an lcsb_iterate call."""
+    say("two-array means full size: h=16 f32 3+13 sweeps")
+    torch.cuda.empty_cache()
+    T, M = _pair(pk, 16, "f32", "two_array")
+    for chunk in (3, 13):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        assert T.rate() == M.rate()
     _same_certs(T, M, "full size")
     for k in (1, 2):
         a, ao = T.lag(k)

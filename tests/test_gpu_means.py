@@ -15,6 +15,7 @@ import pytest
 import torch
 
 import oracle
+import seeded_inputs as si
 
 pytestmark = pytest.mark.gpu
 
@@ -186,6 +187,39 @@ def test_means_full_size_matches_the_entry_ring(pk, h, dtype, first, rest):
         assert torch.equal(a, b), k
     del T, M
     torch.cuda.empty_cache()
+
+
+def test_means_l17_fp32_matches_the_entry_ring_sampled(pk):
+    """l = 17 FP32 (2^34 indices, stored entries and mean indices past 2^32):
+    the mean ring and the entry ring, run one after the other (both do not fit
+    together), agree on 2^20 sampled entries of lags 1 and 2, their offsets and
+    both certificates after 6 sweeps (3 + 3, crossing an lcsb_iterate call)."""
+    h = 17
+    say("means vs entries at l=17 FP32, sampled")
+    torch.cuda.empty_cache()
+    got = []
+    for means in (True, False):
+        L = pk.Lcsb(2, 2, h, "f32", means=means)
+        L.init_zero()
+        L.iterate(3)
+        L.iterate(3)
+        cf, _ = L.certify()
+        co, _ = L.certify_optimal()
+        idx = si.sample_indices(L.stored, 1 << 20, seed=17).to(L.device)
+        lags = []
+        for k in (1, 2):
+            t, off = L.lag(k)
+            lags.append((t[idx].cpu().numpy(), off))
+        got.append((lags, cf, co))
+        del L, t
+        torch.cuda.empty_cache()
+    (lm, cfm, com), (le, cfe, coe) = got
+    for (a, ao), (b, bo) in zip(lm, le):
+        assert ao == bo
+        assert np.array_equal(a, b)
+    for x, y in ((cfm, cfe), (com, coe)):
+        for f in CERT_FIELDS:
+            assert x[f] == y[f], (f, x[f], y[f])
 
 
 # ------------------------------------------------------------------ two arrays

@@ -252,8 +252,11 @@ def polish(P, S, best, target, certificate="feasible"):
 
 
 def uses_means(iteration, sigma, d):
-    """Branch-mean buffers serve the sigma = d = 2 ring and two-array pair."""
-    return iteration in ("ring", "two_array") and sigma == 2 and d == 2
+    """Branch-mean buffers serve the sigma = d = 2 ring and two-array pair and
+    the sigma = 2, d = 3 ring."""
+    if sigma != 2:
+        return False
+    return iteration in ("ring", "two_array") if d == 2 else (d == 3 and iteration == "ring")
 
 
 def plain_run(pk, h, target, iteration="ring", certificate="feasible", sigma=2, d=2):
@@ -644,17 +647,20 @@ GENERALITY = [(4, 2, 8, "f32"), (2, 3, 10, "f32"), (4, 2, 8, "f64"), (2, 3, 10, 
 
 
 def config_table(pk, configs=None, emit=True):
-    """Average sweep and certificate time per configuration (HIP events),
-    with the sweep's algorithmic bytes against the HBM peak."""
+    """Average sweep and certificate time per configuration (HIP events; 64
+    sweeps in one call, as a certificate period of the benchmark), with the
+    sweep's algorithmic bytes against the HBM peak.  Rings of the shapes
+    with branch-mean tables sweep from them."""
     import torch
     rows = []
     for sigma, d, h, dt in (CONFIGS if configs is None else configs):
-        L = pk.Lcsb(sigma, d, h, dt)
+        means = uses_means("ring", sigma, d)
+        L = pk.Lcsb(sigma, d, h, dt, means=means)
         L.init_zero()
         L.iterate(8)
         stream = torch.cuda.current_stream()
         e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-        reps = 16
+        reps = 64
         e[0].record(stream)
         L.iterate(reps)
         e[1].record(stream)
@@ -672,7 +678,7 @@ def config_table(pk, configs=None, emit=True):
         folded = L.swap_symmetric()  # exchange-folded: every table at one entry per pair
         algo = (d + 1) * elem * L.stored // (2 if folded else 1)
         rows.append({"sigma": sigma, "d": d, "l": h, "dtype": dt, "entries": L.n,
-                     "exchange_folded": folded,
+                     "exchange_folded": folded, "branch_means": means,
                      "sweep_ms": round(sweep_ms, 4), "certificate_ms": round(cert_ms, 3),
                      "optimal_certificate_ms": round(opt_ms, 3),
                      "algorithmic_GBps": round(algo / sweep_ms / 1e6, 1),

@@ -55,10 +55,11 @@ struct lcsb_ctx {
     int lags;        // tables the context keeps: d for the ring, 2 for the two-array iteration
     int packed;      // LCSB_ITER_TWO_ARRAY_PACKED: one entry per exchange orbit (packed_index)
     uint64_t entries;  // entries per table: g.ns, or packed_entries(h)
-    // branch-mean tables (lcsb_bind_means): per slot Ma, then Mab at mab_off,
-    // then the table's values at the two-array rate's sample at smp_off
+    // branch-mean tables (lcsb_bind_means): per slot the parts at part_off
+    // (d = 2: Ma, Mab, the table's values at the two-array rate's sample;
+    // d = 3: M1, M3, M12, M23, M123, the sample)
     void *means_buf[4];
-    uint64_t mab_off, smp_off;
+    uint64_t part_off[6];
     int means_ok[4];    // the slot's means are those of its table
     int entries_ok[4];  // the slot's entries hold its table (a branch-mean sweep may skip them)
     int samples_ok[4];  // the slot's sample values are its table's
@@ -104,31 +105,40 @@ void clear_lazy(lcsb_ctx *c)
     }
 }
 
-// sigma = d = 2 rings and two-array pairs (folded, not packed) of l >= 3
-// symmetric in the two strings sweep from the branch-mean tables once they
-// are bound
-bool means_path(const lcsb_ctx *c)
+// Folded tables of l >= 3 symmetric in the two strings sweep from the
+// branch-mean tables once they are bound: sigma = d = 2 (ring or two arrays)
+// and sigma = 2, d = 3 (ring)
+bool means_shape(const lcsb_ctx *c)
 {
-    return c->means_buf[0] && !c->packed && c->swap_sym && c->g.sigma == 2 && c->g.d == 2 &&
-           c->g.h >= 3;
+    if (c->packed || c->g.sigma != 2 || c->g.h < 3) return false;
+    return c->g.d == 2 || (c->g.d == 3 && !c->two_array);
 }
+bool means_path(const lcsb_ctx *c) { return c->means_buf[0] && c->swap_sym && means_shape(c); }
 
 uint64_t round256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
-uint64_t means_mab_offset(const lcsb_ctx *c) { return round256((c->g.ns / 2) * elem_size(c->dtype)); }
-uint64_t means_smp_offset(const lcsb_ctx *c)
+// byte offsets of the parts of a mean buffer; returns the buffer's size
+uint64_t means_layout(const lcsb_ctx *c, uint64_t *off)
 {
-    return round256(means_mab_offset(c) + (c->g.ns / 4) * elem_size(c->dtype));
+    const uint64_t es = elem_size(c->dtype), ns = c->g.ns;
+    // entries per part: d = 2 Ma ns/2, Mab ns/4; d = 3 M1, M3 ns/2, M12, M23 ns/4, M123 ns/8
+    const uint64_t d2[2] = {ns / 2, ns / 4}, d3[5] = {ns / 2, ns / 2, ns / 4, ns / 4, ns / 8};
+    const int parts = c->g.d == 2 ? 2 : 5;
+    uint64_t at = 0;
+    for (int k = 0; k < parts; ++k) {
+        off[k] = at;
+        at = round256(at + (c->g.d == 2 ? d2[k] : d3[k]) * es);
+    }
+    off[parts] = at;  // the sample values
+    return at + kRateSample * es;
 }
 
-void *slot_ma(const lcsb_ctx *c, int slot) { return c->means_buf[slot]; }
-void *slot_mab(const lcsb_ctx *c, int slot)
+void *slot_part(const lcsb_ctx *c, int slot, int part)
 {
-    return static_cast<unsigned char *>(c->means_buf[slot]) + c->mab_off;
+    return static_cast<unsigned char *>(c->means_buf[slot]) + c->part_off[part];
 }
-void *slot_smp(const lcsb_ctx *c, int slot)
-{
-    return static_cast<unsigned char *>(c->means_buf[slot]) + c->smp_off;
-}
+void *slot_ma(const lcsb_ctx *c, int slot) { return slot_part(c, slot, 0); }
+void *slot_mab(const lcsb_ctx *c, int slot) { return slot_part(c, slot, 1); }
+void *slot_smp(const lcsb_ctx *c, int slot) { return slot_part(c, slot, c->g.d == 2 ? 2 : 5); }
 
 // Complete the exchanged entries of a lazily written slot (stream order).
 int materialize(lcsb_ctx *c, int slot)
@@ -267,9 +277,11 @@ int lcsb_bind(lcsb_ctx *c, void *const *bufs, int nbuf, void *ws, void *stream)
 int lcsb_query_means(const lcsb_ctx *c, uint64_t *bytes_per_buf)
 {
     if (!c) return fail(LCSB_EINVAL, "null context");
-    if (c->packed || c->g.sigma != 2 || c->g.d != 2 || c->g.h < 3)
-        return fail(LCSB_EUNSUPPORTED, "branch-mean tables serve sigma = d = 2 folded tables at l >= 3");
-    if (bytes_per_buf) *bytes_per_buf = means_smp_offset(c) + kRateSample * elem_size(c->dtype);
+    if (!means_shape(c))
+        return fail(LCSB_EUNSUPPORTED, "branch-mean tables serve folded sigma = 2 tables of l >= 3 "
+                                       "(d = 2: ring or two arrays; d = 3: ring)");
+    uint64_t off[6];
+    if (bytes_per_buf) *bytes_per_buf = means_layout(c, off);
     return LCSB_OK;
 }
 
@@ -300,8 +312,7 @@ int lcsb_bind_means(lcsb_ctx *c, void *const *bufs, int nbuf)
         c->means_buf[k] = bufs[k];
         c->means_ok[k] = c->samples_ok[k] = 0;
     }
-    c->mab_off = means_mab_offset(c);
-    c->smp_off = means_smp_offset(c);
+    means_layout(c, c->part_off);
     return LCSB_OK;
 }
 
@@ -378,12 +389,47 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
             const int slot = slot_of_lag(c, j);
             if (c->means_ok[slot]) continue;
             if (!c->entries_ok[slot]) return fail(LCSB_ESTATE, "lag %d has neither entries nor means", j);
-            hipError_t e = launch_derive_means(c->g, c->dtype, c->buf[slot], c->lazy[slot],
-                                               slot_ma(c, slot), slot_mab(c, slot), c->stream);
+            hipError_t e =
+                c->g.d == 2
+                    ? launch_derive_means(c->g, c->dtype, c->buf[slot], c->lazy[slot],
+                                          slot_ma(c, slot), slot_mab(c, slot), c->stream)
+                    : launch_derive_means3(c->g, c->dtype, c->buf[slot], c->lazy[slot],
+                                           slot_part(c, slot, 0), slot_part(c, slot, 1),
+                                           slot_part(c, slot, 2), slot_part(c, slot, 3),
+                                           slot_part(c, slot, 4), c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "derive means");
             c->means_ok[slot] = 1;
         }
-        for (int64_t t = 0; t < k; ++t) {
+        for (int64_t t = 0; t < k && c->g.d == 3; ++t) {
+            Means3Launch a;
+            const int r1 = slot_of_lag(c, 1), r2 = slot_of_lag(c, 2), r3 = slot_of_lag(c, 3);
+            a.m1 = slot_part(c, r1, 0);
+            a.m3 = slot_part(c, r1, 1);
+            a.m12 = slot_part(c, r2, 2);
+            a.m23 = slot_part(c, r2, 3);
+            a.m123 = slot_part(c, r3, 4);
+            a.snew = (c->head + 1) % c->nbuf;
+            const bool entries = t >= k - c->g.d;
+            a.out = entries ? c->buf[a.snew] : nullptr;
+            a.n1 = slot_part(c, a.snew, 0);
+            a.n3 = slot_part(c, a.snew, 1);
+            a.n12 = slot_part(c, a.snew, 2);
+            a.n23 = slot_part(c, a.snew, 3);
+            a.n123 = slot_part(c, a.snew, 4);
+            a.offsets = reinterpret_cast<double *>(c->ws + Ws::kOffsets);
+            a.s1 = r1;
+            a.s2 = r2;
+            a.s3 = r3;
+            a.shift = 0;
+            hipError_t e = launch_sweep_means3(c->g, c->dtype, a, c->stream);
+            if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+            c->lazy[a.snew] = 1;
+            c->means_ok[a.snew] = 1;
+            c->entries_ok[a.snew] = entries;
+            c->head = a.snew;
+            c->sweeps++;
+        }
+        for (int64_t t = 0; t < k && c->g.d == 2; ++t) {
             MeansLaunch a;
             const int r1 = slot_of_lag(c, 1), r2 = c->two_array ? r1 : slot_of_lag(c, 2);
             a.ma1 = slot_ma(c, r1);

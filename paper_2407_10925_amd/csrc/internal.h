@@ -89,6 +89,37 @@ __host__ __device__ inline uint64_t mab_index(uint64_t s, uint64_t n)
     return s >> 2;
 }
 
+// sigma = 2, d = 3 (slot bits s1 s2 s3, s1 most significant; stored tuples
+// s < n/2, n = 8^l).  For a stored group prefix P < n/16 (entries 8P .. 8P+7,
+// member u = the last slot) the branch means, each the entry sweep's own:
+//   M1[4P + (u & 3)]   mean over s1 of members u, u + 4      (moves string 1)
+//   M3[4P + (u >> 1)]  mean over s3 of members u, u + 1      (string 3)
+//   M12[2P + s3]       pair tree over (s1 s2) of 8P + s3 + {0, 2, 4, 6}  (strings 1, 2)
+//   M23[2P + s1]       pair tree over (s2 s3) of 8P + 4 s1 + {0, 1, 2, 3} (strings 2, 3)
+//   M123[P]            the eight-member pair tree                 (all three)
+// On a table symmetric in strings 1 and 2 the string-2 mean is M1 at the
+// exchanged tuple and the (s1 s3) mean is M23 at the exchanged tuple; M3, M12
+// and M123 are exchange-symmetric and kept at the lower index of each
+// exchanged pair.  An index with string-1 head 1 is read at its complement.
+__host__ __device__ inline uint64_t d3_fold(uint64_t s, uint64_t n) { return (s & (n >> 1)) ? s ^ (n - 1) : s; }
+__host__ __device__ inline uint64_t m1_index(uint64_t s, uint64_t n)
+{
+    s = d3_fold(s, n);
+    return ((s >> 3) << 2) | (s & 3);
+}
+__host__ __device__ inline uint64_t m3_index(uint64_t s, uint64_t n) { return d3_fold(s, n) >> 1; }
+__host__ __device__ inline uint64_t m12_index(uint64_t s, uint64_t n)
+{
+    s = d3_fold(s, n);
+    return ((s >> 3) << 1) | (s & 1);
+}
+__host__ __device__ inline uint64_t m23_index(uint64_t s, uint64_t n)
+{
+    s = d3_fold(s, n);
+    return ((s >> 3) << 1) | ((s >> 2) & 1);
+}
+__host__ __device__ inline uint64_t m123_index(uint64_t s, uint64_t n) { return d3_fold(s, n) >> 3; }
+
 struct MeansLaunch {
     const void *ma1;   // Ma of lag 1
     const void *mab2;  // Mab of lag 2
@@ -111,6 +142,20 @@ hipError_t launch_means_samples(const Geometry &g, int dtype, const MeansLaunch 
 // pair holds a value, see TwinGroup)
 hipError_t launch_derive_means(const Geometry &g, int dtype, const void *table, int lazy,
                                void *ma, void *mab, hipStream_t s);
+
+// The same for sigma = 2, d = 3 (m1_index .. m123_index): lag 1's M1 and M3,
+// lag 2's M12 and M23, lag 3's M123 read; the new table's five written
+struct Means3Launch {
+    const void *m1, *m3, *m12, *m23, *m123;
+    void *out;  // the new table's entries, or null
+    void *n1, *n3, *n12, *n23, *n123;
+    double *offsets;
+    int s1, s2, s3, snew;
+    int shift;  // FP64: lags 2 and 3 read with their offset differences (two arrays)
+};
+hipError_t launch_sweep_means3(const Geometry &g, int dtype, const Means3Launch &a, hipStream_t s);
+hipError_t launch_derive_means3(const Geometry &g, int dtype, const void *table, int lazy, void *m1,
+                                void *m3, void *m12, void *m23, void *m123, hipStream_t s);
 
 // Certificate passes (see lcsb_cert); results land in the workspace scalars.
 // swap_sym: as in SweepLaunch (the W pass then evaluates one coordinate per

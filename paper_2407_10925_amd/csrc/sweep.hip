@@ -834,6 +834,199 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3(const T *__restrict__ lag1,
     }
 }
 
+// ---------------------------------------------------------------- sigma = 2, d = 3 from branch means
+// The values of sweep_s2d3<T, true, SHIFT> (rings symmetric in strings 1 and
+// 2) from the lags' branch-mean tables (m1_index .. m123_index): the all-match
+// tuple reads lag 3's M123, 001 lag 1's M3 and lag 2's M12, 010 the string-2
+// mean of lag 1 (M1 at the exchanged tuple) and the (s1 s3) mean of lag 2
+// (M23 at the exchanged tuple), 011 lag 2's M23 and lag 1's M1; M3, M12 and
+// M123 are read at the lower index of each exchanged pair.  Each mean is the
+// entry sweep's own, so the tables agree bit for bit.
+//
+// Thread t < n/16 computes the tuples of tail t and of its complement, as
+// sweep_s2d3 does; the eight threads of an octet (t = 8j + v) hold every
+// member of eight aligned groups (heads 000 .. 011, tails 8j + v and their
+// complements, member v or 7 - v), which exchange their values by lane
+// shuffles (q[k] = the value of member u xor k) and each write the means
+// whose first member they hold, in the entry sweep's order of operations.
+// Octets are exchange-folded whole: the lower of octet j and its exchanged
+// octet runs (both members when they are one), and it also writes the
+// exchanged octet's M1 (its string-2 means) and M23 (its (s1 s3) means).
+// Index arithmetic in I (32 bits when every index of the table fits, which
+// halves the integer work the kernel is bound by, else 64); mask = n - 1.
+template <typename I>
+struct D3Idx {
+    I mask, half, r3;
+    __device__ D3Idx(uint64_t n) : mask((I)(n - 1)), half((I)(n >> 1)), r3((I)((n - 1) / 7)) {}
+    // strings 1 and 2 exchanged in every slot, complemented when that puts a
+    // 1 at string 1's head (exchange_twin for d = 3)
+    __device__ __forceinline__ I twin(I j) const
+    {
+        const I x = (j & r3) | ((j & (r3 << 2)) >> 1) | ((j & (r3 << 1)) << 1);
+        return (x & half) ? x ^ mask : x;
+    }
+    __device__ __forceinline__ I fold(I s) const { return (s & half) ? s ^ mask : s; }
+    __device__ __forceinline__ I m1(I s) const { s = fold(s); return ((s >> 3) << 2) | (s & 3); }
+    __device__ __forceinline__ I m3(I s) const { return fold(s) >> 1; }
+    __device__ __forceinline__ I m12(I s) const { s = fold(s); return ((s >> 3) << 1) | (s & 1); }
+    __device__ __forceinline__ I m23(I s) const { s = fold(s); return ((s >> 3) << 1) | ((s >> 2) & 1); }
+    __device__ __forceinline__ I m123(I s) const { return fold(s) >> 3; }
+    // the strings in sm advanced: their bits move up one slot, 0 appended
+    __device__ __forceinline__ I base(I i, I sm) const { return (i & ~sm) | ((i << 3) & sm & mask); }
+};
+
+template <typename T, bool SHIFT, typename I>
+__global__ __launch_bounds__(kBlock) void sweep_s2d3_means(
+    const T *__restrict__ m1a, const T *__restrict__ m3a, const T *__restrict__ m12b,
+    const T *__restrict__ m23b, const T *__restrict__ m123c, T *__restrict__ out,
+    T *__restrict__ n1, T *__restrict__ n3, T *__restrict__ n12, T *__restrict__ n23,
+    T *__restrict__ n123, uint64_t n, int h, double *__restrict__ off, int s1, int s2, int s3,
+    int snew)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kShift = kF32 || SHIFT;
+    const uint64_t t64 = thread_index();
+    const int top = 3 * (h - 1);
+    T d2 = 0, d3 = 0, y0 = 0;
+    if constexpr (!kF32 && SHIFT) {
+        d2 = off[s2] - off[s1];
+        d3 = off[s3] - off[s1];
+    }
+    if constexpr (kF32) {
+        const double o1 = off[s1];
+        d2 = (float)(off[s2] - o1);
+        d3 = (float)(off[s3] - o1);
+        y0 = 1.0f + first(m123c[0] + d3);
+        if (t64 == 0) off[snew] = o1 + (double)y0;
+    }
+    if (t64 >= (n >> 4)) return;
+    const D3Idx<I> ix(n);
+    const I t = (I)t64, mx = (I)((n >> 3) - 1), j = t >> 3;
+    const int v = (int)(t & 7);
+    // whole octets: the exchanged tail of 8j is 8 Ej, or 8 ~Ej + 7 when s2_2 = 1
+    const I t0 = t & ~(I)7, sb = (mx + 1) >> 2, r3t = mx / 7;
+    const I e0 = (t0 & r3t) | ((t0 & (r3t << 2)) >> 1) | ((t0 & (r3t << 1)) << 1);
+    const I pj = ((t & sb) ? e0 ^ mx : e0) >> 3;
+    if (pj < j) return;
+    const bool self = pj == j;
+
+    // reads
+    T val[2][4];
+    {
+        const I tw = ix.m123(ix.twin(8 * t));
+        T all3 = m123c[tw < t ? tw : t];
+        if constexpr (kShift) all3 = all3 + d3;
+        val[0][0] = val[1][0] = (T)1 + first(all3);
+    }
+    const I S3 = ix.r3, S2 = S3 << 1, S1 = S3 << 2;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const I x = c ? mx - t : t;
+        {   // 001: string 3 (lag 1), strings 1 and 2 (lag 2)
+            const I i = ((I)1 << top) | x, b1 = ix.base(i, S3), b2 = ix.base(i, S1 | S2);
+            const I a3 = ix.m3(b1), a3t = ix.m3(ix.twin(b1));
+            const I a12 = ix.m12(b2), a12t = ix.m12(ix.twin(b2));
+            const T k1 = m3a[a3t < a3 ? a3t : a3];
+            T k2 = m12b[a12t < a12 ? a12t : a12];
+            if constexpr (kShift) k2 = k2 + d2;
+            val[c][1] = vmax(first(k1), k2);
+        }
+        {   // 010: string 2 (lag 1), strings 1 and 3 (lag 2), at the exchanged tuples
+            const I i = ((I)2 << top) | x, b1 = ix.base(i, S2), b2 = ix.base(i, S1 | S3);
+            const T k1 = m1a[ix.m1(ix.twin(b1))];
+            T k2 = m23b[ix.m23(ix.twin(b2))];
+            if constexpr (kShift) k2 = k2 + d2;
+            val[c][2] = vmax(first(k1), k2);
+        }
+        {   // 011: strings 2 and 3 (lag 2), string 1 (lag 1)
+            const I i = ((I)3 << top) | x, b2 = ix.base(i, S2 | S3), b1 = ix.base(i, S1);
+            T k2 = m23b[ix.m23(b2)];
+            const T k1 = m1a[ix.m1(b1)];
+            if constexpr (kShift) k2 = k2 + d2;
+            val[c][3] = vmax(first(k2), k1);
+        }
+    }
+    if constexpr (kF32) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) val[c][r] = (T)(val[c][r] - y0);
+    }
+
+    // writes: for head r and tail x (t, or its complement: prefix P = j or
+    // ~j, member u = v or 7 - v), the entry at the lower index of its
+    // exchanged pair when asked, and the group means this lane begins, from
+    // q[k] = the value of member u xor k
+    const T half = (T)0.5, quarter = (T)0.25, eighth = (T)0.125;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        T q[8];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            // the 000 groups of j and ~j hold the same lane values: one exchange
+            if (!(r == 0 && c == 1)) {
+                q[0] = val[c][r];
+#pragma unroll
+                for (int k = 1; k < 8; ++k) q[k] = __shfl_xor(q[0], k);
+            }
+            const int u = c ? 7 - v : v;
+            const I jj = ((I)r << top) | (c ? mx - t : t);  // = 8P + u
+            const I P = jj >> 3, tw = ix.twin(jj);
+            if (out) put(out + (tw < jj ? tw : jj), val[c][r]);
+            if (!(u & 4)) put(n1 + (4 * P + (I)(u & 3)), (q[0] + q[4]) * half);
+            if (!(u & 1)) {
+                const I own = 4 * P + (I)(u >> 1), twi = ix.m3(tw);
+                put(n3 + (twi < own ? twi : own), (q[0] + q[1]) * half);
+            }
+            if (!(u & 6)) {
+                const I own = 2 * P + (I)(u & 1), twi = ix.m12(tw);
+                put(n12 + (twi < own ? twi : own), ((q[0] + q[6]) + (q[2] + q[4])) * quarter);
+            }
+            if (!(u & 3)) put(n23 + (2 * P + (I)(u >> 2)), ((q[0] + q[3]) + (q[1] + q[2])) * quarter);
+            if (u == 0) {
+                const I twi = ix.m123(tw);
+                put(n123 + (twi < P ? twi : P),
+                    (((q[0] + q[7]) + (q[1] + q[6])) + ((q[2] + q[5]) + (q[3] + q[4]))) * eighth);
+            }
+            if (!self) {  // the exchanged octet's string-2 and (s1 s3) means
+                if (!(u & 2)) put(n1 + ix.m1(tw), (q[0] + q[2]) * half);
+                if (!(u & 5)) put(n23 + ix.m23(tw), ((q[0] + q[5]) + (q[1] + q[4])) * quarter);
+            }
+        }
+    }
+}
+
+// the five means of a stored table, one thread per group prefix P < n/16
+template <typename T>
+__global__ __launch_bounds__(kBlock) void derive_means3(const T *__restrict__ tab, int lazy,
+                                                       T *__restrict__ m1, T *__restrict__ m3,
+                                                       T *__restrict__ m12, T *__restrict__ m23,
+                                                       T *__restrict__ m123, uint64_t n)
+{
+    const uint64_t P = thread_index();
+    if (P >= (n >> 4)) return;
+    T e[8];
+    if (lazy) {
+        const TwinGroup tg = twin_group8(8 * P, n);
+        T q[8];
+        load8(tab + tg.read, q);
+        twin_values8(q, tg.mode, e);
+    } else {
+        load8(tab + 8 * P, e);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        m1[4 * P + k] = (e[k] + e[k + 4]) * (T)0.5;
+        m3[4 * P + k] = (e[2 * k] + e[2 * k + 1]) * (T)0.5;
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        m12[2 * P + b] = pair4(e[b], e[2 + b], e[4 + b], e[6 + b]) * (T)0.25;
+        m23[2 * P + b] = pair4(e[4 * b], e[4 * b + 1], e[4 * b + 2], e[4 * b + 3]) * (T)0.25;
+    }
+    m123[P] = pair8(e) * (T)0.125;
+}
+
 // ---------------------------------------------------------------- l = 1
 // Every tuple is its head slot and each branch appends its symbols in that
 // slot, so a branch group straddles the stored half: every value is read at
@@ -1156,6 +1349,49 @@ hipError_t launch_derive_means(const Geometry &g, int dtype, const void *table, 
         derive_means<double><<<grid, dim3(kBlock), 0, s>>>(static_cast<const double *>(table),
                                                            lazy, static_cast<double *>(ma),
                                                            static_cast<double *>(mab), g.n);
+    return hipGetLastError();
+}
+
+template <typename T, bool SHIFT, typename I>
+hipError_t means3_typed(const Geometry &g, const Means3Launch &a, hipStream_t s)
+{
+    sweep_s2d3_means<T, SHIFT, I><<<sweep_grid(g.n >> 4), dim3(kBlock), 0, s>>>(
+        static_cast<const T *>(a.m1), static_cast<const T *>(a.m3), static_cast<const T *>(a.m12),
+        static_cast<const T *>(a.m23), static_cast<const T *>(a.m123), static_cast<T *>(a.out),
+        static_cast<T *>(a.n1), static_cast<T *>(a.n3), static_cast<T *>(a.n12),
+        static_cast<T *>(a.n23), static_cast<T *>(a.n123), g.n, g.h, a.offsets, a.s1, a.s2, a.s3,
+        a.snew);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_means3(const Geometry &g, int dtype, const Means3Launch &a, hipStream_t s)
+{
+    if (g.sigma != 2 || g.d != 3 || g.h < 3) return hipErrorInvalidValue;
+    if (g.n <= (1ull << 31)) {  // every index, and 8 t, in 32 bits
+        if (dtype == LCSB_F32) return means3_typed<float, false, uint32_t>(g, a, s);
+        return a.shift ? means3_typed<double, true, uint32_t>(g, a, s)
+                       : means3_typed<double, false, uint32_t>(g, a, s);
+    }
+    if (dtype == LCSB_F32) return means3_typed<float, false, uint64_t>(g, a, s);
+    return a.shift ? means3_typed<double, true, uint64_t>(g, a, s)
+                   : means3_typed<double, false, uint64_t>(g, a, s);
+}
+
+hipError_t launch_derive_means3(const Geometry &g, int dtype, const void *table, int lazy, void *m1,
+                                void *m3, void *m12, void *m23, void *m123, hipStream_t s)
+{
+    if (g.sigma != 2 || g.d != 3 || g.h < 3) return hipErrorInvalidValue;
+    const dim3 grid = sweep_grid(g.n >> 4);
+    if (dtype == LCSB_F32)
+        derive_means3<float><<<grid, dim3(kBlock), 0, s>>>(
+            static_cast<const float *>(table), lazy, static_cast<float *>(m1),
+            static_cast<float *>(m3), static_cast<float *>(m12), static_cast<float *>(m23),
+            static_cast<float *>(m123), g.n);
+    else
+        derive_means3<double><<<grid, dim3(kBlock), 0, s>>>(
+            static_cast<const double *>(table), lazy, static_cast<double *>(m1),
+            static_cast<double *>(m3), static_cast<double *>(m12), static_cast<double *>(m23),
+            static_cast<double *>(m123), g.n);
     return hipGetLastError();
 }
 

@@ -307,8 +307,172 @@ static void means(int h, uint64_t count = 0)
     EXPECT(miss == 0, "h=%d: %llu all-advance means read but never written", h, (unsigned long long)miss);
 }
 
+// Branch-mean tables for sigma = 2, d = 3 (m1_index .. m123_index): on a
+// table that gives every orbit of the complement and the exchange of strings
+// 1 and 2 one pseudo-random integer (an all-match tuple one for its tail's
+// orbit), emulate the octets of eight lanes of the branch-mean sweep (lane v
+// of octet j holds tail t = 8j + v and its complement; member u = v, or 7 - v
+// for the complement's groups; partners by lane xor): every mean a lane
+// writes equals its definition, the exchange-folded tables (M3, M12, M123)
+// are written at the lower index of each exchanged pair, M1 and M23 in full
+// (the exchanged octet's through its string-2 and (s1 s3) means), every read
+// (with the lower-index redirect where folded) finds the mean the entry
+// sweep forms, and every index read is written.
+static double orbit_value3(uint64_t s, uint64_t n)
+{
+    const int h = __builtin_ctzll(n) / 3;
+    const uint64_t head = s >> (3 * (h - 1));
+    const bool match = head == 0 || head == 7;
+    if (match) s &= (n >> 3) - 1;
+    const uint64_t m = match ? (n >> 3) - 1 : n - 1;
+    const uint64_t e = exchange12(s, m + 1), c = s ^ m, ec = e ^ m;
+    uint64_t r = s < c ? s : c;
+    r = r < e ? r : e;
+    r = r < ec ? r : ec;
+    if (match) r |= 1ull << 62;
+    uint64_t z = (r + 0x9E3779B97F4A7C15ull) * 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 29;
+    return (double)(z & 0xFFFF);
+}
+
+static void means3(int h, uint64_t count = 0)
+{
+    const uint64_t n = 1ull << (3 * h), mx = (n >> 3) - 1, s2bit = (mx + 1) >> 2;
+    const int top = 3 * (h - 1);
+    const uint64_t mask = n - 1, r3 = mask / 7, S1 = r3 << 2, S2 = r3 << 1, S3 = r3;
+    auto T = [&](uint64_t s) { return orbit_value3(s, n); };
+    auto base = [&](uint64_t i, uint64_t sm) { return (i & ~sm) | ((i << 3) & sm & mask); };
+    auto p4 = [](double a, double b, double c, double d) { return ((a + d) + (b + c)) * 0.25; };
+    auto p8 = [&](uint64_t g) {
+        return (((T(g) + T(g + 7)) + (T(g + 1) + T(g + 6))) + ((T(g + 2) + T(g + 5)) + (T(g + 3) + T(g + 4)))) * 0.125;
+    };
+    auto m1_def = [&](uint64_t k) { const uint64_t P = k >> 2, r = k & 3; return (T(8 * P + r) + T(8 * P + 4 + r)) * 0.5; };
+    auto m3_def = [&](uint64_t k) { const uint64_t P = k >> 2, q = k & 3; return (T(8 * P + 2 * q) + T(8 * P + 2 * q + 1)) * 0.5; };
+    auto m12_def = [&](uint64_t k) { const uint64_t g = 8 * (k >> 1) + (k & 1); return p4(T(g), T(g + 2), T(g + 4), T(g + 6)); };
+    auto m23_def = [&](uint64_t k) { const uint64_t g = 8 * (k >> 1) + 4 * (k & 1); return p4(T(g), T(g + 1), T(g + 2), T(g + 3)); };
+    auto lower = [](uint64_t a, uint64_t b) { return a < b ? a : b; };
+    const uint64_t octets = n >> 7;
+    std::vector<char> w1(count ? 0 : n / 4), w3(count ? 0 : n / 4), w12(count ? 0 : n / 8),
+        w23(count ? 0 : n / 8), w123(count ? 0 : n / 16);
+    std::vector<uint64_t> need3, need12, need123;
+    const uint64_t visits = count ? count + 2 : octets;
+    for (uint64_t k = 0; k < visits; ++k) {
+        const uint64_t j = !count ? k : k == count ? 0 : k == count + 1 ? octets - 1
+                                                   : (k * 0x9E3779B97F4A7C15ull) % octets;
+        const uint64_t e0 = exchange12(8 * j, n >> 3);
+        const uint64_t pj = ((8 * j) & s2bit ? e0 ^ mx : e0) >> 3;
+        if (pj < j) continue;
+        // lane values: [head r][c][v]
+        double lv[4][2][8];
+        for (int v = 0; v < 8; ++v) {
+            const uint64_t t = 8 * j + (uint64_t)v;
+            for (int c = 0; c < 2; ++c)
+                for (int r = 0; r < 4; ++r) lv[r][c][v] = T(((uint64_t)r << top) | (c ? mx - t : t));
+            // reads
+            const uint64_t g = 8 * t;
+            const uint64_t r123 = lower(m123_index(g, n), m123_index(exchange_twin(g, n, 3), n));
+            EXPECT(r123 < n / 16 && m123_index(g, n) == t, "d=3 h=%d: match read", h);
+            EXPECT(p8(8 * r123) == p8(g), "d=3 h=%d t=%llu: all-advance mean", h, (unsigned long long)t);
+            if (!count) need123.push_back(r123);
+            for (int c = 0; c < 2; ++c) {
+                const uint64_t x = c ? mx - t : t;
+                {   // 001
+                    const uint64_t i = (1ull << top) | x, b1 = base(i, S3), b2 = base(i, S1 | S2);
+                    const uint64_t a3 = lower(m3_index(b1, n), m3_index(exchange_twin(b1, n, 3), n));
+                    const uint64_t a12 = lower(m12_index(b2, n), m12_index(exchange_twin(b2, n, 3), n));
+                    EXPECT(a3 < n / 4 && a12 < n / 8, "d=3 h=%d: 001 read out of range", h);
+                    EXPECT(m3_def(a3) == (T(b1) + T(b1 + 1)) * 0.5, "d=3 h=%d x=%llu: 001 string-3 mean", h,
+                           (unsigned long long)x);
+                    EXPECT(m12_def(a12) == p4(T(b2), T(b2 + 2), T(b2 + 4), T(b2 + 6)),
+                           "d=3 h=%d x=%llu: 001 strings-1,2 mean", h, (unsigned long long)x);
+                    if (!count) { need3.push_back(a3); need12.push_back(a12); }
+                }
+                {   // 010
+                    const uint64_t i = (2ull << top) | x, b1 = base(i, S2), b2 = base(i, S1 | S3);
+                    const uint64_t a1 = m1_index(exchange_twin(b1, n, 3), n);
+                    const uint64_t a23 = m23_index(exchange_twin(b2, n, 3), n);
+                    EXPECT(a1 < n / 4 && a23 < n / 8, "d=3 h=%d: 010 read out of range", h);
+                    EXPECT(m1_def(a1) == (T(b1) + T(b1 + 2)) * 0.5, "d=3 h=%d x=%llu: 010 string-2 mean", h,
+                           (unsigned long long)x);
+                    EXPECT(m23_def(a23) == p4(T(b2), T(b2 + 1), T(b2 + 4), T(b2 + 5)),
+                           "d=3 h=%d x=%llu: 010 strings-1,3 mean", h, (unsigned long long)x);
+                }
+                {   // 011
+                    const uint64_t i = (3ull << top) | x, b2 = base(i, S2 | S3), b1 = base(i, S1);
+                    const uint64_t a23 = m23_index(b2, n), a1 = m1_index(b1, n);
+                    EXPECT(a1 < n / 4 && a23 < n / 8, "d=3 h=%d: 011 read out of range", h);
+                    EXPECT(m23_def(a23) == p4(T(b2), T(b2 + 1), T(b2 + 2), T(b2 + 3)),
+                           "d=3 h=%d x=%llu: 011 strings-2,3 mean", h, (unsigned long long)x);
+                    EXPECT(m1_def(a1) == (T(b1) + T(b1 + 4)) * 0.5, "d=3 h=%d x=%llu: 011 string-1 mean", h,
+                           (unsigned long long)x);
+                }
+            }
+        }
+        // writes: the eight groups of the octet, as the lanes form them
+        const uint64_t jc = (mx >> 3) - j;
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 2; ++c) {
+                const uint64_t P = ((uint64_t)r << (top - 3)) | (c ? jc : j);
+                double m[8];
+                for (int u = 0; u < 8; ++u) m[u] = lv[r][c][c ? 7 - u : u];
+                for (int u = 0; u < 8; ++u)
+                    EXPECT(T(8 * P + (uint64_t)u) == m[u], "d=3 h=%d: group %llu member %d", h,
+                           (unsigned long long)P, u);
+                auto put = [&](std::vector<char> &w, uint64_t idx, uint64_t size, double val, double def,
+                               const char *what) {
+                    EXPECT(idx < size, "d=3 h=%d: %s write out of range", h, what);
+                    if (idx >= size) return;
+                    EXPECT(val == def, "d=3 h=%d P=%llu: %s write differs from its definition", h,
+                           (unsigned long long)P, what);
+                    if (!count) w[idx] = 1;
+                };
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t i1 = 4 * P + (uint64_t)q;
+                    put(w1, i1, n / 4, (m[q] + m[q + 4]) * 0.5, m1_def(i1), "M1");
+                    const uint64_t i3 = lower(4 * P + (uint64_t)q, m3_index(exchange_twin(8 * P + 2 * q, n, 3), n));
+                    put(w3, i3, n / 4, (m[2 * q] + m[2 * q + 1]) * 0.5, m3_def(i3), "M3");
+                }
+                for (int b = 0; b < 2; ++b) {
+                    const uint64_t i12 = lower(2 * P + (uint64_t)b, m12_index(exchange_twin(8 * P + b, n, 3), n));
+                    put(w12, i12, n / 8, p4(m[b], m[2 + b], m[4 + b], m[6 + b]), m12_def(i12), "M12");
+                    put(w23, 2 * P + (uint64_t)b, n / 8, p4(m[4 * b], m[4 * b + 1], m[4 * b + 2], m[4 * b + 3]),
+                        m23_def(2 * P + (uint64_t)b), "M23");
+                }
+                const double all = (((m[0] + m[7]) + (m[1] + m[6])) + ((m[2] + m[5]) + (m[3] + m[4]))) * 0.125;
+                const uint64_t i123 = lower(P, m123_index(exchange_twin(8 * P, n, 3), n));
+                put(w123, i123, n / 16, all, p8(8 * i123), "M123");
+                if (pj != j) {  // the exchanged octet's M1 and M23
+                    for (int u : {0, 1, 4, 5}) {
+                        const uint64_t i1 = m1_index(exchange_twin(8 * P + (uint64_t)u, n, 3), n);
+                        EXPECT(i1 == m1_index(exchange_twin(8 * P + (uint64_t)(u ^ 2), n, 3), n),
+                               "d=3 h=%d: string-2 pair splits", h);
+                        put(w1, i1, n / 4, (m[u] + m[u ^ 2]) * 0.5, m1_def(i1), "twin M1");
+                    }
+                    for (int s2 = 0; s2 < 2; ++s2) {
+                        const int u0 = 2 * s2;
+                        const uint64_t i23 = m23_index(exchange_twin(8 * P + (uint64_t)u0, n, 3), n);
+                        put(w23, i23, n / 8, p4(m[u0], m[u0 + 1], m[u0 + 4], m[u0 + 5]), m23_def(i23),
+                            "twin M23");
+                    }
+                }
+            }
+    }
+    if (count) return;
+    uint64_t miss = 0;
+    for (char f : w1) miss += !f;
+    for (char f : w23) miss += !f;
+    EXPECT(miss == 0, "d=3 h=%d: %llu M1/M23 entries never written", h, (unsigned long long)miss);
+    miss = 0;
+    for (uint64_t i : need3) miss += !w3[i];
+    for (uint64_t i : need12) miss += !w12[i];
+    for (uint64_t i : need123) miss += !w123[i];
+    EXPECT(miss == 0, "d=3 h=%d: %llu folded means read but never written", h, (unsigned long long)miss);
+}
+
 int main()
 {
+    for (int h = 3; h <= 6; ++h) means3(h);
+    for (int h = 7; h <= 12; ++h) means3(h, 1u << 12);
     for (int h = 3; h <= 10; ++h) means(h);
     for (int h = 11; h <= 18; ++h) means(h, 1u << 16);
     for (int h = 2; h <= 10; ++h) packed(h);

@@ -35,9 +35,9 @@ def pk():
     return pk
 
 
-def _pair(pk, h, dtype, iteration="ring"):
-    T = pk.Lcsb(2, 2, h, dtype, iteration=iteration)
-    M = pk.Lcsb(2, 2, h, dtype, iteration=iteration, means=True)
+def _pair(pk, h, dtype, iteration="ring", d=2):
+    T = pk.Lcsb(2, d, h, dtype, iteration=iteration)
+    M = pk.Lcsb(2, d, h, dtype, iteration=iteration, means=True)
     T.init_zero()
     M.init_zero()
     assert T.swap_symmetric() and M.swap_symmetric()
@@ -58,9 +58,9 @@ def _same_certs(T, M, tag=""):
 
 
 def _same_tables_host(T, M, tag=""):
-    """Lags 1 and 2 as stored and as FP64 true values (read_table leaves the
+    """Every lag as stored and as FP64 true values (read_table leaves the
     means of the mean context in use)."""
-    for k in (1, 2):
+    for k in range(1, T.lags + 1):
         for as_f64 in (False, True):
             a, b = T.read_table(k, as_f64), M.read_table(k, as_f64)
             if not np.array_equal(a, b):
@@ -310,6 +310,89 @@ def test_two_array_means_full_size(pk):
         assert T.rate() == M.rate()
     _same_certs(T, M, "full size")
     for k in (1, 2):
+        a, ao = T.lag(k)
+        b, bo = M.lag(k)
+        assert ao == bo
+        assert torch.equal(a, b), k
+    del T, M
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ sigma = 2, d = 3
+# M1, M3 of lag 1, M12, M23 of lag 2 and M123 of lag 3 (m1_index .. m123_index).
+
+@pytest.mark.parametrize("h", [3, 4])
+def test_d3_means_trajectory_matches_the_oracle(pk, h):
+    say(f"d=3 means vs oracle: h={h}")
+    M = pk.Lcsb(2, 3, h, "f64", means=True)
+    M.init_zero()
+    N = 8 ** h
+    ring = [np.zeros(N)] * 3
+    done = 0
+    for chunk in (1, 1, 2, 3, 5, 8, 20):
+        for _ in range(chunk):
+            ring = [oracle.sweep(2, 3, h, ring), ring[0], ring[1]]
+        M.iterate(chunk)
+        done += chunk
+        for k in (1, 2, 3):
+            assert np.array_equal(M.read_table(k), ring[k - 1][: N // 2]), (done, k)
+
+
+@pytest.mark.parametrize("h", [3, 4, 6, 8])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_d3_means_ring_matches_the_entry_ring(pk, h, dtype):
+    say(f"d=3 means vs entries: h={h} {dtype}")
+    T, M = _pair(pk, h, dtype, d=3)
+    done = 0
+    for chunk in (1, 2, 7, 40, 0, 1):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        done += chunk
+        _same_tables_host(T, M, f"after {done}")
+        _same_certs(T, M, f"after {done}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_d3_means_writes_through_lag(pk, dtype):
+    h = 5
+    say(f"d=3 means after writes through lcsb_lag: {dtype}")
+    T, M = _pair(pk, h, dtype, d=3)
+    T.iterate(7)
+    M.iterate(7)
+    n = 8 ** h
+    for k, i in ((1, 0x2a5b), (3, 0x1c3d)):  # stored indices (below n/2 = 16384)
+        # the exchanged twin: strings 1 and 2 swapped in every slot, complemented
+        # when that puts a 1 at string 1's head
+        r3 = (n - 1) // 7
+        e = (i & r3) | ((i & (r3 << 2)) >> 1) | ((i & (r3 << 1)) << 1)
+        if e >= n // 2:
+            e ^= n - 1
+        for L in (T, M):
+            t, _ = L.lag(k)
+            t[i] = t[i] + 0.375
+            if e != i:
+                t[e] = t[e] + 0.375
+        torch.cuda.synchronize()
+    assert T.swap_symmetric() and M.swap_symmetric()
+    for chunk in (1, 5):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        _same_tables_host(T, M, f"planted, +{chunk}")
+        _same_certs(T, M, f"planted, +{chunk}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_d3_means_full_size(pk, dtype):
+    """The benchmark's (2, 3, 10): whole lags on the device and both
+    certificates after sweeps that cross an lcsb_iterate call."""
+    say(f"d=3 means full size: h=10 {dtype}")
+    torch.cuda.empty_cache()
+    T, M = _pair(pk, 10, dtype, d=3)
+    for chunk in (4, 20):
+        T.iterate(chunk)
+        M.iterate(chunk)
+    _same_certs(T, M, "full size")
+    for k in (1, 2, 3):
         a, ao = T.lag(k)
         b, bo = M.lag(k)
         assert ao == bo

@@ -650,12 +650,17 @@ def config_table(pk, configs=None, emit=True):
     """Average sweep and certificate time per configuration (HIP events; 64
     sweeps in one call, as a certificate period of the benchmark), with the
     sweep's algorithmic bytes against the HBM peak.  Rings of the shapes
-    with branch-mean tables sweep from them."""
+    with branch-mean tables sweep from them where they fit beside the ring."""
     import torch
     rows = []
     for sigma, d, h, dt in (CONFIGS if configs is None else configs):
         means = uses_means("ring", sigma, d)
-        L = pk.Lcsb(sigma, d, h, dt, means=means)
+        try:
+            L = pk.Lcsb(sigma, d, h, dt, means=means)
+        except torch.cuda.OutOfMemoryError:  # the means do not fit beside the ring
+            torch.cuda.empty_cache()
+            means = False
+            L = pk.Lcsb(sigma, d, h, dt)
         L.init_zero()
         L.iterate(8)
         stream = torch.cuda.current_stream()

@@ -34,6 +34,7 @@ Also printed in the same JSON line:
                 for the same started from the learned warm start
 """
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -658,6 +659,9 @@ def config_table(pk, configs=None, emit=True):
         try:
             L = pk.Lcsb(sigma, d, h, dt, means=means)
         except torch.cuda.OutOfMemoryError:  # the means do not fit beside the ring
+            L = None
+        if L is None:  # (outside the handler, so the partial context can be freed)
+            gc.collect()
             torch.cuda.empty_cache()
             means = False
             L = pk.Lcsb(sigma, d, h, dt)

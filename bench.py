@@ -254,7 +254,9 @@ def polish(P, S, best, target, certificate="feasible"):
 
 def uses_means(iteration, sigma, d):
     """Branch-mean buffers serve the sigma = d = 2 ring and two-array pair and
-    the sigma = 2, d = 3 ring."""
+    the sigma = 2, d = 3 and sigma = 4, d = 2 rings."""
+    if sigma == 4:
+        return d == 2 and iteration == "ring"
     if sigma != 2:
         return False
     return iteration in ("ring", "two_array") if d == 2 else (d == 3 and iteration == "ring")

@@ -244,27 +244,35 @@ int lcsb_certify_optimal(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
 int lcsb_certify_optimal_noalloc(int sigma, int d, int h, int dtype, const void *u,
                                  int exchange_symmetric, double *dev_out, void *stream);
 
-/* Branch-mean tables (sigma = d = 2, ring or two-array iteration on folded
- * tables, l >= 3; eq. (3) and Algorithm 1:
- * a branch that moves string 1 reads the mean of 2 entries that differ in
- * the appended symbol, the all-match tuple the mean of the 4 entries of an
- * aligned group).  For a stored group prefix P < n/8 (entries 4P .. 4P+3):
+/* Branch-mean tables (folded tables, l >= 3: sigma = d = 2, ring or
+ * two-array iteration; sigma = 2, d = 3 and sigma = 4, d = 2, rings.  Eq. (3)
+ * and Algorithm 1: a branch that advances some strings reads the mean of the
+ * entries that differ in those strings' appended symbols).  sigma = d = 2,
+ * for a stored group prefix P < n/8 (entries 4P .. 4P+3):
  *   Ma[2P + b] = (T[4P + b] + T[4P + 2 + b]) * 1/2,
- *   Mab[P]     = ((T[4P] + T[4P+3]) + (T[4P+1] + T[4P+2])) * 1/4,
- * the means the entry-reading sweep forms (same operations, same order).  On
- * tables symmetric in the two strings (lcsb_swap_symmetric; the zero start)
- * a sweep then reads one mean per branch instead of its 2 or 4 entries (the
- * advance-b mean is Ma at the exchanged tuple; Mab is kept at the lower
- * prefix of each exchanged pair of groups): about 0.64 of the bytes per
- * sweep, with the same table bit for bit.  Each sweep writes its table's
- * means and, on the last d sweeps of an lcsb_iterate call, its entries, so
- * every lag a caller or a certificate sees is complete; the two-array rate
- * reads the new table's values at its 4096 sample coordinates, which are
- * computed from the same means with the sweep's operations.  Other tables
- * sweep from the entries.
+ *   Mab[P]     = ((T[4P] + T[4P+3]) + (T[4P+1] + T[4P+2])) * 1/4;
+ * sigma = 2, d = 3, for the aligned group of eight (appended bits s1 s2 s3):
+ *   M1 (over s1), M3 (over s3), M12 (over s1 s2), M23 (over s2 s3) and M123
+ *   (all eight, complement-paired tree);
+ * sigma = 4, for the aligned group of sixteen (member 4 a + b):
+ *   M4a[4P + b] = ((T[16P+b] + T[16P+4+b]) + (T[16P+8+b] + T[16P+12+b])) * 1/4,
+ *   M4ab[P]     = the sixteen members summed pair by pair ({ab, ba} grouped
+ *                 by a xor b, then {aa, ~a~a}) * 1/16;
+ * in each case the means the entry-reading sweep forms (same operations, same
+ * order).  On tables symmetric in the two strings (lcsb_swap_symmetric; the
+ * zero start) a sweep then reads one mean per branch instead of its entries
+ * (a mean over string 2's symbols is the one over string 1's at the
+ * exchanged tuple; means over both strings are kept at the lower prefix of
+ * each exchanged pair of groups), with the same table bit for bit.  Each
+ * sweep writes its table's means and, on the last d sweeps of an
+ * lcsb_iterate call, its entries, so every lag a caller or a certificate sees
+ * is complete; the two-array rate reads the new table's values at its 4096
+ * sample coordinates, which are computed from the same means with the
+ * sweep's operations.  Other tables sweep from the entries.
  *
- * lcsb_query_means: bytes of one mean buffer (Ma, then Mab, then the 4096
- * sample values, each 256-byte aligned; about 3/4 of a table buffer).
+ * lcsb_query_means: bytes of one mean buffer (the parts in the order above,
+ * then the 4096 sample values, each 256-byte aligned; about 3/4 of a table
+ * buffer for sigma = d = 2, 7/4 for d = 3, 5/16 for sigma = 4).
  * LCSB_EUNSUPPORTED for other shapes, packed tables and l < 3.  lcsb_bind_means (after lcsb_bind): nbuf = the ring's buffer count
  * of caller-owned device buffers, 256-byte aligned, distinct from the ring
  * buffers and the workspace, kept until unbound or the context is destroyed;

@@ -106,12 +106,13 @@ void clear_lazy(lcsb_ctx *c)
 }
 
 // Folded tables of l >= 3 symmetric in the two strings sweep from the
-// branch-mean tables once they are bound: sigma = d = 2 (ring or two arrays)
-// and sigma = 2, d = 3 (ring)
+// branch-mean tables once they are bound: sigma = d = 2 (ring or two arrays),
+// sigma = 2, d = 3 and sigma = 4, d = 2 (rings)
 bool means_shape(const lcsb_ctx *c)
 {
-    if (c->packed || c->g.sigma != 2 || c->g.h < 3) return false;
-    return c->g.d == 2 || (c->g.d == 3 && !c->two_array);
+    if (c->packed || c->g.h < 3) return false;
+    if (c->g.sigma == 4) return c->g.d == 2 && !c->two_array;
+    return c->g.sigma == 2 && (c->g.d == 2 || (c->g.d == 3 && !c->two_array));
 }
 bool means_path(const lcsb_ctx *c) { return c->means_buf[0] && c->swap_sym && means_shape(c); }
 
@@ -120,13 +121,16 @@ uint64_t round256(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
 uint64_t means_layout(const lcsb_ctx *c, uint64_t *off)
 {
     const uint64_t es = elem_size(c->dtype), ns = c->g.ns;
-    // entries per part: d = 2 Ma ns/2, Mab ns/4; d = 3 M1, M3 ns/2, M12, M23 ns/4, M123 ns/8
-    const uint64_t d2[2] = {ns / 2, ns / 4}, d3[5] = {ns / 2, ns / 2, ns / 4, ns / 4, ns / 8};
+    // entries per part: d = 2 Ma ns/2, Mab ns/4; d = 3 M1, M3 ns/2, M12, M23
+    // ns/4, M123 ns/8; sigma = 4 M4a ns/4, M4ab ns/16
+    const uint64_t d2[2] = {ns / 2, ns / 4}, d3[5] = {ns / 2, ns / 2, ns / 4, ns / 4, ns / 8},
+                   s4[2] = {ns / 4, ns / 16};
+    const uint64_t *cnt = c->g.sigma == 4 ? s4 : c->g.d == 2 ? d2 : d3;
     const int parts = c->g.d == 2 ? 2 : 5;
     uint64_t at = 0;
     for (int k = 0; k < parts; ++k) {
         off[k] = at;
-        at = round256(at + (c->g.d == 2 ? d2[k] : d3[k]) * es);
+        at = round256(at + cnt[k] * es);
     }
     off[parts] = at;  // the sample values
     return at + kRateSample * es;
@@ -390,7 +394,10 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
             if (c->means_ok[slot]) continue;
             if (!c->entries_ok[slot]) return fail(LCSB_ESTATE, "lag %d has neither entries nor means", j);
             hipError_t e =
-                c->g.d == 2
+                c->g.sigma == 4
+                    ? launch_derive_means4(c->g, c->dtype, c->buf[slot], c->lazy[slot],
+                                           slot_ma(c, slot), slot_mab(c, slot), c->stream)
+                : c->g.d == 2
                     ? launch_derive_means(c->g, c->dtype, c->buf[slot], c->lazy[slot],
                                           slot_ma(c, slot), slot_mab(c, slot), c->stream)
                     : launch_derive_means3(c->g, c->dtype, c->buf[slot], c->lazy[slot],
@@ -446,7 +453,8 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
             a.ma_new = slot_ma(c, a.snew);
             a.mab_new = slot_mab(c, a.snew);
             a.offsets = reinterpret_cast<double *>(c->ws + Ws::kOffsets);
-            hipError_t e = launch_sweep_means(c->g, c->dtype, a, c->stream);
+            hipError_t e = c->g.sigma == 4 ? launch_sweep_means4(c->g, c->dtype, a, c->stream)
+                                           : launch_sweep_means(c->g, c->dtype, a, c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
             if (c->two_array) {
                 // the rate of the next step from the new table's sample values

@@ -120,6 +120,26 @@ __host__ __device__ inline uint64_t m23_index(uint64_t s, uint64_t n)
 }
 __host__ __device__ inline uint64_t m123_index(uint64_t s, uint64_t n) { return d3_fold(s, n) >> 3; }
 
+// sigma = 4, d = 2 (slot = a: 2 bits high, b: 2 bits low; stored tuples have
+// string-1 head 0, n = 16^l).  For a stored group prefix P < n/64 (entries
+// 16P .. 16P+15, member u = 4 a_l + b_l):
+//   M4a[4P + b]  tree4 over a_l of members 4a + b      (advance a)
+//   M4ab[P]      the sixteen-member tree of the group    (advance both)
+// The advance-b mean (over b_l) is M4a at the exchanged tuple; M4ab is
+// exchange-symmetric and kept at the lower prefix of each exchanged pair.
+// An index whose string-1 head is m is read at its relabelling by m.
+__host__ __device__ inline uint64_t s4_fold(uint64_t s, uint64_t n)
+{
+    const uint64_t m = (s >> (63 - __builtin_clzll(n) - 2)) & 3;
+    return s ^ (m * ((n - 1) / 3));
+}
+__host__ __device__ inline uint64_t m4a_index(uint64_t s, uint64_t n)
+{
+    s = s4_fold(s, n);
+    return ((s >> 4) << 2) | (s & 3);
+}
+__host__ __device__ inline uint64_t m4ab_index(uint64_t s, uint64_t n) { return s4_fold(s, n) >> 4; }
+
 struct MeansLaunch {
     const void *ma1;   // Ma of lag 1
     const void *mab2;  // Mab of lag 2
@@ -154,6 +174,11 @@ struct Means3Launch {
     int shift;  // FP64: lags 2 and 3 read with their offset differences (two arrays)
 };
 hipError_t launch_sweep_means3(const Geometry &g, int dtype, const Means3Launch &a, hipStream_t s);
+// sigma = 4, d = 2 (m4a_index, m4ab_index): lag 1's M4a and lag 2's M4ab
+// read, the new table's written (MeansLaunch: ma = M4a, mab = M4ab)
+hipError_t launch_sweep_means4(const Geometry &g, int dtype, const MeansLaunch &a, hipStream_t s);
+hipError_t launch_derive_means4(const Geometry &g, int dtype, const void *table, int lazy, void *ma,
+                                void *mab, hipStream_t s);
 hipError_t launch_derive_means3(const Geometry &g, int dtype, const void *table, int lazy, void *m1,
                                 void *m3, void *m12, void *m23, void *m123, hipStream_t s);
 

@@ -663,6 +663,181 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
     }
 }
 
+// ---------------------------------------------------------------- sigma = 4, d = 2 from branch means
+// The values of sweep_s4d2<T, true, SHIFT> from the lags' branch means
+// (m4a_index, m4ab_index): the thread's four advance-a means of lag 1 (M4a),
+// its four advance-b means (M4a at the exchanged tuples) and its all-advance
+// mean of lag 2 (M4ab at the lower prefix of its exchanged pair) instead of
+// 16 + 16 + 16 entries; each mean is the entry sweep's own (tree4 over the
+// appended symbol, which relabelling and exchange only permute by xor; the
+// sixteen-member tree, invariant under the twin permutations).
+//
+// The sixteen threads of a hexadecet (t = 16J + w) hold every member of
+// sixteen aligned groups (heads (0, b1), images m: member u = w xor 5m), and
+// exchange values by lane shuffles: the advance-a mean over a_l pairs lanes
+// at distance 4, then 8; the exchanged hexadecet's advance-a means (this
+// one's advance-b means) at 1, then 2; the sixteen-member tree
+// (((1 4)(11 14))((2 8)(7 13)))(((3 12)(6 9))((0 15)(5 10))) at 5, 10 or 15,
+// then 10 or 5, then 3, then 2, so that member 1's lane ends with the whole
+// tree in the entry sweep's order.  Hexadecets are exchange-folded whole.
+template <typename I>
+struct S4Idx {
+    I mask, rep, A, B;
+    int hs;  // the string-1 head's shift
+    __device__ S4Idx(uint64_t n, int h)
+        : mask((I)(n - 1)), rep((I)((n - 1) / 3)), A((I)(kAlt4Hi & (n - 1))),
+          B((I)(~kAlt4Hi & (n - 1))), hs(4 * h - 2)
+    {
+    }
+    __device__ __forceinline__ I fold(I s) const { return s ^ (((s >> hs) & 3) * rep); }
+    __device__ __forceinline__ I exch(I x) const { return ((x & A) >> 2) | ((x & B) << 2); }
+    __device__ __forceinline__ I twin(I j) const { return fold(exch(j)); }
+    __device__ __forceinline__ I ma(I s) const { s = fold(s); return ((s >> 4) << 2) | (s & 3); }
+    __device__ __forceinline__ I mab(I s) const { return fold(s) >> 4; }
+};
+
+template <typename T, bool SHIFT, typename I>
+__global__ __launch_bounds__(kBlock) void sweep_s4d2_means(const T *__restrict__ ma1,
+                                                          const T *__restrict__ mab2,
+                                                          T *__restrict__ out,
+                                                          T *__restrict__ na,
+                                                          T *__restrict__ nab, uint64_t n, int h,
+                                                          double *__restrict__ off, int s1,
+                                                          int s2, int snew)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kShift = kF32 || SHIFT;
+    const uint64_t t64 = thread_index();
+    const int top = 4 * (h - 1);
+    T d2 = 0, y0 = 0;
+    if constexpr (!kF32 && SHIFT) d2 = off[s2] - off[s1];
+    if constexpr (kF32) {
+        const double o1 = off[s1];
+        d2 = (float)(off[s2] - o1);
+        y0 = 1.0f + first(mab2[0] + d2);
+        if (t64 == 0) off[snew] = o1 + (double)y0;
+    }
+    if (t64 >= (n >> 6)) return;
+    const S4Idx<I> ix(n, h);
+    const I t = (I)t64, rep = (I)(((n >> 4) - 1) / 3), repJ = (I)(((n >> 8) - 1) / 3);
+    const I J = t >> 4;
+    const int w = (int)(t & 15);
+    const I sx = (t >> (top - 4)) & 3;  // string-2 symbol at position 2 (string 1's is 0)
+    const I pJ = (ix.exch(t & ~(I)15) ^ (sx * rep)) >> 4;
+    if (pJ < J) return;
+    const bool self = pJ == J;
+
+    // reads: the all-advance mean of t's group, the advance-a means of
+    // (0, v)|t, the advance-b means of the images
+    T both;
+    {
+        const I tw = ix.mab(ix.twin(16 * t));
+        both = mab2[tw < t ? tw : t];
+        if constexpr (kShift) both = both + d2;
+    }
+    const T match = (T)1 + first(both);
+    T ma[4], mb[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const I i = ((I)v << top) | t, sa = ((i << 4) & ix.A) | (i & ix.B);
+        ma[v] = ma1[ix.ma(sa)];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const I x = t ^ ((I)m * rep), sb = (x & ix.A) | ((x << 4) & ix.B);
+        mb[m] = ma1[ix.ma(ix.twin(sb))];
+    }
+    T val[4][4];  // [m][b1]
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        val[m][0] = match;
+#pragma unroll
+        for (int b1 = 1; b1 < 4; ++b1) {
+            T best = first(mb[m]);  // z = 0
+#pragma unroll
+            for (int z = 1; z < 4; ++z) best = vmax(best, z == b1 ? ma[b1 ^ m] : both);
+            val[m][b1] = best;
+        }
+    }
+    if constexpr (kF32) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int b1 = 0; b1 < 4; ++b1) val[m][b1] = (T)(val[m][b1] - y0);
+    }
+    if (out) {  // entries at the lower index of each exchanged pair, as sweep_s4d2
+        const I p = ix.exch(t) ^ (sx * rep);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const I x = t ^ ((I)m * rep);
+#pragma unroll
+            for (int b1 = 0; b1 < 4; ++b1) {
+                const I xt = p ^ (((I)m ^ (I)b1 ^ sx) * rep);
+                put(out + (((I)b1 << top) | (xt < x ? xt : x)), val[m][b1]);
+            }
+        }
+    }
+
+    // means: group (b1, m) has prefix P = (0, b1)|(J xor m rep) and this
+    // lane's member u = w xor 5m
+    const T quarter = (T)0.25, sixteenth = (T)0.0625;
+#pragma unroll
+    for (int b1 = 0; b1 < 4; ++b1) {
+        T v0 = 0, s5 = 0, s10 = 0, s15 = 0, p1 = 0, p8 = 0, q1 = 0, q2 = 0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (b1 != 0 || m == 0) {  // the all-match groups of the images hold the same lane values
+                v0 = val[m][b1];
+                s5 = __shfl_xor(v0, 5);
+                s10 = __shfl_xor(v0, 10);
+                s15 = __shfl_xor(v0, 15);
+                p1 = v0 + __shfl_xor(v0, 4);
+                p8 = __shfl_xor(p1, 8);
+                q1 = v0 + __shfl_xor(v0, 1);
+                q2 = __shfl_xor(q1, 2);
+            }
+            const int u = w ^ (5 * m);
+            const I P = ((I)b1 << (top - 4)) | (J ^ ((I)m * repJ));
+            const I tw = ix.twin(16 * P + (I)u);
+            const bool g5 = u == 1 || u == 4 || u == 11 || u == 14;
+            const bool g10 = u == 2 || u == 8 || u == 7 || u == 13;
+            const T L1 = v0 + (g5 ? s5 : g10 ? s10 : s15);
+            const T a10 = __shfl_xor(L1, 10), a5 = __shfl_xor(L1, 5);
+            const T L2 = L1 + (g5 ? a10 : a5);
+            const T L3 = L2 + __shfl_xor(L2, 3);
+            const T L4 = L3 + __shfl_xor(L3, 2);
+            if (!(u & 12)) put(na + (4 * P + (I)(u & 3)), (p1 + p8) * quarter);
+            if (u == 1) {
+                const I at = ix.mab(tw);
+                put(nab + (at < P ? at : P), L4 * sixteenth);
+            }
+            if (!self && !(u & 3)) put(na + ix.ma(tw), (q1 + q2) * quarter);
+        }
+    }
+}
+
+// M4a and M4ab of a stored table, one thread per group prefix P < n/64
+template <typename T>
+__global__ __launch_bounds__(kBlock) void derive_means4(const T *__restrict__ tab, int lazy,
+                                                       T *__restrict__ ma, T *__restrict__ mab,
+                                                       uint64_t n)
+{
+    const uint64_t P = thread_index();
+    if (P >= (n >> 6)) return;
+    T e[16];
+    if (lazy) {
+        const Twin16 tw = twin_group16(16 * P, n);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) e[v] = tab[member16(16 * P, tw, v)];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k += 4) load4(tab + 16 * P + k, e + k);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) ma[4 * P + b] = tree4(e[b], e[4 + b], e[8 + b], e[12 + b]) * (T)0.25;
+    mab[P] = tree16(e) * (T)0.0625;
+}
+
 // ---------------------------------------------------------------- sigma = 2, d = 3
 // Slot = (s1, s2, s3) bits; stored heads 000 (all-match), 001, 010, 011.
 // Each mismatched tuple has one branch moving the single string whose head
@@ -1392,6 +1567,45 @@ hipError_t launch_derive_means3(const Geometry &g, int dtype, const void *table,
             static_cast<const double *>(table), lazy, static_cast<double *>(m1),
             static_cast<double *>(m3), static_cast<double *>(m12), static_cast<double *>(m23),
             static_cast<double *>(m123), g.n);
+    return hipGetLastError();
+}
+
+template <typename T, bool SHIFT, typename I>
+hipError_t means4_typed(const Geometry &g, const MeansLaunch &a, hipStream_t s)
+{
+    sweep_s4d2_means<T, SHIFT, I><<<sweep_grid(g.n >> 6), dim3(kBlock), 0, s>>>(
+        static_cast<const T *>(a.ma1), static_cast<const T *>(a.mab2), static_cast<T *>(a.out),
+        static_cast<T *>(a.ma_new), static_cast<T *>(a.mab_new), g.n, g.h, a.offsets, a.s1, a.s2,
+        a.snew);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_means4(const Geometry &g, int dtype, const MeansLaunch &a, hipStream_t s)
+{
+    if (g.sigma != 4 || g.d != 2 || g.h < 3) return hipErrorInvalidValue;
+    if (g.n <= (1ull << 32)) {  // every index in 32 bits
+        if (dtype == LCSB_F32) return means4_typed<float, false, uint32_t>(g, a, s);
+        return a.shift ? means4_typed<double, true, uint32_t>(g, a, s)
+                       : means4_typed<double, false, uint32_t>(g, a, s);
+    }
+    if (dtype == LCSB_F32) return means4_typed<float, false, uint64_t>(g, a, s);
+    return a.shift ? means4_typed<double, true, uint64_t>(g, a, s)
+                   : means4_typed<double, false, uint64_t>(g, a, s);
+}
+
+hipError_t launch_derive_means4(const Geometry &g, int dtype, const void *table, int lazy, void *ma,
+                                void *mab, hipStream_t s)
+{
+    if (g.sigma != 4 || g.d != 2 || g.h < 3) return hipErrorInvalidValue;
+    const dim3 grid = sweep_grid(g.n >> 6);
+    if (dtype == LCSB_F32)
+        derive_means4<float><<<grid, dim3(kBlock), 0, s>>>(static_cast<const float *>(table), lazy,
+                                                           static_cast<float *>(ma),
+                                                           static_cast<float *>(mab), g.n);
+    else
+        derive_means4<double><<<grid, dim3(kBlock), 0, s>>>(static_cast<const double *>(table),
+                                                            lazy, static_cast<double *>(ma),
+                                                            static_cast<double *>(mab), g.n);
     return hipGetLastError();
 }
 

@@ -469,8 +469,168 @@ static void means3(int h, uint64_t count = 0)
     EXPECT(miss == 0, "d=3 h=%d: %llu folded means read but never written", h, (unsigned long long)miss);
 }
 
+// Branch-mean tables for sigma = 4 (m4a_index, m4ab_index): on a table that
+// gives every orbit of the relabellings and the exchange one pseudo-random
+// integer (an all-match tuple one for its tail's orbit), emulate the
+// sixteen lanes of a hexadecet (lane w of hexadecet J holds tail t = 16J + w
+// and its images t xor m rep; group (b1, m) has member u = w xor 5m in lane
+// w): the advance-a means (tree4 over a_l, partners at lane distances 4 and
+// 8), the exchanged hexadecet's advance-a means from this one's advance-b
+// means (distances 1 and 2), and the sixteen-member tree in four levels of
+// lane pairs (distances 5, 10 or 15; 10 or 5; 3; 2) equal their
+// definitions; reads find the entry sweep's means; every index read is
+// written.
+static uint64_t relabel4(uint64_t s, uint64_t n, uint64_t m) { return s ^ (m * ((n - 1) / 3)); }
+
+static double orbit_value4(uint64_t s, uint64_t n)
+{
+    const int h = __builtin_ctzll(n) / 4;
+    const uint64_t head = s >> (4 * (h - 1));
+    const bool match = (head >> 2) == (head & 3);
+    uint64_t m = n;
+    if (match) {
+        s &= (n >> 4) - 1;
+        m = n >> 4;
+    }
+    uint64_t r = ~0ull;
+    for (int e = 0; e < 2; ++e) {
+        const uint64_t x = e ? exchange4(s, m) : s;
+        for (uint64_t k = 0; k < 4; ++k) {
+            const uint64_t y = relabel4(x, m, k);
+            r = y < r ? y : r;
+        }
+    }
+    if (match) r |= 1ull << 62;
+    uint64_t z = (r + 0x9E3779B97F4A7C15ull) * 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 29;
+    return (double)(z & 0xFFFF);
+}
+
+static void means4(int h, uint64_t count = 0)
+{
+    const uint64_t n = 1ull << (4 * h), nt = n >> 4;  // tails
+    const int top = 4 * (h - 1);
+    const uint64_t rep = (nt - 1) / 3, am = 0xCCCCCCCCCCCCCCCCull & (n - 1), bm = ~am & (n - 1);
+    auto T = [&](uint64_t s) { return orbit_value4(s, n); };
+    auto tree4 = [](double a, double b, double c, double d) { return ((a + b) + (c + d)) * 0.25; };
+    auto tree16 = [&](const double *g) {
+        return ((((g[1] + g[4]) + (g[11] + g[14])) + ((g[2] + g[8]) + (g[7] + g[13]))) +
+                (((g[3] + g[12]) + (g[6] + g[9])) + ((g[0] + g[15]) + (g[5] + g[10])))) * 0.0625;
+    };
+    auto ma_def = [&](uint64_t k) {
+        const uint64_t g = 16 * (k >> 2) + (k & 3);
+        return tree4(T(g), T(g + 4), T(g + 8), T(g + 12));
+    };
+    auto mab_def = [&](uint64_t P) {
+        double g[16];
+        for (int u = 0; u < 16; ++u) g[u] = T(16 * P + (uint64_t)u);
+        return tree16(g);
+    };
+    auto lower = [](uint64_t a, uint64_t b) { return a < b ? a : b; };
+    const uint64_t hexes = n >> 10;  // J < n/1024: tails with a_2 = 0, in sixteens
+    std::vector<char> wa(count ? 0 : n / 16), wab(count ? 0 : n / 64);
+    std::vector<uint64_t> need_ab;
+    const uint64_t visits = count ? count + 2 : hexes;
+    for (uint64_t k = 0; k < visits; ++k) {
+        const uint64_t J = !count ? k : k == count ? 0 : k == count + 1 ? hexes - 1
+                                                   : (k * 0x9E3779B97F4A7C15ull) % hexes;
+        const uint64_t t0 = 16 * J;
+        const uint64_t sx0 = (t0 >> (top - 4)) & 3;
+        const uint64_t pJ = (exchange4(t0, nt) ^ (sx0 * rep)) >> 4;
+        if (pJ < J) continue;
+        const bool self = pJ == J;
+        double lv[16][4][4];  // [lane w][m][b1]
+        for (int w = 0; w < 16; ++w) {
+            const uint64_t t = t0 + (uint64_t)w;
+            // reads
+            {
+                const uint64_t tw = m4ab_index(exchange_twin4(16 * t, n), n), at = lower(t, tw);
+                EXPECT(at < n / 64, "s4 h=%d: all-advance read out of range", h);
+                EXPECT(mab_def(at) == mab_def(t), "s4 h=%d t=%llu: all-advance mean", h, (unsigned long long)t);
+                if (!count) need_ab.push_back(at);
+            }
+            for (int v = 0; v < 4; ++v) {
+                const uint64_t i = ((uint64_t)v << top) | t, sa = ((i << 4) & am) | (i & bm);
+                const uint64_t ia = m4a_index(sa, n);
+                EXPECT(ia < n / 16, "s4 h=%d: advance-a read out of range", h);
+                EXPECT(ma_def(ia) == tree4(T(sa), T(sa + 4), T(sa + 8), T(sa + 12)),
+                       "s4 h=%d i=%llu: advance-a mean", h, (unsigned long long)i);
+            }
+            for (uint64_t m = 0; m < 4; ++m) {
+                const uint64_t x = t ^ (m * rep), sb = (x & am) | ((x << 4) & bm);
+                const uint64_t ib = m4a_index(exchange_twin4(sb, n), n);
+                EXPECT(ib < n / 16, "s4 h=%d: advance-b read out of range", h);
+                EXPECT(ma_def(ib) == tree4(T(sb), T(sb + 1), T(sb + 2), T(sb + 3)),
+                       "s4 h=%d x=%llu: advance-b mean", h, (unsigned long long)x);
+                for (int b1 = 0; b1 < 4; ++b1) lv[w][m][b1] = T(((uint64_t)b1 << top) | x);
+            }
+        }
+        // writes, as the lanes form them
+        for (int b1 = 0; b1 < 4; ++b1)
+            for (uint64_t m = 0; m < 4; ++m) {
+                const uint64_t P = ((uint64_t)b1 << (top - 4)) | (J ^ (m * ((nt >> 4) - 1) / 3));
+                double val[16];  // by lane
+                for (int w = 0; w < 16; ++w) val[w] = lv[w][m][b1];
+                for (int w = 0; w < 16; ++w) {
+                    const int u = w ^ (int)(5 * m);
+                    EXPECT(T(16 * P + (uint64_t)u) == val[w], "s4 h=%d: group %llu member %d", h,
+                           (unsigned long long)P, u);
+                }
+                auto sh = [&](const double *a, int w, int d) { return a[w ^ d]; };
+                double L1[16], L2[16], L3[16], L4[16], p1[16];
+                for (int w = 0; w < 16; ++w) {
+                    const int u = w ^ (int)(5 * m);
+                    const int d1 = (u == 1 || u == 4 || u == 11 || u == 14) ? 5
+                                 : (u == 2 || u == 8 || u == 7 || u == 13) ? 10 : 15;
+                    L1[w] = val[w] + sh(val, w, d1);
+                    p1[w] = val[w] + sh(val, w, 4);
+                }
+                for (int w = 0; w < 16; ++w) {
+                    const int u = w ^ (int)(5 * m);
+                    const int d2 = (u == 1 || u == 4 || u == 11 || u == 14) ? 10 : 5;
+                    L2[w] = L1[w] + sh(L1, w, d2);
+                }
+                for (int w = 0; w < 16; ++w) L3[w] = L2[w] + sh(L2, w, 3);
+                for (int w = 0; w < 16; ++w) L4[w] = L3[w] + sh(L3, w, 2);
+                for (int w = 0; w < 16; ++w) {
+                    const int u = w ^ (int)(5 * m);
+                    const uint64_t tw = exchange_twin4(16 * P + (uint64_t)u, n);
+                    if (!(u & 12)) {  // own advance-a mean
+                        const uint64_t idx = 4 * P + (uint64_t)(u & 3);
+                        const double a = (p1[w] + sh(p1, w, 8)) * 0.25;
+                        EXPECT(idx < n / 16 && a == ma_def(idx), "s4 h=%d P=%llu: M4a", h, (unsigned long long)P);
+                        if (!count) wa[idx] = 1;
+                    }
+                    if (u == 1) {
+                        const uint64_t at = lower(P, m4ab_index(tw, n));
+                        const double a = L4[w] * 0.0625;
+                        EXPECT(at < n / 64 && a == mab_def(at), "s4 h=%d P=%llu: M4ab", h, (unsigned long long)P);
+                        if (!count) wab[at] = 1;
+                    }
+                    if (!self && !(u & 3)) {  // the exchanged hexadecet's advance-a mean
+                        const double q1 = val[w] + sh(val, w, 1), q2 = sh(val, w, 2) + sh(val, w, 3);
+                        const double b = (q1 + q2) * 0.25;
+                        const uint64_t idx = m4a_index(tw, n);
+                        EXPECT(idx < n / 16 && b == ma_def(idx), "s4 h=%d P=%llu: twin M4a", h,
+                               (unsigned long long)P);
+                        if (!count) wa[idx] = 1;
+                    }
+                }
+            }
+    }
+    if (count) return;
+    uint64_t miss = 0;
+    for (char f : wa) miss += !f;
+    EXPECT(miss == 0, "s4 h=%d: %llu advance-a means never written", h, (unsigned long long)miss);
+    miss = 0;
+    for (uint64_t P : need_ab) miss += !wab[P];
+    EXPECT(miss == 0, "s4 h=%d: %llu all-advance means read but never written", h, (unsigned long long)miss);
+}
+
 int main()
 {
+    for (int h = 3; h <= 4; ++h) means4(h);
+    for (int h = 5; h <= 8; ++h) means4(h, 1u << 10);
     for (int h = 3; h <= 6; ++h) means3(h);
     for (int h = 7; h <= 12; ++h) means3(h, 1u << 12);
     for (int h = 3; h <= 10; ++h) means(h);

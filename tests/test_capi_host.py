@@ -101,11 +101,12 @@ def test_branch_mean_buffers_are_checked_without_a_gpu(lib):
     """lcsb_query_means / lcsb_bind_means: sizes for sigma = d = 2 folded
     tables (Ma, n/4 entries, then Mab, n/8, then the 4096 sample values of the
     two-array rate, each at a 256-byte boundary) and for the sigma = 2, d = 3
-    ring, refusals for other shapes and iterations, packed tables and l < 3,
+    and sigma = 4, d = 2 rings, refusals for other shapes and iterations,
+    packed tables and l < 3,
     and pointer checks before anything is stored (no buffer is dereferenced)."""
     from paper_2407_10925_amd import _capi
     mb = C.c_uint64()
-    for (sigma, d, h, it) in ((2, 3, 5, 1), (4, 2, 4, 0), (2, 2, 2, 0), (2, 3, 2, 0), (2, 2, 5, 2)):
+    for (sigma, d, h, it) in ((2, 3, 5, 1), (4, 2, 4, 1), (4, 2, 2, 0), (2, 2, 2, 0), (2, 3, 2, 0), (2, 2, 5, 2)):
         ctx = C.c_void_p()
         assert lib.lcsb_create_iter(sigma, d, h, 0, it, C.byref(ctx)) == 0
         assert lib.lcsb_query_means(ctx, C.byref(mb)) == _capi.LCSB_EUNSUPPORTED, (sigma, d, h, it)
@@ -142,6 +143,16 @@ def test_branch_mean_buffers_are_checked_without_a_gpu(lib):
         assert lib.lcsb_query_means(ctx, C.byref(mb)) == 0
         n, at = 8 ** 4, 0
         for part in (n // 4, n // 4, n // 8, n // 8, n // 16):
+            at = (at + part * elem + 255) // 256 * 256
+        assert mb.value == at + 4096 * elem
+        assert lib.lcsb_destroy(ctx) == 0
+    # sigma = 4, d = 2 ring: M4a (n/16 entries), M4ab (n/64), the sample
+    for dtype, elem in ((0, 8), (1, 4)):
+        ctx = C.c_void_p()
+        assert lib.lcsb_create(4, 2, 3, dtype, C.byref(ctx)) == 0
+        assert lib.lcsb_query_means(ctx, C.byref(mb)) == 0
+        n, at = 16 ** 3, 0
+        for part in (n // 16, n // 64):
             at = (at + part * elem + 255) // 256 * 256
         assert mb.value == at + 4096 * elem
         assert lib.lcsb_destroy(ctx) == 0

@@ -35,9 +35,9 @@ def pk():
     return pk
 
 
-def _pair(pk, h, dtype, iteration="ring", d=2):
-    T = pk.Lcsb(2, d, h, dtype, iteration=iteration)
-    M = pk.Lcsb(2, d, h, dtype, iteration=iteration, means=True)
+def _pair(pk, h, dtype, iteration="ring", d=2, sigma=2):
+    T = pk.Lcsb(sigma, d, h, dtype, iteration=iteration)
+    M = pk.Lcsb(sigma, d, h, dtype, iteration=iteration, means=True)
     T.init_zero()
     M.init_zero()
     assert T.swap_symmetric() and M.swap_symmetric()
@@ -393,6 +393,97 @@ def test_d3_means_full_size(pk, dtype):
         M.iterate(chunk)
     _same_certs(T, M, "full size")
     for k in (1, 2, 3):
+        a, ao = T.lag(k)
+        b, bo = M.lag(k)
+        assert ao == bo
+        assert torch.equal(a, b), k
+    del T, M
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ sigma = 4, d = 2
+# M4a of lag 1 and M4ab of lag 2 (m4a_index, m4ab_index); sixteen lanes of a
+# hexadecet exchange values by shuffles.
+
+def _twin4(i, h):
+    """The exchanged tuple of stored index i: the two strings' symbols swapped
+    in every 4-bit slot, relabelled so that string 1's head is 0."""
+    n = 16 ** h
+    a = 0xCCCCCCCCCCCCCCCC & (n - 1)
+    b = 0x3333333333333333 & (n - 1)
+    x = ((i & a) >> 2) | ((i & b) << 2)
+    m = (x >> (4 * h - 2)) & 3
+    return x ^ (m * ((n - 1) // 3))
+
+
+@pytest.mark.parametrize("h", [3])
+def test_s4_means_trajectory_matches_the_oracle(pk, h):
+    say(f"sigma=4 means vs oracle: h={h}")
+    M = pk.Lcsb(4, 2, h, "f64", means=True)
+    M.init_zero()
+    N = 16 ** h
+    ring = [np.zeros(N)] * 2
+    done = 0
+    for chunk in (1, 1, 2, 3, 5, 8, 20):
+        for _ in range(chunk):
+            ring = [oracle.sweep(4, 2, h, ring), ring[0]]
+        M.iterate(chunk)
+        done += chunk
+        for k in (1, 2):
+            assert np.array_equal(M.read_table(k), ring[k - 1][: N // 4]), (done, k)
+
+
+@pytest.mark.parametrize("h", [3, 4, 5, 7])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_s4_means_ring_matches_the_entry_ring(pk, h, dtype):
+    say(f"sigma=4 means vs entries: h={h} {dtype}")
+    T, M = _pair(pk, h, dtype, sigma=4)
+    done = 0
+    for chunk in (1, 2, 7, 40, 0, 1):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        done += chunk
+        _same_tables_host(T, M, f"after {done}")
+        _same_certs(T, M, f"after {done}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_s4_means_writes_through_lag(pk, dtype):
+    h = 4
+    say(f"sigma=4 means after writes through lcsb_lag: {dtype}")
+    T, M = _pair(pk, h, dtype, sigma=4)
+    T.iterate(7)
+    M.iterate(7)
+    for k, i in ((1, 0x2a5b), (2, 0x1c3d)):  # stored indices (below n/4 = 16384)
+        e = _twin4(i, h)
+        assert e < 16 ** h // 4
+        for L in (T, M):
+            t, _ = L.lag(k)
+            t[i] = t[i] + 0.375
+            if e != i:
+                t[e] = t[e] + 0.375
+        torch.cuda.synchronize()
+    assert T.swap_symmetric() and M.swap_symmetric()
+    for chunk in (1, 5):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        _same_tables_host(T, M, f"planted, +{chunk}")
+        _same_certs(T, M, f"planted, +{chunk}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_s4_means_full_size(pk, dtype):
+    """The benchmark's (4, 2, 8), 2^30 stored entries (32-bit indices at the
+    2^32 limit): whole lags on the device and both certificates after sweeps
+    that cross an lcsb_iterate call."""
+    say(f"sigma=4 means full size: h=8 {dtype}")
+    torch.cuda.empty_cache()
+    T, M = _pair(pk, 8, dtype, sigma=4)
+    for chunk in (4, 20):
+        T.iterate(chunk)
+        M.iterate(chunk)
+    _same_certs(T, M, "full size")
+    for k in (1, 2):
         a, ao = T.lag(k)
         b, bo = M.lag(k)
         assert ao == bo

@@ -90,6 +90,18 @@ __device__ __forceinline__ T first(T v) { return v > -(T)INFINITY ? v : -(T)INFI
 template <typename T>
 __device__ __forceinline__ void put(T *p, T v) { __builtin_nontemporal_store(v, p); }
 
+// contiguous aligned stores, loads
+template <typename T>
+__device__ __forceinline__ void store4(T *p, const T *g)
+{
+    using V = T __attribute__((ext_vector_type(4)));
+    V v;
+    v.x = g[0];
+    v.y = g[1];
+    v.z = g[2];
+    v.w = g[3];
+    *reinterpret_cast<V *>(p) = v;
+}
 // contiguous aligned loads
 __device__ __forceinline__ void load2(const double *p, double &a, double &b)
 {
@@ -673,13 +685,11 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2(const T *__restrict__ lag1,
 // sixteen-member tree, invariant under the twin permutations).
 //
 // The sixteen threads of a hexadecet (t = 16J + w) hold every member of
-// sixteen aligned groups (heads (0, b1), images m: member u = w xor 5m), and
-// exchange values by lane shuffles: the advance-a mean over a_l pairs lanes
-// at distance 4, then 8; the exchanged hexadecet's advance-a means (this
-// one's advance-b means) at 1, then 2; the sixteen-member tree
-// (((1 4)(11 14))((2 8)(7 13)))(((3 12)(6 9))((0 15)(5 10))) at 5, 10 or 15,
-// then 10 or 5, then 3, then 2, so that member 1's lane ends with the whole
-// tree in the entry sweep's order.  Hexadecets are exchange-folded whole.
+// sixteen aligned groups (heads (0, b1), images m: member u = w xor 5m); a
+// pass through LDS gives each lane one whole group, whose four advance-a
+// means, four advance-a means of the exchanged group (this one's advance-b
+// means) and sixteen-member tree it forms in registers.  Hexadecets are
+// exchange-folded whole: the lower of a hexadecet and its exchanged one runs.
 template <typename I>
 struct S4Idx {
     I mask, rep, A, B;
@@ -717,6 +727,8 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2_means(const T *__restrict__
         y0 = 1.0f + first(mab2[0] + d2);
         if (t64 == 0) off[snew] = o1 + (double)y0;
     }
+    constexpr int kStride = 17, kHex = 16 * kStride;
+    __shared__ T lds[(kBlock / 16) * kHex];
     if (t64 >= (n >> 6)) return;
     const S4Idx<I> ix(n, h);
     const I t = (I)t64, rep = (I)(((n >> 4) - 1) / 3), repJ = (I)(((n >> 8) - 1) / 3);
@@ -778,41 +790,50 @@ __global__ __launch_bounds__(kBlock) void sweep_s4d2_means(const T *__restrict__
         }
     }
 
-    // means: group (b1, m) has prefix P = (0, b1)|(J xor m rep) and this
-    // lane's member u = w xor 5m
-    const T quarter = (T)0.25, sixteenth = (T)0.0625;
+    // means: the hexadecet's sixteen groups (b1, m), prefix P = (0, b1)|(J xor
+    // m rep), lane w holding member u = w xor 5m of each, pass through LDS
+    // (members padded to 17 values: the writes of one group and the reads of
+    // one member across the groups fall in distinct banks) so that lane w
+    // holds every member of group (w >> 2, w & 3); the hexadecet lies in one
+    // wave, which orders its own LDS accesses
+    T *hx = lds + (threadIdx.x >> 4) * kHex;
 #pragma unroll
-    for (int b1 = 0; b1 < 4; ++b1) {
-        T v0 = 0, s5 = 0, s10 = 0, s15 = 0, p1 = 0, p8 = 0, q1 = 0, q2 = 0;
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (b1 != 0 || m == 0) {  // the all-match groups of the images hold the same lane values
-                v0 = val[m][b1];
-                s5 = __shfl_xor(v0, 5);
-                s10 = __shfl_xor(v0, 10);
-                s15 = __shfl_xor(v0, 15);
-                p1 = v0 + __shfl_xor(v0, 4);
-                p8 = __shfl_xor(p1, 8);
-                q1 = v0 + __shfl_xor(v0, 1);
-                q2 = __shfl_xor(q1, 2);
-            }
-            const int u = w ^ (5 * m);
-            const I P = ((I)b1 << (top - 4)) | (J ^ ((I)m * repJ));
-            const I tw = ix.twin(16 * P + (I)u);
-            const bool g5 = u == 1 || u == 4 || u == 11 || u == 14;
-            const bool g10 = u == 2 || u == 8 || u == 7 || u == 13;
-            const T L1 = v0 + (g5 ? s5 : g10 ? s10 : s15);
-            const T a10 = __shfl_xor(L1, 10), a5 = __shfl_xor(L1, 5);
-            const T L2 = L1 + (g5 ? a10 : a5);
-            const T L3 = L2 + __shfl_xor(L2, 3);
-            const T L4 = L3 + __shfl_xor(L3, 2);
-            if (!(u & 12)) put(na + (4 * P + (I)(u & 3)), (p1 + p8) * quarter);
-            if (u == 1) {
-                const I at = ix.mab(tw);
-                put(nab + (at < P ? at : P), L4 * sixteenth);
-            }
-            if (!self && !(u & 3)) put(na + ix.ma(tw), (q1 + q2) * quarter);
-        }
+        for (int b1 = 0; b1 < 4; ++b1) hx[(4 * b1 + m) * kStride + (w ^ (5 * m))] = val[m][b1];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    T e[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) e[u] = hx[w * kStride + u];
+    const int gm = w & 3;
+    const I P = ((I)(w >> 2) << (top - 4)) | (J ^ ((I)gm * repJ));
+    const T quarter = (T)0.25;
+    T own[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) own[b] = tree4(e[b], e[4 + b], e[8 + b], e[12 + b]) * quarter;
+    store4(na + 4 * P, own);
+    const I tw = ix.twin(16 * P);  // member 0 of the exchanged group
+    {
+        const I at = ix.mab(tw);
+        nab[at < P ? at : P] = tree16(e) * (T)0.0625;
+    }
+    if (!self) {
+        // the exchanged group's advance-a means: member 4 c1 + c2 sits there
+        // at a = c2 xor m', b = c1 xor m' (m' its relabelling), so its mean
+        // for b is this group's mean over c2 at c1 = b xor m'
+        const I at = ix.ma(tw);
+        const int r = (int)(at & 3);
+        T q[4];
+#pragma unroll
+        for (int c1 = 0; c1 < 4; ++c1)
+            q[c1] = tree4(e[4 * c1], e[4 * c1 + 1], e[4 * c1 + 2], e[4 * c1 + 3]) * quarter;
+        const bool r1 = r & 1, r2 = r & 2;
+        const T a0 = r1 ? q[1] : q[0], a1 = r1 ? q[0] : q[1];
+        const T a2 = r1 ? q[3] : q[2], a3 = r1 ? q[2] : q[3];
+        T tv[4] = {r2 ? a2 : a0, r2 ? a3 : a1, r2 ? a0 : a2, r2 ? a1 : a3};
+        store4(na + (at & ~(I)3), tv);
     }
 }
 

@@ -649,6 +649,22 @@ CONFIGS = [  # (sigma, d, l, dtype)
 GENERALITY = [(4, 2, 8, "f32"), (2, 3, 10, "f32"), (4, 2, 8, "f64"), (2, 3, 10, "f64")]
 
 
+def designed_bytes(sigma, d, n, elem, means, folded, reps=64):
+    """HBM bytes per sweep that the kernel a configuration runs is designed to
+    move (values x elem).  Branch-mean sweeps: sigma = d = 2 reads Ma (n/4)
+    and Mab at the lower prefixes (n/16) and writes both; d = 3 reads 13/32 n
+    and writes 19/32 n; sigma = 4 reads M4a (n/16) and M4ab (n/128) and writes
+    both; each also writes its stored entries at one per exchanged pair on the
+    last d sweeps of a `reps`-sweep call.  Entry sweeps: the algorithmic bytes
+    times their designed re-read (lag 1 twice: 4/3 for d = 2; 1.625 for d = 3)."""
+    stored = n // (2 if sigma == 2 else 4)
+    lower = stored // 2 if folded else stored
+    if means:
+        vals = {(2, 2): 2 * 5 * n / 16, (2, 3): n, (4, 2): 2 * 9 * n / 128}[(sigma, d)]
+        return (vals + d / reps * lower) * elem
+    return (d + 1) * lower * elem * (1.625 if d == 3 else 4 / 3)
+
+
 def config_table(pk, configs=None, emit=True):
     """Average sweep and certificate time per configuration (HIP events; 64
     sweeps in one call, as a certificate period of the benchmark), with the
@@ -688,12 +704,19 @@ def config_table(pk, configs=None, emit=True):
         elem = 8 if dt == "f64" else 4
         folded = L.swap_symmetric()  # exchange-folded: every table at one entry per pair
         algo = (d + 1) * elem * L.stored // (2 if folded else 1)
+        kern = designed_bytes(sigma, d, L.n, elem, means, folded, reps)
+        # algorithmic: each lag read once and one table written (what an
+        # entry-reading sweep moves at least; a branch-mean sweep moves less,
+        # so its fraction can pass 1); designed: what the kernel that ran moves
         rows.append({"sigma": sigma, "d": d, "l": h, "dtype": dt, "entries": L.n,
                      "exchange_folded": folded, "branch_means": means,
                      "sweep_ms": round(sweep_ms, 4), "certificate_ms": round(cert_ms, 3),
                      "optimal_certificate_ms": round(opt_ms, 3),
                      "algorithmic_GBps": round(algo / sweep_ms / 1e6, 1),
                      "frac_of_peak": round(algo / sweep_ms / 1e6 / HBM_PEAK_GBS, 4),
+                     "designed_GB": round(kern / 1e9, 4),
+                     "designed_GBps": round(kern / sweep_ms / 1e6, 1),
+                     "designed_frac_of_peak": round(kern / sweep_ms / 1e6 / HBM_PEAK_GBS, 4),
                      "updates_per_s": L.n / sweep_ms * 1e3})
         log(json.dumps(rows[-1]))
         del L

@@ -490,3 +490,41 @@ def test_s4_means_full_size(pk, dtype):
         assert torch.equal(a, b), k
     del T, M
     torch.cuda.empty_cache()
+
+
+def test_s4_means_l9_fp32_matches_the_entry_ring_sampled(pk):
+    """sigma = 4, l = 9 FP32 (2^36 indices, 2^34 stored: the kernel's 64-bit
+    index arithmetic): the mean ring and the entry ring, run one after the
+    other (both do not fit together), agree on 2^20 sampled entries of lags 1
+    and 2, their offsets and both certificates after 6 sweeps (3 + 3, crossing
+    an lcsb_iterate call)."""
+    h = 9
+    need = 3 * 4 * (16 ** h // 4) + 3 * 4 * (16 ** h // 16 + 16 ** h // 64) + 4 * 2**30
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory")
+    say("sigma=4 means vs entries at l=9 FP32, sampled")
+    got = []
+    for means in (True, False):
+        L = pk.Lcsb(4, 2, h, "f32", means=means)
+        L.init_zero()
+        L.iterate(3)
+        L.iterate(3)
+        cf, _ = L.certify()
+        co, _ = L.certify_optimal()
+        idx = si.sample_indices(L.stored, 1 << 20, seed=19).to(L.device)
+        lags = []
+        for k in (1, 2):
+            t, off = L.lag(k)
+            lags.append((t[idx].cpu().numpy(), off))
+        got.append((lags, cf, co))
+        del L, t
+        torch.cuda.empty_cache()
+    (lm, cfm, com), (le, cfe, coe) = got
+    for (a, ao), (b, bo) in zip(lm, le):
+        assert ao == bo
+        assert np.array_equal(a, b)
+    for x, y in ((cfm, cfe), (com, coe)):
+        for f in CERT_FIELDS:
+            assert x[f] == y[f], (f, x[f], y[f])

@@ -528,3 +528,41 @@ def test_s4_means_l9_fp32_matches_the_entry_ring_sampled(pk):
     for x, y in ((cfm, cfe), (com, coe)):
         for f in CERT_FIELDS:
             assert x[f] == y[f], (f, x[f], y[f])
+
+
+def test_d3_means_l11_fp32_matches_the_entry_ring_sampled(pk):
+    """sigma = 2, d = 3, l = 11 FP32 (2^33 indices, 2^32 stored: the kernel's
+    64-bit index arithmetic): the mean ring and the entry ring, one after the
+    other, agree on 2^20 sampled entries of lags 1 to 3, their offsets and
+    both certificates after 7 sweeps (3 + 4, crossing an lcsb_iterate call)."""
+    h = 11
+    n = 8 ** h
+    need = 4 * 4 * (n // 2) + 4 * 4 * (n // 4 + n // 4 + n // 8 + n // 8 + n // 16) + 4 * 2**30
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory")
+    say("d=3 means vs entries at l=11 FP32, sampled")
+    got = []
+    for means in (True, False):
+        L = pk.Lcsb(2, 3, h, "f32", means=means)
+        L.init_zero()
+        L.iterate(3)
+        L.iterate(4)
+        cf, _ = L.certify()
+        co, _ = L.certify_optimal()
+        idx = si.sample_indices(L.stored, 1 << 20, seed=23).to(L.device)
+        lags = []
+        for k in (1, 2, 3):
+            t, off = L.lag(k)
+            lags.append((t[idx].cpu().numpy(), off))
+        got.append((lags, cf, co))
+        del L, t
+        torch.cuda.empty_cache()
+    (lm, cfm, com), (le, cfe, coe) = got
+    for (a, ao), (b, bo) in zip(lm, le):
+        assert ao == bo
+        assert np.array_equal(a, b)
+    for x, y in ((cfm, cfe), (com, coe)):
+        for f in CERT_FIELDS:
+            assert x[f] == y[f], (f, x[f], y[f])

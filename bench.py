@@ -253,20 +253,37 @@ def polish(P, S, best, target, certificate="feasible"):
 
 
 def uses_means(iteration, sigma, d):
-    """Branch-mean buffers serve the sigma = d = 2 ring and two-array pair and
-    the sigma = 2, d = 3 and sigma = 4, d = 2 rings."""
+    """Branch-mean buffers serve the d = 2 rings and two-array pairs (sigma = 2
+    or 4) and the sigma = 2, d = 3 ring."""
     if sigma == 4:
-        return d == 2 and iteration == "ring"
+        return d == 2 and iteration in ("ring", "two_array")
     if sigma != 2:
         return False
     return iteration in ("ring", "two_array") if d == 2 else (d == 3 and iteration == "ring")
+
+
+def new_ring(pk, sigma, d, h, dtype, iteration="ring", means=True, **kw):
+    """An Lcsb with branch-mean buffers where its shape takes them and they fit
+    beside its tables (`L.means` is then non-empty), else without them."""
+    import torch
+    if means and uses_means(iteration, sigma, d):
+        L = None
+        try:
+            L = pk.Lcsb(sigma, d, h, dtype, iteration=iteration, means=True, **kw)
+        except torch.cuda.OutOfMemoryError:
+            pass
+        if L is not None:
+            return L
+        gc.collect()  # the partial context, outside the handler
+        torch.cuda.empty_cache()
+    return pk.Lcsb(sigma, d, h, dtype, iteration=iteration, **kw)
 
 
 def plain_run(pk, h, target, iteration="ring", certificate="feasible", sigma=2, d=2):
     """FP64 from zero, a certificate every TTB_CADENCE sweeps, until the best
     bound reaches target (one lcsb_run, timed from the init call)."""
     import torch
-    P = pk.Lcsb(sigma, d, h, "f64", iteration=iteration, means=uses_means(iteration, sigma, d))
+    P = new_ring(pk, sigma, d, h, "f64", iteration)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P.init_zero()
@@ -286,10 +303,8 @@ def mixed_run(pk, h, target, iteration="ring", certificate="feasible", sigma=2, 
     """FP32 from zero to its error floor, then the FP64 polish to target, the
     FP32 tables inside the FP64 buffers (widened in place)."""
     import torch
-    means = uses_means(iteration, sigma, d)
-    P = pk.Lcsb(sigma, d, h, "f64", iteration=iteration, means=means)
-    M = pk.Lcsb(sigma, d, h, "f32", iteration=iteration,
-                bufs=[b.view(torch.float32) for b in P.bufs], means=means)
+    P = new_ring(pk, sigma, d, h, "f64", iteration)
+    M = new_ring(pk, sigma, d, h, "f32", iteration, bufs=[b.view(torch.float32) for b in P.bufs])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     M.init_zero()
@@ -673,16 +688,8 @@ def config_table(pk, configs=None, emit=True):
     import torch
     rows = []
     for sigma, d, h, dt in (CONFIGS if configs is None else configs):
-        means = uses_means("ring", sigma, d)
-        try:
-            L = pk.Lcsb(sigma, d, h, dt, means=means)
-        except torch.cuda.OutOfMemoryError:  # the means do not fit beside the ring
-            L = None
-        if L is None:  # (outside the handler, so the partial context can be freed)
-            gc.collect()
-            torch.cuda.empty_cache()
-            means = False
-            L = pk.Lcsb(sigma, d, h, dt)
+        L = new_ring(pk, sigma, d, h, dt)  # without means where they do not fit
+        means = bool(L.means)
         L.init_zero()
         L.iterate(8)
         stream = torch.cuda.current_stream()
@@ -731,7 +738,7 @@ def profile_only(pk, h, sweeps, sigma=2, d=2, dtype="f32", means=True):
     lcsb_iterate call (the sigma = d = 2 ring with its branch-mean buffers
     unless means is False)."""
     import torch
-    L = pk.Lcsb(sigma, d, h, dtype, means=means and uses_means("ring", sigma, d))
+    L = new_ring(pk, sigma, d, h, dtype, means=means)
     L.init_zero()
     L.iterate(sweeps)
     torch.cuda.synchronize()
@@ -799,9 +806,9 @@ def converge_only(pk, h, sigma=2, d=2, iteration="ring", certificate="feasible")
     the ring or the two-array iteration, with Algorithm 2's or the largest-r
     certificate."""
     import torch
-    P = pk.Lcsb(sigma, d, h, "f64", iteration=iteration)
+    P = new_ring(pk, sigma, d, h, "f64", iteration)
     log(f"plain FP64 {iteration} at sigma={sigma} d={d} l={h}: {P.n} indices, {P.stored} "
-        f"stored, {P.nbuf * 8 * P.stored / 2**30:.0f} GiB of tables")
+        f"stored, {P.nbuf * 8 * P.stored / 2**30:.0f} GiB of tables, branch means: {bool(P.means)}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     P.init_zero()
@@ -826,8 +833,7 @@ def converge_only(pk, h, sigma=2, d=2, iteration="ring", certificate="feasible")
     out["plain_f64"] = {"seconds_to_target": round(time.perf_counter() - t0, 3),
                         "sweeps_to_target": cur["sweep"], "certificates": certs}
     log(f"plain to B - 1e-9: {out['plain_f64']['seconds_to_target']:.2f} s, {cur['sweep']} sweeps")
-    M = pk.Lcsb(sigma, d, h, "f32", iteration=iteration,
-                bufs=[b.view(torch.float32) for b in P.bufs])
+    M = new_ring(pk, sigma, d, h, "f32", iteration, bufs=[b.view(torch.float32) for b in P.bufs])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     M.init_zero()
@@ -836,6 +842,7 @@ def converge_only(pk, h, sigma=2, d=2, iteration="ring", certificate="feasible")
     sweeps64, certs64, best = polish(P, M, best, target, certificate)
     torch.cuda.synchronize()
     t_mixed = time.perf_counter() - t0
+    out["branch_means"] = {"f64": bool(P.means), "f32": bool(M.means)}
     out["mixed_f32_polish"] = {"seconds_to_target": round(t_mixed, 3), "sweeps_f32": sweeps32,
                                "sweeps_f64": sweeps64, "certificates": certs32 + certs64,
                                "bound": best["bound"], "reached": best["bound"] >= target}
@@ -907,9 +914,9 @@ def two_array_f32_only(pk, h, max_sweeps, sigma=2, d=2):
     fits one GPU there).  Prints the best certified bound, rounded down at the
     6th decimal as the paper's tables print it, and the certificate trail."""
     import torch
-    L = pk.Lcsb(sigma, d, h, "f32", iteration="two_array")
+    L = new_ring(pk, sigma, d, h, "f32", "two_array")
     log(f"two-array FP32 at sigma={sigma} d={d} l={h}: {L.n} indices, {L.stored} stored, "
-        f"{2 * 4 * L.stored / 2**30:.0f} GiB")
+        f"{2 * 4 * L.stored / 2**30:.0f} GiB, branch means: {bool(L.means)}")
     trail = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()

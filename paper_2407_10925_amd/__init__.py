@@ -38,8 +38,8 @@ class Lcsb:
         ``iteration``: "ring" (Algorithm 2), "two_array" or "two_array_packed"
         (lcsb_create_iter; packed tables hold ``stored`` = packed_entries
         entries, one per exchange orbit).  ``means``: allocate and bind the
-        branch-mean buffers (lcsb_bind_means; folded tables of h >= 3: sigma = d = 2
-        ring or two arrays, sigma = 2, d = 3 and sigma = 4, d = 2 rings)."""
+        branch-mean buffers (lcsb_bind_means; folded tables of h >= 3: d = 2 rings
+        and two-array pairs, sigma = 2 or 4, and sigma = 2, d = 3 rings)."""
         import torch
 
         if dtype not in _DTYPES:

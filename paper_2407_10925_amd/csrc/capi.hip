@@ -106,12 +106,12 @@ void clear_lazy(lcsb_ctx *c)
 }
 
 // Folded tables of l >= 3 symmetric in the two strings sweep from the
-// branch-mean tables once they are bound: sigma = d = 2 (ring or two arrays),
-// sigma = 2, d = 3 and sigma = 4, d = 2 (rings)
+// branch-mean tables once they are bound: d = 2 (sigma = 2 or 4, ring or two
+// arrays) and sigma = 2, d = 3 (ring)
 bool means_shape(const lcsb_ctx *c)
 {
     if (c->packed || c->g.h < 3) return false;
-    if (c->g.sigma == 4) return c->g.d == 2 && !c->two_array;
+    if (c->g.sigma == 4) return c->g.d == 2;
     return c->g.sigma == 2 && (c->g.d == 2 || (c->g.d == 3 && !c->two_array));
 }
 bool means_path(const lcsb_ctx *c) { return c->means_buf[0] && c->swap_sym && means_shape(c); }

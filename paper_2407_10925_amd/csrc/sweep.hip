@@ -862,6 +862,59 @@ __global__ __launch_bounds__(kBlock) void derive_means4(const T *__restrict__ ta
     mab[P] = tree16(e) * (T)0.0625;
 }
 
+// The new table's values at the two-array rate's sample coordinates (each at
+// the lower index of its exchanged pair), in sample order: what
+// sweep_s4d2_means computes for that tuple (the thread owning tail x is
+// t = x with string 1's symbol at position 2 relabelled to 0, x its image m),
+// from the same means with the same operations.
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(kBlock) void means_samples4(const T *__restrict__ ma1,
+                                                        const T *__restrict__ mab2,
+                                                        T *__restrict__ smp, uint64_t n, int h,
+                                                        const double *__restrict__ off, int s1,
+                                                        int s2)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kShift = kF32 || SHIFT;
+    T d2 = 0, y0 = 0;
+    if constexpr (!kF32 && SHIFT) d2 = off[s2] - off[s1];
+    if constexpr (kF32) {
+        d2 = (float)(off[s2] - off[s1]);
+        y0 = 1.0f + first(mab2[0] + d2);
+    }
+    const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (uint64_t)kRateSample) return;
+    const int top = 4 * (h - 1);
+    uint64_t c = (i * kRateSampleMul) & ((n >> 2) - 1);
+    const uint64_t tw = exchange_twin4(c, n);
+    c = tw < c ? tw : c;
+    const int b1 = (int)((c >> top) & 3);
+    const uint64_t x = c & ((1ull << top) - 1), rep = ((n >> 4) - 1) / 3;
+    const int m = (int)((x >> (top - 2)) & 3);
+    const uint64_t t = x ^ ((uint64_t)m * rep);
+    T both;
+    {
+        const uint64_t at = m4ab_index(exchange_twin4(16 * t, n), n);
+        both = mab2[at < t ? at : t];
+        if constexpr (kShift) both = both + d2;
+    }
+    T v;
+    if (b1 == 0) {
+        v = (T)1 + first(both);
+    } else {
+        const uint64_t am = kAlt4Hi & (n - 1), bm = ~kAlt4Hi & (n - 1);
+        const uint64_t sb = (x & am) | ((x << 4) & bm);
+        const T mb = ma1[m4a_index(exchange_twin4(sb, n), n)];
+        const uint64_t iv = ((uint64_t)(b1 ^ m) << top) | t, sa = ((iv << 4) & am) | (iv & bm);
+        const T ma = ma1[m4a_index(sa, n)];
+        T best = first(mb);  // z = 0
+#pragma unroll
+        for (int z = 1; z < 4; ++z) best = vmax(best, z == b1 ? ma : both);
+        v = best;
+    }
+    smp[i] = kF32 ? (T)(v - y0) : v;
+}
+
 // ---------------------------------------------------------------- sigma = 2, d = 3
 // Slot = (s1, s2, s3) bits; stored heads 000 (all-match), 001, 010, 011.
 // Each mismatched tuple has one branch moving the single string whose head
@@ -1528,10 +1581,25 @@ hipError_t launch_sweep_means(const Geometry &g, int dtype, const MeansLaunch &a
     return means_dispatch(g, dtype, a, nullptr, s);
 }
 
+template <typename T, bool SHIFT>
+hipError_t samples4_typed(const Geometry &g, const MeansLaunch &a, void *samples, hipStream_t s)
+{
+    means_samples4<T, SHIFT><<<kRateSample / kBlock, dim3(kBlock), 0, s>>>(
+        static_cast<const T *>(a.ma1), static_cast<const T *>(a.mab2), static_cast<T *>(samples),
+        g.n, g.h, a.offsets, a.s1, a.s2);
+    return hipGetLastError();
+}
+
 hipError_t launch_means_samples(const Geometry &g, int dtype, const MeansLaunch &a, void *samples,
                                 hipStream_t s)
 {
     if (!samples) return hipErrorInvalidValue;
+    if (g.sigma == 4) {
+        if (g.d != 2 || g.h < 3) return hipErrorInvalidValue;
+        if (dtype == LCSB_F32) return samples4_typed<float, false>(g, a, samples, s);
+        return a.shift ? samples4_typed<double, true>(g, a, samples, s)
+                       : samples4_typed<double, false>(g, a, samples, s);
+    }
     return means_dispatch(g, dtype, a, samples, s);
 }
 

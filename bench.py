@@ -253,13 +253,11 @@ def polish(P, S, best, target, certificate="feasible"):
 
 
 def uses_means(iteration, sigma, d):
-    """Branch-mean buffers serve the d = 2 rings and two-array pairs (sigma = 2
-    or 4) and the sigma = 2, d = 3 ring."""
-    if sigma == 4:
-        return d == 2 and iteration in ("ring", "two_array")
-    if sigma != 2:
+    """Branch-mean buffers serve the rings and two-array pairs of sigma = 2
+    (d = 2, 3) and sigma = 4 (d = 2)."""
+    if iteration not in ("ring", "two_array"):
         return False
-    return iteration in ("ring", "two_array") if d == 2 else (d == 3 and iteration == "ring")
+    return (sigma == 2 and d in (2, 3)) or (sigma == 4 and d == 2)
 
 
 def new_ring(pk, sigma, d, h, dtype, iteration="ring", means=True, **kw):

@@ -244,8 +244,8 @@ int lcsb_certify_optimal(lcsb_ctx *ctx, lcsb_cert *cur, lcsb_cert *best);
 int lcsb_certify_optimal_noalloc(int sigma, int d, int h, int dtype, const void *u,
                                  int exchange_symmetric, double *dev_out, void *stream);
 
-/* Branch-mean tables (folded tables, l >= 3: d = 2 with sigma = 2 or 4, ring
- * or two-array iteration; sigma = 2, d = 3, ring.  Eq. (3)
+/* Branch-mean tables (folded tables, l >= 3: sigma = 2 with d = 2 or 3 and
+ * sigma = 4 with d = 2, ring or two-array iteration.  Eq. (3)
  * and Algorithm 1: a branch that advances some strings reads the mean of the
  * entries that differ in those strings' appended symbols).  sigma = d = 2,
  * for a stored group prefix P < n/8 (entries 4P .. 4P+3):

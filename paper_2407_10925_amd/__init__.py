@@ -38,8 +38,8 @@ class Lcsb:
         ``iteration``: "ring" (Algorithm 2), "two_array" or "two_array_packed"
         (lcsb_create_iter; packed tables hold ``stored`` = packed_entries
         entries, one per exchange orbit).  ``means``: allocate and bind the
-        branch-mean buffers (lcsb_bind_means; folded tables of h >= 3: d = 2 rings
-        and two-array pairs, sigma = 2 or 4, and sigma = 2, d = 3 rings)."""
+        branch-mean buffers (lcsb_bind_means; folded tables of h >= 3, rings and
+        two-array pairs: sigma = 2 with d = 2 or 3, sigma = 4 with d = 2)."""
         import torch
 
         if dtype not in _DTYPES:

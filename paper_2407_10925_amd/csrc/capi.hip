@@ -106,13 +106,13 @@ void clear_lazy(lcsb_ctx *c)
 }
 
 // Folded tables of l >= 3 symmetric in the two strings sweep from the
-// branch-mean tables once they are bound: d = 2 (sigma = 2 or 4, ring or two
-// arrays) and sigma = 2, d = 3 (ring)
+// branch-mean tables once they are bound: sigma = 2 with d = 2 or 3 and
+// sigma = 4 with d = 2, rings and two arrays
 bool means_shape(const lcsb_ctx *c)
 {
     if (c->packed || c->g.h < 3) return false;
     if (c->g.sigma == 4) return c->g.d == 2;
-    return c->g.sigma == 2 && (c->g.d == 2 || (c->g.d == 3 && !c->two_array));
+    return c->g.sigma == 2 && (c->g.d == 2 || c->g.d == 3);
 }
 bool means_path(const lcsb_ctx *c) { return c->means_buf[0] && c->swap_sym && means_shape(c); }
 
@@ -409,7 +409,10 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
         }
         for (int64_t t = 0; t < k && c->g.d == 3; ++t) {
             Means3Launch a;
-            const int r1 = slot_of_lag(c, 1), r2 = slot_of_lag(c, 2), r3 = slot_of_lag(c, 3);
+            // two arrays: every lag is u, lags 2 and 3 read relative to offsets
+            // slots kSlotLag2/3 (u - R, u - 2R, set by the rate pass)
+            const int r1 = slot_of_lag(c, 1), r2 = c->two_array ? r1 : slot_of_lag(c, 2),
+                      r3 = c->two_array ? r1 : slot_of_lag(c, 3);
             a.m1 = slot_part(c, r1, 0);
             a.m3 = slot_part(c, r1, 1);
             a.m12 = slot_part(c, r2, 2);
@@ -424,12 +427,24 @@ int lcsb_iterate(lcsb_ctx *c, int64_t k)
             a.n23 = slot_part(c, a.snew, 3);
             a.n123 = slot_part(c, a.snew, 4);
             a.offsets = reinterpret_cast<double *>(c->ws + Ws::kOffsets);
-            a.s1 = r1;
-            a.s2 = r2;
-            a.s3 = r3;
-            a.shift = 0;
+            a.s1 = c->two_array && c->dtype != LCSB_F32 ? Ws::kSlotZero : r1;
+            a.s2 = c->two_array ? Ws::kSlotLag2 : r2;
+            a.s3 = c->two_array ? Ws::kSlotLag3 : r3;
+            a.shift = c->two_array;
             hipError_t e = launch_sweep_means3(c->g, c->dtype, a, c->stream);
             if (e != hipSuccess) return hip_fail(c, e, "sweep launch");
+            if (c->two_array) {  // the next rate from sample values, as for d = 2
+                if ((e = launch_means_samples3(c->g, c->dtype, a, slot_smp(c, a.snew), c->stream)) !=
+                    hipSuccess)
+                    return hip_fail(c, e, "sample values");
+                if (!c->samples_ok[r1] && !c->entries_ok[r1])
+                    return fail(LCSB_ESTATE, "the old table has neither entries nor sample values");
+                e = launch_two_array_rate(c->g, c->dtype, c->buf[a.snew], c->buf[r1], a.snew, r1,
+                                          c->swap_sym, 0, c->ws, c->stream, slot_smp(c, a.snew),
+                                          c->samples_ok[r1] ? slot_smp(c, r1) : nullptr);
+                if (e != hipSuccess) return hip_fail(c, e, "rate");
+                c->samples_ok[a.snew] = 1;
+            }
             c->lazy[a.snew] = 1;
             c->means_ok[a.snew] = 1;
             c->entries_ok[a.snew] = entries;

@@ -174,6 +174,10 @@ struct Means3Launch {
     int shift;  // FP64: lags 2 and 3 read with their offset differences (two arrays)
 };
 hipError_t launch_sweep_means3(const Geometry &g, int dtype, const Means3Launch &a, hipStream_t s);
+// the two-array rate's sample values of the table launch_sweep_means3 computes
+// from the same means (in sample order, kRateSample values)
+hipError_t launch_means_samples3(const Geometry &g, int dtype, const Means3Launch &a,
+                                 void *samples, hipStream_t s);
 // sigma = 4, d = 2 (m4a_index, m4ab_index): lag 1's M4a and lag 2's M4ab
 // read, the new table's written (MeansLaunch: ma = M4a, mab = M4ab)
 hipError_t launch_sweep_means4(const Geometry &g, int dtype, const MeansLaunch &a, hipStream_t s);

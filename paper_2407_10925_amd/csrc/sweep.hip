@@ -1248,6 +1248,72 @@ __global__ __launch_bounds__(kBlock) void sweep_s2d3_means(
     }
 }
 
+// The new table's values at the two-array rate's sample coordinates (each at
+// the lower index of its exchanged pair), in sample order: what
+// sweep_s2d3_means computes for head r and tail x (the all-match tuple from
+// the group at the folded prefix of x), from the same means with the same
+// operations.
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(kBlock) void means_samples3(
+    const T *__restrict__ m1a, const T *__restrict__ m3a, const T *__restrict__ m12b,
+    const T *__restrict__ m23b, const T *__restrict__ m123c, T *__restrict__ smp, uint64_t n,
+    int h, const double *__restrict__ off, int s1, int s2, int s3)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kShift = kF32 || SHIFT;
+    T d2 = 0, d3 = 0, y0 = 0;
+    if constexpr (!kF32 && SHIFT) {
+        d2 = off[s2] - off[s1];
+        d3 = off[s3] - off[s1];
+    }
+    if constexpr (kF32) {
+        const double o1 = off[s1];
+        d2 = (float)(off[s2] - o1);
+        d3 = (float)(off[s3] - o1);
+        y0 = 1.0f + first(m123c[0] + d3);
+    }
+    const uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= (uint64_t)kRateSample) return;
+    const D3Idx<uint64_t> ix(n);
+    const int top = 3 * (h - 1);
+    uint64_t c = (k * kRateSampleMul) & ((n >> 1) - 1);
+    const uint64_t tw = ix.twin(c);
+    c = tw < c ? tw : c;
+    const int r = (int)((c >> top) & 3);
+    const uint64_t x = c & ((1ull << top) - 1), mx = (n >> 3) - 1;
+    const uint64_t S3 = ix.r3, S2 = S3 << 1, S1 = S3 << 2;
+    const uint64_t i = ((uint64_t)r << top) | x;
+    T v;
+    if (r == 0) {
+        const uint64_t t = x < (n >> 4) ? x : mx - x;
+        const uint64_t at = ix.m123(ix.twin(8 * t));
+        T all3 = m123c[at < t ? at : t];
+        if constexpr (kShift) all3 = all3 + d3;
+        v = (T)1 + first(all3);
+    } else if (r == 1) {  // string 3 (lag 1), strings 1 and 2 (lag 2)
+        const uint64_t b1 = ix.base(i, S3), b2 = ix.base(i, S1 | S2);
+        const uint64_t a3 = ix.m3(b1), a3t = ix.m3(ix.twin(b1));
+        const uint64_t a12 = ix.m12(b2), a12t = ix.m12(ix.twin(b2));
+        const T k1 = m3a[a3t < a3 ? a3t : a3];
+        T k2 = m12b[a12t < a12 ? a12t : a12];
+        if constexpr (kShift) k2 = k2 + d2;
+        v = vmax(first(k1), k2);
+    } else if (r == 2) {  // string 2 (lag 1), strings 1 and 3 (lag 2), at the exchanged tuples
+        const uint64_t b1 = ix.base(i, S2), b2 = ix.base(i, S1 | S3);
+        const T k1 = m1a[ix.m1(ix.twin(b1))];
+        T k2 = m23b[ix.m23(ix.twin(b2))];
+        if constexpr (kShift) k2 = k2 + d2;
+        v = vmax(first(k1), k2);
+    } else {  // strings 2 and 3 (lag 2), string 1 (lag 1)
+        const uint64_t b2 = ix.base(i, S2 | S3), b1 = ix.base(i, S1);
+        T k2 = m23b[ix.m23(b2)];
+        const T k1 = m1a[ix.m1(b1)];
+        if constexpr (kShift) k2 = k2 + d2;
+        v = vmax(first(k2), k1);
+    }
+    smp[k] = kF32 ? (T)(v - y0) : v;
+}
+
 // the five means of a stored table, one thread per group prefix P < n/16
 template <typename T>
 __global__ __launch_bounds__(kBlock) void derive_means3(const T *__restrict__ tab, int lazy,
@@ -1642,6 +1708,25 @@ hipError_t launch_sweep_means3(const Geometry &g, int dtype, const Means3Launch 
     if (dtype == LCSB_F32) return means3_typed<float, false, uint64_t>(g, a, s);
     return a.shift ? means3_typed<double, true, uint64_t>(g, a, s)
                    : means3_typed<double, false, uint64_t>(g, a, s);
+}
+
+template <typename T, bool SHIFT>
+hipError_t samples3_typed(const Geometry &g, const Means3Launch &a, void *samples, hipStream_t s)
+{
+    means_samples3<T, SHIFT><<<kRateSample / kBlock, dim3(kBlock), 0, s>>>(
+        static_cast<const T *>(a.m1), static_cast<const T *>(a.m3), static_cast<const T *>(a.m12),
+        static_cast<const T *>(a.m23), static_cast<const T *>(a.m123), static_cast<T *>(samples),
+        g.n, g.h, a.offsets, a.s1, a.s2, a.s3);
+    return hipGetLastError();
+}
+
+hipError_t launch_means_samples3(const Geometry &g, int dtype, const Means3Launch &a,
+                                 void *samples, hipStream_t s)
+{
+    if (!samples || g.sigma != 2 || g.d != 3 || g.h < 3) return hipErrorInvalidValue;
+    if (dtype == LCSB_F32) return samples3_typed<float, false>(g, a, samples, s);
+    return a.shift ? samples3_typed<double, true>(g, a, samples, s)
+                   : samples3_typed<double, false>(g, a, samples, s);
 }
 
 hipError_t launch_derive_means3(const Geometry &g, int dtype, const void *table, int lazy, void *m1,

@@ -101,13 +101,12 @@ def test_branch_mean_buffers_are_checked_without_a_gpu(lib):
     """lcsb_query_means / lcsb_bind_means: sizes for sigma = d = 2 folded
     tables (Ma, n/4 entries, then Mab, n/8, then the 4096 sample values of the
     two-array rate, each at a 256-byte boundary) and for the sigma = 2, d = 3
-    and sigma = 4, d = 2 rings and two-array pairs, refusals for other shapes
-    and iterations,
-    packed tables and l < 3,
+    and sigma = 4, d = 2 rings, the two-array pairs of every such shape,
+    refusals for packed tables, l < 3 and other shapes,
     and pointer checks before anything is stored (no buffer is dereferenced)."""
     from paper_2407_10925_amd import _capi
     mb = C.c_uint64()
-    for (sigma, d, h, it) in ((2, 3, 5, 1), (4, 2, 2, 1), (4, 2, 2, 0), (2, 2, 2, 0), (2, 3, 2, 0), (2, 2, 5, 2)):
+    for (sigma, d, h, it) in ((2, 3, 2, 1), (4, 2, 2, 1), (4, 2, 2, 0), (2, 2, 2, 0), (2, 3, 2, 0), (2, 2, 5, 2)):
         ctx = C.c_void_p()
         assert lib.lcsb_create_iter(sigma, d, h, 0, it, C.byref(ctx)) == 0
         assert lib.lcsb_query_means(ctx, C.byref(mb)) == _capi.LCSB_EUNSUPPORTED, (sigma, d, h, it)
@@ -133,9 +132,9 @@ def test_branch_mean_buffers_are_checked_without_a_gpu(lib):
         assert lib.lcsb_bind_means(ctx, means, 3) == 0
         assert lib.lcsb_bind_means(ctx, None, 0) == 0  # unbind
         assert lib.lcsb_destroy(ctx) == 0
-    for sigma, h in ((2, 5), (4, 3)):  # the two-array pairs take them too
+    for sigma, d, h in ((2, 2, 5), (4, 2, 3), (2, 3, 4)):  # the two-array pairs take them too
         ctx = C.c_void_p()
-        assert lib.lcsb_create_iter(sigma, 2, h, 0, 1, C.byref(ctx)) == 0
+        assert lib.lcsb_create_iter(sigma, d, h, 0, 1, C.byref(ctx)) == 0
         assert lib.lcsb_query_means(ctx, C.byref(mb)) == 0
         assert lib.lcsb_destroy(ctx) == 0
     # sigma = 2, d = 3 ring: M1, M3 (n/4 each), M12, M23 (n/8), M123 (n/16), the sample

@@ -656,3 +656,97 @@ def test_s4_two_array_means_full_size(pk, dtype):
         assert torch.equal(a, b), k
     del T, M
     torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ d = 3, two arrays
+# The rate's sample values recomputed from the five means (means_samples3).
+
+@pytest.mark.parametrize("h", [3, 4])
+def test_d3_two_array_means_matches_the_oracle(pk, h):
+    say(f"d=3 two-array means vs oracle: h={h}")
+    _, hist, (u, u_prev, R) = oracle.two_array_run(2, 3, h, 30, cadence=30, certificate="optimal")
+    M = pk.Lcsb(2, 3, h, "f64", iteration="two_array", means=True)
+    M.init_zero()
+    for chunk in (1, 4, 25):
+        M.iterate(chunk)
+    N = 8 ** h
+    assert np.array_equal(M.read_table(1), u[: N // 2])
+    assert np.array_equal(M.read_table(2), u_prev[: N // 2])
+    assert M.rate() == R
+    cp, _ = M.certify_optimal()
+    c = hist[-1]["cert"]
+    assert (cp["R"], cp["bound"], cp["argmax_W"], cp["nonfinite"]) == \
+        (c["r"], c["bound"], c["argmin"], c["nonfinite"])
+
+
+@pytest.mark.parametrize("h", [3, 4, 6, 8])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_d3_two_array_means_matches_the_entry_pair(pk, h, dtype):
+    say(f"d=3 two-array means vs entries: h={h} {dtype}")
+    T, M = _pair(pk, h, dtype, "two_array", d=3)
+    done = 0
+    for chunk in (1, 2, 7, 40, 0, 1):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        done += chunk
+        assert T.rate() == M.rate(), done
+        _same_tables_host(T, M, f"after {done}")
+        _same_certs(T, M, f"after {done}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_d3_two_array_means_run_and_writes_through_lag(pk, dtype):
+    """lcsb_run stops alike with and without means; a write through lcsb_lag
+    (both members of an exchanged pair) re-derives the means."""
+    h = 5
+    say(f"d=3 two-array means: run, writes through lcsb_lag: {dtype}")
+    res = []
+    for means in (False, True):
+        L = pk.Lcsb(2, 3, h, dtype, iteration="two_array", means=means)
+        L.init_zero()
+        cur, best, certs, why = L.run(8, max_sweeps=200, stop_delta=1e-9, certificate="optimal")
+        res.append((cur["sweep"], best["bound"], best["argmax_W"], certs, why, L.rate()))
+        del L
+    assert res[0] == res[1]
+    T, M = _pair(pk, h, dtype, "two_array", d=3)
+    T.iterate(5)
+    M.iterate(5)
+    n = 8 ** h
+    i = 0x2a5b
+    r3 = (n - 1) // 7
+    e = (i & r3) | ((i & (r3 << 2)) >> 1) | ((i & (r3 << 1)) << 1)
+    if e >= n // 2:
+        e ^= n - 1
+    for L in (T, M):
+        t, _ = L.lag(1)
+        t[i] = t[i] + 0.625
+        if e != i:
+            t[e] = t[e] + 0.625
+    torch.cuda.synchronize()
+    for chunk in (1, 6):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        assert T.rate() == M.rate()
+        _same_tables_host(T, M, f"planted, +{chunk}")
+        _same_certs(T, M, f"planted, +{chunk}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_d3_two_array_means_full_size(pk, dtype):
+    """(2, 3, 10): whole tables on the device, the rate and both certificates
+    after sweeps that cross an lcsb_iterate call."""
+    say(f"d=3 two-array means full size: h=10 {dtype}")
+    torch.cuda.empty_cache()
+    T, M = _pair(pk, 10, dtype, "two_array", d=3)
+    for chunk in (3, 13):
+        T.iterate(chunk)
+        M.iterate(chunk)
+        assert T.rate() == M.rate()
+    _same_certs(T, M, "full size")
+    for k in (1, 2):
+        a, ao = T.lag(k)
+        b, bo = M.lag(k)
+        assert ao == bo
+        assert torch.equal(a, b), k
+    del T, M
+    torch.cuda.empty_cache()
